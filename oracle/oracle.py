@@ -1,0 +1,237 @@
+"""CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+ctypes/numpy wrapper around the plain FP64 C oracle (vp_oracle.c,
+vp_oracle_adjoint.c, ...).  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark import this module; the GPU library never
+does.  All arrays are float64, row-major [x][v].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["vp_oracle.c", "vp_oracle_adjoint.c", "vp_oracle_amr.c", "vp_oracle_4d.c"]
+LIB = os.path.join(HERE, "libvp_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP contraction off, OpenMP over rows)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    if not force and os.path.exists(LIB):
+        newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(HERE, "vp_oracle.h")])
+        if os.path.getmtime(LIB) >= newest:
+            return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wno-unused-function", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        _lib = ctypes.CDLL(LIB)
+        _declare(_lib)
+    return _lib
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.c_int
+_F = ctypes.c_double
+_V = ctypes.c_void_p
+
+
+def _declare(L):
+    sig = {
+        "vpo_moment": (None, [_I, _I, _F, _D, _D]),
+        "vpo_poisson_new": (_V, [_I]),
+        "vpo_poisson_free": (None, [_V]),
+        "vpo_poisson_solve": (None, [_V, _F, _D, _D]),
+        "vpo_field": (None, [_I, _F, _D, _D]),
+        "vpo_rhs": (None, [_I, _I, _F, _F, _F, _D, _D, _D, _D]),
+        "vpo_vboundary_flux": (None, [_I, _I, _F, _F, _D, _D, _D, _D, _D]),
+        "vpo_ctx_new": (_V, [_I, _I, _F, _F, _F, _F, _D]),
+        "vpo_ctx_free": (None, [_V]),
+        "vpo_constraints": (None, [_V, _D, _D, _D, _D, _D]),
+        "vpo_rk4_step_stages": (None, [_V, _D, _D, _F, _D, _D]),
+        "vpo_rk4_step": (None, [_V, _D, _D, _F]),
+        "vpo_rk4_step_fixed_a": (None, [_V, _D, _D, _D, _F]),
+        "vpo_rhs_adjoint": (None, [_I, _I, _F, _F, _F, _D, _D, _D, _D, _D, _D]),
+        "vpo_constraints_adjoint": (None, [_V, _D, _D]),
+        "vpo_rk4_adjoint_step": (None, [_V, _D, _D, _D, _F]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _declare_extra(L)
+
+
+def _declare_extra(L):
+    """Entry points of the AMR and 2D+2V oracle files, when present."""
+    extra = {
+        "vpo_interp_weights": (None, [_I, _D]),
+        "vpo_amr_new": (_V, [_I, _I, _F, _F, _F, _F, _I, _I, ctypes.POINTER(ctypes.c_int),
+                             _D, _D]),
+        "vpo_amr_free": (None, [_V]),
+        "vpo_amr_state_size": (ctypes.c_long, [_V]),
+        "vpo_amr_patch_offset": (ctypes.c_long, [_V, _I]),
+        "vpo_amr_reduce_mask": (None, [_V, _D, _D]),
+        "vpo_amr_constraints": (None, [_V, _D, _D, _D]),
+        "vpo_amr_fill_ghosts": (None, [_V, _D, _I, _D]),
+        "vpo_amr_rk4_step": (None, [_V, _D, _D, _F]),
+        "vpo4_ctx_new": (_V, [_I, _I, _I, _I, _F, _F, _F, _F, _F, _D, _D]),
+        "vpo4_ctx_free": (None, [_V]),
+        "vpo4_moment": (None, [_V, _D, _D]),
+        "vpo4_poisson": (None, [_V, _D, _D]),
+        "vpo4_field": (None, [_V, _D, _D, _D]),
+        "vpo4_constraints": (None, [_V, _D, _D, _D, _D]),
+        "vpo4_rhs": (None, [_V, _D, _D, _D, _D]),
+        "vpo4_rk4_step": (None, [_V, _D, _D, _F]),
+    }
+    for name, (res, args) in extra.items():
+        fn = getattr(L, name, None)
+        if fn is not None:
+            fn.restype = res
+            fn.argtypes = args
+
+
+def _p(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def moment(f, dv):
+    f = _f64(f)
+    n = np.empty(f.shape[0])
+    lib().vpo_moment(f.shape[0], f.shape[1], dv, _p(f), _p(n))
+    return n
+
+
+class Poisson:
+    def __init__(self, nx):
+        self.nx = nx
+        self.h = lib().vpo_poisson_new(nx)
+
+    def solve(self, rho, dx):
+        rho = _f64(rho)
+        phi = np.empty(self.nx)
+        lib().vpo_poisson_solve(self.h, dx, _p(rho), _p(phi))
+        return phi
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.vpo_poisson_free(self.h)
+            self.h = None
+
+
+def poisson_solve(rho, dx):
+    return Poisson(len(rho)).solve(rho, dx)
+
+
+def field(phi, dx):
+    phi = _f64(phi)
+    E = np.empty_like(phi)
+    lib().vpo_field(len(phi), dx, _p(phi), _p(E))
+    return E
+
+
+def rhs(f, a, dx, dv, v_lo, vghost):
+    f, a, vg = _f64(f), _f64(a), _f64(vghost)
+    k = np.empty_like(f)
+    lib().vpo_rhs(f.shape[0], f.shape[1], dx, dv, v_lo, _p(vg), _p(f), _p(a), _p(k))
+    return k
+
+
+def vboundary_flux(f, a, dx, dv, vghost):
+    f, a, vg = _f64(f), _f64(a), _f64(vghost)
+    lo = np.empty(f.shape[0])
+    hi = np.empty(f.shape[0])
+    lib().vpo_vboundary_flux(f.shape[0], f.shape[1], dx, dv, _p(vg), _p(f), _p(a), _p(lo), _p(hi))
+    return lo, hi
+
+
+def rhs_adjoint(f, a, kbar, dx, dv, v_lo, vghost):
+    f, a, kb, vg = _f64(f), _f64(a), _f64(kbar), _f64(vghost)
+    fb = np.empty_like(f)
+    ab = np.empty(f.shape[0])
+    lib().vpo_rhs_adjoint(f.shape[0], f.shape[1], dx, dv, v_lo, _p(vg), _p(f), _p(a), _p(kb),
+                          _p(fb), _p(ab))
+    return fb, ab
+
+
+class Oracle1D:
+    """Single-level 1D+1V oracle bound to one mesh (Poisson factors kept)."""
+
+    def __init__(self, nx, nv, x_len, v_lo, v_hi, qm, vghost):
+        self.nx, self.nv = nx, nv
+        self.dx = x_len / nx
+        self.dv = (v_hi - v_lo) / nv
+        self.v_lo = v_lo
+        self.qm = qm
+        self.vghost = _f64(vghost)
+        self.h = lib().vpo_ctx_new(nx, nv, x_len, v_lo, v_hi, qm, _p(self.vghost))
+
+    @classmethod
+    def from_problem(cls, prob):
+        return cls(prob.nx, prob.nv, prob.x_len, prob.v_lo, prob.v_hi, prob.qm, prob.vghost)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.vpo_ctx_free(self.h)
+            self.h = None
+
+    def constraints(self, f):
+        """Return (a, n, phi, E) for the state f."""
+        f = _f64(f)
+        a, n, phi, E = (np.empty(self.nx) for _ in range(4))
+        lib().vpo_constraints(self.h, _p(f), _p(a), _p(n), _p(phi), _p(E))
+        return a, n, phi, E
+
+    def rhs(self, f, a):
+        return rhs(f, a, self.dx, self.dv, self.v_lo, self.vghost)
+
+    def step(self, f, dt):
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().vpo_rk4_step(self.h, _p(f), _p(out), dt)
+        return out
+
+    def step_stages(self, f, dt):
+        f = _f64(f)
+        out = np.empty_like(f)
+        sf = np.empty((4,) + f.shape)
+        sa = np.empty((4, self.nx))
+        lib().vpo_rk4_step_stages(self.h, _p(f), _p(out), dt, _p(sf), _p(sa))
+        return out, sf, sa
+
+    def step_fixed_a(self, f, a, dt):
+        f, a = _f64(f), _f64(a)
+        out = np.empty_like(f)
+        lib().vpo_rk4_step_fixed_a(self.h, _p(f), _p(out), _p(a), dt)
+        return out
+
+    def constraints_adjoint(self, abar, fbar):
+        abar = _f64(abar)
+        fbar = np.array(fbar, dtype=np.float64, copy=True)
+        lib().vpo_constraints_adjoint(self.h, _p(abar), _p(fbar))
+        return fbar
+
+    def adjoint_step(self, f_n, lam_np1, dt):
+        f_n, lam = _f64(f_n), _f64(lam_np1)
+        out = np.empty_like(f_n)
+        lib().vpo_rk4_adjoint_step(self.h, _p(f_n), _p(lam), _p(out), dt)
+        return out

@@ -1,0 +1,46 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.  Declarations of the plain
+ * FP64 reference implementation; not used by the GPU library.
+ * Arrays are row-major [x][v] (v contiguous), all sizes in cells.
+ */
+#ifndef VP_ORACLE_H
+#define VP_ORACLE_H
+
+typedef struct vpo_poisson vpo_poisson;
+typedef struct vpo_ctx {
+    int nx, nv;
+    double dx, dv, v_lo, qm;
+    double vghost[4];      /* equilibrium cell averages at j = -2, -1, nv, nv+1 */
+    vpo_poisson* P;
+} vpo_ctx;
+
+void vpo_moment(int nx, int nv, double dv, const double* f, double* n);
+vpo_poisson* vpo_poisson_new(int N);
+void vpo_poisson_free(vpo_poisson* P);
+void vpo_poisson_solve(const vpo_poisson* P, double dx, const double* rho, double* phi);
+void vpo_field(int nx, double dx, const double* phi, double* E);
+void vpo_rhs(int nx, int nv, double dx, double dv, double v_lo,
+             const double* vghost, const double* f, const double* a, double* k);
+void vpo_vboundary_flux(int nx, int nv, double dx, double dv,
+                        const double* vghost, const double* f, const double* a,
+                        double* g_lo, double* g_hi);
+
+vpo_ctx* vpo_ctx_new(int nx, int nv, double x_len, double v_lo, double v_hi,
+                     double qm, const double* vghost);
+void vpo_ctx_free(vpo_ctx* c);
+void vpo_constraints(const vpo_ctx* c, const double* f, double* a,
+                     double* n_out, double* phi_out, double* E_out);
+void vpo_rk4_step_stages(const vpo_ctx* c, const double* f_in, double* f_out, double dt,
+                         double* stage_f, double* stage_a);
+void vpo_rk4_step(const vpo_ctx* c, const double* f_in, double* f_out, double dt);
+void vpo_rk4_step_fixed_a(const vpo_ctx* c, const double* f_in, double* f_out,
+                          const double* a, double dt);
+
+void vpo_rhs_adjoint(int nx, int nv, double dx, double dv, double v_lo,
+                     const double* vghost, const double* f, const double* a,
+                     const double* kbar, double* fbar, double* abar);
+void vpo_constraints_adjoint(const vpo_ctx* c, const double* abar, double* fbar);
+void vpo_rk4_adjoint_step(const vpo_ctx* c, const double* f_n, const double* lam_np1,
+                          double* lam_n, double dt);
+
+#endif

@@ -1,0 +1,312 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: closed
+forms (DFT symbol of the Poisson operator, exact cell averages of
+polynomials, the exact free-streaming solution), invariants (telescoping
+mass identity), textbook special cases (the RK4 stability polynomial, the
+Landau dispersion relation) and convergence rates.  A dropped term, a wrong
+sign or index, or a wrong coefficient in any part of the discretisation of
+section 2 fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import Polynomial
+
+import vp_inputs as I
+
+
+def cell_avg_poly(P, lo, h, n):
+    Pi = P.integ()
+    xl = lo + np.arange(n) * h
+    return (Pi(xl + h) - Pi(xl)) / h
+
+
+# ------------------------------------------------------------------ Poisson / field
+
+
+@pytest.mark.parametrize("nx", [5, 8, 37, 64])
+def test_poisson_dft_symbol(oracle, nx):
+    """For rho_i = cos(theta m i) the periodic solution of the discrete
+    potential equation (section 2) is 12 dx^2 rho_i / lambda(theta) with
+    lambda(theta) = 30 - 32 cos(theta) + 2 cos(2 theta): pins the five
+    stencil weights and the dx^2 scaling of the right-hand side."""
+    dx = 0.37
+    i = np.arange(nx)
+    for m in range(1, nx // 2 + 1):
+        th = 2.0 * math.pi * m / nx
+        lam = 30.0 - 32.0 * math.cos(th) + 2.0 * math.cos(2.0 * th)
+        for rho in (np.cos(th * i), np.sin(th * i) if 2 * m != nx else np.cos(th * i)):
+            phi = oracle.poisson_solve(rho + 3.0, dx)        # constant part is projected out
+            np.testing.assert_allclose(phi, 12.0 * dx * dx * rho / lam, rtol=0, atol=1e-12)
+
+
+def test_poisson_zero_mean_and_constant(oracle):
+    rng = np.random.default_rng(5)
+    rho = rng.normal(size=50)
+    phi = oracle.poisson_solve(rho, 0.1)
+    assert abs(phi.sum()) < 1e-12
+    np.testing.assert_allclose(oracle.poisson_solve(np.full(50, 2.5), 0.1), 0.0, atol=1e-13)
+
+
+def test_poisson_field_fourth_order(oracle):
+    """phi'' = -rho (i.e. the paper's Laplacian of phi = n - 1 with rho =
+    1 - n) and E = -phi': for rho = cos(kx), phi = cos(kx)/k^2 and
+    E = sin(kx)/k.  Cell averages converge at fourth order, and E has the
+    sign of the physical field (a wrong sign fails by O(1))."""
+    L, k = 4.0 * math.pi, 0.5
+    errs_phi, errs_E = [], []
+    for nx in (16, 32, 64):
+        dx = L / nx
+        rho = I.cos_cell_average(0.0, L, nx, k)
+        phi = oracle.poisson_solve(rho, dx)
+        E = oracle.field(phi, dx)
+        phi_ex = I.cos_cell_average(0.0, L, nx, k) / k ** 2
+        xl = np.arange(nx) * dx
+        E_ex = (-np.cos(k * (xl + dx)) + np.cos(k * xl)) / (k * dx) / k
+        errs_phi.append(np.abs(phi - phi_ex).max())
+        errs_E.append(np.abs(E - E_ex).max())
+    for e in (errs_phi, errs_E):
+        rates = [math.log2(e[i] / e[i + 1]) for i in range(len(e) - 1)]
+        assert min(rates) > 3.8, (e, rates)
+    assert errs_E[-1] < 1e-5
+
+
+def test_moment_of_equilibrium(oracle):
+    """dv * sum of exact cell averages of the Maxwellian telescopes to
+    Phi(v_hi) - Phi(v_lo) (closed form via erf)."""
+    p = I.landau(8, 40)
+    f = np.tile(p.veq[2:-2], (8, 1))
+    n = oracle.moment(f, p.dv)
+    exact = 0.5 * (math.erf(p.v_hi / math.sqrt(2)) - math.erf(p.v_lo / math.sqrt(2)))
+    np.testing.assert_allclose(n, exact, rtol=1e-14)
+
+
+# ------------------------------------------------------------------ RHS exactness
+
+
+def exact_rhs(P, Q, A, x_lo, dx, nx, v_lo, dv, nv):
+    """Exact cell average of -d/dx(v f) - d/dv(a f) for f = P(x) Q(v),
+    a = A(x): a difference of exact face integrals."""
+    xf = x_lo + np.arange(nx + 1) * dx
+    vf = v_lo + np.arange(nv + 1) * dv
+    vQ = (Polynomial([0, 1]) * Q).integ()
+    AP = (A * P).integ()
+    mom_v = (vQ(vf[1:]) - vQ(vf[:-1])) / dv           # (1/dv) int v Q dv over cell j
+    mom_x = (AP(xf[1:]) - AP(xf[:-1])) / dx           # (1/dx) int A P dx over cell i
+    dP = (P(xf[1:]) - P(xf[:-1])) / dx
+    dQ = (Q(vf[1:]) - Q(vf[:-1])) / dv
+    return -dP[:, None] * mom_v[None, :] - mom_x[:, None] * dQ[None, :]
+
+
+CASES = {
+    # x-quadratic f times x-linear a: the product-rule (1/48) correction is exercised
+    "product_rule": (Polynomial([1.0, 0.3, -0.05]), Polynomial([0.5, 0.2, -0.1]), Polynomial([0.7, -0.2])),
+    # x-cubic f: fourth-order face average in x
+    "cubic_x": (Polynomial([1.0, 0.1, 0.02, -0.003]), Polynomial([0.5, 0.2, -0.1]), Polynomial([0.4])),
+    # v-cubic f (x-constant): fourth-order face average in v
+    "cubic_v": (Polynomial([1.3]), Polynomial([0.5, 0.2, -0.1, 0.03]), Polynomial([0.7, -0.2, 0.01])),
+    # quadratic a times x-linear f
+    "product_rule_2": (Polynomial([1.0, -0.4]), Polynomial([0.5, 0.2, -0.1]), Polynomial([0.3, 0.1, -0.02])),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_rhs_polynomial_exactness(oracle, case):
+    """The fourth-order fluxes of section 2 are exact for the polynomial
+    classes below; interior cells (no periodic wrap, no velocity ghost)
+    must match the exact cell-averaged divergence to round-off."""
+    P, Q, A = CASES[case]
+    nx, nv = 16, 14
+    x_lo, dx, v_lo, dv = 0.0, 0.31, -2.0, 0.27
+    f = cell_avg_poly(P, x_lo, dx, nx)[:, None] * cell_avg_poly(Q, v_lo, dv, nv)[None, :]
+    a = cell_avg_poly(A, x_lo, dx, nx)
+    k = oracle.rhs(f, a, nx * dx / nx, dv, v_lo, np.zeros(4))
+    ex = exact_rhs(P, Q, A, x_lo, dx, nx, v_lo, dv, nv)
+    sl = (slice(2, nx - 2), slice(2, nv - 2))
+    scale = np.abs(ex[sl]).max()
+    np.testing.assert_allclose(k[sl], ex[sl], rtol=0, atol=1e-12 * scale)
+    if case == "product_rule":
+        # the correction term is far above the tolerance, so its sign is pinned
+        corr = dx * dx / 12.0 * abs(A.deriv()(0.0)) * np.abs(P.deriv()(x_lo + dx * np.arange(nx))).max()
+        assert corr * 0.02 / dv > 1e-6 * scale
+
+
+# ------------------------------------------------------------------ conservation
+
+
+def test_mass_identity(oracle):
+    """Flux form: over one RK4 step the mass change equals minus dt dx
+    times the b-weighted velocity-boundary fluxes of the four stages
+    (x fluxes telescope by periodicity)."""
+    rng = np.random.default_rng(3)
+    p = I.landau(24, 20)
+    o = oracle.Oracle1D.from_problem(p)
+    f = p.initial_state() * (1.0 + 0.1 * rng.random((24, 20)))
+    dt = 0.01
+    out, sf, sa = o.step_stages(f, dt)
+    dm = (out.sum() - f.sum()) * p.dx * p.dv
+    b = [1 / 6, 1 / 3, 1 / 3, 1 / 6]
+    flux = 0.0
+    for s in range(4):
+        lo, hi = oracle.vboundary_flux(sf[s], sa[s], p.dx, p.dv, p.vghost)
+        flux += b[s] * (hi - lo).sum()
+    assert abs(dm - (-dt * p.dx * flux)) < 1e-15 * f.sum() * p.dx * p.dv * 100
+    assert abs(flux) > 0   # the boundary flux is not trivially zero here
+
+
+def test_mass_conserved_without_field(oracle):
+    p = I.landau(16, 16)
+    o = oracle.Oracle1D.from_problem(p)
+    rng = np.random.default_rng(4)
+    f = rng.random((16, 16))
+    g = o.step_fixed_a(f, np.zeros(16), 0.02)
+    np.testing.assert_allclose(g.sum(), f.sum(), rtol=1e-14)
+
+
+# ------------------------------------------------------------------ RK4
+
+
+def test_rk4_stability_polynomial(oracle):
+    """With zero ghosts and a static field the semi-discrete operator L is
+    linear, so one classic RK4 step must equal P(dt L) f with
+    P(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 (section 2, eq. rk4)."""
+    rng = np.random.default_rng(7)
+    nx, nv = 12, 10
+    x_len, v_lo, v_hi = 3.0, -2.0, 2.0
+    o = oracle.Oracle1D(nx, nv, x_len, v_lo, v_hi, -1.0, np.zeros(4))
+    f = rng.random((nx, nv))
+    a = rng.normal(0, 0.5, nx)
+    dt = 0.05
+    term, total = f.copy(), f.copy()
+    for m in range(1, 5):
+        term = dt * o.rhs(term, a) / m
+        total += term
+    np.testing.assert_allclose(o.step_fixed_a(f, a, dt), total, rtol=0, atol=1e-13)
+
+
+def free_streaming_exact(p, t, eps, k):
+    """Exact cell averages of (1 + eps cos(k (x - v t))) M(v)."""
+    nodes, w = np.polynomial.legendre.leggauss(16)
+    vl = p.v_lo + np.arange(p.nv) * p.dv
+    v = vl[:, None] + 0.5 * p.dv * (nodes[None, :] + 1.0)
+    Mv = I.maxwellian(v)
+    xl = p.x_lo + np.arange(p.nx) * p.dx
+    xr = xl + p.dx
+    # int over x of cos(k (x - v t)) = [sin(k (x - v t))]/k
+    sx = (np.sin(k * (xr[:, None, None] - v[None] * t)) - np.sin(k * (xl[:, None, None] - v[None] * t))) / (k * p.dx)
+    return p.veq[None, 2:-2] + eps * 0.5 * (Mv[None] * sx * w[None, None, :]).sum(-1)
+
+
+def test_free_streaming_fourth_order(oracle):
+    """E = 0: the exact solution is f0(x - v t, v); the error of the cell
+    averages after t = 0.5 falls at fourth order."""
+    errs = []
+    T = 0.5
+    for n in (32, 64, 128):
+        p = I.landau(n, n, eps=0.05)
+        o = oracle.Oracle1D.from_problem(p)
+        f = p.initial_state()
+        nsteps = int(math.ceil(T / (0.5 * p.dx / 8.0)))
+        dt = T / nsteps
+        a = np.zeros(n)
+        for _ in range(nsteps):
+            f = o.step_fixed_a(f, a, dt)
+        errs.append(np.abs(f - free_streaming_exact(p, T, 0.05, 0.5)).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 3.7, (errs, rates)
+
+
+def restrict2(f):
+    return 0.25 * (f[0::2, 0::2] + f[1::2, 0::2] + f[0::2, 1::2] + f[1::2, 1::2])
+
+
+def test_static_field_self_convergence(oracle):
+    """Prescribed a(x) = a0 sin(kx): the self-convergence rate is about 4;
+    a wrong sign of the product-rule term drops it to about 2."""
+    T, a0, k = 0.5, 0.6, 0.5
+    sols = []
+    for n in (32, 64, 128):
+        p = I.landau(n, n, eps=0.05)
+        o = oracle.Oracle1D.from_problem(p)
+        xl = np.arange(n) * p.dx
+        a = a0 * (-np.cos(k * (xl + p.dx)) + np.cos(k * xl)) / (k * p.dx)
+        f = p.initial_state()
+        dt0 = 0.5 / (8.0 / p.dx + a0 / p.dv)
+        nsteps = int(math.ceil(T / dt0))
+        for _ in range(nsteps):
+            f = o.step_fixed_a(f, a, T / nsteps)
+        sols.append(f)
+    e1 = np.abs(sols[0] - restrict2(sols[1])).max()
+    e2 = np.abs(sols[1] - restrict2(sols[2])).max()
+    assert math.log2(e1 / e2) > 3.6, (e1, e2)
+
+
+# ------------------------------------------------------------------ Landau damping
+
+
+def landau_root(k=0.5):
+    from scipy.special import wofz
+
+    def D(w):
+        z = w / (math.sqrt(2.0) * k)
+        Z = 1j * math.sqrt(math.pi) * wofz(z)
+        return 1.0 + (1.0 + z * Z) / k ** 2
+
+    w = 1.4 - 0.15j
+    for _ in range(50):
+        h = 1e-7
+        dD = (D(w + h) - D(w - h)) / (2 * h)
+        w = w - D(w) / dD
+    assert abs(D(w)) < 1e-12
+    return w
+
+
+def test_landau_dispersion_root():
+    w = landau_root()
+    assert abs(w.real - 1.41566) < 1e-4 and abs(w.imag + 0.15336) < 1e-4
+
+
+def landau_fit(step_fn, constraints_fn, p, dt, t_end=30.0, t_fit=(2.0, 30.0)):
+    """Run to t_end, fit the decay rate and frequency of the L2 norm of E
+    from its local maxima (parabolic peak refinement in log amplitude)."""
+    f = p.initial_state()
+    ts, amp = [], []
+    t = 0.0
+    while t < t_end:
+        E = constraints_fn(f)
+        ts.append(t)
+        amp.append(math.sqrt(float((E * E).sum()) * p.dx))
+        f = step_fn(f, dt)
+        t += dt
+    ts, amp = np.array(ts), np.log(np.array(amp))
+    tp, ap = [], []
+    for i in range(1, len(amp) - 1):
+        if amp[i] > amp[i - 1] and amp[i] >= amp[i + 1]:
+            y0, y1, y2 = amp[i - 1:i + 2]
+            d = 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+            tp.append(ts[i] + d * dt)
+            ap.append(y1 - 0.25 * (y0 - y2) * d)
+    tp, ap = np.array(tp), np.array(ap)
+    m = (tp > t_fit[0]) & (tp < t_fit[1])
+    gamma = np.polyfit(tp[m], ap[m], 1)[0]
+    omega = math.pi / np.diff(tp[m]).mean()
+    return gamma, omega
+
+
+@pytest.mark.slow
+def test_landau_damping_rate(oracle):
+    """Linear Landau damping, k = 0.5, eps = 0.01: the decay rate and
+    frequency of the field amplitude over t in [2, 30] match the root of
+    the Vlasov-Poisson dispersion relation.  This pins the coupling: the
+    sign of E, the dx^2 Poisson scaling and the moment.  64 x 128 cells:
+    at 64 velocity cells the filamentation is under-resolved by t ~ 20 and
+    the fitted rate drifts to about -0.148."""
+    w = landau_root()
+    p = I.landau(64, 128)
+    o = oracle.Oracle1D.from_problem(p)
+    dt = 0.5 / (8.0 / p.dx + 0.01 / p.dv)
+    gamma, omega = landau_fit(o.step, lambda f: o.constraints(f)[3], p, dt)
+    assert abs(gamma - w.imag) < 0.002, gamma
+    assert abs(omega - w.real) < 0.005, omega
