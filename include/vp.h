@@ -1,0 +1,247 @@
+/*
+ * vp.h -- C ABI of the MI355X (gfx950) Vlasov-Poisson library.
+ *
+ * The library advances the electrostatic Vlasov-Poisson system with
+ * immobile ions (Hittinger & Banks, "Block-Structured Adaptive Mesh
+ * Refinement Algorithms for Vlasov Simulation", section 2):
+ *
+ *     df/dt + v . grad_x f + (q/m) E . grad_v f = 0,
+ *     E = -grad_x phi,  laplacian(phi) = int f dv - 1,
+ *
+ * discretised by the fourth-order finite-volume method of section 2
+ * (cell averages, face averages with the ideal (unlimited) weights,
+ * product-rule flux corrections, flux divergence) and integrated with the
+ * classic four-stage RK4 scheme (eq. rk4), with the field re-solved at
+ * every predictor state and after the update (Alg. smsvphu).  Phase space
+ * is 1D+1V or 2D+2V; x is periodic; the velocity box is truncated.
+ *
+ * Conventions (every entry point):
+ *   - Arrays are caller-owned device memory (e.g. torch tensors), passed
+ *     as plain pointers; the library never allocates or frees them.
+ *     Phase-space state f is row-major with the velocity index fastest:
+ *     1D+1V f[x][v], 2D+2V f[x][y][vx][vy].  Its element type is the
+ *     plan's dtype (double for VP_F64, float for VP_F32).  Configuration-
+ *     space arrays (n, phi, E, a) are always double.
+ *   - Work is only enqueued on `stream`; no call synchronises the device
+ *     or the host.  Calls that share a plan may run concurrently only
+ *     with distinct `work` buffers.
+ *   - No call inside the time loop allocates device memory: scratch comes
+ *     from the caller's `work` buffer of at least vp_workspace_bytes().
+ *   - Errors: a vp_status is returned; VP_OK is 0.  Argument, shape and
+ *     dtype errors are detected on the host before any launch, nothing is
+ *     enqueued, and vp_last_error() returns a thread-local message.  No
+ *     exception crosses the ABI and the library never aborts.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum vp_status {
+    VP_OK = 0,
+    VP_EINVAL = 1,     /* bad argument (null pointer, non-positive size, bad box) */
+    VP_ESHAPE = 2,     /* sizes inconsistent with the plan                         */
+    VP_EDTYPE = 3,     /* unsupported element type for this call                    */
+    VP_ENOTSUP = 4,    /* valid request outside what this build supports            */
+    VP_EHIP = 5,       /* a HIP runtime call failed                                 */
+    VP_ENOMEM = 6      /* plan tables could not be allocated                        */
+} vp_status;
+
+typedef enum vp_dtype { VP_F64 = 0, VP_F32 = 1 } vp_dtype;
+
+#define VP_MAX_LEVELS 2
+
+/*
+ * Problem statement (section 2 of the paper; the box hierarchy of
+ * section 3).  Directions are ordered configuration first, then velocity:
+ * 1D+1V (x, v), 2D+2V (x, y, vx, vy).
+ *
+ *   ndim      N = M, the number of configuration (= velocity) dimensions: 1 or 2
+ *   dtype     element type of the phase-space state (vp_dtype)
+ *   n_levels  1 (uniform mesh) or 2 (coarse level plus level-1 patches)
+ *   cells     level-0 cells per direction
+ *   ratio     level-0 -> level-1 refinement ratio per direction (n_levels == 2)
+ *   x_lo, x_len  periodic configuration box [x_lo, x_lo + x_len) per direction
+ *   v_lo, v_hi   truncated velocity box per velocity direction
+ *   qm        charge-to-mass ratio of the species (-1 for electrons)
+ *   veq[l][d] host pointer: the cell averages of the unperturbed equilibrium
+ *             along velocity direction d on level l, including two ghost
+ *             cells on each side (cells_v(l) + 4 values, index 0 is j = -2).
+ *             The velocity ghost cells of f hold these values (the
+ *             characteristic boundary condition of section 2 with the
+ *             equilibrium supplied on both ends); in 2D+2V the equilibrium
+ *             is the product veq[l][0][j] * veq[l][1][k].  Copied at plan
+ *             creation.
+ */
+typedef struct vp_problem {
+    int32_t ndim;
+    int32_t dtype;
+    int32_t n_levels;
+    int32_t cells[4];
+    int32_t ratio[4];
+    double x_lo[2];
+    double x_len[2];
+    double v_lo[2];
+    double v_hi[2];
+    double qm;
+    const double* veq[VP_MAX_LEVELS][2];
+} vp_problem;
+
+/*
+ * A level-1 patch: inclusive cell range [lo, hi] per direction in the
+ * level-1 global index space (section 3, box notation).  Level 0 always
+ * covers the whole domain and is implicit.  Patches must be disjoint,
+ * aligned to the refinement ratio and inside the domain.
+ */
+typedef struct vp_box {
+    int32_t level;
+    int32_t lo[4];
+    int32_t hi[4];
+} vp_box;
+
+typedef struct vp_plan vp_plan;
+
+/* Creates an immutable plan: validates the problem and boxes, builds the
+ * device tables (tile tables, coarse-fine maps, Poisson factors).  The
+ * plan owns only these tables.  boxes may be NULL when nbox == 0. */
+vp_status vp_plan_create(const vp_problem* problem, const vp_box* boxes, int32_t nbox,
+                         vp_plan** out);
+vp_status vp_plan_destroy(vp_plan* plan);
+const char* vp_last_error(void);
+
+/* Sizes derived from the plan.
+ *   vp_state_elems   elements of a phase-space state f: level 0 followed by
+ *                    each level-1 patch (in box order), each row-major.
+ *   vp_patch_offset  element offset of patch p's data in f (p = -1: level 0)
+ *   vp_config_elems  doubles of n, phi, E: the finest configuration mesh
+ *   vp_field_elems   doubles of the acceleration array a: (q/m) E on every
+ *                    level's configuration mesh (level 0 first)
+ *   vp_workspace_bytes  minimum size of `work` for every call below
+ *   vp_stage_elems   elements of the stage record of vp_rk4_step_record
+ */
+size_t vp_state_elems(const vp_plan* plan);
+int64_t vp_patch_offset(const vp_plan* plan, int32_t patch);
+size_t vp_config_elems(const vp_plan* plan);
+size_t vp_field_elems(const vp_plan* plan);
+size_t vp_workspace_bytes(const vp_plan* plan);
+size_t vp_stage_elems(const vp_plan* plan);
+
+/*
+ * k = L(f; a): the semi-discrete right-hand side (section 2,
+ * eq. semi-discrete) for every cell of every patch.
+ *   f  state (plan dtype), vp_state_elems
+ *   a  acceleration (q/m) E per level, vp_field_elems (from vp_inject_field)
+ *   k  output, same layout and dtype as f; must not alias f
+ * Ghost cells are synthesised: x periodic, velocity ghosts from veq, and on
+ * level 1 copies from neighbouring patches or fifth-order conservative
+ * interpolation from level 0 (section 3, sub-cell interpolation).
+ */
+vp_status vp_rhs(const vp_plan* plan, const void* f, const double* a, void* k,
+                 hipStream_t stream);
+
+/*
+ * n = dv sum_j f_ij: the velocity moment (section 2; section 3,
+ * reduction) on the finest configuration mesh.  On two levels the
+ * Sub-Patch reduction is used: uncovered coarse columns are summed over
+ * velocity, refined in x by the linear fifth-order sub-cell interpolant
+ * and added to the fine-patch sums.  rho = 1 - n.
+ *   n  output, vp_config_elems doubles
+ */
+vp_status vp_reduce_moment(const vp_plan* plan, const void* f, double* n, void* work,
+                           hipStream_t stream);
+
+/*
+ * Periodic fourth-order Poisson problem of section 2 (discrete potential
+ * equation, read with 12 dx^2 on the right-hand side) for rho = 1 - n,
+ * with the null space projected out (sum rho = 0, zero-mean phi), and the
+ * fourth-order cell-averaged field E = -D phi.
+ *   n    input, vp_config_elems
+ *   phi  output or NULL
+ *   E    output or NULL (vp_config_elems per configuration direction,
+ *        direction-major in 2D+2V)
+ */
+vp_status vp_poisson_periodic(const vp_plan* plan, const double* n, double* phi, double* E,
+                              void* work, hipStream_t stream);
+
+/*
+ * Injection (section 3, Alg. inject): a = (q/m) E on every level's
+ * configuration mesh; the finest level takes E directly, level 0 the mean
+ * of the ratio fine values covering each coarse cell.  The phase-space
+ * kernels read a as a per-row scalar (the restricted hierarchy is used
+ * directly, no phase-space copy).
+ *   E  input, as written by vp_poisson_periodic
+ *   a  output, vp_field_elems
+ */
+vp_status vp_inject_field(const vp_plan* plan, const double* E, double* a, hipStream_t stream);
+
+/*
+ * One synchronous RK4 Vlasov-Poisson step (Alg. smsvphu without
+ * regridding), in place.
+ *   f     state, overwritten with f^{n+1}
+ *   a     on entry the acceleration of f (from vp_inject_field or the
+ *         previous step); on exit that of f^{n+1} (the post-update
+ *         constraint of Alg. smsvphu)
+ *   dt    time step
+ *   work  >= vp_workspace_bytes
+ * On two levels the coarse level is advanced everywhere, the fine ghosts
+ * are filled from the coarse predictor of the same stage, and at the end
+ * the coarse cells next to coarse-fine faces take the fine accumulated
+ * flux and covered coarse cells the average of the fine cells
+ * (Alg. msfduc).
+ */
+vp_status vp_rk4_step(const vp_plan* plan, void* f, double* a, double dt, void* work,
+                      hipStream_t stream);
+
+/*
+ * As vp_rk4_step (single level), and also records the stage states
+ * f(2), f(3), f(4) and the four stage accelerations in `stages`
+ * (vp_stage_elems elements of the plan dtype; the accelerations are
+ * stored as doubles at the end, see vp_stage_elems) for a later
+ * vp_adjoint_step.
+ */
+vp_status vp_rk4_step_record(const vp_plan* plan, void* f, double* a, double dt,
+                             void* stages, void* work, hipStream_t stream);
+
+/*
+ * Discrete adjoint of one RK4 step (single level, FP64): lam_n =
+ * (d f^{n+1} / d f^n)^T lam_np1 at the state f_n, including the adjoint of
+ * the moment reduction, the Poisson solve, the field and the injection.
+ *   f_n      state at the start of the step
+ *   a_n      its acceleration
+ *   stages   record written by vp_rk4_step_record from (f_n, a_n), or NULL
+ *            to recompute the stages internally
+ *   lam_np1  cotangent of f^{n+1}
+ *   lam_n    output cotangent of f^n (may alias lam_np1)
+ * VP_ENOTSUP for two-level or FP32 plans.
+ */
+vp_status vp_adjoint_step(const vp_plan* plan, const void* f_n, const double* a_n,
+                          const void* stages, const void* lam_np1, void* lam_n, double dt,
+                          void* work, hipStream_t stream);
+
+/*
+ * Kernel timing (a profiling aid, per-routine exclusive timers): while
+ * enabled, every launch made by this plan is bracketed by a pair of HIP
+ * events recorded on the launch's stream.  vp_timing_read synchronises on
+ * those events, returns the accumulated milliseconds and launch counts of
+ * each kernel class and clears them.  Classes: 0 stage / right-hand-side
+ * kernels, 1 field solve (moment finalisation + Poisson + field),
+ * 2 velocity moment, 3 coarse-fine synchronisation, 4 adjoint stage
+ * kernels, 5 other.  At most 8192 launches are recorded between reads;
+ * later launches run untimed.
+ */
+#define VP_TIMING_CLASSES 6
+vp_status vp_timing_enable(vp_plan* plan, int32_t enable);
+vp_status vp_timing_read(vp_plan* plan, double* ms, int64_t* counts, int32_t nclass);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

@@ -53,6 +53,7 @@ _V = ctypes.c_void_p
 
 def _declare(L):
     sig = {
+        "vpo_num_threads": (_I, []),
         "vpo_moment": (None, [_I, _I, _F, _D, _D]),
         "vpo_poisson_new": (_V, [_I]),
         "vpo_poisson_free": (None, [_V]),
@@ -112,6 +113,10 @@ def _p(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads():
+    return lib().vpo_num_threads()
 
 
 def moment(f, dv):

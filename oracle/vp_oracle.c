@@ -435,3 +435,11 @@ void vpo_rk4_step_fixed_a(const vpo_ctx* c, const double* f_in, double* f_out,
     }
     free(fn); free(fs); free(ks);
 }
+
+/* Threads the OpenMP loops of the oracle use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int vpo_num_threads(void) { return omp_get_max_threads(); }
+#else
+int vpo_num_threads(void) { return 1; }
+#endif

@@ -14,6 +14,7 @@ typedef struct vpo_ctx {
     vpo_poisson* P;
 } vpo_ctx;
 
+int vpo_num_threads(void);
 void vpo_moment(int nx, int nv, double dv, const double* f, double* n);
 vpo_poisson* vpo_poisson_new(int N);
 void vpo_poisson_free(vpo_poisson* P);

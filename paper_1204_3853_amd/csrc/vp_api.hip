@@ -1,0 +1,345 @@
+// Host runtime and C ABI of the MI355X Vlasov-Poisson library: plan
+// creation and validation, workspace layout, and the enqueue sequences of
+// the entry points declared in include/vp.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Periodic Green's function of (S + S^-1 - 14) on n cells:
+//   g_k = c (r^k + r^(n-k)) / (1 - r^n),  r = 1 / (7 + sqrt 48),  c = -1 / (1/r - r),
+// the sum over periodic images of the free-space solution c r^|k|.
+std::vector<double> tridiag_green(int n, int taps)
+{
+    const double r = 1.0 / (7.0 + std::sqrt(48.0));
+    const double c = -1.0 / (1.0 / r - r);
+    const double rn = std::pow(r, n);
+    const int cnt = (n <= 2 * taps + 1) ? n : taps + 1;
+    std::vector<double> g(cnt);
+    for (int k = 0; k < cnt; ++k) g[k] = c * (std::pow(r, k) + std::pow(r, n - k)) / (1.0 - rn);
+    return g;
+}
+constexpr int kGreenTaps = 20;   // r^20 ~ 1.6e-23: truncation far below FP64 rounding
+
+StageShape pick_shape(const vp_plan* p, std::initializer_list<const void*> ptrs)
+{
+    bool al = true;
+    for (const void* q : ptrs)
+        if (q && !aligned16(q)) al = false;
+    if (p->dtype == VP_F64) {
+        if (al && p->nv % 2 == 0) return p->shape;
+        return StageShape{128, 1, p->shape.tx};
+    }
+    if (al && p->nv % 4 == 0) return p->shape;
+    return StageShape{128, 1, p->shape.tx};
+}
+
+int strips_for(const vp_plan* p, const StageShape& sh)
+{
+    const int tv = sh.nt * sh.w;
+    return (p->nv + tv - 1) / tv;
+}
+
+char* wsp(void* work, size_t off) { return static_cast<char*>(work) + off; }
+
+Stage1DArgs base_args(const vp_plan* p, const StageShape& sh)
+{
+    Stage1DArgs a{};
+    a.nx = p->nx;
+    a.nv = p->nv;
+    a.tx = sh.tx;
+    a.nstrip = strips_for(p, sh);
+    a.dxi = 1.0 / p->dx;
+    a.dvi = 1.0 / p->dv;
+    a.dv24 = p->dv / 24.0;
+    a.v_lo = p->v_lo;
+    a.dv = p->dv;
+    for (int q = 0; q < 4; ++q) a.vg[q] = p->vg[q];
+    return a;
+}
+
+vp_status check_plan(const vp_plan* p)
+{
+    if (!p) return fail(VP_EINVAL, "plan is NULL");
+    return VP_OK;
+}
+
+// one RK4 step; stage states go to st[0..2] (or the workspace ping-pong
+// buffers) and stage accelerations to sa[0..3] (or in place in `a`)
+vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, void* st_f,
+                 double* st_a, hipStream_t stream)
+{
+    const size_t sb = p->state_elems * p->esize;
+    void* acc = wsp(work, p->ws_acc);
+    void* s2 = st_f ? st_f : wsp(work, p->ws_fsa);
+    void* s3 = st_f ? static_cast<char*>(st_f) + sb : wsp(work, p->ws_fsb);
+    void* s4 = st_f ? static_cast<char*>(st_f) + 2 * sb : wsp(work, p->ws_fsa);
+    double* part = reinterpret_cast<double*>(wsp(work, p->ws_part));
+    const StageShape sh = pick_shape(p, {f, acc, s2, s3, s4});
+    Stage1DArgs A = base_args(p, sh);
+    A.part = part;
+    const double cacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    const double cnext[3] = {0.5 * dt, 0.5 * dt, dt};
+    double* sa[5] = {a, a, a, a, a};
+    if (st_a) {
+        VP_HIP(hipMemcpyAsync(st_a, a, sizeof(double) * p->nx, hipMemcpyDeviceToDevice, stream));
+        for (int s = 0; s < 4; ++s) sa[s] = st_a + (size_t)s * p->nx;
+    }
+    const void* in[4] = {f, s2, s3, s4};
+    void* out[4] = {s2, s3, s4, f};
+    for (int s = 0; s < 4; ++s) {
+        A.fs = in[s];
+        A.fn = f;
+        A.acc = acc;
+        A.fout = out[s];
+        A.a = sa[s];
+        A.c_acc = cacc[s];
+        A.c_next = s < 3 ? cnext[s] : 0.0;
+        const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
+        VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage1d(p->dtype, sh, kind, A, stream); }));
+        double* a_next = (s < 3) ? sa[s + 1] : a;
+        VP_HIP(timed(p, kTField, stream, [&] {
+            return launch_poisson1d(part, A.nstrip, nullptr, p->dv, p->nx, p->dx, p->pb.qm, p->d_green, p->gk,
+                                    nullptr, nullptr, nullptr, a_next, stream);
+        }));
+    }
+    return VP_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+vp_status fail(vp_status code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+vp_status hip_fail(hipError_t e, const char* what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return VP_EHIP;
+}
+
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" {
+
+const char* vp_last_error(void) { return g_last_error.c_str(); }
+
+vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox, vp_plan** out)
+{
+    if (!pb || !out) return fail(VP_EINVAL, "vp_plan_create: NULL problem or output pointer");
+    *out = nullptr;
+    if (pb->ndim != 1 && pb->ndim != 2) return fail(VP_EINVAL, "ndim must be 1 or 2");
+    if (pb->dtype != VP_F64 && pb->dtype != VP_F32) return fail(VP_EDTYPE, "dtype must be VP_F64 or VP_F32");
+    if (pb->n_levels < 1 || pb->n_levels > VP_MAX_LEVELS) return fail(VP_EINVAL, "n_levels must be 1 or 2");
+    if (nbox < 0 || (nbox > 0 && !boxes)) return fail(VP_EINVAL, "bad box list");
+    const int nd = 2 * pb->ndim;
+    for (int d = 0; d < nd; ++d)
+        if (pb->cells[d] < 1) return fail(VP_EINVAL, "cells must be positive");
+    for (int d = 0; d < pb->ndim; ++d) {
+        if (!(pb->x_len[d] > 0.0)) return fail(VP_EINVAL, "x_len must be positive");
+        if (!(pb->v_hi[d] > pb->v_lo[d])) return fail(VP_EINVAL, "v_hi must exceed v_lo");
+        if (!pb->veq[0][d]) return fail(VP_EINVAL, "veq[0][d] (equilibrium with ghosts) is required");
+    }
+    if (pb->ndim != 1 || pb->n_levels != 1 || nbox != 0)
+        return fail(VP_ENOTSUP, "this call sequence supports the single-level 1D+1V problem");
+
+    vp_plan* p = new (std::nothrow) vp_plan();
+    if (!p) return fail(VP_ENOMEM, "out of host memory");
+    p->pb = *pb;
+    p->ndim = pb->ndim;
+    p->dtype = pb->dtype;
+    p->nlev = pb->n_levels;
+    p->esize = pb->dtype == VP_F64 ? 8 : 4;
+    p->nx = pb->cells[0];
+    p->nv = pb->cells[1];
+    p->dx = pb->x_len[0] / p->nx;
+    p->dv = (pb->v_hi[0] - pb->v_lo[0]) / p->nv;
+    p->v_lo = pb->v_lo[0];
+    p->veq[0][0].assign(pb->veq[0][0], pb->veq[0][0] + p->nv + 4);
+    p->vg[0] = p->veq[0][0][0];
+    p->vg[1] = p->veq[0][0][1];
+    p->vg[2] = p->veq[0][0][p->nv + 2];
+    p->vg[3] = p->veq[0][0][p->nv + 3];
+    for (int l = 0; l < VP_MAX_LEVELS; ++l)
+        for (int d = 0; d < 2; ++d) p->pb.veq[l][d] = nullptr;
+    if (p->nx > kMaxPoisson1D) {
+        delete p;
+        return fail(VP_ENOTSUP, "configuration mesh larger than 8192 cells");
+    }
+    p->shape = p->dtype == VP_F64 ? StageShape{128, 2, 32} : StageShape{64, 4, 32};
+    p->state_elems = (size_t)p->nx * p->nv;
+
+    // Poisson tables
+    std::vector<double> g = tridiag_green(p->nx, kGreenTaps);
+    p->gk = kGreenTaps;
+    hipError_t e = hipMalloc(&p->d_green, g.size() * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_green, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = poisson1d_prepare();
+    if (e != hipSuccess) {
+        vp_status st = hip_fail(e, "vp_plan_create: Poisson tables");
+        if (p->d_green) (void)hipFree(p->d_green);
+        delete p;
+        return st;
+    }
+
+    // workspace: acc, two predictor buffers, moment partials, config scratch
+    const size_t sb = align256(p->state_elems * p->esize);
+    const int max_strips = (p->nv + 63) / 64;
+    size_t off = 0;
+    p->ws_acc = off; off += sb;
+    p->ws_fsa = off; off += sb;
+    p->ws_fsb = off; off += sb;
+    p->ws_part = off; off += align256((size_t)max_strips * p->nx * sizeof(double));
+    p->ws_cfg = off; off += align256((size_t)4 * p->nx * sizeof(double));
+    p->ws_total = off;
+    *out = p;
+    return VP_OK;
+}
+
+vp_status vp_timing_enable(vp_plan* p, int32_t enable)
+{
+    if (vp_status s = check_plan(p)) return s;
+    Timing& T = p->timing;
+    if (enable && T.ev.empty()) {
+        T.ev.resize(2 * Timing::kMaxRecords, nullptr);
+        T.cls.resize(Timing::kMaxRecords, 0);
+        for (auto& e : T.ev) VP_HIP(hipEventCreate(&e));
+    }
+    T.enabled = enable != 0;
+    T.used = 0;
+    return VP_OK;
+}
+
+vp_status vp_timing_read(vp_plan* p, double* ms, int64_t* counts, int32_t nclass)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!ms || !counts || nclass < 1) return fail(VP_EINVAL, "vp_timing_read: bad output arrays");
+    for (int c = 0; c < nclass; ++c) { ms[c] = 0.0; counts[c] = 0; }
+    Timing& T = p->timing;
+    for (int r = 0; r < T.used; ++r) {
+        VP_HIP(hipEventSynchronize(T.ev[2 * r + 1]));
+        float t = 0.f;
+        VP_HIP(hipEventElapsedTime(&t, T.ev[2 * r], T.ev[2 * r + 1]));
+        const int c = T.cls[r];
+        if (c < nclass) { ms[c] += t; counts[c] += 1; }
+    }
+    T.used = 0;
+    return VP_OK;
+}
+
+vp_status vp_plan_destroy(vp_plan* p)
+{
+    if (!p) return VP_OK;
+    for (auto& e : p->timing.ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->d_green) (void)hipFree(p->d_green);
+    delete p;
+    return VP_OK;
+}
+
+size_t vp_state_elems(const vp_plan* p) { return p ? p->state_elems : 0; }
+int64_t vp_patch_offset(const vp_plan* p, int32_t patch) { return (p && patch == -1) ? 0 : -1; }
+size_t vp_config_elems(const vp_plan* p) { return p ? (size_t)p->nx : 0; }
+size_t vp_field_elems(const vp_plan* p) { return p ? (size_t)p->nx : 0; }
+size_t vp_workspace_bytes(const vp_plan* p) { return p ? p->ws_total : 0; }
+
+size_t vp_stage_elems(const vp_plan* p)
+{
+    if (!p) return 0;
+    const size_t a_bytes = 4 * (size_t)p->nx * sizeof(double);
+    return 3 * p->state_elems + (a_bytes + p->esize - 1) / p->esize;
+}
+
+vp_status vp_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!f || !a || !k) return fail(VP_EINVAL, "vp_rhs: NULL pointer");
+    if (f == k) return fail(VP_EINVAL, "vp_rhs: k must not alias f");
+    const StageShape sh = pick_shape(p, {f, k});
+    Stage1DArgs A = base_args(p, sh);
+    A.fs = f;
+    A.fout = k;
+    A.a = a;
+    VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage1d(p->dtype, sh, kRhs, A, stream); }));
+    return VP_OK;
+}
+
+vp_status vp_reduce_moment(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream)
+{
+    (void)work;
+    if (vp_status s = check_plan(p)) return s;
+    if (!f || !n) return fail(VP_EINVAL, "vp_reduce_moment: NULL pointer");
+    VP_HIP(timed(p, kTMoment, stream, [&] { return launch_moment_rows(p->dtype, f, p->nx, p->nv, p->dv, n, stream); }));
+    return VP_OK;
+}
+
+vp_status vp_poisson_periodic(const vp_plan* p, const double* n, double* phi, double* E, void* work,
+                              hipStream_t stream)
+{
+    (void)work;
+    if (vp_status s = check_plan(p)) return s;
+    if (!n) return fail(VP_EINVAL, "vp_poisson_periodic: NULL n");
+    VP_HIP(timed(p, kTField, stream, [&] {
+        return launch_poisson1d(nullptr, 0, n, p->dv, p->nx, p->dx, p->pb.qm, p->d_green, p->gk, nullptr, phi, E,
+                                nullptr, stream);
+    }));
+    return VP_OK;
+}
+
+vp_status vp_inject_field(const vp_plan* p, const double* E, double* a, hipStream_t stream)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!E || !a) return fail(VP_EINVAL, "vp_inject_field: NULL pointer");
+    VP_HIP(timed(p, kTOther, stream, [&] { return launch_scale(E, p->pb.qm, a, p->nx, stream); }));
+    return VP_OK;
+}
+
+vp_status vp_rk4_step(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!f || !a || !work) return fail(VP_EINVAL, "vp_rk4_step: NULL pointer");
+    if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step: dt is not finite");
+    return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
+}
+
+vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, void* stages, void* work,
+                             hipStream_t stream)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!f || !a || !work || !stages) return fail(VP_EINVAL, "vp_rk4_step_record: NULL pointer");
+    if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_record: dt is not finite");
+    double* st_a = reinterpret_cast<double*>(static_cast<char*>(stages) + 3 * p->state_elems * p->esize);
+    if (reinterpret_cast<uintptr_t>(st_a) % 8) return fail(VP_EINVAL, "stage record misaligned");
+    return rk4_1d(p, f, a, dt, work, stages, st_a, stream);
+}
+
+vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, const void* stages,
+                          const void* lam_np1, void* lam_n, double dt, void* work, hipStream_t stream)
+{
+    (void)f_n; (void)a_n; (void)stages; (void)lam_np1; (void)lam_n; (void)dt; (void)work; (void)stream;
+    if (vp_status s = check_plan(p)) return s;
+    return fail(VP_ENOTSUP, "vp_adjoint_step: not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,284 @@
+"""Python binding of the MI355X Vlasov-Poisson library (include/vp.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libvp.so.  Device memory and streams come from PyTorch; arrays
+are passed to the C ABI as raw pointers of contiguous tensors, and work is
+enqueued on torch's current stream.  There is no CPU fallback: if the
+library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvp.so")
+
+VP_F64, VP_F32 = 0, 1
+VP_MAX_LEVELS = 2
+_STATUS = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ESHAPE", 3: "VP_EDTYPE", 4: "VP_ENOTSUP", 5: "VP_EHIP",
+           6: "VP_ENOMEM"}
+
+
+class VPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class vp_problem(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("n_levels", ctypes.c_int32),
+        ("cells", ctypes.c_int32 * 4),
+        ("ratio", ctypes.c_int32 * 4),
+        ("x_lo", ctypes.c_double * 2),
+        ("x_len", ctypes.c_double * 2),
+        ("v_lo", ctypes.c_double * 2),
+        ("v_hi", ctypes.c_double * 2),
+        ("qm", ctypes.c_double),
+        ("veq", (ctypes.POINTER(ctypes.c_double) * 2) * VP_MAX_LEVELS),
+    ]
+
+
+class vp_box(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("lo", ctypes.c_int32 * 4), ("hi", ctypes.c_int32 * 4)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_S = ctypes.c_size_t
+
+SIGNATURES = {
+    "vp_plan_create": (ctypes.c_int, [ctypes.POINTER(vp_problem), ctypes.POINTER(vp_box), ctypes.c_int32,
+                                      ctypes.POINTER(_P)]),
+    "vp_plan_destroy": (ctypes.c_int, [_P]),
+    "vp_last_error": (ctypes.c_char_p, []),
+    "vp_state_elems": (_S, [_P]),
+    "vp_patch_offset": (ctypes.c_int64, [_P, ctypes.c_int32]),
+    "vp_config_elems": (_S, [_P]),
+    "vp_field_elems": (_S, [_P]),
+    "vp_workspace_bytes": (_S, [_P]),
+    "vp_stage_elems": (_S, [_P]),
+    "vp_rhs": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "vp_reduce_moment": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "vp_poisson_periodic": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "vp_inject_field": (ctypes.c_int, [_P, _P, _P, _P]),
+    "vp_rk4_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P]),
+    "vp_rk4_step_record": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P]),
+    "vp_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P, _P]),
+    "vp_timing_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int32]),
+}
+
+TIMING_CLASSES = ["stage", "field", "moment", "sync", "adjoint", "other"]
+
+
+def lib():
+    """Load libvp.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise VPError(code, lib().vp_last_error().decode(errors="replace"))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Plan:
+    """An immutable plan (vp_plan) plus the device workspace used by its calls.
+
+    problem: a vp_inputs.Problem1D-like object (nx, nv, x_lo, x_len, v_lo,
+    v_hi, qm, veq) or a dict with the fields of vp_problem.
+    """
+
+    def __init__(self, problem, dtype=torch.float64, boxes=None, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the Vlasov-Poisson library needs a HIP GPU (torch.cuda is unavailable)")
+        self.device = torch.device(device)
+        self.dtype = dtype
+        pb = vp_problem()
+        self._keep = []
+        spec = problem if isinstance(problem, dict) else _problem_dict(problem)
+        pb.ndim = spec["ndim"]
+        pb.dtype = VP_F64 if dtype == torch.float64 else VP_F32
+        pb.n_levels = spec.get("n_levels", 1)
+        for d, c in enumerate(spec["cells"]):
+            pb.cells[d] = c
+        for d, r in enumerate(spec.get("ratio", [1, 1, 1, 1])):
+            pb.ratio[d] = r
+        for d in range(spec["ndim"]):
+            pb.x_lo[d] = spec["x_lo"][d]
+            pb.x_len[d] = spec["x_len"][d]
+            pb.v_lo[d] = spec["v_lo"][d]
+            pb.v_hi[d] = spec["v_hi"][d]
+        pb.qm = spec["qm"]
+        for lvl, dirs in enumerate(spec["veq"]):
+            for d, arr in enumerate(dirs):
+                buf = (ctypes.c_double * len(arr))(*[float(x) for x in arr])
+                self._keep.append(buf)
+                pb.veq[lvl][d] = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+        self.spec = spec
+        nbox = 0
+        bx = None
+        if boxes:
+            nbox = len(boxes)
+            bx = (vp_box * nbox)()
+            for q, b in enumerate(boxes):
+                bx[q].level = b.get("level", 1)
+                for d, v in enumerate(b["lo"]):
+                    bx[q].lo[d] = v
+                for d, v in enumerate(b["hi"]):
+                    bx[q].hi[d] = v
+        h = ctypes.c_void_p()
+        _check(lib().vp_plan_create(ctypes.byref(pb), bx, nbox, ctypes.byref(h)))
+        self.h = h
+        L = lib()
+        self.state_elems = L.vp_state_elems(h)
+        self.config_elems = L.vp_config_elems(h)
+        self.field_elems = L.vp_field_elems(h)
+        self.workspace_bytes = L.vp_workspace_bytes(h)
+        self.stage_elems = L.vp_stage_elems(h)
+        self.work = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.vp_plan_destroy(self.h)
+            self.h = None
+
+    def timing_enable(self, enable=True):
+        _check(lib().vp_timing_enable(self.h, int(enable)))
+
+    def timing_read(self):
+        """{class: (total ms, launches)} since the last read; clears the record."""
+        n = len(TIMING_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(lib().vp_timing_read(self.h, ms, cnt, n))
+        return {c: (ms[i], cnt[i]) for i, c in enumerate(TIMING_CLASSES)}
+
+    def patch_offset(self, p):
+        return lib().vp_patch_offset(self.h, p)
+
+    # ---------------------------------------------------------------- checks
+    def _state(self, t, name):
+        if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and t.numel() == self.state_elems):
+            raise ValueError(f"{name}: expected a contiguous {self.dtype} CUDA tensor of {self.state_elems} "
+                             f"elements, got {t.dtype} {tuple(t.shape)} on {t.device}")
+        return t
+
+    def _cfg(self, t, name, n):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor of {n} elements")
+        return t
+
+
+def _problem_dict(p):
+    """Problem spec from a vp_inputs.Problem1D / Problem2D."""
+    if hasattr(p, "nvx"):
+        return {"ndim": 2, "cells": [p.nx, p.ny, p.nvx, p.nvy], "x_lo": [0.0, 0.0],
+                "x_len": [p.x_len, p.y_len], "v_lo": [p.v_lo, p.v_lo], "v_hi": [p.v_hi, p.v_hi],
+                "qm": p.qm, "veq": [[p.veq_x, p.veq_y]]}
+    return {"ndim": 1, "cells": [p.nx, p.nv], "x_lo": [p.x_lo], "x_len": [p.x_len], "v_lo": [p.v_lo],
+            "v_hi": [p.v_hi], "qm": p.qm, "veq": [[p.veq]]}
+
+
+# -------------------------------------------------------------------- entry points
+
+
+def rhs(plan, f, a, k=None):
+    plan._state(f, "f")
+    plan._cfg(a, "a", plan.field_elems)
+    if k is None:
+        k = torch.empty_like(f)
+    plan._state(k, "k")
+    _check(lib().vp_rhs(plan.h, _ptr(f), _ptr(a), _ptr(k), _stream()))
+    return k
+
+
+def reduce_moment(plan, f, n=None):
+    plan._state(f, "f")
+    if n is None:
+        n = torch.empty(plan.config_elems, dtype=torch.float64, device=f.device)
+    plan._cfg(n, "n", plan.config_elems)
+    _check(lib().vp_reduce_moment(plan.h, _ptr(f), _ptr(n), _ptr(plan.work), _stream()))
+    return n
+
+
+def poisson_periodic(plan, n, phi=None, E=None):
+    ndir = plan.spec["ndim"]
+    plan._cfg(n, "n", plan.config_elems)
+    if phi is None:
+        phi = torch.empty(plan.config_elems, dtype=torch.float64, device=n.device)
+    if E is None:
+        E = torch.empty(plan.config_elems * ndir, dtype=torch.float64, device=n.device)
+    plan._cfg(phi, "phi", plan.config_elems)
+    plan._cfg(E, "E", plan.config_elems * ndir)
+    _check(lib().vp_poisson_periodic(plan.h, _ptr(n), _ptr(phi), _ptr(E), _ptr(plan.work), _stream()))
+    return phi, E
+
+
+def inject_field(plan, E, a=None):
+    if a is None:
+        a = torch.empty(plan.field_elems, dtype=torch.float64, device=E.device)
+    plan._cfg(a, "a", plan.field_elems)
+    _check(lib().vp_inject_field(plan.h, _ptr(E), _ptr(a), _stream()))
+    return a
+
+
+def field_of(plan, f):
+    """a = (q/m) E(f): moment, Poisson and injection in sequence."""
+    n = reduce_moment(plan, f)
+    _, E = poisson_periodic(plan, n)
+    return inject_field(plan, E)
+
+
+def rk4_step(plan, f, a, dt):
+    plan._state(f, "f")
+    plan._cfg(a, "a", plan.field_elems)
+    _check(lib().vp_rk4_step(plan.h, _ptr(f), _ptr(a), ctypes.c_double(dt), _ptr(plan.work), _stream()))
+    return f, a
+
+
+def rk4_step_record(plan, f, a, dt, stages=None):
+    plan._state(f, "f")
+    plan._cfg(a, "a", plan.field_elems)
+    if stages is None:
+        stages = torch.empty(plan.stage_elems, dtype=plan.dtype, device=f.device)
+    _check(lib().vp_rk4_step_record(plan.h, _ptr(f), _ptr(a), ctypes.c_double(dt), _ptr(stages),
+                                    _ptr(plan.work), _stream()))
+    return f, a, stages
+
+
+def adjoint_step(plan, f_n, a_n, lam_np1, dt, stages=None, lam_n=None):
+    plan._state(f_n, "f_n")
+    plan._cfg(a_n, "a_n", plan.field_elems)
+    plan._state(lam_np1, "lam_np1")
+    if lam_n is None:
+        lam_n = torch.empty_like(lam_np1)
+    _check(lib().vp_adjoint_step(plan.h, _ptr(f_n), _ptr(a_n), _ptr(stages), _ptr(lam_np1), _ptr(lam_n),
+                                 ctypes.c_double(dt), _ptr(plan.work), _stream()))
+    return lam_n
