@@ -226,6 +226,19 @@ vp_status vp_adjoint_step(const vp_plan* plan, const void* f_n, const double* a_
                           void* work, hipStream_t stream);
 
 /*
+ * Tile shapes of the stage kernels, for autotuning.  A shape is (threads
+ * per block, velocity cells per thread, configuration rows per tile).
+ * vp_tile_shape_count / _get enumerate the shapes compiled for the plan's
+ * dtype; vp_tile_shape_set selects one for every later call on the plan
+ * (results agree to rounding for every shape; only speed changes).  Not safe
+ * to call while other calls on the same plan are being enqueued.
+ */
+int32_t vp_tile_shape_count(const vp_plan* plan);
+vp_status vp_tile_shape_get(const vp_plan* plan, int32_t index, int32_t* threads, int32_t* cells,
+                            int32_t* rows);
+vp_status vp_tile_shape_set(vp_plan* plan, int32_t index);
+
+/*
  * Kernel timing (a profiling aid, per-routine exclusive timers): while
  * enabled, every launch made by this plan is bracketed by a pair of HIP
  * events recorded on the launch's stream.  vp_timing_read synchronises on

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvp.so")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950",
+    "--offload-arch=gfx950:xnack-",
     "-O3",
     "-std=c++17",
     "-fPIC",

@@ -33,7 +33,23 @@ std::vector<double> tridiag_green(int n, int taps)
     for (int k = 0; k < cnt; ++k) g[k] = c * (std::pow(r, k) + std::pow(r, n - k)) / (1.0 - rn);
     return g;
 }
-constexpr int kGreenTaps = 20;   // r^20 ~ 1.6e-23: truncation far below FP64 rounding
+
+// shapes compiled into the stage-kernel dispatch, per dtype
+const int kTxChoices[] = {8, 16, 32, 64, 128};
+std::vector<StageShape> shape_table(int dtype)
+{
+    std::vector<StageShape> v;
+    const int nw[][2] = {{64, 2}, {128, 2}, {256, 2}};
+    const int nwf[][2] = {{64, 4}, {128, 4}};
+    if (dtype == VP_F64) {
+        for (auto& a : nw)
+            for (int tx : kTxChoices) v.push_back(StageShape{a[0], a[1], tx});
+    } else {
+        for (auto& a : nwf)
+            for (int tx : kTxChoices) v.push_back(StageShape{a[0], a[1], tx});
+    }
+    return v;
+}
 
 StageShape pick_shape(const vp_plan* p, std::initializer_list<const void*> ptrs)
 {
@@ -89,6 +105,7 @@ vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, vo
     void* s3 = st_f ? static_cast<char*>(st_f) + sb : wsp(work, p->ws_fsb);
     void* s4 = st_f ? static_cast<char*>(st_f) + 2 * sb : wsp(work, p->ws_fsa);
     double* part = reinterpret_cast<double*>(wsp(work, p->ws_part));
+    double* ncfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
     const StageShape sh = pick_shape(p, {f, acc, s2, s3, s4});
     Stage1DArgs A = base_args(p, sh);
     A.part = part;
@@ -114,7 +131,7 @@ vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, vo
         double* a_next = (s < 3) ? sa[s + 1] : a;
         VP_HIP(timed(p, kTField, stream, [&] {
             return launch_poisson1d(part, A.nstrip, nullptr, p->dv, p->nx, p->dx, p->pb.qm, p->d_green, p->gk,
-                                    nullptr, nullptr, nullptr, a_next, stream);
+                                    ncfg, nullptr, nullptr, a_next, stream);
         }));
     }
     return VP_OK;
@@ -186,7 +203,7 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
         delete p;
         return fail(VP_ENOTSUP, "configuration mesh larger than 8192 cells");
     }
-    p->shape = p->dtype == VP_F64 ? StageShape{128, 2, 32} : StageShape{64, 4, 32};
+    p->shape = p->dtype == VP_F64 ? StageShape{256, 2, 16} : StageShape{128, 4, 16};
     p->state_elems = (size_t)p->nx * p->nv;
 
     // Poisson tables
@@ -214,6 +231,31 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
     p->ws_cfg = off; off += align256((size_t)4 * p->nx * sizeof(double));
     p->ws_total = off;
     *out = p;
+    return VP_OK;
+}
+
+int32_t vp_tile_shape_count(const vp_plan* p)
+{
+    return p ? (int32_t)shape_table(p->dtype).size() : 0;
+}
+
+vp_status vp_tile_shape_get(const vp_plan* p, int32_t index, int32_t* threads, int32_t* cells, int32_t* rows)
+{
+    if (vp_status s = check_plan(p)) return s;
+    const auto tab = shape_table(p->dtype);
+    if (index < 0 || index >= (int32_t)tab.size()) return fail(VP_EINVAL, "vp_tile_shape_get: index out of range");
+    if (threads) *threads = tab[index].nt;
+    if (cells) *cells = tab[index].w;
+    if (rows) *rows = tab[index].tx;
+    return VP_OK;
+}
+
+vp_status vp_tile_shape_set(vp_plan* p, int32_t index)
+{
+    if (vp_status s = check_plan(p)) return s;
+    const auto tab = shape_table(p->dtype);
+    if (index < 0 || index >= (int32_t)tab.size()) return fail(VP_EINVAL, "vp_tile_shape_set: index out of range");
+    p->shape = tab[index];
     return VP_OK;
 }
 

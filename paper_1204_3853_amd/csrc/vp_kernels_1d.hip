@@ -91,15 +91,24 @@ __device__ __forceinline__ T face4(T um1, T u0, T u1, T u2)
     return (T(7) * (u0 + u1) - (um1 + u2)) * T(1.0 / 12.0);
 }
 
+// Stage kernel.  A block owns a strip of TV = NT*W velocity cells and a
+// segment of configuration rows [i0, i1).  The march proceeds in batches
+// of RB rows: all loads of a batch (RB new rows of the stage state plus the
+// f^n / accumulator rows being updated) are issued together, so each wave
+// keeps RB rows of traffic in flight; the rows go through an 8-slot LDS
+// ring that holds the stencil's x-neighbourhood rows i-2 .. i+RB+1.
 template <typename T, int W, int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_stage1d(Stage1DArgs A)
 {
+    constexpr int RB = 4;                                    // rows per batch
+    constexpr int NSLOT = 8;                                 // ring rows (>= RB + 4)
     constexpr int TV = NT * W;
     constexpr int LPAD = (W > 2) ? W : 2;                    // keeps own data W-aligned in LDS
     constexpr int RW = ((LPAD + TV + 2 + 3) / 4) * 4;
     constexpr int NWAVE = NT / 64;
-    __shared__ __attribute__((aligned(16))) T ring[5][RW];
+    __shared__ __attribute__((aligned(16))) T ring[NSLOT][RW];
     __shared__ double mom[NWAVE][kMaxTx];
+    __shared__ double aseg[kMaxTx + RB + 2];   // a_{i0-1} .. a_{i1}, then padding
 
     const T* __restrict__ fs = static_cast<const T*>(A.fs);
     const T* __restrict__ fn = static_cast<const T*>(A.fn);
@@ -117,55 +126,51 @@ __global__ __launch_bounds__(NT) void k_stage1d(Stage1DArgs A)
     const int t = threadIdx.x;
     const int jt = j0 + t * W;
     const bool own_in = jt < nv;          // nv % W == 0 for W > 1, so the whole vector is in range
+    const int jld = own_in ? jt : 0;      // out-of-range threads load a valid cell and discard it
     const int lane = t & 63, wave = t >> 6;
+    const int c0 = LPAD + t * W;          // LDS column of the first own cell
 
-    // register copy of one row of the stage state: own cells + halo cells
-    T cur[W];
-    T curh[2] = {T(0), T(0)};
-    auto load_row = [&](int r) {
-        const T* row = fs + (size_t)r * nv;
-        if (own_in) {
-            VecIO<T, W>::ld(row + jt, cur);
-        } else {
+    // values of own cells that lie outside [0, nv): velocity ghosts or unused
+    T oconst[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) cur[w] = ghost_val(row, jt + w, nv, A.vg);
-        }
-        if (t == 0) {
-            curh[0] = ghost_val(row, j0 - 2, nv, A.vg);
-            curh[1] = ghost_val(row, j0 - 1, nv, A.vg);
-        } else if (t == NT - 1) {
-            curh[0] = ghost_val(row, j0 + TV, nv, A.vg);
-            curh[1] = ghost_val(row, j0 + TV + 1, nv, A.vg);
-        }
-    };
-    auto store_row = [&](int slot) {
-        T* dst = &ring[slot][0];
-#pragma unroll
-        for (int w = 0; w < W; ++w) dst[LPAD + t * W + w] = cur[w];
-        if (t == 0) {
-            dst[LPAD - 2] = curh[0];
-            dst[LPAD - 1] = curh[1];
-        } else if (t == NT - 1) {
-            dst[LPAD + TV] = curh[0];
-            dst[LPAD + TV + 1] = curh[1];
-        }
-    };
-    // LDS column index of global velocity cell j
-    const int c0 = LPAD + t * W;   // own first cell
+    for (int w = 0; w < W; ++w) {
+        const int j = jt + w;
+        oconst[w] = (j == nv) ? (T)A.vg[2] : (j == nv + 1) ? (T)A.vg[3] : T(0);
+    }
+    // threads 0..3 also stage one strip-halo cell: j0-2, j0-1, j0+TV, j0+TV+1
+    const bool has_halo = t < 4;
+    const int hj = t < 2 ? j0 - 2 + t : j0 + TV + (t - 2);
+    const int hcol = t < 2 ? LPAD - 2 + t : LPAD + TV + (t - 2);
+    const bool halo_in = has_halo && hj >= 0 && hj < nv;
+    const int hld = halo_in ? hj : jld;
+    const T hconst = (hj == -2) ? (T)A.vg[0] : (hj == -1) ? (T)A.vg[1] : (hj == nv) ? (T)A.vg[2]
+                   : (hj == nv + 1) ? (T)A.vg[3] : T(0);
 
-    // face average along x at columns jt-1 .. jt+W of face (row r1 - 1/2 .. ) from 4 ring rows
-    auto fx_cols = [&](int sm1, int s0, int s1, int s2, T* Fx) {
+    auto slot_of = [&](int r) { return (r - i0 + 2) & (NSLOT - 1); };   // r >= i0 - 2
+    auto load_row = [&](int r, T* v, T& h) {
+        const T* row = fs + (size_t)wrapi(r, nx) * nv;
+        VecIO<T, W>::ld(row + jld, v);
+        h = row[hld];
+    };
+    auto store_row = [&](int r, const T* v, T h) {
+        T* dst = &ring[slot_of(r)][0];
+#pragma unroll
+        for (int w = 0; w < W; ++w) dst[c0 + w] = own_in ? v[w] : oconst[w];
+        if (has_halo) dst[hcol] = halo_in ? h : hconst;
+    };
+    auto fx_cols = [&](int r, T* Fx) {      // x-face r + 1/2 at columns jt-1 .. jt+W
+        const int sm1 = slot_of(r - 1), s0 = slot_of(r), s1 = slot_of(r + 1), s2 = slot_of(r + 2);
 #pragma unroll
         for (int q = 0; q < W + 2; ++q) {
             const int c = c0 - 1 + q;
             Fx[q] = face4<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c]);
         }
     };
-    // face average along v at faces jt-1/2 .. jt+W-1/2 of one ring row
-    auto fv_faces = [&](int s, T* Fv) {
+    auto fv_faces = [&](int r, T* Fv) {     // v-faces jt-1/2 .. jt+W-1/2 of row r
+        const int sl = slot_of(r);
         T u[W + 4];
 #pragma unroll
-        for (int q = 0; q < W + 4; ++q) u[q] = ring[s][c0 - 2 + q];
+        for (int q = 0; q < W + 4; ++q) u[q] = ring[sl][c0 - 2 + q];
 #pragma unroll
         for (int m = 0; m <= W; ++m) Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
     };
@@ -174,114 +179,132 @@ __global__ __launch_bounds__(NT) void k_stage1d(Stage1DArgs A)
 #pragma unroll
     for (int w = 0; w < W; ++w) vb[w] = (T)(A.v_lo + ((double)(jt + w) + 0.5) * A.dv);
     const T dxi = (T)A.dxi, dvi = (T)A.dvi, dv24 = (T)A.dv24;
+    const T cacc = (T)A.c_acc, cnext = (T)A.c_next;
 
-    // ---- prologue: rows i0-2 .. i0+1 into slots 0..3
-#pragma unroll 1
-    for (int q = 0; q < 4; ++q) {
-        load_row(wrapi(i0 - 2 + q, nx));
-        store_row(q);
+    // ---- prologue: rows i0-2 .. i0+1
+    {
+        T v[4][W], h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) load_row(i0 - 2 + q, v[q], h[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) store_row(i0 - 2 + q, v[q], h[q]);
     }
-    if (i0 < i1) load_row(wrapi(i0 + 2, nx));
+    for (int q = t; q < i1 - i0 + 2; q += NT) aseg[q] = av[wrapi(i0 - 1 + q, nx)];
+    for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
     __syncthreads();
 
     T gx_old[W];
     {
         T Fx[W + 2];
-        fx_cols(0, 1, 2, 3, Fx);
+        fx_cols(i0 - 1, Fx);
 #pragma unroll
         for (int w = 0; w < W; ++w) gx_old[w] = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
     }
     T fvA[W + 1], fvB[W + 1];
-    fv_faces(1, fvA);
-    fv_faces(2, fvB);
-    T a_m1 = (T)av[wrapi(i0 - 1, nx)];
-    T a_0 = (T)av[i0 < nx ? i0 : 0];
+    fv_faces(i0 - 1, fvA);
+    fv_faces(i0, fvB);
 
 #pragma unroll 1
-    for (int i = i0; i < i1; ++i) {
-        const int q = i - i0;
-        const int s_m1 = (q + 1) % 5, s_0 = (q + 2) % 5, s_p1 = (q + 3) % 5, s_p2 = (q + 4) % 5;
-        store_row(s_p2);
-        if (i + 1 < i1) load_row(wrapi(i + 3, nx));
-
-        T fnv[W], accv[W];
-        const size_t rowoff = (size_t)i * nv + jt;
-        if (KIND == kStage23 && own_in) VecIO<T, W>::ld(fn + rowoff, fnv);
-        if ((KIND == kStage23 || KIND == kStage4) && own_in) VecIO<T, W>::ld(acc + rowoff, accv);
-        const T a_p1 = (T)av[wrapi(i + 1, nx)];
-
+    for (int ib = i0; ib < i1; ib += RB) {
+        // issue every load of the batch; indices past the segment are clamped
+        // so that all loads and their uses are unconditional
+        T v[RB][W], h[RB], fnv[RB][W], accv[RB][W];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            load_row(min(ib + 2 + q, i1 + 1), v[q], h[q]);      // new stage-state row
+            const size_t off = (size_t)min(ib + q, i1 - 1) * nv + jld;
+            if (KIND == kStage23) VecIO<T, W>::ld(fn + off, fnv[q]);
+            if (KIND == kStage23 || KIND == kStage4) VecIO<T, W>::ld(acc + off, accv[q]);
+        }
+        __syncthreads();                              // previous batch done reading its ring rows
+#pragma unroll
+        for (int q = 0; q < RB; ++q) store_row(ib + 2 + q, v[q], h[q]);
         __syncthreads();
 
-        T Fx[W + 2];
-        fx_cols(s_m1, s_0, s_p1, s_p2, Fx);
-        T fvC[W + 1];
-        fv_faces(s_p1, fvC);
-        const T da48 = (a_p1 - a_m1) * T(1.0 / 48.0);
-        T gv[W + 1];
+        // compute the batch (rows past the segment are computed and dropped);
+        // results stay in registers and are stored together
+        T o1[RB][W], o2[RB][W];
 #pragma unroll
-        for (int m = 0; m <= W; ++m) gv[m] = a_0 * fvB[m] + da48 * (fvC[m] - fvA[m]);
-        T kk[W];
+        for (int q = 0; q < RB; ++q) {
+            const int i = ib + q;
+            const int qa = i - i0;
+            const T a_m1 = (T)aseg[qa], a_0 = (T)aseg[qa + 1], a_p1 = (T)aseg[qa + 2];
+            T Fx[W + 2];
+            fx_cols(i, Fx);
+            T fvC[W + 1];
+            fv_faces(i + 1, fvC);
+            const T da48 = (a_p1 - a_m1) * T(1.0 / 48.0);
+            T gv[W + 1];
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-            const T gx_new = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
-            kk[w] = -(gx_new - gx_old[w]) * dxi - (gv[w + 1] - gv[w]) * dvi;
-            gx_old[w] = gx_new;
-        }
+            for (int m = 0; m <= W; ++m) gv[m] = a_0 * fvB[m] + da48 * (fvC[m] - fvA[m]);
+            T kk[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const T gx_new = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
+                kk[w] = -(gx_new - gx_old[w]) * dxi - (gv[w + 1] - gv[w]) * dvi;
+                gx_old[w] = gx_new;
+            }
+#pragma unroll
+            for (int m = 0; m <= W; ++m) { fvA[m] = fvB[m]; fvB[m] = fvC[m]; }
 
-        if (KIND == kRhs) {
-            if (own_in) VecIO<T, W>::st(fout + rowoff, kk);
-        } else {
-            T nxt[W];
-            if (KIND == kStage1) {
+            if (KIND == kRhs) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) o1[q][w] = kk[w];
+            } else if (KIND == kStage1) {
                 // f^n is the stage state itself: take it from the ring
+                const int sl = slot_of(i);
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    const T f0 = ring[s_0][c0 + w];
-                    accv[w] = f0 + (T)A.c_acc * kk[w];
-                    nxt[w] = f0 + (T)A.c_next * kk[w];
-                }
-                if (own_in) {
-                    VecIO<T, W>::st(acc + rowoff, accv);
-                    VecIO<T, W>::st(fout + rowoff, nxt);
+                    const T f0 = ring[sl][c0 + w];
+                    o1[q][w] = f0 + cacc * kk[w];      // accumulator
+                    o2[q][w] = f0 + cnext * kk[w];     // next predictor
                 }
             } else if (KIND == kStage23) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    accv[w] = accv[w] + (T)A.c_acc * kk[w];
-                    nxt[w] = fnv[w] + (T)A.c_next * kk[w];
-                }
-                if (own_in) {
-                    VecIO<T, W>::st(acc + rowoff, accv);
-                    VecIO<T, W>::st(fout + rowoff, nxt);
+                    o1[q][w] = accv[q][w] + cacc * kk[w];
+                    o2[q][w] = fnv[q][w] + cnext * kk[w];
                 }
             } else {  // kStage4: f^{n+1} = acc + dt/6 k4
 #pragma unroll
-                for (int w = 0; w < W; ++w) nxt[w] = accv[w] + (T)A.c_acc * kk[w];
-                if (own_in) VecIO<T, W>::st(fout + rowoff, nxt);
+                for (int w = 0; w < W; ++w) o2[q][w] = accv[q][w] + cacc * kk[w];
             }
-            if (A.part) {
-                double s = 0.0;
+            if (KIND != kRhs && A.part) {
+                double sm = 0.0;
                 if (own_in) {
 #pragma unroll
-                    for (int w = 0; w < W; ++w) s += (double)nxt[w];
+                    for (int w = 0; w < W; ++w) sm += (double)o2[q][w];
                 }
-                s = wave_sum(s);
-                if (lane == 0) mom[wave][q] = s;
+                sm = wave_sum(sm);
+                if (lane == 0 && i < i1) mom[wave][qa] = sm;
             }
         }
+        if (own_in) {
 #pragma unroll
-        for (int m = 0; m <= W; ++m) { fvA[m] = fvB[m]; fvB[m] = fvC[m]; }
-        a_m1 = a_0;
-        a_0 = a_p1;
+            for (int q = 0; q < RB; ++q) {
+                const int i = ib + q;
+                if (i < i1) {
+                    const size_t rowoff = (size_t)i * nv + jt;
+                    if (KIND == kRhs) {
+                        VecIO<T, W>::st(fout + rowoff, o1[q]);
+                    } else if (KIND == kStage4) {
+                        VecIO<T, W>::st(fout + rowoff, o2[q]);
+                    } else {
+                        VecIO<T, W>::st(acc + rowoff, o1[q]);
+                        VecIO<T, W>::st(fout + rowoff, o2[q]);
+                    }
+                }
+            }
+        }
     }
 
     if (KIND != kRhs && A.part) {
         __syncthreads();
         for (int q = t; q < i1 - i0; q += NT) {
-            double s = 0.0;
+            double sm = 0.0;
 #pragma unroll
-            for (int wv = 0; wv < NWAVE; ++wv) s += mom[wv][q];
-            A.part[(size_t)strip * nx + i0 + q] = s;
+            for (int wv = 0; wv < NWAVE; ++wv) sm += mom[wv][q];
+            A.part[(size_t)strip * nx + i0 + q] = sm;
         }
     }
 }
@@ -312,28 +335,40 @@ __global__ __launch_bounds__(256) void k_moment_rows(const T* __restrict__ f, in
 // per cell) followed by the periodic second difference
 // d_i - d_{i-1} = y_i with d_i = phi_{i+1} - phi_i (two prefix sums).  The
 // field only needs d:  E_i = -(7 (d_i + d_{i-1}) - d_{i+1} - d_{i-2}) / (12 dx).
+//
+// The null space: (S + S^-1 - 14) maps constants to -12 times themselves,
+// so removing the mean of y after the convolution is the same as projecting
+// rho onto zero mean first.  d is the prefix sum of y minus its mean; the
+// mean of the prefix sums follows from the same block reduction as the mean
+// of y:  sum_i D_i = sum_m y~_m (N - m).
+//
+// One block of kPoissonThreads threads; thread t owns the contiguous cells
+// [t c, t c + c), c = ceil(nx / kPoissonThreads).
 
-__device__ double block_sum_1024(double s, double* red)
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red)
 {
-    s = wave_sum(s);
+    a = wave_sum(a);
+    b = wave_sum(b);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = kPoissonThreads / 64;
     __syncthreads();
-    if (lane == 0) red[wave] = s;
+    if (lane == 0) { red[wave] = a; red[NW + wave] = b; }
     __syncthreads();
-    double tot = 0.0;
+    double ta = 0.0, tb = 0.0;
 #pragma unroll
-    for (int wv = 0; wv < kPoissonThreads / 64; ++wv) tot += red[wv];
-    return tot;
+    for (int wv = 0; wv < NW; ++wv) { ta += red[wv]; tb += red[NW + wv]; }
+    a = ta;
+    b = tb;
 }
 
 // exclusive prefix of per-thread values over the block, fixed order
-__device__ double block_exclusive_scan_1024(double v, double* red)
+__device__ double block_exclusive_scan(double v, double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        double y = __shfl_up(x, o, 64);
+        const double y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
     __syncthreads();
@@ -344,108 +379,133 @@ __device__ double block_exclusive_scan_1024(double v, double* red)
     return off + x - v;
 }
 
+// n_i = dv * sum over strips of the stage kernel's per-strip partial sums,
+// one row per thread with all strip loads in flight, fixed summation order.
+__global__ __launch_bounds__(256) void k_moment_finalize(const double* __restrict__ part, int nstrip, int nx,
+                                                        double dv, double* __restrict__ n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nx) return;
+    double acc = 0.0;
+    for (int q0 = 0; q0 < nstrip; q0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = (q0 + u < nstrip) ? part[(size_t)(q0 + u) * nx + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    n[i] = dv * acc;
+}
+
 __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
-    const double* __restrict__ part, int nstrip, const double* __restrict__ n_in, double dv, int nx,
-    double dx, double qm, const double* __restrict__ green, int gk, double* __restrict__ n_out,
+    const double* __restrict__ n_in, int nx, double dx, double qm, const double* __restrict__ green, int gk,
     double* __restrict__ phi_out, double* __restrict__ E_out, double* __restrict__ a_out)
 {
+    constexpr int K = kGreenTaps;
     extern __shared__ double sm[];
-    double* r = sm;            // nx: rho, then r, then y
-    double* d = sm + nx;       // nx: d = phi_{i+1} - phi_i
-    __shared__ double red[kPoissonThreads / 64];
+    double* rext = sm;                 // r with a K-cell periodic halo: rext[K + i] = r_i; later d
+    double* ybuf = sm + nx + 2 * K;    // y
+    __shared__ double red[2 * (kPoissonThreads / 64)];
+    __shared__ double gs[K + 1];
     const int t = threadIdx.x;
-    const int c = (nx + kPoissonThreads - 1) / kPoissonThreads;
-    const int lo = min(t * c, nx), hi = min(lo + c, nx);
+    const bool full = nx <= 2 * gk + 1;   // the table then holds all nx periodic values
+    if (!full && t <= K) gs[t] = green[t];
 
-    // moment and charge density
-    double s = 0.0;
-    for (int i = t; i < nx; i += kPoissonThreads) {
-        double n;
-        if (part) {
-            double acc = 0.0;
-            for (int q = 0; q < nstrip; ++q) acc += part[(size_t)q * nx + i];
-            n = dv * acc;
-        } else {
-            n = n_in[i];
-        }
-        if (n_out) n_out[i] = n;
-        r[i] = 1.0 - n;
-    }
-    __syncthreads();
-    for (int i = lo; i < hi; ++i) s += r[i];
-    const double mean_rho = block_sum_1024(s, red) / nx;
+    // r = 12 dx^2 (1 - n); every load of the block is issued before any is used
     const double scale = 12.0 * dx * dx;
-    for (int i = lo; i < hi; ++i) r[i] = scale * (r[i] - mean_rho);
-    __syncthreads();
-
-    // y = (S + S^-1 - 14)^-1 r ; each thread keeps its contiguous chunk in registers
-    constexpr int CM = kMaxPoisson1D / kPoissonThreads;
-    double yv[CM];
-    const bool full = nx <= 2 * gk + 1;
+    {
+        constexpr int RM = kMaxPoisson1D / kPoissonThreads;
+        double nv[RM];
 #pragma unroll
-    for (int m = 0; m < CM; ++m) {
-        const int i = lo + m;
-        double acc = 0.0;
-        if (i < hi) {
-            if (full) {
-                for (int q = 0; q < nx; ++q) acc += green[wrapi(i - q, nx)] * r[q];
-            } else {
-                acc = green[0] * r[i];
-                for (int o = 1; o <= gk; ++o) acc += green[o] * (r[wrapi(i + o, nx)] + r[wrapi(i - o, nx)]);
-            }
+        for (int m = 0; m < RM; ++m) {
+            const int i = t + m * kPoissonThreads;
+            nv[m] = i < nx ? n_in[i] : 0.0;
         }
-        yv[m] = acc;
+#pragma unroll
+        for (int m = 0; m < RM; ++m) {
+            const int i = t + m * kPoissonThreads;
+            if (i < nx) rext[K + i] = scale * (1.0 - nv[m]);
+        }
     }
-    s = 0.0;
-#pragma unroll
-    for (int m = 0; m < CM; ++m) s += yv[m];
-    const double mean_y = block_sum_1024(s, red) / nx;
-
-    // d = prefix(y) - mean(prefix(y))
-    double run = 0.0;
-#pragma unroll
-    for (int m = 0; m < CM; ++m) {
-        if (lo + m < hi) run += yv[m] - mean_y;
-        yv[m] = run;
-    }
-    const double off = block_exclusive_scan_1024(run, red);
-    s = 0.0;
-#pragma unroll
-    for (int m = 0; m < CM; ++m) {
-        yv[m] += off;
-        if (lo + m < hi) s += yv[m];
-    }
-    const double mean_d = block_sum_1024(s, red) / nx;
-#pragma unroll
-    for (int m = 0; m < CM; ++m)
-        if (lo + m < hi) d[lo + m] = yv[m] - mean_d;
     __syncthreads();
+    if (t < 2 * K) {   // periodic halo cells r_{-K..-1} and r_{nx..nx+K-1}
+        const int e = t < K ? t - K : nx + (t - K);
+        rext[K + e] = rext[K + wrapi(e, nx)];
+    }
+    __syncthreads();
+
+    // Thread t owns the contiguous chunk [t c, t c + c) for the prefix sums,
+    // c a power of two; y is stored with one pad cell per chunk so that the
+    // chunk-wise reads of a wave fall on different LDS banks.  Elementwise
+    // work uses strided ownership (consecutive lanes, consecutive cells).
+    int lc = 0;
+    while ((kPoissonThreads << lc) < nx) ++lc;
+    const int c = 1 << lc;
+    const int lo = min(t * c, nx), hi = min(lo + c, nx);
+    auto pidx = [&](int i) { return i + (i >> lc); };
+
+    // y = (S + S^-1 - 14)^-1 r, plus the sums for mean(y) and mean(D)
+    double sy = 0.0, syw = 0.0;
+    for (int i = t; i < nx; i += kPoissonThreads) {
+        double acc;
+        if (full) {
+            acc = 0.0;
+            for (int q = 0; q < nx; ++q) acc += green[wrapi(i - q, nx)] * rext[K + q];
+        } else {
+            const double* rc = rext + K + i;
+            acc = gs[0] * rc[0];
+#pragma unroll
+            for (int o = 1; o <= K; ++o) acc += gs[o] * (rc[o] + rc[-o]);
+        }
+        ybuf[pidx(i)] = acc;
+        sy += acc;
+        syw += acc * (double)(nx - i);
+    }
+    block_sum2(sy, syw, red);
+    const double mean_y = sy / nx;
+    // mean of D_i = sum_{m<=i} (y_m - mean_y):  (sum_m y_m (N - m) - mean_y N (N + 1) / 2) / N
+    const double mean_D = (syw - mean_y * 0.5 * (double)nx * (double)(nx + 1)) / nx;
+
+    // d = D - mean(D), written with a 2-cell periodic halo: dext[2 + i] = d_i
+    double run = 0.0;
+    for (int i = lo; i < hi; ++i) run += ybuf[pidx(i)] - mean_y;
+    const double off = block_exclusive_scan(run, red);   // ends with a barrier: rext is free
+    double* dext = rext;
+    double pre = off - mean_D;
+    for (int i = lo; i < hi; ++i) {
+        pre += ybuf[pidx(i)] - mean_y;
+        dext[2 + i] = pre;
+        // the owners of the first and last two cells also write the halo
+        if (i < 2) dext[2 + nx + i] = pre;
+        if (i >= nx - 2) dext[2 + i - nx] = pre;
+    }
+    __syncthreads();
+    if (nx < 2) {      // one cell: every halo cell is d_0
+        if (t == 0) dext[0] = dext[4] = dext[2];
+        __syncthreads();
+    }
 
     for (int i = t; i < nx; i += kPoissonThreads) {
-        const double E = -(7.0 * (d[i] + d[wrapi(i - 1, nx)]) - d[wrapi(i + 1, nx)] - d[wrapi(i - 2, nx)]) /
-                         (12.0 * dx);
+        const double* dc = dext + 2 + i;
+        const double E = -(7.0 * (dc[0] + dc[-1]) - dc[1] - dc[-2]) / (12.0 * dx);
         if (E_out) E_out[i] = E;
         if (a_out) a_out[i] = qm * E;
     }
     if (phi_out) {
         // phi_i = sum_{m < i} d_m + const, zero mean
-        double run2 = 0.0;
-#pragma unroll
-        for (int m = 0; m < CM; ++m) {
-            yv[m] = run2;
-            if (lo + m < hi) run2 += d[lo + m];
+        double run2 = 0.0, sw = 0.0;
+        for (int i = lo; i < hi; ++i) run2 += dext[2 + i];
+        const double off2 = block_exclusive_scan(run2, red);
+        double p2 = off2;
+        for (int i = lo; i < hi; ++i) {
+            ybuf[pidx(i)] = p2;
+            sw += p2;
+            p2 += dext[2 + i];
         }
-        const double off2 = block_exclusive_scan_1024(run2, red);
-        s = 0.0;
-#pragma unroll
-        for (int m = 0; m < CM; ++m) {
-            yv[m] += off2;
-            if (lo + m < hi) s += yv[m];
-        }
-        const double mean_phi = block_sum_1024(s, red) / nx;
-#pragma unroll
-        for (int m = 0; m < CM; ++m)
-            if (lo + m < hi) phi_out[lo + m] = yv[m] - mean_phi;
+        double dummy = 0.0;
+        block_sum2(sw, dummy, red);
+        const double mean_phi = sw / nx;
+        for (int i = t; i < nx; i += kPoissonThreads) phi_out[i] = ybuf[pidx(i)] - mean_phi;
     }
 }
 
@@ -506,16 +566,23 @@ hipError_t poisson1d_prepare()
 {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson1d),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(2 * kMaxPoisson1D * sizeof(double)));
+                               (int)((2 * kMaxPoisson1D + 2 * kGreenTaps + kPoissonThreads + 1) * sizeof(double)));
 }
 
 hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, double dv, int nx,
                             double dx, double qm, const double* green, int gk, double* n_out,
                             double* phi, double* E, double* a, hipStream_t stream)
 {
-    const size_t lds = 2 * (size_t)nx * sizeof(double);
-    hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, part, nstrip, n_in,
-                       dv, nx, dx, qm, green, gk, n_out, phi, E, a);
+    // with partial sums: finalise the moment into n_out first (n_out is required)
+    if (part) {
+        if (!n_out) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_moment_finalize, dim3((nx + 255) / 256), dim3(256), 0, stream, part, nstrip, nx,
+                           dv, n_out);
+        n_in = n_out;
+    }
+    const size_t lds = (2 * (size_t)nx + 2 * kGreenTaps + kPoissonThreads + 1) * sizeof(double);
+    hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
+                       phi, E, a);
     return hipGetLastError();
 }
 

@@ -72,6 +72,10 @@ SIGNATURES = {
     "vp_rk4_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P]),
     "vp_rk4_step_record": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P]),
     "vp_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P, _P]),
+    "vp_tile_shape_count": (ctypes.c_int32, [_P]),
+    "vp_tile_shape_get": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "vp_tile_shape_set": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vp_timing_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int32]),
@@ -179,6 +183,18 @@ class Plan:
         cnt = (ctypes.c_int64 * n)()
         _check(lib().vp_timing_read(self.h, ms, cnt, n))
         return {c: (ms[i], cnt[i]) for i, c in enumerate(TIMING_CLASSES)}
+
+    def tile_shapes(self):
+        """[(threads, cells per thread, rows per tile)] compiled for this plan."""
+        out = []
+        for q in range(lib().vp_tile_shape_count(self.h)):
+            a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            _check(lib().vp_tile_shape_get(self.h, q, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+            out.append((a.value, b.value, c.value))
+        return out
+
+    def set_tile_shape(self, index):
+        _check(lib().vp_tile_shape_set(self.h, index))
 
     def patch_offset(self, p):
         return lib().vp_patch_offset(self.h, p)
