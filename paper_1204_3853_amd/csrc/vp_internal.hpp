@@ -39,7 +39,7 @@ struct StageShape {
 constexpr int kMaxTx = 128;          // bound on rows per segment (LDS moment buffer)
 constexpr int kPoissonThreads = 256;
 constexpr int kMaxPoisson1D = 8192;  // configuration cells handled by the one-block solver
-constexpr int kGreenTaps = 20;       // taps of the truncated Green's function: r^20 ~ 1.6e-23
+constexpr int kGreenTaps = 16;       // taps of the truncated Green's function: r^17 ~ 3.6e-20
 
 // Arguments of the 1D+1V stage kernels.  Pointers are element pointers of
 // the plan dtype T (passed as void* and cast in the launcher).

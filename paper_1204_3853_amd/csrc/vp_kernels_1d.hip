@@ -402,14 +402,26 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
     double* __restrict__ phi_out, double* __restrict__ E_out, double* __restrict__ a_out)
 {
     constexpr int K = kGreenTaps;
+    constexpr int SUB = 8;               // outputs per register window of the convolution
     extern __shared__ double sm[];
-    double* rext = sm;                 // r with a K-cell periodic halo: rext[K + i] = r_i; later d
-    double* ybuf = sm + nx + 2 * K;    // y
     __shared__ double red[2 * (kPoissonThreads / 64)];
     __shared__ double gs[K + 1];
     const int t = threadIdx.x;
     const bool full = nx <= 2 * gk + 1;   // the table then holds all nx periodic values
     if (!full && t <= K) gs[t] = green[t];
+
+    // Thread t owns the contiguous chunk [t c, t c + c) (c a power of two)
+    // for the convolution and the prefix sums.  LDS arrays carry one pad
+    // cell per chunk, so a wave's chunk-wise accesses fall on different
+    // banks; elementwise loops use strided ownership.
+    int lc = 0;
+    while ((kPoissonThreads << lc) < nx) ++lc;
+    const int c = 1 << lc;
+    const int lo = min(t * c, nx), hi = min(lo + c, nx);
+    auto pad = [&](int j) { return j + (j >> lc); };
+    double* rext = sm;                                   // r_i at pad(i + K), i in [-K, nx + K + SUB)
+    double* ybuf = sm + pad(nx + 2 * K + SUB) + 1;       // y_i at pad(i); later d_i at pad(i + 2)
+    auto rp = [&](int i) { return pad(i + K); };
 
     // r = 12 dx^2 (1 - n); every load of the block is issued before any is used
     const double scale = 12.0 * dx * dx;
@@ -424,88 +436,92 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
 #pragma unroll
         for (int m = 0; m < RM; ++m) {
             const int i = t + m * kPoissonThreads;
-            if (i < nx) rext[K + i] = scale * (1.0 - nv[m]);
+            if (i < nx) rext[rp(i)] = scale * (1.0 - nv[m]);
         }
     }
     __syncthreads();
-    if (t < 2 * K) {   // periodic halo cells r_{-K..-1} and r_{nx..nx+K-1}
-        const int e = t < K ? t - K : nx + (t - K);
-        rext[K + e] = rext[K + wrapi(e, nx)];
+    for (int e = t; e < 2 * K + SUB; e += kPoissonThreads) {   // periodic halo
+        const int i = e < K ? e - K : nx + (e - K);
+        rext[rp(i)] = rext[rp(wrapi(i, nx))];
     }
     __syncthreads();
 
-    // Thread t owns the contiguous chunk [t c, t c + c) for the prefix sums,
-    // c a power of two; y is stored with one pad cell per chunk so that the
-    // chunk-wise reads of a wave fall on different LDS banks.  Elementwise
-    // work uses strided ownership (consecutive lanes, consecutive cells).
-    int lc = 0;
-    while ((kPoissonThreads << lc) < nx) ++lc;
-    const int c = 1 << lc;
-    const int lo = min(t * c, nx), hi = min(lo + c, nx);
-    auto pidx = [&](int i) { return i + (i >> lc); };
-
-    // y = (S + S^-1 - 14)^-1 r, plus the sums for mean(y) and mean(D)
+    // y = (S + S^-1 - 14)^-1 r over the own chunk, plus the sums for mean(y)
+    // and mean(D)
     double sy = 0.0, syw = 0.0;
-    for (int i = t; i < nx; i += kPoissonThreads) {
-        double acc;
-        if (full) {
-            acc = 0.0;
-            for (int q = 0; q < nx; ++q) acc += green[wrapi(i - q, nx)] * rext[K + q];
-        } else {
-            const double* rc = rext + K + i;
-            acc = gs[0] * rc[0];
-#pragma unroll
-            for (int o = 1; o <= K; ++o) acc += gs[o] * (rc[o] + rc[-o]);
+    if (full) {
+        for (int i = lo; i < hi; ++i) {
+            double acc = 0.0;
+            for (int q = 0; q < nx; ++q) acc += green[wrapi(i - q, nx)] * rext[rp(q)];
+            ybuf[pad(i)] = acc;
+            sy += acc;
+            syw += acc * (double)(nx - i);
         }
-        ybuf[pidx(i)] = acc;
-        sy += acc;
-        syw += acc * (double)(nx - i);
+    } else {
+        for (int j0 = lo; j0 < hi; j0 += SUB) {
+            double w[SUB + 2 * K];
+#pragma unroll
+            for (int q = 0; q < SUB + 2 * K; ++q) w[q] = rext[rp(j0 - K + q)];
+#pragma unroll
+            for (int u = 0; u < SUB; ++u) {
+                double acc = gs[0] * w[u + K];
+#pragma unroll
+                for (int o = 1; o <= K; ++o) acc += gs[o] * (w[u + K + o] + w[u + K - o]);
+                const int i = j0 + u;
+                if (i < hi) {
+                    ybuf[pad(i)] = acc;
+                    sy += acc;
+                    syw += acc * (double)(nx - i);
+                }
+            }
+        }
     }
     block_sum2(sy, syw, red);
     const double mean_y = sy / nx;
     // mean of D_i = sum_{m<=i} (y_m - mean_y):  (sum_m y_m (N - m) - mean_y N (N + 1) / 2) / N
     const double mean_D = (syw - mean_y * 0.5 * (double)nx * (double)(nx + 1)) / nx;
 
-    // d = D - mean(D), written with a 2-cell periodic halo: dext[2 + i] = d_i
+    // d = D - mean(D); d_i is written over rext at dp(i), with a 2-cell periodic halo
     double run = 0.0;
-    for (int i = lo; i < hi; ++i) run += ybuf[pidx(i)] - mean_y;
+    for (int i = lo; i < hi; ++i) run += ybuf[pad(i)] - mean_y;
     const double off = block_exclusive_scan(run, red);   // ends with a barrier: rext is free
     double* dext = rext;
+    auto dp = [&](int i) { return pad(i + 2); };
     double pre = off - mean_D;
     for (int i = lo; i < hi; ++i) {
-        pre += ybuf[pidx(i)] - mean_y;
-        dext[2 + i] = pre;
+        pre += ybuf[pad(i)] - mean_y;
+        dext[dp(i)] = pre;
         // the owners of the first and last two cells also write the halo
-        if (i < 2) dext[2 + nx + i] = pre;
-        if (i >= nx - 2) dext[2 + i - nx] = pre;
+        if (i < 2) dext[dp(nx + i)] = pre;
+        if (i >= nx - 2) dext[dp(i - nx)] = pre;
     }
     __syncthreads();
     if (nx < 2) {      // one cell: every halo cell is d_0
-        if (t == 0) dext[0] = dext[4] = dext[2];
+        if (t == 0) dext[dp(-2)] = dext[dp(-1)] = dext[dp(1)] = dext[dp(2)] = dext[dp(0)];
         __syncthreads();
     }
 
     for (int i = t; i < nx; i += kPoissonThreads) {
-        const double* dc = dext + 2 + i;
-        const double E = -(7.0 * (dc[0] + dc[-1]) - dc[1] - dc[-2]) / (12.0 * dx);
+        const double E = -(7.0 * (dext[dp(i)] + dext[dp(i - 1)]) - dext[dp(i + 1)] - dext[dp(i - 2)]) /
+                         (12.0 * dx);
         if (E_out) E_out[i] = E;
         if (a_out) a_out[i] = qm * E;
     }
     if (phi_out) {
         // phi_i = sum_{m < i} d_m + const, zero mean
         double run2 = 0.0, sw = 0.0;
-        for (int i = lo; i < hi; ++i) run2 += dext[2 + i];
+        for (int i = lo; i < hi; ++i) run2 += dext[dp(i)];
         const double off2 = block_exclusive_scan(run2, red);
         double p2 = off2;
         for (int i = lo; i < hi; ++i) {
-            ybuf[pidx(i)] = p2;
+            ybuf[pad(i)] = p2;
             sw += p2;
-            p2 += dext[2 + i];
+            p2 += dext[dp(i)];
         }
         double dummy = 0.0;
         block_sum2(sw, dummy, red);
         const double mean_phi = sw / nx;
-        for (int i = t; i < nx; i += kPoissonThreads) phi_out[i] = ybuf[pidx(i)] - mean_phi;
+        for (int i = t; i < nx; i += kPoissonThreads) phi_out[i] = ybuf[pad(i)] - mean_phi;
     }
 }
 
@@ -562,11 +578,21 @@ hipError_t launch_moment_rows(int dtype, const void* f, int nx, int nv, double d
     return hipGetLastError();
 }
 
+// LDS doubles of k_poisson1d for nx cells: the padded r (and later d)
+// array over [-K, nx + K + 8) and the padded y array over [0, nx)
+size_t poisson1d_lds_doubles(int nx)
+{
+    int lc = 0;
+    while ((kPoissonThreads << lc) < nx) ++lc;
+    auto pad = [&](size_t j) { return j + (j >> lc); };
+    return pad((size_t)nx + 2 * kGreenTaps + 8) + 1 + pad((size_t)nx) + 1;
+}
+
 hipError_t poisson1d_prepare()
 {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson1d),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)((2 * kMaxPoisson1D + 2 * kGreenTaps + kPoissonThreads + 1) * sizeof(double)));
+                               (int)(poisson1d_lds_doubles(kMaxPoisson1D) * sizeof(double)));
 }
 
 hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, double dv, int nx,
@@ -580,7 +606,7 @@ hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, 
                            dv, n_out);
         n_in = n_out;
     }
-    const size_t lds = (2 * (size_t)nx + 2 * kGreenTaps + kPoissonThreads + 1) * sizeof(double);
+    const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
                        phi, E, a);
     return hipGetLastError();
