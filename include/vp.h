@@ -226,6 +226,18 @@ vp_status vp_adjoint_step(const vp_plan* plan, const void* f_n, const double* a_
                           void* work, hipStream_t stream);
 
 /*
+ * Adjoint of the map f -> a = (q/m) E(f) (velocity moment, periodic
+ * Poisson solve, field, injection; section 2): fbar_ij = (K^T abar)_i for
+ * every velocity cell j, where K f = a.  With the Poisson solution
+ * operator S (symmetric) and the field stencil D (antisymmetric),
+ * K^T abar = -dv S D (q/m) abar, broadcast over v.  Single level, FP64.
+ *   abar  vp_field_elems doubles
+ *   fbar  output state (FP64)
+ */
+vp_status vp_field_adjoint(const vp_plan* plan, const double* abar, void* fbar, void* work,
+                           hipStream_t stream);
+
+/*
  * Tile shapes of the stage kernels, for autotuning.  A shape is (threads
  * per block, velocity cells per thread, configuration rows per tile).
  * vp_tile_shape_count / _get enumerate the shapes compiled for the plan's

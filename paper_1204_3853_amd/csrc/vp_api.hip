@@ -228,7 +228,12 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
     p->ws_fsa = off; off += sb;
     p->ws_fsb = off; off += sb;
     p->ws_part = off; off += align256((size_t)max_strips * p->nx * sizeof(double));
-    p->ws_cfg = off; off += align256((size_t)4 * p->nx * sizeof(double));
+    p->ws_cfg = off; off += align256((size_t)8 * p->nx * sizeof(double));
+    if (p->dtype == VP_F64) {   // adjoint recompute: copy of f_n and a_n, stage record
+        p->ws_tmpf = off; off += sb;
+        p->ws_tmpa = off; off += align256((size_t)p->nx * sizeof(double));
+        p->ws_stages = off; off += align256(3 * p->state_elems * p->esize + 4 * (size_t)p->nx * sizeof(double));
+    }
     p->ws_total = off;
     *out = p;
     return VP_OK;
@@ -376,12 +381,95 @@ vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, vo
     return rk4_1d(p, f, a, dt, work, stages, st_a, stream);
 }
 
+vp_status vp_field_adjoint(const vp_plan* p, const double* abar, void* fbar, void* work, hipStream_t stream)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!abar || !fbar || !work) return fail(VP_EINVAL, "vp_field_adjoint: NULL pointer");
+    if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_field_adjoint: FP64 only");
+    double* cfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
+    double* ab = cfg;
+    double* z = cfg + p->nx;
+    VP_HIP(hipMemcpyAsync(ab, abar, sizeof(double) * p->nx, hipMemcpyDeviceToDevice, stream));
+    VP_HIP(timed(p, kTField, stream, [&] {
+        return launch_poisson1d_adjoint(nullptr, 0, p->nx, p->dx, p->dv, p->pb.qm, p->d_green, p->gk, ab, z, stream);
+    }));
+    VP_HIP(timed(p, kTOther, stream, [&] {
+        return launch_row_broadcast(z, p->nx, p->nv, static_cast<double*>(fbar), stream);
+    }));
+    return VP_OK;
+}
+
 vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, const void* stages,
                           const void* lam_np1, void* lam_n, double dt, void* work, hipStream_t stream)
 {
-    (void)f_n; (void)a_n; (void)stages; (void)lam_np1; (void)lam_n; (void)dt; (void)work; (void)stream;
     if (vp_status s = check_plan(p)) return s;
-    return fail(VP_ENOTSUP, "vp_adjoint_step: not available in this build");
+    if (!f_n || !a_n || !lam_np1 || !lam_n || !work) return fail(VP_EINVAL, "vp_adjoint_step: NULL pointer");
+    if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is FP64 only");
+    if (p->nlev != 1 || p->ndim != 1) return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
+    if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_adjoint_step: dt is not finite");
+    const size_t N = p->state_elems;
+    const int nx = p->nx, nv = p->nv;
+    // stage states f(1..4) and accelerations a(1..4)
+    const double* st = static_cast<const double*>(stages);
+    if (!st) {
+        double* tf = reinterpret_cast<double*>(wsp(work, p->ws_tmpf));
+        double* ta = reinterpret_cast<double*>(wsp(work, p->ws_tmpa));
+        double* rec = reinterpret_cast<double*>(wsp(work, p->ws_stages));
+        VP_HIP(hipMemcpyAsync(tf, f_n, N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        VP_HIP(hipMemcpyAsync(ta, a_n, nx * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        if (vp_status s = rk4_1d(p, tf, ta, dt, work, rec, rec + 3 * N, stream)) return s;
+        st = rec;
+    }
+    const double* fst[4] = {static_cast<const double*>(f_n), st, st + N, st + 2 * N};
+    const double* ast[4] = {st + 3 * N, st + 3 * N + nx, st + 3 * N + 2 * nx, st + 3 * N + 3 * nx};
+
+    double* mu = reinterpret_cast<double*>(wsp(work, p->ws_acc));
+    double* gbuf[2] = {reinterpret_cast<double*>(wsp(work, p->ws_fsa)), reinterpret_cast<double*>(wsp(work, p->ws_fsb))};
+    double* part = reinterpret_cast<double*>(wsp(work, p->ws_part));
+    double* cfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
+    double* abar = cfg;
+    double* zbuf[2] = {cfg + nx, cfg + 2 * nx};
+
+    const bool al = aligned16(f_n) && aligned16(lam_np1) && aligned16(st) && aligned16(mu) && nv % 2 == 0 &&
+                    (N * sizeof(double)) % 16 == 0;
+    const int w = al ? 2 : 1;
+    Adjoint1DArgs A{};
+    A.nx = nx;
+    A.nv = nv;
+    A.tx = 16;
+    A.nstrip = (nv + 128 * w - 1) / (128 * w);
+    A.dxi = 1.0 / p->dx;
+    A.dvi = 1.0 / p->dv;
+    A.dv24 = p->dv / 24.0;
+    A.v_lo = p->v_lo;
+    A.dv = p->dv;
+    for (int q = 0; q < 4; ++q) A.vg[q] = p->vg[q];
+    A.lam = static_cast<const double*>(lam_np1);
+    A.part = part;
+    const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double alpha[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int s = 3; s >= 0; --s) {
+        const int cur = s & 1, prev = (s + 1) & 1;
+        A.fs = fst[s];
+        A.a = ast[s];
+        A.g_out = gbuf[cur];
+        A.c1 = dt * b[s];
+        A.c2 = s < 3 ? dt * alpha[s + 1] : 0.0;
+        A.g_prev = s < 3 ? gbuf[prev] : nullptr;
+        A.z_prev = s < 3 ? zbuf[prev] : nullptr;
+        A.mu_in = (s < 2) ? mu : nullptr;     // s = 2 (third from the top) starts from lam
+        A.mu_out = mu;
+        const bool first = (s == 3);
+        VP_HIP(timed(p, kTAdjoint, stream, [&] { return launch_adjoint_stage1d(w, first, A, stream); }));
+        VP_HIP(timed(p, kTField, stream, [&] {
+            return launch_poisson1d_adjoint(part, A.nstrip, nx, p->dx, p->dv, p->pb.qm, p->d_green, p->gk, abar,
+                                            zbuf[cur], stream);
+        }));
+    }
+    VP_HIP(timed(p, kTOther, stream, [&] {
+        return launch_adjoint_final(mu, gbuf[0], zbuf[0], nx, nv, static_cast<double*>(lam_n), stream);
+    }));
+    return VP_OK;
 }
 
 }  // extern "C"

@@ -58,6 +58,23 @@ struct Stage1DArgs {
 
 enum StageKind : int { kRhs = 0, kStage1 = 1, kStage23 = 2, kStage4 = 3 };
 
+// Arguments of the adjoint stage kernel (FP64, single level).
+struct Adjoint1DArgs {
+    int nx, nv, tx, nstrip;
+    double dxi, dvi, dv24, v_lo, dv;
+    double vg[4];
+    const double* lam;      // cotangent of f^{n+1}
+    const double* g_prev;   // g_{s+1} (null for s = 4)
+    const double* z_prev;   // z_{s+1}, one value per x row (null for s = 4)
+    const double* mu_in;    // running cotangent of f^n (null: start from lam)
+    double* mu_out;
+    const double* fs;       // stage state f(s)
+    const double* a;        // its acceleration a(s)
+    double* g_out;          // g_s
+    double* part;           // per-strip partial sums of abar_s [nstrip][nx]
+    double c1, c2;          // dt b_s, dt alpha_{s+1}
+};
+
 // Launchers (defined in vp_kernels_1d.hip).
 hipError_t launch_stage1d(int dtype, const StageShape& sh, int kind, const Stage1DArgs& args,
                           hipStream_t stream);
@@ -67,6 +84,15 @@ hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, 
                             int nx, double dx, double qm, const double* green, int gk,
                             double* n_out, double* phi, double* E, double* a,
                             hipStream_t stream);
+// z = -dv S D (q/m) abar: the adjoint of the moment -> Poisson -> field chain
+// applied to the per-strip partial sums of abar (finalised into abar_out)
+// (part == null: abar_out already holds abar)
+hipError_t launch_poisson1d_adjoint(const double* part, int nstrip, int nx, double dx, double dv, double qm,
+                                    const double* green, int gk, double* abar_out, double* z, hipStream_t stream);
+hipError_t launch_row_broadcast(const double* z, int nx, int nv, double* out, hipStream_t stream);
+hipError_t launch_adjoint_stage1d(int w, bool first, const Adjoint1DArgs& a, hipStream_t stream);
+hipError_t launch_adjoint_final(const double* mu, const double* g, const double* z, int nx, int nv, double* out,
+                                hipStream_t stream);
 hipError_t launch_scale(const double* x, double s, double* y, int n, hipStream_t stream);
 hipError_t poisson1d_prepare();
 
@@ -106,6 +132,7 @@ struct vp_plan {
 
     // workspace layout (byte offsets)
     size_t ws_acc = 0, ws_fsa = 0, ws_fsb = 0, ws_part = 0, ws_cfg = 0, ws_total = 0;
+    size_t ws_tmpf = 0, ws_stages = 0, ws_tmpa = 0;   // adjoint recompute (f_n copy, stage record)
     size_t state_elems = 0;
 
     mutable Timing timing;

@@ -397,9 +397,14 @@ __global__ __launch_bounds__(256) void k_moment_finalize(const double* __restric
     n[i] = dv * acc;
 }
 
+// adjoint = 0: r = 12 dx^2 (1 - n) from the moment n_in; outputs phi, E, a.
+// adjoint = 1: n_in holds abar; r = 12 dx^2 D (q/m) abar (D the field
+// stencil without its sign); phi_out receives phi_scale * S r / (12 dx^2)-
+// solution, i.e. z = -dv S D (q/m) abar with phi_scale = -dv.
 __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
     const double* __restrict__ n_in, int nx, double dx, double qm, const double* __restrict__ green, int gk,
-    double* __restrict__ phi_out, double* __restrict__ E_out, double* __restrict__ a_out)
+    double* __restrict__ phi_out, double* __restrict__ E_out, double* __restrict__ a_out, int adjoint,
+    double phi_scale)
 {
     constexpr int K = kGreenTaps;
     constexpr int SUB = 8;               // outputs per register window of the convolution
@@ -433,10 +438,29 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
             const int i = t + m * kPoissonThreads;
             nv[m] = i < nx ? n_in[i] : 0.0;
         }
+        if (!adjoint) {
 #pragma unroll
-        for (int m = 0; m < RM; ++m) {
-            const int i = t + m * kPoissonThreads;
-            if (i < nx) rext[rp(i)] = scale * (1.0 - nv[m]);
+            for (int m = 0; m < RM; ++m) {
+                const int i = t + m * kPoissonThreads;
+                if (i < nx) rext[rp(i)] = scale * (1.0 - nv[m]);
+            }
+        } else {
+            // u = D (q/m) abar through a temporary copy of (q/m) abar in ybuf
+#pragma unroll
+            for (int m = 0; m < RM; ++m) {
+                const int i = t + m * kPoissonThreads;
+                if (i < nx) ybuf[i] = qm * nv[m];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < RM; ++m) {
+                const int i = t + m * kPoissonThreads;
+                if (i < nx) {
+                    const double d1 = ybuf[wrapi(i + 1, nx)] - ybuf[wrapi(i - 1, nx)];
+                    const double d2 = ybuf[wrapi(i + 2, nx)] - ybuf[wrapi(i - 2, nx)];
+                    rext[rp(i)] = scale * (8.0 * d1 - d2) / (12.0 * dx);
+                }
+            }
         }
     }
     __syncthreads();
@@ -521,7 +545,7 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
         double dummy = 0.0;
         block_sum2(sw, dummy, red);
         const double mean_phi = sw / nx;
-        for (int i = t; i < nx; i += kPoissonThreads) phi_out[i] = ybuf[pad(i)] - mean_phi;
+        for (int i = t; i < nx; i += kPoissonThreads) phi_out[i] = phi_scale * (ybuf[pad(i)] - mean_phi);
     }
 }
 
@@ -608,7 +632,33 @@ hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, 
     }
     const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
-                       phi, E, a);
+                       phi, E, a, 0, 1.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_poisson1d_adjoint(const double* part, int nstrip, int nx, double dx, double dv, double qm,
+                                    const double* green, int gk, double* abar_out, double* z, hipStream_t stream)
+{
+    if (part)
+        hipLaunchKernelGGL(k_moment_finalize, dim3((nx + 255) / 256), dim3(256), 0, stream, part, nstrip, nx, 1.0,
+                           abar_out);
+    const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
+    hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, abar_out, nx, dx, qm, green,
+                       gk, z, nullptr, nullptr, 1, -dv);
+    return hipGetLastError();
+}
+
+__global__ void k_row_broadcast(const double* __restrict__ z, int nv, size_t total, double* __restrict__ out)
+{
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < total) out[p] = z[p / nv];
+}
+
+hipError_t launch_row_broadcast(const double* z, int nx, int nv, double* out, hipStream_t stream)
+{
+    const size_t total = (size_t)nx * nv;
+    hipLaunchKernelGGL(k_row_broadcast, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, z, nv, total,
+                       out);
     return hipGetLastError();
 }
 

@@ -72,6 +72,7 @@ SIGNATURES = {
     "vp_rk4_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P]),
     "vp_rk4_step_record": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P]),
     "vp_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P, _P]),
+    "vp_field_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "vp_tile_shape_count": (ctypes.c_int32, [_P]),
     "vp_tile_shape_get": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
@@ -298,3 +299,12 @@ def adjoint_step(plan, f_n, a_n, lam_np1, dt, stages=None, lam_n=None):
     _check(lib().vp_adjoint_step(plan.h, _ptr(f_n), _ptr(a_n), _ptr(stages), _ptr(lam_np1), _ptr(lam_n),
                                  ctypes.c_double(dt), _ptr(plan.work), _stream()))
     return lam_n
+
+
+def field_adjoint(plan, abar, fbar=None):
+    """fbar = K^T abar: adjoint of f -> a (moment, Poisson, field, injection)."""
+    plan._cfg(abar, "abar", plan.field_elems)
+    if fbar is None:
+        fbar = torch.empty(plan.state_elems, dtype=torch.float64, device=abar.device)
+    _check(lib().vp_field_adjoint(plan.h, _ptr(abar), _ptr(fbar), _ptr(plan.work), _stream()))
+    return fbar

@@ -122,6 +122,22 @@ def two_stream(nx=4096, nv=4096):
     return Problem1D(nx, nv, 0.0, 10.0 * math.pi, -8.0, 8.0, profile="two_stream", eps=1e-3, k=0.2)
 
 
+def adjoint_setup(nx: int = 512, nv: int = 512, seed: int = 0):
+    """Adjoint workload: Landau mesh, f0_ij = (1 + c_i + p_i) g_j with c the
+    exact cell averages of 0.01 cos(0.5 x) and the perturbation profile
+    p ~ N(0, sigma = 1e-3) (seeded)."""
+    prob = landau(nx, nv, eps=0.0)
+    c = 0.01 * cos_cell_average(prob.x_lo, prob.x_len, nx, 0.5)
+    p = np.random.default_rng(seed).normal(0.0, 1e-3, nx)
+    return prob, c, p
+
+
+def adjoint_directions(nx: int, count: int = 8, seed: int = 1):
+    """Unit-norm random directions for finite-difference checks."""
+    d = np.random.default_rng(seed).normal(size=(count, nx))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
 def random_state(nx: int, nv: int, seed: int = 1234):
     """Random parity input: f ~ U[0, 1), a ~ N(0, 0.1)."""
     rng = np.random.default_rng(seed)
