@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline-pass", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-adjoint", action="store_true")
     return ap.parse_args()
 
 
@@ -63,6 +64,44 @@ def cpu_baseline(n, dt, seconds):
             break
     return {"value": n * n * steps / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{steps} full RK4 steps of the {n}x{n} two-stream mesh, FP64, {el:.1f} s"}
+
+
+def adjoint_ratio(steps=400, every=20):
+    """Adjoint workload (Landau 512 x 512, FP64, 400 steps, checkpoint every
+    20): wall time of the forward rollout and of the backward pass
+    (segment recompute + discrete adjoint + field-energy gradient)."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import autograd as AG
+    from paper_1204_3853_amd import vp
+    prob, c, pvec = I.adjoint_setup(512, 512, seed=0)
+    g = prob.veq[2:-2]
+    dt = 1.531e-3
+    plan = vp.Plan(prob)
+    pt = torch.tensor(pvec, dtype=torch.float64, device="cuda", requires_grad=True)
+    ct = torch.tensor(c, dtype=torch.float64, device="cuda")
+    gt = torch.tensor(g, dtype=torch.float64, device="cuda")
+
+    def run():
+        pt.grad = None
+        f0 = ((1.0 + ct + pt)[:, None] * gt[None, :]).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fT = AG.rollout(f0, plan, dt, steps, every)
+        W = AG.field_energy(fT, plan)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        W.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    run()                                         # warm-up
+    fw, bw = min(run() for _ in range(3))
+    return {"workload": "Landau 1D+1V 512x512 FP64, 400 RK4 steps, checkpoint every 20, "
+                        "gradient of 1/2 sum E^2 w.r.t. the 512-value initial profile",
+            "forward_ms": round(fw * 1e3, 2), "backward_ms": round(bw * 1e3, 2), "ratio": round(bw / fw, 3)}
 
 
 def main():
@@ -126,6 +165,8 @@ def main():
                     "algorithmic_bytes_per_launch": bytes_launch,
                     "field_solve_us_per_launch": round(timing["field"][0] / max(timing["field"][1], 1) * 1e3, 2)}
 
+    adj = None if args.no_adjoint else adjoint_ratio()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(n, dt, args.cpu_seconds)
@@ -147,6 +188,7 @@ def main():
                                f"x in [0,10pi), v in [-8,8], dt={dt}", "cells": cells, "dt": dt},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 

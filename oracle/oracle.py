@@ -240,3 +240,65 @@ class Oracle1D:
         out = np.empty_like(f_n)
         lib().vpo_rk4_adjoint_step(self.h, _p(f_n), _p(lam), _p(out), dt)
         return out
+
+
+def interp_weights(R):
+    """b_j(s) table (R x 5) of the conservative fifth-order sub-cell interpolation."""
+    out = np.empty((R, 5))
+    lib().vpo_interp_weights(R, _p(out))
+    return out
+
+
+class OracleAMR:
+    """Two-level 1D+1V oracle: coarse (ncx x ncv) plus level-1 patches
+    (boxes: dicts with inclusive lo/hi in the level-1 index space)."""
+
+    def __init__(self, ncx, ncv, x_len, v_lo, v_hi, qm, R, boxes, veq_c, veq_f):
+        self.ncx, self.ncv, self.R = ncx, ncv, R
+        self.boxes = boxes
+        arr = np.array([[b["lo"][0], b["lo"][1], b["hi"][0], b["hi"][1]] for b in boxes], dtype=np.int32).ravel()
+        if arr.size == 0:
+            arr = np.zeros(4, dtype=np.int32)
+        self._boxes = np.ascontiguousarray(arr)
+        self.veq_c, self.veq_f = _f64(veq_c), _f64(veq_f)
+        self.h = lib().vpo_amr_new(ncx, ncv, x_len, v_lo, v_hi, qm, R, len(boxes),
+                                   self._boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   _p(self.veq_c), _p(self.veq_f))
+        self.size = lib().vpo_amr_state_size(self.h)
+        self.nfx = ncx * R
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.vpo_amr_free(self.h)
+            self.h = None
+
+    def offset(self, p):
+        return lib().vpo_amr_patch_offset(self.h, p)
+
+    def reduce_mask(self, f):
+        f = _f64(f)
+        n = np.empty(self.nfx)
+        lib().vpo_amr_reduce_mask(self.h, _p(f), _p(n))
+        return n
+
+    def constraints(self, f):
+        """(a = [a_coarse (ncx), a_fine (ncx R)], E on the fine mesh)"""
+        f = _f64(f)
+        a = np.empty(self.ncx + self.nfx)
+        E = np.empty(self.nfx)
+        lib().vpo_amr_constraints(self.h, _p(f), _p(a), _p(E))
+        return a, E
+
+    def ghosted_patch(self, f, p):
+        f = _f64(f)
+        b = self.boxes[p]
+        nx, nv = b["hi"][0] - b["lo"][0] + 1, b["hi"][1] - b["lo"][1] + 1
+        out = np.empty((nx + 4, nv + 4))
+        lib().vpo_amr_fill_ghosts(self.h, _p(f), p, _p(out))
+        return out
+
+    def step(self, f, dt):
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().vpo_amr_rk4_step(self.h, _p(f), _p(out), dt)
+        return out

@@ -44,4 +44,16 @@ void vpo_constraints_adjoint(const vpo_ctx* c, const double* abar, double* fbar)
 void vpo_rk4_adjoint_step(const vpo_ctx* c, const double* f_n, const double* lam_np1,
                           double* lam_n, double dt);
 
+/* two-level hierarchy (vp_oracle_amr.c) */
+void vpo_interp_weights(int R, double* out);
+void* vpo_amr_new(int ncx, int ncv, double x_len, double v_lo, double v_hi, double qm, int R, int np,
+                  int* boxes, double* veq_c, double* veq_f);
+void vpo_amr_free(void* h);
+long vpo_amr_state_size(void* h);
+long vpo_amr_patch_offset(void* h, int p);
+void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out);
+void vpo_amr_reduce_mask(void* h, double* f, double* n);
+void vpo_amr_constraints(void* h, double* f, double* a, double* E_out);
+void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt);
+
 #endif

@@ -1,0 +1,368 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Two-level (coarse level + level-1 patches) 1D+1V Vlasov-Poisson step,
+ * written as the paper's synchronous multi-level algorithm (section 3,
+ * Algs. ssthu / mspsc / msrhsfa / msfduc / smsvphu, without regridding):
+ *
+ *   for each stage: predictor on every level; fine ghost cells filled by
+ *   conservative sub-cell interpolation from the coarse predictor of the
+ *   same stage; the constraint (Mask Reduction of section 3 -> periodic
+ *   Poisson on the finest configuration mesh -> field -> injection);
+ *   fluxes on every patch; F_accum += b_s F.
+ *   update: every level from its accumulated fluxes, with the coarse
+ *   fluxes on coarse-fine faces replaced by the mean of the fine ones
+ *   (coarsened fluxes), then covered coarse cells take the average of the
+ *   fine cells (restriction is plain summation).
+ *
+ * Readings (listed with the others in the design notes):
+ *   - sub-cell interpolation: the linear fifth-order cell-average formula of
+ *     section 3 with p_k(s) = ((s+1)^{k+1} - s^{k+1}) / R^k and the cubic
+ *     coefficient of gamma_1 equal to 20 (the printed p_k and 40 break
+ *     conservation and the partition of unity);
+ *   - two dimensions: x first, then v (dimension by dimension);
+ *   - the coarse field is the mean of the R fine field values;
+ *   - fine ghosts outside the velocity domain hold the fine equilibrium.
+ * The configuration requires every patch boundary to be a coarse-fine
+ * interface (patches separated by at least one coarse cell).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "vp_oracle.h"
+
+static int wrap(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+static int fdiv(int a, int b) { int q = a / b; return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q; }
+
+/* b_j(s), j = -2..2 at out[s*5 + j + 2]: fine-cell averages of the
+ * fifth-order interpolant, u^f_{Ri+s} = sum_j b_j(s) u_{i+j} */
+void vpo_interp_weights(int R, double* out)
+{
+    for (int s = 0; s < R; ++s) {
+        double p[5];
+        p[0] = 1.0;
+        for (int k = 1; k <= 4; ++k)
+            p[k] = (pow(s + 1.0, k + 1) - pow((double)s, k + 1)) / pow((double)R, k);
+        out[s * 5 + 0] = (p[4] - 5 * p[3] + 5 * p[2] + 5 * p[1] - 6) / 120.0;
+        out[s * 5 + 1] = (-4 * p[4] + 15 * p[3] + 10 * p[2] - 75 * p[1] + 54) / 120.0;
+        out[s * 5 + 2] = (6 * p[4] - 15 * p[3] - 40 * p[2] + 75 * p[1] + 94) / 120.0;
+        out[s * 5 + 3] = (-4 * p[4] + 5 * p[3] + 30 * p[2] - 5 * p[1] - 26) / 120.0;
+        out[s * 5 + 4] = (p[4] - 5 * p[2] + 4) / 120.0;
+    }
+}
+
+typedef struct {
+    int ncx, ncv, R, nfx, nfv, np;
+    double dxc, dvc, dxf, dvf, v_lo, qm;
+    int* box;             /* np x 4: lo_x, lo_v, hi_x, hi_v (fine index space) */
+    long* off;            /* np + 1 element offsets, off[0] = coarse size */
+    unsigned char* cov;   /* coarse cell covered by a patch */
+    double* veq_c;        /* ncv + 4 */
+    double* veq_f;        /* nfv + 4 */
+    double B[16][5];      /* R <= 16 */
+    vpo_poisson* P;
+    long total;
+} vpo_amr;
+
+void* vpo_amr_new(int ncx, int ncv, double x_len, double v_lo, double v_hi, double qm, int R, int np,
+                  int* boxes, double* veq_c, double* veq_f)
+{
+    vpo_amr* c = (vpo_amr*)calloc(1, sizeof(*c));
+    c->ncx = ncx; c->ncv = ncv; c->R = R; c->nfx = ncx * R; c->nfv = ncv * R; c->np = np;
+    c->dxc = x_len / ncx; c->dvc = (v_hi - v_lo) / ncv;
+    c->dxf = c->dxc / R; c->dvf = c->dvc / R;
+    c->v_lo = v_lo; c->qm = qm;
+    c->box = (int*)malloc(sizeof(int) * 4 * (np > 0 ? np : 1));
+    memcpy(c->box, boxes, sizeof(int) * 4 * np);
+    c->off = (long*)malloc(sizeof(long) * (np + 1));
+    long o = (long)ncx * ncv;
+    for (int p = 0; p < np; ++p) {
+        c->off[p] = o;
+        o += (long)(boxes[4 * p + 2] - boxes[4 * p] + 1) * (boxes[4 * p + 3] - boxes[4 * p + 1] + 1);
+    }
+    c->off[np] = o;
+    c->total = o;
+    c->cov = (unsigned char*)calloc((size_t)ncx * ncv, 1);
+    for (int p = 0; p < np; ++p)
+        for (int i = boxes[4 * p] / R; i <= boxes[4 * p + 2] / R; ++i)
+            for (int j = boxes[4 * p + 1] / R; j <= boxes[4 * p + 3] / R; ++j) c->cov[(size_t)i * ncv + j] = 1;
+    c->veq_c = (double*)malloc(sizeof(double) * (ncv + 4));
+    memcpy(c->veq_c, veq_c, sizeof(double) * (ncv + 4));
+    c->veq_f = (double*)malloc(sizeof(double) * (c->nfv + 4));
+    memcpy(c->veq_f, veq_f, sizeof(double) * (c->nfv + 4));
+    vpo_interp_weights(R, &c->B[0][0]);
+    c->P = vpo_poisson_new(c->nfx);
+    return c;
+}
+
+void vpo_amr_free(void* h)
+{
+    vpo_amr* c = (vpo_amr*)h;
+    if (!c) return;
+    free(c->box); free(c->off); free(c->cov); free(c->veq_c); free(c->veq_f);
+    vpo_poisson_free(c->P);
+    free(c);
+}
+
+long vpo_amr_state_size(void* h) { return ((vpo_amr*)h)->total; }
+long vpo_amr_patch_offset(void* h, int p) { vpo_amr* c = (vpo_amr*)h; return p < 0 ? 0 : c->off[p]; }
+
+#define NXP(c, p) ((c)->box[4 * (p) + 2] - (c)->box[4 * (p)] + 1)
+#define NVP(c, p) ((c)->box[4 * (p) + 3] - (c)->box[4 * (p) + 1] + 1)
+
+/* coarse value with x periodic and the coarse velocity ghosts */
+static double coarse_at(const vpo_amr* c, const double* f, int i, int j)
+{
+    if (j < 0 || j >= c->ncv) return c->veq_c[j + 2];
+    return f[(size_t)wrap(i, c->ncx) * c->ncv + j];
+}
+
+/* fine-cell value at global fine indices (I, J) interpolated from the coarse
+ * level: first along x, then along v */
+static double interp_fine(const vpo_amr* c, const double* f, int I, int J)
+{
+    if (J < 0 || J >= c->nfv) return c->veq_f[J + 2];
+    const int R = c->R;
+    int ci = fdiv(I, R), s = I - ci * R;
+    int cj = fdiv(J, R), t = J - cj * R;
+    double acc = 0.0;
+    for (int b = -2; b <= 2; ++b) {
+        double gx = 0.0;
+        for (int a = -2; a <= 2; ++a) gx += c->B[s][a + 2] * coarse_at(c, f, ci + a, cj + b);
+        acc += c->B[t][b + 2] * gx;
+    }
+    return acc;
+}
+
+/* patch p with two ghost layers: (nxp + 4) x (nvp + 4), ghosts from the coarse level */
+void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out)
+{
+    vpo_amr* c = (vpo_amr*)h;
+    int nxp = NXP(c, p), nvp = NVP(c, p), x0 = c->box[4 * p], v0 = c->box[4 * p + 1];
+    int W = nvp + 4;
+    const double* fp = f + c->off[p];
+    for (int r = -2; r < nxp + 2; ++r)
+        for (int q = -2; q < nvp + 2; ++q) {
+            double v;
+            if (r >= 0 && r < nxp && q >= 0 && q < nvp) v = fp[(size_t)r * nvp + q];
+            else v = interp_fine(c, f, x0 + r, v0 + q);
+            out[(size_t)(r + 2) * W + (q + 2)] = v;
+        }
+}
+
+/* Mask Reduction (section 3): refine coarse data in x, mask covered coarse
+ * cells, sum over v; add the fine patches' sums; n on the finest x mesh */
+void vpo_amr_reduce_mask(void* h, double* f, double* n)
+{
+    vpo_amr* c = (vpo_amr*)h;
+    const int R = c->R;
+    for (int I = 0; I < c->nfx; ++I) {
+        int i = I / R, s = I % R;
+        double sc = 0.0;
+        for (int j = 0; j < c->ncv; ++j) {
+            double fx = 0.0;
+            for (int a = -2; a <= 2; ++a) fx += c->B[s][a + 2] * coarse_at(c, f, i + a, j);
+            if (!c->cov[(size_t)i * c->ncv + j]) sc += fx;
+        }
+        double sf = 0.0;
+        for (int p = 0; p < c->np; ++p) {
+            int x0 = c->box[4 * p], x1 = c->box[4 * p + 2];
+            if (I < x0 || I > x1) continue;
+            int nvp = NVP(c, p);
+            const double* row = f + c->off[p] + (size_t)(I - x0) * nvp;
+            for (int q = 0; q < nvp; ++q) sf += row[q];
+        }
+        n[I] = c->dvc * sc + c->dvf * sf;
+    }
+}
+
+/* a on both levels: [a_c (ncx)][a_f (nfx)]; E on the fine mesh */
+void vpo_amr_constraints(void* h, double* f, double* a, double* E_out)
+{
+    vpo_amr* c = (vpo_amr*)h;
+    int nfx = c->nfx, R = c->R;
+    double* n = (double*)malloc(sizeof(double) * nfx);
+    double* rho = (double*)malloc(sizeof(double) * nfx);
+    double* phi = (double*)malloc(sizeof(double) * nfx);
+    double* E = (double*)malloc(sizeof(double) * nfx);
+    vpo_amr_reduce_mask(h, f, n);
+    for (int I = 0; I < nfx; ++I) rho[I] = 1.0 - n[I];
+    vpo_poisson_solve(c->P, c->dxf, rho, phi);
+    vpo_field(nfx, c->dxf, phi, E);
+    for (int i = 0; i < c->ncx; ++i) {
+        double s = 0.0;
+        for (int q = 0; q < R; ++q) s += E[i * R + q];
+        a[i] = c->qm * s / R;
+    }
+    for (int I = 0; I < nfx; ++I) a[c->ncx + I] = c->qm * E[I];
+    if (E_out) memcpy(E_out, E, sizeof(double) * nfx);
+    free(n); free(rho); free(phi); free(E);
+}
+
+static double face4(double um1, double u0, double u1, double u2)
+{
+    return (7.0 * (u0 + u1) - (um1 + u2)) / 12.0;
+}
+
+/* Fluxes of section 2 on one patch from its ghosted data g ((nx+4) x (nv+4)):
+ * Gx[(nx+1) x nv] for x faces -1/2 .. nx-1/2, Gv[nx x (nv+1)] for v faces
+ * -1/2 .. nv-1/2.  a_ext[i + 1] = a at patch row i, i = -1 .. nx. */
+static void patch_fluxes(int nx, int nv, const double* g, double dv, double v0, const double* a_ext,
+                         double* Gx, double* Gv)
+{
+    int W = nv + 4;
+#define G(i, j) g[(size_t)((i) + 2) * W + ((j) + 2)]
+    for (int i = -1; i < nx; ++i)           /* face i + 1/2 */
+        for (int j = 0; j < nv; ++j) {
+            double fc = face4(G(i - 1, j), G(i, j), G(i + 1, j), G(i + 2, j));
+            double fu = face4(G(i - 1, j + 1), G(i, j + 1), G(i + 1, j + 1), G(i + 2, j + 1));
+            double fd = face4(G(i - 1, j - 1), G(i, j - 1), G(i + 1, j - 1), G(i + 2, j - 1));
+            double vb = v0 + (j + 0.5) * dv;
+            Gx[(size_t)(i + 1) * nv + j] = vb * fc + dv / 24.0 * (fu - fd);
+        }
+    for (int i = 0; i < nx; ++i) {
+        double ai = a_ext[i + 1], da = a_ext[i + 2] - a_ext[i];
+        for (int j = -1; j < nv; ++j) {      /* face j + 1/2 */
+            double fc = face4(G(i, j - 1), G(i, j), G(i, j + 1), G(i, j + 2));
+            double fp = face4(G(i + 1, j - 1), G(i + 1, j), G(i + 1, j + 1), G(i + 1, j + 2));
+            double fm = face4(G(i - 1, j - 1), G(i - 1, j), G(i - 1, j + 1), G(i - 1, j + 2));
+            Gv[(size_t)i * (nv + 1) + (j + 1)] = ai * fc + da / 48.0 * (fp - fm);
+        }
+    }
+#undef G
+}
+
+/* flux divergence: k_ij = -(Gx_{i+1/2} - Gx_{i-1/2})/dx - (Gv_{j+1/2} - Gv_{j-1/2})/dv */
+static void divergence(int nx, int nv, const double* Gx, const double* Gv, double dx, double dv, double* k)
+{
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < nv; ++j)
+            k[(size_t)i * nv + j] = -(Gx[(size_t)(i + 1) * nv + j] - Gx[(size_t)i * nv + j]) / dx
+                                    - (Gv[(size_t)i * (nv + 1) + j + 1] - Gv[(size_t)i * (nv + 1) + j]) / dv;
+}
+
+/* all fluxes of the hierarchy for state f and accelerations a */
+static void hierarchy_fluxes(const vpo_amr* c, double* f, const double* a, double** Gx, double** Gv)
+{
+    int ncx = c->ncx, ncv = c->ncv;
+    /* coarse level: one periodic patch with velocity ghosts */
+    {
+        int W = ncv + 4;
+        double* g = (double*)malloc(sizeof(double) * (size_t)(ncx + 4) * W);
+        for (int i = -2; i < ncx + 2; ++i)
+            for (int j = -2; j < ncv + 2; ++j) g[(size_t)(i + 2) * W + j + 2] = coarse_at(c, f, i, j);
+        double* ae = (double*)malloc(sizeof(double) * (ncx + 2));
+        for (int i = -1; i <= ncx; ++i) ae[i + 1] = a[wrap(i, ncx)];
+        patch_fluxes(ncx, ncv, g, c->dvc, c->v_lo, ae, Gx[0], Gv[0]);
+        free(ae);
+        free(g);
+    }
+    for (int p = 0; p < c->np; ++p) {
+        int nxp = NXP(c, p), nvp = NVP(c, p), x0 = c->box[4 * p], v0 = c->box[4 * p + 1];
+        double* g = (double*)malloc(sizeof(double) * (size_t)(nxp + 4) * (nvp + 4));
+        vpo_amr_fill_ghosts((void*)c, f, p, g);
+        double* ae = (double*)malloc(sizeof(double) * (nxp + 2));
+        for (int i = -1; i <= nxp; ++i) ae[i + 1] = a[ncx + wrap(x0 + i, c->nfx)];
+        patch_fluxes(nxp, nvp, g, c->dvf, c->v_lo + v0 * c->dvf, ae, Gx[p + 1], Gv[p + 1]);
+        free(ae);
+        free(g);
+    }
+}
+
+/* one synchronous RK4 step of the two-level hierarchy (Alg. smsvphu) */
+void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt)
+{
+    static const double alpha[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    vpo_amr* c = (vpo_amr*)h;
+    const int np = c->np, ncx = c->ncx, ncv = c->ncv, R = c->R;
+    const long N = c->total;
+    double* fn = (double*)malloc(sizeof(double) * N);
+    double* fs = (double*)malloc(sizeof(double) * N);
+    double* k = (double*)calloc(N, sizeof(double));
+    double* a = (double*)malloc(sizeof(double) * (ncx + c->nfx));
+    memcpy(fn, f_in, sizeof(double) * N);
+    double **Gx = (double**)malloc(sizeof(double*) * (np + 1)), **Gv = (double**)malloc(sizeof(double*) * (np + 1));
+    double **Ax = (double**)malloc(sizeof(double*) * (np + 1)), **Av = (double**)malloc(sizeof(double*) * (np + 1));
+    for (int p = 0; p <= np; ++p) {
+        int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
+        Gx[p] = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * nv);
+        Gv[p] = (double*)malloc(sizeof(double) * (size_t)nx * (nv + 1));
+        Ax[p] = (double*)calloc((size_t)(nx + 1) * nv, sizeof(double));
+        Av[p] = (double*)calloc((size_t)nx * (nv + 1), sizeof(double));
+    }
+    for (int s = 0; s < 4; ++s) {
+        /* ComputePredictorState on every level */
+        for (long q = 0; q < N; ++q) fs[q] = fn[q] + alpha[s] * dt * k[q];
+        /* ComputeInstantaneousConstraints */
+        vpo_amr_constraints(h, fs, a, NULL);
+        /* ComputeRHS: fluxes, divergence, flux accumulation */
+        hierarchy_fluxes(c, fs, a, Gx, Gv);
+        for (int p = 0; p <= np; ++p) {
+            int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
+            double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
+            divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
+            for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[p][q] += bw[s] * Gx[p][q];
+            for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[p][q] += bw[s] * Gv[p][q];
+        }
+    }
+    /* ComputeUpdate: finest level first */
+    for (int p = 1; p <= np; ++p) {
+        int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
+        divergence(nx, nv, Ax[p], Av[p], c->dxf, c->dvf, k + c->off[p - 1]);
+        for (long q = 0; q < (long)nx * nv; ++q) f_out[c->off[p - 1] + q] = fn[c->off[p - 1] + q] + dt * k[c->off[p - 1] + q];
+    }
+    /* coarsen the fine accumulated fluxes onto the coarse-fine faces */
+    for (int p = 0; p < np; ++p) {
+        int x0 = c->box[4 * p], v0 = c->box[4 * p + 1], nxp = NXP(c, p), nvp = NVP(c, p);
+        int ci0 = x0 / R, ci1 = (x0 + nxp) / R - 1, cj0 = v0 / R, cj1 = (v0 + nvp) / R - 1;
+        for (int cj = cj0; cj <= cj1; ++cj) {       /* x faces at ci0 - 1/2 and ci1 + 1/2 */
+            double lo = 0.0, hi = 0.0;
+            for (int t = 0; t < R; ++t) {
+                int J = cj * R + t - v0;
+                lo += Ax[p + 1][(size_t)0 * nvp + J];
+                hi += Ax[p + 1][(size_t)nxp * nvp + J];
+            }
+            Ax[0][(size_t)wrap(ci0, ncx) * ncv + cj] = lo / R;              /* face ci0 - 1/2 */
+            Ax[0][(size_t)(wrap(ci1, ncx) + 1) * ncv + cj] = hi / R;        /* face ci1 + 1/2 */
+        }
+        for (int ci = ci0; ci <= ci1; ++ci) {       /* v faces at cj0 - 1/2 and cj1 + 1/2 */
+            double lo = 0.0, hi = 0.0;
+            for (int s2 = 0; s2 < R; ++s2) {
+                int I = ci * R + s2 - x0;
+                lo += Av[p + 1][(size_t)I * (nvp + 1) + 0];
+                hi += Av[p + 1][(size_t)I * (nvp + 1) + nvp];
+            }
+            Av[0][(size_t)ci * (ncv + 1) + cj0] = lo / R;
+            Av[0][(size_t)ci * (ncv + 1) + cj1 + 1] = hi / R;
+        }
+    }
+    /* periodic x: coarse face 0 - 1/2 and face ncx - 1/2 are the same face */
+    for (int j = 0; j < ncv; ++j) {
+        double* f0 = &Ax[0][j];
+        double* fN = &Ax[0][(size_t)ncx * ncv + j];
+        /* one of the two may have been replaced above; keep them equal */
+        if (*f0 != *fN) {
+            int left_cov = c->cov[(size_t)(ncx - 1) * ncv + j], right_cov = c->cov[j];
+            if (left_cov != right_cov) { double v = left_cov ? *fN : *f0; *f0 = v; *fN = v; }
+        }
+    }
+    divergence(ncx, ncv, Ax[0], Av[0], c->dxc, c->dvc, k);
+    for (long q = 0; q < (long)ncx * ncv; ++q) f_out[q] = fn[q] + dt * k[q];
+    /* average fine data down onto covered coarse cells */
+    for (int p = 0; p < np; ++p) {
+        int x0 = c->box[4 * p], v0 = c->box[4 * p + 1], nxp = NXP(c, p), nvp = NVP(c, p);
+        for (int ci = x0 / R; ci < (x0 + nxp) / R; ++ci)
+            for (int cj = v0 / R; cj < (v0 + nvp) / R; ++cj) {
+                double sum = 0.0;
+                for (int s2 = 0; s2 < R; ++s2)
+                    for (int t = 0; t < R; ++t)
+                        sum += f_out[c->off[p] + (size_t)(ci * R + s2 - x0) * nvp + (cj * R + t - v0)];
+                f_out[(size_t)ci * ncv + cj] = sum / (R * R);
+            }
+    }
+    for (int p = 0; p <= np; ++p) { free(Gx[p]); free(Gv[p]); free(Ax[p]); free(Av[p]); }
+    free(Gx); free(Gv); free(Ax); free(Av);
+    free(fn); free(fs); free(k); free(a);
+}

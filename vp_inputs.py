@@ -194,12 +194,13 @@ class Problem2D:
 
 def amr_boxes(seed: int = 0, coarse=(512, 512), ratio: int = 4, npatch: int = 40,
               side_lo: int = 16, side_hi: int = 128, v_lo: float = -8.0, v_hi: float = 8.0,
-              v_band: float = 3.0):
-    """Seeded layout of disjoint level-1 patches (inclusive lo/hi in the
-    level-1 index space), sides drawn uniformly from {side_lo, side_lo+4, ...,
-    side_hi}, lo corners aligned to the refinement ratio, confined to the
-    velocity band |v| < v_band and not wrapping in x.  Overlapping draws
-    are rejected; touching patches are allowed."""
+              v_band: float = 3.0, gap: int = 4):
+    """Seeded layout of level-1 patches (inclusive lo/hi in the level-1 index
+    space): sides drawn uniformly from {side_lo, side_lo+4, ..., side_hi},
+    corners aligned to the refinement ratio, confined to the velocity band
+    |v| < v_band, not wrapping in x.  Patches grown by `gap` fine cells (one
+    coarse cell) must not intersect, so every patch boundary is a
+    coarse-fine interface; draws that violate this are rejected."""
     rng = np.random.default_rng(seed)
     nxf, nvf = coarse[0] * ratio, coarse[1] * ratio
     dvf = (v_hi - v_lo) / nvf
@@ -210,24 +211,41 @@ def amr_boxes(seed: int = 0, coarse=(512, 512), ratio: int = 4, npatch: int = 40
     tries = 0
     while len(boxes) < npatch:
         tries += 1
-        if tries > 100000:
+        if tries > 200000:
             raise RuntimeError("could not place patches")
         wx = int(rng.choice(sides))
         wv = int(rng.choice(sides))
         if wv > band_hi - band_lo:
             continue
         x0 = int(rng.integers(0, (nxf - wx) // ratio + 1)) * ratio
-        v0 = int(rng.integers(band_lo // ratio + (1 if band_lo % ratio else 0),
-                              (band_hi - wv) // ratio + 1)) * ratio
+        v0 = int(rng.integers(-(-band_lo // ratio), (band_hi - wv) // ratio + 1)) * ratio
         lo = (x0, v0)
         hi = (x0 + wx - 1, v0 + wv - 1)
         if v0 < band_lo or hi[1] >= band_hi:
             continue
-        ok = all(hi[0] < b[0][0] or b[1][0] < lo[0] or hi[1] < b[0][1] or b[1][1] < lo[1]
+        ok = all(hi[0] + gap < b[0][0] or b[1][0] + gap < lo[0] or hi[1] + gap < b[0][1] or b[1][1] + gap < lo[1]
                  for b in boxes)
         if ok:
             boxes.append((lo, hi))
     return [{"level": 1, "lo": list(b[0]), "hi": list(b[1])} for b in boxes]
+
+
+def amr_landau(boxes, coarse=(512, 512), ratio: int = 4, eps: float = 0.01, k: float = 0.5):
+    """Two-level Landau problem: exact cell averages of (1 + eps cos(k x)) M(v)
+    on the coarse level (all cells) and on every patch, concatenated in the
+    state layout [coarse][patch 0][patch 1]...; returns (state, veq_c, veq_f)."""
+    ncx, ncv = coarse
+    x_len, v_lo, v_hi = 4.0 * math.pi, -8.0, 8.0
+    veq_c = cell_average_1d(maxwellian, v_lo, v_hi, ncv, first=-2, count=ncv + 4)
+    nvf = ncv * ratio
+    veq_f = cell_average_1d(maxwellian, v_lo, v_hi, nvf, first=-2, count=nvf + 4)
+    xc = 1.0 + eps * cos_cell_average(0.0, x_len, ncx, k)
+    xf = 1.0 + eps * cos_cell_average(0.0, x_len, ncx * ratio, k)
+    parts = [(xc[:, None] * veq_c[None, 2:ncv + 2]).ravel()]
+    for b in boxes:
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        parts.append((xf[x0:x1 + 1, None] * veq_f[None, 2 + v0:2 + v1 + 1]).ravel())
+    return np.concatenate(parts), veq_c, veq_f
 
 
 def save_boxes(path, boxes):
