@@ -97,8 +97,14 @@ typedef struct vp_problem {
 /*
  * A level-1 patch: inclusive cell range [lo, hi] per direction in the
  * level-1 global index space (section 3, box notation).  Level 0 always
- * covers the whole domain and is implicit.  Patches must be disjoint,
- * aligned to the refinement ratio and inside the domain.
+ * covers the whole domain and is implicit.  Patches must be inside the
+ * domain (no periodic wrap inside one patch) and aligned to the refinement
+ * ratio (lo and hi + 1 multiples of it), and any two patches must be
+ * separated by at least one level-0 cell, also across the periodic
+ * boundary, so that every patch boundary is a coarse-fine interface
+ * (VP_EINVAL for a bad box, VP_ENOTSUP for patches that touch).  Two
+ * levels are supported for 1D+1V in FP64 with ratio 2 or 4 (equal in x
+ * and v) and a finest configuration mesh of at most 8192 cells.
  */
 typedef struct vp_box {
     int32_t level;
@@ -140,8 +146,9 @@ size_t vp_stage_elems(const vp_plan* plan);
  *   a  acceleration (q/m) E per level, vp_field_elems (from vp_inject_field)
  *   k  output, same layout and dtype as f; must not alias f
  * Ghost cells are synthesised: x periodic, velocity ghosts from veq, and on
- * level 1 copies from neighbouring patches or fifth-order conservative
- * interpolation from level 0 (section 3, sub-cell interpolation).
+ * level 1 the fifth-order conservative sub-cell interpolation of level 0,
+ * along x then along v (section 3); level-1 ghosts outside the velocity
+ * box take veq[1][0].
  */
 vp_status vp_rhs(const vp_plan* plan, const void* f, const double* a, void* k,
                  hipStream_t stream);
@@ -240,15 +247,43 @@ vp_status vp_field_adjoint(const vp_plan* plan, const double* abar, void* fbar, 
 /*
  * Tile shapes of the stage kernels, for autotuning.  A shape is (threads
  * per block, velocity cells per thread, configuration rows per tile).
- * vp_tile_shape_count / _get enumerate the shapes compiled for the plan's
- * dtype; vp_tile_shape_set selects one for every later call on the plan
- * (results agree to rounding for every shape; only speed changes).  Not safe
- * to call while other calls on the same plan are being enqueued.
+ * vp_tile_shape_count / _get enumerate the shapes compiled for the plan
+ * (its dtype and number of levels); vp_tile_shape_set selects one for
+ * every later call on the plan (results agree to rounding for every shape;
+ * only speed changes).  On two levels a shape with two cells per thread
+ * needs even patch widths in v (VP_EINVAL otherwise).  Not safe to call
+ * while other calls on the same plan are being enqueued.
  */
 int32_t vp_tile_shape_count(const vp_plan* plan);
 vp_status vp_tile_shape_get(const vp_plan* plan, int32_t index, int32_t* threads, int32_t* cells,
                             int32_t* rows);
 vp_status vp_tile_shape_set(vp_plan* plan, int32_t index);
+
+/*
+ * Launch structure of a two-level stage (the task-parallel overhead of
+ * section 4 is what the persistent form removes):
+ *   VP_LAUNCH_PERSISTENT  one launch per RK4 stage walks a tile table that
+ *                         holds every tile of level 0, of every level-1
+ *                         patch and the coarse-fine face chunks (default)
+ *   VP_LAUNCH_PER_PATCH   one launch for level 0, one per patch and one for
+ *                         the face chunks (the per-patch baseline)
+ * Both run the same tiles with the same arithmetic: results are
+ * bitwise identical.  No effect on single-level plans.
+ */
+#define VP_LAUNCH_PERSISTENT 0
+#define VP_LAUNCH_PER_PATCH 1
+vp_status vp_launch_mode_set(vp_plan* plan, int32_t mode);
+
+/*
+ * Autotuner: times `reps` RK4 steps (after one warm-up step) for every
+ * tile shape valid for the plan, selects the fastest with
+ * vp_tile_shape_set and returns its index and mean step time in ms (either
+ * output may be NULL).  f and a are used as scratch: they are advanced by
+ * (reps + 1) steps per shape, so pass copies of the state.  Unlike the
+ * other calls it synchronises on its own timing events.
+ */
+vp_status vp_autotune(vp_plan* plan, void* f, double* a, double dt, int32_t reps, void* work,
+                      hipStream_t stream, int32_t* best_index, float* best_ms);
 
 /*
  * Kernel timing (a profiling aid, per-routine exclusive timers): while

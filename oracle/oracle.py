@@ -91,6 +91,7 @@ def _declare_extra(L):
         "vpo_amr_constraints": (None, [_V, _D, _D, _D]),
         "vpo_amr_fill_ghosts": (None, [_V, _D, _I, _D]),
         "vpo_amr_rk4_step": (None, [_V, _D, _D, _F]),
+        "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
         "vpo4_ctx_new": (_V, [_I, _I, _I, _I, _F, _F, _F, _F, _F, _D, _D]),
         "vpo4_ctx_free": (None, [_V]),
         "vpo4_moment": (None, [_V, _D, _D]),
@@ -296,6 +297,13 @@ class OracleAMR:
         out = np.empty((nx + 4, nv + 4))
         lib().vpo_amr_fill_ghosts(self.h, _p(f), p, _p(out))
         return out
+
+    def rhs(self, f, a):
+        """k = L(f; a) on every patch, a = [a_coarse, a_fine]"""
+        f, a = _f64(f), _f64(a)
+        k = np.empty_like(f)
+        lib().vpo_amr_rhs(self.h, _p(f), _p(a), _p(k))
+        return k
 
     def step(self, f, dt):
         f = _f64(f)

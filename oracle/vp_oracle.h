@@ -54,6 +54,7 @@ long vpo_amr_patch_offset(void* h, int p);
 void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out);
 void vpo_amr_reduce_mask(void* h, double* f, double* n);
 void vpo_amr_constraints(void* h, double* f, double* a, double* E_out);
+void vpo_amr_rhs(void* h, double* f, double* a, double* k);
 void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt);
 
 #endif

@@ -270,6 +270,30 @@ static void hierarchy_fluxes(const vpo_amr* c, double* f, const double* a, doubl
     }
 }
 
+/* k = L(f; a) on every patch of the hierarchy (the ComputeRHS fluxes and
+ * divergence of one stage, without accumulation) */
+void vpo_amr_rhs(void* h, double* f, double* a, double* k)
+{
+    vpo_amr* c = (vpo_amr*)h;
+    const int np = c->np;
+    double **Gx = (double**)malloc(sizeof(double*) * (np + 1)), **Gv = (double**)malloc(sizeof(double*) * (np + 1));
+    for (int p = 0; p <= np; ++p) {
+        int nx = p == 0 ? c->ncx : NXP(c, p - 1), nv = p == 0 ? c->ncv : NVP(c, p - 1);
+        Gx[p] = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * nv);
+        Gv[p] = (double*)malloc(sizeof(double) * (size_t)nx * (nv + 1));
+    }
+    hierarchy_fluxes(c, f, a, Gx, Gv);
+    for (int p = 0; p <= np; ++p) {
+        int nx = p == 0 ? c->ncx : NXP(c, p - 1), nv = p == 0 ? c->ncv : NVP(c, p - 1);
+        double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
+        divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
+        free(Gx[p]);
+        free(Gv[p]);
+    }
+    free(Gx);
+    free(Gv);
+}
+
 /* one synchronous RK4 step of the two-level hierarchy (Alg. smsvphu) */
 void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt)
 {

@@ -1,0 +1,500 @@
+// Host runtime of the two-level path: box validation and box calculus
+// (section 3: coverage, coarse-fine faces, the Sub-Patch decomposition of
+// Alg. subdiv), device tables, and the enqueue sequence of one synchronous
+// RK4 step (Alg. smsvphu without regridding).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+namespace {
+
+struct Box {
+    int xlo, vlo, xhi, vhi;   // inclusive
+    bool empty() const { return xlo > xhi || vlo > vhi; }
+};
+
+Box intersect(const Box& a, const Box& b)
+{
+    return Box{std::max(a.xlo, b.xlo), std::max(a.vlo, b.vlo), std::min(a.xhi, b.xhi), std::min(a.vhi, b.vhi)};
+}
+
+// b_j(s) of the fifth-order conservative sub-cell interpolation (section 3),
+// with p_k(s) = ((s+1)^{k+1} - s^{k+1}) / R^k
+std::vector<double> interp_table(int R)
+{
+    std::vector<double> B((size_t)R * 5);
+    for (int s = 0; s < R; ++s) {
+        double p[5];
+        p[0] = 1.0;
+        for (int k = 1; k <= 4; ++k) p[k] = (std::pow(s + 1.0, k + 1) - std::pow((double)s, k + 1)) / std::pow((double)R, k);
+        B[s * 5 + 0] = (p[4] - 5 * p[3] + 5 * p[2] + 5 * p[1] - 6) / 120.0;
+        B[s * 5 + 1] = (-4 * p[4] + 15 * p[3] + 10 * p[2] - 75 * p[1] + 54) / 120.0;
+        B[s * 5 + 2] = (6 * p[4] - 15 * p[3] - 40 * p[2] + 75 * p[1] + 94) / 120.0;
+        B[s * 5 + 3] = (-4 * p[4] + 5 * p[3] + 30 * p[2] - 5 * p[1] - 26) / 120.0;
+        B[s * 5 + 4] = (p[4] - 5 * p[2] + 4) / 120.0;
+    }
+    return B;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& v)
+{
+    if (*dst) (void)hipFree(*dst);
+    *dst = nullptr;
+    if (v.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(dst, v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+char* wsp(void* work, size_t off) { return static_cast<char*>(work) + off; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// tile table for the shape (nt, w, tx)
+void build_tiles(AmrPlan& A)
+{
+    const int tv = A.nt * A.w;
+    A.tiles.clear();
+    A.patch_tile_begin.clear();
+    A.nstrip_c = (A.ncv + tv - 1) / tv;
+    const int nseg_c = (A.ncx + A.tx - 1) / A.tx;
+    A.ncoarse_tiles = A.nstrip_c * nseg_c;
+    for (int t = 0; t < A.ncoarse_tiles; ++t) A.tiles.push_back(AmrTile{kTileCoarse, 0, t, 0});
+    for (size_t p = 0; p < A.patches.size(); ++p) {
+        A.patch_tile_begin.push_back((int)A.tiles.size());
+        const AmrPatch& P = A.patches[p];
+        const int ns = (P.nv + tv - 1) / tv, nseg = (P.nx + A.tx - 1) / A.tx;
+        for (int g = 0; g < nseg; ++g)
+            for (int b = 0; b < ns; ++b) A.tiles.push_back(AmrTile{kTileFine, (int)p, g, b});
+    }
+    A.face_tile_begin = (int)A.tiles.size();
+    A.patch_tile_begin.push_back(A.face_tile_begin);
+    const int nf = (int)A.faces.size();
+    for (int f0 = 0; f0 < nf; f0 += A.nt) A.tiles.push_back(AmrTile{kTileFaces, f0, std::min(A.nt, nf - f0), 0});
+    A.ntiles = (int)A.tiles.size();
+}
+
+AmrArgs stage_args(const vp_plan* p, const void* fs, const void* fn, void* acc, void* fout, const double* a,
+                   double c_acc, double c_next, double c_flux, int first, void* work)
+{
+    const AmrPlan& M = *p->amr;
+    AmrArgs A{};
+    Stage1DArgs& C = A.coarse;
+    C.nx = M.ncx;
+    C.nv = M.ncv;
+    C.tx = M.tx;
+    C.nstrip = M.nstrip_c;
+    C.dxi = 1.0 / M.dxc;
+    C.dvi = 1.0 / M.dvc;
+    C.dv24 = M.dvc / 24.0;
+    C.v_lo = M.v_lo;
+    C.dv = M.dvc;
+    for (int q = 0; q < 4; ++q) C.vg[q] = M.vgc[q];
+    C.fs = fs;
+    C.fn = fn;
+    C.acc = acc;
+    C.fout = fout;
+    C.a = a;
+    C.part = nullptr;
+    C.c_acc = c_acc;
+    C.c_next = c_next;
+    A.patches = M.d_patches;
+    A.tiles = M.d_tiles;
+    A.ntiles = M.ntiles;
+    A.nfx = M.nfx;
+    A.nfv = M.nfv;
+    A.R = M.R;
+    A.lr = M.lr;
+    A.tx = M.tx;
+    A.dxfi = 1.0 / M.dxf;
+    A.dvfi = 1.0 / M.dvf;
+    A.dvf24 = M.dvf / 24.0;
+    A.dvf = M.dvf;
+    A.v_lo = M.v_lo;
+    for (int q = 0; q < 4; ++q) A.vgf[q] = M.vgf[q];
+    A.a_f = a + M.ncx;
+    A.B = M.d_B;
+    A.faces = M.d_faces;
+    A.cf_acc = work ? reinterpret_cast<double*>(wsp(work, M.ws_cf)) : nullptr;
+    A.ff_acc = work ? reinterpret_cast<double*>(wsp(work, M.ws_ff)) : nullptr;
+    A.c_flux = c_flux;
+    A.first = first;
+    return A;
+}
+
+hipError_t launch_stage_all(const vp_plan* p, int kind, const AmrArgs& A, hipStream_t stream)
+{
+    const AmrPlan& M = *p->amr;
+    const int cap = 256 * 8;
+    if (M.mode == 0) {
+        const int grid = std::min(M.ntiles, cap);
+        return launch_amr_stage(M.w, M.nt, kind, A, 0, M.ntiles, grid, stream);
+    }
+    // baseline: the coarse level, each patch and the face chunks as separate launches
+    hipError_t e = launch_amr_stage(M.w, M.nt, kind, A, 0, M.ncoarse_tiles, std::min(M.ncoarse_tiles, cap), stream);
+    if (e != hipSuccess) return e;
+    for (size_t q = 0; q + 1 < M.patch_tile_begin.size(); ++q) {
+        const int t0 = M.patch_tile_begin[q], t1 = M.patch_tile_begin[q + 1];
+        e = launch_amr_stage(M.w, M.nt, kind, A, t0, t1, std::min(t1 - t0, cap), stream);
+        if (e != hipSuccess) return e;
+    }
+    if (M.ntiles > M.face_tile_begin)
+        e = launch_amr_stage(M.w, M.nt, kind, A, M.face_tile_begin, M.ntiles,
+                             std::min(M.ntiles - M.face_tile_begin, cap), stream);
+    return e;
+}
+
+// reduction -> Poisson on the finest configuration mesh -> injection
+vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, hipStream_t stream)
+{
+    const AmrPlan& M = *p->amr;
+    double* slots = reinterpret_cast<double*>(wsp(work, M.ws_slots));
+    double* n = reinterpret_cast<double*>(wsp(work, M.ws_n));
+    double* E = reinterpret_cast<double*>(wsp(work, M.ws_E));
+    VP_HIP(timed(p, kTMoment, stream, [&] {
+        hipError_t e = launch_amr_rowsum(f, M.d_task_off, M.d_task_len, M.ntasks, slots, stream);
+        if (e != hipSuccess) return e;
+        return launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.nfx, n, stream);
+    }));
+    VP_HIP(timed(p, kTField, stream, [&] {
+        return launch_poisson1d(nullptr, 0, n, M.dvf, M.nfx, M.dxf, p->pb.qm, p->d_green, p->gk, nullptr, nullptr, E,
+                                nullptr, stream);
+    }));
+    VP_HIP(timed(p, kTOther, stream, [&] { return launch_amr_inject(E, M.ncx, M.R, p->pb.qm, a, stream); }));
+    return VP_OK;
+}
+
+}  // namespace
+
+vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx)
+{
+    AmrPlan& M = *p->amr;
+    if (!((nt == 64 || nt == 128) && (w == 1 || w == 2) && tx >= 1 && tx <= kMaxTx))
+        return fail(VP_EINVAL, "two-level tile shape must be threads 64|128, cells 1|2, rows 1..128");
+    if (w == 2) {
+        if (M.ncv % 2) return fail(VP_EINVAL, "two cells per thread needs an even coarse velocity count");
+        for (const AmrPatch& P : M.patches)
+            if (P.nv % 2) return fail(VP_EINVAL, "two cells per thread needs even patch widths");
+    }
+    VP_HIP(hipDeviceSynchronize());       // the old tile table may still be read by queued launches
+    M.nt = nt;
+    M.w = w;
+    M.tx = tx;
+    build_tiles(M);
+    VP_HIP(upload(&M.d_tiles, M.tiles));
+    return VP_OK;
+}
+
+vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox)
+{
+    if (pb->ndim != 1) return fail(VP_ENOTSUP, "two levels are supported for 1D+1V");
+    if (pb->dtype != VP_F64) return fail(VP_ENOTSUP, "two levels are supported in FP64");
+    const int R = pb->ratio[0];
+    if (pb->ratio[1] != R || (R != 2 && R != 4)) return fail(VP_ENOTSUP, "refinement ratio must be 2 or 4, equal in x and v");
+    if (!pb->veq[1][0]) return fail(VP_EINVAL, "veq[1][0] (level-1 equilibrium with ghosts) is required");
+    AmrPlan* M = new AmrPlan();
+    p->amr = M;
+    M->ncx = pb->cells[0];
+    M->ncv = pb->cells[1];
+    M->R = R;
+    M->lr = R == 4 ? 2 : 1;
+    M->nfx = M->ncx * R;
+    M->nfv = M->ncv * R;
+    M->dxc = pb->x_len[0] / M->ncx;
+    M->dvc = (pb->v_hi[0] - pb->v_lo[0]) / M->ncv;
+    M->dxf = M->dxc / R;
+    M->dvf = M->dvc / R;
+    M->v_lo = pb->v_lo[0];
+    const double* vc = pb->veq[0][0];
+    const double* vf = pb->veq[1][0];
+    M->vgc[0] = vc[0]; M->vgc[1] = vc[1]; M->vgc[2] = vc[M->ncv + 2]; M->vgc[3] = vc[M->ncv + 3];
+    M->vgf[0] = vf[0]; M->vgf[1] = vf[1]; M->vgf[2] = vf[M->nfv + 2]; M->vgf[3] = vf[M->nfv + 3];
+    if (M->nfx > kMaxPoisson1D) return fail(VP_ENOTSUP, "finest configuration mesh larger than 8192 cells");
+
+    // ---- boxes: level 1, inside the domain, aligned to R, separated by one coarse cell
+    std::vector<Box> bx;
+    for (int q = 0; q < nbox; ++q) {
+        const vp_box& b = boxes[q];
+        if (b.level != 1) return fail(VP_EINVAL, "boxes must be on level 1");
+        Box B{b.lo[0], b.lo[1], b.hi[0], b.hi[1]};
+        if (B.empty() || B.xlo < 0 || B.vlo < 0 || B.xhi >= M->nfx || B.vhi >= M->nfv)
+            return fail(VP_EINVAL, "box " + std::to_string(q) + " is empty or outside the level-1 domain");
+        if (B.xlo % R || B.vlo % R || (B.xhi + 1) % R || (B.vhi + 1) % R)
+            return fail(VP_EINVAL, "box " + std::to_string(q) + " is not aligned to the refinement ratio");
+        for (size_t r = 0; r < bx.size(); ++r) {
+            const Box& o = bx[r];
+            Box grown{B.xlo - R, B.vlo - R, B.xhi + R, B.vhi + R};
+            if (!intersect(grown, o).empty())
+                return fail(VP_ENOTSUP, "boxes " + std::to_string(r) + " and " + std::to_string(q) +
+                                            " overlap or are closer than one coarse cell");
+            // periodic images in x
+            for (int sh : {-M->nfx, M->nfx}) {
+                Box g2{grown.xlo + sh, grown.vlo, grown.xhi + sh, grown.vhi};
+                if (!intersect(g2, o).empty())
+                    return fail(VP_ENOTSUP, "boxes " + std::to_string(r) + " and " + std::to_string(q) +
+                                                " are closer than one coarse cell across the periodic boundary");
+            }
+        }
+        bx.push_back(B);
+    }
+
+    // ---- patches and state layout
+    size_t off = (size_t)M->ncx * M->ncv, foff = 0;
+    for (const Box& B : bx) {
+        AmrPatch P{};
+        P.off = (long long)off;
+        P.foff = (long long)foff;
+        P.gx0 = B.xlo;
+        P.gv0 = B.vlo;
+        P.nx = B.xhi - B.xlo + 1;
+        P.nv = B.vhi - B.vlo + 1;
+        off += (size_t)P.nx * P.nv;
+        foff += 2 * (size_t)(P.nx + P.nv);
+        M->patches.push_back(P);
+    }
+    M->total = off;
+    M->fflux = foff;
+
+    // ---- coverage of coarse cells, coarse-fine faces, corrections, restriction
+    const int ncx = M->ncx, ncv = M->ncv;
+    std::vector<int> owner((size_t)ncx * ncv, -1);
+    for (size_t q = 0; q < bx.size(); ++q)
+        for (int i = bx[q].xlo / R; i <= bx[q].xhi / R; ++i)
+            for (int j = bx[q].vlo / R; j <= bx[q].vhi / R; ++j) owner[(size_t)i * ncv + j] = (int)q;
+    auto own = [&](int i, int j) { return owner[(size_t)(((i % ncx) + ncx) % ncx) * ncv + j]; };
+    std::vector<std::vector<int>> corr((size_t)ncx * ncv);   // per coarse cell: encoded faces
+    for (int i = 0; i < ncx; ++i)
+        for (int j = 0; j < ncv; ++j) {
+            // x face between (i, j) and (i + 1, j)
+            const int a = own(i, j), b = own(i + 1, j);
+            if ((a < 0) != (b < 0)) {
+                AmrFace F{i, j, 0, 0};
+                const int q = a >= 0 ? a : b;
+                const AmrPatch& P = M->patches[q];
+                // covered on the high side: the patch's lower x face; else its upper x face
+                F.fine = (int)(P.foff + (a < 0 ? 0 : P.nv) + (j * R - P.gv0));
+                const int fi = (int)M->faces.size();
+                M->faces.push_back(F);
+                if (a < 0) corr[(size_t)i * ncv + j].push_back(fi);                               // face above cell (i, j)
+                else corr[(size_t)(((i + 1) % ncx)) * ncv + j].push_back(-fi - 1);              // face below cell (i+1, j)
+            }
+            if (j + 1 < ncv) {
+                const int c = own(i, j + 1);
+                if ((a < 0) != (c < 0)) {
+                    AmrFace F{i, j, 1, 0};
+                    const int q = a >= 0 ? a : c;
+                    const AmrPatch& P = M->patches[q];
+                    F.fine = (int)(P.foff + 2 * P.nv + (a < 0 ? 0 : P.nx) + (i * R - P.gx0));
+                    const int fi = (int)M->faces.size();
+                    M->faces.push_back(F);
+                    if (a < 0) corr[(size_t)i * ncv + j].push_back(fi);
+                    else corr[(size_t)i * ncv + j + 1].push_back(-fi - 1);
+                }
+            }
+        }
+    std::vector<int> corr_ptr{0}, corr_face, corr_cell;
+    for (size_t c = 0; c < corr.size(); ++c) {
+        if (corr[c].empty()) continue;
+        corr_cell.push_back((int)c);
+        for (int e : corr[c]) corr_face.push_back(e);
+        corr_ptr.push_back((int)corr_face.size());
+    }
+    M->ncorr = (int)corr_cell.size();
+    std::vector<int> cov_cell, cov_nv;
+    std::vector<long long> cov_fine;
+    for (int i = 0; i < ncx; ++i)
+        for (int j = 0; j < ncv; ++j) {
+            const int q = owner[(size_t)i * ncv + j];
+            if (q < 0) continue;
+            const AmrPatch& P = M->patches[q];
+            cov_cell.push_back(i * ncv + j);
+            cov_fine.push_back(P.off + (long long)(i * R - P.gx0) * P.nv + (j * R - P.gv0));
+            cov_nv.push_back(P.nv);
+        }
+    M->ncov = (int)cov_cell.size();
+
+    // ---- Sub-Patch reduction: Alg. subdiv on the coarse level, then the
+    // row-sum tasks (each sub-patch grown by two columns in x) and the
+    // fixed-order contribution list of every fine configuration cell
+    std::vector<Box> S{Box{0, 0, ncx - 1, ncv - 1}};
+    for (const Box& B : bx) {
+        const Box P{B.xlo / R, B.vlo / R, B.xhi / R, B.vhi / R};
+        const Box ext{P.xlo, 0, P.xhi, ncv - 1};
+        std::vector<Box> S2;
+        for (const Box& s : S) {
+            const Box in = intersect(s, ext);
+            if (in.empty()) { S2.push_back(s); continue; }
+            if (s.xlo < in.xlo) S2.push_back(Box{s.xlo, s.vlo, in.xlo - 1, s.vhi});
+            if (in.xhi < s.xhi) S2.push_back(Box{in.xhi + 1, s.vlo, s.xhi, s.vhi});
+            const Box below{in.xlo, in.vlo, in.xhi, std::min(in.vhi, P.vlo - 1)};
+            const Box above{in.xlo, std::max(in.vlo, P.vhi + 1), in.xhi, in.vhi};
+            if (!below.empty()) S2.push_back(below);
+            if (!above.empty()) S2.push_back(above);
+        }
+        S.swap(S2);
+    }
+    M->nsub = (int)S.size();
+    std::vector<long long> task_off;
+    std::vector<int> task_len, sub_base, fine_base;
+    for (const Box& s : S) {
+        sub_base.push_back((int)task_off.size());
+        for (int i = s.xlo - 2; i <= s.xhi + 2; ++i) {
+            task_off.push_back((long long)(((i % ncx) + ncx) % ncx) * ncv + s.vlo);
+            task_len.push_back(s.vhi - s.vlo + 1);
+        }
+    }
+    for (const AmrPatch& P : M->patches) {
+        fine_base.push_back((int)task_off.size());
+        for (int r = 0; r < P.nx; ++r) {
+            task_off.push_back(P.off + (long long)r * P.nv);
+            task_len.push_back(P.nv);
+        }
+    }
+    M->ntasks = (int)task_off.size();
+    const std::vector<double> B = interp_table(R);
+    std::vector<int> rowptr{0}, idx;
+    std::vector<double> w;
+    for (int I = 0; I < M->nfx; ++I) {
+        const int i = I / R, s = I % R;
+        for (size_t q = 0; q < S.size(); ++q) {
+            if (i < S[q].xlo || i > S[q].xhi) continue;
+            for (int a = -2; a <= 2; ++a) {
+                idx.push_back(sub_base[q] + (i + a - (S[q].xlo - 2)));
+                w.push_back(B[s * 5 + a + 2] * M->dvc);
+            }
+        }
+        for (size_t q = 0; q < M->patches.size(); ++q) {
+            const AmrPatch& P = M->patches[q];
+            if (I < P.gx0 || I >= P.gx0 + P.nx) continue;
+            idx.push_back(fine_base[q] + (I - P.gx0));
+            w.push_back(M->dvf);
+        }
+        rowptr.push_back((int)idx.size());
+    }
+
+    // ---- device tables
+    M->w = (M->ncv % 2 == 0 && std::all_of(M->patches.begin(), M->patches.end(),
+                                           [](const AmrPatch& P) { return P.nv % 2 == 0; })) ? 2 : 1;
+    M->nt = 64;
+    M->tx = 8;
+    build_tiles(*M);
+    VP_HIP(upload(&M->d_patches, M->patches));
+    VP_HIP(upload(&M->d_tiles, M->tiles));
+    VP_HIP(upload(&M->d_faces, M->faces));
+    VP_HIP(upload(&M->d_B, B));
+    VP_HIP(upload(&M->d_task_off, task_off));
+    VP_HIP(upload(&M->d_task_len, task_len));
+    VP_HIP(upload(&M->d_rowptr, rowptr));
+    VP_HIP(upload(&M->d_idx, idx));
+    VP_HIP(upload(&M->d_w, w));
+    VP_HIP(upload(&M->d_corr_ptr, corr_ptr));
+    VP_HIP(upload(&M->d_corr_face, corr_face));
+    VP_HIP(upload(&M->d_corr_cell, corr_cell));
+    VP_HIP(upload(&M->d_cov_cell, cov_cell));
+    VP_HIP(upload(&M->d_cov_fine, cov_fine));
+    VP_HIP(upload(&M->d_cov_nv, cov_nv));
+
+    // ---- workspace: acc, two predictors, accumulated face fluxes, reduction slots, n, E
+    const size_t sb = align256(M->total * sizeof(double));
+    size_t o = 0;
+    p->ws_acc = o; o += sb;
+    p->ws_fsa = o; o += sb;
+    p->ws_fsb = o; o += sb;
+    M->ws_cf = o; o += align256(std::max<size_t>(M->faces.size(), 1) * sizeof(double));
+    M->ws_ff = o; o += align256(std::max<size_t>(M->fflux, 1) * sizeof(double));
+    M->ws_slots = o; o += align256(std::max(M->ntasks, 1) * sizeof(double));
+    M->ws_n = o; o += align256((size_t)M->nfx * sizeof(double));
+    M->ws_E = o; o += align256((size_t)M->nfx * sizeof(double));
+    p->ws_total = o;
+    p->state_elems = M->total;
+    return VP_OK;
+}
+
+void amr_destroy(vp_plan* p)
+{
+    AmrPlan* M = p->amr;
+    if (!M) return;
+    void* ptrs[] = {M->d_patches, M->d_tiles, M->d_faces, M->d_B, M->d_task_off, M->d_task_len, M->d_rowptr,
+                    M->d_idx, M->d_w, M->d_corr_ptr, M->d_corr_face, M->d_corr_cell, M->d_cov_cell,
+                    M->d_cov_fine, M->d_cov_nv};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete M;
+    p->amr = nullptr;
+}
+
+vp_status amr_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream)
+{
+    AmrArgs A = stage_args(p, f, nullptr, nullptr, k, a, 0.0, 0.0, 0.0, 0, nullptr);
+    VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage_all(p, kRhs, A, stream); }));
+    return VP_OK;
+}
+
+vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream)
+{
+    const AmrPlan& M = *p->amr;
+    double* slots = reinterpret_cast<double*>(wsp(work, M.ws_slots));
+    VP_HIP(timed(p, kTMoment, stream, [&] {
+        hipError_t e = launch_amr_rowsum(static_cast<const double*>(f), M.d_task_off, M.d_task_len, M.ntasks,
+                                         slots, stream);
+        if (e != hipSuccess) return e;
+        return launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.nfx, n, stream);
+    }));
+    return VP_OK;
+}
+
+vp_status amr_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream)
+{
+    const AmrPlan& M = *p->amr;
+    VP_HIP(timed(p, kTOther, stream, [&] { return launch_amr_inject(E, M.ncx, M.R, p->pb.qm, a, stream); }));
+    return VP_OK;
+}
+
+vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
+{
+    const AmrPlan& M = *p->amr;
+    void* acc = wsp(work, p->ws_acc);
+    void* s2 = wsp(work, p->ws_fsa);
+    void* s3 = wsp(work, p->ws_fsb);
+    void* s4 = s2;
+    const void* in[4] = {f, s2, s3, s4};
+    void* out[4] = {s2, s3, s4, f};
+    const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double cnext[3] = {0.5 * dt, 0.5 * dt, dt};
+    for (int s = 0; s < 4; ++s) {
+        const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
+        AmrArgs A = stage_args(p, in[s], f, acc, out[s], a, dt * b[s], s < 3 ? cnext[s] : 0.0, b[s], s == 0, work);
+        VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage_all(p, kind, A, stream); }));
+        if (s < 3)
+            if (vp_status st = constraint(p, static_cast<const double*>(out[s]), a, work, stream)) return st;
+    }
+    AmrSyncArgs S{};
+    S.f = static_cast<double*>(f);
+    S.ncv = M.ncv;
+    S.R = M.R;
+    S.cf_acc = reinterpret_cast<const double*>(wsp(work, M.ws_cf));
+    S.ff_acc = reinterpret_cast<const double*>(wsp(work, M.ws_ff));
+    S.faces = M.d_faces;
+    S.corr_ptr = M.d_corr_ptr;
+    S.corr_face = M.d_corr_face;
+    S.corr_cell = M.d_corr_cell;
+    S.ncorr = M.ncorr;
+    S.cov_cell = M.d_cov_cell;
+    S.cov_fine = M.d_cov_fine;
+    S.cov_nv = M.d_cov_nv;
+    S.ncov = M.ncov;
+    S.dtx = dt / M.dxc;
+    S.dtv = dt / M.dvc;
+    VP_HIP(timed(p, kTSync, stream, [&] { return launch_amr_sync(S, stream); }));
+    return constraint(p, static_cast<const double*>(f), a, work, stream);
+}
+
+}  // namespace vp

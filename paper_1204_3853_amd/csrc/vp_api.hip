@@ -137,6 +137,64 @@ vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, vo
     return VP_OK;
 }
 
+// two-level plan: geometry, box calculus and tables (vp_amr.hip), then the
+// Poisson tables of the finest configuration mesh
+vp_status create_two_level(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out)
+{
+    vp_plan* p = new (std::nothrow) vp_plan();
+    if (!p) return fail(VP_ENOMEM, "out of host memory");
+    p->pb = *pb;
+    p->ndim = pb->ndim;
+    p->dtype = pb->dtype;
+    p->nlev = 2;
+    p->esize = pb->dtype == VP_F64 ? 8 : 4;
+    for (int l = 0; l < VP_MAX_LEVELS; ++l)
+        for (int d = 0; d < 2; ++d) p->pb.veq[l][d] = nullptr;
+    vp_status st = amr_create(p, pb, boxes, nbox);
+    if (st != VP_OK) {
+        amr_destroy(p);
+        delete p;
+        return st;
+    }
+    const AmrPlan& M = *p->amr;
+    // the configuration-space calls act on the finest configuration mesh
+    p->nx = M.nfx;
+    p->nv = M.nfv;
+    p->dx = M.dxf;
+    p->dv = M.dvf;
+    p->v_lo = M.v_lo;
+    std::vector<double> g = tridiag_green(p->nx, kGreenTaps);
+    p->gk = kGreenTaps;
+    hipError_t e = hipMalloc(&p->d_green, g.size() * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_green, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = poisson1d_prepare();
+    if (e != hipSuccess) {
+        st = hip_fail(e, "vp_plan_create: Poisson tables");
+        if (p->d_green) (void)hipFree(p->d_green);
+        amr_destroy(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return VP_OK;
+}
+
+// two-level tile shapes: threads x cells per thread x rows per tile
+std::vector<StageShape> amr_shape_table()
+{
+    std::vector<StageShape> v;
+    for (int w : {2, 1})
+        for (int nt : {64, 128})
+            for (int tx : {4, 8, 16, 32}) v.push_back(StageShape{nt, w, tx});
+    return v;
+}
+
+std::vector<StageShape> plan_shapes(const vp_plan* p)
+{
+    return p->amr ? amr_shape_table() : shape_table(p->dtype);
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -177,8 +235,9 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
         if (!(pb->v_hi[d] > pb->v_lo[d])) return fail(VP_EINVAL, "v_hi must exceed v_lo");
         if (!pb->veq[0][d]) return fail(VP_EINVAL, "veq[0][d] (equilibrium with ghosts) is required");
     }
-    if (pb->ndim != 1 || pb->n_levels != 1 || nbox != 0)
-        return fail(VP_ENOTSUP, "this call sequence supports the single-level 1D+1V problem");
+    if (pb->n_levels == 2) return create_two_level(pb, boxes, nbox, out);
+    if (nbox != 0) return fail(VP_EINVAL, "a single-level plan takes no boxes");
+    if (pb->ndim != 1) return fail(VP_ENOTSUP, "this call sequence supports the 1D+1V problem");
 
     vp_plan* p = new (std::nothrow) vp_plan();
     if (!p) return fail(VP_ENOMEM, "out of host memory");
@@ -241,13 +300,13 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
 
 int32_t vp_tile_shape_count(const vp_plan* p)
 {
-    return p ? (int32_t)shape_table(p->dtype).size() : 0;
+    return p ? (int32_t)plan_shapes(p).size() : 0;
 }
 
 vp_status vp_tile_shape_get(const vp_plan* p, int32_t index, int32_t* threads, int32_t* cells, int32_t* rows)
 {
     if (vp_status s = check_plan(p)) return s;
-    const auto tab = shape_table(p->dtype);
+    const auto tab = plan_shapes(p);
     if (index < 0 || index >= (int32_t)tab.size()) return fail(VP_EINVAL, "vp_tile_shape_get: index out of range");
     if (threads) *threads = tab[index].nt;
     if (cells) *cells = tab[index].w;
@@ -258,9 +317,62 @@ vp_status vp_tile_shape_get(const vp_plan* p, int32_t index, int32_t* threads, i
 vp_status vp_tile_shape_set(vp_plan* p, int32_t index)
 {
     if (vp_status s = check_plan(p)) return s;
-    const auto tab = shape_table(p->dtype);
+    const auto tab = plan_shapes(p);
     if (index < 0 || index >= (int32_t)tab.size()) return fail(VP_EINVAL, "vp_tile_shape_set: index out of range");
+    if (p->amr) {
+        if (vp_status s = amr_set_shape(p, tab[index].nt, tab[index].w, tab[index].tx)) return s;
+    }
     p->shape = tab[index];
+    return VP_OK;
+}
+
+vp_status vp_launch_mode_set(vp_plan* p, int32_t mode)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (mode != VP_LAUNCH_PERSISTENT && mode != VP_LAUNCH_PER_PATCH)
+        return fail(VP_EINVAL, "vp_launch_mode_set: unknown mode");
+    if (p->amr) p->amr->mode = mode;
+    return VP_OK;
+}
+
+vp_status vp_autotune(vp_plan* p, void* f, double* a, double dt, int32_t reps, void* work, hipStream_t stream,
+                      int32_t* best_index, float* best_ms)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!f || !a || !work) return fail(VP_EINVAL, "vp_autotune: NULL pointer");
+    if (reps < 1 || !std::isfinite(dt)) return fail(VP_EINVAL, "vp_autotune: reps must be positive and dt finite");
+    const auto tab = plan_shapes(p);
+    const StageShape keep = p->shape;
+    const bool timing = p->timing.enabled;
+    p->timing.enabled = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    VP_HIP(hipEventCreate(&e0));
+    VP_HIP(hipEventCreate(&e1));
+    int best = -1;
+    float best_t = 0.f;
+    vp_status st = VP_OK;
+    for (int k = 0; k < (int)tab.size() && st == VP_OK; ++k) {
+        if (vp_tile_shape_set(p, k) != VP_OK) continue;          // shape not valid for this plan
+        st = vp_rk4_step(p, f, a, dt, work, stream);             // warm-up
+        if (st != VP_OK) break;
+        hipError_t e = hipEventRecord(e0, stream);
+        for (int r = 0; r < reps && st == VP_OK && e == hipSuccess; ++r) st = vp_rk4_step(p, f, a, dt, work, stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) st = hip_fail(e, "vp_autotune: timing");
+        if (st == VP_OK && (best < 0 || t < best_t)) { best = k; best_t = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->timing.enabled = timing;
+    if (st != VP_OK) return st;
+    if (best < 0) return fail(VP_ENOTSUP, "vp_autotune: no tile shape is valid for this plan");
+    if (vp_status s = vp_tile_shape_set(p, best)) return s;
+    (void)keep;
+    if (best_index) *best_index = best;
+    if (best_ms) *best_ms = best_t / reps;
     return VP_OK;
 }
 
@@ -301,19 +413,32 @@ vp_status vp_plan_destroy(vp_plan* p)
     for (auto& e : p->timing.ev)
         if (e) (void)hipEventDestroy(e);
     if (p->d_green) (void)hipFree(p->d_green);
+    amr_destroy(p);
     delete p;
     return VP_OK;
 }
 
 size_t vp_state_elems(const vp_plan* p) { return p ? p->state_elems : 0; }
-int64_t vp_patch_offset(const vp_plan* p, int32_t patch) { return (p && patch == -1) ? 0 : -1; }
+
+int64_t vp_patch_offset(const vp_plan* p, int32_t patch)
+{
+    if (!p) return -1;
+    if (patch == -1) return 0;
+    if (p->amr && patch >= 0 && patch < (int32_t)p->amr->patches.size()) return p->amr->patches[patch].off;
+    return -1;
+}
+
 size_t vp_config_elems(const vp_plan* p) { return p ? (size_t)p->nx : 0; }
-size_t vp_field_elems(const vp_plan* p) { return p ? (size_t)p->nx : 0; }
+size_t vp_field_elems(const vp_plan* p)
+{
+    if (!p) return 0;
+    return p->amr ? (size_t)(p->amr->ncx + p->amr->nfx) : (size_t)p->nx;
+}
 size_t vp_workspace_bytes(const vp_plan* p) { return p ? p->ws_total : 0; }
 
 size_t vp_stage_elems(const vp_plan* p)
 {
-    if (!p) return 0;
+    if (!p || p->amr) return 0;
     const size_t a_bytes = 4 * (size_t)p->nx * sizeof(double);
     return 3 * p->state_elems + (a_bytes + p->esize - 1) / p->esize;
 }
@@ -323,6 +448,7 @@ vp_status vp_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipS
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a || !k) return fail(VP_EINVAL, "vp_rhs: NULL pointer");
     if (f == k) return fail(VP_EINVAL, "vp_rhs: k must not alias f");
+    if (p->amr) return amr_rhs(p, f, a, k, stream);
     const StageShape sh = pick_shape(p, {f, k});
     Stage1DArgs A = base_args(p, sh);
     A.fs = f;
@@ -334,9 +460,12 @@ vp_status vp_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipS
 
 vp_status vp_reduce_moment(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream)
 {
-    (void)work;
     if (vp_status s = check_plan(p)) return s;
     if (!f || !n) return fail(VP_EINVAL, "vp_reduce_moment: NULL pointer");
+    if (p->amr) {
+        if (!work) return fail(VP_EINVAL, "vp_reduce_moment: a two-level plan needs the workspace");
+        return amr_reduce(p, f, n, work, stream);
+    }
     VP_HIP(timed(p, kTMoment, stream, [&] { return launch_moment_rows(p->dtype, f, p->nx, p->nv, p->dv, n, stream); }));
     return VP_OK;
 }
@@ -358,6 +487,7 @@ vp_status vp_inject_field(const vp_plan* p, const double* E, double* a, hipStrea
 {
     if (vp_status s = check_plan(p)) return s;
     if (!E || !a) return fail(VP_EINVAL, "vp_inject_field: NULL pointer");
+    if (p->amr) return amr_inject(p, E, a, stream);
     VP_HIP(timed(p, kTOther, stream, [&] { return launch_scale(E, p->pb.qm, a, p->nx, stream); }));
     return VP_OK;
 }
@@ -367,6 +497,7 @@ vp_status vp_rk4_step(const vp_plan* p, void* f, double* a, double dt, void* wor
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a || !work) return fail(VP_EINVAL, "vp_rk4_step: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step: dt is not finite");
+    if (p->amr) return amr_rk4(p, f, a, dt, work, stream);
     return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
 }
 
@@ -376,6 +507,7 @@ vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, vo
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a || !work || !stages) return fail(VP_EINVAL, "vp_rk4_step_record: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_record: dt is not finite");
+    if (p->amr) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level plans only");
     double* st_a = reinterpret_cast<double*>(static_cast<char*>(stages) + 3 * p->state_elems * p->esize);
     if (reinterpret_cast<uintptr_t>(st_a) % 8) return fail(VP_EINVAL, "stage record misaligned");
     return rk4_1d(p, f, a, dt, work, stages, st_a, stream);
@@ -386,6 +518,7 @@ vp_status vp_field_adjoint(const vp_plan* p, const double* abar, void* fbar, voi
     if (vp_status s = check_plan(p)) return s;
     if (!abar || !fbar || !work) return fail(VP_EINVAL, "vp_field_adjoint: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_field_adjoint: FP64 only");
+    if (p->amr) return fail(VP_ENOTSUP, "vp_field_adjoint: single-level plans only");
     double* cfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
     double* ab = cfg;
     double* z = cfg + p->nx;
@@ -405,7 +538,7 @@ vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, 
     if (vp_status s = check_plan(p)) return s;
     if (!f_n || !a_n || !lam_np1 || !lam_n || !work) return fail(VP_EINVAL, "vp_adjoint_step: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is FP64 only");
-    if (p->nlev != 1 || p->ndim != 1) return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
+    if (p->amr || p->nlev != 1 || p->ndim != 1) return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_adjoint_step: dt is not finite");
     const size_t N = p->state_elems;
     const int nx = p->nx, nv = p->nv;

@@ -75,6 +75,48 @@ struct Adjoint1DArgs {
     double c1, c2;          // dt b_s, dt alpha_{s+1}
 };
 
+// ----------------------------------------------------------------- two levels
+
+struct AmrPatch {              // one level-1 patch
+    long long off;             // element offset of its cells in the state
+    long long foff;            // offset of its boundary-flux block: [x lo: nv][x hi: nv][v lo: nx][v hi: nx]
+    int gx0, gv0;              // level-1 global index of its cell (0, 0)
+    int nx, nv;                // cells
+};
+
+enum AmrTileKind : int { kTileCoarse = 0, kTileFine = 1, kTileFaces = 2 };
+struct AmrTile {
+    int kind;
+    int p;                     // fine: patch; faces: first face
+    int a;                     // coarse: tile index; fine: row segment; faces: face count
+    int b;                     // fine: velocity strip
+};
+
+struct AmrFace {               // coarse face on a coarse-fine interface
+    int i, j;                  // coarse cell on the low side ((i, j) | (i+1, j) or (i, j) | (i, j+1))
+    int dir;                   // 0: x face, 1: v face
+    int fine;                  // index in the fine boundary-flux buffer of the first of R fine faces
+};
+
+struct AmrArgs {
+    Stage1DArgs coarse;        // the coarse level as a single-level problem (state base pointers)
+    const AmrPatch* patches;
+    const AmrTile* tiles;
+    int ntiles;
+    int nfx, nfv;              // level-1 index space
+    int R, lr;                 // refinement ratio (same in x and v) and log2 R
+    int tx;                    // rows per fine tile
+    double dxfi, dvfi, dvf24, dvf, v_lo;
+    double vgf[4];             // level-1 velocity ghosts j = -2, -1, nfv, nfv+1
+    const double* a_f;         // level-1 acceleration (nfx)
+    const double* B;           // sub-cell interpolation weights b_j(s) at B[s * 5 + j + 2] (device)
+    const AmrFace* faces;
+    double* cf_acc;            // accumulated coarse fluxes on the listed faces
+    double* ff_acc;            // accumulated fine boundary fluxes
+    double c_flux;             // b_s (0: no accumulation)
+    int first;                 // first stage: store instead of add
+};
+
 // Launchers (defined in vp_kernels_1d.hip).
 hipError_t launch_stage1d(int dtype, const StageShape& sh, int kind, const Stage1DArgs& args,
                           hipStream_t stream);
@@ -96,6 +138,34 @@ hipError_t launch_adjoint_final(const double* mu, const double* g, const double*
 hipError_t launch_scale(const double* x, double s, double* y, int n, hipStream_t stream);
 hipError_t poisson1d_prepare();
 
+// two-level launchers (vp_kernels_amr.hip)
+hipError_t launch_amr_stage(int w, int nt, int kind, const AmrArgs& a, int t_begin, int t_end, int grid,
+                            hipStream_t stream);
+hipError_t launch_amr_rowsum(const double* f, const long long* task_off, const int* task_len, int ntasks,
+                             double* slots, hipStream_t stream);
+hipError_t launch_amr_reduce_finalize(const double* slots, const int* rowptr, const int* idx, const double* w,
+                                      int nfx, double* n, hipStream_t stream);
+hipError_t launch_amr_inject(const double* E, int ncx, int R, double qm, double* a, hipStream_t stream);
+// end of step: coarse cells next to coarse-fine faces take the fine
+// accumulated fluxes; covered coarse cells take the mean of their fine cells
+struct AmrSyncArgs {
+    double* f;                 // state (coarse level at offset 0)
+    int ncv, R;
+    const double* cf_acc;
+    const double* ff_acc;
+    const AmrFace* faces;
+    const int* corr_ptr;       // CSR over corrected coarse cells
+    const int* corr_face;      // face index, negated-minus-one when the cell is on the high side
+    const int* corr_cell;      // coarse cell index of each CSR row
+    int ncorr;
+    const int* cov_cell;       // covered coarse cells
+    const long long* cov_fine; // element offset of the first fine cell under each covered cell
+    const int* cov_nv;         // row stride (patch width) of that fine block
+    int ncov;
+    double dtx, dtv;           // dt / dx_coarse, dt / dv_coarse
+};
+hipError_t launch_amr_sync(const AmrSyncArgs& a, hipStream_t stream);
+
 }  // namespace vp
 
 // ----------------------------------------------------------------- timing
@@ -108,6 +178,47 @@ struct Timing {
     int used = 0;
     static constexpr int kMaxRecords = 8192;
 };
+
+// ----------------------------------------------------------------- two-level plan
+
+namespace vp {
+struct AmrPlan {
+    int ncx = 0, ncv = 0, R = 4, lr = 2, nfx = 0, nfv = 0;
+    double dxc = 0, dvc = 0, dxf = 0, dvf = 0, v_lo = 0;
+    double vgc[4] = {0, 0, 0, 0}, vgf[4] = {0, 0, 0, 0};
+    std::vector<AmrPatch> patches;
+    std::vector<AmrFace> faces;
+    size_t total = 0, fflux = 0;
+    // tile shape (threads, cells per thread, rows per tile) and launch mode
+    int nt = 64, w = 2, tx = 8;
+    int mode = 0;                                    // 0 persistent, 1 one launch per patch
+    int ncoarse_tiles = 0, ntiles = 0, nstrip_c = 1;
+    std::vector<AmrTile> tiles;
+    std::vector<int> patch_tile_begin;               // per patch, plus the face chunks at the end
+    int face_tile_begin = 0;
+    // device tables
+    AmrPatch* d_patches = nullptr;
+    AmrTile* d_tiles = nullptr;
+    AmrFace* d_faces = nullptr;
+    double* d_B = nullptr;
+    int ntasks = 0;
+    long long* d_task_off = nullptr;
+    int* d_task_len = nullptr;
+    int* d_rowptr = nullptr;
+    int* d_idx = nullptr;
+    double* d_w = nullptr;
+    int ncorr = 0, ncov = 0;
+    int* d_corr_ptr = nullptr;
+    int* d_corr_face = nullptr;
+    int* d_corr_cell = nullptr;
+    int* d_cov_cell = nullptr;
+    long long* d_cov_fine = nullptr;
+    int* d_cov_nv = nullptr;
+    int nsub = 0;                                    // sub-patches of the coarse level (Alg. subdiv)
+    // workspace offsets
+    size_t ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0;
+};
+}  // namespace vp
 
 // ----------------------------------------------------------------- the plan
 
@@ -136,7 +247,19 @@ struct vp_plan {
     size_t state_elems = 0;
 
     mutable Timing timing;
+    vp::AmrPlan* amr = nullptr;
 };
+
+namespace vp {
+// two-level host sequences (vp_amr.hip)
+vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);
+void amr_destroy(vp_plan* p);
+vp_status amr_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream);
+vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream);
+vp_status amr_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
+vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
+vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx);
+}  // namespace vp
 
 namespace vp {
 // Runs `launch` (returning hipError_t) bracketed by timing events of class cls.

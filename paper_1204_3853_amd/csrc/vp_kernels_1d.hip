@@ -12,301 +12,18 @@
 #include <hip/hip_runtime.h>
 
 #include "vp_internal.hpp"
+#include "vp_stage_tile.hpp"
 
 namespace vp {
 
 namespace {
 
-// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so that tiles sharing halo rows and columns
-// run under the same L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, l = b >> 3;
-    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
+using namespace dev;
 
-__device__ __forceinline__ int wrapi(int i, int n)
-{
-    if (i >= 0 && i < n) return i;
-    int r = i % n;
-    return r < 0 ? r + n : r;
-}
-
-template <typename T>
-__device__ __forceinline__ T ghost_val(const T* __restrict__ row, int j, int nv, const double* vg)
-{
-    if (j >= 0 && j < nv) return row[j];
-    if (j == -2) return (T)vg[0];
-    if (j == -1) return (T)vg[1];
-    if (j == nv) return (T)vg[2];
-    if (j == nv + 1) return (T)vg[3];
-    return (T)0;
-}
-
-template <typename T, int W> struct VecIO;
-template <> struct VecIO<double, 1> {
-    static __device__ __forceinline__ void ld(const double* p, double* o) { o[0] = p[0]; }
-    static __device__ __forceinline__ void st(double* p, const double* o) { p[0] = o[0]; }
-};
-template <> struct VecIO<double, 2> {
-    static __device__ __forceinline__ void ld(const double* p, double* o)
-    {
-        double2 v = *reinterpret_cast<const double2*>(p);
-        o[0] = v.x; o[1] = v.y;
-    }
-    static __device__ __forceinline__ void st(double* p, const double* o)
-    {
-        *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
-    }
-};
-template <> struct VecIO<float, 1> {
-    static __device__ __forceinline__ void ld(const float* p, float* o) { o[0] = p[0]; }
-    static __device__ __forceinline__ void st(float* p, const float* o) { p[0] = o[0]; }
-};
-template <> struct VecIO<float, 4> {
-    static __device__ __forceinline__ void ld(const float* p, float* o)
-    {
-        float4 v = *reinterpret_cast<const float4*>(p);
-        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-    }
-    static __device__ __forceinline__ void st(float* p, const float* o)
-    {
-        *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
-    }
-};
-
-__device__ __forceinline__ double wave_sum(double s)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
-    return s;
-}
-
-template <typename T>
-__device__ __forceinline__ T face4(T um1, T u0, T u1, T u2)
-{
-    // ideal-weight (unlimited) face average of cell averages
-    return (T(7) * (u0 + u1) - (um1 + u2)) * T(1.0 / 12.0);
-}
-
-// Stage kernel.  A block owns a strip of TV = NT*W velocity cells and a
-// segment of configuration rows [i0, i1).  The march proceeds in batches
-// of RB rows: all loads of a batch (RB new rows of the stage state plus the
-// f^n / accumulator rows being updated) are issued together, so each wave
-// keeps RB rows of traffic in flight; the rows go through an 8-slot LDS
-// ring that holds the stencil's x-neighbourhood rows i-2 .. i+RB+1.
 template <typename T, int W, int NT, int KIND>
 __global__ __launch_bounds__(NT) void k_stage1d(Stage1DArgs A)
 {
-    constexpr int RB = 4;                                    // rows per batch
-    constexpr int NSLOT = 8;                                 // ring rows (>= RB + 4)
-    constexpr int TV = NT * W;
-    constexpr int LPAD = (W > 2) ? W : 2;                    // keeps own data W-aligned in LDS
-    constexpr int RW = ((LPAD + TV + 2 + 3) / 4) * 4;
-    constexpr int NWAVE = NT / 64;
-    __shared__ __attribute__((aligned(16))) T ring[NSLOT][RW];
-    __shared__ double mom[NWAVE][kMaxTx];
-    __shared__ double aseg[kMaxTx + RB + 2];   // a_{i0-1} .. a_{i1}, then padding
-
-    const T* __restrict__ fs = static_cast<const T*>(A.fs);
-    const T* __restrict__ fn = static_cast<const T*>(A.fn);
-    T* __restrict__ acc = static_cast<T*>(A.acc);
-    T* __restrict__ fout = static_cast<T*>(A.fout);
-    const double* __restrict__ av = A.a;
-
-    const int nx = A.nx, nv = A.nv;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int strip = tile % A.nstrip;
-    const int seg = tile / A.nstrip;
-    const int j0 = strip * TV;
-    const int i0 = seg * A.tx;
-    const int i1 = min(i0 + A.tx, nx);
-    const int t = threadIdx.x;
-    const int jt = j0 + t * W;
-    const bool own_in = jt < nv;          // nv % W == 0 for W > 1, so the whole vector is in range
-    const int jld = own_in ? jt : 0;      // out-of-range threads load a valid cell and discard it
-    const int lane = t & 63, wave = t >> 6;
-    const int c0 = LPAD + t * W;          // LDS column of the first own cell
-
-    // values of own cells that lie outside [0, nv): velocity ghosts or unused
-    T oconst[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        const int j = jt + w;
-        oconst[w] = (j == nv) ? (T)A.vg[2] : (j == nv + 1) ? (T)A.vg[3] : T(0);
-    }
-    // threads 0..3 also stage one strip-halo cell: j0-2, j0-1, j0+TV, j0+TV+1
-    const bool has_halo = t < 4;
-    const int hj = t < 2 ? j0 - 2 + t : j0 + TV + (t - 2);
-    const int hcol = t < 2 ? LPAD - 2 + t : LPAD + TV + (t - 2);
-    const bool halo_in = has_halo && hj >= 0 && hj < nv;
-    const int hld = halo_in ? hj : jld;
-    const T hconst = (hj == -2) ? (T)A.vg[0] : (hj == -1) ? (T)A.vg[1] : (hj == nv) ? (T)A.vg[2]
-                   : (hj == nv + 1) ? (T)A.vg[3] : T(0);
-
-    auto slot_of = [&](int r) { return (r - i0 + 2) & (NSLOT - 1); };   // r >= i0 - 2
-    auto load_row = [&](int r, T* v, T& h) {
-        const T* row = fs + (size_t)wrapi(r, nx) * nv;
-        VecIO<T, W>::ld(row + jld, v);
-        h = row[hld];
-    };
-    auto store_row = [&](int r, const T* v, T h) {
-        T* dst = &ring[slot_of(r)][0];
-#pragma unroll
-        for (int w = 0; w < W; ++w) dst[c0 + w] = own_in ? v[w] : oconst[w];
-        if (has_halo) dst[hcol] = halo_in ? h : hconst;
-    };
-    auto fx_cols = [&](int r, T* Fx) {      // x-face r + 1/2 at columns jt-1 .. jt+W
-        const int sm1 = slot_of(r - 1), s0 = slot_of(r), s1 = slot_of(r + 1), s2 = slot_of(r + 2);
-#pragma unroll
-        for (int q = 0; q < W + 2; ++q) {
-            const int c = c0 - 1 + q;
-            Fx[q] = face4<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c]);
-        }
-    };
-    auto fv_faces = [&](int r, T* Fv) {     // v-faces jt-1/2 .. jt+W-1/2 of row r
-        const int sl = slot_of(r);
-        T u[W + 4];
-#pragma unroll
-        for (int q = 0; q < W + 4; ++q) u[q] = ring[sl][c0 - 2 + q];
-#pragma unroll
-        for (int m = 0; m <= W; ++m) Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
-    };
-
-    T vb[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) vb[w] = (T)(A.v_lo + ((double)(jt + w) + 0.5) * A.dv);
-    const T dxi = (T)A.dxi, dvi = (T)A.dvi, dv24 = (T)A.dv24;
-    const T cacc = (T)A.c_acc, cnext = (T)A.c_next;
-
-    // ---- prologue: rows i0-2 .. i0+1
-    {
-        T v[4][W], h[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) load_row(i0 - 2 + q, v[q], h[q]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) store_row(i0 - 2 + q, v[q], h[q]);
-    }
-    for (int q = t; q < i1 - i0 + 2; q += NT) aseg[q] = av[wrapi(i0 - 1 + q, nx)];
-    for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
-    __syncthreads();
-
-    T gx_old[W];
-    {
-        T Fx[W + 2];
-        fx_cols(i0 - 1, Fx);
-#pragma unroll
-        for (int w = 0; w < W; ++w) gx_old[w] = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
-    }
-    T fvA[W + 1], fvB[W + 1];
-    fv_faces(i0 - 1, fvA);
-    fv_faces(i0, fvB);
-
-#pragma unroll 1
-    for (int ib = i0; ib < i1; ib += RB) {
-        // issue every load of the batch; indices past the segment are clamped
-        // so that all loads and their uses are unconditional
-        T v[RB][W], h[RB], fnv[RB][W], accv[RB][W];
-#pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            load_row(min(ib + 2 + q, i1 + 1), v[q], h[q]);      // new stage-state row
-            const size_t off = (size_t)min(ib + q, i1 - 1) * nv + jld;
-            if (KIND == kStage23) VecIO<T, W>::ld(fn + off, fnv[q]);
-            if (KIND == kStage23 || KIND == kStage4) VecIO<T, W>::ld(acc + off, accv[q]);
-        }
-        __syncthreads();                              // previous batch done reading its ring rows
-#pragma unroll
-        for (int q = 0; q < RB; ++q) store_row(ib + 2 + q, v[q], h[q]);
-        __syncthreads();
-
-        // compute the batch (rows past the segment are computed and dropped);
-        // results stay in registers and are stored together
-        T o1[RB][W], o2[RB][W];
-#pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            const int i = ib + q;
-            const int qa = i - i0;
-            const T a_m1 = (T)aseg[qa], a_0 = (T)aseg[qa + 1], a_p1 = (T)aseg[qa + 2];
-            T Fx[W + 2];
-            fx_cols(i, Fx);
-            T fvC[W + 1];
-            fv_faces(i + 1, fvC);
-            const T da48 = (a_p1 - a_m1) * T(1.0 / 48.0);
-            T gv[W + 1];
-#pragma unroll
-            for (int m = 0; m <= W; ++m) gv[m] = a_0 * fvB[m] + da48 * (fvC[m] - fvA[m]);
-            T kk[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const T gx_new = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
-                kk[w] = -(gx_new - gx_old[w]) * dxi - (gv[w + 1] - gv[w]) * dvi;
-                gx_old[w] = gx_new;
-            }
-#pragma unroll
-            for (int m = 0; m <= W; ++m) { fvA[m] = fvB[m]; fvB[m] = fvC[m]; }
-
-            if (KIND == kRhs) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) o1[q][w] = kk[w];
-            } else if (KIND == kStage1) {
-                // f^n is the stage state itself: take it from the ring
-                const int sl = slot_of(i);
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const T f0 = ring[sl][c0 + w];
-                    o1[q][w] = f0 + cacc * kk[w];      // accumulator
-                    o2[q][w] = f0 + cnext * kk[w];     // next predictor
-                }
-            } else if (KIND == kStage23) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    o1[q][w] = accv[q][w] + cacc * kk[w];
-                    o2[q][w] = fnv[q][w] + cnext * kk[w];
-                }
-            } else {  // kStage4: f^{n+1} = acc + dt/6 k4
-#pragma unroll
-                for (int w = 0; w < W; ++w) o2[q][w] = accv[q][w] + cacc * kk[w];
-            }
-            if (KIND != kRhs && A.part) {
-                double sm = 0.0;
-                if (own_in) {
-#pragma unroll
-                    for (int w = 0; w < W; ++w) sm += (double)o2[q][w];
-                }
-                sm = wave_sum(sm);
-                if (lane == 0 && i < i1) mom[wave][qa] = sm;
-            }
-        }
-        if (own_in) {
-#pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                const int i = ib + q;
-                if (i < i1) {
-                    const size_t rowoff = (size_t)i * nv + jt;
-                    if (KIND == kRhs) {
-                        VecIO<T, W>::st(fout + rowoff, o1[q]);
-                    } else if (KIND == kStage4) {
-                        VecIO<T, W>::st(fout + rowoff, o2[q]);
-                    } else {
-                        VecIO<T, W>::st(acc + rowoff, o1[q]);
-                        VecIO<T, W>::st(fout + rowoff, o2[q]);
-                    }
-                }
-            }
-        }
-    }
-
-    if (KIND != kRhs && A.part) {
-        __syncthreads();
-        for (int q = t; q < i1 - i0; q += NT) {
-            double sm = 0.0;
-#pragma unroll
-            for (int wv = 0; wv < NWAVE; ++wv) sm += mom[wv][q];
-            A.part[(size_t)strip * nx + i0 + q] = sm;
-        }
-    }
+    stage_tile_uniform<T, W, NT, KIND>(A, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // n_i = dv * sum_j f_ij, one block per row, fixed summation order.

@@ -77,12 +77,16 @@ SIGNATURES = {
     "vp_tile_shape_get": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "vp_tile_shape_set": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vp_launch_mode_set": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vp_autotune": (ctypes.c_int, [_P, _P, _P, _D, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_float)]),
     "vp_timing_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int32]),
 }
 
 TIMING_CLASSES = ["stage", "field", "moment", "sync", "adjoint", "other"]
+LAUNCH_PERSISTENT, LAUNCH_PER_PATCH = 0, 1
 
 
 def lib():
@@ -200,6 +204,22 @@ class Plan:
     def patch_offset(self, p):
         return lib().vp_patch_offset(self.h, p)
 
+    def set_launch_mode(self, mode):
+        """LAUNCH_PERSISTENT (one launch per stage over the tile table) or
+        LAUNCH_PER_PATCH (one launch per patch)."""
+        _check(lib().vp_launch_mode_set(self.h, int(mode)))
+
+    def autotune(self, f, a, dt, reps=3):
+        """Times every tile shape on `reps` RK4 steps of copies of (f, a),
+        selects the fastest; returns (index, shape, ms per step)."""
+        self._state(f, "f")
+        self._cfg(a, "a", self.field_elems)
+        fw, aw = f.clone(), a.clone()
+        best, ms = ctypes.c_int32(), ctypes.c_float()
+        _check(lib().vp_autotune(self.h, _ptr(fw), _ptr(aw), ctypes.c_double(dt), int(reps), _ptr(self.work),
+                                 _stream(), ctypes.byref(best), ctypes.byref(ms)))
+        return best.value, self.tile_shapes()[best.value], ms.value
+
     # ---------------------------------------------------------------- checks
     def _state(self, t, name):
         if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and t.numel() == self.state_elems):
@@ -211,6 +231,12 @@ class Plan:
         if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
             raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor of {n} elements")
         return t
+
+
+def two_level_spec(ncx, ncv, x_len, v_lo, v_hi, qm, ratio, veq_c, veq_f, x_lo=0.0):
+    """Problem spec of a two-level 1D+1V hierarchy (level 0: ncx x ncv)."""
+    return {"ndim": 1, "n_levels": 2, "cells": [ncx, ncv], "ratio": [ratio, ratio], "x_lo": [x_lo],
+            "x_len": [x_len], "v_lo": [v_lo], "v_hi": [v_hi], "qm": qm, "veq": [[veq_c], [veq_f]]}
 
 
 def _problem_dict(p):

@@ -1,0 +1,248 @@
+"""GPU parity of the two-level (coarse level + level-1 patches) path
+against the FP64 two-level oracle (section 3: sub-cell interpolation of
+ghost cells, Mask/Sub-Patch reduction, injection, synchronous RK4 with
+coarse-fine flux correction and average-down).
+
+Layouts: a small hierarchy (32 x 48 coarse, ratio 4, three patches, one
+touching the periodic x boundary), a ratio-2 hierarchy with an odd coarse
+velocity count (one cell per thread, ragged strips) and patches touching
+both ends of the velocity box, and the 512 x 512
+ratio-4 hierarchy with 40 seeded patches of sides 16..128 inside |v| < 3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import vp_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SMALL = [{"level": 1, "lo": [16, 40], "hi": [39, 63]}, {"level": 1, "lo": [60, 68], "hi": [83, 87]},
+         {"level": 1, "lo": [0, 96], "hi": [15, 111]}]
+RATIO2 = [{"level": 1, "lo": [6, 20], "hi": [17, 33]}, {"level": 1, "lo": [0, 50], "hi": [9, 61]},
+          {"level": 1, "lo": [30, 36], "hi": [45, 43]}, {"level": 1, "lo": [20, 0], "hi": [27, 7]},
+          {"level": 1, "lo": [36, 80], "hi": [41, 89]}]
+
+LAYOUTS = {
+    "small": dict(boxes=SMALL, ncx=32, ncv=48, R=4),
+    "ratio2_odd": dict(boxes=RATIO2, ncx=24, ncv=45, R=2),
+}
+
+
+def rel_tol():
+    return 1e-12
+
+
+@pytest.fixture(scope="module")
+def vp():
+    from paper_1204_3853_amd import vp as V
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return V
+
+
+class Case:
+    def __init__(self, vp, oracle, boxes, ncx, ncv, R, eps=0.05, k=0.5, noise=0.01, seed=0):
+        self.boxes, self.ncx, self.ncv, self.R = boxes, ncx, ncv, R
+        f, veq_c, veq_f = I.amr_landau(boxes, coarse=(ncx, ncv), ratio=R, eps=eps, k=k)
+        rng = np.random.default_rng(seed)
+        f = f * (1.0 + noise * rng.random(f.size))        # non-smooth content on every level
+        self.f0 = f
+        self.spec = vp.two_level_spec(ncx, ncv, 4 * math.pi, -8.0, 8.0, -1.0, R, veq_c, veq_f)
+        self.plan = vp.Plan(self.spec, boxes=boxes)
+        self.o = oracle.OracleAMR(ncx, ncv, 4 * math.pi, -8.0, 8.0, -1.0, R, boxes, veq_c, veq_f)
+        dxf = 4 * math.pi / (ncx * R)
+        self.dt = 0.5 * dxf / 8.0
+
+    def gpu(self, x):
+        return torch.tensor(x, dtype=torch.float64, device="cuda")
+
+
+def cmp(got, want, tol, what):
+    got = got.detach().cpu().numpy() if hasattr(got, "detach") else got
+    scale = max(np.abs(want).max(), 1e-300)
+    err = np.abs(got - want).max()
+    assert err <= tol * scale, f"{what}: max err {err:.3e} (rel {err / scale:.3e}) > {tol:.1e}"
+
+
+@pytest.fixture(scope="module", params=list(LAYOUTS))
+def case(request, vp, oracle):
+    L = LAYOUTS[request.param]
+    return Case(vp, oracle, L["boxes"], L["ncx"], L["ncv"], L["R"])
+
+
+@pytest.fixture(scope="module")
+def full(vp, oracle):
+    boxes = I.amr_boxes(0)
+    return Case(vp, oracle, boxes, 512, 512, 4, eps=0.01, k=0.5, noise=0.0)
+
+
+def test_sizes(case):
+    assert case.plan.state_elems == case.o.size
+    for p in range(len(case.boxes)):
+        assert case.plan.patch_offset(p) == case.o.offset(p)
+    assert case.plan.config_elems == case.ncx * case.R
+    assert case.plan.field_elems == case.ncx + case.ncx * case.R
+
+
+def test_reduce_matches_mask_reduction(vp, case):
+    f = case.gpu(case.f0)
+    n = vp.reduce_moment(case.plan, f)
+    cmp(n, case.o.reduce_mask(case.f0), 1e-13, "moment")
+
+
+def test_constraints(vp, case):
+    f = case.gpu(case.f0)
+    a = vp.field_of(case.plan, f)
+    a_o, _ = case.o.constraints(case.f0)
+    cmp(a, a_o, 1e-11, "a")
+
+
+def test_rhs(vp, case):
+    a_o, _ = case.o.constraints(case.f0)
+    k = vp.rhs(case.plan, case.gpu(case.f0), case.gpu(a_o))
+    cmp(k, case.o.rhs(case.f0, a_o), rel_tol(), "rhs")
+
+
+def test_one_step(vp, case):
+    f = case.gpu(case.f0)
+    a = vp.field_of(case.plan, f)
+    vp.rk4_step(case.plan, f, a, case.dt)
+    want = case.o.step(case.f0, case.dt)
+    cmp(f, want, rel_tol(), "step")
+    a_o, _ = case.o.constraints(want)
+    cmp(a, a_o, 1e-11, "a after step")
+
+
+def test_several_steps(vp, case):
+    f = case.gpu(case.f0)
+    a = vp.field_of(case.plan, f)
+    want = case.f0
+    for s in range(6):
+        vp.rk4_step(case.plan, f, a, case.dt)
+        want = case.o.step(want, case.dt)
+        cmp(f, want, rel_tol() * (s + 1), f"step {s + 1}")
+
+
+def test_every_tile_shape(vp, case):
+    """Every tile shape (and both launch structures) gives the same step."""
+    ref = case.gpu(case.f0)
+    a_ref = vp.field_of(case.plan, ref)
+    vp.rk4_step(case.plan, ref, a_ref, case.dt)
+    shapes = case.plan.tile_shapes()
+    tried = 0
+    for q, shp in enumerate(shapes):
+        try:
+            case.plan.set_tile_shape(q)
+        except vp.VPError:
+            assert shp[1] == 2       # two cells per thread need even widths
+            continue
+        for mode in (vp.LAUNCH_PERSISTENT, vp.LAUNCH_PER_PATCH):
+            case.plan.set_launch_mode(mode)
+            f = case.gpu(case.f0)
+            a = vp.field_of(case.plan, f)
+            vp.rk4_step(case.plan, f, a, case.dt)
+            cmp(f, ref.cpu().numpy(), 1e-14, f"shape {shp} mode {mode}")
+        tried += 1
+    case.plan.set_launch_mode(vp.LAUNCH_PERSISTENT)
+    try:
+        case.plan.set_tile_shape(shapes.index((64, 2, 8)))
+    except vp.VPError:
+        case.plan.set_tile_shape(shapes.index((64, 1, 8)))
+    assert tried >= 8
+
+
+def test_full_config_one_step(vp, full):
+    f = full.gpu(full.f0)
+    a = vp.field_of(full.plan, f)
+    a_o, _ = full.o.constraints(full.f0)
+    cmp(a, a_o, 1e-11, "a")
+    vp.rk4_step(full.plan, f, a, full.dt)
+    cmp(f, full.o.step(full.f0, full.dt), rel_tol(), "step")
+
+
+def test_full_config_persistent_equals_per_patch(vp, full):
+    """Same tiles, same arithmetic: bitwise identical results."""
+    outs = []
+    for mode in (vp.LAUNCH_PERSISTENT, vp.LAUNCH_PER_PATCH):
+        full.plan.set_launch_mode(mode)
+        f = full.gpu(full.f0)
+        a = vp.field_of(full.plan, f)
+        for _ in range(3):
+            vp.rk4_step(full.plan, f, a, full.dt)
+        outs.append((f.clone(), a.clone()))
+    full.plan.set_launch_mode(vp.LAUNCH_PERSISTENT)
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+def composite_mass(case, f):
+    R, ncx, ncv = case.R, case.ncx, case.ncv
+    dxc, dvc = 4 * math.pi / ncx, 16.0 / ncv
+    fc = f[: ncx * ncv].reshape(ncx, ncv)
+    cov = np.zeros((ncx, ncv), bool)
+    m = 0.0
+    for p, b in enumerate(case.boxes):
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        cov[x0 // R:(x1 + 1) // R, v0 // R:(v1 + 1) // R] = True
+        off = case.o.offset(p)
+        m += f[off: off + (x1 - x0 + 1) * (v1 - v0 + 1)].sum() * dxc * dvc / R / R
+    return m + fc[~cov].sum() * dxc * dvc
+
+
+def test_full_config_mass_and_drift(vp, full):
+    """20 steps at the full size: composite mass conserved to round-off and
+    the state stays within the per-step tolerance of the oracle."""
+    f = full.gpu(full.f0)
+    a = vp.field_of(full.plan, f)
+    want = full.f0
+    for _ in range(20):
+        vp.rk4_step(full.plan, f, a, full.dt)
+        want = full.o.step(want, full.dt)
+    got = f.cpu().numpy()
+    cmp(got, want, 20 * rel_tol(), "20 steps")
+    m0, m1 = composite_mass(full, full.f0), composite_mass(full, got)
+    assert abs(m1 - m0) <= 1e-13 * abs(m0)
+
+
+def test_graph_replay_matches_eager(vp, full):
+    """The stage chain captured in a HIP graph (torch.cuda.CUDAGraph) and
+    replayed gives the eager results, replay after replay."""
+    f_e = full.gpu(full.f0)
+    a_e = vp.field_of(full.plan, f_e)
+    f_g, a_g = f_e.clone(), a_e.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        vp.rk4_step(full.plan, f_g, a_g, full.dt)          # warm-up on the side stream
+    torch.cuda.current_stream().wait_stream(s)
+    vp.rk4_step(full.plan, f_e, a_e, full.dt)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        vp.rk4_step(full.plan, f_g, a_g, full.dt)
+    for r in range(3):
+        g.replay()
+        vp.rk4_step(full.plan, f_e, a_e, full.dt)
+        torch.cuda.synchronize()
+        assert torch.equal(f_g, f_e), f"replay {r}"
+        assert torch.equal(a_g, a_e), f"replay {r}"
+
+
+def test_autotune(vp, case):
+    f = case.gpu(case.f0)
+    a = vp.field_of(case.plan, f)
+    q, shape, ms = case.plan.autotune(f, a, case.dt, reps=1)
+    assert 0 <= q < len(case.plan.tile_shapes()) and ms > 0
+    g = f.clone()
+    vp.rk4_step(case.plan, g, a.clone(), case.dt)
+    cmp(g, case.o.step(case.f0, case.dt), rel_tol(), f"step with tuned shape {shape}")
+
+
+def test_adjoint_not_supported(vp, case):
+    f = case.gpu(case.f0)
+    a = vp.field_of(case.plan, f)
+    with pytest.raises(vp.VPError, match="ENOTSUP"):
+        vp.adjoint_step(case.plan, f, a, f.clone(), case.dt)
