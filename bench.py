@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-roofline-pass", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--amr-only", action="store_true", help="run only the two-level section (for profiling)")
     return ap.parse_args()
 
 
@@ -104,17 +106,113 @@ def adjoint_ratio(steps=400, every=20):
             "forward_ms": round(fw * 1e3, 2), "backward_ms": round(bw * 1e3, 2), "ratio": round(bw / fw, 3)}
 
 
+def amr_dt(boxes, a, ncx=512, ncv=512, R=4, x_len=4 * math.pi, v_lo=-8.0, v_hi=8.0, cfl=0.5):
+    """dt at CFL 0.5 with nu = dt (max face |v| / dx + max |a| / dv) on each
+    level, the largest over the levels (the fine level, whose patches lie in
+    |v| < 3, sets it)."""
+    dxc, dvc = x_len / ncx, (v_hi - v_lo) / ncv
+    dxf, dvf = dxc / R, dvc / R
+    nu_c = max(abs(v_lo), abs(v_hi)) / dxc + abs(a[:ncx]).max() / dvc
+    vmax_f = max(max(abs(v_lo + b["lo"][1] * dvf), abs(v_lo + (b["hi"][1] + 1) * dvf)) for b in boxes)
+    nu_f = vmax_f / dxf + abs(a[ncx:]).max() / dvf
+    return cfl / max(nu_c, nu_f)
+
+
+def amr_bench(steps=100, warmup=3):
+    """Two-level Landau hierarchy (coarse 512 x 512, ratio 4, 40 seeded
+    patches of sides 16..128 inside |v| < 3; FP64): RK4 steps with the
+    persistent tile-table launch (autotuned tile shape), the same steps
+    captured in a HIP graph and replayed, and the per-patch launch
+    baseline."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+    boxes = I.amr_boxes(0)
+    f0, veq_c, veq_f = I.amr_landau(boxes)
+    spec = vp.two_level_spec(512, 512, 4 * math.pi, -8.0, 8.0, -1.0, 4, veq_c, veq_f)
+    plan = vp.Plan(spec, boxes=boxes)
+    f = torch.tensor(f0, dtype=torch.float64, device="cuda")
+    a = vp.field_of(plan, f)
+    dt = amr_dt(boxes, a.cpu().numpy())
+    tuned, shape, _ = plan.autotune(f, a, dt, reps=5)
+
+    def timed_steps(n):
+        st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(warmup):
+            vp.rk4_step(plan, f, a, dt)
+        st.record()
+        for _ in range(n):
+            vp.rk4_step(plan, f, a, dt)
+        sp.record()
+        torch.cuda.synchronize()
+        return st.elapsed_time(sp) / n
+
+    plan.set_launch_mode(vp.LAUNCH_PERSISTENT)
+    ms_persistent = timed_steps(steps)
+    plan.timing_enable(True)
+    for _ in range(steps):
+        vp.rk4_step(plan, f, a, dt)
+    torch.cuda.synchronize()
+    tm = plan.timing_read()
+    plan.timing_enable(False)
+    plan.set_launch_mode(vp.LAUNCH_PER_PATCH)
+    ms_per_patch = timed_steps(steps)
+    plan.set_launch_mode(vp.LAUNCH_PERSISTENT)
+
+    # graph-captured step chain
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        vp.rk4_step(plan, f, a, dt)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        vp.rk4_step(plan, f, a, dt)
+    for _ in range(warmup):
+        g.replay()
+    st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.record()
+    for _ in range(steps):
+        g.replay()
+    sp.record()
+    torch.cuda.synchronize()
+    ms_graph = st.elapsed_time(sp) / steps
+
+    cells = plan.state_elems
+    stage_ms, stage_n = tm["stage"]
+    stage_us = stage_ms / stage_n * 1e3
+    bytes_launch = 4 * 8 * cells            # 16 state words per cell per step over 4 stage launches
+    per_launch = {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in tm.items() if v[1]}
+    return {"workload": "Landau 1D+1V two-level: coarse 512x512, ratio 4, 40 patches (seed 0, sides 16..128, "
+                        "|v|<3), FP64, dt=%.4g" % dt,
+            "cells": cells, "fine_cells": cells - 512 * 512,
+            "tuned_shape": {"threads": shape[0], "cells_per_thread": shape[1], "rows": shape[2]},
+            "ms_per_step_persistent": round(ms_persistent, 4),
+            "ms_per_step_graph": round(ms_graph, 4),
+            "ms_per_step_per_patch": round(ms_per_patch, 4),
+            "speedup_persistent_vs_per_patch": round(ms_per_patch / ms_persistent, 3),
+            "speedup_graph_vs_per_patch": round(ms_per_patch / ms_graph, 3),
+            "cell_updates_per_s_graph": cells / (ms_graph * 1e-3),
+            "stage_kernel": {"avg_launch_us": round(stage_us, 2), "algorithmic_bytes_per_launch": bytes_launch,
+                             "achieved_GBs": round(bytes_launch / (stage_us * 1e-6) / 1e9, 1)},
+            "us_per_launch_by_class": per_launch}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described in DESIGN.md, not launched)"}))
+        print(json.dumps({"error": "only one GPU is supported: run with --gpus 1 (the path is written "
+                                   "for one device; sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import torch
 
     import vp_inputs as I
     from paper_1204_3853_amd import vp
 
+    if args.amr_only:
+        print(json.dumps({"amr": amr_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
     n = args.n
     p = I.two_stream(n, n)
@@ -166,6 +264,7 @@ def main():
                     "field_solve_us_per_launch": round(timing["field"][0] / max(timing["field"][1], 1) * 1e3, 2)}
 
     adj = None if args.no_adjoint else adjoint_ratio()
+    amr = None if args.no_amr else amr_bench()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -189,6 +288,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "adjoint": adj,
+        "amr": amr,
     }
     print(json.dumps(out), flush=True)
 
