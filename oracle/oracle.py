@@ -95,11 +95,12 @@ def _declare_extra(L):
         "vpo4_ctx_new": (_V, [_I, _I, _I, _I, _F, _F, _F, _F, _F, _D, _D]),
         "vpo4_ctx_free": (None, [_V]),
         "vpo4_moment": (None, [_V, _D, _D]),
-        "vpo4_poisson": (None, [_V, _D, _D]),
-        "vpo4_field": (None, [_V, _D, _D, _D]),
+        "vpo4_poisson": (_F, [_V, _D, _D]),
+        "vpo4_field": (None, [_V, _D, _D]),
         "vpo4_constraints": (None, [_V, _D, _D, _D, _D]),
-        "vpo4_rhs": (None, [_V, _D, _D, _D, _D]),
+        "vpo4_rhs": (None, [_V, _D, _D, _D]),
         "vpo4_rk4_step": (None, [_V, _D, _D, _F]),
+        "vpo4_rk4_step_fixed_a": (None, [_V, _D, _D, _D, _F]),
     }
     for name, (res, args) in extra.items():
         fn = getattr(L, name, None)
@@ -309,4 +310,69 @@ class OracleAMR:
         f = _f64(f)
         out = np.empty_like(f)
         lib().vpo_amr_rk4_step(self.h, _p(f), _p(out), dt)
+        return out
+
+
+class Oracle4D:
+    """Single-level 2D+2V oracle, f as [x][y][vx][vy]; a and E hold the x
+    component (nx ny values, [x][y]) followed by the y component."""
+
+    def __init__(self, nx, ny, nvx, nvy, x_len, y_len, v_lo, v_hi, qm, veq_x, veq_y):
+        self.nx, self.ny, self.nvx, self.nvy = nx, ny, nvx, nvy
+        self.veq_x, self.veq_y = _f64(veq_x), _f64(veq_y)
+        self.h = lib().vpo4_ctx_new(nx, ny, nvx, nvy, x_len, y_len, v_lo, v_hi, qm, _p(self.veq_x),
+                                    _p(self.veq_y))
+
+    @classmethod
+    def from_problem(cls, p):
+        return cls(p.nx, p.ny, p.nvx, p.nvy, p.x_len, p.y_len, p.v_lo, p.v_hi, p.qm, p.veq_x, p.veq_y)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.vpo4_ctx_free(self.h)
+            self.h = None
+
+    def moment(self, f):
+        f = _f64(f)
+        n = np.empty(self.nx * self.ny)
+        lib().vpo4_moment(self.h, _p(f), _p(n))
+        return n.reshape(self.nx, self.ny)
+
+    def poisson(self, rho):
+        """(phi, relative residual)"""
+        rho = _f64(rho).ravel()
+        phi = np.empty_like(rho)
+        res = lib().vpo4_poisson(self.h, _p(rho), _p(phi))
+        return phi.reshape(self.nx, self.ny), res
+
+    def field(self, phi):
+        phi = _f64(phi).ravel()
+        E = np.empty(2 * phi.size)
+        lib().vpo4_field(self.h, _p(phi), _p(E))
+        return E
+
+    def constraints(self, f):
+        """(a, phi, E): a = (q/m) E, each [Ex; Ey] flattened"""
+        f = _f64(f)
+        n = self.nx * self.ny
+        a, phi, E = np.empty(2 * n), np.empty(n), np.empty(2 * n)
+        lib().vpo4_constraints(self.h, _p(f), _p(a), _p(phi), _p(E))
+        return a, phi, E
+
+    def rhs(self, f, a):
+        f, a = _f64(f), _f64(a)
+        k = np.empty_like(f)
+        lib().vpo4_rhs(self.h, _p(f), _p(a), _p(k))
+        return k
+
+    def step(self, f, dt):
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().vpo4_rk4_step(self.h, _p(f), _p(out), dt)
+        return out
+
+    def step_fixed_a(self, f, a, dt):
+        f, a = _f64(f), _f64(a)
+        out = np.empty_like(f)
+        lib().vpo4_rk4_step_fixed_a(self.h, _p(f), _p(out), _p(a), dt)
         return out

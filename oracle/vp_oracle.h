@@ -55,6 +55,18 @@ void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out);
 void vpo_amr_reduce_mask(void* h, double* f, double* n);
 void vpo_amr_constraints(void* h, double* f, double* a, double* E_out);
 void vpo_amr_rhs(void* h, double* f, double* a, double* k);
+
+/* 2D+2V single level, f[x][y][vx][vy]; a and E hold the x component, then y */
+void* vpo4_ctx_new(int nx, int ny, int nvx, int nvy, double x_len, double y_len, double v_lo, double v_hi,
+                   double qm, const double* veq_x, const double* veq_y);
+void vpo4_ctx_free(void* h);
+void vpo4_moment(void* h, double* f, double* n);
+double vpo4_poisson(void* h, double* rho, double* phi);
+void vpo4_field(void* h, double* phi, double* E);
+void vpo4_constraints(void* h, double* f, double* a, double* phi_out, double* E_out);
+void vpo4_rhs(void* h, double* f, double* a, double* k);
+void vpo4_rk4_step(void* h, double* f_in, double* f_out, double dt);
+void vpo4_rk4_step_fixed_a(void* h, double* f_in, double* f_out, double* a, double dt);
 void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt);
 
 #endif
