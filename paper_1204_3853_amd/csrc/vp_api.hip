@@ -180,6 +180,35 @@ vp_status create_two_level(const vp_problem* pb, const vp_box* boxes, int nbox, 
     return VP_OK;
 }
 
+// single-level 2D+2V plan (vp_4d.hip)
+vp_status create_4d(const vp_problem* pb, vp_plan** out)
+{
+    vp_plan* p = new (std::nothrow) vp_plan();
+    if (!p) return fail(VP_ENOMEM, "out of host memory");
+    p->pb = *pb;
+    p->ndim = 2;
+    p->dtype = pb->dtype;
+    p->nlev = 1;
+    p->esize = 8;
+    for (int l = 0; l < VP_MAX_LEVELS; ++l)
+        for (int d = 0; d < 2; ++d) p->pb.veq[l][d] = nullptr;
+    vp_status st = p4_create(p, pb);
+    if (st != VP_OK) {
+        p4_destroy(p);
+        delete p;
+        return st;
+    }
+    p->nx = pb->cells[0] * pb->cells[1];        // configuration cells
+    *out = p;
+    return VP_OK;
+}
+
+// 2D+2V shapes: one wave per configuration cell, 1, 2 or 4 vx positions per load batch
+std::vector<StageShape> shape_table_4d()
+{
+    return {StageShape{256, 1, 1}, StageShape{256, 1, 2}, StageShape{256, 1, 4}};
+}
+
 // two-level tile shapes: threads x cells per thread x rows per tile
 std::vector<StageShape> amr_shape_table()
 {
@@ -192,6 +221,7 @@ std::vector<StageShape> amr_shape_table()
 
 std::vector<StageShape> plan_shapes(const vp_plan* p)
 {
+    if (p->p4) return shape_table_4d();
     return p->amr ? amr_shape_table() : shape_table(p->dtype);
 }
 
@@ -237,7 +267,7 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
     }
     if (pb->n_levels == 2) return create_two_level(pb, boxes, nbox, out);
     if (nbox != 0) return fail(VP_EINVAL, "a single-level plan takes no boxes");
-    if (pb->ndim != 1) return fail(VP_ENOTSUP, "this call sequence supports the 1D+1V problem");
+    if (pb->ndim == 2) return create_4d(pb, out);
 
     vp_plan* p = new (std::nothrow) vp_plan();
     if (!p) return fail(VP_ENOMEM, "out of host memory");
@@ -322,6 +352,7 @@ vp_status vp_tile_shape_set(vp_plan* p, int32_t index)
     if (p->amr) {
         if (vp_status s = amr_set_shape(p, tab[index].nt, tab[index].w, tab[index].tx)) return s;
     }
+    if (p->p4) p->p4->rb = tab[index].tx;
     p->shape = tab[index];
     return VP_OK;
 }
@@ -414,6 +445,7 @@ vp_status vp_plan_destroy(vp_plan* p)
         if (e) (void)hipEventDestroy(e);
     if (p->d_green) (void)hipFree(p->d_green);
     amr_destroy(p);
+    p4_destroy(p);
     delete p;
     return VP_OK;
 }
@@ -432,13 +464,14 @@ size_t vp_config_elems(const vp_plan* p) { return p ? (size_t)p->nx : 0; }
 size_t vp_field_elems(const vp_plan* p)
 {
     if (!p) return 0;
+    if (p->p4) return 2 * (size_t)p->nx;
     return p->amr ? (size_t)(p->amr->ncx + p->amr->nfx) : (size_t)p->nx;
 }
 size_t vp_workspace_bytes(const vp_plan* p) { return p ? p->ws_total : 0; }
 
 size_t vp_stage_elems(const vp_plan* p)
 {
-    if (!p || p->amr) return 0;
+    if (!p || p->amr || p->p4) return 0;
     const size_t a_bytes = 4 * (size_t)p->nx * sizeof(double);
     return 3 * p->state_elems + (a_bytes + p->esize - 1) / p->esize;
 }
@@ -449,6 +482,7 @@ vp_status vp_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipS
     if (!f || !a || !k) return fail(VP_EINVAL, "vp_rhs: NULL pointer");
     if (f == k) return fail(VP_EINVAL, "vp_rhs: k must not alias f");
     if (p->amr) return amr_rhs(p, f, a, k, stream);
+    if (p->p4) return p4_rhs(p, f, a, k, stream);
     const StageShape sh = pick_shape(p, {f, k});
     Stage1DArgs A = base_args(p, sh);
     A.fs = f;
@@ -466,6 +500,7 @@ vp_status vp_reduce_moment(const vp_plan* p, const void* f, double* n, void* wor
         if (!work) return fail(VP_EINVAL, "vp_reduce_moment: a two-level plan needs the workspace");
         return amr_reduce(p, f, n, work, stream);
     }
+    if (p->p4) return p4_reduce(p, f, n, stream);
     VP_HIP(timed(p, kTMoment, stream, [&] { return launch_moment_rows(p->dtype, f, p->nx, p->nv, p->dv, n, stream); }));
     return VP_OK;
 }
@@ -476,6 +511,7 @@ vp_status vp_poisson_periodic(const vp_plan* p, const double* n, double* phi, do
     (void)work;
     if (vp_status s = check_plan(p)) return s;
     if (!n) return fail(VP_EINVAL, "vp_poisson_periodic: NULL n");
+    if (p->p4) return p4_poisson(p, n, phi, E, stream);
     VP_HIP(timed(p, kTField, stream, [&] {
         return launch_poisson1d(nullptr, 0, n, p->dv, p->nx, p->dx, p->pb.qm, p->d_green, p->gk, nullptr, phi, E,
                                 nullptr, stream);
@@ -488,6 +524,10 @@ vp_status vp_inject_field(const vp_plan* p, const double* E, double* a, hipStrea
     if (vp_status s = check_plan(p)) return s;
     if (!E || !a) return fail(VP_EINVAL, "vp_inject_field: NULL pointer");
     if (p->amr) return amr_inject(p, E, a, stream);
+    if (p->p4) {
+        VP_HIP(timed(p, kTOther, stream, [&] { return launch_scale(E, p->pb.qm, a, 2 * p->nx, stream); }));
+        return VP_OK;
+    }
     VP_HIP(timed(p, kTOther, stream, [&] { return launch_scale(E, p->pb.qm, a, p->nx, stream); }));
     return VP_OK;
 }
@@ -498,6 +538,7 @@ vp_status vp_rk4_step(const vp_plan* p, void* f, double* a, double dt, void* wor
     if (!f || !a || !work) return fail(VP_EINVAL, "vp_rk4_step: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step: dt is not finite");
     if (p->amr) return amr_rk4(p, f, a, dt, work, stream);
+    if (p->p4) return p4_rk4(p, f, a, dt, work, stream);
     return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
 }
 
@@ -507,7 +548,7 @@ vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, vo
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a || !work || !stages) return fail(VP_EINVAL, "vp_rk4_step_record: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_record: dt is not finite");
-    if (p->amr) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level plans only");
+    if (p->amr || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level 1D+1V plans only");
     double* st_a = reinterpret_cast<double*>(static_cast<char*>(stages) + 3 * p->state_elems * p->esize);
     if (reinterpret_cast<uintptr_t>(st_a) % 8) return fail(VP_EINVAL, "stage record misaligned");
     return rk4_1d(p, f, a, dt, work, stages, st_a, stream);
@@ -518,7 +559,7 @@ vp_status vp_field_adjoint(const vp_plan* p, const double* abar, void* fbar, voi
     if (vp_status s = check_plan(p)) return s;
     if (!abar || !fbar || !work) return fail(VP_EINVAL, "vp_field_adjoint: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_field_adjoint: FP64 only");
-    if (p->amr) return fail(VP_ENOTSUP, "vp_field_adjoint: single-level plans only");
+    if (p->amr || p->p4) return fail(VP_ENOTSUP, "vp_field_adjoint: single-level 1D+1V plans only");
     double* cfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
     double* ab = cfg;
     double* z = cfg + p->nx;
@@ -538,7 +579,8 @@ vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, 
     if (vp_status s = check_plan(p)) return s;
     if (!f_n || !a_n || !lam_np1 || !lam_n || !work) return fail(VP_EINVAL, "vp_adjoint_step: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is FP64 only");
-    if (p->amr || p->nlev != 1 || p->ndim != 1) return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
+    if (p->amr || p->p4 || p->nlev != 1 || p->ndim != 1)
+        return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_adjoint_step: dt is not finite");
     const size_t N = p->state_elems;
     const int nx = p->nx, nv = p->nv;

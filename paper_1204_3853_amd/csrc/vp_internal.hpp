@@ -75,6 +75,26 @@ struct Adjoint1DArgs {
     double c1, c2;          // dt b_s, dt alpha_{s+1}
 };
 
+// ----------------------------------------------------------------- 2D+2V
+
+constexpr int kMaxPoisson2D = 64;     // configuration cells per direction of the 2D+2V path
+constexpr int kMaxVy4D = 64;          // velocity cells along vy (one lane each)
+
+// Arguments of the 2D+2V stage kernel (FP64).
+struct Stage4DArgs {
+    int nx, ny, nvx, nvy;
+    double dxi, dyi, dvxi, dvyi, dvx24, dvy24, vx_lo, vy_lo, dvx, dvy;
+    const double* gx;          // 1D equilibrium along vx with ghosts (nvx + 4), device
+    const double* gy;          // 1D equilibrium along vy with ghosts (nvy + 4), device
+    const double* fs;
+    const double* fn;
+    double* acc;
+    double* fout;
+    const double* a;           // a_x (nx ny), then a_y
+    double* n;                 // velocity moment of the output per configuration cell (or null)
+    double c_acc, c_next, mscale;
+};
+
 // ----------------------------------------------------------------- two levels
 
 struct AmrPatch {              // one level-1 patch
@@ -137,6 +157,14 @@ hipError_t launch_adjoint_final(const double* mu, const double* g, const double*
                                 hipStream_t stream);
 hipError_t launch_scale(const double* x, double s, double* y, int n, hipStream_t stream);
 hipError_t poisson1d_prepare();
+
+// 2D+2V launchers (vp_kernels_4d.hip)
+hipError_t launch_stage4d(int rb, int kind, const Stage4DArgs& a, hipStream_t stream);
+hipError_t launch_moment4d(const double* f, int ncfg, size_t plane, double scale, double* n, hipStream_t stream);
+hipError_t poisson2d_prepare();
+hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
+                            const double* QxT, const double* Qy, const double* QyT, const double* invlamT,
+                            double* phi, double* E, double* a, hipStream_t stream);
 
 // two-level launchers (vp_kernels_amr.hip)
 hipError_t launch_amr_stage(int w, int nt, int kind, const AmrArgs& a, int t_begin, int t_end, int grid,
@@ -220,6 +248,24 @@ struct AmrPlan {
 };
 }  // namespace vp
 
+// ----------------------------------------------------------------- 2D+2V plan
+
+namespace vp {
+struct Plan4D {
+    int nx = 0, ny = 0, nvx = 0, nvy = 0;
+    double dx = 0, dy = 0, dvx = 0, dvy = 0, v_lo = 0;
+    int rb = 2;                                      // vx positions per load batch
+    double* d_gx = nullptr;
+    double* d_gy = nullptr;
+    double* d_Qx = nullptr;
+    double* d_QxT = nullptr;
+    double* d_Qy = nullptr;
+    double* d_QyT = nullptr;
+    double* d_invlamT = nullptr;
+    size_t ws_n = 0, ws_E = 0;
+};
+}  // namespace vp
+
 // ----------------------------------------------------------------- the plan
 
 struct vp_plan {
@@ -248,6 +294,7 @@ struct vp_plan {
 
     mutable Timing timing;
     vp::AmrPlan* amr = nullptr;
+    vp::Plan4D* p4 = nullptr;
 };
 
 namespace vp {
@@ -259,6 +306,13 @@ vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hip
 vp_status amr_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
 vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
 vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx);
+// 2D+2V host sequences (vp_4d.hip)
+vp_status p4_create(vp_plan* p, const vp_problem* pb);
+void p4_destroy(vp_plan* p);
+vp_status p4_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream);
+vp_status p4_reduce(const vp_plan* p, const void* f, double* n, hipStream_t stream);
+vp_status p4_poisson(const vp_plan* p, const double* n, double* phi, double* E, hipStream_t stream);
+vp_status p4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
 }  // namespace vp
 
 namespace vp {

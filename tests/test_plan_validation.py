@@ -87,3 +87,32 @@ def test_single_level_rejects_boxes(V):
     pb, keep = make_problem(V)
     pb.n_levels = 1
     assert create(V, pb, [((16, 40), (39, 63))])[0] == 1
+
+
+def make_problem_4d(V, nx=8, ny=8, nvx=16, nvy=16, dtype=0):
+    pb = V.vp_problem()
+    pb.ndim, pb.dtype, pb.n_levels = 2, dtype, 1
+    for d, c in enumerate((nx, ny, nvx, nvy)):
+        pb.cells[d] = c
+    for d in range(2):
+        pb.x_len[d] = 4 * math.pi
+        pb.v_lo[d], pb.v_hi[d] = -6.0, 6.0
+    pb.qm = -1.0
+    gx = I.cell_average_1d(I.maxwellian, -6, 6, nvx, first=-2, count=nvx + 4)
+    gy = I.cell_average_1d(I.maxwellian, -6, 6, nvy, first=-2, count=nvy + 4)
+    keep = [(ctypes.c_double * len(gx))(*gx), (ctypes.c_double * len(gy))(*gy)]
+    pb.veq[0][0] = ctypes.cast(keep[0], ctypes.POINTER(ctypes.c_double))
+    pb.veq[0][1] = ctypes.cast(keep[1], ctypes.POINTER(ctypes.c_double))
+    return pb, keep
+
+
+@pytest.mark.parametrize("kw,code", [(dict(nvy=65), 4), (dict(nx=65), 4), (dict(ny=80), 4), (dict(dtype=1), 4)])
+def test_4d_limits(V, kw, code):
+    pb, keep = make_problem_4d(V, **kw)
+    assert create(V, pb, [])[0] == code
+
+
+def test_4d_needs_vy_equilibrium(V):
+    pb, keep = make_problem_4d(V)
+    pb.veq[0][1] = None
+    assert create(V, pb, [])[0] == 1
