@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--amr-only", action="store_true", help="run only the two-level section (for profiling)")
+    ap.add_argument("--no-4d", action="store_true")
+    ap.add_argument("--4d-only", dest="fourd_only", action="store_true", help="run only the 2D+2V section")
     return ap.parse_args()
 
 
@@ -199,6 +201,47 @@ def amr_bench(steps=100, warmup=3):
             "us_per_launch_by_class": per_launch}
 
 
+def fourd_bench(steps=50, warmup=3):
+    """2D+2V 64^4 FP64 (x, y in [0, 4pi), v in [-6, 6]^2, Landau-type
+    initial state): RK4 steps after the load-batch autotune."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+    p = I.Problem2D(64, 64, 64, 64)
+    plan = vp.Plan(p)
+    f = torch.tensor(p.initial_state().ravel(), dtype=torch.float64, device="cuda")
+    a = vp.field_of(plan, f)
+    dt = 8.153e-3
+    tuned, shape, _ = plan.autotune(f, a, dt, reps=3)
+    for _ in range(warmup):
+        vp.rk4_step(plan, f, a, dt)
+    st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    st.record()
+    for _ in range(steps):
+        vp.rk4_step(plan, f, a, dt)
+    sp.record()
+    torch.cuda.synchronize()
+    ms = st.elapsed_time(sp) / steps
+    plan.timing_enable(True)
+    for _ in range(steps):
+        vp.rk4_step(plan, f, a, dt)
+    torch.cuda.synchronize()
+    tm = plan.timing_read()
+    plan.timing_enable(False)
+    cells = plan.state_elems
+    stage_us = tm["stage"][0] / tm["stage"][1] * 1e3
+    bytes_launch = 4 * 8 * cells
+    return {"workload": "2D+2V Vlasov-Poisson 64^4 FP64, x,y in [0,4pi), v in [-6,6]^2, dt=%g" % dt,
+            "cells": cells, "steps": steps, "ms_per_step": round(ms, 4), "cell_updates_per_s": cells / (ms * 1e-3),
+            "tuned_vx_batch": shape[2],
+            "stage_kernel": {"avg_launch_us": round(stage_us, 2), "algorithmic_bytes_per_launch": bytes_launch,
+                             "achieved_GBs": round(bytes_launch / (stage_us * 1e-6) / 1e9, 1),
+                             "frac_of_peak": round(bytes_launch / (stage_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+            "field_solve_us": round(tm["field"][0] / tm["field"][1] * 1e3, 2)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -210,6 +253,9 @@ def main():
     import vp_inputs as I
     from paper_1204_3853_amd import vp
 
+    if args.fourd_only:
+        print(json.dumps({"2d2v": fourd_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
     if args.amr_only:
         print(json.dumps({"amr": amr_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
         return
@@ -265,6 +311,7 @@ def main():
 
     adj = None if args.no_adjoint else adjoint_ratio()
     amr = None if args.no_amr else amr_bench()
+    fourd = None if args.no_4d else fourd_bench()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -289,6 +336,7 @@ def main():
         "cpu_baseline": cpu,
         "adjoint": adj,
         "amr": amr,
+        "2d2v": fourd,
     }
     print(json.dumps(out), flush=True)
 

@@ -46,14 +46,6 @@ std::vector<double> fourier_symbol(int n, double h)
     return lam;
 }
 
-std::vector<double> transpose(const std::vector<double>& Q, int n)
-{
-    std::vector<double> T(Q.size());
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) T[(size_t)j * n + i] = Q[(size_t)i * n + j];
-    return T;
-}
-
 hipError_t upload(double** dst, const std::vector<double>& v)
 {
     hipError_t e = hipMalloc(dst, v.size() * sizeof(double));
@@ -124,9 +116,7 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     VP_HIP(upload(&M->d_gx, gx));
     VP_HIP(upload(&M->d_gy, gy));
     VP_HIP(upload(&M->d_Qx, Qx));
-    VP_HIP(upload(&M->d_QxT, transpose(Qx, M->nx)));
     VP_HIP(upload(&M->d_Qy, Qy));
-    VP_HIP(upload(&M->d_QyT, transpose(Qy, M->ny)));
     VP_HIP(upload(&M->d_invlamT, inv));
     VP_HIP(poisson2d_prepare());
 
@@ -146,7 +136,7 @@ void p4_destroy(vp_plan* p)
 {
     Plan4D* M = p->p4;
     if (!M) return;
-    double* ptrs[] = {M->d_gx, M->d_gy, M->d_Qx, M->d_QxT, M->d_Qy, M->d_QyT, M->d_invlamT};
+    double* ptrs[] = {M->d_gx, M->d_gy, M->d_Qx, M->d_Qy, M->d_invlamT};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
     delete M;
@@ -177,8 +167,8 @@ vp_status p4_poisson(const vp_plan* p, const double* n, double* phi, double* E, 
 {
     const Plan4D& M = *p->p4;
     VP_HIP(timed(p, kTField, stream, [&] {
-        return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_QxT, M.d_Qy, M.d_QyT, M.d_invlamT,
-                                phi, E, nullptr, stream);
+        return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_Qy, M.d_invlamT, phi, E, nullptr,
+                                stream);
     }));
     return VP_OK;
 }
@@ -208,8 +198,8 @@ vp_status p4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
         const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
         VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage4d(M.rb, kind, A, stream); }));
         VP_HIP(timed(p, kTField, stream, [&] {
-            return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_QxT, M.d_Qy, M.d_QyT,
-                                    M.d_invlamT, nullptr, nullptr, a, stream);
+            return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_Qy, M.d_invlamT, nullptr,
+                                    nullptr, a, stream);
         }));
     }
     return VP_OK;

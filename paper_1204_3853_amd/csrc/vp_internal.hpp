@@ -163,8 +163,8 @@ hipError_t launch_stage4d(int rb, int kind, const Stage4DArgs& a, hipStream_t st
 hipError_t launch_moment4d(const double* f, int ncfg, size_t plane, double scale, double* n, hipStream_t stream);
 hipError_t poisson2d_prepare();
 hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
-                            const double* QxT, const double* Qy, const double* QyT, const double* invlamT,
-                            double* phi, double* E, double* a, hipStream_t stream);
+                            const double* Qy, const double* invlamT, double* phi, double* E, double* a,
+                            hipStream_t stream);
 
 // two-level launchers (vp_kernels_amr.hip)
 hipError_t launch_amr_stage(int w, int nt, int kind, const AmrArgs& a, int t_begin, int t_end, int grid,
@@ -258,9 +258,7 @@ struct Plan4D {
     double* d_gx = nullptr;
     double* d_gy = nullptr;
     double* d_Qx = nullptr;
-    double* d_QxT = nullptr;
     double* d_Qy = nullptr;
-    double* d_QyT = nullptr;
     double* d_invlamT = nullptr;
     size_t ws_n = 0, ws_E = 0;
 };

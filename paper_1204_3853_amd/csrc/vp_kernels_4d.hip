@@ -27,7 +27,21 @@ __device__ __forceinline__ double f4(double um1, double u0, double u1, double u2
     return (7.0 * (u0 + u1) - (um1 + u2)) * (1.0 / 12.0);
 }
 
-template <int KIND, int RB>
+// The fluxes enter the update only through differences across a cell, and
+// face averages and product-rule corrections are linear in the cell
+// values, so the wave combines before it differentiates:
+//   x: Gx(x+1/2) - Gx(x-1/2) = vbar_x Dx + (dvx/24) (Dx(vx+1) - Dx(vx-1)),
+//      Dx = (8 (f(x+1) - f(x-1)) - (f(x+2) - f(x-2))) / 12, the difference
+//      of the two x-face averages;
+//   y: the same with Dy and the vy neighbours (lanes);
+//   vx: Gvx on a face is the face average along vx of
+//      V = ax f + (dax_x (f(x+1) - f(x-1)) + dax_y (f(y+1) - f(y-1))) / 48;
+//   vy: Gvy is the face average along vy of the corresponding U with ay.
+// Ghost cells hold the equilibrium, which is the same in every plane, so
+// V and U there reduce to ax g and ay g.
+// The march is software-pipelined: the rows of NB - 1 positions ahead of
+// the one being consumed are in flight while a position is computed.
+template <int KIND, int NB>
 __global__ __launch_bounds__(256) void k_stage4d(Stage4DArgs A)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -45,128 +59,94 @@ __global__ __launch_bounds__(256) void k_stage4d(Stage4DArgs A)
     const double* __restrict__ fs = A.fs;
     const double* ax = A.a;
     const double* ay = A.a + nx * ny;
-    const double axc = ax[cfg(x, y)], dax_x = ax[cfg(x + 1, y)] - ax[cfg(x - 1, y)],
-                 dax_y = ax[cfg(x, y + 1)] - ax[cfg(x, y - 1)];
-    const double ayc = ay[cfg(x, y)], day_x = ay[cfg(x + 1, y)] - ay[cfg(x - 1, y)],
-                 day_y = ay[cfg(x, y + 1)] - ay[cfg(x, y - 1)];
+    const double axc = ax[cfg(x, y)], cax_x = (ax[cfg(x + 1, y)] - ax[cfg(x - 1, y)]) * (1.0 / 48.0),
+                 cax_y = (ax[cfg(x, y + 1)] - ax[cfg(x, y - 1)]) * (1.0 / 48.0);
+    const double ayc = ay[cfg(x, y)], cay_x = (ay[cfg(x + 1, y)] - ay[cfg(x - 1, y)]) * (1.0 / 48.0),
+                 cay_y = (ay[cfg(x, y + 1)] - ay[cfg(x, y - 1)]) * (1.0 / 48.0);
 
     const bool act = lane < nvy;
     const int vyl = act ? lane : nvy - 1;
-    // 1D equilibrium factors along vy at lane + d, d = -2..2 (used where lane + d is a ghost)
-    double gyd[5];
+    double gyd[5];                                      // vy equilibrium factors at lane - 2 .. lane + 2
 #pragma unroll
     for (int d = 0; d < 5; ++d) gyd[d] = A.gy[min(max(lane + d, 0), nvy + 3)];
     const double gyl = gyd[2];
     const double vby = A.vy_lo + ((double)lane + 0.5) * A.dvy;
     const double dxi = A.dxi, dyi = A.dyi, dvxi = A.dvxi, dvyi = A.dvyi, dvx24 = A.dvx24, dvy24 = A.dvy24;
 
-    // value of lane + d of a row at a vx position whose equilibrium factor is gq
+    // lane + d of a per-lane quantity whose ghost value at lane + d is gq * gy[lane + d]
     auto nb = [&](double u, int d, double gq) {
         const double s = __shfl(u, lane + d, 64);
         const int src = lane + d;
         return (src >= 0 && src < nvy) ? s : gq * gyd[d + 2];
     };
-    // rows of the nine planes at vx position p (equilibrium products outside the velocity box)
-    auto ld9 = [&](int p, double* v) {
+
+    double Lb[NB][9], FNb[NB], ACb[NB];
+    // loads of lead position p (and of f^n / acc at the output position p - 2) into slot s
+    auto issue = [&](int p, int s) {
         const int pc = min(max(p, 0), nvx - 1);
         const size_t o = (size_t)pc * nvy + vyl;
-        double r[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) r[q] = fs[po[q] + o];
+        for (int q = 0; q < 9; ++q) Lb[s][q] = fs[po[q] + o];
+        const size_t oo = po[0] + (size_t)min(max(p - 2, 0), nvx - 1) * nvy + vyl;
+        if (KIND == kStage23) FNb[s] = A.fn[oo];
+        if (KIND == kStage23 || KIND == kStage4) ACb[s] = A.acc[oo];
+    };
+
+    // rolling state along vx: V at t-1 .. t+2, U, f and Dx at t-1/t .. t+2, Dy at t .. t+2
+    double vw[4] = {0, 0, 0, 0}, uw[3] = {0, 0, 0}, cw[3] = {0, 0, 0}, dxw[4] = {0, 0, 0, 0}, dyw[3] = {0, 0, 0};
+    auto shift_in = [&](const double* r, int p) {
         const bool in = p >= 0 && p < nvx;
-        const double g = A.gx[min(p + 2, nvx + 3)] * gyl;
+        const double g = A.gx[min(max(p + 2, 0), nvx + 3)] * gyl;
+        double v[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) v[q] = in ? r[q] : g;
+        vw[0] = vw[1]; vw[1] = vw[2]; vw[2] = vw[3];
+        vw[3] = axc * v[0] + (cax_x * (v[2] - v[1]) + cax_y * (v[4] - v[3]));
+        uw[0] = uw[1]; uw[1] = uw[2];
+        uw[2] = ayc * v[0] + (cay_x * (v[2] - v[1]) + cay_y * (v[4] - v[3]));
+        cw[0] = cw[1]; cw[1] = cw[2]; cw[2] = v[0];
+        dxw[0] = dxw[1]; dxw[1] = dxw[2]; dxw[2] = dxw[3];
+        dxw[3] = (8.0 * (v[2] - v[1]) - (v[6] - v[5])) * (1.0 / 12.0);
+        dyw[0] = dyw[1]; dyw[1] = dyw[2];
+        dyw[2] = (8.0 * (v[4] - v[3]) - (v[8] - v[7])) * (1.0 / 12.0);
     };
 
-    // rolling state: rows at t-1 .. t+2 of the five planes used along vx and vy,
-    // x-face averages at t-1 .. t+2, y-face averages at t .. t+2
-    double w[5][4], fxl[4], fxh[4], fyl[3], fyh[3];
 #pragma unroll
-    for (int q = 0; q < 5; ++q)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) w[q][m] = 0.0;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) { fxl[m] = 0.0; fxh[m] = 0.0; }
-#pragma unroll
-    for (int m = 0; m < 3; ++m) { fyl[m] = 0.0; fyh[m] = 0.0; }
-    auto shift_in = [&](const double* v) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            w[q][0] = w[q][1]; w[q][1] = w[q][2]; w[q][2] = w[q][3]; w[q][3] = v[q];
-        }
-        fxl[0] = fxl[1]; fxl[1] = fxl[2]; fxl[2] = fxl[3];
-        fxh[0] = fxh[1]; fxh[1] = fxh[2]; fxh[2] = fxh[3];
-        fxl[3] = f4(v[5], v[1], v[0], v[2]);             // face x - 1/2
-        fxh[3] = f4(v[1], v[0], v[2], v[6]);             // face x + 1/2
-        fyl[0] = fyl[1]; fyl[1] = fyl[2];
-        fyh[0] = fyh[1]; fyh[1] = fyh[2];
-        fyl[2] = f4(v[7], v[3], v[0], v[4]);             // face y - 1/2
-        fyh[2] = f4(v[3], v[0], v[4], v[8]);             // face y + 1/2
-    };
-    // flux through the vx face between window positions 0..3 (face between 1 and 2)
-    auto gvx = [&]() {
-        const double fc = f4(w[0][0], w[0][1], w[0][2], w[0][3]);
-        const double fxm = f4(w[1][0], w[1][1], w[1][2], w[1][3]);
-        const double fxp = f4(w[2][0], w[2][1], w[2][2], w[2][3]);
-        const double fym = f4(w[3][0], w[3][1], w[3][2], w[3][3]);
-        const double fyp = f4(w[4][0], w[4][1], w[4][2], w[4][3]);
-        return axc * fc + (dax_x * (fxp - fxm) + dax_y * (fyp - fym)) * (1.0 / 48.0);
-    };
-
-    {
-        double v[9];
-#pragma unroll 1
-        for (int p = -2; p <= 1; ++p) {
-            ld9(p, v);
-            shift_in(v);
-        }
+    for (int p = -2; p <= 1; ++p) {
+        issue(p, 0);
+        shift_in(Lb[0], p);
     }
-    double gvx_lo = gvx();                               // face -1/2
+    double gvx_lo = f4(vw[0], vw[1], vw[2], vw[3]);      // face -1/2
     double msum = 0.0;
     const double cacc = A.c_acc, cnext = A.c_next;
+#pragma unroll
+    for (int s = 0; s < NB - 1; ++s) issue(2 + s, s);
 
 #pragma unroll 1
-    for (int tb = 0; tb < nvx; tb += RB) {
-        double L[RB][9], FN[RB], AC[RB];
+    for (int tb = 0; tb < nvx; tb += NB) {
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            ld9(tb + q + 2, L[q]);
-            const size_t o = po[0] + (size_t)min(tb + q, nvx - 1) * nvy + vyl;
-            if (KIND == kStage23) FN[q] = A.fn[o];
-            if (KIND == kStage23 || KIND == kStage4) AC[q] = A.acc[o];
-        }
-#pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            const int t = tb + q;
-            shift_in(L[q]);
+        for (int s = 0; s < NB; ++s) {
+            const int t = tb + s;
+            issue(t + 2 + NB - 1, (s + NB - 1) % NB);
+            shift_in(Lb[s], t + 2);
             if (t >= nvx) continue;                      // uniform
             const double gxt = A.gx[t + 2];
-            // x
+            // x and y: differences of the face fluxes
             const double vbx = A.vx_lo + ((double)t + 0.5) * A.dvx;
-            const double gxh = vbx * fxh[1] + dvx24 * (fxh[2] - fxh[0]);
-            const double gxl = vbx * fxl[1] + dvx24 * (fxl[2] - fxl[0]);
-            // y (product-rule term along vy from the neighbouring lanes)
-            const double gyh = vby * fyh[0] + dvy24 * (nb(fyh[0], 1, gxt) - nb(fyh[0], -1, gxt));
-            const double gyl2 = vby * fyl[0] + dvy24 * (nb(fyl[0], 1, gxt) - nb(fyl[0], -1, gxt));
+            const double kx = (vbx * dxw[1] + dvx24 * (dxw[2] - dxw[0])) * dxi;
+            const double ky = (vby * dyw[0] + dvy24 * (nb(dyw[0], 1, 0.0) - nb(dyw[0], -1, 0.0))) * dyi;
             // vx
-            const double gvx_hi = gvx();
-            // vy: upper face from lanes -1 .. +2 of the five planes; lower face from lane - 1
-            double fh[5], flb[5];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const double u0 = w[q][1];
-                const double um = nb(u0, -1, gxt), u1 = nb(u0, 1, gxt), u2 = nb(u0, 2, gxt);
-                fh[q] = f4(um, u0, u1, u2);
-                flb[q] = f4(gxt * gyd[0], um, u0, u1);   // lower face of lane 0 (velocity-box face)
-            }
-            const double gvy_hi = ayc * fh[0] + (day_x * (fh[2] - fh[1]) + day_y * (fh[4] - fh[3])) * (1.0 / 48.0);
-            const double gvy_b = ayc * flb[0] + (day_x * (flb[2] - flb[1]) + day_y * (flb[4] - flb[3])) * (1.0 / 48.0);
+            const double gvx_hi = f4(vw[0], vw[1], vw[2], vw[3]);
+            // vy: upper face from lanes -1 .. +2; lower face from lane - 1 (lane 0: the box face)
+            const double gu = ayc * gxt;
+            const double u0 = uw[0];
+            const double um = nb(u0, -1, gu), u1 = nb(u0, 1, gu), u2 = nb(u0, 2, gu);
+            const double gvy_hi = f4(um, u0, u1, u2);
+            const double gvy_b = f4(gu * gyd[0], um, u0, u1);
             const double gvy_s = __shfl(gvy_hi, lane - 1, 64);
             const double gvy_lo = lane == 0 ? gvy_b : gvy_s;
 
-            const double k = -(gxh - gxl) * dxi - (gyh - gyl2) * dyi - (gvx_hi - gvx_lo) * dvxi -
-                             (gvy_hi - gvy_lo) * dvyi;
+            const double k = -kx - ky - (gvx_hi - gvx_lo) * dvxi - (gvy_hi - gvy_lo) * dvyi;
             gvx_lo = gvx_hi;
 
             const size_t o = po[0] + (size_t)t * nvy + lane;
@@ -175,14 +155,14 @@ __global__ __launch_bounds__(256) void k_stage4d(Stage4DArgs A)
                 out = k;
                 if (act) A.fout[o] = out;
             } else if (KIND == kStage1) {
-                const double f0 = w[0][1];
+                const double f0 = cw[0];
                 out = f0 + cnext * k;
                 if (act) { A.acc[o] = f0 + cacc * k; A.fout[o] = out; }
             } else if (KIND == kStage23) {
-                out = FN[q] + cnext * k;
-                if (act) { A.acc[o] = AC[q] + cacc * k; A.fout[o] = out; }
+                out = FNb[s] + cnext * k;
+                if (act) { A.acc[o] = ACb[s] + cacc * k; A.fout[o] = out; }
             } else {
-                out = AC[q] + cacc * k;
+                out = ACb[s] + cacc * k;
                 if (act) A.fout[o] = out;
             }
             if (act) msum += out;
@@ -212,11 +192,13 @@ __global__ __launch_bounds__(256) void k_moment4d(const double* __restrict__ f, 
 
 constexpr int kLd = kMaxPoisson2D + 1;
 
-// C = A B for A (M x K) and B (K x N) in LDS with row stride kLd; each
-// thread computes a 4 x 4 block; C is stored transposed when `tr`.
-// Rows and columns past the sizes are zero in A and B, so the padded
-// entries of C come out zero.
-__device__ __forceinline__ void mm_lds(const double* A, const double* B, int M, int K, int N, double* C, bool tr)
+// C = A B for A (M x K) and B (K x N) in LDS with row stride kLd (BT: B
+// is stored transposed, element (k, n) at B[n * kLd + k]); each thread
+// computes a 4 x 4 block; C is stored transposed when TR.  Rows and
+// columns past the sizes are zero in A and B, so the padded entries of C
+// come out zero.
+template <bool BT, bool TR>
+__device__ __forceinline__ void mm_lds(const double* A, const double* B, int M, int K, int N, double* C)
 {
     const int t = threadIdx.x;
     const int r0 = (t >> 4) * 4, c0 = (t & 15) * 4;
@@ -228,7 +210,7 @@ __device__ __forceinline__ void mm_lds(const double* A, const double* B, int M, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = A[(r0 + r) * kLd + k];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = B[k * kLd + c0 + c];
+        for (int c = 0; c < 4; ++c) b[c] = BT ? B[(c0 + c) * kLd + k] : B[k * kLd + c0 + c];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -238,27 +220,36 @@ __device__ __forceinline__ void mm_lds(const double* A, const double* B, int M, 
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            if (tr) C[(c0 + c) * kLd + r0 + r] = acc[r][c];
+            if (TR) C[(c0 + c) * kLd + r0 + r] = acc[r][c];
             else C[(r0 + r) * kLd + c0 + c] = acc[r][c];
         }
 }
 
-__device__ __forceinline__ void load_mat(const double* __restrict__ g, int rows, int cols, double* S)
+constexpr int kPer = kMaxPoisson2D * kMaxPoisson2D / 256;   // matrix entries per thread
+
+// a rows x cols row-major matrix, kPer entries per thread, all loads in flight together
+__device__ __forceinline__ void fetch(const double* __restrict__ g, int count, double* v)
 {
-    for (int q = threadIdx.x; q < rows * cols; q += 256) {
-        const int r = q / cols, c = q - (q / cols) * cols;
-        S[r * kLd + c] = g[q];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) v[r] = g[min((int)threadIdx.x + r * 256, count - 1)];
+}
+
+__device__ __forceinline__ void store_mat(const double* v, int rows, int cols, double* S)
+{
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int q = (int)threadIdx.x + r * 256;
+        if (q < rows * cols) S[(q / cols) * kLd + q % cols] = v[r];
     }
 }
 
 // Periodic Poisson problem of the summed 1D fourth-order operators,
-// solved in the real orthonormal Fourier basis that diagonalises every
+// solved in the real orthonormal Fourier basis Q that diagonalises every
 // symmetric circulant matrix: phi = Qx [ (Qx^T rho Qy) / lambda ] Qy^T,
 // the zero mode dropped.  Then E = -D phi per direction and a = (q/m) E.
 __global__ __launch_bounds__(256) void k_poisson2d(const double* __restrict__ n, int nx, int ny, double dx,
                                                   double dy, double qm, const double* __restrict__ Qx,
-                                                  const double* __restrict__ QxT, const double* __restrict__ Qy,
-                                                  const double* __restrict__ QyT,
+                                                  const double* __restrict__ Qy,
                                                   const double* __restrict__ invlamT, double* __restrict__ phi_out,
                                                   double* __restrict__ E_out, double* __restrict__ a_out)
 {
@@ -266,14 +257,21 @@ __global__ __launch_bounds__(256) void k_poisson2d(const double* __restrict__ n,
     constexpr int S = kMaxPoisson2D * kLd;
     double* A = sm;
     double* B = sm + S;
-    double* Q1 = sm + 2 * S;
-    double* Q2 = sm + 3 * S;
+    double* QY = sm + 2 * S;
+    double* QX = sm + 3 * S;
     __shared__ double red[256];
     const int t = threadIdx.x;
     const int N = nx * ny;
+    double vn[kPer], vqx[kPer], vqy[kPer], vil[kPer];
+    fetch(n, N, vn);
+    fetch(Qx, nx * nx, vqx);
+    fetch(Qy, ny * ny, vqy);
+    fetch(invlamT, N, vil);
     for (int q = t; q < 4 * S; q += 256) sm[q] = 0.0;
     double s = 0.0;
-    for (int q = t; q < N; q += 256) s += n[q];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+        if (t + r * 256 < N) s += vn[r];
     red[t] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -281,28 +279,25 @@ __global__ __launch_bounds__(256) void k_poisson2d(const double* __restrict__ n,
         __syncthreads();
     }
     const double mean = red[0] / N;
-    // rho - mean(rho) = mean(n) - n
-    for (int q = t; q < N; q += 256) {
-        const int i = q / ny, j = q - (q / ny) * ny;
-        A[i * kLd + j] = mean - n[q];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) vn[r] = mean - vn[r];       // rho - mean(rho) = mean(n) - n
+    store_mat(vn, nx, ny, A);
+    store_mat(vqy, ny, ny, QY);
+    store_mat(vqx, nx, nx, QX);
+    __syncthreads();
+    mm_lds<false, true>(A, QY, nx, ny, ny, B);     // B[l][i] = (rho Qy)[i][l]
+    __syncthreads();
+    mm_lds<false, false>(B, QX, ny, nx, nx, A);    // A[l][k] = (Qx^T rho Qy)[k][l]
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int q = t + r * 256;
+        if (q < N) A[(q / nx) * kLd + q % nx] *= vil[r];
     }
-    load_mat(Qy, ny, ny, Q1);
-    load_mat(Qx, nx, nx, Q2);
     __syncthreads();
-    mm_lds(A, Q1, nx, ny, ny, B, true);        // B[l][i] = (rho Qy)[i][l]
+    mm_lds<true, true>(A, QX, ny, nx, nx, B);      // B[i][l] = sum_k Qx[i][k] A[l][k]
     __syncthreads();
-    mm_lds(B, Q2, ny, nx, nx, A, false);       // A[l][k] = (Qx^T rho Qy)[k][l]
-    __syncthreads();
-    for (int q = t; q < N; q += 256) {
-        const int l = q / nx, k = q - (q / nx) * nx;
-        A[l * kLd + k] *= invlamT[q];
-    }
-    load_mat(QxT, nx, nx, Q2);
-    load_mat(QyT, ny, ny, Q1);
-    __syncthreads();
-    mm_lds(A, Q2, ny, nx, nx, B, true);        // B[i][l] = (Qx hat)[i][l]
-    __syncthreads();
-    mm_lds(B, Q1, nx, ny, ny, A, false);       // A[i][j] = phi
+    mm_lds<true, false>(B, QY, nx, ny, ny, A);     // A[i][j] = sum_l B[i][l] Qy[j][l] = phi
     __syncthreads();
     const double cx = 1.0 / (12.0 * dx), cy = 1.0 / (12.0 * dy);
     for (int q = t; q < N; q += 256) {
@@ -323,8 +318,8 @@ hipError_t launch_stage4d_k(int rb, const Stage4DArgs& a, hipStream_t stream)
     const int ncfg = a.nx * a.ny;
     const dim3 g((ncfg + 3) / 4), b(256);
     switch (rb) {
-    case 1: hipLaunchKernelGGL((k_stage4d<KIND, 1>), g, b, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((k_stage4d<KIND, 2>), g, b, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((k_stage4d<KIND, 2>), g, b, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((k_stage4d<KIND, 3>), g, b, 0, stream, a); break;
     case 4: hipLaunchKernelGGL((k_stage4d<KIND, 4>), g, b, 0, stream, a); break;
     default: return hipErrorInvalidValue;
     }
@@ -358,12 +353,12 @@ hipError_t poisson2d_prepare()
 }
 
 hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
-                            const double* QxT, const double* Qy, const double* QyT, const double* invlamT,
-                            double* phi, double* E, double* a, hipStream_t stream)
+                            const double* Qy, const double* invlamT, double* phi, double* E, double* a,
+                            hipStream_t stream)
 {
     if (nx > kMaxPoisson2D || ny > kMaxPoisson2D) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_poisson2d, dim3(1), dim3(256), poisson2d_lds_bytes(), stream, n, nx, ny, dx, dy, qm, Qx,
-                       QxT, Qy, QyT, invlamT, phi, E, a);
+                       Qy, invlamT, phi, E, a);
     return hipGetLastError();
 }
 
