@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "phase-space cell-updates/s per RK4 step, % peak HBM GB/s; adjoint/forward ratio"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage1d_two_stream_4096.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage1d_two_stream_4096_traffic.md")
 
 
 def parse():
@@ -44,8 +44,24 @@ def parse():
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--amr-only", action="store_true", help="run only the two-level section (for profiling)")
     ap.add_argument("--no-4d", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run three device-to-device copies of MIB MiB (reference for HBM traffic counters)")
     ap.add_argument("--4d-only", dest="fourd_only", action="store_true", help="run only the 2D+2V section")
     return ap.parse_args()
+
+
+def read_traffic(n, dtype):
+    """HBM bytes per stage launch from the committed counter summary, when it
+    covers this workload (a line `traffic: n=<n> dtype=<dtype> bytes_per_launch=<B>`)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("traffic:"):
+                kv = dict(item.split("=") for item in line.split()[1:])
+                if int(kv["n"]) == n and kv["dtype"] == dtype:
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(n, dt, seconds):
@@ -259,6 +275,13 @@ def main():
     if args.amr_only:
         print(json.dumps({"amr": amr_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
         return
+    if args.calibrate_copy:
+        src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
     n = args.n
     p = I.two_stream(n, n)
@@ -297,12 +320,7 @@ def main():
         avg_ms = st_ms / st_n
         bytes_launch = bytes_step / 4.0
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-        traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            with open(TRAFFIC_FILE) as fh:
-                tr = json.load(fh)
-            if tr.get("n") == n and tr.get("dtype") == args.dtype:
-                traffic = tr.get("bytes_per_launch")
+        traffic = read_traffic(n, args.dtype)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "k_stage1d (4 launches per RK4 step)", "avg_launch_us": round(avg_ms * 1e3, 2),
