@@ -89,6 +89,11 @@ __device__ __forceinline__ T face4(T um1, T u0, T u1, T u2)
 // f^n / accumulator rows being updated) are issued together, so each wave
 // keeps RB rows of traffic in flight; the rows go through an 8-slot LDS
 // ring that holds the stencil's x-neighbourhood rows i-2 .. i+RB+1.
+// Even segments march towards increasing x and odd segments towards
+// decreasing x, so two neighbouring segments reach the rows they share
+// (each other's two halo rows) at about the same time, while those rows
+// are still in L2.  Every face flux is formed from the same four rows in
+// either direction, so the results do not depend on the direction.
 template <typename T, int W, int NT, int KIND>
 __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int tile)
 {
@@ -172,44 +177,54 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
     const T dxi = (T)A.dxi, dvi = (T)A.dvi, dv24 = (T)A.dv24;
     const T cacc = (T)A.c_acc, cnext = (T)A.c_next;
 
-    // ---- prologue: rows i0-2 .. i0+1
+    // march direction: +1 for even segments, -1 for odd ones
+    const bool dn = (seg & 1) != 0;
+    const int D = dn ? -1 : 1;
+    const int ifirst = dn ? i1 - 1 : i0;              // first output row of the march
+    const int len = i1 - i0;
+
+    // ---- prologue: the four rows around the first output row
     {
         T v[4][W], h[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) load_row(i0 - 2 + q, v[q], h[q]);
+        for (int q = 0; q < 4; ++q) load_row(ifirst + D * (q - 2), v[q], h[q]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) store_row(i0 - 2 + q, v[q], h[q]);
+        for (int q = 0; q < 4; ++q) store_row(ifirst + D * (q - 2), v[q], h[q]);
     }
     for (int q = t; q < i1 - i0 + 2; q += NT) aseg[q] = av[wrapi(i0 - 1 + q, nx)];
     for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
     __syncthreads();
 
+    // x-flux on the face behind the first row, v-face averages of the row
+    // behind and of the first row
     T gx_old[W];
     {
         T Fx[W + 2];
-        fx_cols(i0 - 1, Fx);
+        fx_cols(dn ? i1 - 1 : i0 - 1, Fx);
 #pragma unroll
         for (int w = 0; w < W; ++w) gx_old[w] = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
     }
-    T fvA[W + 1], fvB[W + 1];
-    fv_faces(i0 - 1, fvA);
-    fv_faces(i0, fvB);
+    T fvP[W + 1], fvB[W + 1];
+    fv_faces(ifirst - D, fvP);
+    fv_faces(ifirst, fvB);
 
 #pragma unroll 1
-    for (int ib = i0; ib < i1; ib += RB) {
-        // issue every load of the batch; indices past the segment are clamped
+    for (int mb = 0; mb < len; mb += RB) {
+        // issue every load of the batch; rows past the segment are clamped
         // so that all loads and their uses are unconditional
         T v[RB][W], h[RB], fnv[RB][W], accv[RB][W];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            load_row(min(ib + 2 + q, i1 + 1), v[q], h[q]);      // new stage-state row
-            const size_t off = (size_t)min(ib + q, i1 - 1) * nv + jld;
+            const int rn = ifirst + D * (mb + q + 2);                      // new stage-state row
+            load_row(dn ? max(rn, i0 - 2) : min(rn, i1 + 1), v[q], h[q]);
+            const int ro = ifirst + D * min(mb + q, len - 1);              // row being updated
+            const size_t off = (size_t)ro * nv + jld;
             if (KIND == kStage23) VecIO<T, W>::ld(fn + off, fnv[q]);
             if (KIND == kStage23 || KIND == kStage4) VecIO<T, W>::ld(acc + off, accv[q]);
         }
         __syncthreads();                              // previous batch done reading its ring rows
 #pragma unroll
-        for (int q = 0; q < RB; ++q) store_row(ib + 2 + q, v[q], h[q]);
+        for (int q = 0; q < RB; ++q) store_row(ifirst + D * (mb + q + 2), v[q], h[q]);
         __syncthreads();
 
         // compute the batch (rows past the segment are computed and dropped);
@@ -217,26 +232,33 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
         T o1[RB][W], o2[RB][W];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            const int i = ib + q;
+            const int i = ifirst + D * (mb + q);
             const int qa = i - i0;
-            const T a_m1 = (T)aseg[qa], a_0 = (T)aseg[qa + 1], a_p1 = (T)aseg[qa + 2];
+            const int qc = max(qa, 0);                // rows past a downward segment are dropped
+            const T a_m1 = (T)aseg[qc], a_0 = (T)aseg[qc + 1], a_p1 = (T)aseg[qc + 2];
             T Fx[W + 2];
-            fx_cols(i, Fx);
-            T fvC[W + 1];
-            fv_faces(i + 1, fvC);
+            fx_cols(dn ? i - 1 : i, Fx);              // the face ahead of row i
+            T fvN[W + 1];
+            fv_faces(i + D, fvN);                     // the row ahead
             const T da48 = (a_p1 - a_m1) * T(1.0 / 48.0);
             T gv[W + 1];
 #pragma unroll
-            for (int m = 0; m <= W; ++m) gv[m] = a_0 * fvB[m] + da48 * (fvC[m] - fvA[m]);
+            for (int m = 0; m <= W; ++m) {
+                const T fa = dn ? fvN[m] : fvP[m];    // row i - 1
+                const T fc = dn ? fvP[m] : fvN[m];    // row i + 1
+                gv[m] = a_0 * fvB[m] + da48 * (fc - fa);
+            }
             T kk[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 const T gx_new = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
-                kk[w] = -(gx_new - gx_old[w]) * dxi - (gv[w + 1] - gv[w]) * dvi;
+                const T ghi = dn ? gx_old[w] : gx_new;   // face i + 1/2
+                const T glo = dn ? gx_new : gx_old[w];   // face i - 1/2
+                kk[w] = -(ghi - glo) * dxi - (gv[w + 1] - gv[w]) * dvi;
                 gx_old[w] = gx_new;
             }
 #pragma unroll
-            for (int m = 0; m <= W; ++m) { fvA[m] = fvB[m]; fvB[m] = fvC[m]; }
+            for (int m = 0; m <= W; ++m) { fvP[m] = fvB[m]; fvB[m] = fvN[m]; }
 
             if (KIND == kRhs) {
 #pragma unroll
@@ -267,14 +289,14 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
                     for (int w = 0; w < W; ++w) sm += (double)o2[q][w];
                 }
                 sm = wave_sum(sm);
-                if (lane == 0 && i < i1) mom[wave][qa] = sm;
+                if (lane == 0 && mb + q < len) mom[wave][qa] = sm;
             }
         }
         if (own_in) {
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
-                const int i = ib + q;
-                if (i < i1) {
+                if (mb + q < len) {
+                    const int i = ifirst + D * (mb + q);
                     const size_t rowoff = (size_t)i * nv + jt;
                     if (KIND == kRhs) {
                         VecIO<T, W>::st(fout + rowoff, o1[q]);
