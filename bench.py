@@ -44,22 +44,27 @@ def parse():
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--amr-only", action="store_true", help="run only the two-level section (for profiling)")
     ap.add_argument("--no-4d", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape of the main workload")
+    ap.add_argument("--tile-shape", default=None, metavar="T,W,R",
+                    help="use this tile shape (threads, cells per thread, rows) instead of autotuning")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three device-to-device copies of MIB MiB (reference for HBM traffic counters)")
     ap.add_argument("--4d-only", dest="fourd_only", action="store_true", help="run only the 2D+2V section")
     return ap.parse_args()
 
 
-def read_traffic(n, dtype):
+def read_traffic(n, dtype, shape):
     """HBM bytes per stage launch from the committed counter summary, when it
-    covers this workload (a line `traffic: n=<n> dtype=<dtype> bytes_per_launch=<B>`)."""
-    if not os.path.exists(TRAFFIC_FILE):
+    covers this workload and tile shape (lines
+    `traffic: n=<n> dtype=<dtype> shape=<T>x<W>x<R> bytes_per_launch=<B>`)."""
+    if not os.path.exists(TRAFFIC_FILE) or shape is None:
         return None
+    want = "x".join(str(v) for v in shape)
     with open(TRAFFIC_FILE) as fh:
         for line in fh:
             if line.startswith("traffic:"):
                 kv = dict(item.split("=") for item in line.split()[1:])
-                if int(kv["n"]) == n and kv["dtype"] == dtype:
+                if int(kv["n"]) == n and kv["dtype"] == dtype and kv.get("shape") == want:
                     return float(kv["bytes_per_launch"])
     return None
 
@@ -291,6 +296,14 @@ def main():
     f = f0.clone()
     a = vp.field_of(plan, f)
     cells = n * n
+    shapes = plan.tile_shapes()
+    if args.tile_shape:
+        shape = tuple(int(x) for x in args.tile_shape.split(","))
+        plan.set_tile_shape(shapes.index(shape))
+    elif not args.no_autotune:
+        _, shape, _ = plan.autotune(f, a, dt, reps=5)     # on copies of (f, a); picks the tile shape
+    else:
+        shape = None
 
     for _ in range(args.warmup):
         vp.rk4_step(plan, f, a, dt)
@@ -320,7 +333,7 @@ def main():
         avg_ms = st_ms / st_n
         bytes_launch = bytes_step / 4.0
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-        traffic = read_traffic(n, args.dtype)
+        traffic = read_traffic(n, args.dtype, shape)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "k_stage1d (4 launches per RK4 step)", "avg_launch_us": round(avg_ms * 1e3, 2),
@@ -349,7 +362,9 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": f"two-stream 1D+1V Vlasov-Poisson, uniform {n}x{n} cells, RK4, "
-                               f"x in [0,10pi), v in [-8,8], dt={dt}", "cells": cells, "dt": dt},
+                               f"x in [0,10pi), v in [-8,8], dt={dt}", "cells": cells, "dt": dt,
+                   "tile_shape": None if shape is None else {"threads": shape[0], "cells_per_thread": shape[1],
+                                                             "rows": shape[2]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "adjoint": adj,
