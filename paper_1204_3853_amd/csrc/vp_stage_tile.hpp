@@ -37,35 +37,61 @@ __device__ __forceinline__ T ghost_val(const T* __restrict__ row, int j, int nv,
     return (T)0;
 }
 
+// W consecutive elements per thread.  ld/st are ordinary accesses; ldn/stn
+// are non-temporal (streamed data read or written once per launch).
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
 template <typename T, int W> struct VecIO;
 template <> struct VecIO<double, 1> {
     static __device__ __forceinline__ void ld(const double* p, double* o) { o[0] = p[0]; }
     static __device__ __forceinline__ void st(double* p, const double* o) { p[0] = o[0]; }
+    static __device__ __forceinline__ void ldn(const double* p, double* o) { o[0] = __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ void stn(double* p, const double* o) { __builtin_nontemporal_store(o[0], p); }
 };
 template <> struct VecIO<double, 2> {
     static __device__ __forceinline__ void ld(const double* p, double* o)
     {
-        double2 v = *reinterpret_cast<const double2*>(p);
+        const vd2 v = *reinterpret_cast<const vd2*>(p);
         o[0] = v.x; o[1] = v.y;
     }
     static __device__ __forceinline__ void st(double* p, const double* o)
     {
-        *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
+        *reinterpret_cast<vd2*>(p) = vd2{o[0], o[1]};
+    }
+    static __device__ __forceinline__ void ldn(const double* p, double* o)
+    {
+        const vd2 v = __builtin_nontemporal_load(reinterpret_cast<const vd2*>(p));
+        o[0] = v.x; o[1] = v.y;
+    }
+    static __device__ __forceinline__ void stn(double* p, const double* o)
+    {
+        __builtin_nontemporal_store(vd2{o[0], o[1]}, reinterpret_cast<vd2*>(p));
     }
 };
 template <> struct VecIO<float, 1> {
     static __device__ __forceinline__ void ld(const float* p, float* o) { o[0] = p[0]; }
     static __device__ __forceinline__ void st(float* p, const float* o) { p[0] = o[0]; }
+    static __device__ __forceinline__ void ldn(const float* p, float* o) { o[0] = __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ void stn(float* p, const float* o) { __builtin_nontemporal_store(o[0], p); }
 };
 template <> struct VecIO<float, 4> {
     static __device__ __forceinline__ void ld(const float* p, float* o)
     {
-        float4 v = *reinterpret_cast<const float4*>(p);
+        const vf4 v = *reinterpret_cast<const vf4*>(p);
         o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
     }
     static __device__ __forceinline__ void st(float* p, const float* o)
     {
-        *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<vf4*>(p) = vf4{o[0], o[1], o[2], o[3]};
+    }
+    static __device__ __forceinline__ void ldn(const float* p, float* o)
+    {
+        const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(p));
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    }
+    static __device__ __forceinline__ void stn(float* p, const float* o)
+    {
+        __builtin_nontemporal_store(vf4{o[0], o[1], o[2], o[3]}, reinterpret_cast<vf4*>(p));
     }
 };
 
@@ -219,8 +245,8 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
             load_row(dn ? max(rn, i0 - 2) : min(rn, i1 + 1), v[q], h[q]);
             const int ro = ifirst + D * min(mb + q, len - 1);              // row being updated
             const size_t off = (size_t)ro * nv + jld;
-            if (KIND == kStage23) VecIO<T, W>::ld(fn + off, fnv[q]);
-            if (KIND == kStage23 || KIND == kStage4) VecIO<T, W>::ld(acc + off, accv[q]);
+            if (KIND == kStage23) VecIO<T, W>::ldn(fn + off, fnv[q]);
+            if (KIND == kStage23 || KIND == kStage4) VecIO<T, W>::ldn(acc + off, accv[q]);
         }
         __syncthreads();                              // previous batch done reading its ring rows
 #pragma unroll
@@ -299,12 +325,12 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
                     const int i = ifirst + D * (mb + q);
                     const size_t rowoff = (size_t)i * nv + jt;
                     if (KIND == kRhs) {
-                        VecIO<T, W>::st(fout + rowoff, o1[q]);
+                        VecIO<T, W>::stn(fout + rowoff, o1[q]);
                     } else if (KIND == kStage4) {
-                        VecIO<T, W>::st(fout + rowoff, o2[q]);
+                        VecIO<T, W>::stn(fout + rowoff, o2[q]);
                     } else {
-                        VecIO<T, W>::st(acc + rowoff, o1[q]);
-                        VecIO<T, W>::st(fout + rowoff, o2[q]);
+                        VecIO<T, W>::stn(acc + rowoff, o1[q]);
+                        VecIO<T, W>::stn(fout + rowoff, o2[q]);
                     }
                 }
             }
