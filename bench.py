@@ -202,6 +202,20 @@ def amr_bench(steps=100, warmup=3):
     torch.cuda.synchronize()
     ms_graph = st.elapsed_time(sp) / steps
 
+    # reduction alone, Sub-Patch (Alg. spreduce) vs Mask (Alg. mreduce)
+    red = {}
+    for name, alg in (("sub_patch", vp.REDUCE_SUBPATCH), ("mask", vp.REDUCE_MASK)):
+        plan.set_reduction(alg)
+        n_out = vp.reduce_moment(plan, f)
+        plan.timing_enable(True)
+        for _ in range(200):
+            vp.reduce_moment(plan, f, n_out)
+        torch.cuda.synchronize()
+        t = plan.timing_read()["moment"]
+        plan.timing_enable(False)
+        red[name] = round(t[0] / t[1] * 1e3, 2)
+    plan.set_reduction(vp.REDUCE_SUBPATCH)
+
     cells = plan.state_elems
     stage_ms, stage_n = tm["stage"]
     stage_us = stage_ms / stage_n * 1e3
@@ -219,7 +233,9 @@ def amr_bench(steps=100, warmup=3):
             "cell_updates_per_s_graph": cells / (ms_graph * 1e-3),
             "stage_kernel": {"avg_launch_us": round(stage_us, 2), "algorithmic_bytes_per_launch": bytes_launch,
                              "achieved_GBs": round(bytes_launch / (stage_us * 1e-6) / 1e9, 1)},
-            "us_per_launch_by_class": per_launch}
+            "us_per_launch_by_class": per_launch,
+            "reduction_us": {"sub_patch": red["sub_patch"], "mask": red["mask"],
+                             "sub_patch_over_mask": round(red["sub_patch"] / red["mask"], 3)}}
 
 
 def fourd_bench(steps=50, warmup=3):

@@ -165,6 +165,23 @@ vp_status vp_reduce_moment(const vp_plan* plan, const void* f, double* n, void* 
                            hipStream_t stream);
 
 /*
+ * Reduction algorithm of a two-level plan (section 3):
+ *   VP_REDUCE_SUBPATCH  Sub-Patch reduction (Alg. spreduce, default): the
+ *                       uncovered coarse region is split into rectangles
+ *                       (Alg. subdiv), each grown by two columns in x,
+ *                       summed over its velocity range and refined in x
+ *   VP_REDUCE_MASK      Mask reduction (Alg. mreduce): every coarse row is
+ *                       refined in x, masked by the coverage of the target
+ *                       column and summed over velocity
+ * Both give the same n up to rounding; they differ in cost.  No effect on
+ * single-level plans.  Not safe to call while calls on the plan are being
+ * enqueued.
+ */
+#define VP_REDUCE_SUBPATCH 0
+#define VP_REDUCE_MASK 1
+vp_status vp_reduction_set(vp_plan* plan, int32_t algorithm);
+
+/*
  * Periodic fourth-order Poisson problem of section 2 (discrete potential
  * equation, read with 12 dx^2 on the right-hand side) for rho = 1 - n,
  * with the null space projected out (sum rho = 0, zero-mean phi), and the

@@ -152,18 +152,31 @@ hipError_t launch_stage_all(const vp_plan* p, int kind, const AmrArgs& A, hipStr
     return e;
 }
 
+// velocity moment on the finest configuration mesh, by the plan's reduction algorithm
+hipError_t reduce_launch(const AmrPlan& M, const double* f, double* n, void* work, hipStream_t stream)
+{
+    if (M.reduce_mode == VP_REDUCE_MASK) {
+        double* sm = reinterpret_cast<double*>(wsp(work, M.ws_slots_m));
+        hipError_t e = launch_amr_mask_rows(f, M.d_mask, M.ncx, M.ncv, sm, stream);
+        if (e != hipSuccess) return e;
+        e = launch_amr_rowsum(f, M.d_task_off + M.fine_task0, M.d_task_len + M.fine_task0, M.ntasks - M.fine_task0,
+                              sm + 5 * M.ncx, stream);
+        if (e != hipSuccess) return e;
+        return launch_amr_reduce_finalize(sm, M.d_rowptr_m, M.d_idx_m, M.d_w_m, M.nfx, n, stream);
+    }
+    double* slots = reinterpret_cast<double*>(wsp(work, M.ws_slots));
+    hipError_t e = launch_amr_rowsum(f, M.d_task_off, M.d_task_len, M.ntasks, slots, stream);
+    if (e != hipSuccess) return e;
+    return launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.nfx, n, stream);
+}
+
 // reduction -> Poisson on the finest configuration mesh -> injection
 vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, hipStream_t stream)
 {
     const AmrPlan& M = *p->amr;
-    double* slots = reinterpret_cast<double*>(wsp(work, M.ws_slots));
     double* n = reinterpret_cast<double*>(wsp(work, M.ws_n));
     double* E = reinterpret_cast<double*>(wsp(work, M.ws_E));
-    VP_HIP(timed(p, kTMoment, stream, [&] {
-        hipError_t e = launch_amr_rowsum(f, M.d_task_off, M.d_task_len, M.ntasks, slots, stream);
-        if (e != hipSuccess) return e;
-        return launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.nfx, n, stream);
-    }));
+    VP_HIP(timed(p, kTMoment, stream, [&] { return reduce_launch(M, f, n, work, stream); }));
     VP_HIP(timed(p, kTField, stream, [&] {
         return launch_poisson1d(nullptr, 0, n, M.dvf, M.nfx, M.dxf, p->pb.qm, p->d_green, p->gk, nullptr, nullptr, E,
                                 nullptr, stream);
@@ -359,6 +372,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
         }
     }
     M->ntasks = (int)task_off.size();
+    M->fine_task0 = fine_base.empty() ? M->ntasks : fine_base[0];
     const std::vector<double> B = interp_table(R);
     std::vector<int> rowptr{0}, idx;
     std::vector<double> w;
@@ -378,6 +392,26 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
             w.push_back(M->dvf);
         }
         rowptr.push_back((int)idx.size());
+    }
+
+    // ---- Mask reduction lists: the masked, x-refined coarse sums S[i][a] and the fine row sums
+    std::vector<unsigned char> mask((size_t)ncx * ncv);
+    for (size_t c = 0; c < mask.size(); ++c) mask[c] = owner[c] >= 0 ? 1 : 0;
+    std::vector<int> rowptr_m{0}, idx_m;
+    std::vector<double> w_m;
+    for (int I = 0; I < M->nfx; ++I) {
+        const int i = I / R, s = I % R;
+        for (int a = -2; a <= 2; ++a) {
+            idx_m.push_back(i * 5 + a + 2);
+            w_m.push_back(B[s * 5 + a + 2] * M->dvc);
+        }
+        for (size_t q = 0; q < M->patches.size(); ++q) {
+            const AmrPatch& P = M->patches[q];
+            if (I < P.gx0 || I >= P.gx0 + P.nx) continue;
+            idx_m.push_back(5 * ncx + (fine_base[q] - M->fine_task0) + (I - P.gx0));
+            w_m.push_back(M->dvf);
+        }
+        rowptr_m.push_back((int)idx_m.size());
     }
 
     // ---- device tables
@@ -401,6 +435,10 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     VP_HIP(upload(&M->d_cov_cell, cov_cell));
     VP_HIP(upload(&M->d_cov_fine, cov_fine));
     VP_HIP(upload(&M->d_cov_nv, cov_nv));
+    VP_HIP(upload(&M->d_mask, mask));
+    VP_HIP(upload(&M->d_rowptr_m, rowptr_m));
+    VP_HIP(upload(&M->d_idx_m, idx_m));
+    VP_HIP(upload(&M->d_w_m, w_m));
 
     // ---- workspace: acc, two predictors, accumulated face fluxes, reduction slots, n, E
     const size_t sb = align256(M->total * sizeof(double));
@@ -411,6 +449,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->ws_cf = o; o += align256(std::max<size_t>(M->faces.size(), 1) * sizeof(double));
     M->ws_ff = o; o += align256(std::max<size_t>(M->fflux, 1) * sizeof(double));
     M->ws_slots = o; o += align256(std::max(M->ntasks, 1) * sizeof(double));
+    M->ws_slots_m = o; o += align256((size_t)(5 * ncx + (M->ntasks - M->fine_task0)) * sizeof(double));
     M->ws_n = o; o += align256((size_t)M->nfx * sizeof(double));
     M->ws_E = o; o += align256((size_t)M->nfx * sizeof(double));
     p->ws_total = o;
@@ -424,7 +463,7 @@ void amr_destroy(vp_plan* p)
     if (!M) return;
     void* ptrs[] = {M->d_patches, M->d_tiles, M->d_faces, M->d_B, M->d_task_off, M->d_task_len, M->d_rowptr,
                     M->d_idx, M->d_w, M->d_corr_ptr, M->d_corr_face, M->d_corr_cell, M->d_cov_cell,
-                    M->d_cov_fine, M->d_cov_nv};
+                    M->d_cov_fine, M->d_cov_nv, M->d_mask, M->d_rowptr_m, M->d_idx_m, M->d_w_m};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete M;
@@ -441,13 +480,7 @@ vp_status amr_rhs(const vp_plan* p, const void* f, const double* a, void* k, hip
 vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream)
 {
     const AmrPlan& M = *p->amr;
-    double* slots = reinterpret_cast<double*>(wsp(work, M.ws_slots));
-    VP_HIP(timed(p, kTMoment, stream, [&] {
-        hipError_t e = launch_amr_rowsum(static_cast<const double*>(f), M.d_task_off, M.d_task_len, M.ntasks,
-                                         slots, stream);
-        if (e != hipSuccess) return e;
-        return launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.nfx, n, stream);
-    }));
+    VP_HIP(timed(p, kTMoment, stream, [&] { return reduce_launch(M, static_cast<const double*>(f), n, work, stream); }));
     return VP_OK;
 }
 

@@ -357,6 +357,15 @@ vp_status vp_tile_shape_set(vp_plan* p, int32_t index)
     return VP_OK;
 }
 
+vp_status vp_reduction_set(vp_plan* p, int32_t algorithm)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (algorithm != VP_REDUCE_SUBPATCH && algorithm != VP_REDUCE_MASK)
+        return fail(VP_EINVAL, "vp_reduction_set: unknown algorithm");
+    if (p->amr) p->amr->reduce_mode = algorithm;
+    return VP_OK;
+}
+
 vp_status vp_launch_mode_set(vp_plan* p, int32_t mode)
 {
     if (vp_status s = check_plan(p)) return s;

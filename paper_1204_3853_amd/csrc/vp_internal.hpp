@@ -173,6 +173,9 @@ hipError_t launch_amr_rowsum(const double* f, const long long* task_off, const i
                              double* slots, hipStream_t stream);
 hipError_t launch_amr_reduce_finalize(const double* slots, const int* rowptr, const int* idx, const double* w,
                                       int nfx, double* n, hipStream_t stream);
+// Mask reduction: S[i * 5 + a + 2] = sum over uncovered (i, j) of f_coarse(i + a, j)
+hipError_t launch_amr_mask_rows(const double* f, const unsigned char* covered, int ncx, int ncv, double* S,
+                                hipStream_t stream);
 hipError_t launch_amr_inject(const double* E, int ncx, int R, double qm, double* a, hipStream_t stream);
 // end of step: coarse cells next to coarse-fine faces take the fine
 // accumulated fluxes; covered coarse cells take the mean of their fine cells
@@ -243,6 +246,14 @@ struct AmrPlan {
     long long* d_cov_fine = nullptr;
     int* d_cov_nv = nullptr;
     int nsub = 0;                                    // sub-patches of the coarse level (Alg. subdiv)
+    // Mask reduction (Alg. mreduce): coverage mask, fixed-order lists over [S (5 ncx) | fine row sums]
+    int reduce_mode = 0;                             // VP_REDUCE_SUBPATCH or VP_REDUCE_MASK
+    int fine_task0 = 0;                              // first fine-row task in the task list
+    unsigned char* d_mask = nullptr;
+    int* d_rowptr_m = nullptr;
+    int* d_idx_m = nullptr;
+    double* d_w_m = nullptr;
+    size_t ws_slots_m = 0;
     // workspace offsets
     size_t ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0;
 };

@@ -88,8 +88,8 @@ __global__ __launch_bounds__(256) void k_stage4d(Stage4DArgs A)
 #pragma unroll
         for (int q = 0; q < 9; ++q) Lb[s][q] = fs[po[q] + o];
         const size_t oo = po[0] + (size_t)min(max(p - 2, 0), nvx - 1) * nvy + vyl;
-        if (KIND == kStage23) FNb[s] = A.fn[oo];
-        if (KIND == kStage23 || KIND == kStage4) ACb[s] = A.acc[oo];
+        if (KIND == kStage23) FNb[s] = __builtin_nontemporal_load(A.fn + oo);
+        if (KIND == kStage23 || KIND == kStage4) ACb[s] = __builtin_nontemporal_load(A.acc + oo);
     };
 
     // rolling state along vx: V at t-1 .. t+2, U, f and Dx at t-1/t .. t+2, Dy at t .. t+2
@@ -153,17 +153,23 @@ __global__ __launch_bounds__(256) void k_stage4d(Stage4DArgs A)
             double out;
             if (KIND == kRhs) {
                 out = k;
-                if (act) A.fout[o] = out;
+                if (act) __builtin_nontemporal_store(out, A.fout + o);
             } else if (KIND == kStage1) {
                 const double f0 = cw[0];
                 out = f0 + cnext * k;
-                if (act) { A.acc[o] = f0 + cacc * k; A.fout[o] = out; }
+                if (act) {
+                    __builtin_nontemporal_store(f0 + cacc * k, A.acc + o);
+                    __builtin_nontemporal_store(out, A.fout + o);
+                }
             } else if (KIND == kStage23) {
                 out = FNb[s] + cnext * k;
-                if (act) { A.acc[o] = ACb[s] + cacc * k; A.fout[o] = out; }
+                if (act) {
+                    __builtin_nontemporal_store(ACb[s] + cacc * k, A.acc + o);
+                    __builtin_nontemporal_store(out, A.fout + o);
+                }
             } else {
                 out = ACb[s] + cacc * k;
-                if (act) A.fout[o] = out;
+                if (act) __builtin_nontemporal_store(out, A.fout + o);
             }
             if (act) msum += out;
         }

@@ -365,6 +365,26 @@ __global__ __launch_bounds__(256) void k_amr_rowsum(const double* __restrict__ f
     if (lane == 0) slots[task] = s;
 }
 
+// Mask reduction rows (Alg. mreduce): the coarse level is refined in x
+// before it is masked, so the sum for target column i of the x-stencil
+// offset a runs over row i + a with the coverage mask of column i.  One
+// wave per (i, a).
+__global__ __launch_bounds__(256) void k_amr_mask_rows(const double* __restrict__ f,
+                                                      const unsigned char* __restrict__ covered, int ncx, int ncv,
+                                                      double* __restrict__ S)
+{
+    const int task = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (task >= 5 * ncx) return;         // uniform per wave
+    const int i = task / 5, a = task - (task / 5) * 5 - 2;
+    const double* row = f + (size_t)wrapi(i + a, ncx) * ncv;
+    const unsigned char* m = covered + (size_t)i * ncv;
+    double s = 0.0;
+    for (int j = lane; j < ncv; j += 64) s += m[j] ? 0.0 : row[j];
+    s = wave_sum(s);
+    if (lane == 0) S[task] = s;
+}
+
 // n_I = sum_k w_k slots[idx_k] over the fixed-order list of cell I
 __global__ __launch_bounds__(256) void k_amr_reduce_finalize(const double* __restrict__ slots,
                                                             const int* __restrict__ rowptr,
@@ -463,6 +483,13 @@ hipError_t launch_amr_reduce_finalize(const double* slots, const int* rowptr, co
 {
     hipLaunchKernelGGL(k_amr_reduce_finalize, dim3((nfx + 255) / 256), dim3(256), 0, stream, slots, rowptr, idx,
                        w, nfx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_mask_rows(const double* f, const unsigned char* covered, int ncx, int ncv, double* S,
+                                hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_amr_mask_rows, dim3((5 * ncx + 3) / 4), dim3(256), 0, stream, f, covered, ncx, ncv, S);
     return hipGetLastError();
 }
 

@@ -94,6 +94,21 @@ def test_reduce_matches_mask_reduction(vp, case):
     cmp(n, case.o.reduce_mask(case.f0), 1e-13, "moment")
 
 
+def test_mask_reduction(vp, case):
+    """Alg. mreduce on the GPU: the same n as the oracle's Mask reduction and
+    as the GPU Sub-Patch reduction, to rounding."""
+    f = case.gpu(case.f0)
+    n_sp = vp.reduce_moment(case.plan, f).cpu().numpy()
+    case.plan.set_reduction(vp.REDUCE_MASK)
+    try:
+        n_m = vp.reduce_moment(case.plan, f)
+    finally:
+        case.plan.set_reduction(vp.REDUCE_SUBPATCH)
+    want = case.o.reduce_mask(case.f0)
+    cmp(n_m, want, 1e-13, "mask n")
+    cmp(n_m, n_sp, 1e-13, "mask vs sub-patch")
+
+
 def test_constraints(vp, case):
     f = case.gpu(case.f0)
     a = vp.field_of(case.plan, f)
@@ -162,6 +177,17 @@ def test_full_config_one_step(vp, full):
     cmp(a, a_o, 1e-11, "a")
     vp.rk4_step(full.plan, f, a, full.dt)
     cmp(f, full.o.step(full.f0, full.dt), rel_tol(), "step")
+
+
+def test_full_config_step_with_mask_reduction(vp, full):
+    full.plan.set_reduction(vp.REDUCE_MASK)
+    try:
+        f = full.gpu(full.f0)
+        a = vp.field_of(full.plan, f)
+        vp.rk4_step(full.plan, f, a, full.dt)
+    finally:
+        full.plan.set_reduction(vp.REDUCE_SUBPATCH)
+    cmp(f, full.o.step(full.f0, full.dt), rel_tol(), "step (mask reduction)")
 
 
 def test_full_config_persistent_equals_per_patch(vp, full):
