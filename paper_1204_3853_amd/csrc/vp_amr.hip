@@ -170,18 +170,18 @@ hipError_t reduce_launch(const AmrPlan& M, const double* f, double* n, void* wor
     return launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.nfx, n, stream);
 }
 
-// reduction -> Poisson on the finest configuration mesh -> injection
+// reduction -> Poisson on the finest configuration mesh -> injection (the
+// Poisson block also injects the field onto both levels)
 vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, hipStream_t stream)
 {
     const AmrPlan& M = *p->amr;
     double* n = reinterpret_cast<double*>(wsp(work, M.ws_n));
     double* E = reinterpret_cast<double*>(wsp(work, M.ws_E));
     VP_HIP(timed(p, kTMoment, stream, [&] { return reduce_launch(M, f, n, work, stream); }));
+    const PoissonExtra X{nullptr, nullptr, nullptr, nullptr, M.R};
     VP_HIP(timed(p, kTField, stream, [&] {
-        return launch_poisson1d(nullptr, 0, n, M.dvf, M.nfx, M.dxf, p->pb.qm, p->d_green, p->gk, nullptr, nullptr, E,
-                                nullptr, stream);
+        return launch_poisson1d_inject(n, X, M.nfx, M.dxf, p->pb.qm, p->d_green, p->gk, E, a, stream);
     }));
-    VP_HIP(timed(p, kTOther, stream, [&] { return launch_amr_inject(E, M.ncx, M.R, p->pb.qm, a, stream); }));
     return VP_OK;
 }
 

@@ -137,6 +137,17 @@ struct AmrArgs {
     int first;                 // first stage: store instead of add
 };
 
+// Optional inputs and outputs of the 1D Poisson kernel for two-level plans:
+// the moment taken from a fixed-order weighted list over row-sum slots, and
+// the injection onto both levels.
+struct PoissonExtra {
+    const double* slots;       // null: the kernel reads n
+    const int* rowptr;
+    const int* idx;
+    const double* w;
+    int inject_R;              // > 0: a = [(q/m) mean of R fine E per coarse cell][(q/m) E]
+};
+
 // Launchers (defined in vp_kernels_1d.hip).
 hipError_t launch_stage1d(int dtype, const StageShape& sh, int kind, const Stage1DArgs& args,
                           hipStream_t stream);
@@ -156,6 +167,10 @@ hipError_t launch_adjoint_stage1d(int w, bool first, const Adjoint1DArgs& a, hip
 hipError_t launch_adjoint_final(const double* mu, const double* g, const double* z, int nx, int nv, double* out,
                                 hipStream_t stream);
 hipError_t launch_scale(const double* x, double s, double* y, int n, hipStream_t stream);
+// Poisson, field and two-level injection in one launch; the moment is n_in,
+// or is finalised from the weighted list of x when x.slots is set
+hipError_t launch_poisson1d_inject(const double* n_in, const PoissonExtra& x, int nx, double dx, double qm,
+                                   const double* green, int gk, double* E, double* a, hipStream_t stream);
 hipError_t poisson1d_prepare();
 
 // 2D+2V launchers (vp_kernels_4d.hip)

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_moment_finalize(const double* __restric
 __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
     const double* __restrict__ n_in, int nx, double dx, double qm, const double* __restrict__ green, int gk,
     double* __restrict__ phi_out, double* __restrict__ E_out, double* __restrict__ a_out, int adjoint,
-    double phi_scale)
+    double phi_scale, PoissonExtra X)
 {
     constexpr int K = kGreenTaps;
     constexpr int SUB = 8;               // outputs per register window of the convolution
@@ -150,10 +150,25 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
     {
         constexpr int RM = kMaxPoisson1D / kPoissonThreads;
         double nv[RM];
+        if (X.slots) {
+            // n_i = sum_k w_k slots[idx_k] over the fixed-order list of cell i
 #pragma unroll
-        for (int m = 0; m < RM; ++m) {
-            const int i = t + m * kPoissonThreads;
-            nv[m] = i < nx ? n_in[i] : 0.0;
+            for (int m = 0; m < RM; ++m) {
+                const int i = t + m * kPoissonThreads;
+                double sacc = 0.0;
+                if (i < nx) {
+                    const int k0 = X.rowptr[i], k1 = X.rowptr[i + 1];
+#pragma unroll 4
+                    for (int k = k0; k < k1; ++k) sacc += X.w[k] * X.slots[X.idx[k]];
+                }
+                nv[m] = sacc;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < RM; ++m) {
+                const int i = t + m * kPoissonThreads;
+                nv[m] = i < nx ? n_in[i] : 0.0;
+            }
         }
         if (!adjoint) {
 #pragma unroll
@@ -246,7 +261,23 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
         const double E = -(7.0 * (dext[dp(i)] + dext[dp(i - 1)]) - dext[dp(i + 1)] - dext[dp(i - 2)]) /
                          (12.0 * dx);
         if (E_out) E_out[i] = E;
-        if (a_out) a_out[i] = qm * E;
+        if (X.inject_R > 0) {
+            ybuf[pad(i)] = E;
+            a_out[nx / X.inject_R + i] = qm * E;
+        } else if (a_out) {
+            a_out[i] = qm * E;
+        }
+    }
+    if (X.inject_R > 0) {
+        // two levels: the coarse acceleration is (q/m) times the mean of the R fine values
+        __syncthreads();
+        const int R = X.inject_R;
+        for (int k = t; k < nx / R; k += kPoissonThreads) {
+            double se = 0.0;
+            for (int q = 0; q < R; ++q) se += ybuf[pad(k * R + q)];
+            a_out[k] = qm * (se / R);
+        }
+        return;      // phi is not requested with injection
     }
     if (phi_out) {
         // phi_i = sum_{m < i} d_m + const, zero mean
@@ -349,7 +380,17 @@ hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, 
     }
     const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
-                       phi, E, a, 0, 1.0);
+                       phi, E, a, 0, 1.0, PoissonExtra{});
+    return hipGetLastError();
+}
+
+hipError_t launch_poisson1d_inject(const double* n_in, const PoissonExtra& x, int nx, double dx, double qm,
+                                   const double* green, int gk, double* E, double* a, hipStream_t stream)
+{
+    if ((!x.slots && !n_in) || !a || x.inject_R < 1 || nx % x.inject_R) return hipErrorInvalidValue;
+    const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
+    hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
+                       nullptr, E, a, 0, 1.0, x);
     return hipGetLastError();
 }
 
@@ -361,7 +402,7 @@ hipError_t launch_poisson1d_adjoint(const double* part, int nstrip, int nx, doub
                            abar_out);
     const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, abar_out, nx, dx, qm, green,
-                       gk, z, nullptr, nullptr, 1, -dv);
+                       gk, z, nullptr, nullptr, 1, -dv, PoissonExtra{});
     return hipGetLastError();
 }
 

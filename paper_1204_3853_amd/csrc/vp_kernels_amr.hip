@@ -385,18 +385,23 @@ __global__ __launch_bounds__(256) void k_amr_mask_rows(const double* __restrict_
     if (lane == 0) S[task] = s;
 }
 
-// n_I = sum_k w_k slots[idx_k] over the fixed-order list of cell I
+// n_I = sum_k w_k slots[idx_k] over the list of cell I; 16 lanes per cell
+// take every 16th entry and combine in a fixed butterfly order
 __global__ __launch_bounds__(256) void k_amr_reduce_finalize(const double* __restrict__ slots,
                                                             const int* __restrict__ rowptr,
                                                             const int* __restrict__ idx,
                                                             const double* __restrict__ w, int nfx,
                                                             double* __restrict__ n)
 {
-    const int I = (int)blockIdx.x * 256 + threadIdx.x;
-    if (I >= nfx) return;
+    const int I = (int)blockIdx.x * 16 + (int)(threadIdx.x >> 4);
+    const int l = threadIdx.x & 15;
+    const int Ic = min(I, nfx - 1);                     // lanes of a cell past the end compute and drop
+    const int k0 = rowptr[Ic], k1 = rowptr[Ic + 1];
     double s = 0.0;
-    for (int k = rowptr[I]; k < rowptr[I + 1]; ++k) s += w[k] * slots[idx[k]];
-    n[I] = s;
+    for (int k = k0 + l; k < k1; k += 16) s += w[k] * slots[idx[k]];
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 16);
+    if (l == 0 && I < nfx) n[I] = s;
 }
 
 // a_c = (q/m) mean of the R fine E values over each coarse cell, a_f = (q/m) E
@@ -481,7 +486,7 @@ hipError_t launch_amr_rowsum(const double* f, const long long* task_off, const i
 hipError_t launch_amr_reduce_finalize(const double* slots, const int* rowptr, const int* idx, const double* w,
                                       int nfx, double* n, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_amr_reduce_finalize, dim3((nfx + 255) / 256), dim3(256), 0, stream, slots, rowptr, idx,
+    hipLaunchKernelGGL(k_amr_reduce_finalize, dim3((nfx + 15) / 16), dim3(256), 0, stream, slots, rowptr, idx,
                        w, nfx, n);
     return hipGetLastError();
 }
