@@ -38,28 +38,6 @@ __device__ __forceinline__ double coarse_at(const Stage1DArgs& C, const double* 
     return (j >= 0 && j < C.nv) ? x : pick_ghost(j, C.nv, g0, g1, g2, g3);
 }
 
-// level-1 cell (X, V) in the global level-1 index space, interpolated from
-// the coarse level: along x first, then along v
-__device__ __forceinline__ double interp_fine(const AmrArgs& A, int X, int V)
-{
-    const double cg0 = A.coarse.vg[0], cg1 = A.coarse.vg[1], cg2 = A.coarse.vg[2], cg3 = A.coarse.vg[3];
-    const double* fc = static_cast<const double*>(A.coarse.fs);
-    const int Vc = min(max(V, 0), A.nfv - 1);
-    const int ci = X >> A.lr, s = X & (A.R - 1);
-    const int cj = Vc >> A.lr, t = Vc & (A.R - 1);
-    double acc = 0.0;
-#pragma unroll
-    for (int b = -2; b <= 2; ++b) {
-        double gx = 0.0;
-#pragma unroll
-        for (int a = -2; a <= 2; ++a)
-            gx += A.B[s * 5 + a + 2] * coarse_at(A.coarse, fc, ci + a, cj + b, cg0, cg1, cg2, cg3);
-        acc += A.B[t * 5 + b + 2] * gx;
-    }
-    const double fg0 = A.vgf[0], fg1 = A.vgf[1], fg2 = A.vgf[2], fg3 = A.vgf[3];
-    return (V >= 0 && V < A.nfv) ? acc : pick_ghost(V, A.nfv, fg0, fg1, fg2, fg3);
-}
-
 __device__ __forceinline__ void flux_acc(double* p, double v, const AmrArgs& A)
 {
     if (A.first) *p = A.c_flux * v;
@@ -67,7 +45,8 @@ __device__ __forceinline__ void flux_acc(double* p, double v, const AmrArgs& A)
 }
 
 // Stage tile on a level-1 patch (FP64): same march and arithmetic as the
-// single-level tile; the halo cells come from interp_fine.
+// single-level tile; the halo cells are interpolated from the coarse level
+// (x then v, the sub-cell weights b_j(s) of section 3).
 template <int W, int NT, int KIND>
 __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile& tl)
 {
@@ -106,27 +85,82 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
     // Coarse-fine halo of the tile, interpolated once into LDS before the
     // march: patch rows -2, -1 (first segment) and nx, nx+1 (last segment)
     // over the tile's columns, and columns -2, -1, nv, nv+1 of its rows.
+    // For each of these (up to four) regions the coarse cells its stencils
+    // touch are first copied into an LDS window (one batch of loads, held
+    // in the ring's storage, which the march has not started using), and
+    // the interpolation then reads only LDS.
     __shared__ T hrow[4][RW];                 // rows -2, -1, nx, nx+1; column c <-> j = j0 - 2 + c
     __shared__ T hcol[kMaxTx + 4][4];         // rows i0-2 .. i1+1; columns -2, -1, nv, nv+1
+    __shared__ double bs[16 * 5];             // b_j(s), s < R
     {
+        const Stage1DArgs& C = A.coarse;
+        const double* fc = static_cast<const double*>(C.fs);
+        const double cg0 = C.vg[0], cg1 = C.vg[1], cg2 = C.vg[2], cg3 = C.vg[3];
+        const double fg0 = A.vgf[0], fg1 = A.vgf[1], fg2 = A.vgf[2], fg3 = A.vgf[3];
+        const int R = A.R, lr = A.lr;
+        for (int k = t; k < R * 5; k += NT) bs[k] = A.B[k];
+        double* win = &ring[0][0];
+        constexpr int kWinCap = NSLOT * RW;
         const bool top = i0 == 0, bot = i1 == nx;
-        const int ncols = TV + 4;
-        for (int k = t; k < 4 * ncols; k += NT) {
-            const int q = k / ncols, c = k - q * ncols;
-            if ((q < 2 && !top) || (q >= 2 && !bot)) continue;
-            const int r = q < 2 ? q - 2 : nx + (q - 2);
-            const int j = j0 - 2 + c;
-            hrow[q][c] = (j >= -2 && j <= nv + 1) ? interp_fine(A, P.gx0 + r, P.gv0 + j) : T(0);
-        }
         const bool left = j0 == 0, right = j0 + TV + 1 >= nv;
-        for (int k = t; k < 4 * (i1 - i0 + 4); k += NT) {
-            const int q = k & 3, rr = k >> 2;
-            const int r = i0 - 2 + rr;
-            if (r < 0 || r >= nx || (q < 2 && !left) || (q >= 2 && !right)) continue;
-            const int j = q < 2 ? q - 2 : nv + (q - 2);
-            hcol[rr][q] = interp_fine(A, P.gx0 + r, P.gv0 + j);
+        // fine cell (X, V) from the window with origin (wi0, wj0) and row length ww
+        auto interp_win = [&](int X, int V, int wi0, int wj0, int ww) -> T {
+            if (V < 0 || V >= A.nfv) return pick_ghost(V, A.nfv, fg0, fg1, fg2, fg3);
+            const int ci = X >> lr, sx = X & (R - 1);
+            const int cj = V >> lr, sv = V & (R - 1);
+            const double* w0 = win + (ci - 2 - wi0) * ww + (cj - 2 - wj0);
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                double gx = 0.0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) gx += bs[sx * 5 + a] * w0[a * ww + b];
+                acc += bs[sv * 5 + b] * gx;
+            }
+            return acc;
+        };
+        // copy coarse rows wi0 .. wi0+wh-1, columns wj0 .. wj0+ww-1 into the window
+        auto fill = [&](int wi0, int wj0, int wh, int ww) {
+            const int cnt = min(wh * ww, kWinCap);
+            for (int k = t; k < cnt; k += NT) {
+                const int r = k / ww, c = k - (k / ww) * ww;
+                win[k] = coarse_at(C, fc, wi0 + r, wj0 + c, cg0, cg1, cg2, cg3);
+            }
+        };
+        const int vlo = P.gv0 + j0 - 2, vhi = P.gv0 + j0 + TV + 1;
+        const int cjlo = max(min(vlo, A.nfv - 1), 0) >> lr, cjhi = max(min(vhi, A.nfv - 1), 0) >> lr;
+        __syncthreads();                      // bs visible; the ring is free
+        for (int q2 = 0; q2 < 2; ++q2) {      // top rows, then bottom rows
+            if (q2 == 0 ? !top : !bot) continue;
+            const int X0 = P.gx0 + (q2 == 0 ? -2 : nx);
+            const int wi0 = (X0 >> lr) - 2, wj0 = cjlo - 2, ww = cjhi - cjlo + 5;
+            fill(wi0, wj0, 5 + ((X0 + 1) >> lr) - (X0 >> lr), ww);
+            __syncthreads();
+            const int ncols = TV + 4;
+            for (int k = t; k < 2 * ncols; k += NT) {
+                const int q = k / ncols, c = k - q * ncols;
+                const int j = j0 - 2 + c;
+                hrow[2 * q2 + q][c] = (j >= -2 && j <= nv + 1) ? interp_win(X0 + q, P.gv0 + j, wi0, wj0, ww) : T(0);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        for (int q2 = 0; q2 < 2; ++q2) {      // left columns, then right columns
+            if (q2 == 0 ? !left : !right) continue;
+            const int rlo = max(i0 - 2, 0), rhi = min(i1 + 1, nx - 1);
+            const int V0 = P.gv0 + (q2 == 0 ? -2 : nv);
+            const int cv0 = max(min(V0, A.nfv - 1), 0) >> lr, cv1 = max(min(V0 + 1, A.nfv - 1), 0) >> lr;
+            const int wi0 = ((P.gx0 + rlo) >> lr) - 2, wj0 = cv0 - 2, ww = cv1 - cv0 + 5;
+            fill(wi0, wj0, ((P.gx0 + rhi) >> lr) - ((P.gx0 + rlo) >> lr) + 5, ww);
+            __syncthreads();
+            for (int k = t; k < 2 * (i1 - i0 + 4); k += NT) {
+                const int q = k & 1, rr = k >> 1;
+                const int r = i0 - 2 + rr;
+                if (r < 0 || r >= nx) continue;
+                const int j = q2 == 0 ? q - 2 : nv + q;
+                hcol[rr][2 * q2 + q] = interp_win(P.gx0 + r, P.gv0 + j, wi0, wj0, ww);
+            }
+            __syncthreads();
+        }
     }
     // value of a cell of the tile window that is not patch data
     auto halo_val = [&](int r, int j) -> T {
