@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["vp_oracle.c", "vp_oracle_adjoint.c", "vp_oracle_amr.c", "vp_oracle_4d.c"]
+SOURCES = ["vp_oracle.c", "vp_oracle_adjoint.c", "vp_oracle_amr.c", "vp_oracle_4d.c", "vp_oracle_limited.c"]
 LIB = os.path.join(HERE, "libvp_oracle.so")
 
 
@@ -92,6 +92,10 @@ def _declare_extra(L):
         "vpo_amr_fill_ghosts": (None, [_V, _D, _I, _D]),
         "vpo_amr_rk4_step": (None, [_V, _D, _D, _F]),
         "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
+        "vpo_face_limited": (_F, [_F, _F, _F, _F, _I]),
+        "vpo_rhs_limited": (None, [_I, _I, _F, _F, _F, _D, _D, _D, _D]),
+        "vpo_rk4_step_limited": (None, [_V, _D, _D, _F]),
+        "vpo_rk4_step_fixed_a_limited": (None, [_V, _D, _D, _D, _F]),
         "vpo4_ctx_new": (_V, [_I, _I, _I, _I, _F, _F, _F, _F, _F, _D, _D]),
         "vpo4_ctx_free": (None, [_V]),
         "vpo4_moment": (None, [_V, _D, _D]),
@@ -171,6 +175,18 @@ def vboundary_flux(f, a, dx, dv, vghost):
     return lo, hi
 
 
+def face_limited(um1, u0, u1, u2, upwind_left):
+    """limited face average between u0 and u1 (section 2, eq. limitedFace)"""
+    return lib().vpo_face_limited(float(um1), float(u0), float(u1), float(u2), int(bool(upwind_left)))
+
+
+def rhs_limited(f, a, dx, dv, v_lo, vghost):
+    f, a, vg = _f64(f), _f64(a), _f64(vghost)
+    k = np.empty_like(f)
+    lib().vpo_rhs_limited(f.shape[0], f.shape[1], dx, dv, v_lo, _p(vg), _p(f), _p(a), _p(k))
+    return k
+
+
 def rhs_adjoint(f, a, kbar, dx, dv, v_lo, vghost):
     f, a, kb, vg = _f64(f), _f64(a), _f64(kbar), _f64(vghost)
     fb = np.empty_like(f)
@@ -229,6 +245,21 @@ class Oracle1D:
         f, a = _f64(f), _f64(a)
         out = np.empty_like(f)
         lib().vpo_rk4_step_fixed_a(self.h, _p(f), _p(out), _p(a), dt)
+        return out
+
+    def rhs_limited(self, f, a):
+        return rhs_limited(f, a, self.dx, self.dv, self.v_lo, self.vghost)
+
+    def step_limited(self, f, dt):
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().vpo_rk4_step_limited(self.h, _p(f), _p(out), dt)
+        return out
+
+    def step_fixed_a_limited(self, f, a, dt):
+        f, a = _f64(f), _f64(a)
+        out = np.empty_like(f)
+        lib().vpo_rk4_step_fixed_a_limited(self.h, _p(f), _p(out), _p(a), dt)
         return out
 
     def constraints_adjoint(self, abar, fbar):

@@ -56,6 +56,13 @@ void vpo_amr_reduce_mask(void* h, double* f, double* n);
 void vpo_amr_constraints(void* h, double* f, double* a, double* E_out);
 void vpo_amr_rhs(void* h, double* f, double* a, double* k);
 
+/* limited face averages (section 2, eq. limitedFace), 1D+1V single level */
+double vpo_face_limited(double um1, double u0, double u1, double u2, int upwind_left);
+void vpo_rhs_limited(int nx, int nv, double dx, double dv, double v_lo, const double* vghost, const double* f,
+                     const double* a, double* k);
+void vpo_rk4_step_limited(const vpo_ctx* c, const double* f_in, double* f_out, double dt);
+void vpo_rk4_step_fixed_a_limited(const vpo_ctx* c, const double* f_in, double* f_out, const double* a, double dt);
+
 /* 2D+2V single level, f[x][y][vx][vy]; a and E hold the x component, then y */
 void* vpo4_ctx_new(int nx, int ny, int nvx, int nvy, double x_len, double y_len, double v_lo, double v_hi,
                    double qm, const double* veq_x, const double* veq_y);
