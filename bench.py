@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--amr-only", action="store_true", help="run only the two-level section (for profiling)")
     ap.add_argument("--no-4d", action="store_true")
+    ap.add_argument("--no-limited", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape of the main workload")
     ap.add_argument("--tile-shape", default=None, metavar="T,W,R",
                     help="use this tile shape (threads, cells per thread, rows) instead of autotuning")
@@ -127,6 +128,45 @@ def adjoint_ratio(steps=400, every=20):
     return {"workload": "Landau 1D+1V 512x512 FP64, 400 RK4 steps, checkpoint every 20, "
                         "gradient of 1/2 sum E^2 w.r.t. the 512-value initial profile",
             "forward_ms": round(fw * 1e3, 2), "backward_ms": round(bw * 1e3, 2), "ratio": round(bw / fw, 3)}
+
+
+def limited_bench(n=4096, steps=20, warmup=3):
+    """The main workload with the limited face averages (section 2, eq.
+    limitedFace): same bytes per step, more arithmetic per face."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+    p = I.two_stream(n, n)
+    dt = 4.788e-4 * (4096 / n)
+    plan = vp.Plan(p)
+    plan.set_face_scheme(vp.FACE_LIMITED)
+    f = torch.tensor(p.initial_state(), dtype=torch.float64, device="cuda")
+    a = vp.field_of(plan, f)
+    _, shape, _ = plan.autotune(f, a, dt, reps=3)
+    for _ in range(warmup):
+        vp.rk4_step(plan, f, a, dt)
+    st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    st.record()
+    for _ in range(steps):
+        vp.rk4_step(plan, f, a, dt)
+    sp.record()
+    torch.cuda.synchronize()
+    ms = st.elapsed_time(sp) / steps
+    plan.timing_enable(True)
+    for _ in range(steps):
+        vp.rk4_step(plan, f, a, dt)
+    torch.cuda.synchronize()
+    tm = plan.timing_read()
+    plan.timing_enable(False)
+    stage_us = tm["stage"][0] / tm["stage"][1] * 1e3
+    bytes_launch = 4 * 8 * n * n
+    return {"workload": f"two-stream 1D+1V {n}x{n} FP64 with limited face averages, dt={dt}",
+            "tile_shape": {"threads": shape[0], "cells_per_thread": shape[1], "rows": shape[2]},
+            "ms_per_step": round(ms, 4), "cell_updates_per_s": n * n / (ms * 1e-3),
+            "stage_kernel": {"avg_launch_us": round(stage_us, 2), "algorithmic_bytes_per_launch": bytes_launch,
+                             "achieved_GBs": round(bytes_launch / (stage_us * 1e-6) / 1e9, 1)}}
 
 
 def amr_dt(boxes, a, ncx=512, ncv=512, R=4, x_len=4 * math.pi, v_lo=-8.0, v_hi=8.0, cfl=0.5):
@@ -359,6 +399,7 @@ def main():
     adj = None if args.no_adjoint else adjoint_ratio()
     amr = None if args.no_amr else amr_bench()
     fourd = None if args.no_4d else fourd_bench()
+    limited = None if args.no_limited else limited_bench(n)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -386,6 +427,7 @@ def main():
         "adjoint": adj,
         "amr": amr,
         "2d2v": fourd,
+        "limited": limited,
     }
     print(json.dumps(out), flush=True)
 

@@ -165,6 +165,25 @@ vp_status vp_reduce_moment(const vp_plan* plan, const void* f, double* n, void* 
                            hipStream_t stream);
 
 /*
+ * Face averages of the single-level 1D+1V scheme (section 2):
+ *   VP_FACE_CENTERED  the ideal weights 1/2, 1/2: the centred fourth-order
+ *                     face average (default)
+ *   VP_FACE_LIMITED   eq. limitedFace: the left- and right-biased
+ *                     third-order candidates (eqs. thirdLeft, thirdRight)
+ *                     weighted by provisional WENO weights (Jiang-Shu
+ *                     smoothness of the two stencils, ideal weights 1/2,
+ *                     epsilon 1e-6, power 2), the larger weight given to
+ *                     the upwind candidate (x faces: sign of the column's
+ *                     velocity; v faces: sign of the row's acceleration)
+ * The limited scheme is nonlinear: vp_rk4_step_record / vp_adjoint_step
+ * return VP_ENOTSUP for it.  VP_ENOTSUP for two-level and 2D+2V plans.
+ * Not safe to call while calls on the plan are being enqueued.
+ */
+#define VP_FACE_CENTERED 0
+#define VP_FACE_LIMITED 1
+vp_status vp_face_scheme_set(vp_plan* plan, int32_t scheme);
+
+/*
  * Reduction algorithm of a two-level plan (section 3):
  *   VP_REDUCE_SUBPATCH  Sub-Patch reduction (Alg. spreduce, default): the
  *                       uncovered coarse region is split into rectangles

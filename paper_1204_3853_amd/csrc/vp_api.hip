@@ -85,6 +85,7 @@ Stage1DArgs base_args(const vp_plan* p, const StageShape& sh)
     a.v_lo = p->v_lo;
     a.dv = p->dv;
     for (int q = 0; q < 4; ++q) a.vg[q] = p->vg[q];
+    a.lim = p->face_scheme == VP_FACE_LIMITED;
     return a;
 }
 
@@ -357,6 +358,17 @@ vp_status vp_tile_shape_set(vp_plan* p, int32_t index)
     return VP_OK;
 }
 
+vp_status vp_face_scheme_set(vp_plan* p, int32_t scheme)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (scheme != VP_FACE_CENTERED && scheme != VP_FACE_LIMITED)
+        return fail(VP_EINVAL, "vp_face_scheme_set: unknown scheme");
+    if (scheme == VP_FACE_LIMITED && (p->amr || p->p4))
+        return fail(VP_ENOTSUP, "vp_face_scheme_set: limited faces are built for single-level 1D+1V plans");
+    p->face_scheme = scheme;
+    return VP_OK;
+}
+
 vp_status vp_reduction_set(vp_plan* p, int32_t algorithm)
 {
     if (vp_status s = check_plan(p)) return s;
@@ -558,6 +570,8 @@ vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, vo
     if (!f || !a || !work || !stages) return fail(VP_EINVAL, "vp_rk4_step_record: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_record: dt is not finite");
     if (p->amr || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level 1D+1V plans only");
+    if (p->face_scheme != VP_FACE_CENTERED)
+        return fail(VP_ENOTSUP, "vp_rk4_step_record: the adjoint is built for the centred (unlimited) scheme");
     double* st_a = reinterpret_cast<double*>(static_cast<char*>(stages) + 3 * p->state_elems * p->esize);
     if (reinterpret_cast<uintptr_t>(st_a) % 8) return fail(VP_EINVAL, "stage record misaligned");
     return rk4_1d(p, f, a, dt, work, stages, st_a, stream);
@@ -590,6 +604,8 @@ vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, 
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is FP64 only");
     if (p->amr || p->p4 || p->nlev != 1 || p->ndim != 1)
         return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
+    if (p->face_scheme != VP_FACE_CENTERED)
+        return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is built for the centred (unlimited) scheme");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_adjoint_step: dt is not finite");
     const size_t N = p->state_elems;
     const int nx = p->nx, nv = p->nv;

@@ -54,6 +54,7 @@ struct Stage1DArgs {
     const double* a;          // (q/m) E per x cell
     double* part;             // velocity-moment partial sums [nstrip][nx] (or null)
     double c_acc, c_next;     // dt b_s and dt alpha_{s+1}
+    int lim;                  // limited face averages (section 2) instead of the centred ones
 };
 
 enum StageKind : int { kRhs = 0, kStage1 = 1, kStage23 = 2, kStage4 = 3 };
@@ -305,6 +306,7 @@ struct vp_plan {
 
     vp::StageShape shape{128, 2, 32};
     int nstrip = 1;
+    int face_scheme = VP_FACE_CENTERED;
 
     // periodic Green's function of the tridiagonal factor of the Poisson
     // operator (device), gk taps on each side

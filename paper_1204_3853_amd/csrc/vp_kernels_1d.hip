@@ -20,10 +20,10 @@ namespace {
 
 using namespace dev;
 
-template <typename T, int W, int NT, int KIND>
+template <typename T, int W, int NT, int KIND, bool LIM>
 __global__ __launch_bounds__(NT) void k_stage1d(Stage1DArgs A)
 {
-    stage_tile_uniform<T, W, NT, KIND>(A, xcd_remap(blockIdx.x, gridDim.x));
+    stage_tile_uniform<T, W, NT, KIND, LIM>(A, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // n_i = dv * sum_j f_ij, one block per row, fixed summation order.
@@ -309,11 +309,20 @@ hipError_t launch_stage_t(int kind, const Stage1DArgs& a, hipStream_t stream)
     const int nstrip = a.nstrip;
     const int nseg = (a.nx + a.tx - 1) / a.tx;
     const dim3 grid(nstrip * nseg), block(NT);
-    switch (kind) {
-    case kRhs: hipLaunchKernelGGL((k_stage1d<T, W, NT, kRhs>), grid, block, 0, stream, a); break;
-    case kStage1: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage1>), grid, block, 0, stream, a); break;
-    case kStage23: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage23>), grid, block, 0, stream, a); break;
-    default: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage4>), grid, block, 0, stream, a); break;
+    if (a.lim) {
+        switch (kind) {
+        case kRhs: hipLaunchKernelGGL((k_stage1d<T, W, NT, kRhs, true>), grid, block, 0, stream, a); break;
+        case kStage1: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage1, true>), grid, block, 0, stream, a); break;
+        case kStage23: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage23, true>), grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage4, true>), grid, block, 0, stream, a); break;
+        }
+    } else {
+        switch (kind) {
+        case kRhs: hipLaunchKernelGGL((k_stage1d<T, W, NT, kRhs, false>), grid, block, 0, stream, a); break;
+        case kStage1: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage1, false>), grid, block, 0, stream, a); break;
+        case kStage23: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage23, false>), grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage4, false>), grid, block, 0, stream, a); break;
+        }
     }
     return hipGetLastError();
 }

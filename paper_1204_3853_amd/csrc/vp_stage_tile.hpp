@@ -109,6 +109,35 @@ __device__ __forceinline__ T face4(T um1, T u0, T u1, T u2)
     return (T(7) * (u0 + u1) - (um1 + u2)) * T(1.0 / 12.0);
 }
 
+// lo + x h rounded after the product and after the sum (never fused)
+__device__ __forceinline__ double centre_unfused(double lo, double x, double h)
+{
+#pragma clang fp contract(off)
+    const double p = x * h;
+    return lo + p;
+}
+
+// Limited face average between u0 and u1 (section 2, eq. limitedFace): the
+// left- and right-biased third-order candidates (eqs. thirdLeft,
+// thirdRight) weighted by provisional WENO weights from the Jiang-Shu
+// smoothness of their stencils (ideal weights 1/2, epsilon 1e-6, power 2),
+// the larger weight given to the upwind candidate (upl: flow towards +).
+template <typename T>
+__device__ __forceinline__ T face_lim(T um1, T u0, T u1, T u2, bool upl)
+{
+    const T fl = (T(5) * u0 + T(2) * u1 - um1) * T(1.0 / 6.0);
+    const T fr = (T(2) * u0 + T(5) * u1 - u2) * T(1.0 / 6.0);
+    const T d1 = um1 - T(2) * u0 + u1, e1 = um1 - u1;
+    const T d2 = u0 - T(2) * u1 + u2, e2 = T(3) * u0 - T(4) * u1 + u2;
+    const T bl = T(13.0 / 12.0) * d1 * d1 + T(0.25) * e1 * e1 + T(1e-6);
+    const T br = T(13.0 / 12.0) * d2 * d2 + T(0.25) * e2 * e2 + T(1e-6);
+    const T sl = bl * bl, sr = br * br;
+    const T wl = sr / (sl + sr);                 // provisional left weight, (1/sl) / (1/sl + 1/sr)
+    const T wmax = wl > T(0.5) ? wl : T(1) - wl;
+    const T wmin = T(1) - wmax;
+    return upl ? wmax * fl + wmin * fr : wmin * fl + wmax * fr;
+}
+
 // Stage kernel.  A block owns a strip of TV = NT*W velocity cells and a
 // segment of configuration rows [i0, i1).  The march proceeds in batches
 // of RB rows: all loads of a batch (RB new rows of the stage state plus the
@@ -120,7 +149,7 @@ __device__ __forceinline__ T face4(T um1, T u0, T u1, T u2)
 // (each other's two halo rows) at about the same time, while those rows
 // are still in L2.  Every face flux is formed from the same four rows in
 // either direction, so the results do not depend on the direction.
-template <typename T, int W, int NT, int KIND>
+template <typename T, int W, int NT, int KIND, bool LIM = false>
 __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int tile)
 {
     constexpr int RB = 4;                                    // rows per batch
@@ -180,12 +209,22 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
         for (int w = 0; w < W; ++w) dst[c0 + w] = own_in ? v[w] : oconst[w];
         if (has_halo) dst[hcol] = halo_in ? h : hconst;
     };
+    // limited faces: x faces are upwinded by the sign of the column velocity,
+    // v faces by the sign of the row's acceleration.  The cell-centre
+    // velocity is rounded after the product and after the sum (no fused
+    // multiply-add), so that a centre velocity that is zero in exact
+    // arithmetic gets the same sign as in an unfused evaluation of
+    // v_lo + (j + 1/2) dv.
+    bool upx[W + 2];
+#pragma unroll
+    for (int q = 0; q < W + 2; ++q) upx[q] = centre_unfused(A.v_lo, (double)(jt - 1 + q) + 0.5, A.dv) > 0.0;
     auto fx_cols = [&](int r, T* Fx) {      // x-face r + 1/2 at columns jt-1 .. jt+W
         const int sm1 = slot_of(r - 1), s0 = slot_of(r), s1 = slot_of(r + 1), s2 = slot_of(r + 2);
 #pragma unroll
         for (int q = 0; q < W + 2; ++q) {
             const int c = c0 - 1 + q;
-            Fx[q] = face4<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c]);
+            if (LIM) Fx[q] = face_lim<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c], upx[q]);
+            else Fx[q] = face4<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c]);
         }
     };
     auto fv_faces = [&](int r, T* Fv) {     // v-faces jt-1/2 .. jt+W-1/2 of row r
@@ -193,8 +232,12 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
         T u[W + 4];
 #pragma unroll
         for (int q = 0; q < W + 4; ++q) u[q] = ring[sl][c0 - 2 + q];
+        const bool upv = LIM && aseg[max(r - i0 + 1, 0)] > 0.0;
 #pragma unroll
-        for (int m = 0; m <= W; ++m) Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
+        for (int m = 0; m <= W; ++m) {
+            if (LIM) Fv[m] = face_lim<T>(u[m], u[m + 1], u[m + 2], u[m + 3], upv);
+            else Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
+        }
     };
 
     T vb[W];

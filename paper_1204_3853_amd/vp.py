@@ -79,6 +79,7 @@ SIGNATURES = {
     "vp_tile_shape_set": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vp_launch_mode_set": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vp_reduction_set": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vp_face_scheme_set": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vp_autotune": (ctypes.c_int, [_P, _P, _P, _D, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_float)]),
     "vp_timing_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -89,6 +90,7 @@ SIGNATURES = {
 TIMING_CLASSES = ["stage", "field", "moment", "sync", "adjoint", "other"]
 LAUNCH_PERSISTENT, LAUNCH_PER_PATCH = 0, 1
 REDUCE_SUBPATCH, REDUCE_MASK = 0, 1
+FACE_CENTERED, FACE_LIMITED = 0, 1
 
 
 def lib():
@@ -210,6 +212,10 @@ class Plan:
         """LAUNCH_PERSISTENT (one launch per stage over the tile table) or
         LAUNCH_PER_PATCH (one launch per patch)."""
         _check(lib().vp_launch_mode_set(self.h, int(mode)))
+
+    def set_face_scheme(self, scheme):
+        """FACE_CENTERED (ideal weights) or FACE_LIMITED (section 2, eq. limitedFace)."""
+        _check(lib().vp_face_scheme_set(self.h, int(scheme)))
 
     def set_reduction(self, algorithm):
         """REDUCE_SUBPATCH (Alg. spreduce) or REDUCE_MASK (Alg. mreduce), two-level plans."""
