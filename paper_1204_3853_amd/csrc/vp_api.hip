@@ -131,6 +131,9 @@ vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, vo
         VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage1d(p->dtype, sh, kind, A, stream); }));
         double* a_next = (s < 3) ? sa[s + 1] : a;
         VP_HIP(timed(p, kTField, stream, [&] {
+            if (p->nx >= kFieldSplitMin)
+                return launch_field_split(part, A.nstrip, p->nx, p->dv, p->dx, p->pb.qm, p->d_green, ncfg, a_next,
+                                          stream);
             return launch_poisson1d(part, A.nstrip, nullptr, p->dv, p->nx, p->dx, p->pb.qm, p->d_green, p->gk,
                                     ncfg, nullptr, nullptr, a_next, stream);
         }));

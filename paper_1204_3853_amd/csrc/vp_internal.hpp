@@ -40,6 +40,8 @@ constexpr int kMaxTx = 128;          // bound on rows per segment (LDS moment bu
 constexpr int kPoissonThreads = 256;
 constexpr int kMaxPoisson1D = 8192;  // configuration cells handled by the one-block solver
 constexpr int kGreenTaps = 16;       // taps of the truncated Green's function: r^17 ~ 3.6e-20
+constexpr int kFieldChunk = 256;     // configuration cells per block of the split field solve
+constexpr int kFieldSplitMin = 1024; // smallest mesh that takes the split field solve
 
 // Arguments of the 1D+1V stage kernels.  Pointers are element pointers of
 // the plan dtype T (passed as void* and cast in the launcher).
@@ -168,6 +170,10 @@ hipError_t launch_adjoint_stage1d(int w, bool first, const Adjoint1DArgs& a, hip
 hipError_t launch_adjoint_final(const double* mu, const double* g, const double* z, int nx, int nv, double* out,
                                 hipStream_t stream);
 hipError_t launch_scale(const double* x, double s, double* y, int n, hipStream_t stream);
+// moment from strip partials, Poisson, field and a = (q/m) E over many blocks
+// (nx >= kFieldSplitMin); work holds nx + 2 ceil(nx / kFieldChunk) doubles
+hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv, double dx, double qm,
+                              const double* green, double* work, double* a, hipStream_t stream);
 // Poisson, field and two-level injection in one launch; the moment is n_in,
 // or is finalised from the weighted list of x when x.slots is set
 hipError_t launch_poisson1d_inject(const double* n_in, const PoissonExtra& x, int nx, double dx, double qm,

@@ -96,6 +96,122 @@ __device__ double block_exclusive_scan(double v, double* red)
     return off + x - v;
 }
 
+// ---------------------------------------------------------------- split field solve
+//
+// The same solve as k_poisson1d, spread over chunks of kFieldChunk
+// configuration cells so that many CUs share it (for meshes of at least
+// kFieldSplitMin cells):
+//   k_field_chunks: per chunk, the moment from the stage kernel's strip
+//     partials (with a 16-cell periodic halo), r = 12 dx^2 (1 - n), the
+//     tridiagonal-factor inverse y = g * r over the chunk, and the chunk's
+//     sums of y and of y_m (N - m);
+//   k_field_finish: per chunk, the global mean of y and of D from the
+//     chunk sums, the chunk's prefix offset, an in-chunk scan for
+//     d = D - mean(D) (D_i = sum_{m <= i} (y_m - mean y)), and the field
+//     E_i = -(7 (d_i + d_{i-1}) - d_{i+1} - d_{i-2}) / (12 dx), a = (q/m) E.
+// All sums run in a fixed order.
+
+__global__ __launch_bounds__(kFieldChunk) void k_field_chunks(const double* __restrict__ part, int nstrip, int nx,
+                                                              double dv, double dx, const double* __restrict__ green,
+                                                              double* __restrict__ y, double* __restrict__ csum)
+{
+    constexpr int K = kGreenTaps;
+    __shared__ double r[kFieldChunk + 2 * K];
+    __shared__ double gs[K + 1];
+    __shared__ double red[2 * (kFieldChunk / 64)];
+    const int t = threadIdx.x;
+    const int c0 = blockIdx.x * kFieldChunk;
+    if (t <= K) gs[t] = green[t];
+    const double scale = 12.0 * dx * dx;
+    for (int q = t; q < kFieldChunk + 2 * K; q += kFieldChunk) {
+        const int i = wrapi(c0 - K + q, nx);
+        double v[16];
+        double acc = 0.0;
+        for (int s0 = 0; s0 < nstrip; s0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = (s0 + u < nstrip) ? part[(size_t)(s0 + u) * nx + i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v[u];
+        }
+        r[q] = scale * (1.0 - dv * acc);
+    }
+    __syncthreads();
+    const int i = c0 + t;
+    double yi = gs[0] * r[t + K];
+#pragma unroll
+    for (int o = 1; o <= K; ++o) yi += gs[o] * (r[t + K + o] + r[t + K - o]);
+    double sy = 0.0, sw = 0.0;
+    if (i < nx) {
+        y[i] = yi;
+        sy = yi;
+        sw = yi * (double)(nx - i);
+    }
+    sy = wave_sum(sy);
+    sw = wave_sum(sw);
+    const int lane = t & 63, wave = t >> 6;
+    if (lane == 0) { red[wave] = sy; red[kFieldChunk / 64 + wave] = sw; }
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < kFieldChunk / 64; ++w) { a += red[w]; b += red[kFieldChunk / 64 + w]; }
+        csum[2 * blockIdx.x] = a;
+        csum[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __restrict__ y,
+                                                              const double* __restrict__ csum, int nchunk, int nx,
+                                                              double dx, double qm, double* __restrict__ a_out)
+{
+    __shared__ double d[kFieldChunk + 4];     // d_i for i = c0 - 2 .. c0 + kFieldChunk + 1
+    __shared__ double red[kFieldChunk / 64];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int c = blockIdx.x, c0 = c * kFieldChunk;
+    // global sums and the prefix of y - mean(y) up to the chunk start, in chunk order
+    double sy = 0.0, sw = 0.0, pre = 0.0;
+    for (int q = 0; q < nchunk; ++q) {
+        if (q == c) pre = sy;
+        sy += csum[2 * q];
+        sw += csum[2 * q + 1];
+    }
+    const double ybar = sy / nx;
+    const double mean_D = (sw - ybar * 0.5 * (double)nx * (double)(nx + 1)) / nx;
+    const double off = pre - ybar * (double)c0 - mean_D;            // d_{c0 - 1}
+    // inclusive scan of y - mean(y) over rows c0 .. c0 + kFieldChunk + 1 (periodic)
+    const double yv = y[wrapi(c0 + t, nx)] - ybar;
+    double x = yv;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_up(x, o, 64);
+        if (lane >= o) x += u;
+    }
+    if (lane == 63) red[wave] = x;
+    __syncthreads();
+    double wo = 0.0;
+    for (int w = 0; w < wave; ++w) wo += red[w];
+    d[t + 2] = off + wo + x;
+    if (t < 2) {
+        // rows past the chunk: d continues with y of rows c0 + 256, c0 + 257
+        double tail = 0.0;
+        for (int w = 0; w < kFieldChunk / 64; ++w) tail += red[w];
+        double e = off + tail + (y[wrapi(c0 + kFieldChunk, nx)] - ybar);
+        if (t == 1) e += y[wrapi(c0 + kFieldChunk + 1, nx)] - ybar;
+        d[kFieldChunk + 2 + t] = e;
+    }
+    if (t == 0) {
+        // rows before the chunk: d_{c0 - 1} = off, d_{c0 - 2} = off - (y_{c0 - 1} - mean y)
+        d[1] = off;
+        d[0] = off - (y[wrapi(c0 - 1, nx)] - ybar);
+    }
+    __syncthreads();
+    const int i = c0 + t;
+    if (i < nx) {
+        const double E = -(7.0 * (d[t + 2] + d[t + 1]) - d[t + 3] - d[t]) / (12.0 * dx);
+        a_out[i] = qm * E;
+    }
+}
+
 // n_i = dv * sum over strips of the stage kernel's per-strip partial sums,
 // one row per thread with all strip loads in flight, fixed summation order.
 __global__ __launch_bounds__(256) void k_moment_finalize(const double* __restrict__ part, int nstrip, int nx,
@@ -400,6 +516,19 @@ hipError_t launch_poisson1d_inject(const double* n_in, const PoissonExtra& x, in
     const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
                        nullptr, E, a, 0, 1.0, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv, double dx, double qm,
+                              const double* green, double* work, double* a, hipStream_t stream)
+{
+    if (nx < kFieldSplitMin || nx > kMaxPoisson1D) return hipErrorInvalidValue;
+    const int nchunk = (nx + kFieldChunk - 1) / kFieldChunk;
+    double* y = work;
+    double* csum = work + nx;
+    hipLaunchKernelGGL(k_field_chunks, dim3(nchunk), dim3(kFieldChunk), 0, stream, part, nstrip, nx, dv, dx, green,
+                       y, csum);
+    hipLaunchKernelGGL(k_field_finish, dim3(nchunk), dim3(kFieldChunk), 0, stream, y, csum, nchunk, nx, dx, qm, a);
     return hipGetLastError();
 }
 

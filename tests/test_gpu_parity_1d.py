@@ -21,6 +21,8 @@ import vp_inputs as I
 pytestmark = pytest.mark.gpu
 
 SIZES = [(8, 8), (5, 12), (37, 45), (64, 64), (300, 517), (130, 1030), (257, 256)]
+# configuration meshes that take the chunked field solve (ragged last chunk included)
+SPLIT_SIZES = [(1024, 12), (1030, 16), (2051, 8), (8192, 6)]
 
 
 @pytest.fixture(scope="module")
@@ -93,7 +95,7 @@ def test_poisson_field(V, oracle, nx):
     np.testing.assert_array_equal(host(a), -host(E))
 
 
-@pytest.mark.parametrize("nx,nv", SIZES)
+@pytest.mark.parametrize("nx,nv", SIZES + SPLIT_SIZES)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("init", ["landau", "random"])
 def test_rk4_step(V, oracle, nx, nv, dtype, init):
@@ -109,14 +111,17 @@ def test_rk4_step(V, oracle, nx, nv, dtype, init):
     o = oracle.Oracle1D.from_problem(p)
     a0 = o.constraints(f_in)[0]
     ag = V.field_of(plan, fg)
-    assert np.abs(host(ag) - a0).max() <= 1e-10 * max(np.abs(a0).max(), 1e-12) + 1e-15
+    # the field is a prefix sum over nx cells: its rounding grows with nx
+    atol_a = max(1e-10, 5e-14 * nx)
+    assert np.abs(host(ag) - a0).max() <= atol_a * max(np.abs(a0).max(), 1e-12) + 1e-15
     dt = 0.5 / (8.0 / p.dx + 0.1 / p.dv)
     V.rk4_step(plan, fg, ag, dt)
     fo = o.step(f_in, dt)
     tol = 1e-12 if dtype == torch.float64 else 1e-5
     assert rel(host(fg), fo) <= tol
     a1 = o.constraints(fo)[0]
-    assert np.abs(host(ag) - a1).max() <= (1e-9 if dtype == torch.float64 else 1e-4) * max(np.abs(a1).max(), 1e-12) + 1e-15
+    assert np.abs(host(ag) - a1).max() <= (max(1e-9, 5e-13 * nx) if dtype == torch.float64 else 1e-4) * \
+        max(np.abs(a1).max(), 1e-12) + 1e-15
 
 
 def test_rk4_landau_100_steps(V, oracle):
