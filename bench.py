@@ -7,8 +7,9 @@ moment, plus four field solves) over the whole phase-space mesh, with the
 state resident in HBM.  Prints one JSON line.
 
   value     cell-updates/s = cells * K / (time of K steps)
-  roofline  the stage kernels: algorithmic bytes (16 state words per cell
-            per RK4 step over the four stage launches) / their average
+  roofline  the stage kernels: algorithmic bytes (13 state words per cell
+            per RK4 step, 2 + 4 + 3 + 4 over the four stage launches of
+            the lean stage schedule) / their average
             launch duration measured with HIP events in a second pass of
             K steps, against the 8 TB/s HBM peak
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
@@ -161,7 +162,7 @@ def limited_bench(n=4096, steps=20, warmup=3):
     tm = plan.timing_read()
     plan.timing_enable(False)
     stage_us = tm["stage"][0] / tm["stage"][1] * 1e3
-    bytes_launch = 4 * 8 * n * n
+    bytes_launch = 13 * 8 * n * n / 4        # 13 state words per cell per step over 4 stage launches
     return {"workload": f"two-stream 1D+1V {n}x{n} FP64 with limited face averages, dt={dt}",
             "tile_shape": {"threads": shape[0], "cells_per_thread": shape[1], "rows": shape[2]},
             "ms_per_step": round(ms, 4), "cell_updates_per_s": n * n / (ms * 1e-3),
@@ -375,7 +376,7 @@ def main():
     value = cells * args.steps / (ms * 1e-3)
 
     esize = 8 if dtype == torch.float64 else 4
-    bytes_step = 16 * esize * cells           # algorithmic bytes of the four stage launches
+    bytes_step = 13 * esize * cells           # algorithmic bytes of the four stage launches
     roofline = None
     timing = None
     if not args.no_roofline_pass:

@@ -10,6 +10,7 @@
 // Every state element is read from HBM once per stage (halo rows and
 // columns are re-read from cache), and v is the contiguous, coalesced axis.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "vp_internal.hpp"
 #include "vp_stage_tile.hpp"
@@ -20,10 +21,18 @@ namespace {
 
 using namespace dev;
 
-template <typename T, int W, int NT, int KIND, bool LIM>
-__global__ __launch_bounds__(NT) void k_stage1d(Stage1DArgs A)
+// The FP64 centred-face kernels are held to 128 VGPRs (four waves per SIMD).
+template <typename T, int W, int NT, int KIND>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1))) void k_stage1d(Stage1DArgs A)
 {
-    stage_tile_uniform<T, W, NT, KIND, LIM>(A, xcd_remap(blockIdx.x, gridDim.x));
+    stage_tile_uniform<T, W, NT, KIND, false>(A, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// limited face averages (section 2, eq. limitedFace)
+template <typename T, int W, int NT, int KIND>
+__global__ __launch_bounds__(NT) void k_stage1d_lim(Stage1DArgs A)
+{
+    stage_tile_uniform<T, W, NT, KIND, true>(A, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // n_i = dv * sum_j f_ij, one block per row, fixed summation order.
@@ -425,21 +434,22 @@ hipError_t launch_stage_t(int kind, const Stage1DArgs& a, hipStream_t stream)
     const int nstrip = a.nstrip;
     const int nseg = (a.nx + a.tx - 1) / a.tx;
     const dim3 grid(nstrip * nseg), block(NT);
-    if (a.lim) {
-        switch (kind) {
-        case kRhs: hipLaunchKernelGGL((k_stage1d<T, W, NT, kRhs, true>), grid, block, 0, stream, a); break;
-        case kStage1: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage1, true>), grid, block, 0, stream, a); break;
-        case kStage23: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage23, true>), grid, block, 0, stream, a); break;
-        default: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage4, true>), grid, block, 0, stream, a); break;
-        }
-    } else {
-        switch (kind) {
-        case kRhs: hipLaunchKernelGGL((k_stage1d<T, W, NT, kRhs, false>), grid, block, 0, stream, a); break;
-        case kStage1: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage1, false>), grid, block, 0, stream, a); break;
-        case kStage23: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage23, false>), grid, block, 0, stream, a); break;
-        default: hipLaunchKernelGGL((k_stage1d<T, W, NT, kStage4, false>), grid, block, 0, stream, a); break;
-        }
+    auto go = [&](auto kind_c) {
+        constexpr int K = decltype(kind_c)::value;
+        if (a.lim) hipLaunchKernelGGL((k_stage1d_lim<T, W, NT, K>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_stage1d<T, W, NT, K>), grid, block, 0, stream, a);
+        return true;
+    };
+    bool ok = false;
+    switch (kind) {
+    case kRhs: ok = go(std::integral_constant<int, kRhs>{}); break;
+    case kLean1: ok = go(std::integral_constant<int, kLean1>{}); break;
+    case kLean2: ok = go(std::integral_constant<int, kLean2>{}); break;
+    case kLean3: ok = go(std::integral_constant<int, kLean3>{}); break;
+    case kLean4: ok = go(std::integral_constant<int, kLean4>{}); break;
+    default: break;
     }
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

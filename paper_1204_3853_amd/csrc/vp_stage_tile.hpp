@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "vp_internal.hpp"
 
@@ -95,6 +96,44 @@ template <> struct VecIO<float, 4> {
     }
 };
 
+// x moved across lanes by the DPP pattern CTRL (a permutation within each
+// row of 16 lanes), as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each row of 16 lanes, the same value in every lane of the row:
+// neighbours within quads (quad_perm 1,0,3,2), the other pair of the quad
+// (quad_perm 2,3,0,1), the other quad of the half row (row_half_mirror),
+// the other half row (row_mirror).
+__device__ __forceinline__ double row16_sum(double s)
+{
+    s += dpp_f64<0xB1>(s);
+    s += dpp_f64<0x4E>(s);
+    s += dpp_f64<0x141>(s);
+    s += dpp_f64<0x140>(s);
+    return s;
+}
+
+// Wave sums of four values per lane: returns, in every lane of lane group
+// g = lane / 16, the sum of s[g] over the 64 lanes.  Lanes l and l ^ 32
+// trade the two rows the other half keeps (rows 0, 1 stay in the lower
+// half, rows 2, 3 in the upper one), then lanes l and l ^ 16 trade one of
+// those, and a reduction within the 16 lanes finishes the sum.
+__device__ __forceinline__ double wave_sum4(const double (&s)[4], int lane)
+{
+    const bool hi = (lane & 32) != 0, mid = (lane & 16) != 0;
+    const double t0 = (hi ? s[2] : s[0]) + __shfl_xor(hi ? s[0] : s[2], 32, 64);
+    const double t1 = (hi ? s[3] : s[1]) + __shfl_xor(hi ? s[1] : s[3], 32, 64);
+    const double u = (mid ? t1 : t0) + __shfl_xor(mid ? t0 : t1, 16, 64);
+    return row16_sum(u);
+}
+
 __device__ __forceinline__ double wave_sum(double s)
 {
 #pragma unroll
@@ -155,10 +194,13 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
     constexpr int RB = 4;                                    // rows per batch
     constexpr int NSLOT = 8;                                 // ring rows (>= RB + 4)
     constexpr int TV = NT * W;
-    constexpr int LPAD = (W > 2) ? W : 2;                    // keeps own data W-aligned in LDS
-    constexpr int RW = ((LPAD + TV + 2 + 3) / 4) * 4;
+    constexpr int PW = NT + 4;                               // plane width: lane slots -2 .. NT+1
     constexpr int NWAVE = NT / 64;
-    __shared__ __attribute__((aligned(16))) T ring[NSLOT][RW];
+    // A ring row is stored as W planes: column j0 + W*u + w (w < W) sits in
+    // plane w at index u + 2.  Lanes then read and write consecutive 8-byte
+    // words of one plane, which is free of LDS bank conflicts, where a
+    // row-major row would put a W*8-byte stride between lanes.
+    __shared__ __attribute__((aligned(16))) T ring[NSLOT][W][PW];
     __shared__ double mom[NWAVE][kMaxTx];
     __shared__ double aseg[kMaxTx + RB + 2];   // a_{i0-1} .. a_{i1}, then padding
 
@@ -179,7 +221,6 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
     const bool own_in = jt < nv;          // nv % W == 0 for W > 1, so the whole vector is in range
     const int jld = own_in ? jt : 0;      // out-of-range threads load a valid cell and discard it
     const int lane = t & 63, wave = t >> 6;
-    const int c0 = LPAD + t * W;          // LDS column of the first own cell
 
     // values of own cells that lie outside [0, nv): velocity ghosts or unused
     T oconst[W];
@@ -191,7 +232,8 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
     // threads 0..3 also stage one strip-halo cell: j0-2, j0-1, j0+TV, j0+TV+1
     const bool has_halo = t < 4;
     const int hj = t < 2 ? j0 - 2 + t : j0 + TV + (t - 2);
-    const int hcol = t < 2 ? LPAD - 2 + t : LPAD + TV + (t - 2);
+    const int hu = (hj - j0 + 2 * W);                 // >= 0
+    const int hplane = hu % W, hidx = hu / W;         // plane index (u + 2) of the halo cell
     const bool halo_in = has_halo && hj >= 0 && hj < nv;
     const int hld = halo_in ? hj : jld;
     const T hconst = (hj == -2) ? (T)A.vg[0] : (hj == -1) ? (T)A.vg[1] : (hj == nv) ? (T)A.vg[2]
@@ -203,11 +245,15 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
         VecIO<T, W>::ld(row + jld, v);
         h = row[hld];
     };
+    // column jt + m of this thread, m in [-2, W + 1] (a compile-time constant)
+    auto cell = [&](int sl, int m) -> T& {
+        return ring[sl][(m + 2 * W) % W][t + (m + 2 * W) / W];
+    };
     auto store_row = [&](int r, const T* v, T h) {
-        T* dst = &ring[slot_of(r)][0];
+        const int sl = slot_of(r);
 #pragma unroll
-        for (int w = 0; w < W; ++w) dst[c0 + w] = own_in ? v[w] : oconst[w];
-        if (has_halo) dst[hcol] = halo_in ? h : hconst;
+        for (int w = 0; w < W; ++w) cell(sl, w) = own_in ? v[w] : oconst[w];
+        if (has_halo) ring[sl][hplane][hidx] = halo_in ? h : hconst;
     };
     // limited faces: x faces are upwinded by the sign of the column velocity,
     // v faces by the sign of the row's acceleration.  The cell-centre
@@ -222,16 +268,16 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
         const int sm1 = slot_of(r - 1), s0 = slot_of(r), s1 = slot_of(r + 1), s2 = slot_of(r + 2);
 #pragma unroll
         for (int q = 0; q < W + 2; ++q) {
-            const int c = c0 - 1 + q;
-            if (LIM) Fx[q] = face_lim<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c], upx[q]);
-            else Fx[q] = face4<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c]);
+            const int m = q - 1;
+            if (LIM) Fx[q] = face_lim<T>(cell(sm1, m), cell(s0, m), cell(s1, m), cell(s2, m), upx[q]);
+            else Fx[q] = face4<T>(cell(sm1, m), cell(s0, m), cell(s1, m), cell(s2, m));
         }
     };
     auto fv_faces = [&](int r, T* Fv) {     // v-faces jt-1/2 .. jt+W-1/2 of row r
         const int sl = slot_of(r);
         T u[W + 4];
 #pragma unroll
-        for (int q = 0; q < W + 4; ++q) u[q] = ring[sl][c0 - 2 + q];
+        for (int q = 0; q < W + 4; ++q) u[q] = cell(sl, q - 2);
         const bool upv = LIM && aseg[max(r - i0 + 1, 0)] > 0.0;
 #pragma unroll
         for (int m = 0; m <= W; ++m) {
@@ -246,130 +292,182 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
     const T dxi = (T)A.dxi, dvi = (T)A.dvi, dv24 = (T)A.dv24;
     const T cacc = (T)A.c_acc, cnext = (T)A.c_next;
 
-    // march direction: +1 for even segments, -1 for odd ones
-    const bool dn = (seg & 1) != 0;
-    const int D = dn ? -1 : 1;
-    const int ifirst = dn ? i1 - 1 : i0;              // first output row of the march
     const int len = i1 - i0;
+    static_assert(RB == 4, "the batch reduction of the velocity moments folds four rows");
 
-    // ---- prologue: the four rows around the first output row
-    {
-        T v[4][W], h[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) load_row(ifirst + D * (q - 2), v[q], h[q]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) store_row(ifirst + D * (q - 2), v[q], h[q]);
-    }
-    for (int q = t; q < i1 - i0 + 2; q += NT) aseg[q] = av[wrapi(i0 - 1 + q, nx)];
-    for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
-    __syncthreads();
+    // The march runs towards increasing x on even segments and towards
+    // decreasing x on odd ones; each direction is compiled separately so
+    // that the direction costs no selects in the loop.
+    auto march = [&](auto dn_c) {
+        constexpr bool DN = decltype(dn_c)::value;
+        constexpr int D = DN ? -1 : 1;
+        const int ifirst = DN ? i1 - 1 : i0;          // first output row of the march
 
-    // x-flux on the face behind the first row, v-face averages of the row
-    // behind and of the first row
-    T gx_old[W];
-    {
-        T Fx[W + 2];
-        fx_cols(dn ? i1 - 1 : i0 - 1, Fx);
+        // ---- prologue: the four rows around the first output row
+        {
+            T v[4][W], h[4];
 #pragma unroll
-        for (int w = 0; w < W; ++w) gx_old[w] = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
-    }
-    T fvP[W + 1], fvB[W + 1];
-    fv_faces(ifirst - D, fvP);
-    fv_faces(ifirst, fvB);
-
-#pragma unroll 1
-    for (int mb = 0; mb < len; mb += RB) {
-        // issue every load of the batch; rows past the segment are clamped
-        // so that all loads and their uses are unconditional
-        T v[RB][W], h[RB], fnv[RB][W], accv[RB][W];
+            for (int q = 0; q < 4; ++q) load_row(ifirst + D * (q - 2), v[q], h[q]);
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            const int rn = ifirst + D * (mb + q + 2);                      // new stage-state row
-            load_row(dn ? max(rn, i0 - 2) : min(rn, i1 + 1), v[q], h[q]);
-            const int ro = ifirst + D * min(mb + q, len - 1);              // row being updated
-            const size_t off = (size_t)ro * nv + jld;
-            if (KIND == kStage23) VecIO<T, W>::ldn(fn + off, fnv[q]);
-            if (KIND == kStage23 || KIND == kStage4) VecIO<T, W>::ldn(acc + off, accv[q]);
+            for (int q = 0; q < 4; ++q) store_row(ifirst + D * (q - 2), v[q], h[q]);
         }
-        __syncthreads();                              // previous batch done reading its ring rows
-#pragma unroll
-        for (int q = 0; q < RB; ++q) store_row(ifirst + D * (mb + q + 2), v[q], h[q]);
+        for (int q = t; q < i1 - i0 + 2; q += NT) aseg[q] = av[wrapi(i0 - 1 + q, nx)];
+        for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
         __syncthreads();
 
-        // compute the batch (rows past the segment are computed and dropped);
-        // results stay in registers and are stored together
-        T o1[RB][W], o2[RB][W];
-#pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            const int i = ifirst + D * (mb + q);
-            const int qa = i - i0;
-            const int qc = max(qa, 0);                // rows past a downward segment are dropped
-            const T a_m1 = (T)aseg[qc], a_0 = (T)aseg[qc + 1], a_p1 = (T)aseg[qc + 2];
+        // x-flux on the face behind the first row, v-face averages of the row
+        // behind and of the first row
+        T gx_old[W];
+        {
             T Fx[W + 2];
-            fx_cols(dn ? i - 1 : i, Fx);              // the face ahead of row i
-            T fvN[W + 1];
-            fv_faces(i + D, fvN);                     // the row ahead
-            const T da48 = (a_p1 - a_m1) * T(1.0 / 48.0);
-            T gv[W + 1];
+            fx_cols(DN ? i1 - 1 : i0 - 1, Fx);
 #pragma unroll
-            for (int m = 0; m <= W; ++m) {
-                const T fa = dn ? fvN[m] : fvP[m];    // row i - 1
-                const T fc = dn ? fvP[m] : fvN[m];    // row i + 1
-                gv[m] = a_0 * fvB[m] + da48 * (fc - fa);
-            }
-            T kk[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const T gx_new = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
-                const T ghi = dn ? gx_old[w] : gx_new;   // face i + 1/2
-                const T glo = dn ? gx_new : gx_old[w];   // face i - 1/2
-                kk[w] = -(ghi - glo) * dxi - (gv[w + 1] - gv[w]) * dvi;
-                gx_old[w] = gx_new;
-            }
-#pragma unroll
-            for (int m = 0; m <= W; ++m) { fvP[m] = fvB[m]; fvB[m] = fvN[m]; }
-
-            if (KIND == kRhs) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) o1[q][w] = kk[w];
-            } else if (KIND == kStage1) {
-                // f^n is the stage state itself: take it from the ring
-                const int sl = slot_of(i);
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const T f0 = ring[sl][c0 + w];
-                    o1[q][w] = f0 + cacc * kk[w];      // accumulator
-                    o2[q][w] = f0 + cnext * kk[w];     // next predictor
-                }
-            } else if (KIND == kStage23) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    o1[q][w] = accv[q][w] + cacc * kk[w];
-                    o2[q][w] = fnv[q][w] + cnext * kk[w];
-                }
-            } else {  // kStage4: f^{n+1} = acc + dt/6 k4
-#pragma unroll
-                for (int w = 0; w < W; ++w) o2[q][w] = accv[q][w] + cacc * kk[w];
-            }
-            if (KIND != kRhs && A.part) {
-                double sm = 0.0;
-                if (own_in) {
-#pragma unroll
-                    for (int w = 0; w < W; ++w) sm += (double)o2[q][w];
-                }
-                sm = wave_sum(sm);
-                if (lane == 0 && mb + q < len) mom[wave][qa] = sm;
-            }
+            for (int w = 0; w < W; ++w) gx_old[w] = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
         }
-        if (own_in) {
+        T fvP[W + 1], fvB[W + 1];
+        fv_faces(ifirst - D, fvP);
+        fv_faces(ifirst, fvB);
+
+        // The new stage-state rows of batch mb are rows mb + 2 .. mb + RB + 1 of
+        // the march (the rows ahead of the batch's output rows); rows past the
+        // segment are clamped so that all loads and their uses are unconditional.
+        auto load_batch = [&](int mb, T (*v)[W], T* h) {
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
-                if (mb + q < len) {
-                    const int i = ifirst + D * (mb + q);
+                const int rn = ifirst + D * (mb + q + 2);
+                load_row(DN ? max(rn, i0 - 2) : min(rn, i1 + 1), v[q], h[q]);
+            }
+        };
+        auto store_batch = [&](int mb, T (*v)[W], T* h) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) store_row(ifirst + D * (mb + q + 2), v[q], h[q]);
+        };
+        // Stages that stream few words per cell load the rows of the next batch
+        // while the current one is computed (the rows stay in registers until
+        // the ring slots they replace are free); the others load a batch just
+        // before computing it.
+        constexpr bool PF = KIND == kLean1;
+        if (PF) {
+            T v[RB][W], h[RB];
+            load_batch(0, v, h);
+            store_batch(0, v, h);
+            __syncthreads();
+        }
+
+#pragma unroll 1
+        for (int mb = 0; mb < len; mb += RB) {
+            T v[RB][W], h[RB], fnv[RB][W], accv[RB][W];
+            const bool more = mb + RB < len;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                if (!PF) {
+                    const int rn = ifirst + D * (mb + q + 2);
+                    load_row(DN ? max(rn, i0 - 2) : min(rn, i1 + 1), v[q], h[q]);
+                }
+                const int ro = ifirst + D * min(mb + q, len - 1);              // row being updated
+                const size_t off = (size_t)ro * nv + jld;
+                if (KIND == kStage23 || KIND == kLean2 || KIND == kLean3 || KIND == kLean4) VecIO<T, W>::ldn(fn + off, fnv[q]);
+                if (KIND == kStage23 || KIND == kStage4 || KIND == kLean4) VecIO<T, W>::ldn(acc + off, accv[q]);
+            }
+            // The prefetch is issued after the loads this batch consumes (loads
+            // complete in order, so this batch does not wait for the prefetch)
+            // and unconditionally, clamped past the segment (a load under a
+            // branch makes the compiler wait for it before the compute).
+            if (PF) load_batch(mb + RB, v, h);
+            if (!PF) {
+                __syncthreads();                          // previous batch done reading its ring rows
+                store_batch(mb, v, h);
+                __syncthreads();
+            }
+
+            // compute the batch (rows past the segment are computed and dropped);
+            // results stay in registers and are stored together
+            T o1[RB][W], o2[RB][W];
+            double sm4[RB];                           // velocity sums of the batch's new rows
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int i = ifirst + D * (mb + q);
+                const int qa = i - i0;
+                const int qc = max(qa, 0);                // rows past a downward segment are dropped
+                const T a_m1 = (T)aseg[qc], a_0 = (T)aseg[qc + 1], a_p1 = (T)aseg[qc + 2];
+                T Fx[W + 2];
+                fx_cols(DN ? i - 1 : i, Fx);              // the face ahead of row i
+                T fvN[W + 1];
+                fv_faces(i + D, fvN);                     // the row ahead
+                const T da48 = (a_p1 - a_m1) * T(1.0 / 48.0);
+                T gv[W + 1];
+#pragma unroll
+                for (int m = 0; m <= W; ++m) {
+                    const T fa = DN ? fvN[m] : fvP[m];    // row i - 1
+                    const T fc = DN ? fvP[m] : fvN[m];    // row i + 1
+                    gv[m] = a_0 * fvB[m] + da48 * (fc - fa);
+                }
+                T kk[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const T gx_new = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
+                    const T ghi = DN ? gx_old[w] : gx_new;   // face i + 1/2
+                    const T glo = DN ? gx_new : gx_old[w];   // face i - 1/2
+                    kk[w] = -(ghi - glo) * dxi - (gv[w + 1] - gv[w]) * dvi;
+                    gx_old[w] = gx_new;
+                }
+#pragma unroll
+                for (int m = 0; m <= W; ++m) { fvP[m] = fvB[m]; fvB[m] = fvN[m]; }
+
+                if (KIND == kRhs) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) o1[q][w] = kk[w];
+                } else if (KIND == kStage1) {
+                    // f^n is the stage state itself: take it from the ring
+                    const int sl = slot_of(i);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const T f0 = cell(sl, w);
+                        o1[q][w] = f0 + cacc * kk[w];      // accumulator
+                        o2[q][w] = f0 + cnext * kk[w];     // next predictor
+                    }
+                } else if (KIND == kStage23) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        o1[q][w] = accv[q][w] + cacc * kk[w];
+                        o2[q][w] = fnv[q][w] + cnext * kk[w];
+                    }
+                } else if (KIND == kStage4) {  // f^{n+1} = acc + dt/6 k4
+#pragma unroll
+                    for (int w = 0; w < W; ++w) o2[q][w] = accv[q][w] + cacc * kk[w];
+                } else if (KIND == kLean1) {   // f(2) = f^n + dt/2 k1, f^n from the ring
+                    const int sl = slot_of(i);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) o2[q][w] = cell(sl, w) + cnext * kk[w];
+                } else if (KIND == kLean2) {   // f(3), and acc from f(2) = the stage state
+                    const int sl = slot_of(i);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const T f2 = cell(sl, w);
+                        o1[q][w] = fnv[q][w] + ((f2 - fnv[q][w]) * T(1.0 / 3.0) + cacc * kk[w]);
+                        o2[q][w] = fnv[q][w] + cnext * kk[w];
+                    }
+                } else if (KIND == kLean3) {   // f(4) = f^n + dt k3
+#pragma unroll
+                    for (int w = 0; w < W; ++w) o2[q][w] = fnv[q][w] + cnext * kk[w];
+                } else {                       // kLean4: f^{n+1} from acc, f(4) = the stage state, f^n
+                    const int sl = slot_of(i);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const T f4 = cell(sl, w);
+                        o2[q][w] = accv[q][w] + ((f4 - fnv[q][w]) * T(1.0 / 3.0) + cacc * kk[w]);
+                    }
+                }
+                sm4[q] = 0.0;
+                if (own_in) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) sm4[q] += (double)o2[q][w];
+                }
+                if (own_in && mb + q < len) {
                     const size_t rowoff = (size_t)i * nv + jt;
                     if (KIND == kRhs) {
                         VecIO<T, W>::stn(fout + rowoff, o1[q]);
-                    } else if (KIND == kStage4) {
+                    } else if (KIND == kStage4 || KIND == kLean1 || KIND == kLean3 || KIND == kLean4) {
                         VecIO<T, W>::stn(fout + rowoff, o2[q]);
                     } else {
                         VecIO<T, W>::stn(acc + rowoff, o1[q]);
@@ -377,8 +475,20 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
                     }
                 }
             }
+            if (KIND != kRhs && A.part) {
+                const double tot = wave_sum4(sm4, lane);  // row q = lane / 16 of the batch
+                const int g = lane >> 4;
+                if ((lane & 15) == 0 && mb + g < len) mom[wave][ifirst + D * (mb + g) - i0] = tot;
+            }
+            if (PF && more) {
+                __syncthreads();                          // this batch done reading its ring rows
+                store_batch(mb + RB, v, h);
+                __syncthreads();
+            }
         }
-    }
+    };
+    if (seg & 1) march(std::true_type{});
+    else march(std::false_type{});
 
     if (KIND != kRhs && A.part) {
         __syncthreads();
