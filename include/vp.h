@@ -209,6 +209,9 @@ vp_status vp_reduction_set(vp_plan* plan, int32_t algorithm);
  *   phi  output or NULL
  *   E    output or NULL (vp_config_elems per configuration direction,
  *        direction-major in 2D+2V)
+ *   work unused (may be NULL); 2D+2V plans keep the Fourier coefficients
+ *        in plan-owned device memory, so calls on one 2D+2V plan must be
+ *        ordered on one stream
  */
 vp_status vp_poisson_periodic(const vp_plan* plan, const double* n, double* phi, double* E,
                               void* work, hipStream_t stream);

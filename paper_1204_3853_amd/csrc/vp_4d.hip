@@ -118,7 +118,7 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     VP_HIP(upload(&M->d_Qx, Qx));
     VP_HIP(upload(&M->d_Qy, Qy));
     VP_HIP(upload(&M->d_invlamT, inv));
-    VP_HIP(poisson2d_prepare());
+    VP_HIP(upload(&M->d_g, std::vector<double>((size_t)M->nx * M->ny, 0.0)));
 
     p->state_elems = (size_t)M->nx * M->ny * M->nvx * M->nvy;
     const size_t sb = align256(p->state_elems * sizeof(double));
@@ -127,7 +127,7 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     p->ws_fsa = o; o += sb;
     p->ws_fsb = o; o += sb;
     M->ws_n = o; o += align256((size_t)M->nx * M->ny * sizeof(double));
-    M->ws_E = o; o += align256((size_t)2 * M->nx * M->ny * sizeof(double));
+    M->ws_E = o; o += align256((size_t)2 * M->nx * M->ny * sizeof(double));   // Fourier coefficients in rk4
     p->ws_total = o;
     return VP_OK;
 }
@@ -136,7 +136,7 @@ void p4_destroy(vp_plan* p)
 {
     Plan4D* M = p->p4;
     if (!M) return;
-    double* ptrs[] = {M->d_gx, M->d_gy, M->d_Qx, M->d_Qy, M->d_invlamT};
+    double* ptrs[] = {M->d_gx, M->d_gy, M->d_Qx, M->d_Qy, M->d_invlamT, M->d_g};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
     delete M;
@@ -167,8 +167,8 @@ vp_status p4_poisson(const vp_plan* p, const double* n, double* phi, double* E, 
 {
     const Plan4D& M = *p->p4;
     VP_HIP(timed(p, kTField, stream, [&] {
-        return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_Qy, M.d_invlamT, phi, E, nullptr,
-                                stream);
+        return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_Qy, M.d_invlamT, M.d_g, phi, E,
+                                nullptr, stream);
     }));
     return VP_OK;
 }
@@ -181,6 +181,7 @@ vp_status p4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
     double* s2 = reinterpret_cast<double*>(wsp(work, p->ws_fsa));
     double* s3 = reinterpret_cast<double*>(wsp(work, p->ws_fsb));
     double* n = reinterpret_cast<double*>(wsp(work, M.ws_n));
+    double* g = reinterpret_cast<double*>(wsp(work, M.ws_E));
     const double* in[4] = {fd, s2, s3, s2};
     double* out[4] = {s2, s3, s2, fd};
     const double cacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
@@ -198,7 +199,7 @@ vp_status p4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
         const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
         VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage4d(M.rb, kind, A, stream); }));
         VP_HIP(timed(p, kTField, stream, [&] {
-            return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_Qy, M.d_invlamT, nullptr,
+            return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_Qy, M.d_invlamT, g, nullptr,
                                     nullptr, a, stream);
         }));
     }

@@ -192,9 +192,9 @@ hipError_t poisson1d_prepare();
 // 2D+2V launchers (vp_kernels_4d.hip)
 hipError_t launch_stage4d(int rb, int kind, const Stage4DArgs& a, hipStream_t stream);
 hipError_t launch_moment4d(const double* f, int ncfg, size_t plane, double scale, double* n, hipStream_t stream);
-hipError_t poisson2d_prepare();
+// g: nx * ny doubles of device scratch (the scaled Fourier coefficients)
 hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
-                            const double* Qy, const double* invlamT, double* phi, double* E, double* a,
+                            const double* Qy, const double* invlamT, double* g, double* phi, double* E, double* a,
                             hipStream_t stream);
 
 // two-level launchers (vp_kernels_amr.hip)
@@ -302,6 +302,7 @@ struct Plan4D {
     double* d_Qx = nullptr;
     double* d_Qy = nullptr;
     double* d_invlamT = nullptr;
+    double* d_g = nullptr;                           // Fourier coefficients of vp_poisson_periodic calls
     size_t ws_n = 0, ws_E = 0;
 };
 }  // namespace vp

@@ -195,126 +195,147 @@ __global__ __launch_bounds__(256) void k_moment4d(const double* __restrict__ f, 
 }
 
 // ---------------------------------------------------------------- 2D Poisson
+//
+// Periodic Poisson problem of the summed 1D fourth-order operators, solved
+// in the real orthonormal Fourier basis Q (columns = basis vectors) that
+// diagonalises every symmetric circulant matrix:
+//   g = (Qx^T rho Qy) / lambda (zero mode dropped),  phi = Qx g Qy^T,
+// then E = -D phi per direction and a = (q/m) E.  Two launches of one
+// block per row (nx, ny <= 64): the forward transform of one Fourier row,
+// then the inverse transform of five x rows and the field of the middle
+// one.  Rows computed by several blocks are computed identically.
 
-constexpr int kLd = kMaxPoisson2D + 1;
+constexpr int kP2 = kMaxPoisson2D;          // 64: rows and columns per matrix at most
+constexpr int kP2Q = 256 / kP2;             // 4 groups of 64 threads split each sum
 
-// C = A B for A (M x K) and B (K x N) in LDS with row stride kLd (BT: B
-// is stored transposed, element (k, n) at B[n * kLd + k]); each thread
-// computes a 4 x 4 block; C is stored transposed when TR.  Rows and
-// columns past the sizes are zero in A and B, so the padded entries of C
-// come out zero.
-template <bool BT, bool TR>
-__device__ __forceinline__ void mm_lds(const double* A, const double* B, int M, int K, int N, double* C)
+// block k: g[k][l] = invlam(k, l) sum_j (sum_i Qx[i][k] rho'[i][j]) Qy[j][l],
+// rho' = rho - mean(rho) = mean(n) - n
+__global__ __launch_bounds__(256) void k_poisson2d_fwd(const double* __restrict__ n, int nx, int ny,
+                                                      const double* __restrict__ Qx,
+                                                      const double* __restrict__ Qy,
+                                                      const double* __restrict__ invlamT, double* __restrict__ g)
 {
-    const int t = threadIdx.x;
-    const int r0 = (t >> 4) * 4, c0 = (t & 15) * 4;
-    if (r0 >= M || c0 >= N) return;
-    double acc[4][4] = {};
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-        double a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = A[(r0 + r) * kLd + k];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = BT ? B[(c0 + c) * kLd + k] : B[k * kLd + c0 + c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (TR) C[(c0 + c) * kLd + r0 + r] = acc[r][c];
-            else C[(r0 + r) * kLd + c0 + c] = acc[r][c];
-        }
-}
-
-constexpr int kPer = kMaxPoisson2D * kMaxPoisson2D / 256;   // matrix entries per thread
-
-// a rows x cols row-major matrix, kPer entries per thread, all loads in flight together
-__device__ __forceinline__ void fetch(const double* __restrict__ g, int count, double* v)
-{
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) v[r] = g[min((int)threadIdx.x + r * 256, count - 1)];
-}
-
-__device__ __forceinline__ void store_mat(const double* v, int rows, int cols, double* S)
-{
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        const int q = (int)threadIdx.x + r * 256;
-        if (q < rows * cols) S[(q / cols) * kLd + q % cols] = v[r];
-    }
-}
-
-// Periodic Poisson problem of the summed 1D fourth-order operators,
-// solved in the real orthonormal Fourier basis Q that diagonalises every
-// symmetric circulant matrix: phi = Qx [ (Qx^T rho Qy) / lambda ] Qy^T,
-// the zero mode dropped.  Then E = -D phi per direction and a = (q/m) E.
-__global__ __launch_bounds__(256) void k_poisson2d(const double* __restrict__ n, int nx, int ny, double dx,
-                                                  double dy, double qm, const double* __restrict__ Qx,
-                                                  const double* __restrict__ Qy,
-                                                  const double* __restrict__ invlamT, double* __restrict__ phi_out,
-                                                  double* __restrict__ E_out, double* __restrict__ a_out)
-{
-    extern __shared__ double sm[];
-    constexpr int S = kMaxPoisson2D * kLd;
-    double* A = sm;
-    double* B = sm + S;
-    double* QY = sm + 2 * S;
-    double* QX = sm + 3 * S;
-    __shared__ double red[256];
-    const int t = threadIdx.x;
+    constexpr int SEG = kP2 / kP2Q;          // 16 terms of a sum per thread
+    __shared__ double part[kP2Q][kP2];
+    __shared__ double w[kP2];
+    __shared__ double red[256 / 64];
+    const int t = threadIdx.x, lane = t & 63, q = t >> 6;
+    const int k = blockIdx.x;
     const int N = nx * ny;
-    double vn[kPer], vqx[kPer], vqy[kPer], vil[kPer];
-    fetch(n, N, vn);
-    fetch(Qx, nx * nx, vqx);
-    fetch(Qy, ny * ny, vqy);
-    fetch(invlamT, N, vil);
-    for (int q = t; q < 4 * S; q += 256) sm[q] = 0.0;
-    double s = 0.0;
+    // every load of the block in flight together: the mean's share, the
+    // rho column j = lane for rows i in [SEG q, SEG q + SEG), and Qx[i][k]
+    double vm[kP2 * kP2 / 256], vn[SEG], vq[SEG], vy[SEG];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r)
-        if (t + r * 256 < N) s += vn[r];
-    red[t] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
+    for (int r = 0; r < kP2 * kP2 / 256; ++r) {
+        const int e = t + r * 256;
+        vm[r] = e < N ? n[e] : 0.0;
     }
-    const double mean = red[0] / N;
+    const int j = lane;
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) vn[r] = mean - vn[r];       // rho - mean(rho) = mean(n) - n
-    store_mat(vn, nx, ny, A);
-    store_mat(vqy, ny, ny, QY);
-    store_mat(vqx, nx, nx, QX);
-    __syncthreads();
-    mm_lds<false, true>(A, QY, nx, ny, ny, B);     // B[l][i] = (rho Qy)[i][l]
-    __syncthreads();
-    mm_lds<false, false>(B, QX, ny, nx, nx, A);    // A[l][k] = (Qx^T rho Qy)[k][l]
-    __syncthreads();
+    for (int u = 0; u < SEG; ++u) {
+        const int i = q * SEG + u;
+        const bool in = i < nx && j < ny;
+        vn[u] = in ? n[i * ny + j] : 0.0;
+        vq[u] = i < nx ? Qx[i * nx + k] : 0.0;
+        const int jj = q * SEG + u;              // step 2: Qy[jj][l = lane]
+        vy[u] = (jj < ny && lane < ny) ? Qy[jj * ny + lane] : 0.0;
+    }
+    double sm = 0.0;
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        const int q = t + r * 256;
-        if (q < N) A[(q / nx) * kLd + q % nx] *= vil[r];
+    for (int r = 0; r < kP2 * kP2 / 256; ++r) sm += vm[r];
+    sm = wave_sum(sm);
+    if (lane == 0) red[q] = sm;
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int r = 0; r < 256 / 64; ++r) tot += red[r];
+    const double mean = tot / N;
+    // w[j] = sum_i Qx[i][k] rho'[i][j]
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < SEG; ++u) acc += vq[u] * (mean - vn[u]);
+    part[q][lane] = acc;
+    __syncthreads();
+    if (t < kP2) w[t] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+    __syncthreads();
+    // g[k][l] = invlam * sum_j w[j] Qy[j][l], l = lane
+    acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < SEG; ++u) acc += w[q * SEG + u] * vy[u];
+    part[q][lane] = acc;
+    __syncthreads();
+    if (t < ny) {
+        const double s2 = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+        g[k * ny + t] = s2 * invlamT[t * nx + k];
+    }
+}
+
+// block i: phi at rows i-2 .. i+2 (periodic), phi[i'][j] = sum_l h[i'][l] Qy[j][l]
+// with h[i'][l] = sum_k Qx[i'][k] g[k][l]; then E and a at row i
+__global__ __launch_bounds__(256) void k_poisson2d_inv(const double* __restrict__ g, int nx, int ny, double dx,
+                                                      double dy, double qm, const double* __restrict__ Qx,
+                                                      const double* __restrict__ Qy, double* __restrict__ phi_out,
+                                                      double* __restrict__ E_out, double* __restrict__ a_out)
+{
+    constexpr int SEG = kP2 / kP2Q;
+    __shared__ double part[kP2Q][5][kP2];
+    __shared__ double h[5][kP2];
+    __shared__ double ph[5][kP2];
+    __shared__ double qx[5][kP2];
+    const int t = threadIdx.x, lane = t & 63, q = t >> 6;
+    const int i = blockIdx.x;
+    const int N = nx * ny;
+    // Qx rows i-2 .. i+2 into LDS; g column l = lane for k in [SEG q, SEG q + SEG);
+    // Qy[j = lane][l] for l in [SEG q, SEG q + SEG)
+    for (int e = t; e < 5 * kP2; e += 256) {
+        const int r = e / kP2, kk = e - r * kP2;
+        qx[r][kk] = kk < nx ? Qx[wrapi(i - 2 + r, nx) * nx + kk] : 0.0;
+    }
+    double vg[SEG], vy[SEG];
+#pragma unroll
+    for (int u = 0; u < SEG; ++u) {
+        const int kk = q * SEG + u;
+        vg[u] = (kk < nx && lane < ny) ? g[kk * ny + lane] : 0.0;
+        const int l = q * SEG + u;
+        vy[u] = (l < ny && lane < ny) ? Qy[lane * ny + l] : 0.0;
     }
     __syncthreads();
-    mm_lds<true, true>(A, QX, ny, nx, nx, B);      // B[i][l] = sum_k Qx[i][k] A[l][k]
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < SEG; ++u) acc += qx[r][q * SEG + u] * vg[u];
+        part[q][r][lane] = acc;
+    }
     __syncthreads();
-    mm_lds<true, false>(B, QY, nx, ny, ny, A);     // A[i][j] = sum_l B[i][l] Qy[j][l] = phi
+    for (int e = t; e < 5 * kP2; e += 256) {
+        const int r = e / kP2, l = e - r * kP2;
+        h[r][l] = ((part[0][r][l] + part[1][r][l]) + part[2][r][l]) + part[3][r][l];
+    }
     __syncthreads();
-    const double cx = 1.0 / (12.0 * dx), cy = 1.0 / (12.0 * dy);
-    for (int q = t; q < N; q += 256) {
-        const int i = q / ny, j = q - (q / ny) * ny;
-        const int ip1 = wrapi(i + 1, nx), im1 = wrapi(i - 1, nx), ip2 = wrapi(i + 2, nx), im2 = wrapi(i - 2, nx);
-        const int jp1 = wrapi(j + 1, ny), jm1 = wrapi(j - 1, ny), jp2 = wrapi(j + 2, ny), jm2 = wrapi(j - 2, ny);
-        const double ex = -(8.0 * (A[ip1 * kLd + j] - A[im1 * kLd + j]) - (A[ip2 * kLd + j] - A[im2 * kLd + j])) * cx;
-        const double ey = -(8.0 * (A[i * kLd + jp1] - A[i * kLd + jm1]) - (A[i * kLd + jp2] - A[i * kLd + jm2])) * cy;
-        if (phi_out) phi_out[q] = A[i * kLd + j];
-        if (E_out) { E_out[q] = ex; E_out[N + q] = ey; }
-        if (a_out) { a_out[q] = qm * ex; a_out[N + q] = qm * ey; }
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < SEG; ++u) acc += h[r][q * SEG + u] * vy[u];
+        part[q][r][lane] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < 5 * kP2; e += 256) {
+        const int r = e / kP2, jj = e - r * kP2;
+        ph[r][jj] = ((part[0][r][jj] + part[1][r][jj]) + part[2][r][jj]) + part[3][r][jj];
+    }
+    __syncthreads();
+    if (t < ny) {
+        const int jj = t;
+        const int jp1 = wrapi(jj + 1, ny), jm1 = wrapi(jj - 1, ny), jp2 = wrapi(jj + 2, ny), jm2 = wrapi(jj - 2, ny);
+        const double cx = 1.0 / (12.0 * dx), cy = 1.0 / (12.0 * dy);
+        const double ex = -(8.0 * (ph[3][jj] - ph[1][jj]) - (ph[4][jj] - ph[0][jj])) * cx;
+        const double ey = -(8.0 * (ph[2][jp1] - ph[2][jm1]) - (ph[2][jp2] - ph[2][jm2])) * cy;
+        const int e = i * ny + jj;
+        if (phi_out) phi_out[e] = ph[2][jj];
+        if (E_out) { E_out[e] = ex; E_out[N + e] = ey; }
+        if (a_out) { a_out[e] = qm * ex; a_out[N + e] = qm * ey; }
     }
 }
 
@@ -350,21 +371,13 @@ hipError_t launch_moment4d(const double* f, int ncfg, size_t plane, double scale
     return hipGetLastError();
 }
 
-size_t poisson2d_lds_bytes() { return (size_t)4 * kMaxPoisson2D * kLd * sizeof(double); }
-
-hipError_t poisson2d_prepare()
-{
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_poisson2d),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)poisson2d_lds_bytes());
-}
-
 hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
-                            const double* Qy, const double* invlamT, double* phi, double* E, double* a,
+                            const double* Qy, const double* invlamT, double* g, double* phi, double* E, double* a,
                             hipStream_t stream)
 {
-    if (nx > kMaxPoisson2D || ny > kMaxPoisson2D) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_poisson2d, dim3(1), dim3(256), poisson2d_lds_bytes(), stream, n, nx, ny, dx, dy, qm, Qx,
-                       Qy, invlamT, phi, E, a);
+    if (nx > kMaxPoisson2D || ny > kMaxPoisson2D || !g) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_poisson2d_fwd, dim3(nx), dim3(256), 0, stream, n, nx, ny, Qx, Qy, invlamT, g);
+    hipLaunchKernelGGL(k_poisson2d_inv, dim3(nx), dim3(256), 0, stream, g, nx, ny, dx, dy, qm, Qx, Qy, phi, E, a);
     return hipGetLastError();
 }
 
