@@ -310,10 +310,10 @@ def fourd_bench(steps=50, warmup=3):
     plan.timing_enable(False)
     cells = plan.state_elems
     stage_us = tm["stage"][0] / tm["stage"][1] * 1e3
-    bytes_launch = 4 * 8 * cells
+    bytes_launch = 13 * 8 * cells / 4         # 13 state words per cell per step over 4 stage launches
     return {"workload": "2D+2V Vlasov-Poisson 64^4 FP64, x,y in [0,4pi), v in [-6,6]^2, dt=%g" % dt,
             "cells": cells, "steps": steps, "ms_per_step": round(ms, 4), "cell_updates_per_s": cells / (ms * 1e-3),
-            "tuned_vx_batch": shape[2],
+            "tuned_tile": {"threads": shape[0], "cells_x": shape[1], "cells_y": shape[2]},
             "stage_kernel": {"avg_launch_us": round(stage_us, 2), "algorithmic_bytes_per_launch": bytes_launch,
                              "achieved_GBs": round(bytes_launch / (stage_us * 1e-6) / 1e9, 1),
                              "frac_of_peak": round(bytes_launch / (stage_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},

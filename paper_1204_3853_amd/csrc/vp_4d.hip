@@ -98,6 +98,7 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     if (M->nx > kMaxPoisson2D || M->ny > kMaxPoisson2D)
         return fail(VP_ENOTSUP, "2D+2V configuration mesh is limited to 64 x 64 cells");
     if (M->nvy > kMaxVy4D) return fail(VP_ENOTSUP, "2D+2V is limited to 64 cells along vy");
+    if (M->nvx > kMaxVx4D) return fail(VP_ENOTSUP, "2D+2V is limited to 1024 cells along vx");
     M->dx = pb->x_len[0] / M->nx;
     M->dy = pb->x_len[1] / M->ny;
     M->dvx = (pb->v_hi[0] - pb->v_lo[0]) / M->nvx;
@@ -149,7 +150,7 @@ vp_status p4_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipS
     A.fs = static_cast<const double*>(f);
     A.fout = static_cast<double*>(k);
     A.a = a;
-    VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage4d(p->p4->rb, kRhs, A, stream); }));
+    VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage4d(p->p4->tile_x, p->p4->tile_y, kRhs, A, stream); }));
     return VP_OK;
 }
 
@@ -184,8 +185,12 @@ vp_status p4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
     double* g = reinterpret_cast<double*>(wsp(work, M.ws_E));
     const double* in[4] = {fd, s2, s3, s2};
     double* out[4] = {s2, s3, s2, fd};
-    const double cacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    // the lean stage schedule (2 + 4 + 3 + 4 state words per cell): stage 2
+    // adds dt/3 k2 to the accumulator, stage 4 dt/6 k4; the other slopes
+    // are read back from the predictors
+    const double cacc[4] = {0.0, dt / 3.0, 0.0, dt / 6.0};
     const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
+    const int kinds[4] = {kLean1, kLean2, kLean3, kLean4};
     Stage4DArgs A = base(p);
     A.fn = fd;
     A.acc = acc;
@@ -196,8 +201,8 @@ vp_status p4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
         A.fout = out[s];
         A.c_acc = cacc[s];
         A.c_next = cnext[s];
-        const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
-        VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage4d(M.rb, kind, A, stream); }));
+        const int kind = kinds[s];
+        VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage4d(M.tile_x, M.tile_y, kind, A, stream); }));
         VP_HIP(timed(p, kTField, stream, [&] {
             return launch_poisson2d(n, M.nx, M.ny, M.dx, M.dy, p->pb.qm, M.d_Qx, M.d_Qy, M.d_invlamT, g, nullptr,
                                     nullptr, a, stream);

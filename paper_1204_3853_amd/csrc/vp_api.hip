@@ -206,14 +206,15 @@ vp_status create_4d(const vp_problem* pb, vp_plan** out)
         return st;
     }
     p->nx = pb->cells[0] * pb->cells[1];        // configuration cells
+    p->shape = StageShape{1024, 4, 4};
     *out = p;
     return VP_OK;
 }
 
-// 2D+2V shapes: one wave per configuration cell, 1, 2 or 4 vx positions per load batch
+// 2D+2V shapes: threads, then a tile of w x tx configuration cells (one wave per cell)
 std::vector<StageShape> shape_table_4d()
 {
-    return {StageShape{256, 1, 1}, StageShape{256, 1, 2}, StageShape{256, 1, 4}};
+    return {StageShape{1024, 4, 4}, StageShape{512, 2, 4}, StageShape{512, 4, 2}, StageShape{256, 2, 2}};
 }
 
 // two-level tile shapes: threads x cells per thread x rows per tile
@@ -359,7 +360,10 @@ vp_status vp_tile_shape_set(vp_plan* p, int32_t index)
     if (p->amr) {
         if (vp_status s = amr_set_shape(p, tab[index].nt, tab[index].w, tab[index].tx)) return s;
     }
-    if (p->p4) p->p4->rb = tab[index].tx;
+    if (p->p4) {
+        p->p4->tile_x = tab[index].w;
+        p->p4->tile_y = tab[index].tx;
+    }
     p->shape = tab[index];
     return VP_OK;
 }

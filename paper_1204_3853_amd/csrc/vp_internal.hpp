@@ -91,6 +91,7 @@ struct Adjoint1DArgs {
 
 constexpr int kMaxPoisson2D = 64;     // configuration cells per direction of the 2D+2V path
 constexpr int kMaxVy4D = 64;          // velocity cells along vy (one lane each)
+constexpr int kMaxVx4D = 1024;        // velocity cells along vx (equilibrium factors staged in LDS)
 
 // Arguments of the 2D+2V stage kernel (FP64).
 struct Stage4DArgs {
@@ -190,7 +191,8 @@ hipError_t launch_poisson1d_inject(const double* n_in, const PoissonExtra& x, in
 hipError_t poisson1d_prepare();
 
 // 2D+2V launchers (vp_kernels_4d.hip)
-hipError_t launch_stage4d(int rb, int kind, const Stage4DArgs& a, hipStream_t stream);
+// tx x ty configuration cells per block (4x4, 2x4, 4x2, 2x2), one wave per cell
+hipError_t launch_stage4d(int tx, int ty, int kind, const Stage4DArgs& a, hipStream_t stream);
 hipError_t launch_moment4d(const double* f, int ncfg, size_t plane, double scale, double* n, hipStream_t stream);
 // g: nx * ny doubles of device scratch (the scaled Fourier coefficients)
 hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
@@ -296,7 +298,7 @@ namespace vp {
 struct Plan4D {
     int nx = 0, ny = 0, nvx = 0, nvy = 0;
     double dx = 0, dy = 0, dvx = 0, dvy = 0, v_lo = 0;
-    int rb = 2;                                      // vx positions per load batch
+    int tile_x = 4, tile_y = 4;                      // configuration cells per block of the stage kernel
     double* d_gx = nullptr;
     double* d_gy = nullptr;
     double* d_Qx = nullptr;

@@ -3,15 +3,17 @@
 //
 // Stage kernel: one wavefront per configuration cell (x, y) advances that
 // cell's whole velocity plane.  Lane l owns the velocity column vy = l and
-// the wave marches along vx; at each vx position it loads the rows of the
+// the wave marches along vx; at each vx position it reads the rows of the
 // nine planes of the stencil (the cell itself and its x +-1, +-2 and
-// y +-1, +-2 neighbours), 64 contiguous doubles per row.  Face averages
-// along x and y are formed from those rows, faces along vx from a rolling
-// window of the march, and faces along vy from neighbouring lanes
-// (cross-lane permutes); the velocity ghosts are products of the 1D
-// equilibrium cell averages.  The wave also sums its output plane, which
-// gives the velocity moment of the configuration cell directly.
+// y +-1, +-2 neighbours), 64 contiguous doubles per row, from rows the
+// block stages in LDS for its whole tile of cells.  Face averages along x
+// and y are formed from those rows, faces along vx from a rolling window of
+// the march, and faces along vy from neighbouring lanes (cross-lane
+// permutes); the velocity ghosts are products of the 1D equilibrium cell
+// averages.  The wave also sums its output plane, which gives the velocity
+// moment of the configuration cell directly.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "vp_internal.hpp"
 #include "vp_stage_tile.hpp"
@@ -39,67 +41,152 @@ __device__ __forceinline__ double f4(double um1, double u0, double u1, double u2
 //   vy: Gvy is the face average along vy of the corresponding U with ay.
 // Ghost cells hold the equilibrium, which is the same in every plane, so
 // V and U there reduce to ax g and ay g.
-// The march is software-pipelined: the rows of NB - 1 positions ahead of
-// the one being consumed are in flight while a position is computed.
-template <int KIND, int NB>
-__global__ __launch_bounds__(256) void k_stage4d(Stage4DArgs A)
+//
+// A block owns a tile of TX x TY configuration cells, one wave per cell.
+// At every vx position the block stages in LDS the rows of all planes its
+// waves read: the tile and a cross-shaped halo two cells deep in x and in
+// y, TX TY + 4 (TX + TY) rows, each loaded once per block (3 rows per cell
+// for a 4 x 4 tile, where a wave loading its own nine rows would take 9).
+// Each wave loads its share of the rows three positions ahead into
+// registers (three register sets), stores the rows of the next position
+// into a three-slot LDS ring after computing the current one, and the
+// block meets at one barrier per position.  Waves whose cell lies past the
+// mesh (partial tiles) load and wait like the others and store nothing.
+// a double that is the same in every lane of the wave, in scalar registers
+__device__ __forceinline__ double uniform_f64(double x)
 {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// DPP wave shifts: lane l reads lane l + 1 (wave_shl:1) or lane l - 1
+// (wave_shr:1); the lane with no source is overridden by the callers
+constexpr int kLaneNext = 0x130;
+constexpr int kLanePrev = 0x138;
+
+template <int TX, int TY>
+struct Tile4D {
+    static constexpr int NW = TX * TY;                 // waves
+    static constexpr int NP = NW + 4 * (TX + TY);      // plane rows per position
+    static constexpr int LPW = (NP + NW - 1) / NW;     // rows loaded per wave per position
+    // LDS row of plane (i, j) relative to the tile origin; (i, j) lies in the
+    // tile or in its cross halo
+    static __device__ __forceinline__ int pid(int i, int j)
+    {
+        if (i >= 0 && i < TX && j >= 0 && j < TY) return i * TY + j;
+        if (j >= 0 && j < TY) return NW + (i < 0 ? i + 2 : i - TX + 2) * TY + j;
+        return NW + 4 * TY + (j < 0 ? j + 2 : j - TY + 2) * TX + i;
+    }
+    // inverse of pid
+    static __device__ __forceinline__ void plane_ij(int q, int& i, int& j)
+    {
+        if (q < NW) { i = q / TY; j = q - i * TY; return; }
+        q -= NW;
+        if (q < 4 * TY) { const int sd = q / TY; j = q - sd * TY; i = sd < 2 ? sd - 2 : TX + sd - 2; return; }
+        q -= 4 * TY;
+        const int sd = q / TX;
+        i = q - sd * TX;
+        j = sd < 2 ? sd - 2 : TY + sd - 2;
+    }
+};
+
+template <int KIND, int TX, int TY>
+__global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
+{
+    using TL = Tile4D<TX, TY>;
+    constexpr int NP = TL::NP, LPW = TL::LPW, NW = TL::NW;
+    static_assert(NP % NW == 0, "every wave loads the same number of ring rows");
+    // ring slots = register sets = prefetch distance in positions
+    constexpr bool NEED_FN = KIND == kStage23 || KIND == kLean2 || KIND == kLean3 || KIND == kLean4;
+    constexpr bool NEED_AC = KIND == kStage23 || KIND == kStage4 || KIND == kLean4;
+    constexpr int S = 3;
+    __shared__ double rows[S][NP][64];
+    __shared__ double gxs[kMaxVx4D + 4];               // vx equilibrium factors with ghosts
+    __shared__ double gys[kMaxVy4D + 4];               // vy equilibrium factors with ghosts
+
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
-    const int cell = xcd_remap((int)blockIdx.x, (int)gridDim.x) * 4 + wave;
     const int nx = A.nx, ny = A.ny, nvx = A.nvx, nvy = A.nvy;
-    if (cell >= nx * ny) return;                        // uniform per wave; the kernel has no block barrier
-    const int x = cell / ny, y = cell - (cell / ny) * ny;
+    const int nty = (ny + TY - 1) / TY;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int x0 = (tile / nty) * TX, y0 = (tile - (tile / nty) * nty) * TY;
+    const int tx = wave / TY, ty = wave - (wave / TY) * TY;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool cell_in = x < nx && y < ny;
     const size_t P = (size_t)nvx * nvy;
     auto cfg = [&](int xx, int yy) { return wrapi(xx, nx) * ny + wrapi(yy, ny); };
-    // the nine planes: c, x-1, x+1, y-1, y+1, x-2, x+2, y-2, y+2
-    const size_t po[9] = {(size_t)cfg(x, y) * P,     (size_t)cfg(x - 1, y) * P, (size_t)cfg(x + 1, y) * P,
-                          (size_t)cfg(x, y - 1) * P, (size_t)cfg(x, y + 1) * P, (size_t)cfg(x - 2, y) * P,
-                          (size_t)cfg(x + 2, y) * P, (size_t)cfg(x, y - 2) * P, (size_t)cfg(x, y + 2) * P};
-    const double* __restrict__ fs = A.fs;
-    const double* ax = A.a;
-    const double* ay = A.a + nx * ny;
-    const double axc = ax[cfg(x, y)], cax_x = (ax[cfg(x + 1, y)] - ax[cfg(x - 1, y)]) * (1.0 / 48.0),
-                 cax_y = (ax[cfg(x, y + 1)] - ax[cfg(x, y - 1)]) * (1.0 / 48.0);
-    const double ayc = ay[cfg(x, y)], cay_x = (ay[cfg(x + 1, y)] - ay[cfg(x - 1, y)]) * (1.0 / 48.0),
-                 cay_y = (ay[cfg(x, y + 1)] - ay[cfg(x, y - 1)]) * (1.0 / 48.0);
 
     const bool act = lane < nvy;
     const int vyl = act ? lane : nvy - 1;
-    double gyd[5];                                      // vy equilibrium factors at lane - 2 .. lane + 2
+    // rows this wave loads each position: planes wave, wave + NW, ...
+    // (element offsets below 2^31: nx, ny <= 64, nvx <= 1024, nvy <= 64)
+    unsigned lpo[LPW];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) gyd[d] = A.gy[min(max(lane + d, 0), nvy + 3)];
-    const double gyl = gyd[2];
+    for (int k = 0; k < LPW; ++k) {
+        int i = 0, j = 0;
+        TL::plane_ij(wave + k * NW, i, j);
+        lpo[k] = (unsigned)((size_t)cfg(x0 + i, y0 + j) * P + vyl);
+    }
+    for (int q = (int)threadIdx.x; q < nvx + 4; q += 64 * NW) gxs[q] = A.gx[q];
+    for (int q = (int)threadIdx.x; q < nvy + 4; q += 64 * NW) gys[q] = A.gy[q];
+    // rows this wave reads: c, x-1, x+1, y-1, y+1, x-2, x+2, y-2, y+2
+    const int rp[9] = {TL::pid(tx, ty),     TL::pid(tx - 1, ty), TL::pid(tx + 1, ty),
+                       TL::pid(tx, ty - 1), TL::pid(tx, ty + 1), TL::pid(tx - 2, ty),
+                       TL::pid(tx + 2, ty), TL::pid(tx, ty - 2), TL::pid(tx, ty + 2)};
+    const size_t po_c = (size_t)cfg(x, y) * P;
+
+    const double* ax = A.a;
+    const double* ay = A.a + nx * ny;
+    // the wave's accelerations are the same in every lane: keep them in scalar registers
+    const double axc = uniform_f64(ax[cfg(x, y)]),
+                 cax_x = uniform_f64((ax[cfg(x + 1, y)] - ax[cfg(x - 1, y)]) * (1.0 / 48.0)),
+                 cax_y = uniform_f64((ax[cfg(x, y + 1)] - ax[cfg(x, y - 1)]) * (1.0 / 48.0));
+    const double ayc = uniform_f64(ay[cfg(x, y)]),
+                 cay_x = uniform_f64((ay[cfg(x + 1, y)] - ay[cfg(x - 1, y)]) * (1.0 / 48.0)),
+                 cay_y = uniform_f64((ay[cfg(x, y + 1)] - ay[cfg(x, y - 1)]) * (1.0 / 48.0));
+    // vy equilibrium factor of vy cell j (-2 <= j < nvy + 2), staged in LDS
+    auto gy_at = [&](int j) { return gys[min(max(j + 2, 0), nvy + 3)]; };
     const double vby = A.vy_lo + ((double)lane + 0.5) * A.dvy;
     const double dxi = A.dxi, dyi = A.dyi, dvxi = A.dvxi, dvyi = A.dvyi, dvx24 = A.dvx24, dvy24 = A.dvy24;
 
-    // lane + d of a per-lane quantity whose ghost value at lane + d is gq * gy[lane + d]
-    auto nb = [&](double u, int d, double gq) {
-        const double s = __shfl(u, lane + d, 64);
+    // sv = the value of lane + d of a per-lane quantity whose ghost value at
+    // lane + d is gq * gy[lane + d]; lanes past the velocity range take the ghost
+    auto nb = [&](double sv, int d, double gq) {
         const int src = lane + d;
-        return (src >= 0 && src < nvy) ? s : gq * gyd[d + 2];
+        return (src >= 0 && src < nvy) ? sv : gq * gy_at(src);
     };
 
-    double Lb[NB][9], FNb[NB], ACb[NB];
-    // loads of lead position p (and of f^n / acc at the output position p - 2) into slot s
-    auto issue = [&](int p, int s) {
-        const int pc = min(max(p, 0), nvx - 1);
-        const size_t o = (size_t)pc * nvy + vyl;
+    // Iteration m takes in position m - 2 (slot m mod S) and, from m = 4 on,
+    // produces the output at position t = m - 4.  Loads are clamped to the
+    // mesh so that they are unconditional (a load under a branch would be
+    // waited for).
+    const double* __restrict__ fs = A.fs;
+    auto load_rows = [&](int m, double* dst) {
+        const size_t o = (size_t)min(max(m - 2, 0), nvx - 1) * nvy;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Lb[s][q] = fs[po[q] + o];
-        const size_t oo = po[0] + (size_t)min(max(p - 2, 0), nvx - 1) * nvy + vyl;
-        if (KIND == kStage23) FNb[s] = __builtin_nontemporal_load(A.fn + oo);
-        if (KIND == kStage23 || KIND == kStage4) ACb[s] = __builtin_nontemporal_load(A.acc + oo);
+        for (int k = 0; k < LPW; ++k) dst[k] = fs[lpo[k] + o];
+    };
+    auto store_rows = [&](int slot, const double* src) {
+#pragma unroll
+        for (int k = 0; k < LPW; ++k) rows[slot][wave + k * NW][lane] = src[k];
+    };
+    auto load_own = [&](int m, double& fnv, double& acv) {
+        const size_t o = po_c + (size_t)min(max(m - 4, 0), nvx - 1) * nvy + vyl;
+        if (NEED_FN) fnv = __builtin_nontemporal_load(A.fn + o);
+        if (NEED_AC) acv = __builtin_nontemporal_load(A.acc + o);
     };
 
     // rolling state along vx: V at t-1 .. t+2, U, f and Dx at t-1/t .. t+2, Dy at t .. t+2
     double vw[4] = {0, 0, 0, 0}, uw[3] = {0, 0, 0}, cw[3] = {0, 0, 0}, dxw[4] = {0, 0, 0, 0}, dyw[3] = {0, 0, 0};
-    auto shift_in = [&](const double* r, int p) {
+    auto shift_in = [&](int slot, int p) {
+        double (*rs)[64] = rows[slot];
         const bool in = p >= 0 && p < nvx;
-        const double g = A.gx[min(max(p + 2, 0), nvx + 3)] * gyl;
+        const double g = gxs[min(max(p + 2, 0), nvx + 3)] * gy_at(lane);
         double v[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) v[q] = in ? r[q] : g;
+        for (int q = 0; q < 9; ++q) v[q] = in ? rs[rp[q]][lane] : g;
         vw[0] = vw[1]; vw[1] = vw[2]; vw[2] = vw[3];
         vw[3] = axc * v[0] + (cax_x * (v[2] - v[1]) + cax_y * (v[4] - v[3]));
         uw[0] = uw[1]; uw[1] = uw[2];
@@ -111,72 +198,93 @@ __global__ __launch_bounds__(256) void k_stage4d(Stage4DArgs A)
         dyw[2] = (8.0 * (v[4] - v[3]) - (v[8] - v[7])) * (1.0 / 12.0);
     };
 
+    const int M = nvx + 4;
+    double pr[S][LPW], fnr[S], acr[S];
 #pragma unroll
-    for (int p = -2; p <= 1; ++p) {
-        issue(p, 0);
-        shift_in(Lb[0], p);
+    for (int q = 0; q < S; ++q) {
+        load_rows(q, pr[q]);
+        fnr[q] = 0.0;
+        acr[q] = 0.0;
     }
-    double gvx_lo = f4(vw[0], vw[1], vw[2], vw[3]);      // face -1/2
-    double msum = 0.0;
-    const double cacc = A.c_acc, cnext = A.c_next;
-#pragma unroll
-    for (int s = 0; s < NB - 1; ++s) issue(2 + s, s);
+    store_rows(0, pr[0]);
+    __syncthreads();
 
-#pragma unroll 1
-    for (int tb = 0; tb < nvx; tb += NB) {
-#pragma unroll
-        for (int s = 0; s < NB; ++s) {
-            const int t = tb + s;
-            issue(t + 2 + NB - 1, (s + NB - 1) % NB);
-            shift_in(Lb[s], t + 2);
-            if (t >= nvx) continue;                      // uniform
-            const double gxt = A.gx[t + 2];
+    double gvx_lo = 0.0, msum = 0.0;
+    const double cacc = A.c_acc, cnext = A.c_next;
+    // iteration m = m0 + SB uses slot and register set SB (m0 is a multiple
+    // of S), so every slot and set index is a constant
+    int m0 = 0;
+    auto iter = [&](auto sbc) {
+        constexpr int SB = decltype(sbc)::value;
+        constexpr int sb = SB;
+        constexpr int SN = (SB + 1) % S;
+        const int m = m0 + SB;
+        load_rows(m + S, pr[SB]);                        // set SB held the rows of m, stored at m - 1
+        shift_in(SB, m - 2);
+        if (m == 3) gvx_lo = f4(vw[0], vw[1], vw[2], vw[3]);   // face -1/2
+        const int t = m - 4;
+        if (t >= 0 && t < nvx) {                     // uniform
+            const double gxt = gxs[t + 2];
             // x and y: differences of the face fluxes
             const double vbx = A.vx_lo + ((double)t + 0.5) * A.dvx;
             const double kx = (vbx * dxw[1] + dvx24 * (dxw[2] - dxw[0])) * dxi;
-            const double ky = (vby * dyw[0] + dvy24 * (nb(dyw[0], 1, 0.0) - nb(dyw[0], -1, 0.0))) * dyi;
+            const double dyn = dpp_f64<kLaneNext>(dyw[0]), dyp = dpp_f64<kLanePrev>(dyw[0]);
+            const double ky = (vby * dyw[0] + dvy24 * (nb(dyn, 1, 0.0) - nb(dyp, -1, 0.0))) * dyi;
             // vx
             const double gvx_hi = f4(vw[0], vw[1], vw[2], vw[3]);
             // vy: upper face from lanes -1 .. +2; lower face from lane - 1 (lane 0: the box face)
             const double gu = ayc * gxt;
             const double u0 = uw[0];
-            const double um = nb(u0, -1, gu), u1 = nb(u0, 1, gu), u2 = nb(u0, 2, gu);
+            const double r1 = dpp_f64<kLaneNext>(u0), r2 = dpp_f64<kLaneNext>(r1), rm = dpp_f64<kLanePrev>(u0);
+            const double um = nb(rm, -1, gu), u1 = nb(r1, 1, gu), u2 = nb(r2, 2, gu);
             const double gvy_hi = f4(um, u0, u1, u2);
-            const double gvy_b = f4(gu * gyd[0], um, u0, u1);
-            const double gvy_s = __shfl(gvy_hi, lane - 1, 64);
+            const double gvy_b = f4(gu * gy_at(lane - 2), um, u0, u1);
+            const double gvy_s = dpp_f64<kLanePrev>(gvy_hi);
             const double gvy_lo = lane == 0 ? gvy_b : gvy_s;
 
             const double k = -kx - ky - (gvx_hi - gvx_lo) * dvxi - (gvy_hi - gvy_lo) * dvyi;
             gvx_lo = gvx_hi;
 
-            const size_t o = po[0] + (size_t)t * nvy + lane;
+            const size_t o = po_c + (size_t)t * nvy + lane;
+            const bool st = act && cell_in;
+            const double f0 = cw[0];                 // the stage state at the output position
             double out;
             if (KIND == kRhs) {
                 out = k;
-                if (act) __builtin_nontemporal_store(out, A.fout + o);
             } else if (KIND == kStage1) {
-                const double f0 = cw[0];
                 out = f0 + cnext * k;
-                if (act) {
-                    __builtin_nontemporal_store(f0 + cacc * k, A.acc + o);
-                    __builtin_nontemporal_store(out, A.fout + o);
-                }
+                if (st) __builtin_nontemporal_store(f0 + cacc * k, A.acc + o);
             } else if (KIND == kStage23) {
-                out = FNb[s] + cnext * k;
-                if (act) {
-                    __builtin_nontemporal_store(ACb[s] + cacc * k, A.acc + o);
-                    __builtin_nontemporal_store(out, A.fout + o);
-                }
-            } else {
-                out = ACb[s] + cacc * k;
-                if (act) __builtin_nontemporal_store(out, A.fout + o);
+                out = fnr[sb] + cnext * k;
+                if (st) __builtin_nontemporal_store(acr[sb] + cacc * k, A.acc + o);
+            } else if (KIND == kStage4) {
+                out = acr[sb] + cacc * k;
+            } else if (KIND == kLean1) {
+                out = f0 + cnext * k;
+            } else if (KIND == kLean2) {
+                out = fnr[sb] + cnext * k;
+                if (st) __builtin_nontemporal_store(fnr[sb] + ((f0 - fnr[sb]) * (1.0 / 3.0) + cacc * k), A.acc + o);
+            } else if (KIND == kLean3) {
+                out = fnr[sb] + cnext * k;
+            } else {                                 // kLean4
+                out = acr[sb] + ((f0 - fnr[sb]) * (1.0 / 3.0) + cacc * k);
             }
+            if (st) __builtin_nontemporal_store(out, A.fout + o);
             if (act) msum += out;
         }
+        load_own(m + S, fnr[sb], acr[sb]);           // for iteration m + S
+        store_rows(SN, pr[SN]);                          // the rows of m + 1, loaded at m + 1 - S
+        __syncthreads();
+    };
+#pragma unroll 1
+    for (; m0 < M; m0 += S) {
+        iter(std::integral_constant<int, 0>{});
+        iter(std::integral_constant<int, 1>{});
+        if constexpr (S == 3) iter(std::integral_constant<int, 2 % S>{});
     }
-    if (KIND != kRhs && A.n) {
-        const double s = wave_sum(msum);
-        if (lane == 0) A.n[cell] = s * A.mscale;
+    if (KIND != kRhs && A.n && cell_in) {
+        const double sm = wave_sum(msum);
+        if (lane == 0) A.n[cfg(x, y)] = sm * A.mscale;
     }
 }
 
@@ -340,28 +448,28 @@ __global__ __launch_bounds__(256) void k_poisson2d_inv(const double* __restrict_
 }
 
 template <int KIND>
-hipError_t launch_stage4d_k(int rb, const Stage4DArgs& a, hipStream_t stream)
+hipError_t launch_stage4d_k(int tx, int ty, const Stage4DArgs& a, hipStream_t stream)
 {
-    const int ncfg = a.nx * a.ny;
-    const dim3 g((ncfg + 3) / 4), b(256);
-    switch (rb) {
-    case 1: hipLaunchKernelGGL((k_stage4d<KIND, 2>), g, b, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((k_stage4d<KIND, 3>), g, b, 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((k_stage4d<KIND, 4>), g, b, 0, stream, a); break;
-    default: return hipErrorInvalidValue;
-    }
+    const dim3 g((unsigned)(((a.nx + tx - 1) / tx) * ((a.ny + ty - 1) / ty)));
+    if (tx == 4 && ty == 4) hipLaunchKernelGGL((k_stage4d<KIND, 4, 4>), g, dim3(1024), 0, stream, a);
+    else if (tx == 2 && ty == 4) hipLaunchKernelGGL((k_stage4d<KIND, 2, 4>), g, dim3(512), 0, stream, a);
+    else if (tx == 4 && ty == 2) hipLaunchKernelGGL((k_stage4d<KIND, 4, 2>), g, dim3(512), 0, stream, a);
+    else if (tx == 2 && ty == 2) hipLaunchKernelGGL((k_stage4d<KIND, 2, 2>), g, dim3(256), 0, stream, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_stage4d(int rb, int kind, const Stage4DArgs& a, hipStream_t stream)
+hipError_t launch_stage4d(int tx, int ty, int kind, const Stage4DArgs& a, hipStream_t stream)
 {
     switch (kind) {
-    case kRhs: return launch_stage4d_k<kRhs>(rb, a, stream);
-    case kStage1: return launch_stage4d_k<kStage1>(rb, a, stream);
-    case kStage23: return launch_stage4d_k<kStage23>(rb, a, stream);
-    default: return launch_stage4d_k<kStage4>(rb, a, stream);
+    case kRhs: return launch_stage4d_k<kRhs>(tx, ty, a, stream);
+    case kLean1: return launch_stage4d_k<kLean1>(tx, ty, a, stream);
+    case kLean2: return launch_stage4d_k<kLean2>(tx, ty, a, stream);
+    case kLean3: return launch_stage4d_k<kLean3>(tx, ty, a, stream);
+    case kLean4: return launch_stage4d_k<kLean4>(tx, ty, a, stream);
+    default: return hipErrorInvalidValue;
     }
 }
 
