@@ -79,6 +79,8 @@ typedef enum vp_dtype { VP_F64 = 0, VP_F32 = 1 } vp_dtype;
  *             equilibrium supplied on both ends); in 2D+2V the equilibrium
  *             is the product veq[l][0][j] * veq[l][1][k].  Copied at plan
  *             creation.
+ * 2D+2V plans are single-level FP64 with nx, ny <= 64, nvx <= 1024 and
+ * nvy <= 64 (VP_ENOTSUP otherwise).
  */
 typedef struct vp_problem {
     int32_t ndim;
@@ -285,7 +287,9 @@ vp_status vp_field_adjoint(const vp_plan* plan, const double* abar, void* fbar, 
 
 /*
  * Tile shapes of the stage kernels, for autotuning.  A shape is (threads
- * per block, velocity cells per thread, configuration rows per tile).
+ * per block, velocity cells per thread, configuration rows per tile); on
+ * 2D+2V plans it is (threads per block, configuration cells of the tile
+ * along x, along y), one wavefront per configuration cell.
  * vp_tile_shape_count / _get enumerate the shapes compiled for the plan
  * (its dtype and number of levels); vp_tile_shape_set selects one for
  * every later call on the plan (results agree to rounding for every shape;
