@@ -132,17 +132,29 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_chunks(const double* __re
     const int c0 = blockIdx.x * kFieldChunk;
     if (t <= K) gs[t] = green[t];
     const double scale = 12.0 * dx * dx;
-    for (int q = t; q < kFieldChunk + 2 * K; q += kFieldChunk) {
-        const int i = wrapi(c0 - K + q, nx);
-        double v[16];
-        double acc = 0.0;
-        for (int s0 = 0; s0 < nstrip; s0 += 16) {
+    // the moments of rows c0 - K .. c0 + kFieldChunk + K - 1 (periodic); the
+    // loads of both rows a thread owns are in flight together
+    constexpr int NQ = (kFieldChunk + 2 * K + kFieldChunk - 1) / kFieldChunk;
+    double acc[NQ];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = (s0 + u < nstrip) ? part[(size_t)(s0 + u) * nx + i] : 0.0;
+    for (int u = 0; u < NQ; ++u) acc[u] = 0.0;
+    for (int s0 = 0; s0 < nstrip; s0 += 8) {
+        double v[NQ][8];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) acc += v[u];
+        for (int u = 0; u < NQ; ++u) {
+            const int i = wrapi(c0 - K + min(t + u * kFieldChunk, kFieldChunk + 2 * K - 1), nx);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) v[u][m] = (s0 + m < nstrip) ? part[(size_t)(s0 + m) * nx + i] : 0.0;
         }
-        r[q] = scale * (1.0 - dv * acc);
+#pragma unroll
+        for (int u = 0; u < NQ; ++u)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) acc[u] += v[u][m];
+    }
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = t + u * kFieldChunk;
+        if (q < kFieldChunk + 2 * K) r[q] = scale * (1.0 - dv * acc[u]);
     }
     __syncthreads();
     const int i = c0 + t;
@@ -174,21 +186,28 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
 {
     __shared__ double d[kFieldChunk + 4];     // d_i for i = c0 - 2 .. c0 + kFieldChunk + 1
     __shared__ double red[kFieldChunk / 64];
+    __shared__ double cs[2 * (kMaxPoisson1D / kFieldChunk)];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int c = blockIdx.x, c0 = c * kFieldChunk;
+    // the rows of y this block reads, loaded while the chunk sums are summed
+    const double yt = y[wrapi(c0 + t, nx)];
+    const double ye0 = y[wrapi(c0 + kFieldChunk, nx)], ye1 = y[wrapi(c0 + kFieldChunk + 1, nx)];
+    const double ym1 = y[wrapi(c0 - 1, nx)];
+    if (t < 2 * nchunk) cs[t] = csum[t];
+    __syncthreads();
     // global sums and the prefix of y - mean(y) up to the chunk start, in chunk order
     double sy = 0.0, sw = 0.0, pre = 0.0;
     for (int q = 0; q < nchunk; ++q) {
         if (q == c) pre = sy;
-        sy += csum[2 * q];
-        sw += csum[2 * q + 1];
+        sy += cs[2 * q];
+        sw += cs[2 * q + 1];
     }
     const double ybar = sy / nx;
     const double mean_D = (sw - ybar * 0.5 * (double)nx * (double)(nx + 1)) / nx;
     const double off = pre - ybar * (double)c0 - mean_D;            // d_{c0 - 1}
     // inclusive scan of y - mean(y) over rows c0 .. c0 + kFieldChunk + 1 (periodic)
-    const double yv = y[wrapi(c0 + t, nx)] - ybar;
+    const double yv = yt - ybar;
     double x = yv;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -204,14 +223,14 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
         // rows past the chunk: d continues with y of rows c0 + 256, c0 + 257
         double tail = 0.0;
         for (int w = 0; w < kFieldChunk / 64; ++w) tail += red[w];
-        double e = off + tail + (y[wrapi(c0 + kFieldChunk, nx)] - ybar);
-        if (t == 1) e += y[wrapi(c0 + kFieldChunk + 1, nx)] - ybar;
+        double e = off + tail + (ye0 - ybar);
+        if (t == 1) e += ye1 - ybar;
         d[kFieldChunk + 2 + t] = e;
     }
     if (t == 0) {
         // rows before the chunk: d_{c0 - 1} = off, d_{c0 - 2} = off - (y_{c0 - 1} - mean y)
         d[1] = off;
-        d[0] = off - (y[wrapi(c0 - 1, nx)] - ybar);
+        d[0] = off - (ym1 - ybar);
     }
     __syncthreads();
     const int i = c0 + t;
