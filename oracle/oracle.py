@@ -14,7 +14,8 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["vp_oracle.c", "vp_oracle_adjoint.c", "vp_oracle_amr.c", "vp_oracle_4d.c", "vp_oracle_limited.c"]
+SOURCES = ["vp_oracle.c", "vp_oracle_adjoint.c", "vp_oracle_amr.c", "vp_oracle_4d.c", "vp_oracle_limited.c",
+           "vp_oracle_regrid.c"]
 LIB = os.path.join(HERE, "libvp_oracle.so")
 
 
@@ -96,6 +97,10 @@ def _declare_extra(L):
         "vpo_rhs_limited": (None, [_I, _I, _F, _F, _F, _D, _D, _D, _D]),
         "vpo_rk4_step_limited": (None, [_V, _D, _D, _F]),
         "vpo_rk4_step_fixed_a_limited": (None, [_V, _D, _D, _D, _F]),
+        "vpo_tag_value": (_F, [_I, _I, _F, _F, _D, _D, _I, _I]),
+        "vpo_tag": (None, [_I, _I, _F, _F, _D, _D, _F, ctypes.POINTER(ctypes.c_ubyte)]),
+        "vpo_prolong1d": (None, [_D, _I, _D]),
+        "vpo_prolong_box": (None, [_I, _I, _D, _D, _I, _I, _I, _I, _I, _D]),
         "vpo4_ctx_new": (_V, [_I, _I, _I, _I, _F, _F, _F, _F, _F, _D, _D]),
         "vpo4_ctx_free": (None, [_V]),
         "vpo4_moment": (None, [_V, _D, _D]),
@@ -194,6 +199,48 @@ def rhs_adjoint(f, a, kbar, dx, dv, v_lo, vghost):
     lib().vpo_rhs_adjoint(f.shape[0], f.shape[1], dx, dv, v_lo, _p(vg), _p(f), _p(a), _p(kb),
                           _p(fb), _p(ab))
     return fb, ab
+
+
+def tag_values(f, dx, dv, vghost):
+    """delta1 f + delta2 f of every cell of a level (section 3, refinement criterion)."""
+    f = _f64(f)
+    nx, nv = f.shape
+    vg = _f64(vghost)
+    out = np.empty((nx, nv))
+    L = lib()
+    for i in range(nx):
+        for j in range(nv):
+            out[i, j] = L.vpo_tag_value(nx, nv, dx, dv, _p(vg), _p(f), i, j)
+    return out
+
+
+def tag(f, dx, dv, vghost, tol):
+    """1 where delta1 f + delta2 f > tol, else 0 (uint8 [nx][nv])."""
+    f = _f64(f)
+    nx, nv = f.shape
+    vg = _f64(vghost)
+    t = np.zeros((nx, nv), dtype=np.uint8)
+    lib().vpo_tag(nx, nv, dx, dv, _p(vg), _p(f), tol, t.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    return t
+
+
+def prolong1d(u, R):
+    """R fine cell averages of the middle of five coarse cell averages (section 3, conservative
+    limited interpolation)."""
+    u = _f64(u)
+    out = np.empty(R)
+    lib().vpo_prolong1d(_p(u), R, _p(out))
+    return out
+
+
+def prolong_box(fc, vghost_c, R, box):
+    """Fine cell averages on the level-1 box (fx0, fv0, fx1, fv1), x then v."""
+    fc = _f64(fc)
+    vg = _f64(vghost_c)
+    fx0, fv0, fx1, fv1 = box
+    out = np.empty((fx1 - fx0 + 1, fv1 - fv0 + 1))
+    lib().vpo_prolong_box(fc.shape[0], fc.shape[1], _p(fc), _p(vg), R, fx0, fv0, fx1, fv1, _p(out))
+    return out
 
 
 class Oracle1D:

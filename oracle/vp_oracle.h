@@ -56,6 +56,14 @@ void vpo_amr_reduce_mask(void* h, double* f, double* n);
 void vpo_amr_constraints(void* h, double* f, double* a, double* E_out);
 void vpo_amr_rhs(void* h, double* f, double* a, double* k);
 
+/* regridding (section 3): refinement criterion and conservative limited interpolation */
+double vpo_tag_value(int nx, int nv, double dx, double dv, const double* vghost, const double* f, int i, int j);
+void vpo_tag(int nx, int nv, double dx, double dv, const double* vghost, const double* f, double tol,
+             unsigned char* tags);
+void vpo_prolong1d(const double* u, int R, double* out);
+void vpo_prolong_box(int ncx, int ncv, const double* fc, const double* vghost_c, int R, int fx0, int fv0, int fx1,
+                     int fv1, double* out);
+
 /* limited face averages (section 2, eq. limitedFace), 1D+1V single level */
 double vpo_face_limited(double um1, double u0, double u1, double u2, int upwind_left);
 void vpo_rhs_limited(int nx, int nv, double dx, double dv, double v_lo, const double* vghost, const double* f,

@@ -1,0 +1,155 @@
+"""Pins of the regridding pieces of section 3 in the oracle.
+
+Conservative, limited, high-order interpolation (eqs. aux1, aux2,
+interp_r_avg, renormalisation):
+- fine averages agree with a derivation from the definitions: for each of
+  the three candidates, the quadratic with the given cell averages on its
+  three-cell stencil averaged over the sub-cells; Jiang-Shu smoothness as
+  the integral of p'^2 + p''^2 over the coarse cell; weights
+  d_r / (eps + beta_r)^2 normalised.  This fixes the reading of the
+  printed B^(0) (the printed 2 D_i - D_{i-1} fails it);
+- exact conservation of every coarse cell average (1D and the 2D tensor
+  form), exactness for quadratics (every candidate is quadratic);
+- next to a step the interpolation takes the smooth stencil (no
+  overshoot), where fixed ideal weights overshoot.
+
+Refinement criterion delta1 f + delta2 f > tol:
+- closed forms for linear and quadratic data and the powers of the mesh
+  spacing the estimates carry (delta1 ~ h^(3/2) for fixed slopes, delta2
+  ~ h^4 for fixed curvature), translation covariance in periodic x,
+  reflection symmetry, zero for a constant field with matching ghosts.
+"""
+import numpy as np
+import pytest
+from numpy.polynomial import Polynomial
+
+
+def definition_prolong(u, R, eps=1e-6):
+    d = [0.3, 0.6, 0.1]
+    fine = np.zeros(R)
+    alphas, cands = [], []
+    for r in range(3):
+        cells = [(k - r, k - r + 1) for k in range(3)]           # xi intervals, cell i = [0, 1]
+        avgs = [u[2 - r + k] for k in range(3)]
+        A = np.array([[1.0, (b * b - a * a) / 2.0, (b ** 3 - a ** 3) / 3.0] for a, b in cells])
+        p = Polynomial(np.linalg.solve(A, avgs))
+        P = p.integ()
+        cands.append(np.array([(P((s + 1) / R) - P(s / R)) * R for s in range(R)]))
+        s1 = (p.deriv() ** 2).integ()
+        s2 = (p.deriv(2) ** 2).integ()
+        beta = (s1(1) - s1(0)) + (s2(1) - s2(0))
+        alphas.append(d[r] / (eps + beta) ** 2)
+    w = np.array(alphas) / sum(alphas)
+    for r in range(3):
+        fine += w[r] * cands[r]
+    return fine
+
+
+@pytest.mark.parametrize("R", [2, 4])
+def test_prolong_matches_definition(oracle, R):
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        u = rng.standard_normal(5) * rng.choice([1e-2, 1.0, 10.0])
+        got = oracle.prolong1d(u, R)
+        want = definition_prolong(u, R)
+        assert np.abs(got - want).max() <= 1e-11 * max(1.0, np.abs(u).max()), (u, got, want)
+
+
+def test_printed_b0_fails_the_definition(oracle):
+    """The printed B^(0) = 2 D_i - D_{i-1} is not the quadratic's slope on cells i, i+1, i+2."""
+    u = np.array([0.0, 1.0, 0.5, 3.0, 2.0])
+    D = np.diff(u)
+    b_printed = 2 * D[2] - D[1]
+    b_def = 2 * D[2] - D[3]
+    assert abs(b_printed - b_def) > 0.1
+
+
+@pytest.mark.parametrize("R", [2, 3, 4, 8])
+def test_prolong_conserves(oracle, R):
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        u = rng.random(5) * 10.0
+        f = oracle.prolong1d(u, R)
+        assert abs(f.mean() - u[2]) <= 4e-15 * abs(u[2])
+
+
+@pytest.mark.parametrize("R", [2, 4])
+def test_prolong_exact_for_quadratics(oracle, R):
+    c0, c1, c2 = 0.3, -1.2, 0.7
+    P = Polynomial([c0, c1, c2]).integ()
+    u = np.array([P(k + 1) - P(k) for k in range(-2, 3)])     # cells [-2,-1] .. [2,3], cell i = [0,1]
+    want = np.array([(P((s + 1) / R) - P(s / R)) * R for s in range(R)])
+    assert np.abs(oracle.prolong1d(u, R) - want).max() <= 1e-14
+
+
+def test_prolong_takes_the_smooth_side_of_a_step(oracle):
+    R = 4
+    u = np.array([0.0, 0.0, 1.0, 1.0, 1.0])
+    f = oracle.prolong1d(u, R)
+    assert np.abs(f - 1.0).max() <= 1e-9
+    # fixed ideal weights (d_r) would put a new extremum in the cell
+    ideal = definition_prolong(u, R, eps=1e30)
+    assert ideal.max() > 1.0 + 1e-2 or ideal.min() < 1.0 - 1e-2
+
+
+def test_prolong_box_conserves_and_is_exact_for_quadratics(oracle):
+    R, ncx, ncv = 4, 16, 12
+    rng = np.random.default_rng(9)
+    fc = rng.random((ncx, ncv)) + 0.5
+    vg = rng.random(4) + 0.5
+    box = (8, 12, 31, 35)                                     # level-1 indices, aligned to R
+    f = oracle.prolong_box(fc, vg, R, box)
+    assert f.shape == (24, 24)
+    for cx in range(box[0] // R, box[2] // R + 1):
+        for cv in range(box[1] // R, box[3] // R + 1):
+            blk = f[(cx * R - box[0]):(cx * R - box[0] + R), (cv * R - box[1]):(cv * R - box[1] + R)]
+            assert abs(blk.mean() - fc[cx, cv]) <= 1e-14 * fc[cx, cv]
+    # tensor quadratic away from the periodic seam and the v ghosts
+    Px = Polynomial([0.2, 0.05, -0.01]).integ()
+    Pv = Polynomial([1.0, -0.03, 0.02]).integ()
+    cx_avg = np.array([Px(k + 1) - Px(k) for k in range(ncx)])
+    cv_avg = np.array([Pv(k + 1) - Pv(k) for k in range(ncv)])
+    fq = cx_avg[:, None] * cv_avg[None, :]
+    fine = oracle.prolong_box(fq, vg, R, (12, 12, 27, 27))
+    fx = np.array([(Px((k + 1) / R) - Px(k / R)) * R for k in range(12, 28)])
+    fv = np.array([(Pv((k + 1) / R) - Pv(k / R)) * R for k in range(12, 28)])
+    assert np.abs(fine - fx[:, None] * fv[None, :]).max() <= 1e-13
+
+
+def test_tag_closed_forms_and_scaling(oracle):
+    a, b = 0.7, -0.4
+    for n, h in ((32, 0.1), (64, 0.05)):
+        x = (np.arange(n) + 0.5) * h
+        v = (np.arange(n) + 0.5) * h
+        f = a * x[:, None] + b * v[None, :]                    # cell averages of a linear field
+        t = oracle.tag_values(f, h, h, np.zeros(4))
+        d1 = np.sqrt(0.5 * (h * (2 * a * h) ** 2 + h * (2 * b * h) ** 2))
+        assert np.abs(t[2:-2, 2:-2] - d1).max() <= 1e-13
+    # delta1 carries h^(3/2) for a fixed slope, delta2 h^4 for a fixed curvature
+    vals1, vals2 = [], []
+    for h in (0.1, 0.05):
+        n = 40
+        x = (np.arange(n) + 0.5) * h
+        f1 = 2.0 * x[:, None] + 0 * x[None, :]
+        vals1.append(oracle.tag_values(f1, h, h, np.zeros(4))[10, 10])
+        P = Polynomial([0, 0, 3.0]).integ()                    # 3 (x - xc)^2 centred on cell 10: delta1 = 0 there
+        avg = np.array([(P((k + 1 - 10.5) * h) - P((k - 10.5) * h)) / h for k in range(n)])
+        f2 = avg[:, None] + 0 * x[None, :]
+        vals2.append(oracle.tag_values(f2, h, h, np.zeros(4))[10, 10])
+    assert abs(np.log2(vals1[0] / vals1[1]) - 1.5) < 1e-9
+    assert abs(np.log2(vals2[0] / vals2[1]) - 4.0) < 1e-9
+
+
+def test_tag_covariance_and_constant(oracle):
+    rng = np.random.default_rng(3)
+    f = rng.random((24, 20))
+    vg = rng.random(4)
+    t = oracle.tag_values(f, 0.3, 0.2, vg)
+    ts = oracle.tag_values(np.roll(f, 5, axis=0), 0.3, 0.2, vg)
+    assert np.array_equal(np.roll(t, 5, axis=0), ts)
+    tr = oracle.tag_values(f[::-1].copy(), 0.3, 0.2, vg)
+    assert np.abs(tr[::-1] - t).max() <= 1e-15 * np.abs(t).max()
+    c = np.full((24, 20), 0.7)
+    assert np.all(oracle.tag_values(c, 0.3, 0.2, np.full(4, 0.7)) == 0.0)
+    tags = oracle.tag(f, 0.3, 0.2, vg, float(np.median(t)))
+    assert np.array_equal(tags, (t > np.median(t)).astype(np.uint8))
