@@ -343,6 +343,64 @@ vp_status vp_autotune(vp_plan* plan, void* f, double* a, double dt, int32_t reps
 vp_status vp_timing_enable(vp_plan* plan, int32_t enable);
 vp_status vp_timing_read(vp_plan* plan, double* ms, int64_t* counts, int32_t nclass);
 
+/*
+ * Regridding (section 3).
+ *
+ * vp_tag_cells: the refinement criterion of section 3 (mesh refinement
+ * criteria) on level 0 of a 1D+1V FP64 plan (the single level, or the
+ * coarse level of two): a cell is tagged when
+ *   delta1 f + delta2 f > tol,
+ *   delta1 f = [ 1/2 sum_d h_d (f(+e_d) - f(-e_d))^2 ]^(1/2),
+ *   delta2 f = 1/2 sum_d h_d^2 |f(+e_d) - 2 f + f(-e_d)|,
+ * summed over d = x, v (as printed), x periodic, velocity ghosts the
+ * equilibrium.  The value is formed in a fixed order without fused
+ * multiply-adds and with a correctly rounded square root, so that it is
+ * reproducible bit for bit.
+ *   f       the state (level 0 is read)
+ *   tags    output, device uint8 [ncx][ncv]: 1 where tagged, else 0
+ *   values  output or NULL: delta1 f + delta2 f per level-0 cell (double)
+ * Enqueued on `stream`; VP_ENOTSUP for 2D+2V or FP32 plans.
+ */
+vp_status vp_tag_cells(const vp_plan* plan, const void* f, double tol, uint8_t* tags, double* values,
+                       hipStream_t stream);
+
+/*
+ * vp_cluster_tags (host, no device work): level-1 boxes that cover the
+ * tagged level-0 cells, by Berger-Rigoutsos clustering (the paper leaves
+ * the clustering to its AMR library): the bounding box of the tags is
+ * split at a hole of a row or column signature, else at the strongest
+ * inflection of a signature's second difference, else in the middle of
+ * its longer side, until every box holds at least `efficiency` tagged
+ * cells per cell or cannot be split into parts of `min_width` cells; every
+ * box then grows by `buffer` cells, and boxes closer than one level-0 cell
+ * (also across the periodic x boundary) are merged into their bounding
+ * box.  The last level-0 column is never refined, so that boxes reaching
+ * the two ends of the periodic x range stay one cell apart.  The boxes are
+ * returned in level-1 indices (level-0 box times `ratio`), sorted by
+ * (x, v) origin, and satisfy vp_plan_create's rules.
+ *   tags       host uint8 [ncx][ncv]
+ *   boxes      output, room for max_boxes; *nbox receives the count
+ * VP_EINVAL for bad sizes, efficiency outside (0, 1], or more than
+ * max_boxes boxes (*nbox still holds the count).
+ */
+vp_status vp_cluster_tags(const uint8_t* tags, int32_t ncx, int32_t ncv, int32_t ratio, double efficiency,
+                          int32_t min_width, int32_t buffer, vp_box* boxes, int32_t max_boxes, int32_t* nbox);
+
+/*
+ * vp_regrid_transfer: fills the state of new_plan from the state of
+ * old_plan after a regrid (section 3): level 0 is copied; every new
+ * level-1 cell covered by an old level-1 patch takes the old fine value,
+ * the others the conservative, limited, high-order interpolation of
+ * level 0 (section 3, eqs. aux1, aux2, interp_r_avg with the
+ * renormalisation; B^(0) = 2 D_i - D_{i+1}, the value the definition of
+ * the candidate gives), applied in x and then in v.  Both plans are 1D+1V
+ * FP64 with the same level 0 (cells, spacing, equilibrium) and the same
+ * ratio; either may have one level.  f_old and f_new must not overlap.
+ * Enqueued on `stream`.
+ */
+vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const vp_plan* new_plan, void* f_new,
+                             hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,195 @@
+// HIP kernels of regridding (section 3) for 1D+1V levels stored [x][v]
+// (FP64):
+//   k_tag          the refinement criterion delta1 f + delta2 f > tol on a
+//                  level (x periodic, velocity ghosts = equilibrium);
+//   k_prolong      the conservative limited WENO5 interpolation of the
+//                  coarse level into every new level-1 patch, x then v, one
+//                  thread per coarse cell of a patch;
+//   k_copy_old     new fine cells that an old level-1 patch covers take the
+//                  old fine value.
+#include <hip/hip_runtime.h>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+namespace {
+
+__device__ __forceinline__ int wrapr(int i, int n)
+{
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double level_at(const double* f, int nx, int nv, const double* vg, int i, int j)
+{
+    if (j < 0) return vg[j + 2];
+    if (j >= nv) return vg[j - nv + 2];
+    return f[(size_t)wrapr(i, nx) * nv + j];
+}
+
+struct Ghosts {
+    double v[4];   // equilibrium cell averages at j = -2, -1, nv, nv + 1
+};
+
+// delta1 f + delta2 f of one cell.  The operations run in a fixed order
+// without fused multiply-adds (per direction the squared central
+// difference scaled by h, x term plus v term, halved, square root; the
+// second differences as (f(+) - 2 f) + f(-), magnitudes scaled by h^2,
+// x plus v, halved; the sum of the two), so that the value is reproducible
+// to the last bit.
+__device__ double tag_value(const double* f, int nx, int nv, const double* vg, double dx, double dv, int i, int j)
+{
+#pragma clang fp contract(off)
+    const double c = level_at(f, nx, nv, vg, i, j);
+    const double xm = level_at(f, nx, nv, vg, i - 1, j), xp = level_at(f, nx, nv, vg, i + 1, j);
+    const double vm = level_at(f, nx, nv, vg, i, j - 1), vp = level_at(f, nx, nv, vg, i, j + 1);
+    const double gx = xp - xm, gv = vp - vm;
+    const double d1 = __builtin_sqrt(0.5 * (dx * (gx * gx) + dv * (gv * gv)));
+    const double sx = (xp - 2.0 * c) + xm, sv = (vp - 2.0 * c) + vm;
+    const double d2 = 0.5 * ((dx * dx) * __builtin_fabs(sx) + (dv * dv) * __builtin_fabs(sv));
+    return d1 + d2;
+}
+
+__global__ __launch_bounds__(256) void k_tag(const double* __restrict__ f, int nx, int nv, Ghosts g, double dx,
+                                             double dv, double tol, unsigned char* __restrict__ tags,
+                                             double* __restrict__ values)
+{
+    const int j = (int)(blockIdx.x * 256 + threadIdx.x);
+    const int i = (int)blockIdx.y;
+    if (j >= nv) return;
+    const double t = tag_value(f, nx, nv, g.v, dx, dv, i, j);
+    const size_t e = (size_t)i * nv + j;
+    tags[e] = t > tol ? 1 : 0;
+    if (values) values[e] = t;
+}
+
+// R fine cell averages of the middle of u[0..4] (eqs. aux1, aux2,
+// interp_r_avg; B^(0) = 2 D_i - D_{i+1}, the value the definition gives);
+// every candidate renormalised to the coarse average, then combined with
+// the WENO5 weights (ideal weights 3/10, 3/5, 1/10, epsilon 1e-6)
+template <int R>
+__device__ __forceinline__ void prolong1d(const double* u, double* out)
+{
+    const double Dm2 = u[1] - u[0], Dm1 = u[2] - u[1], D0 = u[3] - u[2], Dp1 = u[4] - u[3];
+    const double Lm1 = Dm1 - Dm2, L0 = D0 - Dm1, Lp1 = Dp1 - D0;
+    const double b0 = 13.0 / 12.0 * Lp1 * Lp1 + 0.25 * (Dp1 - 3.0 * D0) * (Dp1 - 3.0 * D0);
+    const double b1 = 13.0 / 12.0 * L0 * L0 + 0.25 * (D0 + Dm1) * (D0 + Dm1);
+    const double b2 = 13.0 / 12.0 * Lm1 * Lm1 + 0.25 * (3.0 * Dm1 - Dm2) * (3.0 * Dm1 - Dm2);
+    const double a0 = 0.3 / ((1e-6 + b0) * (1e-6 + b0));
+    const double a1 = 0.6 / ((1e-6 + b1) * (1e-6 + b1));
+    const double a2 = 0.1 / ((1e-6 + b2) * (1e-6 + b2));
+    const double as = (a0 + a1) + a2;
+    const double w[3] = {a0 / as, a1 / as, a2 / as};
+    const double ui = u[2];
+    const double A[3] = {ui + (2.0 * Dp1 - 5.0 * D0) / 6.0, ui - (D0 + 2.0 * Dm1) / 6.0, ui - (4.0 * Dm1 - Dm2) / 6.0};
+    const double B[3] = {2.0 * D0 - Dp1, Dm1, Dm1};
+    const double C[3] = {Lp1, L0, Lm1};
+#pragma unroll
+    for (int s = 0; s < R; ++s) out[s] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double fine[R];
+        double sum = 0.0;
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            fine[s] = A[r] + B[r] * ((2.0 * s + 1.0) / (2.0 * R)) + C[r] * ((3.0 * s * s + 3.0 * s + 1.0) / (6.0 * R * R));
+            sum += fine[s];
+        }
+        fine[R - 1] += ui - sum / R;
+#pragma unroll
+        for (int s = 0; s < R; ++s) out[s] += w[r] * fine[s];
+    }
+}
+
+// blockIdx.y: new patch; thread: one coarse cell of its footprint
+template <int R>
+__global__ __launch_bounds__(128) void k_prolong(const double* __restrict__ fc, int ncx, int ncv, Ghosts g,
+                                                 const AmrPatch* __restrict__ patches, double* __restrict__ fnew)
+{
+    const AmrPatch P = patches[blockIdx.y];
+    const int pcx = P.nx / R, pcv = P.nv / R;
+    const int q = (int)(blockIdx.x * 128 + threadIdx.x);
+    if (q >= pcx * pcv) return;
+    const int cxl = q / pcv, cvl = q - (q / pcv) * pcv;
+    const int cx = P.gx0 / R + cxl, cv = P.gv0 / R + cvl;
+    // x first: the R fine rows of this coarse column at coarse v rows cv-2 .. cv+2
+    double T[R][5];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+        double u[5], o[R];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) u[k] = level_at(fc, ncx, ncv, g.v, cx - 2 + k, cv - 2 + e);
+        prolong1d<R>(u, o);
+#pragma unroll
+        for (int s = 0; s < R; ++s) T[s][e] = o[s];
+    }
+    // then v
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        double o[R];
+        prolong1d<R>(T[s], o);
+        double* dst = fnew + P.off + (size_t)(cxl * R + s) * P.nv + (size_t)cvl * R;
+#pragma unroll
+        for (int t = 0; t < R; ++t) dst[t] = o[t];
+    }
+}
+
+// blockIdx.y: new patch; thread: one fine cell; the old patches are
+// disjoint, so at most one covers the cell
+__global__ __launch_bounds__(256) void k_copy_old(const double* __restrict__ fold,
+                                                  const AmrPatch* __restrict__ old_patches, int nold,
+                                                  const AmrPatch* __restrict__ new_patches,
+                                                  double* __restrict__ fnew)
+{
+    const AmrPatch P = new_patches[blockIdx.y];
+    const int q = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (q >= P.nx * P.nv) return;
+    const int lx = q / P.nv, lv = q - (q / P.nv) * P.nv;
+    const int gx = P.gx0 + lx, gv = P.gv0 + lv;
+    for (int o = 0; o < nold; ++o) {
+        const AmrPatch Q = old_patches[o];
+        if (gx >= Q.gx0 && gx < Q.gx0 + Q.nx && gv >= Q.gv0 && gv < Q.gv0 + Q.nv) {
+            fnew[P.off + q] = fold[Q.off + (size_t)(gx - Q.gx0) * Q.nv + (gv - Q.gv0)];
+            return;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tag(const double* f, int nx, int nv, const double* vg, double dx, double dv, double tol,
+                      unsigned char* tags, double* values, hipStream_t stream)
+{
+    Ghosts g;
+    for (int q = 0; q < 4; ++q) g.v[q] = vg[q];
+    const dim3 grid((unsigned)((nv + 255) / 256), (unsigned)nx);
+    hipLaunchKernelGGL(k_tag, grid, dim3(256), 0, stream, f, nx, nv, g, dx, dv, tol, tags, values);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const double* fc, int ncx, int ncv, const double* vgc, int R, const AmrPatch* d_patches,
+                          int npatch, int max_coarse_cells, double* fnew, hipStream_t stream)
+{
+    if (npatch == 0) return hipSuccess;
+    Ghosts g;
+    for (int q = 0; q < 4; ++q) g.v[q] = vgc[q];
+    const dim3 grid((unsigned)((max_coarse_cells + 127) / 128), (unsigned)npatch);
+    switch (R) {
+    case 2: hipLaunchKernelGGL((k_prolong<2>), grid, dim3(128), 0, stream, fc, ncx, ncv, g, d_patches, fnew); break;
+    case 4: hipLaunchKernelGGL((k_prolong<4>), grid, dim3(128), 0, stream, fc, ncx, ncv, g, d_patches, fnew); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_old(const double* fold, const AmrPatch* d_old, int nold, const AmrPatch* d_new, int nnew,
+                           int max_fine_cells, double* fnew, hipStream_t stream)
+{
+    if (nnew == 0 || nold == 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_fine_cells + 255) / 256), (unsigned)nnew);
+    hipLaunchKernelGGL(k_copy_old, grid, dim3(256), 0, stream, fold, d_old, nold, d_new, fnew);
+    return hipGetLastError();
+}
+
+}  // namespace vp

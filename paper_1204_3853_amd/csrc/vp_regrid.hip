@@ -1,0 +1,227 @@
+// Regridding entry points (section 3): the refinement criterion on level 0,
+// the clustering of tagged level-0 cells into level-1 boxes (host), and the
+// transfer of a state to a plan with new level-1 patches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vp_internal.hpp"
+
+namespace vp {
+
+hipError_t launch_tag(const double* f, int nx, int nv, const double* vg, double dx, double dv, double tol,
+                      unsigned char* tags, double* values, hipStream_t stream);
+hipError_t launch_prolong(const double* fc, int ncx, int ncv, const double* vgc, int R, const AmrPatch* d_patches,
+                          int npatch, int max_coarse_cells, double* fnew, hipStream_t stream);
+hipError_t launch_copy_old(const double* fold, const AmrPatch* d_old, int nold, const AmrPatch* d_new, int nnew,
+                           int max_fine_cells, double* fnew, hipStream_t stream);
+
+namespace {
+
+// level 0 of a 1D+1V plan: the single level, or the coarse level of two
+struct Level0 {
+    int nx, nv;
+    double dx, dv;
+    const double* vg;
+};
+
+bool level0_of(const vp_plan* p, Level0& L)
+{
+    if (!p || p->p4 || p->ndim != 1) return false;
+    if (p->amr) {
+        const AmrPlan& M = *p->amr;
+        L = Level0{M.ncx, M.ncv, M.dxc, M.dvc, M.vgc};
+    } else {
+        L = Level0{p->nx, p->nv, p->dx, p->dv, p->vg};
+    }
+    return true;
+}
+
+struct CBox {
+    int xlo, vlo, xhi, vhi;        // inclusive, level-0 cells
+    long long area() const { return (long long)(xhi - xlo + 1) * (vhi - vlo + 1); }
+};
+
+// Berger-Rigoutsos: split the bounding box of the tags inside B at a hole
+// of a signature, else at the strongest inflection of a signature's
+// second difference, else in the middle of the longer side, until each
+// box holds at least `eff` tagged cells per cell or cannot be split into
+// two parts of at least `minw` cells.
+void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double eff, int minw,
+                std::vector<CBox>& out)
+{
+    // shrink to the tags' bounding box
+    int xlo = B.xhi + 1, xhi = B.xlo - 1, vlo = B.vhi + 1, vhi = B.vlo - 1;
+    long long nt = 0;
+    for (int i = B.xlo; i <= B.xhi; ++i)
+        for (int j = B.vlo; j <= B.vhi; ++j)
+            if (tag[(size_t)i * nv + j]) {
+                ++nt;
+                xlo = std::min(xlo, i); xhi = std::max(xhi, i);
+                vlo = std::min(vlo, j); vhi = std::max(vhi, j);
+            }
+    if (nt == 0) return;
+    B = CBox{xlo, vlo, xhi, vhi};
+    const int wx = B.xhi - B.xlo + 1, wv = B.vhi - B.vlo + 1;
+    if ((double)nt >= eff * (double)B.area() || (wx < 2 * minw && wv < 2 * minw)) {
+        out.push_back(B);
+        return;
+    }
+    std::vector<long long> sx(wx, 0), sv(wv, 0);
+    for (int i = B.xlo; i <= B.xhi; ++i)
+        for (int j = B.vlo; j <= B.vhi; ++j)
+            if (tag[(size_t)i * nv + j]) { ++sx[i - B.xlo]; ++sv[j - B.vlo]; }
+    // candidate cut: the first cell of the upper part, at offset c of a side
+    // of width w (minw <= c <= w - minw); best = (class, score, distance to the middle)
+    int best_dir = -1, best_cut = 0;
+    long long best_score = -1;
+    int best_class = 3;                      // 0 hole, 1 inflection, 2 middle
+    int best_dist = 1 << 30;
+    auto consider = [&](int dir, int c, int cls, long long score, int w) {
+        const int dist = std::abs(2 * c - w);
+        if (cls < best_class || (cls == best_class && (score > best_score || (score == best_score && dist < best_dist)))) {
+            best_class = cls; best_score = score; best_dist = dist; best_dir = dir; best_cut = c;
+        }
+    };
+    for (int dir = 0; dir < 2; ++dir) {
+        const std::vector<long long>& s = dir == 0 ? sx : sv;
+        const int w = (int)s.size();
+        if (w < 2 * minw) continue;
+        for (int c = minw; c <= w - minw; ++c)
+            if (s[c - 1] == 0 || s[c] == 0) consider(dir, c, 0, 0, w);
+        for (int c = std::max(minw, 2); c <= std::min(w - minw, w - 2); ++c) {
+            // inflection between cells c-1 and c: second differences change sign
+            const long long l0 = s[c - 2] - 2 * s[c - 1] + s[c];
+            const long long l1 = s[c - 1] - 2 * s[c] + s[c + 1];
+            if ((l0 < 0 && l1 > 0) || (l0 > 0 && l1 < 0)) consider(dir, c, 1, std::llabs(l1 - l0), w);
+        }
+        consider(dir, w / 2, 2, w, w);
+    }
+    if (best_dir < 0) {
+        out.push_back(B);
+        return;
+    }
+    CBox lo = B, hi = B;
+    if (best_dir == 0) { lo.xhi = B.xlo + best_cut - 1; hi.xlo = B.xlo + best_cut; }
+    else { lo.vhi = B.vlo + best_cut - 1; hi.vlo = B.vlo + best_cut; }
+    br_cluster(tag, nv, lo, eff, minw, out);
+    br_cluster(tag, nv, hi, eff, minw, out);
+}
+
+bool too_close(const CBox& a, const CBox& b, int period)
+{
+    for (int sh : {0, -period, period}) {
+        const int xlo = std::max(a.xlo - 1, b.xlo + sh), xhi = std::min(a.xhi + 1, b.xhi + sh);
+        const int vlo = std::max(a.vlo - 1, b.vlo), vhi = std::min(a.vhi + 1, b.vhi);
+        if (xlo <= xhi && vlo <= vhi) return true;
+    }
+    return false;
+}
+
+}  // namespace
+
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" {
+
+vp_status vp_tag_cells(const vp_plan* p, const void* f, double tol, uint8_t* tags, double* values,
+                       hipStream_t stream)
+{
+    Level0 L;
+    if (!p) return fail(VP_EINVAL, "vp_tag_cells: plan is NULL");
+    if (!f || !tags) return fail(VP_EINVAL, "vp_tag_cells: NULL pointer");
+    if (!level0_of(p, L)) return fail(VP_ENOTSUP, "vp_tag_cells: 1D+1V plans only");
+    if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_tag_cells: FP64 plans only");
+    VP_HIP(launch_tag(static_cast<const double*>(f), L.nx, L.nv, L.vg, L.dx, L.dv, tol, tags, values, stream));
+    return VP_OK;
+}
+
+vp_status vp_cluster_tags(const uint8_t* tags, int32_t ncx, int32_t ncv, int32_t ratio, double efficiency,
+                          int32_t min_width, int32_t buffer, vp_box* boxes, int32_t max_boxes, int32_t* nbox)
+{
+    if (!tags || !nbox || (max_boxes > 0 && !boxes)) return fail(VP_EINVAL, "vp_cluster_tags: NULL pointer");
+    if (ncx < 3 || ncv < 1 || ratio < 1 || min_width < 1 || buffer < 0 || !(efficiency > 0.0 && efficiency <= 1.0))
+        return fail(VP_EINVAL, "vp_cluster_tags: bad sizes or parameters");
+    // the last level-0 column is never refined: it keeps one coarse cell
+    // between boxes that reach the two ends of the periodic x range
+    std::vector<unsigned char> t(tags, tags + (size_t)ncx * ncv);
+    for (int j = 0; j < ncv; ++j) t[(size_t)(ncx - 1) * ncv + j] = 0;
+    std::vector<CBox> bx;
+    br_cluster(t, ncv, CBox{0, 0, ncx - 2, ncv - 1}, efficiency, min_width, bx);
+    // buffer cells around every box, inside the refinable range
+    for (CBox& b : bx) {
+        b.xlo = std::max(b.xlo - buffer, 0); b.xhi = std::min(b.xhi + buffer, ncx - 2);
+        b.vlo = std::max(b.vlo - buffer, 0); b.vhi = std::min(b.vhi + buffer, ncv - 1);
+    }
+    // boxes closer than one level-0 cell (also across the periodic boundary)
+    // are replaced by their bounding box until none are
+    for (bool merged = true; merged;) {
+        merged = false;
+        for (size_t a = 0; a < bx.size() && !merged; ++a)
+            for (size_t b = a + 1; b < bx.size() && !merged; ++b)
+                if (too_close(bx[a], bx[b], ncx)) {
+                    CBox u{std::min(bx[a].xlo, bx[b].xlo), std::min(bx[a].vlo, bx[b].vlo),
+                           std::max(bx[a].xhi, bx[b].xhi), std::max(bx[a].vhi, bx[b].vhi)};
+                    bx[a] = u;
+                    bx.erase(bx.begin() + (long)b);
+                    merged = true;
+                }
+    }
+    std::sort(bx.begin(), bx.end(), [](const CBox& a, const CBox& b) {
+        return a.xlo != b.xlo ? a.xlo < b.xlo : a.vlo < b.vlo;
+    });
+    *nbox = (int32_t)bx.size();
+    if ((int32_t)bx.size() > max_boxes)
+        return fail(VP_EINVAL, "vp_cluster_tags: " + std::to_string(bx.size()) + " boxes, room for " +
+                                   std::to_string(max_boxes));
+    for (size_t q = 0; q < bx.size(); ++q) {
+        vp_box& o = boxes[q];
+        std::memset(&o, 0, sizeof(o));
+        o.level = 1;
+        o.lo[0] = bx[q].xlo * ratio;
+        o.lo[1] = bx[q].vlo * ratio;
+        o.hi[0] = (bx[q].xhi + 1) * ratio - 1;
+        o.hi[1] = (bx[q].vhi + 1) * ratio - 1;
+    }
+    return VP_OK;
+}
+
+vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const vp_plan* new_plan, void* f_new,
+                             hipStream_t stream)
+{
+    Level0 A, B;
+    if (!old_plan || !new_plan || !f_old || !f_new) return fail(VP_EINVAL, "vp_regrid_transfer: NULL pointer");
+    if (!level0_of(old_plan, A) || !level0_of(new_plan, B))
+        return fail(VP_ENOTSUP, "vp_regrid_transfer: 1D+1V plans only");
+    if (old_plan->dtype != VP_F64 || new_plan->dtype != VP_F64)
+        return fail(VP_ENOTSUP, "vp_regrid_transfer: FP64 plans only");
+    if (A.nx != B.nx || A.nv != B.nv || A.dx != B.dx || A.dv != B.dv || std::memcmp(A.vg, B.vg, 4 * sizeof(double)))
+        return fail(VP_EINVAL, "vp_regrid_transfer: the plans have different level-0 meshes");
+    if (old_plan->amr && new_plan->amr && old_plan->amr->R != new_plan->amr->R)
+        return fail(VP_EINVAL, "vp_regrid_transfer: the plans have different refinement ratios");
+    const double* fo = static_cast<const double*>(f_old);
+    double* fn = static_cast<double*>(f_new);
+    VP_HIP(hipMemcpyAsync(fn, fo, sizeof(double) * (size_t)A.nx * A.nv, hipMemcpyDeviceToDevice, stream));
+    if (!new_plan->amr) return VP_OK;
+    const AmrPlan& N = *new_plan->amr;
+    int max_c = 0, max_f = 0;
+    for (const AmrPatch& P : N.patches) {
+        max_c = std::max(max_c, (P.nx / N.R) * (P.nv / N.R));
+        max_f = std::max(max_f, P.nx * P.nv);
+    }
+    VP_HIP(launch_prolong(fo, A.nx, A.nv, A.vg, N.R, N.d_patches, (int)N.patches.size(), max_c, fn, stream));
+    if (old_plan->amr) {
+        const AmrPlan& O = *old_plan->amr;
+        VP_HIP(launch_copy_old(fo, O.d_patches, (int)O.patches.size(), N.d_patches, (int)N.patches.size(), max_f, fn,
+                               stream));
+    }
+    return VP_OK;
+}
+
+}  // extern "C"

@@ -85,6 +85,11 @@ SIGNATURES = {
     "vp_timing_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int32]),
+    "vp_tag_cells": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
+    "vp_cluster_tags": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       _D, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp_box), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "vp_regrid_transfer": (ctypes.c_int, [_P, _P, _P, _P, _P]),
 }
 
 TIMING_CLASSES = ["stage", "field", "moment", "sync", "adjoint", "other"]
@@ -346,3 +351,52 @@ def field_adjoint(plan, abar, fbar=None):
         fbar = torch.empty(plan.state_elems, dtype=torch.float64, device=abar.device)
     _check(lib().vp_field_adjoint(plan.h, _ptr(abar), _ptr(fbar), _ptr(plan.work), _stream()))
     return fbar
+
+
+# -------------------------------------------------------------------- regridding
+
+
+def tag_cells(plan, f, tol, values=False):
+    """Refinement tags of level 0 (uint8 [ncx][ncv] on the device); with
+    values=True also delta1 f + delta2 f per level-0 cell."""
+    plan._state(f, "f")
+    ncx, ncv = plan.spec["cells"][0], plan.spec["cells"][1]
+    tags = torch.empty((ncx, ncv), dtype=torch.uint8, device=f.device)
+    vals = torch.empty((ncx, ncv), dtype=torch.float64, device=f.device) if values else None
+    _check(lib().vp_tag_cells(plan.h, _ptr(f), ctypes.c_double(tol), _ptr(tags), _ptr(vals), _stream()))
+    return (tags, vals) if values else tags
+
+
+def cluster_tags(tags, ratio, efficiency=0.7, min_width=2, buffer=1, max_boxes=4096):
+    """Level-1 boxes (dicts with level, lo, hi) covering the tagged level-0
+    cells of a host uint8 [ncx][ncv] array (a numpy array or a CPU tensor)."""
+    import numpy as np
+    t = tags.cpu().numpy() if hasattr(tags, "cpu") else tags
+    t = np.ascontiguousarray(t, dtype=np.uint8)
+    ncx, ncv = t.shape
+    out = (vp_box * max_boxes)()
+    n = ctypes.c_int32()
+    _check(lib().vp_cluster_tags(t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ncx, ncv, ratio,
+                                 ctypes.c_double(efficiency), min_width, buffer, out, max_boxes, ctypes.byref(n)))
+    return [{"level": 1, "lo": [out[q].lo[0], out[q].lo[1]], "hi": [out[q].hi[0], out[q].hi[1]]}
+            for q in range(n.value)]
+
+
+def regrid_transfer(old_plan, f_old, new_plan, f_new=None):
+    """The state of new_plan from the state of old_plan after a regrid."""
+    old_plan._state(f_old, "f_old")
+    if f_new is None:
+        f_new = torch.empty(new_plan.state_elems, dtype=new_plan.dtype, device=f_old.device)
+    new_plan._state(f_new, "f_new")
+    _check(lib().vp_regrid_transfer(old_plan.h, _ptr(f_old), new_plan.h, _ptr(f_new), _stream()))
+    return f_new
+
+
+def regrid(plan, f, tol, efficiency=0.7, min_width=2, buffer=1):
+    """Regrid a two-level plan: tag level 0, cluster on the host, create the
+    plan of the new hierarchy and transfer the state.  Returns
+    (new_plan, f_new, boxes)."""
+    tags = tag_cells(plan, f, tol)
+    boxes = cluster_tags(tags.cpu(), plan.spec["ratio"][0], efficiency, min_width, buffer)
+    new_plan = Plan(plan.spec, dtype=plan.dtype, boxes=boxes, device=plan.device)
+    return new_plan, regrid_transfer(plan, f, new_plan), boxes

@@ -1,0 +1,176 @@
+"""GPU parity of regridding (section 3) against the oracle.
+
+- vp_tag_cells: delta1 f + delta2 f per level-0 cell equal to the oracle's
+  bit for bit (both evaluate the same operations in the same order without
+  fused multiply-adds, with a correctly rounded square root), so the tags
+  agree exactly at any threshold; small hierarchies, an odd velocity count,
+  a single-level plan and the 512 x 512 level 0 of the two-level workload.
+- vp_regrid_transfer: level 0 copied exactly; new level-1 cells covered by
+  old patches take the old values exactly; the others match the oracle's
+  conservative limited WENO5 prolongation (x then v) to 1e-12 relative.
+- regrid end to end on the 512 x 512 two-level Landau workload: tags,
+  clustering, plan creation, transfer (coarse averages conserved), then
+  one RK4 step on the new hierarchy against the two-level oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import vp_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SMALL = [{"level": 1, "lo": [16, 40], "hi": [39, 63]}, {"level": 1, "lo": [60, 68], "hi": [83, 87]},
+         {"level": 1, "lo": [0, 96], "hi": [15, 111]}]
+# overlaps the first two SMALL patches partly, covers new ground, and reaches the v boundary
+NEW_SMALL = [{"level": 1, "lo": [24, 48], "hi": [55, 75]}, {"level": 1, "lo": [72, 4], "hi": [95, 23]},
+             {"level": 1, "lo": [100, 160], "hi": [119, 191]}]
+RATIO2 = [{"level": 1, "lo": [6, 20], "hi": [17, 33]}, {"level": 1, "lo": [0, 50], "hi": [9, 61]}]
+NEW_RATIO2 = [{"level": 1, "lo": [8, 16], "hi": [21, 29]}, {"level": 1, "lo": [30, 0], "hi": [35, 89]}]
+
+
+@pytest.fixture(scope="module")
+def vp():
+    from paper_1204_3853_amd import vp as V
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return V
+
+
+def gpu(x):
+    return torch.tensor(x, dtype=torch.float64, device="cuda")
+
+
+def hierarchy(vp, boxes, ncx, ncv, R, noise=0.01, seed=0):
+    f, veq_c, veq_f = I.amr_landau(boxes, coarse=(ncx, ncv), ratio=R, eps=0.05, k=0.5)
+    if noise:
+        f = f * (1.0 + noise * np.random.default_rng(seed).random(f.size))
+    spec = vp.two_level_spec(ncx, ncv, 4 * math.pi, -8.0, 8.0, -1.0, R, veq_c, veq_f)
+    return f, veq_c, veq_f, spec
+
+
+def single_spec(ncx, ncv, veq_c):
+    return {"ndim": 1, "cells": [ncx, ncv], "x_lo": [0.0], "x_len": [4 * math.pi], "v_lo": [-8.0], "v_hi": [8.0],
+            "qm": -1.0, "veq": [[veq_c]]}
+
+
+def ghosts(veq, n):
+    return np.array([veq[0], veq[1], veq[n + 2], veq[n + 3]])
+
+
+@pytest.mark.parametrize("layout", ["small", "ratio2_odd"])
+def test_tag_values_bitwise(vp, oracle, layout):
+    boxes, ncx, ncv, R = (SMALL, 32, 48, 4) if layout == "small" else (RATIO2, 24, 45, 2)
+    f, veq_c, _, spec = hierarchy(vp, boxes, ncx, ncv, R, noise=0.05)
+    plan = vp.Plan(spec, boxes=boxes)
+    tags, vals = vp.tag_cells(plan, gpu(f), 0.0, values=True)
+    f0 = f[:ncx * ncv].reshape(ncx, ncv)
+    dxc, dvc = 4 * math.pi / ncx, 16.0 / ncv
+    want = oracle.tag_values(f0, dxc, dvc, ghosts(veq_c, ncv))
+    got = vals.cpu().numpy()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+    for tol in np.quantile(want, [0.1, 0.5, 0.9]):
+        t = vp.tag_cells(plan, gpu(f), float(tol)).cpu().numpy()
+        assert np.array_equal(t, oracle.tag(f0, dxc, dvc, ghosts(veq_c, ncv), float(tol)))
+
+
+def test_tag_single_level(vp, oracle):
+    p = I.two_stream(64, 96)
+    plan = vp.Plan(p)
+    f0 = p.initial_state() * (1.0 + 0.1 * np.random.default_rng(2).random((64, 96)))
+    tags, vals = vp.tag_cells(plan, gpu(f0), 1e-4, values=True)
+    want = oracle.tag_values(f0, p.dx, p.dv, p.vghost)
+    assert np.array_equal(vals.cpu().numpy(), want)
+    assert np.array_equal(tags.cpu().numpy(), oracle.tag(f0, p.dx, p.dv, p.vghost, 1e-4))
+
+
+def test_tag_full_level0(vp, oracle):
+    boxes = I.amr_boxes(0)
+    f, veq_c, _, spec = hierarchy(vp, boxes, 512, 512, 4, noise=0.0)
+    plan = vp.Plan(spec, boxes=boxes)
+    f0 = f[:512 * 512].reshape(512, 512)
+    dxc, dvc = 4 * math.pi / 512, 16.0 / 512
+    g = ghosts(veq_c, 512)
+    tags, vals = vp.tag_cells(plan, gpu(f), 1e-3, values=True)
+    assert np.array_equal(tags.cpu().numpy(), oracle.tag(f0, dxc, dvc, g, 1e-3))
+    v = vals.cpu().numpy()
+    rng = np.random.default_rng(1)
+    for i, j in zip(rng.integers(0, 512, 300), rng.integers(0, 512, 300)):
+        assert v[i, j] == oracle.lib().vpo_tag_value(512, 512, dxc, dvc, oracle._p(g), oracle._p(np.ascontiguousarray(f0)),
+                                                     int(i), int(j))
+
+
+@pytest.mark.parametrize("layout", ["small", "ratio2_odd"])
+def test_transfer_from_single_level(vp, oracle, layout):
+    boxes, ncx, ncv, R = (NEW_SMALL, 32, 48, 4) if layout == "small" else (NEW_RATIO2, 24, 45, 2)
+    f, veq_c, veq_f, spec = hierarchy(vp, boxes, ncx, ncv, R, noise=0.05)
+    f0 = f[:ncx * ncv]
+    old = vp.Plan(single_spec(ncx, ncv, veq_c))
+    new = vp.Plan(spec, boxes=boxes)
+    fn = vp.regrid_transfer(old, gpu(f0), new).cpu().numpy()
+    assert np.array_equal(fn[:ncx * ncv], f0)
+    g = ghosts(veq_c, ncv)
+    for q, b in enumerate(boxes):
+        off = new.patch_offset(q)
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        want = oracle.prolong_box(f0.reshape(ncx, ncv), g, R, (x0, v0, x1, v1))
+        got = fn[off:off + want.size].reshape(want.shape)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), q
+
+
+def test_transfer_between_hierarchies(vp, oracle):
+    ncx, ncv, R = 32, 48, 4
+    f_old, veq_c, veq_f, spec = hierarchy(vp, SMALL, ncx, ncv, R, noise=0.05)
+    old = vp.Plan(spec, boxes=SMALL)
+    new = vp.Plan(spec, boxes=NEW_SMALL)
+    fn = vp.regrid_transfer(old, gpu(f_old), new).cpu().numpy()
+    f0 = f_old[:ncx * ncv]
+    assert np.array_equal(fn[:ncx * ncv], f0)
+    g = ghosts(veq_c, ncv)
+    for q, b in enumerate(NEW_SMALL):
+        off = new.patch_offset(q)
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        want = oracle.prolong_box(f0.reshape(ncx, ncv), g, R, (x0, v0, x1, v1))
+        for p, ob in enumerate(SMALL):          # old fine values where an old patch covers the cell
+            (a0, b0), (a1, b1) = ob["lo"], ob["hi"]
+            ix0, ix1, iv0, iv1 = max(x0, a0), min(x1, a1), max(v0, b0), min(v1, b1)
+            if ix0 > ix1 or iv0 > iv1:
+                continue
+            ooff = old.patch_offset(p)
+            wv = b1 - b0 + 1
+            blk = f_old[ooff:ooff + (a1 - a0 + 1) * wv].reshape(a1 - a0 + 1, wv)
+            want[ix0 - x0:ix1 - x0 + 1, iv0 - v0:iv1 - v0 + 1] = blk[ix0 - a0:ix1 - a0 + 1, iv0 - b0:iv1 - b0 + 1]
+        got = fn[off:off + want.size].reshape(want.shape)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), q
+
+
+def test_regrid_end_to_end_full(vp, oracle):
+    boxes = I.amr_boxes(0)
+    f, veq_c, veq_f, spec = hierarchy(vp, boxes, 512, 512, 4, noise=0.0)
+    plan = vp.Plan(spec, boxes=boxes)
+    fg = gpu(f)
+    _, vals = vp.tag_cells(plan, fg, 0.0, values=True)
+    tol = float(torch.quantile(vals.flatten().cpu(), 0.97))
+    new_plan, fn, new_boxes = vp.regrid(plan, fg, tol, efficiency=0.7, min_width=2, buffer=1)
+    assert len(new_boxes) > 0
+    fnh = fn.cpu().numpy()
+    assert np.array_equal(fnh[:512 * 512], f[:512 * 512])
+    # every new patch conserves the level-0 averages it refines
+    for q, b in enumerate(new_boxes):
+        off = new_plan.patch_offset(q)
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        blk = fnh[off:off + (x1 - x0 + 1) * (v1 - v0 + 1)].reshape(x1 - x0 + 1, v1 - v0 + 1)
+        means = blk.reshape((x1 - x0 + 1) // 4, 4, (v1 - v0 + 1) // 4, 4).mean(axis=(1, 3))
+        coarse = f[:512 * 512].reshape(512, 512)[x0 // 4:(x1 + 1) // 4, v0 // 4:(v1 + 1) // 4]
+        assert np.abs(means - coarse).max() <= 1e-13 * coarse.max()
+    # one RK4 step on the new hierarchy against the oracle
+    o = oracle.OracleAMR(512, 512, 4 * math.pi, -8.0, 8.0, -1.0, 4, new_boxes, veq_c, veq_f)
+    a = vp.field_of(new_plan, fn)
+    dt = 0.5 * (4 * math.pi / 2048) / 8.0
+    vp.rk4_step(new_plan, fn, a, dt)
+    want = o.step(fnh, dt)
+    got = fn.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()

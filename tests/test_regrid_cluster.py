@@ -1,0 +1,107 @@
+"""Clustering of tagged level-0 cells into level-1 boxes (vp_cluster_tags,
+host code of the library; no GPU needed).
+
+Several clusterings are correct, so the boxes are checked for what every
+valid answer must satisfy: each tagged cell (except in the last level-0
+column, which is never refined) lies in a box; boxes are aligned to the
+ratio, inside the domain, and at least one level-0 cell apart, also across
+the periodic x boundary (the rules of vp_plan_create); every box holds a
+tagged cell; the result does not depend on anything but the tags.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1204_3853_amd import vp
+
+
+def check_boxes(tags, boxes, R):
+    ncx, ncv = tags.shape
+    cov = np.zeros_like(tags, dtype=bool)
+    cboxes = []
+    for b in boxes:
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        assert b["level"] == 1
+        assert x0 % R == 0 and v0 % R == 0 and (x1 + 1) % R == 0 and (v1 + 1) % R == 0
+        cx0, cv0, cx1, cv1 = x0 // R, v0 // R, (x1 + 1) // R - 1, (v1 + 1) // R - 1
+        assert 0 <= cx0 <= cx1 <= ncx - 2 and 0 <= cv0 <= cv1 <= ncv - 1
+        assert tags[cx0:cx1 + 1, cv0:cv1 + 1].any()
+        cov[cx0:cx1 + 1, cv0:cv1 + 1] = True
+        cboxes.append((cx0, cv0, cx1, cv1))
+    t = tags.astype(bool).copy()
+    t[-1, :] = False
+    assert not (t & ~cov).any(), "a tagged cell is not covered"
+    for a in range(len(cboxes)):
+        for b in range(a + 1, len(cboxes)):
+            A, B = cboxes[a], cboxes[b]
+            for sh in (0, -ncx, ncx):
+                sep_x = max(A[0], B[0] + sh) - min(A[2], B[2] + sh)     # > 1 means a gap of a cell
+                sep_v = max(A[1], B[1]) - min(A[3], B[3])
+                assert sep_x > 1 or sep_v > 1, (A, B, sh)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("eff", [0.5, 0.7, 0.9])
+def test_random_blobs(seed, eff):
+    rng = np.random.default_rng(seed)
+    ncx, ncv, R = 64, 48, 4
+    tags = np.zeros((ncx, ncv), np.uint8)
+    for _ in range(rng.integers(1, 8)):
+        cx, cv = rng.integers(0, ncx), rng.integers(0, ncv)
+        rx, rv = rng.integers(1, 6), rng.integers(1, 6)
+        xs = np.arange(cx - rx, cx + rx + 1) % ncx
+        tags[np.ix_(xs, np.arange(max(cv - rv, 0), min(cv + rv + 1, ncv)))] = 1
+    tags |= (rng.random((ncx, ncv)) < 0.01).astype(np.uint8)
+    boxes = vp.cluster_tags(tags, R, efficiency=eff, min_width=2, buffer=1)
+    check_boxes(tags, boxes, R)
+    assert boxes == vp.cluster_tags(tags.copy(), R, efficiency=eff, min_width=2, buffer=1)
+
+
+def test_band_across_the_seam():
+    """A band of tags across all x: boxes stop before the last column."""
+    tags = np.zeros((32, 40), np.uint8)
+    tags[:, 15:25] = 1
+    boxes = vp.cluster_tags(tags, 2, efficiency=0.8, min_width=2, buffer=0)
+    check_boxes(tags, boxes, 2)
+    assert len(boxes) == 1 and boxes[0]["lo"] == [0, 30] and boxes[0]["hi"] == [61, 49]
+
+
+def test_two_blobs_stay_apart_and_dense_boxes():
+    tags = np.zeros((40, 40), np.uint8)
+    tags[4:10, 4:10] = 1
+    tags[20:30, 22:28] = 1
+    boxes = vp.cluster_tags(tags, 4, efficiency=0.9, min_width=2, buffer=0)
+    check_boxes(tags, boxes, 4)
+    got = sorted((b["lo"][0] // 4, b["lo"][1] // 4, (b["hi"][0] + 1) // 4 - 1, (b["hi"][1] + 1) // 4 - 1)
+                 for b in boxes)
+    assert got == [(4, 4, 9, 9), (20, 22, 29, 27)]
+
+
+def test_touching_parts_are_merged():
+    """Boxes of an L-shaped cluster would touch; level-1 patches must be one
+    level-0 cell apart, so the parts end up in one box."""
+    tags = np.zeros((40, 40), np.uint8)
+    tags[2:20, 2:6] = 1
+    tags[2:6, 2:20] = 1
+    boxes = vp.cluster_tags(tags, 2, efficiency=0.8, min_width=2, buffer=0)
+    check_boxes(tags, boxes, 2)
+    assert len(boxes) == 1 and boxes[0]["lo"] == [4, 4] and boxes[0]["hi"] == [39, 39]
+
+
+def test_split_at_a_hole():
+    tags = np.zeros((40, 40), np.uint8)
+    tags[2:12, 5:30] = 1
+    tags[16:26, 5:30] = 1                   # empty rows 12..15
+    boxes = vp.cluster_tags(tags, 2, efficiency=0.9, min_width=2, buffer=0)
+    check_boxes(tags, boxes, 2)
+    assert len(boxes) == 2
+
+
+def test_empty_and_errors():
+    assert vp.cluster_tags(np.zeros((16, 16), np.uint8), 4) == []
+    with pytest.raises(vp.VPError, match="bad sizes"):
+        vp.cluster_tags(np.ones((16, 16), np.uint8), 4, efficiency=1.5)
+    tags = np.zeros((64, 64), np.uint8)
+    tags[::4, ::4] = 1
+    with pytest.raises(vp.VPError, match="room for"):
+        vp.cluster_tags(tags, 2, efficiency=1.0, min_width=1, buffer=0, max_boxes=2)
