@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--amr-only", action="store_true", help="run only the two-level section (for profiling)")
     ap.add_argument("--no-4d", action="store_true")
     ap.add_argument("--no-limited", action="store_true")
+    ap.add_argument("--no-regrid", action="store_true")
+    ap.add_argument("--regrid-only", action="store_true", help="run only the regridding section (for profiling)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape of the main workload")
     ap.add_argument("--tile-shape", default=None, metavar="T,W,R",
                     help="use this tile shape (threads, cells per thread, rows) instead of autotuning")
@@ -279,6 +281,67 @@ def amr_bench(steps=100, warmup=3):
                              "sub_patch_over_mask": round(red["sub_patch"] / red["mask"], 3)}}
 
 
+def regrid_bench(reps=50):
+    """Regridding (section 3): the tagging kernel on the 4096 x 4096
+    two-stream level (8 B read + 1 B written per cell) and on level 0 of the
+    two-level Landau workload; on the latter also the host clustering, the
+    creation of the new plan and the state transfer (prolongation + copy of
+    old fine values)."""
+    import torch
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+
+    def ev_time(fn, n):
+        st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        st.record()
+        for _ in range(n):
+            fn()
+        sp.record()
+        torch.cuda.synchronize()
+        return st.elapsed_time(sp) / n
+
+    out = {}
+    p = I.two_stream(4096, 4096)
+    plan1 = vp.Plan(p)
+    f1 = torch.tensor(p.initial_state(), dtype=torch.float64, device="cuda")
+    tags1 = torch.empty((4096, 4096), dtype=torch.uint8, device="cuda")
+    ms = ev_time(lambda: vp._check(vp.lib().vp_tag_cells(plan1.h, vp._ptr(f1), vp.ctypes.c_double(1e-6),
+                                                         vp._ptr(tags1), None, vp._stream())), reps)
+    cells = 4096 * 4096
+    out["tag_4096"] = {"us": round(ms * 1e3, 2), "algorithmic_bytes": 9 * cells,
+                       "achieved_GBs": round(9 * cells / (ms * 1e-3) / 1e9, 1)}
+    del plan1, f1, tags1
+
+    boxes = I.amr_boxes(0)
+    f, veq_c, veq_f = I.amr_landau(boxes)
+    spec = vp.two_level_spec(512, 512, 4 * math.pi, -8.0, 8.0, -1.0, 4, veq_c, veq_f)
+    plan = vp.Plan(spec, boxes=boxes)
+    fg = torch.tensor(f, dtype=torch.float64, device="cuda")
+    tags, vals = vp.tag_cells(plan, fg, 0.0, values=True)
+    tol = float(torch.quantile(vals.flatten().cpu(), 0.97))
+    ms_tag = ev_time(lambda: vp.tag_cells(plan, fg, tol), reps)
+    th = vp.tag_cells(plan, fg, tol).cpu()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        new_boxes = vp.cluster_tags(th, 4, 0.7, 2, 1)
+    ms_cluster = (time.perf_counter() - t0) / 10 * 1e3
+    t0 = time.perf_counter()
+    new_plan = vp.Plan(spec, boxes=new_boxes)
+    torch.cuda.synchronize()
+    ms_plan = (time.perf_counter() - t0) * 1e3
+    fn = torch.empty(new_plan.state_elems, dtype=torch.float64, device="cuda")
+    ms_transfer = ev_time(lambda: vp.regrid_transfer(plan, fg, new_plan, fn), reps)
+    out["amr"] = {"workload": "level 0 of the two-level Landau workload (512 x 512, ratio 4, 40 patches); "
+                              "tolerance = 97th percentile of delta1 f + delta2 f",
+                  "tagged_cells": int(th.sum()), "new_patches": len(new_boxes),
+                  "new_fine_cells": int(new_plan.state_elems - 512 * 512),
+                  "tag_us": round(ms_tag * 1e3, 2), "cluster_host_ms": round(ms_cluster, 3),
+                  "plan_create_ms": round(ms_plan, 2), "transfer_us": round(ms_transfer * 1e3, 2)}
+    return out
+
+
 def fourd_bench(steps=50, warmup=3):
     """2D+2V 64^4 FP64 (x, y in [0, 4pi), v in [-6, 6]^2, Landau-type
     initial state): RK4 steps after the load-batch autotune."""
@@ -344,6 +407,9 @@ def main():
     if args.amr_only:
         print(json.dumps({"amr": amr_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
         return
+    if args.regrid_only:
+        print(json.dumps({"regrid": regrid_bench()}), flush=True)
+        return
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
     n = args.n
     p = I.two_stream(n, n)
@@ -401,6 +467,7 @@ def main():
     amr = None if args.no_amr else amr_bench()
     fourd = None if args.no_4d else fourd_bench()
     limited = None if args.no_limited else limited_bench(n)
+    regrid = None if args.no_regrid else regrid_bench()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -429,6 +496,7 @@ def main():
         "amr": amr,
         "2d2v": fourd,
         "limited": limited,
+        "regrid": regrid,
     }
     print(json.dumps(out), flush=True)
 

@@ -32,6 +32,17 @@ struct Ghosts {
     double v[4];   // equilibrium cell averages at j = -2, -1, nv, nv + 1
 };
 
+// the same criterion from the values of the cell and its four neighbours
+__device__ __forceinline__ double tag_from(double c, double xm, double xp, double vm, double vp, double dx, double dv)
+{
+#pragma clang fp contract(off)
+    const double gx = xp - xm, gv = vp - vm;
+    const double d1 = __builtin_sqrt(0.5 * (dx * (gx * gx) + dv * (gv * gv)));
+    const double sx = (xp - 2.0 * c) + xm, sv = (vp - 2.0 * c) + vm;
+    const double d2 = 0.5 * ((dx * dx) * __builtin_fabs(sx) + (dv * dv) * __builtin_fabs(sv));
+    return d1 + d2;
+}
+
 // delta1 f + delta2 f of one cell.  The operations run in a fixed order
 // without fused multiply-adds (per direction the squared central
 // difference scaled by h, x term plus v term, halved, square root; the
@@ -40,15 +51,93 @@ struct Ghosts {
 // to the last bit.
 __device__ double tag_value(const double* f, int nx, int nv, const double* vg, double dx, double dv, int i, int j)
 {
-#pragma clang fp contract(off)
     const double c = level_at(f, nx, nv, vg, i, j);
     const double xm = level_at(f, nx, nv, vg, i - 1, j), xp = level_at(f, nx, nv, vg, i + 1, j);
     const double vm = level_at(f, nx, nv, vg, i, j - 1), vp = level_at(f, nx, nv, vg, i, j + 1);
-    const double gx = xp - xm, gv = vp - vm;
-    const double d1 = __builtin_sqrt(0.5 * (dx * (gx * gx) + dv * (gv * gv)));
-    const double sx = (xp - 2.0 * c) + xm, sv = (vp - 2.0 * c) + vm;
-    const double d2 = 0.5 * ((dx * dx) * __builtin_fabs(sx) + (dv * dv) * __builtin_fabs(sv));
-    return d1 + d2;
+    return tag_from(c, xm, xp, vm, vp, dx, dv);
+}
+
+typedef double tag_d2 __attribute__((ext_vector_type(2)));
+
+// DPP wave shifts of a double: lane l reads lane l + 1 (wave_shl:1) or lane
+// l - 1 (wave_shr:1); the lane without a source is overridden by the caller
+template <int CTRL>
+__device__ __forceinline__ double tag_dpp(double x)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+constexpr int kTagRows = 8;     // x rows marched by one thread
+
+// one row of a thread's four cells, and the one value beyond the wave's
+// ends that lane 0 (left neighbour) or lane 63 (right neighbour) needs
+struct TagRow {
+    tag_d2 a, b;
+    double e;
+};
+
+// four consecutive velocity cells per thread (nv % 4 == 0), marching
+// kTagRows x rows with the rows i-1, i, i+1 in registers, so each row is
+// read about once (rows past the end of x, in the last block, are read
+// wrapped and their tags not stored); velocity neighbours come from the adjacent lanes, the
+// tags of the four cells leave in one 4-byte store
+__global__ __launch_bounds__(256) void k_tag4(const double* __restrict__ f, int nx, int nv, Ghosts g, double dx,
+                                              double dv, double tol, unsigned* __restrict__ tags4,
+                                              double* __restrict__ values)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int j0 = (int)(blockIdx.x * 256 + threadIdx.x) * 4;
+    const bool live = j0 < nv;
+    const int jc = live ? j0 : nv - 4;          // idle lanes read a valid group, store nothing
+    const bool edge = lane == 0 || lane == 63;
+    const int je = lane == 0 ? (jc > 0 ? jc - 1 : 0) : (jc + 4 < nv ? jc + 4 : nv - 1);
+    const int i0 = (int)blockIdx.y * kTagRows;
+    const int i1 = i0 + kTagRows < nx ? i0 + kTagRows : nx;
+    auto load = [&](int i, TagRow& r) {
+        const double* row = f + (size_t)wrapr(i, nx) * nv;
+        r.a = *reinterpret_cast<const tag_d2*>(row + jc);
+        r.b = *reinterpret_cast<const tag_d2*>(row + jc + 2);
+        r.e = edge ? row[je] : 0.0;
+    };
+    // fully unrolled, so that the rows need no register moves and the load
+    // of row i + 2 is in flight while row i is evaluated
+    TagRow r[kTagRows + 2];
+    load(i0 - 1, r[0]);
+    load(i0, r[1]);
+#pragma unroll
+    for (int k = 0; k < kTagRows; ++k) {
+        if (k == 0) load(i0 + 1, r[2]);
+        if (k + 3 < kTagRows + 2) load(i0 + k + 2, r[k + 3]);
+        const TagRow& m = r[k];
+        const TagRow& c = r[k + 1];
+        const TagRow& p = r[k + 2];
+        double vlo = tag_dpp<0x138>(c.b.y), vhi = tag_dpp<0x130>(c.a.x);
+        if (lane == 0) vlo = c.e;
+        if (lane == 63) vhi = c.e;
+        if (jc == 0) vlo = g.v[1];
+        if (jc + 4 >= nv) vhi = g.v[2];
+        const double cv[6] = {vlo, c.a.x, c.a.y, c.b.x, c.b.y, vhi};
+        const double xm[4] = {m.a.x, m.a.y, m.b.x, m.b.y}, xp[4] = {p.a.x, p.a.y, p.b.x, p.b.y};
+        unsigned packed = 0;
+        double t[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            t[w] = tag_from(cv[w + 1], xm[w], xp[w], cv[w], cv[w + 2], dx, dv);
+            packed |= (t[w] > tol ? 1u : 0u) << (8 * w);
+        }
+        const int i = i0 + k;
+        if (live && i < i1) {
+            const size_t e = (size_t)i * nv + j0;
+            tags4[e / 4] = packed;
+            if (values) {
+                *reinterpret_cast<tag_d2*>(values + e) = tag_d2{t[0], t[1]};
+                *reinterpret_cast<tag_d2*>(values + e + 2) = tag_d2{t[2], t[3]};
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_tag(const double* __restrict__ f, int nx, int nv, Ghosts g, double dx,
@@ -163,8 +252,16 @@ hipError_t launch_tag(const double* f, int nx, int nv, const double* vg, double 
 {
     Ghosts g;
     for (int q = 0; q < 4; ++q) g.v[q] = vg[q];
-    const dim3 grid((unsigned)((nv + 255) / 256), (unsigned)nx);
-    hipLaunchKernelGGL(k_tag, grid, dim3(256), 0, stream, f, nx, nv, g, dx, dv, tol, tags, values);
+    const bool al = (reinterpret_cast<uintptr_t>(f) % 16 == 0) && (reinterpret_cast<uintptr_t>(tags) % 4 == 0) &&
+                    (!values || reinterpret_cast<uintptr_t>(values) % 16 == 0);
+    if (nv % 4 == 0 && al) {
+        const dim3 grid((unsigned)((nv / 4 + 255) / 256), (unsigned)((nx + kTagRows - 1) / kTagRows));
+        hipLaunchKernelGGL(k_tag4, grid, dim3(256), 0, stream, f, nx, nv, g, dx, dv, tol,
+                           reinterpret_cast<unsigned*>(tags), values);
+    } else {
+        const dim3 grid((unsigned)((nv + 255) / 256), (unsigned)nx);
+        hipLaunchKernelGGL(k_tag, grid, dim3(256), 0, stream, f, nx, nv, g, dx, dv, tol, tags, values);
+    }
     return hipGetLastError();
 }
 
