@@ -401,6 +401,70 @@ vp_status vp_cluster_tags(const uint8_t* tags, int32_t ncx, int32_t ncv, int32_t
 vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const vp_plan* new_plan, void* f_new,
                              hipStream_t stream);
 
+/*
+ * Adaptive two-level run: the time loop of Alg. smsvphu with regridding
+ * (section 3) and the time step control of the numerical results
+ * (section 4), in the library.  A run owns the plan of its current
+ * hierarchy and the device buffers of its state, field and workspace.
+ *
+ * Time step: dt = min(cap, cfl * L), L the largest step with
+ * dt (max|v| / dx + max|a| / dv) <= 1 on every level (level 0 over the
+ * whole mesh; level 1 per patch, over the patch's velocity faces and
+ * configuration columns); cap = dt_initial for the first step, else
+ * dt_growth times the previous step.  Regridding after every
+ * regrid_interval steps: vp_tag_cells with tol, vp_cluster_tags with
+ * efficiency, min_width and buffer, a new plan with the same problem and
+ * the new boxes (default tile shape, launch mode and reduction),
+ * vp_regrid_transfer, then the field of the new state.
+ */
+typedef struct vp_amr_params {
+    double tol;                /* refinement threshold of delta1 f + delta2 f (>= 0)   */
+    int32_t regrid_interval;   /* steps between regrids (>= 1)                          */
+    double efficiency;         /* clustering: tagged fraction of a box, (0, 1]         */
+    int32_t min_width;         /* clustering: smallest split part, level-0 cells (>= 1) */
+    int32_t buffer;            /* level-0 cells added around tagged regions (>= 0)     */
+    double cfl;                /* fraction of the stability limit (> 0; 0.5)           */
+    double dt_growth;          /* largest ratio of consecutive steps (>= 1; 1.1)       */
+    double dt_initial;         /* first time step (> 0)                                 */
+} vp_amr_params;
+
+typedef struct vp_amr_info {
+    double t;                  /* time reached                                           */
+    double dt;                 /* last time step                                         */
+    int64_t steps;             /* steps taken                                            */
+    int32_t regrids;           /* regrids done                                           */
+    int32_t npatch;            /* level-1 patches of the current hierarchy              */
+    int64_t state_elems;       /* elements of the current state (vp_state_elems)        */
+    double regrid_seconds;     /* host wall time spent in regrids (tag read-back,
+                                  clustering, plan creation, transfer, field)            */
+} vp_amr_info;
+
+typedef struct vp_amr_run vp_amr_run;
+
+/* Creates a run from a two-level 1D+1V FP64 problem, its initial boxes and
+ * the initial state f0 (device, the layout of vp_plan_create(problem,
+ * boxes), copied).  Allocates device memory; enqueues the copy and the
+ * field solve on `stream`.  VP_EINVAL for bad parameters or a problem
+ * without two levels; plan creation errors as vp_plan_create. */
+vp_status vp_amr_run_create(const vp_problem* problem, const vp_box* boxes, int32_t nbox, const void* f0,
+                            const vp_amr_params* params, vp_amr_run** out, hipStream_t stream);
+/* Advances `steps` time steps on `stream`.  Synchronises the stream every
+ * step (the time step needs max|a| on the host) and at every regrid, which
+ * allocates the new state and frees the old one.  After an error the run
+ * should only be destroyed. */
+vp_status vp_amr_run_advance(vp_amr_run* run, int32_t steps, hipStream_t stream);
+vp_status vp_amr_run_info(const vp_amr_run* run, vp_amr_info* info);
+/* The plan of the current hierarchy (owned by the run; replaced at a regrid). */
+const vp_plan* vp_amr_run_plan(const vp_amr_run* run);
+/* The current boxes (level-1 index space); *nbox receives the count,
+ * VP_EINVAL when it exceeds max_boxes. */
+vp_status vp_amr_run_boxes(const vp_amr_run* run, vp_box* boxes, int32_t max_boxes, int32_t* nbox);
+/* Copies the current state into dst (device, elems == vp_state_elems of
+ * the current plan, else VP_ESHAPE); enqueued on `stream`. */
+vp_status vp_amr_run_read_state(const vp_amr_run* run, void* dst, size_t elems, hipStream_t stream);
+/* Waits for the device, frees the run's memory and plan.  NULL is a no-op. */
+vp_status vp_amr_run_destroy(vp_amr_run* run);
+
 #ifdef __cplusplus
 }
 #endif

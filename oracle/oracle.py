@@ -243,6 +243,50 @@ def prolong_box(fc, vghost_c, R, box):
     return out
 
 
+def regrid_transfer(f_old, old_boxes, new_boxes, ncx, ncv, R, vghost_c):
+    """State of a new two-level hierarchy after a regrid (section 3): level 0
+    unchanged; a new fine cell keeps the old fine value where an old patch
+    covered it, else takes the conservative limited interpolation of level 0
+    (x then v).  Boxes: dicts with inclusive level-1 lo/hi; states flat
+    [level 0][patch 0][patch 1]..."""
+    f_old = _f64(f_old)
+    nc = ncx * ncv
+    f0 = f_old[:nc].reshape(ncx, ncv)
+    old, off = [], nc
+    for b in old_boxes:
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        n = (x1 - x0 + 1) * (v1 - v0 + 1)
+        old.append(((x0, v0, x1, v1), f_old[off:off + n].reshape(x1 - x0 + 1, v1 - v0 + 1)))
+        off += n
+    parts = [f_old[:nc].copy()]
+    for b in new_boxes:
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        fine = prolong_box(f0, vghost_c, R, (x0, v0, x1, v1))
+        for (a0, b0, a1, b1), blk in old:
+            ix0, ix1, iv0, iv1 = max(x0, a0), min(x1, a1), max(v0, b0), min(v1, b1)
+            if ix0 <= ix1 and iv0 <= iv1:
+                fine[ix0 - x0:ix1 - x0 + 1, iv0 - v0:iv1 - v0 + 1] = blk[ix0 - a0:ix1 - a0 + 1, iv0 - b0:iv1 - b0 + 1]
+        parts.append(fine.ravel())
+    return np.concatenate(parts)
+
+
+def amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, boxes):
+    """Largest dt with dt (max|v| / dx + max|a| / dv) <= 1 on every level of a
+    two-level hierarchy: level 0 over its whole mesh; level 1 per patch, with
+    the largest |v| on the patch's velocity faces and the largest |a| over the
+    fine configuration columns it covers.  a = [a_coarse (ncx)][a_fine (ncx R)]."""
+    a = _f64(a)
+    dxc, dvc = x_len / ncx, (v_hi - v_lo) / ncv
+    dxf, dvf = dxc / R, dvc / R
+    rate = max(abs(v_lo), abs(v_hi)) / dxc + np.abs(a[:ncx]).max() / dvc
+    af = a[ncx:]
+    for b in boxes:
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        vmax = max(abs(v_lo + v0 * dvf), abs(v_lo + (v1 + 1) * dvf))
+        rate = max(rate, vmax / dxf + np.abs(af[x0:x1 + 1]).max() / dvf)
+    return 1.0 / rate
+
+
 class Oracle1D:
     """Single-level 1D+1V oracle bound to one mesh (Poisson factors kept)."""
 

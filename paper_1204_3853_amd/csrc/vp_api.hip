@@ -158,6 +158,11 @@ vp_status create_two_level(const vp_problem* pb, const vp_box* boxes, int nbox, 
     for (int l = 0; l < VP_MAX_LEVELS; ++l)
         for (int d = 0; d < 2; ++d) p->pb.veq[l][d] = nullptr;
     vp_status st = amr_create(p, pb, boxes, nbox);
+    if (st == VP_OK) {
+        // kept so that a plan of another hierarchy can be made from this one
+        p->veq[0][0].assign(pb->veq[0][0], pb->veq[0][0] + pb->cells[1] + 4);
+        p->veq[1][0].assign(pb->veq[1][0], pb->veq[1][0] + pb->cells[1] * pb->ratio[1] + 4);
+    }
     if (st != VP_OK) {
         amr_destroy(p);
         delete p;

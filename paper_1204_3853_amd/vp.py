@@ -48,6 +48,18 @@ class vp_box(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("lo", ctypes.c_int32 * 4), ("hi", ctypes.c_int32 * 4)]
 
 
+class vp_amr_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("regrid_interval", ctypes.c_int32), ("efficiency", ctypes.c_double),
+                ("min_width", ctypes.c_int32), ("buffer", ctypes.c_int32), ("cfl", ctypes.c_double),
+                ("dt_growth", ctypes.c_double), ("dt_initial", ctypes.c_double)]
+
+
+class vp_amr_info(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("regrids", ctypes.c_int32), ("npatch", ctypes.c_int32), ("state_elems", ctypes.c_int64),
+                ("regrid_seconds", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -90,6 +102,14 @@ SIGNATURES = {
                                        _D, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp_box), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32)]),
     "vp_regrid_transfer": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "vp_amr_run_create": (ctypes.c_int, [ctypes.POINTER(vp_problem), ctypes.POINTER(vp_box), ctypes.c_int32, _P,
+                                         ctypes.POINTER(vp_amr_params), ctypes.POINTER(_P), _P]),
+    "vp_amr_run_advance": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "vp_amr_run_info": (ctypes.c_int, [_P, ctypes.POINTER(vp_amr_info)]),
+    "vp_amr_run_plan": (_P, [_P]),
+    "vp_amr_run_boxes": (ctypes.c_int, [_P, ctypes.POINTER(vp_box), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "vp_amr_run_read_state": (ctypes.c_int, [_P, _P, _S, _P]),
+    "vp_amr_run_destroy": (ctypes.c_int, [_P]),
 }
 
 TIMING_CLASSES = ["stage", "field", "moment", "sync", "adjoint", "other"]
@@ -126,6 +146,50 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _make_problem(spec, dtype):
+    """vp_problem from a spec dict; returns (problem, buffers to keep alive)."""
+    pb = vp_problem()
+    keep = []
+    pb.ndim = spec["ndim"]
+    pb.dtype = VP_F64 if dtype == torch.float64 else VP_F32
+    pb.n_levels = spec.get("n_levels", 1)
+    for d, c in enumerate(spec["cells"]):
+        pb.cells[d] = c
+    for d, r in enumerate(spec.get("ratio", [1, 1, 1, 1])):
+        pb.ratio[d] = r
+    for d in range(spec["ndim"]):
+        pb.x_lo[d] = spec["x_lo"][d]
+        pb.x_len[d] = spec["x_len"][d]
+        pb.v_lo[d] = spec["v_lo"][d]
+        pb.v_hi[d] = spec["v_hi"][d]
+    pb.qm = spec["qm"]
+    for lvl, dirs in enumerate(spec["veq"]):
+        for d, arr in enumerate(dirs):
+            buf = (ctypes.c_double * len(arr))(*[float(x) for x in arr])
+            keep.append(buf)
+            pb.veq[lvl][d] = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+    return pb, keep
+
+
+def _make_boxes(boxes):
+    """(vp_box array or None, count) from dicts with level, lo, hi."""
+    if not boxes:
+        return None, 0
+    bx = (vp_box * len(boxes))()
+    for q, b in enumerate(boxes):
+        bx[q].level = b.get("level", 1)
+        for d, v in enumerate(b["lo"]):
+            bx[q].lo[d] = v
+        for d, v in enumerate(b["hi"]):
+            bx[q].hi[d] = v
+    return bx, len(boxes)
+
+
+def _boxes_out(arr, n):
+    return [{"level": arr[q].level, "lo": [arr[q].lo[0], arr[q].lo[1]], "hi": [arr[q].hi[0], arr[q].hi[1]]}
+            for q in range(n)]
+
+
 class Plan:
     """An immutable plan (vp_plan) plus the device workspace used by its calls.
 
@@ -138,39 +202,10 @@ class Plan:
             raise RuntimeError("the Vlasov-Poisson library needs a HIP GPU (torch.cuda is unavailable)")
         self.device = torch.device(device)
         self.dtype = dtype
-        pb = vp_problem()
-        self._keep = []
         spec = problem if isinstance(problem, dict) else _problem_dict(problem)
-        pb.ndim = spec["ndim"]
-        pb.dtype = VP_F64 if dtype == torch.float64 else VP_F32
-        pb.n_levels = spec.get("n_levels", 1)
-        for d, c in enumerate(spec["cells"]):
-            pb.cells[d] = c
-        for d, r in enumerate(spec.get("ratio", [1, 1, 1, 1])):
-            pb.ratio[d] = r
-        for d in range(spec["ndim"]):
-            pb.x_lo[d] = spec["x_lo"][d]
-            pb.x_len[d] = spec["x_len"][d]
-            pb.v_lo[d] = spec["v_lo"][d]
-            pb.v_hi[d] = spec["v_hi"][d]
-        pb.qm = spec["qm"]
-        for lvl, dirs in enumerate(spec["veq"]):
-            for d, arr in enumerate(dirs):
-                buf = (ctypes.c_double * len(arr))(*[float(x) for x in arr])
-                self._keep.append(buf)
-                pb.veq[lvl][d] = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+        pb, self._keep = _make_problem(spec, dtype)
         self.spec = spec
-        nbox = 0
-        bx = None
-        if boxes:
-            nbox = len(boxes)
-            bx = (vp_box * nbox)()
-            for q, b in enumerate(boxes):
-                bx[q].level = b.get("level", 1)
-                for d, v in enumerate(b["lo"]):
-                    bx[q].lo[d] = v
-                for d, v in enumerate(b["hi"]):
-                    bx[q].hi[d] = v
+        bx, nbox = _make_boxes(boxes)
         h = ctypes.c_void_p()
         _check(lib().vp_plan_create(ctypes.byref(pb), bx, nbox, ctypes.byref(h)))
         self.h = h
@@ -378,8 +413,7 @@ def cluster_tags(tags, ratio, efficiency=0.7, min_width=2, buffer=1, max_boxes=4
     n = ctypes.c_int32()
     _check(lib().vp_cluster_tags(t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ncx, ncv, ratio,
                                  ctypes.c_double(efficiency), min_width, buffer, out, max_boxes, ctypes.byref(n)))
-    return [{"level": 1, "lo": [out[q].lo[0], out[q].lo[1]], "hi": [out[q].hi[0], out[q].hi[1]]}
-            for q in range(n.value)]
+    return _boxes_out(out, n.value)
 
 
 def regrid_transfer(old_plan, f_old, new_plan, f_new=None):
@@ -400,3 +434,57 @@ def regrid(plan, f, tol, efficiency=0.7, min_width=2, buffer=1):
     boxes = cluster_tags(tags.cpu(), plan.spec["ratio"][0], efficiency, min_width, buffer)
     new_plan = Plan(plan.spec, dtype=plan.dtype, boxes=boxes, device=plan.device)
     return new_plan, regrid_transfer(plan, f, new_plan), boxes
+
+
+# -------------------------------------------------------------------- adaptive run
+
+
+class AmrRun:
+    """Adaptive two-level run (vp_amr_run): RK4 steps with a time step
+    limited by the stability condition, regridding every regrid_interval
+    steps.  spec: a two-level spec dict (two_level_spec); boxes: the
+    initial level-1 boxes; f0: the initial state in that plan's layout."""
+
+    def __init__(self, spec, boxes, f0, tol, regrid_interval, efficiency=0.7, min_width=2, buffer=1, cfl=0.5,
+                 dt_growth=1.1, dt_initial=0.01):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the Vlasov-Poisson library needs a HIP GPU (torch.cuda is unavailable)")
+        self.spec = spec
+        pb, keep = _make_problem(spec, torch.float64)
+        bx, nbox = _make_boxes(boxes)
+        prm = vp_amr_params(float(tol), int(regrid_interval), float(efficiency), int(min_width), int(buffer),
+                            float(cfl), float(dt_growth), float(dt_initial))
+        if f0.dtype != torch.float64 or not f0.is_cuda or not f0.is_contiguous():
+            raise ValueError("f0: contiguous float64 tensor on the GPU expected")
+        h = ctypes.c_void_p()
+        _check(lib().vp_amr_run_create(ctypes.byref(pb), bx, nbox, _ptr(f0), ctypes.byref(prm), ctypes.byref(h),
+                                       _stream()))
+        self.h = h
+        self.device = f0.device
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.vp_amr_run_destroy(self.h)
+            self.h = None
+
+    def advance(self, steps):
+        _check(lib().vp_amr_run_advance(self.h, int(steps), _stream()))
+
+    def info(self):
+        i = vp_amr_info()
+        _check(lib().vp_amr_run_info(self.h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in vp_amr_info._fields_}
+
+    def boxes(self):
+        n = ctypes.c_int32()
+        cap = max(self.info()["npatch"], 1)
+        arr = (vp_box * cap)()
+        _check(lib().vp_amr_run_boxes(self.h, arr, cap, ctypes.byref(n)))
+        return _boxes_out(arr, n.value)
+
+    def state(self):
+        """A copy of the current state (layout of the current hierarchy)."""
+        n = self.info()["state_elems"]
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(lib().vp_amr_run_read_state(self.h, _ptr(out), n, _stream()))
+        return out

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "vp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:vp_status|size_t|int64_t|const char\*)\s+(vp_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:vp_status|size_t|int64_t|const char\*|const vp_plan\*)\s+(vp_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -50,3 +50,27 @@ def test_null_plan_is_rejected_without_gpu(libvp):
     libvp.vp_last_error.restype = ctypes.c_char_p
     assert libvp.vp_rhs(None, None, None, None, None) == 1   # VP_EINVAL
     assert b"NULL" in libvp.vp_last_error()
+
+
+def test_amr_run_parameters_rejected_without_gpu(libvp):
+    """vp_amr_run_create validates its parameters on the host before any HIP call."""
+    from paper_1204_3853_amd import vp
+    L = vp.lib()
+    pb = vp.vp_problem()
+    pb.ndim, pb.n_levels = 1, 2
+    out = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)
+    good = dict(tol=0.01, regrid_interval=2, efficiency=0.7, min_width=2, buffer=1, cfl=0.5, dt_growth=1.1,
+                dt_initial=0.01)
+    for bad in (dict(regrid_interval=0), dict(efficiency=0.0), dict(efficiency=1.5), dict(min_width=0),
+                dict(buffer=-1), dict(cfl=0.0), dict(dt_growth=0.5), dict(dt_initial=0.0), dict(tol=-1.0),
+                dict(tol=float("nan"))):
+        prm = vp.vp_amr_params(**dict(good, **bad))
+        assert L.vp_amr_run_create(ctypes.byref(pb), None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
+        assert b"bad parameters" in L.vp_last_error()
+    pb.n_levels = 1
+    prm = vp.vp_amr_params(**good)
+    assert L.vp_amr_run_create(ctypes.byref(pb), None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
+    assert b"two levels" in L.vp_last_error()
+    assert L.vp_amr_run_create(None, None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
+    assert L.vp_amr_run_destroy(None) == 0

@@ -1,0 +1,147 @@
+"""GPU parity of the adaptive two-level run (vp_amr_run_*) against the
+oracle on the bump-on-tail problem of section 4.
+
+The run advances RK4 steps with dt = min(cap, cfl * L) (L the stability
+limit of every level, cap = dt_initial first, then dt_growth times the
+previous step) and regrids every regrid_interval steps.  The test follows
+the same sequence with the oracle: its own field, time steps, RK4 steps,
+tags and state transfer.  The boxes of each regrid are taken from the run
+after checking that they are a valid clustering of the oracle's own tags
+(several clusterings are correct, so the boxes are checked, not compared).
+States after every regrid agree to 1e-12 per step relative; the times agree
+to rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import vp_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vp():
+    from paper_1204_3853_amd import vp as V
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return V
+
+
+def check_clustering(tags, values, tol, boxes, R):
+    """Every oracle-tagged level-0 cell (except the last column, never refined,
+    and cells whose criterion is within 1e-9 of tol) lies in a box; boxes are
+    aligned, inside the refinable range and a level-0 cell apart."""
+    ncx, ncv = tags.shape
+    cov = np.zeros(tags.shape, dtype=bool)
+    cb = []
+    for b in boxes:
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        assert x0 % R == 0 and v0 % R == 0 and (x1 + 1) % R == 0 and (v1 + 1) % R == 0
+        c = (x0 // R, v0 // R, (x1 + 1) // R - 1, (v1 + 1) // R - 1)
+        assert 0 <= c[0] <= c[2] <= ncx - 2 and 0 <= c[1] <= c[3] <= ncv - 1
+        cov[c[0]:c[2] + 1, c[1]:c[3] + 1] = True
+        cb.append(c)
+    sure = tags.astype(bool) & (np.abs(values - tol) > 1e-9 * tol)
+    sure[-1, :] = False
+    assert not (sure & ~cov).any()
+    for p in range(len(cb)):
+        for q in range(p + 1, len(cb)):
+            A, B = cb[p], cb[q]
+            for sh in (0, -ncx, ncx):
+                assert max(A[0], B[0] + sh) - min(A[2], B[2] + sh) > 1 or max(A[1], B[1]) - min(A[3], B[3]) > 1
+
+
+def oracle_run(oracle, run, coarse, R, boxes, f0, veq_c, veq_f, tol, interval, blocks, cfl, growth, dt0):
+    """Follows the run block by block; yields (gpu state, oracle state, steps)."""
+    ncx, ncv = coarse
+    x_len, v_lo, v_hi = I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI
+    dxc, dvc = x_len / ncx, (v_hi - v_lo) / ncv
+    g = np.array([veq_c[0], veq_c[1], veq_c[ncv + 2], veq_c[ncv + 3]])
+    o = oracle.OracleAMR(ncx, ncv, x_len, v_lo, v_hi, -1.0, R, boxes, veq_c, veq_f)
+    f = np.array(f0)
+    a, _ = o.constraints(f)
+    dt, t, steps = None, 0.0, 0
+    for _ in range(blocks):
+        run.advance(interval)
+        for _ in range(interval):
+            lim = oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, boxes)
+            dt = min(dt0 if dt is None else growth * dt, cfl * lim)
+            f = o.step(f, dt)
+            a, _ = o.constraints(f)
+            t += dt
+            steps += 1
+        f0c = f[:ncx * ncv].reshape(ncx, ncv)
+        vals = oracle.tag_values(f0c, dxc, dvc, g)
+        tags = oracle.tag(f0c, dxc, dvc, g, tol)
+        new_boxes = run.boxes()
+        check_clustering(tags, vals, tol, new_boxes, R)
+        f = oracle.regrid_transfer(f, boxes, new_boxes, ncx, ncv, R, g)
+        boxes = new_boxes
+        o = oracle.OracleAMR(ncx, ncv, x_len, v_lo, v_hi, -1.0, R, boxes, veq_c, veq_f)
+        a, _ = o.constraints(f)
+        info = run.info()
+        assert info["steps"] == steps and info["npatch"] == len(boxes)
+        assert abs(info["t"] - t) <= 1e-12 * t and abs(info["dt"] - dt) <= 1e-12 * dt
+        yield run.state().cpu().numpy(), f, steps
+
+
+@pytest.mark.parametrize("case", ["bump_32x64_r4", "bump_16x32_r2"])
+def test_run_matches_oracle(vp, oracle, case):
+    coarse, R, tol, interval, blocks = ((32, 64), 4, 0.02, 4, 3) if case == "bump_32x64_r4" else ((16, 32), 2, 0.01, 2, 4)
+    boxes = I.bump_on_tail_initial_boxes(coarse, R)
+    f0, veq_c, veq_f = I.amr_bump_on_tail(boxes, coarse, R)
+    spec = vp.two_level_spec(coarse[0], coarse[1], I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI, -1.0, R, veq_c, veq_f,
+                             x_lo=I.BUMP_X_LO)
+    run = vp.AmrRun(spec, boxes, torch.tensor(f0, device="cuda"), tol, interval, efficiency=0.7, min_width=2,
+                    buffer=1, cfl=0.5, dt_growth=1.1, dt_initial=0.01)
+    seen, layouts = 0, []
+    for got, want, steps in oracle_run(oracle, run, coarse, R, boxes, f0, veq_c, veq_f, tol, interval, blocks,
+                                       0.5, 1.1, 0.01):
+        assert got.shape == want.shape
+        assert np.abs(got - want).max() <= 1e-12 * steps * np.abs(want).max()
+        layouts.append(run.boxes())
+        seen += 1
+    assert seen == blocks and run.info()["regrids"] == blocks
+    # the regrids refine something, and not the initial layout
+    assert all(len(b) > 0 for b in layouts) and layouts[0] != boxes
+
+
+def test_run_without_tags_drops_the_patches(vp, oracle):
+    """A tolerance above every criterion value: the first regrid removes
+    level 1; the run goes on with the coarse level alone."""
+    coarse, R = (16, 32), 4
+    boxes = I.bump_on_tail_initial_boxes(coarse, R)
+    f0, veq_c, veq_f = I.amr_bump_on_tail(boxes, coarse, R)
+    spec = vp.two_level_spec(coarse[0], coarse[1], I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI, -1.0, R, veq_c, veq_f,
+                             x_lo=I.BUMP_X_LO)
+    run = vp.AmrRun(spec, boxes, torch.tensor(f0, device="cuda"), 1e30, 2)
+    results = list(oracle_run(oracle, run, coarse, R, boxes, f0, veq_c, veq_f, 1e30, 2, 2, 0.5, 1.1, 0.01))
+    assert run.boxes() == []
+    for got, want, steps in results:
+        assert got.size == coarse[0] * coarse[1]
+        assert np.abs(got - want).max() <= 1e-12 * steps * np.abs(want).max()
+
+
+def test_run_errors(vp):
+    coarse, R = (16, 32), 4
+    boxes = I.bump_on_tail_initial_boxes(coarse, R)
+    f0, veq_c, veq_f = I.amr_bump_on_tail(boxes, coarse, R)
+    spec = vp.two_level_spec(coarse[0], coarse[1], I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI, -1.0, R, veq_c, veq_f,
+                             x_lo=I.BUMP_X_LO)
+    fg = torch.tensor(f0, device="cuda")
+    with pytest.raises(vp.VPError, match="bad parameters"):
+        vp.AmrRun(spec, boxes, fg, 0.01, 0)
+    with pytest.raises(vp.VPError, match="bad parameters"):
+        vp.AmrRun(spec, boxes, fg, 0.01, 2, dt_growth=0.9)
+    with pytest.raises(vp.VPError, match="two levels"):
+        single = dict(spec, n_levels=1, veq=[[veq_c]])
+        vp.AmrRun(single, [], fg, 0.01, 2)
+    run = vp.AmrRun(spec, boxes, fg, 0.01, 2)
+    with pytest.raises(vp.VPError, match="negative"):
+        run.advance(-1)
+    run.advance(0)
+    assert run.info()["steps"] == 0 and run.info()["t"] == 0.0

@@ -153,3 +153,50 @@ def test_tag_covariance_and_constant(oracle):
     assert np.all(oracle.tag_values(c, 0.3, 0.2, np.full(4, 0.7)) == 0.0)
     tags = oracle.tag(f, 0.3, 0.2, vg, float(np.median(t)))
     assert np.array_equal(tags, (t > np.median(t)).astype(np.uint8))
+
+
+def test_regrid_transfer_keeps_old_values_and_conserves(oracle):
+    """State transfer at a regrid: level 0 unchanged, fine values kept where an
+    old patch covered the cell, every new patch's coarse averages equal to
+    level 0 where it interpolates."""
+    rng = np.random.default_rng(4)
+    ncx, ncv, R = 16, 20, 2
+    f0 = rng.random((ncx, ncv)) + 0.5
+    vg = rng.random(4) + 0.5
+    old_boxes = [{"level": 1, "lo": [4, 8], "hi": [11, 19]}]
+    new_boxes = [{"level": 1, "lo": [8, 4], "hi": [15, 15]}, {"level": 1, "lo": [20, 20], "hi": [27, 39]}]
+    old_fine = rng.random((8, 12)) + 0.5
+    f_old = np.concatenate([f0.ravel(), old_fine.ravel()])
+    fn = oracle.regrid_transfer(f_old, old_boxes, new_boxes, ncx, ncv, R, vg)
+    assert np.array_equal(fn[:ncx * ncv], f0.ravel())
+    p0 = fn[ncx * ncv:ncx * ncv + 8 * 12].reshape(8, 12)
+    p1 = fn[ncx * ncv + 8 * 12:].reshape(8, 20)
+    # overlap of the first new box with the old one: fine x 8..11, v 8..15
+    assert np.array_equal(p0[0:4, 4:12], old_fine[4:8, 0:8])
+    # the second new box touches no old patch: conservative
+    for cx in range(4):
+        for cv in range(10):
+            assert abs(p1[2 * cx:2 * cx + 2, 2 * cv:2 * cv + 2].mean() - f0[10 + cx, 10 + cv]) <= 1e-14
+    # coarse cells of the first box outside the overlap are conserved too
+    for cx, cv in ((4, 2), (5, 3), (7, 2), (6, 7)):
+        blk = p0[2 * (cx - 4):2 * (cx - 4) + 2, 2 * (cv - 2):2 * (cv - 2) + 2]
+        if cx >= 6 or cv < 4:
+            assert abs(blk.mean() - f0[cx, cv]) <= 1e-14
+
+
+def test_stability_limit_closed_forms(oracle):
+    ncx, ncv, R, x_len, v_lo, v_hi = 8, 16, 4, 2.0, -8.0, 10.0
+    dxc, dvc = x_len / ncx, (v_hi - v_lo) / ncv
+    a = np.zeros(ncx + ncx * R)
+    assert oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, []) == pytest.approx(dxc / 10.0, rel=1e-15)
+    a[:ncx] = 0.5
+    a[ncx:] = np.linspace(-2.0, 1.0, ncx * R)
+    want0 = 1.0 / (10.0 / dxc + 0.5 / dvc)
+    assert oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, []) == pytest.approx(want0, rel=1e-15)
+    # a patch over fine v cells 8..15 (faces at v = -5.75 and -3.5) and fine x 0..3 (a in [-2, -1.71])
+    box = {"level": 1, "lo": [0, 8], "hi": [3, 15]}
+    dxf, dvf = dxc / R, dvc / R
+    want1 = 1.0 / (5.75 / dxf + 2.0 / dvf)
+    got = oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, [box])
+    assert got == pytest.approx(min(want0, want1), rel=1e-15)
+    assert got == oracle.amr_stability_limit(-a, ncx, ncv, R, x_len, v_lo, v_hi, [box])

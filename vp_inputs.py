@@ -230,22 +230,50 @@ def amr_boxes(seed: int = 0, coarse=(512, 512), ratio: int = 4, npatch: int = 40
     return [{"level": 1, "lo": list(b[0]), "hi": list(b[1])} for b in boxes]
 
 
-def amr_landau(boxes, coarse=(512, 512), ratio: int = 4, eps: float = 0.01, k: float = 0.5):
-    """Two-level Landau problem: exact cell averages of (1 + eps cos(k x)) M(v)
-    on the coarse level (all cells) and on every patch, concatenated in the
-    state layout [coarse][patch 0][patch 1]...; returns (state, veq_c, veq_f)."""
+def _amr_state(profile, x_lo, x_len, v_lo, v_hi, eps, k, boxes, coarse, ratio):
+    """Exact cell averages of (1 + eps cos(k x)) profile(v) on the coarse
+    level (all cells) and on every patch, concatenated in the state layout
+    [coarse][patch 0][patch 1]...; returns (state, veq_c, veq_f)."""
     ncx, ncv = coarse
-    x_len, v_lo, v_hi = 4.0 * math.pi, -8.0, 8.0
-    veq_c = cell_average_1d(maxwellian, v_lo, v_hi, ncv, first=-2, count=ncv + 4)
+    veq_c = cell_average_1d(profile, v_lo, v_hi, ncv, first=-2, count=ncv + 4)
     nvf = ncv * ratio
-    veq_f = cell_average_1d(maxwellian, v_lo, v_hi, nvf, first=-2, count=nvf + 4)
-    xc = 1.0 + eps * cos_cell_average(0.0, x_len, ncx, k)
-    xf = 1.0 + eps * cos_cell_average(0.0, x_len, ncx * ratio, k)
+    veq_f = cell_average_1d(profile, v_lo, v_hi, nvf, first=-2, count=nvf + 4)
+    xc = 1.0 + eps * cos_cell_average(x_lo, x_len, ncx, k)
+    xf = 1.0 + eps * cos_cell_average(x_lo, x_len, ncx * ratio, k)
     parts = [(xc[:, None] * veq_c[None, 2:ncv + 2]).ravel()]
     for b in boxes:
         (x0, v0), (x1, v1) = b["lo"], b["hi"]
         parts.append((xf[x0:x1 + 1, None] * veq_f[None, 2 + v0:2 + v1 + 1]).ravel())
     return np.concatenate(parts), veq_c, veq_f
+
+
+def amr_landau(boxes, coarse=(512, 512), ratio: int = 4, eps: float = 0.01, k: float = 0.5):
+    """Two-level Landau problem on [0, 4 pi) x [-8, 8]: (1 + eps cos(k x)) M(v);
+    returns (state, veq_c, veq_f)."""
+    return _amr_state(maxwellian, 0.0, 4.0 * math.pi, -8.0, 8.0, eps, k, boxes, coarse, ratio)
+
+
+# bump-on-tail problem of the numerical results (section 4)
+BUMP_X_LO = -10.0 * math.pi / 3.0
+BUMP_X_LEN = 20.0 * math.pi / 3.0
+BUMP_V_LO, BUMP_V_HI = -8.0, 10.0
+
+
+def amr_bump_on_tail(boxes, coarse=(16, 32), ratio: int = 4, eps: float = 0.04, k: float = 0.3):
+    """Two-level bump-on-tail problem: (1 + 0.04 cos(0.3 x)) f_b(v) on
+    [-10 pi/3, 10 pi/3) x [-8, 10]; returns (state, veq_c, veq_f)."""
+    return _amr_state(bump_on_tail_profile, BUMP_X_LO, BUMP_X_LEN, BUMP_V_LO, BUMP_V_HI, eps, k, boxes, coarse,
+                      ratio)
+
+
+def bump_on_tail_initial_boxes(coarse=(16, 32), ratio: int = 4):
+    """The initial refinement of the bump-on-tail run, level-0 cells
+    [0, 15] x [8, 24] of a 16 x 32 mesh, scaled to `coarse`; the last
+    level-0 column is left out (a patch may not meet itself across the
+    periodic boundary)."""
+    ncx, ncv = coarse
+    sv = ncv // 32
+    return [{"level": 1, "lo": [0, 8 * sv * ratio], "hi": [(ncx - 1) * ratio - 1, (24 * sv + sv) * ratio - 1]}]
 
 
 def save_boxes(path, boxes):
