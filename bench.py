@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-limited", action="store_true")
     ap.add_argument("--no-regrid", action="store_true")
     ap.add_argument("--regrid-only", action="store_true", help="run only the regridding section (for profiling)")
+    ap.add_argument("--no-amr-run", action="store_true")
+    ap.add_argument("--amr-run-only", action="store_true", help="run only the adaptive bump-on-tail section")
+    ap.add_argument("--amr-run-t", type=float, default=22.5, help="end time of the adaptive bump-on-tail runs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape of the main workload")
     ap.add_argument("--tile-shape", default=None, metavar="T,W,R",
                     help="use this tile shape (threads, cells per thread, rows) instead of autotuning")
@@ -342,6 +345,73 @@ def regrid_bench(reps=50):
     return out
 
 
+def amr_run_bench(t_end=22.5):
+    """Adaptive bump-on-tail runs (section 4) on the two-level engine: level 0
+    64 x 128, ratio 2, so the finest mesh is the 128 x 256 the paper's AMR
+    runs resolve; tol = 0.01, dt = min(1.1 x previous, 0.5 x stability
+    limit), first dt 0.01.  Three regrid settings after the paper's AMR1-3
+    (regrid interval 2 / 4 / 8 steps, tag buffer 1 / 4 / 8 level-0 cells,
+    smallest split part 2 / 4 / 4 level-0 cells), each run to t_end; then
+    a uniform 128 x 256 run to t_end with the same time step rule.  Reports
+    wall time, regrid time, and the mean number of cells against the
+    uniform mesh."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+    coarse, R, tol = (64, 128), 2, 0.01
+    ncx, ncv = coarse
+    boxes0 = I.bump_on_tail_initial_boxes(coarse, R)
+    f0, veq_c, veq_f = I.amr_bump_on_tail(boxes0, coarse, R)
+    spec = vp.two_level_spec(ncx, ncv, I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI, -1.0, R, veq_c, veq_f,
+                             x_lo=I.BUMP_X_LO)
+    fg = torch.tensor(f0, device="cuda")
+    uniform_cells = ncx * R * ncv * R
+    out = {"workload": f"bump-on-tail, level 0 {ncx} x {ncv}, ratio {R}, tol {tol}, to t = {t_end}"}
+    for name, interval, buf, minw in (("amr1", 2, 1, 2), ("amr2", 4, 4, 4), ("amr3", 8, 8, 4)):
+        run = vp.AmrRun(spec, boxes0, fg, tol, interval, efficiency=0.7, min_width=minw, buffer=buf, cfl=0.5,
+                        dt_growth=1.1, dt_initial=0.01)
+        torch.cuda.synchronize()
+        cell_steps, t0 = 0, time.perf_counter()
+        info = run.info()
+        while info["t"] < t_end:
+            cells = info["state_elems"]
+            run.advance(interval)
+            info = run.info()
+            cell_steps += cells * interval
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"regrid_interval": interval, "tag_buffer": buf, "steps": info["steps"],
+                     "t_end": round(info["t"], 3), "wall_s": round(wall, 3),
+                     "ms_per_step": round(wall / info["steps"] * 1e3, 3), "regrids": info["regrids"],
+                     "regrid_s": round(info["regrid_seconds"], 3), "final_patches": info["npatch"],
+                     "mean_cells": round(cell_steps / info["steps"]), "uniform_cells": uniform_cells,
+                     "mean_reduction": round(1.0 - cell_steps / info["steps"] / uniform_cells, 3)}
+        print(f"amr_run {name}: {out[name]}", file=sys.stderr, flush=True)
+        del run
+    # uniform 128 x 256 reference with the same time step rule
+    nx, nv = ncx * R, ncv * R
+    prob = I.Problem1D(nx=nx, nv=nv, x_lo=I.BUMP_X_LO, x_len=I.BUMP_X_LEN, v_lo=I.BUMP_V_LO, v_hi=I.BUMP_V_HI,
+                       profile="bump_on_tail", eps=0.04, k=0.3)
+    plan = vp.Plan(prob)
+    f = torch.tensor(prob.initial_state().ravel(), device="cuda")
+    a = vp.field_of(plan, f)
+    vmax = max(abs(I.BUMP_V_LO), abs(I.BUMP_V_HI))
+    torch.cuda.synchronize()
+    t, dt, steps, t0 = 0.0, None, 0, time.perf_counter()
+    while t < t_end:
+        lim = 1.0 / (vmax / prob.dx + float(a.abs().max()) / prob.dv)
+        dt = min(0.01 if dt is None else 1.1 * dt, 0.5 * lim)
+        vp.rk4_step(plan, f, a, dt)
+        t += dt
+        steps += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out["uniform"] = {"cells": nx * nv, "steps": steps, "t_end": round(t, 3), "wall_s": round(wall, 3),
+                      "ms_per_step": round(wall / steps * 1e3, 3)}
+    return out
+
+
 def fourd_bench(steps=50, warmup=3):
     """2D+2V 64^4 FP64 (x, y in [0, 4pi), v in [-6, 6]^2, Landau-type
     initial state): RK4 steps after the load-batch autotune."""
@@ -410,6 +480,9 @@ def main():
     if args.regrid_only:
         print(json.dumps({"regrid": regrid_bench()}), flush=True)
         return
+    if args.amr_run_only:
+        print(json.dumps({"amr_run": amr_run_bench(args.amr_run_t)}), flush=True)
+        return
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
     n = args.n
     p = I.two_stream(n, n)
@@ -468,6 +541,7 @@ def main():
     fourd = None if args.no_4d else fourd_bench()
     limited = None if args.no_limited else limited_bench(n)
     regrid = None if args.no_regrid else regrid_bench()
+    amr_run = None if args.no_amr_run else amr_run_bench(args.amr_run_t)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -497,6 +571,7 @@ def main():
         "2d2v": fourd,
         "limited": limited,
         "regrid": regrid,
+        "amr_run": amr_run,
     }
     print(json.dumps(out), flush=True)
 
