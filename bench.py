@@ -7,8 +7,8 @@ moment, plus four field solves) over the whole phase-space mesh, with the
 state resident in HBM.  Prints one JSON line.
 
   value     cell-updates/s = cells * K / (time of K steps)
-  roofline  the stage kernels: algorithmic bytes (13 state words per cell
-            per RK4 step, 2 + 4 + 3 + 4 over the four stage launches of
+  roofline  the stage kernels: algorithmic bytes (12 state words per cell
+            per RK4 step, 2 + 4 + 3 + 3 over the four stage launches of
             the lean stage schedule) / their average
             launch duration measured with HIP events in a second pass of
             K steps, against the 8 TB/s HBM peak
@@ -167,7 +167,7 @@ def limited_bench(n=4096, steps=20, warmup=3):
     tm = plan.timing_read()
     plan.timing_enable(False)
     stage_us = tm["stage"][0] / tm["stage"][1] * 1e3
-    bytes_launch = 13 * 8 * n * n / 4        # 13 state words per cell per step over 4 stage launches
+    bytes_launch = 12 * 8 * n * n / 4        # 12 state words per cell per step over 4 stage launches
     return {"workload": f"two-stream 1D+1V {n}x{n} FP64 with limited face averages, dt={dt}",
             "tile_shape": {"threads": shape[0], "cells_per_thread": shape[1], "rows": shape[2]},
             "ms_per_step": round(ms, 4), "cell_updates_per_s": n * n / (ms * 1e-3),
@@ -443,7 +443,7 @@ def fourd_bench(steps=50, warmup=3):
     plan.timing_enable(False)
     cells = plan.state_elems
     stage_us = tm["stage"][0] / tm["stage"][1] * 1e3
-    bytes_launch = 13 * 8 * cells / 4         # 13 state words per cell per step over 4 stage launches
+    bytes_launch = 12 * 8 * cells / 4         # 12 state words per cell per step over 4 stage launches
     return {"workload": "2D+2V Vlasov-Poisson 64^4 FP64, x,y in [0,4pi), v in [-6,6]^2, dt=%g" % dt,
             "cells": cells, "steps": steps, "ms_per_step": round(ms, 4), "cell_updates_per_s": cells / (ms * 1e-3),
             "tuned_tile": {"threads": shape[0], "cells_x": shape[1], "cells_y": shape[2]},
@@ -515,7 +515,7 @@ def main():
     value = cells * args.steps / (ms * 1e-3)
 
     esize = 8 if dtype == torch.float64 else 4
-    bytes_step = 13 * esize * cells           # algorithmic bytes of the four stage launches
+    bytes_step = 12 * esize * cells           # algorithmic bytes of the four stage launches
     roofline = None
     timing = None
     if not args.no_roofline_pass:

@@ -185,7 +185,7 @@ vp_status p4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
     double* g = reinterpret_cast<double*>(wsp(work, M.ws_E));
     const double* in[4] = {fd, s2, s3, s2};
     double* out[4] = {s2, s3, s2, fd};
-    // the lean stage schedule (2 + 4 + 3 + 4 state words per cell): stage 2
+    // the lean stage schedule (2 + 4 + 3 + 3 state words per cell): stage 2
     // adds dt/3 k2 to the accumulator, stage 4 dt/6 k4; the other slopes
     // are read back from the predictors
     const double cacc[4] = {0.0, dt / 3.0, 0.0, dt / 6.0};

@@ -61,13 +61,14 @@ struct Stage1DArgs {
 
 // Stage kernels.  kStage1/23/4: the accumulator schedule (the accumulator
 // is updated at every stage; 3 + 5 + 5 + 3 state words per cell and step).
-// kLean1..4: the same classical RK4 step with 2 + 4 + 3 + 4 words, using
+// kLean1..4: the same classical RK4 step with 2 + 4 + 3 + 3 words, using
 // that the predictors already hold the earlier slopes:
 //   stage 1: f(2) = f^n + dt/2 k1
-//   stage 2: f(3) = f^n + dt/2 k2,  acc = f^n + (f(2) - f^n)/3 + dt/3 k2
+//   stage 2: f(3) = f^n + dt/2 k2,  acc = (f^n + f(2))/3 + dt/3 k2
 //   stage 3: f(4) = f^n + dt k3
-//   stage 4: f^{n+1} = acc + (f(4) - f^n)/3 + dt/6 k4
-// since dt/6 k1 = (f(2) - f^n)/3 and dt/3 k3 = (f(4) - f^n)/3.
+//   stage 4: f^{n+1} = acc + f(4)/3 + dt/6 k4
+// since f(2)/3 = f^n/3 + dt/6 k1 and f(4)/3 = f^n/3 + dt/3 k3 (the three
+// thirds of f^n add up to f^n); stage 4 does not read f^n.
 enum StageKind : int { kRhs = 0, kStage1 = 1, kStage23 = 2, kStage4 = 3, kLean1 = 4, kLean2 = 5, kLean3 = 6, kLean4 = 7 };
 
 // Arguments of the adjoint stage kernel (FP64, single level).

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
     constexpr int NP = TL::NP, LPW = TL::LPW, NW = TL::NW;
     static_assert(NP % NW == 0, "every wave loads the same number of ring rows");
     // ring slots = register sets = prefetch distance in positions
-    constexpr bool NEED_FN = KIND == kStage23 || KIND == kLean2 || KIND == kLean3 || KIND == kLean4;
+    constexpr bool NEED_FN = KIND == kStage23 || KIND == kLean2 || KIND == kLean3;
     constexpr bool NEED_AC = KIND == kStage23 || KIND == kStage4 || KIND == kLean4;
     constexpr int S = 3;
     __shared__ double rows[S][NP][64];
@@ -263,11 +263,11 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
                 out = f0 + cnext * k;
             } else if (KIND == kLean2) {
                 out = fnr[sb] + cnext * k;
-                if (st) __builtin_nontemporal_store(fnr[sb] + ((f0 - fnr[sb]) * (1.0 / 3.0) + cacc * k), A.acc + o);
+                if (st) __builtin_nontemporal_store((fnr[sb] + f0) * (1.0 / 3.0) + cacc * k, A.acc + o);
             } else if (KIND == kLean3) {
                 out = fnr[sb] + cnext * k;
             } else {                                 // kLean4
-                out = acr[sb] + ((f0 - fnr[sb]) * (1.0 / 3.0) + cacc * k);
+                out = acr[sb] + (f0 * (1.0 / 3.0) + cacc * k);
             }
             if (st) __builtin_nontemporal_store(out, A.fout + o);
             if (act) msum += out;

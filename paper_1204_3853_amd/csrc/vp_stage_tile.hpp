@@ -366,7 +366,7 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
                 }
                 const int ro = ifirst + D * min(mb + q, len - 1);              // row being updated
                 const size_t off = (size_t)ro * nv + jld;
-                if (KIND == kStage23 || KIND == kLean2 || KIND == kLean3 || KIND == kLean4) VecIO<T, W>::ldn(fn + off, fnv[q]);
+                if (KIND == kStage23 || KIND == kLean2 || KIND == kLean3) VecIO<T, W>::ldn(fn + off, fnv[q]);
                 if (KIND == kStage23 || KIND == kStage4 || KIND == kLean4) VecIO<T, W>::ldn(acc + off, accv[q]);
             }
             // The prefetch is issued after the loads this batch consumes (loads
@@ -444,18 +444,18 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const T f2 = cell(sl, w);
-                        o1[q][w] = fnv[q][w] + ((f2 - fnv[q][w]) * T(1.0 / 3.0) + cacc * kk[w]);
+                        o1[q][w] = (fnv[q][w] + f2) * T(1.0 / 3.0) + cacc * kk[w];
                         o2[q][w] = fnv[q][w] + cnext * kk[w];
                     }
                 } else if (KIND == kLean3) {   // f(4) = f^n + dt k3
 #pragma unroll
                     for (int w = 0; w < W; ++w) o2[q][w] = fnv[q][w] + cnext * kk[w];
-                } else {                       // kLean4: f^{n+1} from acc, f(4) = the stage state, f^n
+                } else {                       // kLean4: f^{n+1} from acc and f(4) = the stage state
                     const int sl = slot_of(i);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         const T f4 = cell(sl, w);
-                        o2[q][w] = accv[q][w] + ((f4 - fnv[q][w]) * T(1.0 / 3.0) + cacc * kk[w]);
+                        o2[q][w] = accv[q][w] + (f4 * T(1.0 / 3.0) + cacc * kk[w]);
                     }
                 }
                 sm4[q] = 0.0;
