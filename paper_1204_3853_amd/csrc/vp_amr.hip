@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,39 @@ hipError_t upload(T** dst, const std::vector<T>& v)
 char* wsp(void* work, size_t off) { return static_cast<char*>(work) + off; }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// host tables packed into one device allocation and one copy: add() records
+// each table, commit() allocates, copies and sets the device pointers
+struct TableArena {
+    struct Item {
+        void** dst;
+        const void* src;
+        size_t bytes, off;
+    };
+    std::vector<Item> items;
+    size_t total = 0;
+    template <typename T>
+    void add(T** dst, const std::vector<T>& v)
+    {
+        *dst = nullptr;
+        if (v.empty()) return;
+        items.push_back(Item{reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T), total});
+        total += align256(v.size() * sizeof(T));
+    }
+    hipError_t commit(void** base)
+    {
+        *base = nullptr;
+        if (total == 0) return hipSuccess;
+        std::vector<char> host(total, 0);
+        for (const Item& it : items) std::memcpy(host.data() + it.off, it.src, it.bytes);
+        hipError_t e = hipMalloc(base, total);
+        if (e != hipSuccess) return e;
+        e = hipMemcpy(*base, host.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+        for (const Item& it : items) *it.dst = static_cast<char*>(*base) + it.off;
+        return hipSuccess;
+    }
+};
 
 // tile table for the shape (nt, w, tx)
 void build_tiles(AmrPlan& A)
@@ -420,25 +454,27 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->nt = 64;
     M->tx = 8;
     build_tiles(*M);
-    VP_HIP(upload(&M->d_patches, M->patches));
     VP_HIP(upload(&M->d_tiles, M->tiles));
-    VP_HIP(upload(&M->d_faces, M->faces));
-    VP_HIP(upload(&M->d_B, B));
-    VP_HIP(upload(&M->d_task_off, task_off));
-    VP_HIP(upload(&M->d_task_len, task_len));
-    VP_HIP(upload(&M->d_rowptr, rowptr));
-    VP_HIP(upload(&M->d_idx, idx));
-    VP_HIP(upload(&M->d_w, w));
-    VP_HIP(upload(&M->d_corr_ptr, corr_ptr));
-    VP_HIP(upload(&M->d_corr_face, corr_face));
-    VP_HIP(upload(&M->d_corr_cell, corr_cell));
-    VP_HIP(upload(&M->d_cov_cell, cov_cell));
-    VP_HIP(upload(&M->d_cov_fine, cov_fine));
-    VP_HIP(upload(&M->d_cov_nv, cov_nv));
-    VP_HIP(upload(&M->d_mask, mask));
-    VP_HIP(upload(&M->d_rowptr_m, rowptr_m));
-    VP_HIP(upload(&M->d_idx_m, idx_m));
-    VP_HIP(upload(&M->d_w_m, w_m));
+    TableArena T;
+    T.add(&M->d_patches, M->patches);
+    T.add(&M->d_faces, M->faces);
+    T.add(&M->d_B, B);
+    T.add(&M->d_task_off, task_off);
+    T.add(&M->d_task_len, task_len);
+    T.add(&M->d_rowptr, rowptr);
+    T.add(&M->d_idx, idx);
+    T.add(&M->d_w, w);
+    T.add(&M->d_corr_ptr, corr_ptr);
+    T.add(&M->d_corr_face, corr_face);
+    T.add(&M->d_corr_cell, corr_cell);
+    T.add(&M->d_cov_cell, cov_cell);
+    T.add(&M->d_cov_fine, cov_fine);
+    T.add(&M->d_cov_nv, cov_nv);
+    T.add(&M->d_mask, mask);
+    T.add(&M->d_rowptr_m, rowptr_m);
+    T.add(&M->d_idx_m, idx_m);
+    T.add(&M->d_w_m, w_m);
+    VP_HIP(T.commit(&M->d_tables));
 
     // ---- workspace: acc, two predictors, accumulated face fluxes, reduction slots, n, E
     const size_t sb = align256(M->total * sizeof(double));
@@ -461,11 +497,8 @@ void amr_destroy(vp_plan* p)
 {
     AmrPlan* M = p->amr;
     if (!M) return;
-    void* ptrs[] = {M->d_patches, M->d_tiles, M->d_faces, M->d_B, M->d_task_off, M->d_task_len, M->d_rowptr,
-                    M->d_idx, M->d_w, M->d_corr_ptr, M->d_corr_face, M->d_corr_cell, M->d_cov_cell,
-                    M->d_cov_fine, M->d_cov_nv, M->d_mask, M->d_rowptr_m, M->d_idx_m, M->d_w_m};
-    for (void* q : ptrs)
-        if (q) (void)hipFree(q);
+    if (M->d_tables) (void)hipFree(M->d_tables);
+    if (M->d_tiles) (void)hipFree(M->d_tiles);
     delete M;
     p->amr = nullptr;
 }

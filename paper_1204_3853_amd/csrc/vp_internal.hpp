@@ -261,7 +261,9 @@ struct AmrPlan {
     std::vector<AmrTile> tiles;
     std::vector<int> patch_tile_begin;               // per patch, plus the face chunks at the end
     int face_tile_begin = 0;
-    // device tables
+    // device tables: one allocation (d_tables) holds every table but the
+    // tile table, which a tile shape change rebuilds
+    void* d_tables = nullptr;
     AmrPatch* d_patches = nullptr;
     AmrTile* d_tiles = nullptr;
     AmrFace* d_faces = nullptr;

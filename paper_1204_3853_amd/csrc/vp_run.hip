@@ -19,7 +19,9 @@
 struct vp_amr_run {
     vp_amr_params prm{};
     vp_plan* plan = nullptr;
-    void* f = nullptr;
+    void* f = nullptr;                 // current state, room for f_cap elements
+    void* f_spare = nullptr;           // the other state buffer (target of the next transfer)
+    size_t f_cap = 0, spare_cap = 0;
     double* a = nullptr;
     double* n = nullptr;
     double* phi = nullptr;
@@ -49,6 +51,7 @@ void free_dev(T*& p)
 void run_free(vp_amr_run* r)
 {
     free_dev(r->f);
+    free_dev(r->f_spare);
     free_dev(r->a);
     free_dev(r->n);
     free_dev(r->phi);
@@ -128,26 +131,33 @@ vp_status regrid(vp_amr_run* r, hipStream_t s)
     vp_plan* np = nullptr;
     st = vp_plan_create(&pb, bx.data(), nb, &np);
     if (st != VP_OK) return st;
-    void* fnew = nullptr;
-    hipError_t e = hipMalloc(&fnew, std::max<size_t>(vp_state_elems(np), 1) * sizeof(double));
-    if (e != hipSuccess) {
-        vp_plan_destroy(np);
-        return hip_fail(e, "vp_amr_run_advance: state of the new hierarchy");
+    // the new state goes into the spare buffer (grown when too small); the
+    // old one becomes the spare
+    const size_t ne = std::max<size_t>(vp_state_elems(np), 1);
+    hipError_t e = hipSuccess;
+    if (ne > r->spare_cap) {
+        free_dev(r->f_spare);
+        r->spare_cap = 0;
+        e = hipMalloc(&r->f_spare, ne * sizeof(double));
+        if (e != hipSuccess) {
+            vp_plan_destroy(np);
+            return hip_fail(e, "vp_amr_run_advance: state of the new hierarchy");
+        }
+        r->spare_cap = ne;
     }
     st = ensure_work(r, vp_workspace_bytes(np));
-    if (st == VP_OK) st = vp_regrid_transfer(r->plan, r->f, np, fnew, s);
+    if (st == VP_OK) st = vp_regrid_transfer(r->plan, r->f, np, r->f_spare, s);
     if (st == VP_OK) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "vp_amr_run_advance: transfer");
     }
     if (st != VP_OK) {
-        (void)hipFree(fnew);
         vp_plan_destroy(np);
         return st;
     }
-    free_dev(r->f);
     vp_plan_destroy(r->plan);
-    r->f = fnew;
+    std::swap(r->f, r->f_spare);
+    std::swap(r->f_cap, r->spare_cap);
     r->plan = np;
     r->boxes = bx;
     st = run_field(r, s);
@@ -190,6 +200,7 @@ vp_status vp_amr_run_create(const vp_problem* problem, const vp_box* boxes, int3
     };
     const size_t nf = (size_t)M.nfx;
     st = dev(&r->f, vp_state_elems(r->plan) * sizeof(double));
+    r->f_cap = std::max<size_t>(vp_state_elems(r->plan), 1);
     if (st == VP_OK) st = dev(&r->a, vp_field_elems(r->plan) * sizeof(double));
     if (st == VP_OK) st = dev(&r->n, nf * sizeof(double));
     if (st == VP_OK) st = dev(&r->phi, nf * sizeof(double));
