@@ -366,6 +366,38 @@ class Oracle1D:
         return out
 
 
+def species_field(fs, species, charges, background, dx, poisson=None):
+    """Accelerations of several species on one configuration mesh: the charge
+    density rho = background + sum_s charge_s n_s (n_s the velocity moment of
+    species s), the periodic Poisson solve and field stencil of section 2,
+    a_s = (q/m)_s E.  species: dicts with dv and qm.  Returns ([a_s], E)."""
+    nx = fs[0].shape[0]
+    rho = np.full(nx, float(background))
+    for f, sp, q in zip(fs, species, charges):
+        rho = rho + q * moment(f, sp["dv"])
+    P = poisson if poisson is not None else Poisson(nx)
+    E = field(P.solve(rho, dx), dx)
+    return [sp["qm"] * E for sp in species], E
+
+
+def species_rk4_step(fs, species, charges, background, dx, dt):
+    """One classic RK4 step (eq. rk4) of several species that share the field:
+    at every stage the field of all predictor states, then each species'
+    semi-discrete right-hand side with its own velocity mesh, equilibrium
+    ghosts and acceleration.  species: dicts with dv, v_lo, vghost, qm."""
+    alpha = [0.0, 0.5, 0.5, 1.0]
+    b = [1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]
+    fn = [_f64(f) for f in fs]
+    P = Poisson(fn[0].shape[0])
+    ks = []
+    for s in range(4):
+        stage = [f if s == 0 else f + alpha[s] * dt * k for f, k in zip(fn, ks[-1] if ks else fn)]
+        a, _ = species_field(stage, species, charges, background, dx, P)
+        ks.append([rhs(f, ai, dx, sp["dv"], sp["v_lo"], sp["vghost"]) for f, ai, sp in zip(stage, a, species)])
+    return [f + dt * (b[0] * ks[0][q] + b[1] * ks[1][q] + b[2] * ks[2][q] + b[3] * ks[3][q])
+            for q, f in enumerate(fn)]
+
+
 def interp_weights(R):
     """b_j(s) table (R x 5) of the conservative fifth-order sub-cell interpolation."""
     out = np.empty((R, 5))

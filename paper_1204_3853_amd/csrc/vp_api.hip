@@ -95,42 +95,69 @@ vp_status check_plan(const vp_plan* p)
     return VP_OK;
 }
 
-// one RK4 step; stage states go to st[0..2] (or the workspace ping-pong
-// buffers) and stage accelerations to sa[0..3] (or in place in `a`)
-vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, void* st_f,
-                 double* st_a, hipStream_t stream)
+}  // namespace
+
+Rk4Setup1D rk4_setup_1d(const vp_plan* p, void* f, void* work, double dt, void* st_f)
 {
+    Rk4Setup1D R{};
     const size_t sb = p->state_elems * p->esize;
     void* acc = wsp(work, p->ws_acc);
     void* s2 = st_f ? st_f : wsp(work, p->ws_fsa);
     void* s3 = st_f ? static_cast<char*>(st_f) + sb : wsp(work, p->ws_fsb);
     void* s4 = st_f ? static_cast<char*>(st_f) + 2 * sb : wsp(work, p->ws_fsa);
-    double* part = reinterpret_cast<double*>(wsp(work, p->ws_part));
-    double* ncfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
-    const StageShape sh = pick_shape(p, {f, acc, s2, s3, s4});
-    Stage1DArgs A = base_args(p, sh);
-    A.part = part;
+    R.part = reinterpret_cast<double*>(wsp(work, p->ws_part));
+    R.sh = pick_shape(p, {f, acc, s2, s3, s4});
+    R.A = base_args(p, R.sh);
+    R.A.part = R.part;
+    R.A.fn = f;
+    R.A.acc = acc;
     // the lean schedule: stage 2 adds dt/3 k2 to the accumulator, stage 4
     // dt/6 k4 (the other slopes come from the predictors)
     const double cacc[4] = {0.0, dt / 3.0, 0.0, dt / 6.0};
-    const double cnext[3] = {0.5 * dt, 0.5 * dt, dt};
+    const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
     const int kinds[4] = {kLean1, kLean2, kLean3, kLean4};
+    const void* in[4] = {f, s2, s3, s4};
+    void* out[4] = {s2, s3, s4, f};
+    for (int s = 0; s < 4; ++s) {
+        R.in[s] = in[s];
+        R.out[s] = out[s];
+        R.c_acc[s] = cacc[s];
+        R.c_next[s] = cnext[s];
+        R.kind[s] = kinds[s];
+    }
+    return R;
+}
+
+Stage1DArgs rk4_stage_args_1d(const Rk4Setup1D& R, int s, const double* a)
+{
+    Stage1DArgs A = R.A;
+    A.fs = R.in[s];
+    A.fout = R.out[s];
+    A.a = a;
+    A.c_acc = R.c_acc[s];
+    A.c_next = R.c_next[s];
+    return A;
+}
+
+namespace {
+
+// one RK4 step; stage states go to st[0..2] (or the workspace ping-pong
+// buffers) and stage accelerations to sa[0..3] (or in place in `a`)
+vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, void* st_f,
+                 double* st_a, hipStream_t stream)
+{
+    const Rk4Setup1D R = rk4_setup_1d(p, f, work, dt, st_f);
+    const StageShape sh = R.sh;
+    double* part = R.part;
+    double* ncfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
     double* sa[5] = {a, a, a, a, a};
     if (st_a) {
         VP_HIP(hipMemcpyAsync(st_a, a, sizeof(double) * p->nx, hipMemcpyDeviceToDevice, stream));
         for (int s = 0; s < 4; ++s) sa[s] = st_a + (size_t)s * p->nx;
     }
-    const void* in[4] = {f, s2, s3, s4};
-    void* out[4] = {s2, s3, s4, f};
     for (int s = 0; s < 4; ++s) {
-        A.fs = in[s];
-        A.fn = f;
-        A.acc = acc;
-        A.fout = out[s];
-        A.a = sa[s];
-        A.c_acc = cacc[s];
-        A.c_next = s < 3 ? cnext[s] : 0.0;
-        const int kind = kinds[s];
+        const Stage1DArgs A = rk4_stage_args_1d(R, s, sa[s]);
+        const int kind = R.kind[s];
         VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage1d(p->dtype, sh, kind, A, stream); }));
         double* a_next = (s < 3) ? sa[s + 1] : a;
         VP_HIP(timed(p, kTField, stream, [&] {

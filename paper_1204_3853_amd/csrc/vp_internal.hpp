@@ -181,6 +181,20 @@ hipError_t launch_adjoint_stage1d(int w, bool first, const Adjoint1DArgs& a, hip
 hipError_t launch_adjoint_final(const double* mu, const double* g, const double* z, int nx, int nv, double* out,
                                 hipStream_t stream);
 hipError_t launch_scale(const double* x, double s, double* y, int n, hipStream_t stream);
+// several species on one configuration mesh: per species the per-strip
+// partial sums of its velocity moment (or its moment, nstrip = 1) and the
+// weight w_s (charge times the velocity cell width, or the charge)
+constexpr int kMaxSpecies = 4;
+struct SpeciesMoments {
+    const double* part[kMaxSpecies];
+    int nstrip[kMaxSpecies];
+    double w[kMaxSpecies];
+    int ns;
+    double background;
+};
+// n_eff = 1 - rho with rho = background + sum_s w_s sum_strips part_s, the
+// form the single-species field solves take (rho = 1 - n)
+hipError_t launch_species_neff(const SpeciesMoments& m, int nx, double* n_eff, hipStream_t stream);
 // moment from strip partials, Poisson, field and a = (q/m) E over many blocks
 // (nx >= kFieldSplitMin); work holds nx + 2 ceil(nx / kFieldChunk) doubles
 hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv, double dx, double qm,
@@ -345,6 +359,23 @@ struct vp_plan {
 };
 
 namespace vp {
+// the single-level 1D+1V RK4 step (lean stage schedule) of plan p on state
+// f: tile shape, common stage arguments, the stage input and output states
+// (the workspace ping-pong buffers, or the stage record st_f), the stage
+// coefficients and kinds (vp_api.hip)
+struct Rk4Setup1D {
+    StageShape sh;
+    Stage1DArgs A;
+    const void* in[4];
+    void* out[4];
+    double* part;
+    double c_acc[4], c_next[4];
+    int kind[4];
+};
+Rk4Setup1D rk4_setup_1d(const vp_plan* p, void* f, void* work, double dt, void* st_f);
+// the arguments of stage s (0..3) with the acceleration a
+Stage1DArgs rk4_stage_args_1d(const Rk4Setup1D& R, int s, const double* a);
+
 // two-level host sequences (vp_amr.hip)
 vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);
 void amr_destroy(vp_plan* p);

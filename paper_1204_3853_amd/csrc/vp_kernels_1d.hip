@@ -447,6 +447,29 @@ __global__ void k_scale(const double* __restrict__ x, double s, double* __restri
     if (i < n) y[i] = s * x[i];
 }
 
+// one row per thread: every species' strip sums in a fixed order, then
+// rho = background + sum_s w_s (sum of its strips), n_eff = 1 - rho
+__global__ __launch_bounds__(256) void k_species_neff(SpeciesMoments m, int nx, double* __restrict__ n_eff)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nx) return;
+    double rho = m.background;
+    for (int s = 0; s < m.ns; ++s) {
+        const double* part = m.part[s];
+        const int nstrip = m.nstrip[s];
+        double acc = 0.0;
+        for (int q0 = 0; q0 < nstrip; q0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = (q0 + u < nstrip) ? part[(size_t)(q0 + u) * nx + i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v[u];
+        }
+        rho += m.w[s] * acc;
+    }
+    n_eff[i] = 1.0 - rho;
+}
+
 template <typename T, int W, int NT>
 hipError_t launch_stage_t(int kind, const Stage1DArgs& a, hipStream_t stream)
 {
@@ -590,6 +613,13 @@ hipError_t launch_row_broadcast(const double* z, int nx, int nv, double* out, hi
 hipError_t launch_scale(const double* x, double s, double* y, int n, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_scale, dim3((n + 255) / 256), dim3(256), 0, stream, x, s, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_species_neff(const SpeciesMoments& m, int nx, double* n_eff, hipStream_t stream)
+{
+    if (m.ns < 1 || m.ns > kMaxSpecies) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_species_neff, dim3((nx + 255) / 256), dim3(256), 0, stream, m, nx, n_eff);
     return hipGetLastError();
 }
 

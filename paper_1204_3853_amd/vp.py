@@ -110,6 +110,13 @@ SIGNATURES = {
     "vp_amr_run_boxes": (ctypes.c_int, [_P, ctypes.POINTER(vp_box), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "vp_amr_run_read_state": (ctypes.c_int, [_P, _P, _S, _P]),
     "vp_amr_run_destroy": (ctypes.c_int, [_P]),
+    "vp_species_group_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                               _D, ctypes.POINTER(_P)]),
+    "vp_species_group_destroy": (ctypes.c_int, [_P]),
+    "vp_species_workspace_bytes": (_S, [_P]),
+    "vp_species_field": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _P]),
+    "vp_species_rk4_step": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, ctypes.POINTER(_P), _P,
+                                           _P]),
 }
 
 TIMING_CLASSES = ["stage", "field", "moment", "sync", "adjoint", "other"]
@@ -488,3 +495,55 @@ class AmrRun:
         out = torch.empty(n, dtype=torch.float64, device=self.device)
         _check(lib().vp_amr_run_read_state(self.h, _ptr(out), n, _stream()))
         return out
+
+
+# -------------------------------------------------------------------- several species
+
+
+class SpeciesGroup:
+    """Species on one configuration mesh (vp_species_group): plans of
+    single-level 1D+1V problems (each with its own velocity mesh and qm),
+    their charges, and a uniform neutralising background;
+    rho = background + sum_s charge_s n_s."""
+
+    def __init__(self, plans, charges, background=0.0):
+        n = len(plans)
+        hs = (_P * n)(*[p.h.value for p in plans])
+        ch = (ctypes.c_double * n)(*[float(c) for c in charges])
+        h = ctypes.c_void_p()
+        _check(lib().vp_species_group_create(hs, ch, n, ctypes.c_double(background), ctypes.byref(h)))
+        self.h = h
+        self.plans = list(plans)
+        self.charges = [float(c) for c in charges]
+        self.background = float(background)
+        self.gwork = torch.empty(max(lib().vp_species_workspace_bytes(h), 1), dtype=torch.uint8,
+                                 device=plans[0].device)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.vp_species_group_destroy(self.h)
+            self.h = None
+
+    def _lists(self, fs, as_):
+        if len(fs) != len(self.plans) or len(as_) != len(self.plans):
+            raise ValueError("one state and one acceleration per species expected")
+        for p, f, a in zip(self.plans, fs, as_):
+            p._state(f, "f")
+            p._cfg(a, "a", p.field_elems)
+        n = len(self.plans)
+        return (_P * n)(*[f.data_ptr() for f in fs]), (_P * n)(*[a.data_ptr() for a in as_])
+
+    def field(self, fs, as_=None):
+        """[a_s = (q/m)_s E] of the states fs."""
+        if as_ is None:
+            as_ = [torch.empty(p.field_elems, dtype=torch.float64, device=p.device) for p in self.plans]
+        fp, ap = self._lists(fs, as_)
+        _check(lib().vp_species_field(self.h, fp, ap, _ptr(self.gwork), _stream()))
+        return as_
+
+    def rk4_step(self, fs, as_, dt):
+        """One RK4 step of every species in place; as_ in/out."""
+        fp, ap = self._lists(fs, as_)
+        wp = (_P * len(self.plans))(*[p.work.data_ptr() for p in self.plans])
+        _check(lib().vp_species_rk4_step(self.h, fp, ap, ctypes.c_double(dt), wp, _ptr(self.gwork), _stream()))
+        return fs, as_
