@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-regrid", action="store_true")
     ap.add_argument("--regrid-only", action="store_true", help="run only the regridding section (for profiling)")
     ap.add_argument("--no-amr-run", action="store_true")
+    ap.add_argument("--no-species", action="store_true")
+    ap.add_argument("--species-only", action="store_true", help="run only the two-species section")
     ap.add_argument("--amr-run-only", action="store_true", help="run only the adaptive bump-on-tail section")
     ap.add_argument("--amr-run-t", type=float, default=22.5, help="end time of the adaptive bump-on-tail runs")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape of the main workload")
@@ -412,6 +414,41 @@ def amr_run_bench(t_end=22.5):
     return out
 
 
+def species_bench(steps=20, warmup=3):
+    """Two species on one configuration mesh: electrons (two-stream, 4096 x
+    4096, v in [-8, 8]) and ions of mass ratio 100 (4096 x 1024, v in
+    [-0.8, 0.8]), no background; RK4 steps of both with one field solve per
+    stage from both moments."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+    pe = I.two_stream(4096, 4096)
+    vth = 0.1
+    veq = I.cell_average_1d(lambda u: I.maxwellian(u / vth) / vth, -8 * vth, 8 * vth, 1024, first=-2, count=1028)
+    pi_ = I.Problem1D(nx=4096, nv=1024, x_lo=pe.x_lo, x_len=pe.x_len, v_lo=-8 * vth, v_hi=8 * vth, qm=0.01,
+                      eps=0.0, k=0.2, veq=veq)
+    plans = [vp.Plan(pe), vp.Plan(pi_)]
+    fs = [torch.tensor(p.initial_state().ravel(), device="cuda") for p in (pe, pi_)]
+    g = vp.SpeciesGroup(plans, [-1.0, 1.0], 0.0)
+    a = g.field(fs)
+    dt = 4.788e-4
+    for _ in range(warmup):
+        g.rk4_step(fs, a, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.rk4_step(fs, a, dt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    cells = 4096 * 4096 + 4096 * 1024
+    return {"workload": "electrons 4096 x 4096 (two-stream, v in [-8, 8]) + ions of mass ratio 100 "
+                        "4096 x 1024 (v in [-0.8, 0.8]), FP64, dt=0.0004788",
+            "cells": cells, "steps": steps, "ms_per_step": round(ms, 4),
+            "cell_updates_per_s": cells / (ms * 1e-3),
+            "algorithmic_GBs": round(12 * 8 * cells / (ms * 1e-3) / 1e9, 1)}
+
+
 def fourd_bench(steps=50, warmup=3):
     """2D+2V 64^4 FP64 (x, y in [0, 4pi), v in [-6, 6]^2, Landau-type
     initial state): RK4 steps after the load-batch autotune."""
@@ -480,6 +517,9 @@ def main():
     if args.regrid_only:
         print(json.dumps({"regrid": regrid_bench()}), flush=True)
         return
+    if args.species_only:
+        print(json.dumps({"species": species_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
     if args.amr_run_only:
         print(json.dumps({"amr_run": amr_run_bench(args.amr_run_t)}), flush=True)
         return
@@ -542,6 +582,7 @@ def main():
     limited = None if args.no_limited else limited_bench(n)
     regrid = None if args.no_regrid else regrid_bench()
     amr_run = None if args.no_amr_run else amr_run_bench(args.amr_run_t)
+    species = None if args.no_species else species_bench(steps=args.steps, warmup=args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -572,6 +613,7 @@ def main():
         "limited": limited,
         "regrid": regrid,
         "amr_run": amr_run,
+        "species": species,
     }
     print(json.dumps(out), flush=True)
 
