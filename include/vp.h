@@ -470,9 +470,10 @@ vp_status vp_amr_run_destroy(vp_amr_run* run);
  * own velocity range and mesh and, in the paper's design, its own
  * phase-space hierarchy; without collisions the species interact only
  * through the field (section 1, the motivation for one hierarchy per
- * species).  A group ties together single-level 1D+1V plans of one dtype
- * with the same configuration mesh (cells, x_lo, x_len); each plan keeps
- * its velocity mesh, equilibrium ghost values and charge-to-mass ratio qm.
+ * species).  A group ties together 1D+1V plans of one dtype, single-level
+ * or two-level (one hierarchy per species), whose finest configuration
+ * meshes agree (cells, x_lo, x_len); each plan keeps its velocity mesh,
+ * boxes, equilibrium ghost values and charge-to-mass ratio qm.
  * The charge density is
  *   rho = background + sum_s charge[s] n_s,   n_s the velocity moment of f_s,
  * (background: a uniform neutralising density; 1 with immobile ions of unit
@@ -481,8 +482,7 @@ vp_status vp_amr_run_destroy(vp_amr_run* run);
  * accelerated by a_s = qm_s E.  The group keeps pointers to the plans,
  * which must outlive it.  VP_EINVAL for NULL pointers, 0 or more than
  * VP_MAX_SPECIES species, non-finite charges or background, or plans that
- * differ in dtype or configuration mesh; VP_ENOTSUP for two-level or 2D+2V
- * plans.
+ * differ in dtype or finest configuration mesh; VP_ENOTSUP for 2D+2V plans.
  */
 #define VP_MAX_SPECIES 4
 typedef struct vp_species_group vp_species_group;
@@ -492,13 +492,17 @@ vp_status vp_species_group_destroy(vp_species_group* group);
 /* bytes of the group workspace `gwork` of the calls below */
 size_t vp_species_workspace_bytes(const vp_species_group* group);
 /* a[s] = qm_s E of the states f[s] (f[s]: plan s's layout and dtype;
- * a[s]: nx doubles); enqueued on `stream`. */
-vp_status vp_species_field(const vp_species_group* group, const void* const* f, double* const* a, void* gwork,
-                           hipStream_t stream);
+ * a[s]: vp_field_elems of plan s); enqueued on `stream`.  work may be NULL
+ * when no species has two levels, else work[s] is plan s's workspace. */
+vp_status vp_species_field(const vp_species_group* group, const void* const* f, double* const* a, void* const* work,
+                           void* gwork, hipStream_t stream);
 /* One RK4 step of every species in place (the lean stage schedule of
  * vp_rk4_step per species, one field solve from all species after every
  * stage).  a[s] in: the field of f (vp_species_field); out: the field of
- * the new states.  work[s]: plan s's workspace (vp_workspace_bytes). */
+ * the new states.  work[s]: plan s's workspace (vp_workspace_bytes).  A
+ * two-level species takes the stages of vp_rk4_step and its end-of-step
+ * synchronisation, its moment from its plan's reduction; its a[s] is the
+ * injected [coarse][fine] array (vp_field_elems). */
 vp_status vp_species_rk4_step(const vp_species_group* group, void* const* f, double* const* a, double dt,
                               void* const* work, void* gwork, hipStream_t stream);
 

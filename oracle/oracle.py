@@ -93,6 +93,10 @@ def _declare_extra(L):
         "vpo_amr_fill_ghosts": (None, [_V, _D, _I, _D]),
         "vpo_amr_rk4_step": (None, [_V, _D, _D, _F]),
         "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
+        "vpo_amr_species_constraints": (None, [_I, ctypes.POINTER(_V), ctypes.POINTER(_D), _D, _F,
+                                               ctypes.POINTER(_D)]),
+        "vpo_amr_species_rk4_step": (None, [_I, ctypes.POINTER(_V), ctypes.POINTER(_D), ctypes.POINTER(_D), _D,
+                                            _F, _F]),
         "vpo_face_limited": (_F, [_F, _F, _F, _F, _I]),
         "vpo_rhs_limited": (None, [_I, _I, _F, _F, _F, _D, _D, _D, _D]),
         "vpo_rk4_step_limited": (None, [_V, _D, _D, _F]),
@@ -465,6 +469,32 @@ class OracleAMR:
         out = np.empty_like(f)
         lib().vpo_amr_rk4_step(self.h, _p(f), _p(out), dt)
         return out
+
+
+def _ptr_list(arrays):
+    return (_D * len(arrays))(*[_p(x) for x in arrays])
+
+
+def amr_species_field(hier, fs, charges, background):
+    """[a_s] ([coarse][fine] per species) of several species, each on its own
+    two-level hierarchy (OracleAMR objects with the same finest configuration
+    mesh): rho = background + sum_s charge_s n_s (Mask Reduction)."""
+    fs = [_f64(f) for f in fs]
+    a = [np.empty(h.ncx + h.nfx) for h in hier]
+    hs = (_V * len(hier))(*[h.h for h in hier])
+    ch = np.ascontiguousarray(charges, dtype=np.float64)
+    lib().vpo_amr_species_constraints(len(hier), hs, _ptr_list(fs), _p(ch), float(background), _ptr_list(a))
+    return a
+
+
+def amr_species_rk4_step(hier, fs, charges, background, dt):
+    """One RK4 step of several species' two-level hierarchies sharing the field."""
+    fs = [_f64(f) for f in fs]
+    out = [np.empty_like(f) for f in fs]
+    hs = (_V * len(hier))(*[h.h for h in hier])
+    ch = np.ascontiguousarray(charges, dtype=np.float64)
+    lib().vpo_amr_species_rk4_step(len(hier), hs, _ptr_list(fs), _ptr_list(out), _p(ch), float(background), dt)
+    return out
 
 
 class Oracle4D:

@@ -83,5 +83,11 @@ void vpo4_rhs(void* h, double* f, double* a, double* k);
 void vpo4_rk4_step(void* h, double* f_in, double* f_out, double dt);
 void vpo4_rk4_step_fixed_a(void* h, double* f_in, double* f_out, double* a, double dt);
 void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt);
+/* several species, one two-level hierarchy each, the same finest
+ * configuration mesh; rho = background + sum_s charge_s n_s */
+void vpo_amr_species_constraints(int ns, void* const* hs, double* const* fs, const double* charge,
+                                 double background, double* const* a);
+void vpo_amr_species_rk4_step(int ns, void* const* hs, double* const* f_in, double* const* f_out,
+                              const double* charge, double background, double dt);
 
 #endif

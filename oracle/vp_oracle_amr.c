@@ -295,42 +295,14 @@ void vpo_amr_rhs(void* h, double* f, double* a, double* k)
 }
 
 /* one synchronous RK4 step of the two-level hierarchy (Alg. smsvphu) */
-void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt)
+/* ComputeUpdate of the two-level step from the stage-weighted accumulated
+ * fluxes Ax, Av (k: scratch of the state size): the fine levels first, then
+ * the coarse level with its coarse-fine faces carrying the mean of the fine
+ * fluxes, then covered coarse cells take the average of their fine cells */
+static void amr_update(const vpo_amr* c, const double* fn, double** Ax, double** Av, double* k, double* f_out,
+                       double dt)
 {
-    static const double alpha[4] = {0.0, 0.5, 0.5, 1.0};
-    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    vpo_amr* c = (vpo_amr*)h;
     const int np = c->np, ncx = c->ncx, ncv = c->ncv, R = c->R;
-    const long N = c->total;
-    double* fn = (double*)malloc(sizeof(double) * N);
-    double* fs = (double*)malloc(sizeof(double) * N);
-    double* k = (double*)calloc(N, sizeof(double));
-    double* a = (double*)malloc(sizeof(double) * (ncx + c->nfx));
-    memcpy(fn, f_in, sizeof(double) * N);
-    double **Gx = (double**)malloc(sizeof(double*) * (np + 1)), **Gv = (double**)malloc(sizeof(double*) * (np + 1));
-    double **Ax = (double**)malloc(sizeof(double*) * (np + 1)), **Av = (double**)malloc(sizeof(double*) * (np + 1));
-    for (int p = 0; p <= np; ++p) {
-        int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
-        Gx[p] = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * nv);
-        Gv[p] = (double*)malloc(sizeof(double) * (size_t)nx * (nv + 1));
-        Ax[p] = (double*)calloc((size_t)(nx + 1) * nv, sizeof(double));
-        Av[p] = (double*)calloc((size_t)nx * (nv + 1), sizeof(double));
-    }
-    for (int s = 0; s < 4; ++s) {
-        /* ComputePredictorState on every level */
-        for (long q = 0; q < N; ++q) fs[q] = fn[q] + alpha[s] * dt * k[q];
-        /* ComputeInstantaneousConstraints */
-        vpo_amr_constraints(h, fs, a, NULL);
-        /* ComputeRHS: fluxes, divergence, flux accumulation */
-        hierarchy_fluxes(c, fs, a, Gx, Gv);
-        for (int p = 0; p <= np; ++p) {
-            int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
-            double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
-            divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
-            for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[p][q] += bw[s] * Gx[p][q];
-            for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[p][q] += bw[s] * Gv[p][q];
-        }
-    }
     /* ComputeUpdate: finest level first */
     for (int p = 1; p <= np; ++p) {
         int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
@@ -386,7 +358,143 @@ void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt)
                 f_out[(size_t)ci * ncv + cj] = sum / (R * R);
             }
     }
+}
+
+void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt)
+{
+    static const double alpha[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    vpo_amr* c = (vpo_amr*)h;
+    const int np = c->np, ncx = c->ncx, ncv = c->ncv;
+    const long N = c->total;
+    double* fn = (double*)malloc(sizeof(double) * N);
+    double* fs = (double*)malloc(sizeof(double) * N);
+    double* k = (double*)calloc(N, sizeof(double));
+    double* a = (double*)malloc(sizeof(double) * (ncx + c->nfx));
+    memcpy(fn, f_in, sizeof(double) * N);
+    double **Gx = (double**)malloc(sizeof(double*) * (np + 1)), **Gv = (double**)malloc(sizeof(double*) * (np + 1));
+    double **Ax = (double**)malloc(sizeof(double*) * (np + 1)), **Av = (double**)malloc(sizeof(double*) * (np + 1));
+    for (int p = 0; p <= np; ++p) {
+        int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
+        Gx[p] = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * nv);
+        Gv[p] = (double*)malloc(sizeof(double) * (size_t)nx * (nv + 1));
+        Ax[p] = (double*)calloc((size_t)(nx + 1) * nv, sizeof(double));
+        Av[p] = (double*)calloc((size_t)nx * (nv + 1), sizeof(double));
+    }
+    for (int s = 0; s < 4; ++s) {
+        /* ComputePredictorState on every level */
+        for (long q = 0; q < N; ++q) fs[q] = fn[q] + alpha[s] * dt * k[q];
+        /* ComputeInstantaneousConstraints */
+        vpo_amr_constraints(h, fs, a, NULL);
+        /* ComputeRHS: fluxes, divergence, flux accumulation */
+        hierarchy_fluxes(c, fs, a, Gx, Gv);
+        for (int p = 0; p <= np; ++p) {
+            int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
+            double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
+            divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
+            for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[p][q] += bw[s] * Gx[p][q];
+            for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[p][q] += bw[s] * Gv[p][q];
+        }
+    }
+    amr_update(c, fn, Ax, Av, k, f_out, dt);
     for (int p = 0; p <= np; ++p) { free(Gx[p]); free(Gv[p]); free(Ax[p]); free(Av[p]); }
     free(Gx); free(Gv); free(Ax); free(Av);
     free(fn); free(fs); free(k); free(a);
+}
+
+/* Several species, each on its own two-level hierarchy, with the same
+ * finest configuration mesh (section 1: one phase-space hierarchy per
+ * species, the species coupled only through the field).  The constraint:
+ * rho = background + sum_s charge_s n_s with n_s the Mask Reduction of
+ * species s, the periodic Poisson solve and field on the finest
+ * configuration mesh, a_s injected with the species' own q/m (coarse: the
+ * mean of the R fine values). */
+void vpo_amr_species_constraints(int ns, void* const* hs, double* const* fs, const double* charge,
+                                 double background, double* const* a)
+{
+    const vpo_amr* c0 = (const vpo_amr*)hs[0];
+    const int nfx = c0->nfx;
+    double* n = (double*)malloc(sizeof(double) * nfx);
+    double* rho = (double*)malloc(sizeof(double) * nfx);
+    double* phi = (double*)malloc(sizeof(double) * nfx);
+    double* E = (double*)malloc(sizeof(double) * nfx);
+    for (int I = 0; I < nfx; ++I) rho[I] = background;
+    for (int s = 0; s < ns; ++s) {
+        vpo_amr_reduce_mask(hs[s], fs[s], n);
+        for (int I = 0; I < nfx; ++I) rho[I] += charge[s] * n[I];
+    }
+    vpo_poisson_solve(c0->P, c0->dxf, rho, phi);
+    vpo_field(nfx, c0->dxf, phi, E);
+    for (int s = 0; s < ns; ++s) {
+        const vpo_amr* c = (const vpo_amr*)hs[s];
+        const int R = c->R;
+        for (int i = 0; i < c->ncx; ++i) {
+            double sum = 0.0;
+            for (int q = 0; q < R; ++q) sum += E[i * R + q];
+            a[s][i] = c->qm * sum / R;
+        }
+        for (int I = 0; I < nfx; ++I) a[s][c->ncx + I] = c->qm * E[I];
+    }
+    free(n); free(rho); free(phi); free(E);
+}
+
+/* One synchronous RK4 step of every species' hierarchy (the steps of
+ * vpo_amr_rk4_step per species), the field of all species' predictor
+ * states at every stage. */
+void vpo_amr_species_rk4_step(int ns, void* const* hs, double* const* f_in, double* const* f_out,
+                              const double* charge, double background, double dt)
+{
+    static const double alpha[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    double **fn = (double**)malloc(sizeof(double*) * ns), **fs = (double**)malloc(sizeof(double*) * ns);
+    double **k = (double**)malloc(sizeof(double*) * ns), **a = (double**)malloc(sizeof(double*) * ns);
+    double ***Gx = (double***)malloc(sizeof(double**) * ns), ***Gv = (double***)malloc(sizeof(double**) * ns);
+    double ***Ax = (double***)malloc(sizeof(double**) * ns), ***Av = (double***)malloc(sizeof(double**) * ns);
+    for (int s = 0; s < ns; ++s) {
+        vpo_amr* c = (vpo_amr*)hs[s];
+        const long N = c->total;
+        const int np = c->np;
+        fn[s] = (double*)malloc(sizeof(double) * N);
+        fs[s] = (double*)malloc(sizeof(double) * N);
+        k[s] = (double*)calloc(N, sizeof(double));
+        a[s] = (double*)malloc(sizeof(double) * (c->ncx + c->nfx));
+        memcpy(fn[s], f_in[s], sizeof(double) * N);
+        Gx[s] = (double**)malloc(sizeof(double*) * (np + 1));
+        Gv[s] = (double**)malloc(sizeof(double*) * (np + 1));
+        Ax[s] = (double**)malloc(sizeof(double*) * (np + 1));
+        Av[s] = (double**)malloc(sizeof(double*) * (np + 1));
+        for (int p = 0; p <= np; ++p) {
+            int nx = p == 0 ? c->ncx : NXP(c, p - 1), nv = p == 0 ? c->ncv : NVP(c, p - 1);
+            Gx[s][p] = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * nv);
+            Gv[s][p] = (double*)malloc(sizeof(double) * (size_t)nx * (nv + 1));
+            Ax[s][p] = (double*)calloc((size_t)(nx + 1) * nv, sizeof(double));
+            Av[s][p] = (double*)calloc((size_t)nx * (nv + 1), sizeof(double));
+        }
+    }
+    for (int st = 0; st < 4; ++st) {
+        for (int s = 0; s < ns; ++s) {
+            const long N = ((vpo_amr*)hs[s])->total;
+            for (long q = 0; q < N; ++q) fs[s][q] = fn[s][q] + alpha[st] * dt * k[s][q];
+        }
+        vpo_amr_species_constraints(ns, hs, fs, charge, background, a);
+        for (int s = 0; s < ns; ++s) {
+            vpo_amr* c = (vpo_amr*)hs[s];
+            hierarchy_fluxes(c, fs[s], a[s], Gx[s], Gv[s]);
+            for (int p = 0; p <= c->np; ++p) {
+                int nx = p == 0 ? c->ncx : NXP(c, p - 1), nv = p == 0 ? c->ncv : NVP(c, p - 1);
+                double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
+                divergence(nx, nv, Gx[s][p], Gv[s][p], dx, dv, k[s] + (p == 0 ? 0 : c->off[p - 1]));
+                for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[s][p][q] += bw[st] * Gx[s][p][q];
+                for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[s][p][q] += bw[st] * Gv[s][p][q];
+            }
+        }
+    }
+    for (int s = 0; s < ns; ++s) {
+        vpo_amr* c = (vpo_amr*)hs[s];
+        amr_update(c, fn[s], Ax[s], Av[s], k[s], f_out[s], dt);
+        for (int p = 0; p <= c->np; ++p) { free(Gx[s][p]); free(Gv[s][p]); free(Ax[s][p]); free(Av[s][p]); }
+        free(Gx[s]); free(Gv[s]); free(Ax[s]); free(Av[s]);
+        free(fn[s]); free(fs[s]); free(k[s]); free(a[s]);
+    }
+    free(Gx); free(Gv); free(Ax); free(Av); free(fn); free(fs); free(k); free(a);
 }

@@ -524,24 +524,42 @@ vp_status amr_inject(const vp_plan* p, const double* E, double* a, hipStream_t s
     return VP_OK;
 }
 
-vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
+void* amr_stage_output(const vp_plan* p, int s, void* f, void* work)
 {
-    const AmrPlan& M = *p->amr;
+    void* out[4] = {wsp(work, p->ws_fsa), wsp(work, p->ws_fsb), wsp(work, p->ws_fsa), f};
+    return out[s];
+}
+
+vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt, void* work, hipStream_t stream)
+{
     void* acc = wsp(work, p->ws_acc);
-    void* s2 = wsp(work, p->ws_fsa);
-    void* s3 = wsp(work, p->ws_fsb);
-    void* s4 = s2;
-    const void* in[4] = {f, s2, s3, s4};
-    void* out[4] = {s2, s3, s4, f};
+    const void* in[4] = {f, amr_stage_output(p, 0, f, work), amr_stage_output(p, 1, f, work),
+                         amr_stage_output(p, 2, f, work)};
     const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     const double cnext[3] = {0.5 * dt, 0.5 * dt, dt};
+    const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
+    AmrArgs A = stage_args(p, in[s], f, acc, amr_stage_output(p, s, f, work), a, dt * b[s], s < 3 ? cnext[s] : 0.0,
+                           b[s], s == 0, work);
+    VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage_all(p, kind, A, stream); }));
+    return VP_OK;
+}
+
+vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
+{
     for (int s = 0; s < 4; ++s) {
-        const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
-        AmrArgs A = stage_args(p, in[s], f, acc, out[s], a, dt * b[s], s < 3 ? cnext[s] : 0.0, b[s], s == 0, work);
-        VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage_all(p, kind, A, stream); }));
+        if (vp_status st = amr_stage(p, s, f, a, dt, work, stream)) return st;
         if (s < 3)
-            if (vp_status st = constraint(p, static_cast<const double*>(out[s]), a, work, stream)) return st;
+            if (vp_status st = constraint(p, static_cast<const double*>(amr_stage_output(p, s, f, work)), a, work,
+                                          stream))
+                return st;
     }
+    if (vp_status st = amr_end_sync(p, f, dt, work, stream)) return st;
+    return constraint(p, static_cast<const double*>(f), a, work, stream);
+}
+
+vp_status amr_end_sync(const vp_plan* p, void* f, double dt, void* work, hipStream_t stream)
+{
+    const AmrPlan& M = *p->amr;
     AmrSyncArgs S{};
     S.f = static_cast<double*>(f);
     S.ncv = M.ncv;
@@ -560,7 +578,7 @@ vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, h
     S.dtx = dt / M.dxc;
     S.dtv = dt / M.dvc;
     VP_HIP(timed(p, kTSync, stream, [&] { return launch_amr_sync(S, stream); }));
-    return constraint(p, static_cast<const double*>(f), a, work, stream);
+    return VP_OK;
 }
 
 }  // namespace vp

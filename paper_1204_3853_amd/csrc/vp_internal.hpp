@@ -383,6 +383,12 @@ vp_status amr_rhs(const vp_plan* p, const void* f, const double* a, void* k, hip
 vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream);
 vp_status amr_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
 vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
+// the pieces of amr_rk4: stage s (0..3) reading the acceleration a, its
+// output state (the stage-4 output is f itself), and the end-of-step
+// coarse-fine synchronisation (flux correction and average-down of f)
+vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt, void* work, hipStream_t stream);
+void* amr_stage_output(const vp_plan* p, int s, void* f, void* work);
+vp_status amr_end_sync(const vp_plan* p, void* f, double dt, void* work, hipStream_t stream);
 vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx);
 // 2D+2V host sequences (vp_4d.hip)
 vp_status p4_create(vp_plan* p, const vp_problem* pb);

@@ -1,10 +1,11 @@
 // Several kinetic species on one configuration mesh (section 1: every
-// species has its own velocity range, and in the paper's design its own
-// phase-space hierarchy; collisionless species interact only through the
-// field).  A group ties single-level 1D+1V plans together: each species is
-// advanced by its own plan's stage kernels, and after every stage one field
-// solve from the charge density of all species gives every species its
-// acceleration (q/m)_s E.
+// species has its own velocity range and its own phase-space hierarchy;
+// collisionless species interact only through the field).  A group ties
+// 1D+1V plans together, single-level or two-level: each species is advanced
+// by its own plan's stage kernels, and after every stage one field solve on
+// the shared finest configuration mesh, from the charge density of all
+// species, gives every species its acceleration (q/m)_s E (injected onto
+// both levels of a two-level species).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -48,9 +49,17 @@ vp_status field_from_neff(const vp_species_group* g, void* gwork, double* const*
     for (int s = 0; s < g->ns; ++s) {
         const vp_plan* q = g->plans[s];
         double* as = a[s];
-        VP_HIP(timed(q, kTOther, stream, [&] { return launch_scale(E, q->pb.qm, as, q->nx, stream); }));
+        VP_HIP(timed(q, kTOther, stream, [&] {
+            if (q->amr) return launch_amr_inject(E, q->amr->ncx, q->amr->R, q->pb.qm, as, stream);
+            return launch_scale(E, q->pb.qm, as, q->nx, stream);
+        }));
     }
     return VP_OK;
+}
+
+double* moment_buf(const vp_species_group* g, void* gwork, int s)
+{
+    return gptr(gwork, g->ws_n + (size_t)s * align256s((size_t)g->nx * sizeof(double)));
 }
 
 vp_status check_group_call(const vp_species_group* g, const void* const* f, double* const* a, void* gwork)
@@ -81,8 +90,7 @@ vp_status vp_species_group_create(const vp_plan* const* plans, const double* cha
     for (int s = 0; s < nspecies; ++s) {
         const vp_plan* p = plans[s];
         if (!p) return fail(VP_EINVAL, "vp_species_group_create: NULL plan");
-        if (p->amr || p->p4 || p->ndim != 1)
-            return fail(VP_ENOTSUP, "vp_species_group_create: single-level 1D+1V plans only");
+        if (p->p4 || p->ndim != 1) return fail(VP_ENOTSUP, "vp_species_group_create: 1D+1V plans only");
         if (!std::isfinite(charge[s])) return fail(VP_EINVAL, "vp_species_group_create: charges must be finite");
         if (p->dtype != p0->dtype) return fail(VP_EINVAL, "vp_species_group_create: the plans differ in dtype");
         if (p->nx != p0->nx || p->pb.x_lo[0] != p0->pb.x_lo[0] || p->pb.x_len[0] != p0->pb.x_len[0])
@@ -116,16 +124,18 @@ vp_status vp_species_group_destroy(vp_species_group* g)
 
 size_t vp_species_workspace_bytes(const vp_species_group* g) { return g ? g->ws_total : 0; }
 
-vp_status vp_species_field(const vp_species_group* g, const void* const* f, double* const* a, void* gwork,
-                           hipStream_t stream)
+vp_status vp_species_field(const vp_species_group* g, const void* const* f, double* const* a, void* const* work,
+                           void* gwork, hipStream_t stream)
 {
     if (vp_status st = check_group_call(g, f, a, gwork)) return st;
     SpeciesMoments m{};
     m.ns = g->ns;
     m.background = g->background;
     for (int s = 0; s < g->ns; ++s) {
-        double* ns = gptr(gwork, g->ws_n + (size_t)s * align256s((size_t)g->nx * sizeof(double)));
-        if (vp_status st = vp_reduce_moment(g->plans[s], f[s], ns, nullptr, stream)) return st;
+        double* ns = moment_buf(g, gwork, s);
+        void* ws = work ? work[s] : nullptr;
+        if (g->plans[s]->amr && !ws) return fail(VP_EINVAL, "vp_species_field: a two-level species needs its workspace");
+        if (vp_status st = vp_reduce_moment(g->plans[s], f[s], ns, ws, stream)) return st;
         m.part[s] = ns;
         m.nstrip[s] = 1;
         m.w[s] = g->charge[s];
@@ -146,16 +156,35 @@ vp_status vp_species_rk4_step(const vp_species_group* g, void* const* f, double*
     m.ns = g->ns;
     m.background = g->background;
     for (int s = 0; s < g->ns; ++s) {
-        R[s] = rk4_setup_1d(g->plans[s], f[s], work[s], dt, nullptr);
-        m.part[s] = R[s].part;
-        m.nstrip[s] = R[s].A.nstrip;
-        m.w[s] = g->charge[s] * g->plans[s]->dv;
+        const vp_plan* p = g->plans[s];
+        if (p->amr) {
+            // the moment on the finest configuration mesh, by the plan's reduction
+            m.part[s] = moment_buf(g, gwork, s);
+            m.nstrip[s] = 1;
+            m.w[s] = g->charge[s];
+        } else {
+            // the strip partial sums of the fused stage reduction
+            R[s] = rk4_setup_1d(p, f[s], work[s], dt, nullptr);
+            m.part[s] = R[s].part;
+            m.nstrip[s] = R[s].A.nstrip;
+            m.w[s] = g->charge[s] * p->dv;
+        }
     }
     for (int st = 0; st < 4; ++st) {
         // every species' stage (each reads its a_s of this stage), then one
-        // field solve that writes every a_s of the next stage
+        // field solve that writes every a_s of the next stage; a two-level
+        // species is synchronised (flux correction, average-down) after its
+        // last stage, before its moment is taken
         for (int s = 0; s < g->ns; ++s) {
             const vp_plan* p = g->plans[s];
+            if (p->amr) {
+                if (vp_status e = amr_stage(p, st, f[s], a[s], dt, work[s], stream)) return e;
+                if (st == 3)
+                    if (vp_status e = amr_end_sync(p, f[s], dt, work[s], stream)) return e;
+                const void* out = amr_stage_output(p, st, f[s], work[s]);
+                if (vp_status e = amr_reduce(p, out, moment_buf(g, gwork, s), work[s], stream)) return e;
+                continue;
+            }
             const Stage1DArgs A = rk4_stage_args_1d(R[s], st, a[s]);
             const StageShape sh = R[s].sh;
             const int kind = R[s].kind[st];

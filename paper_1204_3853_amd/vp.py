@@ -114,7 +114,7 @@ SIGNATURES = {
                                                _D, ctypes.POINTER(_P)]),
     "vp_species_group_destroy": (ctypes.c_int, [_P]),
     "vp_species_workspace_bytes": (_S, [_P]),
-    "vp_species_field": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _P]),
+    "vp_species_field": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _P]),
     "vp_species_rk4_step": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, ctypes.POINTER(_P), _P,
                                            _P]),
 }
@@ -501,10 +501,10 @@ class AmrRun:
 
 
 class SpeciesGroup:
-    """Species on one configuration mesh (vp_species_group): plans of
-    single-level 1D+1V problems (each with its own velocity mesh and qm),
-    their charges, and a uniform neutralising background;
-    rho = background + sum_s charge_s n_s."""
+    """Species on one configuration mesh (vp_species_group): plans of 1D+1V
+    problems, single-level or two-level (each with its own velocity mesh,
+    boxes and qm) sharing the finest configuration mesh, their charges, and
+    a uniform neutralising background; rho = background + sum_s charge_s n_s."""
 
     def __init__(self, plans, charges, background=0.0):
         n = len(plans)
@@ -538,7 +538,8 @@ class SpeciesGroup:
         if as_ is None:
             as_ = [torch.empty(p.field_elems, dtype=torch.float64, device=p.device) for p in self.plans]
         fp, ap = self._lists(fs, as_)
-        _check(lib().vp_species_field(self.h, fp, ap, _ptr(self.gwork), _stream()))
+        wp = (_P * len(self.plans))(*[p.work.data_ptr() for p in self.plans])
+        _check(lib().vp_species_field(self.h, fp, ap, wp, _ptr(self.gwork), _stream()))
         return as_
 
     def rk4_step(self, fs, as_, dt):

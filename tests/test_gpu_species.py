@@ -121,5 +121,60 @@ def test_group_errors(vp):
     boxes = [{"level": 1, "lo": [0, 0], "hi": [7, 7]}]
     f, vc, vf = I.amr_landau(boxes, coarse=(32, 48), ratio=4)
     two = vp.Plan(vp.two_level_spec(32, 48, 4 * math.pi, -8.0, 8.0, -1.0, 4, vc, vf), boxes=boxes)
-    with pytest.raises(vp.VPError, match="single-level"):
+    with pytest.raises(vp.VPError, match="configuration mesh"):     # finest meshes of 32 and 128 cells
         vp.SpeciesGroup([plan, two], [-1.0, 1.0])
+    with pytest.raises(vp.VPError, match="1D"):
+        vp.SpeciesGroup([vp.Plan(I.Problem2D(8, 8, 16, 16))], [-1.0])
+
+
+# ---- one two-level hierarchy per species
+
+E_BOXES = [{"level": 1, "lo": [8, 64], "hi": [39, 127]}, {"level": 1, "lo": [64, 80], "hi": [99, 111]}]
+I_BOXES = [{"level": 1, "lo": [0, 32], "hi": [27, 63]}, {"level": 1, "lo": [48, 40], "hi": [119, 55]}]
+
+
+def amr_species(vp, oracle, ncx, ncv, R, qm, v_lo, v_hi, profile, boxes, eps, noise, seed):
+    f, vc, vf = I._amr_state(profile, 0.0, 4 * math.pi, v_lo, v_hi, eps, 0.5, boxes, (ncx, ncv), R)
+    f = f * (1.0 + noise * np.random.default_rng(seed).random(f.size))
+    spec = vp.two_level_spec(ncx, ncv, 4 * math.pi, v_lo, v_hi, qm, R, vc, vf)
+    plan = vp.Plan(spec, boxes=boxes)
+    o = oracle.OracleAMR(ncx, ncv, 4 * math.pi, v_lo, v_hi, qm, R, boxes, vc, vf)
+    return plan, o, f
+
+
+def test_two_level_electrons_and_ions(vp, oracle):
+    ncx, R = 32, 4
+    vth = 0.1
+    ion = lambda u: I.maxwellian(u / vth) / vth
+    pe, oe, fe = amr_species(vp, oracle, ncx, 48, R, -1.0, -8.0, 8.0, I.maxwellian, E_BOXES, 0.05, 0.01, 1)
+    pi_, oi, fi = amr_species(vp, oracle, ncx, 24, R, 0.01, -8 * vth, 8 * vth, ion, I_BOXES, 0.02, 0.01, 2)
+    g = vp.SpeciesGroup([pe, pi_], [-1.0, 1.0], 0.0)
+    fs = [torch.tensor(fe, device="cuda"), torch.tensor(fi, device="cuda")]
+    a = g.field(fs)
+    want_a = oracle.amr_species_field([oe, oi], [fe, fi], [-1.0, 1.0], 0.0)
+    for ag, aw in zip(a, want_a):
+        assert np.abs(ag.cpu().numpy() - aw).max() <= 1e-11 * np.abs(aw).max()
+    want = [fe, fi]
+    dt = 0.5 * (4 * math.pi / (ncx * R)) / 8.0
+    for _ in range(3):
+        g.rk4_step(fs, a, dt)
+        want = oracle.amr_species_rk4_step([oe, oi], want, [-1.0, 1.0], 0.0, dt)
+    for f, w in zip(fs, want):
+        assert np.abs(f.cpu().numpy() - w).max() <= 3e-12 * np.abs(w).max()
+    want_a = oracle.amr_species_field([oe, oi], want, [-1.0, 1.0], 0.0)
+    for ag, aw in zip(a, want_a):
+        assert np.abs(ag.cpu().numpy() - aw).max() <= 1e-9 * np.abs(aw).max()
+
+
+def test_two_level_single_species_matches_the_plan_step(vp, oracle):
+    pe, oe, fe = amr_species(vp, oracle, 32, 48, 4, -1.0, -8.0, 8.0, I.maxwellian, E_BOXES, 0.05, 0.0, 1)
+    f = torch.tensor(fe, device="cuda")
+    f2 = f.clone()
+    a = vp.field_of(pe, f)
+    g = vp.SpeciesGroup([pe], [-1.0], 1.0)
+    a2 = g.field([f2])[0]
+    assert float((a - a2).abs().max()) <= 1e-12 * float(a.abs().max())
+    for _ in range(2):
+        vp.rk4_step(pe, f, a, 0.01)
+        g.rk4_step([f2], [a2], 0.01)
+    assert float((f - f2).abs().max()) <= 1e-12 * float(f.abs().max())

@@ -80,3 +80,48 @@ def test_uniform_heavy_species_is_a_background(oracle):
     want = oracle.Oracle1D.from_problem(pe).step(fe, dt)
     assert np.abs(oe - want).max() <= 1e-12 * np.abs(want).max()
     assert np.abs(oi - fi).max() <= 1e-9 * np.abs(fi).max()
+
+
+# ---- one two-level hierarchy per species
+
+BOXES = [{"level": 1, "lo": [8, 16], "hi": [23, 39]}, {"level": 1, "lo": [40, 8], "hi": [51, 27]}]
+
+
+def amr_setup(oracle, qm, eps=0.05, boxes=BOXES, coarse=(16, 12), R=4):
+    f, vc, vf = I.amr_landau(boxes, coarse=coarse, ratio=R, eps=eps)
+    o = oracle.OracleAMR(coarse[0], coarse[1], 4 * math.pi, -8.0, 8.0, qm, R, boxes, vc, vf)
+    return o, f
+
+
+def test_amr_one_species_is_the_background_model(oracle):
+    o, f = amr_setup(oracle, -1.0)
+    dt = 0.02
+    got = oracle.amr_species_rk4_step([o], [f], [-1.0], 1.0, dt)[0]
+    assert np.array_equal(got, o.step(f, dt))
+    a = oracle.amr_species_field([o], [f], [-1.0], 1.0)[0]
+    assert np.array_equal(a, o.constraints(f)[0])
+
+
+def test_amr_pair_plasma_streams_freely(oracle):
+    oe, f = amr_setup(oracle, -1.0)
+    op, _ = amr_setup(oracle, +1.0)
+    o0, _ = amr_setup(oracle, 0.0)
+    a = oracle.amr_species_field([oe, op], [f, f], [-1.0, 1.0], 0.0)
+    assert np.all(a[0] == 0.0) and np.all(a[1] == 0.0)
+    dt = 0.05
+    out = oracle.amr_species_rk4_step([oe, op], [f, f], [-1.0, 1.0], 0.0, dt)
+    want = o0.step(f, dt)
+    for g in out:
+        assert np.abs(g - want).max() <= 1e-15 * np.abs(want).max()
+
+
+def test_amr_two_beams_sum_like_one_species(oracle):
+    o, f = amr_setup(oracle, -1.0, eps=0.1)
+    rng = np.random.default_rng(3)
+    w = rng.random(f.size)
+    f1, f2 = f * w, f * (1.0 - w)
+    dt = 0.03
+    o1, o2 = oracle.amr_species_rk4_step([o, o], [f1, f2], [-1.0, -1.0], 1.0, dt)
+    want = o.step(f, dt)
+    assert np.abs(o1 + o2 - want).max() <= 1e-13 * np.abs(want).max()
+    assert np.abs(o1 - want).max() > 1e-2 * np.abs(want).max()
