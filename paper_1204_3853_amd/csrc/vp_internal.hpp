@@ -195,10 +195,20 @@ struct SpeciesMoments {
 // n_eff = 1 - rho with rho = background + sum_s w_s sum_strips part_s, the
 // form the single-species field solves take (rho = 1 - n)
 hipError_t launch_species_neff(const SpeciesMoments& m, int nx, double* n_eff, hipStream_t stream);
+// arrays the split field solve writes: a[k] = qm[k] E
+struct FieldOutputs {
+    double* a[kMaxSpecies + 1];
+    double qm[kMaxSpecies + 1];
+    int n;
+};
 // moment from strip partials, Poisson, field and a = (q/m) E over many blocks
 // (nx >= kFieldSplitMin); work holds nx + 2 ceil(nx / kFieldChunk) doubles
 hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv, double dx, double qm,
                               const double* green, double* work, double* a, hipStream_t stream);
+// the same from the charge density of several species (rho = background +
+// sum_s w_s sum_strips part_s), writing every array of `out`
+hipError_t launch_field_split_species(const SpeciesMoments& m, int nx, double dx, const double* green, double* work,
+                                      const FieldOutputs& out, hipStream_t stream);
 // Poisson, field and two-level injection in one launch; the moment is n_in,
 // or is finalised from the weighted list of x when x.slots is set
 hipError_t launch_poisson1d_inject(const double* n_in, const PoissonExtra& x, int nx, double dx, double qm,

@@ -120,8 +120,8 @@ __device__ double block_exclusive_scan(double v, double* red)
 //     E_i = -(7 (d_i + d_{i-1}) - d_{i+1} - d_{i-2}) / (12 dx), a = (q/m) E.
 // All sums run in a fixed order.
 
-__global__ __launch_bounds__(kFieldChunk) void k_field_chunks(const double* __restrict__ part, int nstrip, int nx,
-                                                              double dv, double dx, const double* __restrict__ green,
+__global__ __launch_bounds__(kFieldChunk) void k_field_chunks(SpeciesMoments m, int nx, double dx,
+                                                              const double* __restrict__ green,
                                                               double* __restrict__ y, double* __restrict__ csum)
 {
     constexpr int K = kGreenTaps;
@@ -132,29 +132,40 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_chunks(const double* __re
     const int c0 = blockIdx.x * kFieldChunk;
     if (t <= K) gs[t] = green[t];
     const double scale = 12.0 * dx * dx;
-    // the moments of rows c0 - K .. c0 + kFieldChunk + K - 1 (periodic); the
-    // loads of both rows a thread owns are in flight together
+    // the charge density of rows c0 - K .. c0 + kFieldChunk + K - 1
+    // (periodic): per species the sum of its strip partials (the loads of
+    // both rows a thread owns in flight together), weighted, added to the
+    // background
     constexpr int NQ = (kFieldChunk + 2 * K + kFieldChunk - 1) / kFieldChunk;
-    double acc[NQ];
+    double rho[NQ];
 #pragma unroll
-    for (int u = 0; u < NQ; ++u) acc[u] = 0.0;
-    for (int s0 = 0; s0 < nstrip; s0 += 8) {
-        double v[NQ][8];
+    for (int u = 0; u < NQ; ++u) rho[u] = m.background;
+    for (int sp = 0; sp < m.ns; ++sp) {
+        const double* part = m.part[sp];
+        const int nstrip = m.nstrip[sp];
+        double acc[NQ];
 #pragma unroll
-        for (int u = 0; u < NQ; ++u) {
-            const int i = wrapi(c0 - K + min(t + u * kFieldChunk, kFieldChunk + 2 * K - 1), nx);
+        for (int u = 0; u < NQ; ++u) acc[u] = 0.0;
+        for (int s0 = 0; s0 < nstrip; s0 += 8) {
+            double v[NQ][8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) v[u][m] = (s0 + m < nstrip) ? part[(size_t)(s0 + m) * nx + i] : 0.0;
+            for (int u = 0; u < NQ; ++u) {
+                const int i = wrapi(c0 - K + min(t + u * kFieldChunk, kFieldChunk + 2 * K - 1), nx);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[u][q] = (s0 + q < nstrip) ? part[(size_t)(s0 + q) * nx + i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < NQ; ++u)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[u] += v[u][q];
         }
 #pragma unroll
-        for (int u = 0; u < NQ; ++u)
-#pragma unroll
-            for (int m = 0; m < 8; ++m) acc[u] += v[u][m];
+        for (int u = 0; u < NQ; ++u) rho[u] += m.w[sp] * acc[u];
     }
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
         const int q = t + u * kFieldChunk;
-        if (q < kFieldChunk + 2 * K) r[q] = scale * (1.0 - dv * acc[u]);
+        if (q < kFieldChunk + 2 * K) r[q] = scale * rho[u];
     }
     __syncthreads();
     const int i = c0 + t;
@@ -182,7 +193,7 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_chunks(const double* __re
 
 __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __restrict__ y,
                                                               const double* __restrict__ csum, int nchunk, int nx,
-                                                              double dx, double qm, double* __restrict__ a_out)
+                                                              double dx, FieldOutputs out)
 {
     __shared__ double d[kFieldChunk + 4];     // d_i for i = c0 - 2 .. c0 + kFieldChunk + 1
     __shared__ double red[kFieldChunk / 64];
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
     const int i = c0 + t;
     if (i < nx) {
         const double E = -(7.0 * (d[t + 2] + d[t + 1]) - d[t + 3] - d[t]) / (12.0 * dx);
-        a_out[i] = qm * E;
+        for (int k = 0; k < out.n; ++k) out.a[k][i] = out.qm[k] * E;
     }
 }
 
@@ -578,9 +589,32 @@ hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv,
     const int nchunk = (nx + kFieldChunk - 1) / kFieldChunk;
     double* y = work;
     double* csum = work + nx;
-    hipLaunchKernelGGL(k_field_chunks, dim3(nchunk), dim3(kFieldChunk), 0, stream, part, nstrip, nx, dv, dx, green,
-                       y, csum);
-    hipLaunchKernelGGL(k_field_finish, dim3(nchunk), dim3(kFieldChunk), 0, stream, y, csum, nchunk, nx, dx, qm, a);
+    SpeciesMoments m{};
+    m.part[0] = part;
+    m.nstrip[0] = nstrip;
+    m.w[0] = -dv;
+    m.ns = 1;
+    m.background = 1.0;
+    FieldOutputs out{};
+    out.a[0] = a;
+    out.qm[0] = qm;
+    out.n = 1;
+    hipLaunchKernelGGL(k_field_chunks, dim3(nchunk), dim3(kFieldChunk), 0, stream, m, nx, dx, green, y, csum);
+    hipLaunchKernelGGL(k_field_finish, dim3(nchunk), dim3(kFieldChunk), 0, stream, y, csum, nchunk, nx, dx, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_split_species(const SpeciesMoments& m, int nx, double dx, const double* green, double* work,
+                                      const FieldOutputs& out, hipStream_t stream)
+{
+    if (nx < kFieldSplitMin || nx > kMaxPoisson1D || m.ns < 1 || m.ns > kMaxSpecies || out.n < 1 ||
+        out.n > kMaxSpecies + 1)
+        return hipErrorInvalidValue;
+    const int nchunk = (nx + kFieldChunk - 1) / kFieldChunk;
+    double* y = work;
+    double* csum = work + nx;
+    hipLaunchKernelGGL(k_field_chunks, dim3(nchunk), dim3(kFieldChunk), 0, stream, m, nx, dx, green, y, csum);
+    hipLaunchKernelGGL(k_field_finish, dim3(nchunk), dim3(kFieldChunk), 0, stream, y, csum, nchunk, nx, dx, out);
     return hipGetLastError();
 }
 

@@ -33,22 +33,51 @@ size_t align256s(size_t x) { return (x + 255) & ~size_t(255); }
 
 double* gptr(void* gwork, size_t off) { return reinterpret_cast<double*>(static_cast<char*>(gwork) + off); }
 
-// n_eff -> E on the shared configuration mesh (the single-species solves with
-// unit weights), then a_s = (q/m)_s E
-vp_status field_from_neff(const vp_species_group* g, void* gwork, double* const* a, hipStream_t stream)
+// the field of the species' moments m, then every a_s.  Meshes of at least
+// kFieldSplitMin cells: the split solve takes the charge density straight
+// from the moments and writes a_s = (q/m)_s E of every single-level species
+// (and E for the two-level ones, which inject it onto their levels).
+// Smaller meshes: n_eff = 1 - rho, the one-block solve for E, then a_s.
+vp_status species_field_solve(const vp_species_group* g, const SpeciesMoments& m, void* gwork, double* const* a,
+                              hipStream_t stream)
 {
     const vp_plan* p = g->plans[0];
     double* n_eff = gptr(gwork, g->ws_neff);
     double* E = gptr(gwork, g->ws_E);
     double* cfg = gptr(gwork, g->ws_cfg);
-    VP_HIP(timed(p, kTField, stream, [&] {
-        if (p->nx >= kFieldSplitMin) return launch_field_split(n_eff, 1, p->nx, 1.0, p->dx, 1.0, p->d_green, cfg, E, stream);
-        return launch_poisson1d(nullptr, 0, n_eff, 1.0, p->nx, p->dx, 1.0, p->d_green, p->gk, nullptr, nullptr, nullptr,
-                                E, stream);
-    }));
+    bool need_E = true;
+    if (p->nx >= kFieldSplitMin) {
+        FieldOutputs out{};
+        bool any_amr = false;
+        for (int s = 0; s < g->ns; ++s) {
+            if (g->plans[s]->amr) {
+                any_amr = true;
+                continue;
+            }
+            out.a[out.n] = a[s];
+            out.qm[out.n] = g->plans[s]->pb.qm;
+            ++out.n;
+        }
+        if (any_amr) {
+            out.a[out.n] = E;
+            out.qm[out.n] = 1.0;
+            ++out.n;
+        }
+        VP_HIP(timed(p, kTField, stream, [&] {
+            return launch_field_split_species(m, p->nx, p->dx, p->d_green, cfg, out, stream);
+        }));
+        need_E = false;
+    } else {
+        VP_HIP(launch_species_neff(m, g->nx, n_eff, stream));
+        VP_HIP(timed(p, kTField, stream, [&] {
+            return launch_poisson1d(nullptr, 0, n_eff, 1.0, p->nx, p->dx, 1.0, p->d_green, p->gk, nullptr, nullptr,
+                                    nullptr, E, stream);
+        }));
+    }
     for (int s = 0; s < g->ns; ++s) {
         const vp_plan* q = g->plans[s];
         double* as = a[s];
+        if (!q->amr && !need_E) continue;
         VP_HIP(timed(q, kTOther, stream, [&] {
             if (q->amr) return launch_amr_inject(E, q->amr->ncx, q->amr->R, q->pb.qm, as, stream);
             return launch_scale(E, q->pb.qm, as, q->nx, stream);
@@ -140,8 +169,7 @@ vp_status vp_species_field(const vp_species_group* g, const void* const* f, doub
         m.nstrip[s] = 1;
         m.w[s] = g->charge[s];
     }
-    VP_HIP(launch_species_neff(m, g->nx, gptr(gwork, g->ws_neff), stream));
-    return field_from_neff(g, gwork, a, stream);
+    return species_field_solve(g, m, gwork, a, stream);
 }
 
 vp_status vp_species_rk4_step(const vp_species_group* g, void* const* f, double* const* a, double dt,
@@ -190,8 +218,7 @@ vp_status vp_species_rk4_step(const vp_species_group* g, void* const* f, double*
             const int kind = R[s].kind[st];
             VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage1d(p->dtype, sh, kind, A, stream); }));
         }
-        VP_HIP(launch_species_neff(m, g->nx, gptr(gwork, g->ws_neff), stream));
-        if (vp_status e = field_from_neff(g, gwork, a, stream)) return e;
+        if (vp_status e = species_field_solve(g, m, gwork, a, stream)) return e;
     }
     return VP_OK;
 }
