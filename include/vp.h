@@ -462,8 +462,27 @@ vp_status vp_amr_run_boxes(const vp_amr_run* run, vp_box* boxes, int32_t max_box
 /* Copies the current state into dst (device, elems == vp_state_elems of
  * the current plan, else VP_ESHAPE); enqueued on `stream`. */
 vp_status vp_amr_run_read_state(const vp_amr_run* run, void* dst, size_t elems, hipStream_t stream);
-/* Waits for the device, frees the run's memory and plan.  NULL is a no-op. */
+/* Waits for the device, frees the run's memory and plans.  NULL is a no-op. */
 vp_status vp_amr_run_destroy(vp_amr_run* run);
+
+/* A run of several species, each on its own two-level hierarchy that it
+ * regrids from its own tags (section 1: one hierarchy per species), coupled
+ * through the field of a species group (vp_species_group_create: rho =
+ * background + sum_s charge[s] n_s, the same finest configuration mesh).
+ * problems[s], boxes[s] (nbox[s] of them), f0[s]: as vp_amr_run_create per
+ * species.  The time step takes the stability limit over every level of
+ * every species.  vp_amr_run_info sums patches and state elements over the
+ * species; the calls without a species index address species 0. */
+vp_status vp_amr_run_create_species(int32_t nspecies, const vp_problem* const* problems, const vp_box* const* boxes,
+                                    const int32_t* nbox, const void* const* f0, const double* charge,
+                                    double background, const vp_amr_params* params, vp_amr_run** out,
+                                    hipStream_t stream);
+int32_t vp_amr_run_species_count(const vp_amr_run* run);
+const vp_plan* vp_amr_run_plan_of(const vp_amr_run* run, int32_t species);
+vp_status vp_amr_run_boxes_of(const vp_amr_run* run, int32_t species, vp_box* boxes, int32_t max_boxes,
+                              int32_t* nbox);
+vp_status vp_amr_run_read_state_of(const vp_amr_run* run, int32_t species, void* dst, size_t elems,
+                                   hipStream_t stream);
 
 /*
  * Several kinetic species on one configuration mesh.  Each species has its

@@ -110,6 +110,16 @@ SIGNATURES = {
     "vp_amr_run_boxes": (ctypes.c_int, [_P, ctypes.POINTER(vp_box), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "vp_amr_run_read_state": (ctypes.c_int, [_P, _P, _S, _P]),
     "vp_amr_run_destroy": (ctypes.c_int, [_P]),
+    "vp_amr_run_create_species": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(vp_problem)),
+                                                 ctypes.POINTER(ctypes.POINTER(vp_box)),
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_P),
+                                                 ctypes.POINTER(ctypes.c_double), _D, ctypes.POINTER(vp_amr_params),
+                                                 ctypes.POINTER(_P), _P]),
+    "vp_amr_run_species_count": (ctypes.c_int32, [_P]),
+    "vp_amr_run_plan_of": (_P, [_P, ctypes.c_int32]),
+    "vp_amr_run_boxes_of": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(vp_box), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    "vp_amr_run_read_state_of": (ctypes.c_int, [_P, ctypes.c_int32, _P, _S, _P]),
     "vp_species_group_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                                _D, ctypes.POINTER(_P)]),
     "vp_species_group_destroy": (ctypes.c_int, [_P]),
@@ -453,21 +463,42 @@ class AmrRun:
     initial level-1 boxes; f0: the initial state in that plan's layout."""
 
     def __init__(self, spec, boxes, f0, tol, regrid_interval, efficiency=0.7, min_width=2, buffer=1, cfl=0.5,
-                 dt_growth=1.1, dt_initial=0.01):
+                 dt_growth=1.1, dt_initial=0.01, charges=None, background=None):
+        """One species: spec (a two-level spec dict), boxes, f0.  Several
+        species: lists spec[s], boxes[s], f0[s] and their charges; the field
+        of rho = background + sum_s charge_s n_s."""
         if not torch.cuda.is_available():
             raise RuntimeError("the Vlasov-Poisson library needs a HIP GPU (torch.cuda is unavailable)")
-        self.spec = spec
-        pb, keep = _make_problem(spec, torch.float64)
-        bx, nbox = _make_boxes(boxes)
         prm = vp_amr_params(float(tol), int(regrid_interval), float(efficiency), int(min_width), int(buffer),
                             float(cfl), float(dt_growth), float(dt_initial))
-        if f0.dtype != torch.float64 or not f0.is_cuda or not f0.is_contiguous():
-            raise ValueError("f0: contiguous float64 tensor on the GPU expected")
+        several = charges is not None
+        specs, blist, flist = (spec, boxes, f0) if several else ([spec], [boxes], [f0])
+        for f in flist:
+            if f.dtype != torch.float64 or not f.is_cuda or not f.is_contiguous():
+                raise ValueError("f0: contiguous float64 tensor on the GPU expected")
         h = ctypes.c_void_p()
-        _check(lib().vp_amr_run_create(ctypes.byref(pb), bx, nbox, _ptr(f0), ctypes.byref(prm), ctypes.byref(h),
-                                       _stream()))
+        if several:
+            n = len(specs)
+            made = [_make_problem(sp, torch.float64) for sp in specs]
+            self._keep = made
+            pbs = (ctypes.POINTER(vp_problem) * n)(*[ctypes.pointer(m[0]) for m in made])
+            bxs = [_make_boxes(b) for b in blist]
+            self._keep_boxes = bxs
+            bptr = (ctypes.POINTER(vp_box) * n)(*[ctypes.cast(b[0], ctypes.POINTER(vp_box)) if b[0] is not None
+                                                  else ctypes.POINTER(vp_box)() for b in bxs])
+            nb = (ctypes.c_int32 * n)(*[b[1] for b in bxs])
+            fp = (_P * n)(*[f.data_ptr() for f in flist])
+            ch = (ctypes.c_double * n)(*[float(c) for c in charges])
+            _check(lib().vp_amr_run_create_species(n, pbs, bptr, nb, fp, ch, ctypes.c_double(background or 0.0),
+                                                   ctypes.byref(prm), ctypes.byref(h), _stream()))
+        else:
+            pb, keep = _make_problem(spec, torch.float64)
+            bx, nbox = _make_boxes(boxes)
+            _check(lib().vp_amr_run_create(ctypes.byref(pb), bx, nbox, _ptr(f0), ctypes.byref(prm),
+                                           ctypes.byref(h), _stream()))
         self.h = h
-        self.device = f0.device
+        self.spec = spec
+        self.device = flist[0].device
 
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:
@@ -482,18 +513,22 @@ class AmrRun:
         _check(lib().vp_amr_run_info(self.h, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in vp_amr_info._fields_}
 
-    def boxes(self):
+    @property
+    def species_count(self):
+        return lib().vp_amr_run_species_count(self.h)
+
+    def boxes(self, species=0):
         n = ctypes.c_int32()
         cap = max(self.info()["npatch"], 1)
         arr = (vp_box * cap)()
-        _check(lib().vp_amr_run_boxes(self.h, arr, cap, ctypes.byref(n)))
+        _check(lib().vp_amr_run_boxes_of(self.h, species, arr, cap, ctypes.byref(n)))
         return _boxes_out(arr, n.value)
 
-    def state(self):
-        """A copy of the current state (layout of the current hierarchy)."""
-        n = self.info()["state_elems"]
+    def state(self, species=0):
+        """A copy of the current state of a species (layout of its current hierarchy)."""
+        n = lib().vp_state_elems(lib().vp_amr_run_plan_of(self.h, species))
         out = torch.empty(n, dtype=torch.float64, device=self.device)
-        _check(lib().vp_amr_run_read_state(self.h, _ptr(out), n, _stream()))
+        _check(lib().vp_amr_run_read_state_of(self.h, species, _ptr(out), n, _stream()))
         return out
 
 

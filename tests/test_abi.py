@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "vp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:vp_status|size_t|int64_t|const char\*|const vp_plan\*)\s+(vp_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:vp_status|size_t|int64_t|int32_t|const char\*|const vp_plan\*)\s+(vp_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 

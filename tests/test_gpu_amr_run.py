@@ -145,3 +145,62 @@ def test_run_errors(vp):
         run.advance(-1)
     run.advance(0)
     assert run.info()["steps"] == 0 and run.info()["t"] == 0.0
+
+
+def test_two_species_run_matches_oracle(vp, oracle):
+    """Electrons (bump-on-tail) and ions of mass ratio 100, each on its own
+    two-level hierarchy that it regrids from its own tags; the field of
+    rho = n_i - n_e; the time step from every level of both species."""
+    R, tol, interval, blocks = 4, 0.02, 4, 2
+    x_len = I.BUMP_X_LEN
+    vth = 0.1
+    ion = lambda u: I.maxwellian(u / vth) / vth
+    sp = [dict(coarse=(32, 64), v=(I.BUMP_V_LO, I.BUMP_V_HI), qm=-1.0, charge=-1.0, profile=I.bump_on_tail_profile,
+               eps=0.04, boxes=I.bump_on_tail_initial_boxes((32, 64), R)),
+          dict(coarse=(32, 32), v=(-8 * vth, 8 * vth), qm=0.01, charge=1.0, profile=ion, eps=0.04,
+               boxes=[{"level": 1, "lo": [0, 48], "hi": [63, 79]}])]
+    specs, f0s, hier, veqs = [], [], [], []
+    for s in sp:
+        (ncx, ncv), (v_lo, v_hi) = s["coarse"], s["v"]
+        f, vc, vf = I._amr_state(s["profile"], I.BUMP_X_LO, x_len, v_lo, v_hi, s["eps"], 0.3, s["boxes"], (ncx, ncv), R)
+        specs.append(vp.two_level_spec(ncx, ncv, x_len, v_lo, v_hi, s["qm"], R, vc, vf, x_lo=I.BUMP_X_LO))
+        f0s.append(f)
+        veqs.append((vc, vf))
+        hier.append(oracle.OracleAMR(ncx, ncv, x_len, v_lo, v_hi, s["qm"], R, s["boxes"], vc, vf))
+    charges = [s["charge"] for s in sp]
+    run = vp.AmrRun(specs, [s["boxes"] for s in sp], [torch.tensor(f, device="cuda") for f in f0s], tol, interval,
+                    charges=charges, background=0.0)
+    assert run.species_count == 2
+    fs = [np.array(f) for f in f0s]
+    boxes = [s["boxes"] for s in sp]
+    a = oracle.amr_species_field(hier, fs, charges, 0.0)
+    dt, t, steps = None, 0.0, 0
+    for _ in range(blocks):
+        run.advance(interval)
+        for _ in range(interval):
+            lim = min(oracle.amr_stability_limit(a[q], s["coarse"][0], s["coarse"][1], R, x_len, s["v"][0], s["v"][1],
+                                                 boxes[q]) for q, s in enumerate(sp))
+            dt = min(0.01 if dt is None else 1.1 * dt, 0.5 * lim)
+            fs = oracle.amr_species_rk4_step(hier, fs, charges, 0.0, dt)
+            a = oracle.amr_species_field(hier, fs, charges, 0.0)
+            t += dt
+            steps += 1
+        for q, s in enumerate(sp):
+            (ncx, ncv), (v_lo, v_hi) = s["coarse"], s["v"]
+            vc, vf = veqs[q]
+            g = np.array([vc[0], vc[1], vc[ncv + 2], vc[ncv + 3]])
+            f0c = fs[q][:ncx * ncv].reshape(ncx, ncv)
+            dxc, dvc = x_len / ncx, (v_hi - v_lo) / ncv
+            new_boxes = run.boxes(q)
+            check_clustering(oracle.tag(f0c, dxc, dvc, g, tol), oracle.tag_values(f0c, dxc, dvc, g), tol, new_boxes, R)
+            fs[q] = oracle.regrid_transfer(fs[q], boxes[q], new_boxes, ncx, ncv, R, g)
+            boxes[q] = new_boxes
+            hier[q] = oracle.OracleAMR(ncx, ncv, x_len, v_lo, v_hi, s["qm"], R, new_boxes, vc, vf)
+        a = oracle.amr_species_field(hier, fs, charges, 0.0)
+        info = run.info()
+        assert info["steps"] == steps and abs(info["t"] - t) <= 1e-12 * t
+        for q in range(2):
+            got = run.state(q).cpu().numpy()
+            assert got.shape == fs[q].shape
+            assert np.abs(got - fs[q]).max() <= 1e-12 * steps * np.abs(fs[q]).max(), q
+    assert run.info()["regrids"] == blocks and all(len(run.boxes(q)) > 0 for q in range(2))
