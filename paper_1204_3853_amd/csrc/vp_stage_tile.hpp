@@ -264,28 +264,6 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
     bool upx[W + 2];
 #pragma unroll
     for (int q = 0; q < W + 2; ++q) upx[q] = centre_unfused(A.v_lo, (double)(jt - 1 + q) + 0.5, A.dv) > 0.0;
-    auto fx_cols = [&](int r, T* Fx) {      // x-face r + 1/2 at columns jt-1 .. jt+W
-        const int sm1 = slot_of(r - 1), s0 = slot_of(r), s1 = slot_of(r + 1), s2 = slot_of(r + 2);
-#pragma unroll
-        for (int q = 0; q < W + 2; ++q) {
-            const int m = q - 1;
-            if (LIM) Fx[q] = face_lim<T>(cell(sm1, m), cell(s0, m), cell(s1, m), cell(s2, m), upx[q]);
-            else Fx[q] = face4<T>(cell(sm1, m), cell(s0, m), cell(s1, m), cell(s2, m));
-        }
-    };
-    auto fv_faces = [&](int r, T* Fv) {     // v-faces jt-1/2 .. jt+W-1/2 of row r
-        const int sl = slot_of(r);
-        T u[W + 4];
-#pragma unroll
-        for (int q = 0; q < W + 4; ++q) u[q] = cell(sl, q - 2);
-        const bool upv = LIM && aseg[max(r - i0 + 1, 0)] > 0.0;
-#pragma unroll
-        for (int m = 0; m <= W; ++m) {
-            if (LIM) Fv[m] = face_lim<T>(u[m], u[m + 1], u[m + 2], u[m + 3], upv);
-            else Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
-        }
-    };
-
     T vb[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) vb[w] = (T)(A.v_lo + ((double)(jt + w) + 0.5) * A.dv);
@@ -315,18 +293,55 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
         for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
         __syncthreads();
 
+        // The march window: rows i - D, i, i + D, i + 2D around the current row
+        // i, columns jt - 2 .. jt + W + 1, held in registers, so that every ring
+        // row is read from LDS once on its way through the window.
+        T win[4][W + 4];
+        auto load_win = [&](int r, T* u) {
+            const int sl = slot_of(r);
+#pragma unroll
+            for (int q = 0; q < W + 4; ++q) u[q] = cell(sl, q - 2);
+        };
+        // x faces at columns jt-1 .. jt+W between the middle two of four rows
+        // given in march order (taken in increasing x for the face average)
+        auto fx_rows = [&](const T* r0, const T* r1, const T* r2, const T* r3, T* Fx) {
+            const T* um1 = DN ? r3 : r0;
+            const T* u0 = DN ? r2 : r1;
+            const T* u1 = DN ? r1 : r2;
+            const T* u2 = DN ? r0 : r3;
+#pragma unroll
+            for (int q = 0; q < W + 2; ++q) {
+                if (LIM) Fx[q] = face_lim<T>(um1[q + 1], u0[q + 1], u1[q + 1], u2[q + 1], upx[q]);
+                else Fx[q] = face4<T>(um1[q + 1], u0[q + 1], u1[q + 1], u2[q + 1]);
+            }
+        };
+        // v faces jt-1/2 .. jt+W-1/2 of window row u (row r)
+        auto fv_row = [&](const T* u, int r, T* Fv) {
+            const bool upv = LIM && aseg[max(r - i0 + 1, 0)] > 0.0;
+#pragma unroll
+            for (int m = 0; m <= W; ++m) {
+                if (LIM) Fv[m] = face_lim<T>(u[m], u[m + 1], u[m + 2], u[m + 3], upv);
+                else Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
+            }
+        };
+
         // x-flux on the face behind the first row, v-face averages of the row
         // behind and of the first row
         T gx_old[W];
+        T fvP[W + 1], fvB[W + 1];
         {
+            T pre[W + 4];
+            load_win(ifirst - 2 * D, pre);
+            load_win(ifirst - D, win[0]);
+            load_win(ifirst, win[1]);
+            load_win(ifirst + D, win[2]);
             T Fx[W + 2];
-            fx_cols(DN ? i1 - 1 : i0 - 1, Fx);
+            fx_rows(pre, win[0], win[1], win[2], Fx);
 #pragma unroll
             for (int w = 0; w < W; ++w) gx_old[w] = vb[w] * Fx[w + 1] + dv24 * (Fx[w + 2] - Fx[w]);
+            fv_row(win[0], ifirst - D, fvP);
+            fv_row(win[1], ifirst, fvB);
         }
-        T fvP[W + 1], fvB[W + 1];
-        fv_faces(ifirst - D, fvP);
-        fv_faces(ifirst, fvB);
 
         // The new stage-state rows of batch mb are rows mb + 2 .. mb + RB + 1 of
         // the march (the rows ahead of the batch's output rows); rows past the
@@ -390,10 +405,11 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
                 const int qa = i - i0;
                 const int qc = max(qa, 0);                // rows past a downward segment are dropped
                 const T a_m1 = (T)aseg[qc], a_0 = (T)aseg[qc + 1], a_p1 = (T)aseg[qc + 2];
+                load_win(i + 2 * D, win[3]);
                 T Fx[W + 2];
-                fx_cols(DN ? i - 1 : i, Fx);              // the face ahead of row i
+                fx_rows(win[0], win[1], win[2], win[3], Fx);   // the face ahead of row i
                 T fvN[W + 1];
-                fv_faces(i + D, fvN);                     // the row ahead
+                fv_row(win[2], i + D, fvN);               // the row ahead
                 const T da48 = (a_p1 - a_m1) * T(1.0 / 48.0);
                 T gv[W + 1];
 #pragma unroll
@@ -418,11 +434,10 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
 #pragma unroll
                     for (int w = 0; w < W; ++w) o1[q][w] = kk[w];
                 } else if (KIND == kStage1) {
-                    // f^n is the stage state itself: take it from the ring
-                    const int sl = slot_of(i);
+                    // f^n is the stage state itself: take it from the window
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        const T f0 = cell(sl, w);
+                        const T f0 = win[1][w + 2];
                         o1[q][w] = f0 + cacc * kk[w];      // accumulator
                         o2[q][w] = f0 + cnext * kk[w];     // next predictor
                     }
@@ -435,15 +450,13 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
                 } else if (KIND == kStage4) {  // f^{n+1} = acc + dt/6 k4
 #pragma unroll
                     for (int w = 0; w < W; ++w) o2[q][w] = accv[q][w] + cacc * kk[w];
-                } else if (KIND == kLean1) {   // f(2) = f^n + dt/2 k1, f^n from the ring
-                    const int sl = slot_of(i);
+                } else if (KIND == kLean1) {   // f(2) = f^n + dt/2 k1, f^n from the window
 #pragma unroll
-                    for (int w = 0; w < W; ++w) o2[q][w] = cell(sl, w) + cnext * kk[w];
+                    for (int w = 0; w < W; ++w) o2[q][w] = win[1][w + 2] + cnext * kk[w];
                 } else if (KIND == kLean2) {   // f(3), and acc from f(2) = the stage state
-                    const int sl = slot_of(i);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        const T f2 = cell(sl, w);
+                        const T f2 = win[1][w + 2];
                         o1[q][w] = (fnv[q][w] + f2) * T(1.0 / 3.0) + cacc * kk[w];
                         o2[q][w] = fnv[q][w] + cnext * kk[w];
                     }
@@ -451,10 +464,9 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
 #pragma unroll
                     for (int w = 0; w < W; ++w) o2[q][w] = fnv[q][w] + cnext * kk[w];
                 } else {                       // kLean4: f^{n+1} from acc and f(4) = the stage state
-                    const int sl = slot_of(i);
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        const T f4 = cell(sl, w);
+                        const T f4 = win[1][w + 2];
                         o2[q][w] = accv[q][w] + (f4 * T(1.0 / 3.0) + cacc * kk[w]);
                     }
                 }
@@ -473,6 +485,13 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
                         VecIO<T, W>::stn(acc + rowoff, o1[q]);
                         VecIO<T, W>::stn(fout + rowoff, o2[q]);
                     }
+                }
+                // slide the window one row along the march
+#pragma unroll
+                for (int u = 0; u < W + 4; ++u) {
+                    win[0][u] = win[1][u];
+                    win[1][u] = win[2][u];
+                    win[2][u] = win[3][u];
                 }
             }
             if (KIND != kRhs && A.part) {
