@@ -212,6 +212,29 @@ vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, h
     double* n = reinterpret_cast<double*>(wsp(work, M.ws_n));
     double* E = reinterpret_cast<double*>(wsp(work, M.ws_E));
     VP_HIP(timed(p, kTMoment, stream, [&] { return reduce_launch(M, f, n, work, stream); }));
+    if (M.nfx >= kFieldSplitMin) {
+        // the split solve over many blocks; its last kernel also injects
+        SpeciesMoments m{};
+        m.part[0] = n;
+        m.nstrip[0] = 1;
+        m.w[0] = -1.0;
+        m.ns = 1;
+        m.background = 1.0;
+        FieldOutputs out{};
+        out.a[0] = a + M.ncx;
+        out.qm[0] = p->pb.qm;
+        out.a[1] = E;
+        out.qm[1] = 1.0;
+        out.n = 2;
+        out.inject_a = a;
+        out.inject_qm = p->pb.qm;
+        out.inject_R = M.R;
+        double* scratch = reinterpret_cast<double*>(wsp(work, M.ws_fld));
+        VP_HIP(timed(p, kTField, stream, [&] {
+            return launch_field_split_species(m, M.nfx, M.dxf, p->d_green, scratch, out, stream);
+        }));
+        return VP_OK;
+    }
     const PoissonExtra X{nullptr, nullptr, nullptr, nullptr, M.R};
     VP_HIP(timed(p, kTField, stream, [&] {
         return launch_poisson1d_inject(n, X, M.nfx, M.dxf, p->pb.qm, p->d_green, p->gk, E, a, stream);
@@ -488,6 +511,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->ws_slots_m = o; o += align256((size_t)(5 * ncx + (M->ntasks - M->fine_task0)) * sizeof(double));
     M->ws_n = o; o += align256((size_t)M->nfx * sizeof(double));
     M->ws_E = o; o += align256((size_t)M->nfx * sizeof(double));
+    M->ws_fld = o; o += align256(((size_t)M->nfx + 2 * ((size_t)M->nfx / kFieldChunk + 1) + 64) * sizeof(double));
     p->ws_total = o;
     p->state_elems = M->total;
     return VP_OK;

@@ -195,11 +195,16 @@ struct SpeciesMoments {
 // n_eff = 1 - rho with rho = background + sum_s w_s sum_strips part_s, the
 // form the single-species field solves take (rho = 1 - n)
 hipError_t launch_species_neff(const SpeciesMoments& m, int nx, double* n_eff, hipStream_t stream);
-// arrays the split field solve writes: a[k] = qm[k] E
+// arrays the split field solve writes: a[k] = qm[k] E; with inject_R > 0
+// also the coarse acceleration of a two-level plan, inject_a[c] = inject_qm
+// times the mean of the inject_R fine E values of coarse cell c
 struct FieldOutputs {
     double* a[kMaxSpecies + 1];
     double qm[kMaxSpecies + 1];
     int n;
+    double* inject_a;
+    double inject_qm;
+    int inject_R;
 };
 // moment from strip partials, Poisson, field and a = (q/m) E over many blocks
 // (nx >= kFieldSplitMin); work holds nx + 2 ceil(nx / kFieldChunk) doubles
@@ -315,7 +320,7 @@ struct AmrPlan {
     double* d_w_m = nullptr;
     size_t ws_slots_m = 0;
     // workspace offsets
-    size_t ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0;
+    size_t ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0, ws_fld = 0;
 };
 }  // namespace vp
 

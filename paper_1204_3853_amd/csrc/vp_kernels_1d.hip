@@ -245,9 +245,23 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
     }
     __syncthreads();
     const int i = c0 + t;
+    double E = 0.0;
     if (i < nx) {
-        const double E = -(7.0 * (d[t + 2] + d[t + 1]) - d[t + 3] - d[t]) / (12.0 * dx);
+        E = -(7.0 * (d[t + 2] + d[t + 1]) - d[t + 3] - d[t]) / (12.0 * dx);
         for (int k = 0; k < out.n; ++k) out.a[k][i] = out.qm[k] * E;
+    }
+    if (out.inject_R > 0) {
+        // two levels: the coarse acceleration is (q/m) times the mean of the
+        // R fine values (R divides the chunk size and nx)
+        __syncthreads();
+        d[t] = E;
+        __syncthreads();
+        const int R = out.inject_R;
+        if (t < kFieldChunk / R && c0 + t * R < nx) {
+            double se = 0.0;
+            for (int q = 0; q < R; ++q) se += d[t * R + q];
+            out.inject_a[c0 / R + t] = out.inject_qm * (se / R);
+        }
     }
 }
 
@@ -607,8 +621,10 @@ hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv,
 hipError_t launch_field_split_species(const SpeciesMoments& m, int nx, double dx, const double* green, double* work,
                                       const FieldOutputs& out, hipStream_t stream)
 {
-    if (nx < kFieldSplitMin || nx > kMaxPoisson1D || m.ns < 1 || m.ns > kMaxSpecies || out.n < 1 ||
+    if (nx < kFieldSplitMin || nx > kMaxPoisson1D || m.ns < 1 || m.ns > kMaxSpecies || out.n < 0 ||
         out.n > kMaxSpecies + 1)
+        return hipErrorInvalidValue;
+    if (out.inject_R > 0 && (!out.inject_a || kFieldChunk % out.inject_R || nx % out.inject_R))
         return hipErrorInvalidValue;
     const int nchunk = (nx + kFieldChunk - 1) / kFieldChunk;
     double* y = work;
