@@ -319,11 +319,12 @@ vp_status vp_launch_mode_set(vp_plan* plan, int32_t mode);
 
 /*
  * Autotuner: times `reps` RK4 steps (after one warm-up step) for every
- * tile shape valid for the plan, selects the fastest with
- * vp_tile_shape_set and returns its index and mean step time in ms (either
- * output may be NULL).  f and a are used as scratch: they are advanced by
- * (reps + 1) steps per shape, so pass copies of the state.  Unlike the
- * other calls it synchronises on its own timing events.
+ * tile shape valid for the plan, in three interleaved passes, keeps each
+ * shape's fastest pass, selects the fastest shape with vp_tile_shape_set
+ * and returns its index and mean step time in ms (either output may be
+ * NULL).  f and a are used as scratch: they are advanced by 3 (reps + 1)
+ * steps per shape, so pass copies of the state.  Unlike the other calls it
+ * synchronises on its own timing events.
  */
 vp_status vp_autotune(vp_plan* plan, void* f, double* a, double dt, int32_t reps, void* work,
                       hipStream_t stream, int32_t* best_index, float* best_ms);
