@@ -74,3 +74,28 @@ def test_amr_run_parameters_rejected_without_gpu(libvp):
     assert b"two levels" in L.vp_last_error()
     assert L.vp_amr_run_create(None, None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
     assert L.vp_amr_run_destroy(None) == 0
+
+
+def test_species_group_arguments_rejected_without_gpu(libvp):
+    """vp_species_group_create validates its arguments on the host."""
+    from paper_1204_3853_amd import vp
+    L = vp.lib()
+    out = ctypes.c_void_p()
+    ch = (ctypes.c_double * 2)(-1.0, 1.0)
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert L.vp_species_group_create(None, ch, 2, 0.0, ctypes.byref(out)) == 1
+    assert L.vp_species_group_create(nulls, ch, 0, 0.0, ctypes.byref(out)) == 1
+    assert b"species" in L.vp_last_error()
+    assert L.vp_species_group_create(nulls, ch, 5, 0.0, ctypes.byref(out)) == 1
+    assert L.vp_species_group_create(nulls, ch, 2, float("inf"), ctypes.byref(out)) == 1
+    assert b"finite" in L.vp_last_error()
+    assert L.vp_species_group_create(nulls, ch, 2, 0.0, ctypes.byref(out)) == 1
+    assert b"NULL plan" in L.vp_last_error()
+    assert L.vp_species_group_destroy(None) == 0
+    assert L.vp_species_workspace_bytes(None) == 0
+    assert L.vp_species_rk4_step(None, None, None, ctypes.c_double(0.1), None, None, None) == 1
+    assert L.vp_species_field(None, None, None, None, None, None) == 1
+    run_out = ctypes.c_void_p()
+    assert L.vp_amr_run_create_species(0, None, None, None, None, None, ctypes.c_double(0.0), None,
+                                       ctypes.byref(run_out), None) == 1
+    assert L.vp_amr_run_species_count(None) == 0
