@@ -173,3 +173,27 @@ def test_rhs_rejects_bad_arguments(V):
     code = V.lib().vp_rhs(plan.h, V._ptr(f), None, V._ptr(f), V._stream())
     assert code == 1                                    # VP_EINVAL, nothing enqueued
     assert b"NULL" in V.lib().vp_last_error() or b"alias" in V.lib().vp_last_error()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_rk4_step_every_tile_shape(V, oracle, dtype):
+    """Every compiled tile shape of the stage kernel gives the oracle's step
+    (the autotuner may pick any of them); ragged in x and v for every shape."""
+    nx, nv = 37, 1040
+    p = prob(nx, nv)
+    f = I.random_state(nx, nv, seed=11)[0] * p.veq[None, 2:-2] * 10
+    plan = V.Plan(p, dtype=dtype)
+    f_in = host(dev(f, dtype))
+    o = oracle.Oracle1D.from_problem(p)
+    dt = 0.5 / (8.0 / p.dx + 0.1 / p.dv)
+    want = o.step(f_in, dt)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    shapes = plan.tile_shapes()
+    assert len(shapes) >= 10
+    for q, shp in enumerate(shapes):
+        print(f"shape {shp} {dtype}", flush=True)
+        plan.set_tile_shape(q)
+        fg = dev(f, dtype)
+        ag = V.field_of(plan, fg)
+        V.rk4_step(plan, fg, ag, dt)
+        assert rel(host(fg), want) <= tol, shp
