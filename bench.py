@@ -96,8 +96,17 @@ def cpu_baseline(n, dt, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or steps >= 50:
             break
-    return {"value": n * n * steps / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{steps} full RK4 steps of the {n}x{n} two-stream mesh, FP64, {el:.1f} s"}
+    cores = O.num_threads()
+    value = n * n * steps / el
+    # one thread: one step of the same mesh
+    O.set_num_threads(1)
+    t0 = time.perf_counter()
+    f = o.step(f, dt)
+    el1 = time.perf_counter() - t0
+    O.set_num_threads(cores)
+    return {"value": value, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} full RK4 steps of the {n}x{n} two-stream mesh, FP64, {el:.1f} s",
+            "single_thread": {"value": n * n / el1, "sample": f"1 step on 1 thread, {el1:.1f} s"}}
 
 
 def adjoint_ratio(steps=400, every=20):
@@ -575,6 +584,10 @@ def main():
                     "kernel": "k_stage1d (4 launches per RK4 step)", "avg_launch_us": round(avg_ms * 1e3, 2),
                     "algorithmic_bytes_per_launch": bytes_launch,
                     "field_solve_us_per_launch": round(timing["field"][0] / max(timing["field"][1], 1) * 1e3, 2)}
+        if traffic:
+            # HBM bytes the counters saw per launch, over the same launch time
+            roofline["traffic_GBs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+            roofline["algorithmic_over_traffic"] = round(bytes_launch / traffic, 4)
 
     adj = None if args.no_adjoint else adjoint_ratio()
     amr = None if args.no_amr else amr_bench()

@@ -55,6 +55,7 @@ _V = ctypes.c_void_p
 def _declare(L):
     sig = {
         "vpo_num_threads": (_I, []),
+        "vpo_set_num_threads": (None, [_I]),
         "vpo_moment": (None, [_I, _I, _F, _D, _D]),
         "vpo_poisson_new": (_V, [_I]),
         "vpo_poisson_free": (None, [_V]),
@@ -132,6 +133,11 @@ def _f64(a):
 
 def num_threads():
     return lib().vpo_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's OpenMP loops from now on (timing only)."""
+    lib().vpo_set_num_threads(int(n))
 
 
 def moment(f, dv):

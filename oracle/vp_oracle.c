@@ -436,10 +436,13 @@ void vpo_rk4_step_fixed_a(const vpo_ctx* c, const double* f_in, double* f_out,
     free(fn); free(fs); free(ks);
 }
 
-/* Threads the OpenMP loops of the oracle use (1 without OpenMP). */
+/* Threads the OpenMP loops of the oracle use (1 without OpenMP); the
+ * setter changes the count for later calls (for timing only). */
 #ifdef _OPENMP
 #include <omp.h>
 int vpo_num_threads(void) { return omp_get_max_threads(); }
+void vpo_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 #else
 int vpo_num_threads(void) { return 1; }
+void vpo_set_num_threads(int n) { (void)n; }
 #endif

@@ -15,6 +15,7 @@ typedef struct vpo_ctx {
 } vpo_ctx;
 
 int vpo_num_threads(void);
+void vpo_set_num_threads(int n);
 void vpo_moment(int nx, int nv, double dv, const double* f, double* n);
 vpo_poisson* vpo_poisson_new(int N);
 void vpo_poisson_free(vpo_poisson* P);
