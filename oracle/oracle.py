@@ -93,6 +93,9 @@ def _declare_extra(L):
         "vpo_amr_constraints": (None, [_V, _D, _D, _D]),
         "vpo_amr_fill_ghosts": (None, [_V, _D, _I, _D]),
         "vpo_amr_rk4_step": (None, [_V, _D, _D, _F]),
+        "vpo_amr_subcycle_step": (None, [_V, _D, _D, _F]),
+        "vpo_rk4_dense_weights": (None, [_F, _D]),
+        "vpo_rk4_substage_weights": (None, [_F, _F, _I, _D]),
         "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
         "vpo_amr_species_constraints": (None, [_I, ctypes.POINTER(_V), ctypes.POINTER(_D), _D, _F,
                                                ctypes.POINTER(_D)]),
@@ -475,6 +478,33 @@ class OracleAMR:
         out = np.empty_like(f)
         lib().vpo_amr_rk4_step(self.h, _p(f), _p(out), dt)
         return out
+
+    def subcycle_step(self, f, dt):
+        """One subcycled step: the coarse level takes dt with the field of its
+        own moment on the coarse configuration mesh, the patches R substeps of
+        dt / R with coarse data from the continuous extension of the coarse
+        RK4 step, then refluxing and the average-down (section 5 names
+        asynchronous stepping as future work; the reading is in vp_oracle_amr.c)."""
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().vpo_amr_subcycle_step(self.h, _p(f), _p(out), dt)
+        return out
+
+
+def rk4_dense_weights(theta):
+    """b_1..b_4(theta) of the third-order continuous extension of classical RK4."""
+    b = np.empty(4)
+    lib().vpo_rk4_dense_weights(theta, _p(b))
+    return b
+
+
+def rk4_substage_weights(theta0, eta, s):
+    """Weights w_q (coarse data f_c^n + dt sum_q w_q K_q) of fine stage s of
+    the substep [theta0, theta0 + eta]: the RK4 stage values on the Taylor
+    expansion of the continuous extension at theta0."""
+    w = np.empty(4)
+    lib().vpo_rk4_substage_weights(theta0, eta, s, _p(w))
+    return w
 
 
 def _ptr_list(arrays):

@@ -84,6 +84,12 @@ void vpo4_rhs(void* h, double* f, double* a, double* k);
 void vpo4_rk4_step(void* h, double* f_in, double* f_out, double dt);
 void vpo4_rk4_step_fixed_a(void* h, double* f_in, double* f_out, double* a, double dt);
 void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt);
+/* subcycled two-level step: the coarse level takes dt with its own field,
+ * the patches R substeps of dt/R (continuous extension of the coarse step
+ * in time), then refluxing and the average-down */
+void vpo_rk4_dense_weights(double theta, double* b);
+void vpo_rk4_substage_weights(double theta0, double eta, int s, double* w);
+void vpo_amr_subcycle_step(void* h, double* f_in, double* f_out, double dt);
 /* several species, one two-level hierarchy each, the same finest
  * configuration mesh; rho = background + sum_s charge_s n_s */
 void vpo_amr_species_constraints(int ns, void* const* hs, double* const* fs, const double* charge,

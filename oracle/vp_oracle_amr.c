@@ -243,31 +243,38 @@ static void divergence(int nx, int nv, const double* Gx, const double* Gv, doubl
 }
 
 /* all fluxes of the hierarchy for state f and accelerations a */
-static void hierarchy_fluxes(const vpo_amr* c, double* f, const double* a, double** Gx, double** Gv)
+/* fluxes of the coarse level: one periodic patch with velocity ghosts */
+static void coarse_fluxes(const vpo_amr* c, const double* f, const double* a, double* Gx, double* Gv)
 {
     int ncx = c->ncx, ncv = c->ncv;
-    /* coarse level: one periodic patch with velocity ghosts */
-    {
-        int W = ncv + 4;
-        double* g = (double*)malloc(sizeof(double) * (size_t)(ncx + 4) * W);
-        for (int i = -2; i < ncx + 2; ++i)
-            for (int j = -2; j < ncv + 2; ++j) g[(size_t)(i + 2) * W + j + 2] = coarse_at(c, f, i, j);
-        double* ae = (double*)malloc(sizeof(double) * (ncx + 2));
-        for (int i = -1; i <= ncx; ++i) ae[i + 1] = a[wrap(i, ncx)];
-        patch_fluxes(ncx, ncv, g, c->dvc, c->v_lo, ae, Gx[0], Gv[0]);
-        free(ae);
-        free(g);
-    }
-    for (int p = 0; p < c->np; ++p) {
-        int nxp = NXP(c, p), nvp = NVP(c, p), x0 = c->box[4 * p], v0 = c->box[4 * p + 1];
-        double* g = (double*)malloc(sizeof(double) * (size_t)(nxp + 4) * (nvp + 4));
-        vpo_amr_fill_ghosts((void*)c, f, p, g);
-        double* ae = (double*)malloc(sizeof(double) * (nxp + 2));
-        for (int i = -1; i <= nxp; ++i) ae[i + 1] = a[ncx + wrap(x0 + i, c->nfx)];
-        patch_fluxes(nxp, nvp, g, c->dvf, c->v_lo + v0 * c->dvf, ae, Gx[p + 1], Gv[p + 1]);
-        free(ae);
-        free(g);
-    }
+    int W = ncv + 4;
+    double* g = (double*)malloc(sizeof(double) * (size_t)(ncx + 4) * W);
+    for (int i = -2; i < ncx + 2; ++i)
+        for (int j = -2; j < ncv + 2; ++j) g[(size_t)(i + 2) * W + j + 2] = coarse_at(c, f, i, j);
+    double* ae = (double*)malloc(sizeof(double) * (ncx + 2));
+    for (int i = -1; i <= ncx; ++i) ae[i + 1] = a[wrap(i, ncx)];
+    patch_fluxes(ncx, ncv, g, c->dvc, c->v_lo, ae, Gx, Gv);
+    free(ae);
+    free(g);
+}
+
+/* fluxes of level-1 patch p, its ghost cells filled from the coarse part of f */
+static void fine_patch_fluxes(const vpo_amr* c, double* f, const double* a, int p, double* Gx, double* Gv)
+{
+    int nxp = NXP(c, p), nvp = NVP(c, p), x0 = c->box[4 * p], v0 = c->box[4 * p + 1];
+    double* g = (double*)malloc(sizeof(double) * (size_t)(nxp + 4) * (nvp + 4));
+    vpo_amr_fill_ghosts((void*)c, f, p, g);
+    double* ae = (double*)malloc(sizeof(double) * (nxp + 2));
+    for (int i = -1; i <= nxp; ++i) ae[i + 1] = a[c->ncx + wrap(x0 + i, c->nfx)];
+    patch_fluxes(nxp, nvp, g, c->dvf, c->v_lo + v0 * c->dvf, ae, Gx, Gv);
+    free(ae);
+    free(g);
+}
+
+static void hierarchy_fluxes(const vpo_amr* c, double* f, const double* a, double** Gx, double** Gv)
+{
+    coarse_fluxes(c, f, a, Gx[0], Gv[0]);
+    for (int p = 0; p < c->np; ++p) fine_patch_fluxes(c, f, a, p, Gx[p + 1], Gv[p + 1]);
 }
 
 /* k = L(f; a) on every patch of the hierarchy (the ComputeRHS fluxes and
@@ -296,15 +303,16 @@ void vpo_amr_rhs(void* h, double* f, double* a, double* k)
 
 /* one synchronous RK4 step of the two-level hierarchy (Alg. smsvphu) */
 /* ComputeUpdate of the two-level step from the stage-weighted accumulated
- * fluxes Ax, Av (k: scratch of the state size): the fine levels first, then
- * the coarse level with its coarse-fine faces carrying the mean of the fine
- * fluxes, then covered coarse cells take the average of their fine cells */
+ * fluxes Ax, Av (k: scratch of the state size): the fine levels first
+ * (skipped when update_fine is 0: f_out already holds them), then the coarse
+ * level with its coarse-fine faces carrying the mean of the fine fluxes,
+ * then covered coarse cells take the average of their fine cells */
 static void amr_update(const vpo_amr* c, const double* fn, double** Ax, double** Av, double* k, double* f_out,
-                       double dt)
+                       double dt, int update_fine)
 {
     const int np = c->np, ncx = c->ncx, ncv = c->ncv, R = c->R;
     /* ComputeUpdate: finest level first */
-    for (int p = 1; p <= np; ++p) {
+    for (int p = 1; p <= np && update_fine; ++p) {
         int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
         divergence(nx, nv, Ax[p], Av[p], c->dxf, c->dvf, k + c->off[p - 1]);
         for (long q = 0; q < (long)nx * nv; ++q) f_out[c->off[p - 1] + q] = fn[c->off[p - 1] + q] + dt * k[c->off[p - 1] + q];
@@ -396,7 +404,7 @@ void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt)
             for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[p][q] += bw[s] * Gv[p][q];
         }
     }
-    amr_update(c, fn, Ax, Av, k, f_out, dt);
+    amr_update(c, fn, Ax, Av, k, f_out, dt, 1);
     for (int p = 0; p <= np; ++p) { free(Gx[p]); free(Gv[p]); free(Ax[p]); free(Av[p]); }
     free(Gx); free(Gv); free(Ax); free(Av);
     free(fn); free(fs); free(k); free(a);
@@ -491,10 +499,163 @@ void vpo_amr_species_rk4_step(int ns, void* const* hs, double* const* f_in, doub
     }
     for (int s = 0; s < ns; ++s) {
         vpo_amr* c = (vpo_amr*)hs[s];
-        amr_update(c, fn[s], Ax[s], Av[s], k[s], f_out[s], dt);
+        amr_update(c, fn[s], Ax[s], Av[s], k[s], f_out[s], dt, 1);
         for (int p = 0; p <= c->np; ++p) { free(Gx[s][p]); free(Gv[s][p]); free(Ax[s][p]); free(Av[s][p]); }
         free(Gx[s]); free(Gv[s]); free(Ax[s]); free(Av[s]);
         free(fn[s]); free(fs[s]); free(k[s]); free(a[s]);
     }
     free(Gx); free(Gv); free(Ax); free(Av); free(fn); free(fs); free(k); free(a);
+}
+
+/* ------------------------------------------------------------------------
+ * Subcycled two-level step (the asynchronous time stepping that section 5
+ * names as future work).  Reading, stated in full because the paper gives
+ * no algorithm for it:
+ *   1. the coarse level takes one RK4 step of dt on its own, with the field
+ *      of its own velocity moment on the coarse configuration mesh (covered
+ *      coarse cells hold the mean of their fine cells), keeping its four
+ *      stage slopes K1..K4 and its stage-weighted fluxes;
+ *   2. the fine patches take R RK4 substeps of dt/R.  The coarse level in
+ *      time is the continuous extension of the coarse RK4 step,
+ *      P(theta) = f_c^n + dt sum_q b_q(theta) K_q with b_1 = theta -
+ *      3 theta^2/2 + 2 theta^3/3, b_2 = b_3 = theta^2 - 2 theta^3/3,
+ *      b_4 = -theta^2/2 + 2 theta^3/3 (the third-order dense output of the
+ *      classical scheme).  For the four stages of the substep starting at
+ *      theta0 = m/R, with eta = 1/R and P1, P2, P3 the first three
+ *      theta-derivatives of P at theta0, the coarse data are the values the
+ *      RK4 stages take on the Taylor expansion of P (the construction of
+ *      McCorquodale and Colella for high-order subcycling):
+ *        P,  P + eta/2 P1,  P + eta/2 P1 + eta^2/4 P2,
+ *        P + eta P1 + eta^2/2 P2 + eta^3/4 P3
+ *      (on y' = lambda y these are the RK4 stage values of a step of eta
+ *      started from P); the fine ghost cells come from these coarse data by
+ *      the sub-cell interpolation, and the field from the composite moment
+ *      of them and the fine predictor (the synchronous constraint);
+ *   3. the coarse update takes, on every coarse-fine face, the mean over
+ *      the R fine faces of the fine fluxes averaged over the substeps
+ *      (stage-weighted), then covered coarse cells take the mean of their
+ *      fine cells.
+ * ------------------------------------------------------------------------ */
+
+/* field of the coarse level alone: velocity moment of the coarse cells, the
+ * periodic Poisson solve and field on the ncx-cell configuration mesh */
+static void coarse_level_field(const vpo_amr* c, const vpo_poisson* Pc, const double* fc, double* ac)
+{
+    const int ncx = c->ncx;
+    double* n = (double*)malloc(sizeof(double) * ncx);
+    double* phi = (double*)malloc(sizeof(double) * ncx);
+    double* E = (double*)malloc(sizeof(double) * ncx);
+    vpo_moment(ncx, c->ncv, c->dvc, fc, n);
+    for (int i = 0; i < ncx; ++i) n[i] = 1.0 - n[i];      /* rho = 1 - n */
+    vpo_poisson_solve(Pc, c->dxc, n, phi);
+    vpo_field(ncx, c->dxc, phi, E);
+    for (int i = 0; i < ncx; ++i) ac[i] = c->qm * E[i];
+    free(n); free(phi); free(E);
+}
+
+/* weights of the continuous extension of the classical RK4 step */
+void vpo_rk4_dense_weights(double theta, double* b)
+{
+    const double t2 = theta * theta, t3 = t2 * theta;
+    b[0] = theta - 1.5 * t2 + 2.0 * t3 / 3.0;
+    b[1] = t2 - 2.0 * t3 / 3.0;
+    b[2] = b[1];
+    b[3] = -0.5 * t2 + 2.0 * t3 / 3.0;
+}
+
+/* weights w_q of the coarse data of fine stage s (0..3) of the substep that
+ * starts at theta0 with length eta (in units of the coarse step):
+ * f_c = f_c^n + dt sum_q w_q K_q */
+void vpo_rk4_substage_weights(double theta0, double eta, int s, double* w)
+{
+    const double t = theta0, t2 = t * t;
+    const double d0[4] = {t - 1.5 * t2 + 2.0 * t2 * t / 3.0, t2 - 2.0 * t2 * t / 3.0, t2 - 2.0 * t2 * t / 3.0,
+                          -0.5 * t2 + 2.0 * t2 * t / 3.0};
+    const double d1[4] = {1.0 - 3.0 * t + 2.0 * t2, 2.0 * t - 2.0 * t2, 2.0 * t - 2.0 * t2, -t + 2.0 * t2};
+    const double d2[4] = {-3.0 + 4.0 * t, 2.0 - 4.0 * t, 2.0 - 4.0 * t, -1.0 + 4.0 * t};
+    const double d3[4] = {4.0, -4.0, -4.0, 4.0};
+    static const double c1[4] = {0.0, 0.5, 0.5, 1.0}, c2[4] = {0.0, 0.0, 0.25, 0.5}, c3[4] = {0.0, 0.0, 0.0, 0.25};
+    for (int q = 0; q < 4; ++q)
+        w[q] = d0[q] + c1[s] * eta * d1[q] + c2[s] * eta * eta * d2[q] + c3[s] * eta * eta * eta * d3[q];
+}
+
+void vpo_amr_subcycle_step(void* h, double* f_in, double* f_out, double dt)
+{
+    static const double alpha[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    vpo_amr* c = (vpo_amr*)h;
+    const int np = c->np, ncx = c->ncx, ncv = c->ncv, R = c->R;
+    const long Nc = (long)ncx * ncv, N = c->total;
+    const double hs = dt / R;
+    double* K[4];
+    for (int s = 0; s < 4; ++s) K[s] = (double*)malloc(sizeof(double) * Nc);
+    double* fs = (double*)malloc(sizeof(double) * N);
+    double* kf = (double*)calloc(N, sizeof(double));
+    double* a = (double*)malloc(sizeof(double) * (ncx + c->nfx));
+    double **Gx = (double**)malloc(sizeof(double*) * (np + 1)), **Gv = (double**)malloc(sizeof(double*) * (np + 1));
+    double **Ax = (double**)malloc(sizeof(double*) * (np + 1)), **Av = (double**)malloc(sizeof(double*) * (np + 1));
+    double **Sx = (double**)malloc(sizeof(double*) * (np + 1)), **Sv = (double**)malloc(sizeof(double*) * (np + 1));
+    for (int p = 0; p <= np; ++p) {
+        int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
+        Gx[p] = (double*)malloc(sizeof(double) * (size_t)(nx + 1) * nv);
+        Gv[p] = (double*)malloc(sizeof(double) * (size_t)nx * (nv + 1));
+        Ax[p] = (double*)calloc((size_t)(nx + 1) * nv, sizeof(double));
+        Av[p] = (double*)calloc((size_t)nx * (nv + 1), sizeof(double));
+        Sx[p] = (double*)calloc((size_t)(nx + 1) * nv, sizeof(double));
+        Sv[p] = (double*)calloc((size_t)nx * (nv + 1), sizeof(double));
+    }
+    vpo_poisson* Pc = vpo_poisson_new(ncx);
+
+    /* 1. the coarse level: one RK4 step of dt with its own field */
+    for (int s = 0; s < 4; ++s) {
+        for (long q = 0; q < Nc; ++q) fs[q] = f_in[q] + (s > 0 ? alpha[s] * dt * K[s - 1][q] : 0.0);
+        coarse_level_field(c, Pc, fs, a);
+        coarse_fluxes(c, fs, a, Gx[0], Gv[0]);
+        divergence(ncx, ncv, Gx[0], Gv[0], c->dxc, c->dvc, K[s]);
+        for (size_t q = 0; q < (size_t)(ncx + 1) * ncv; ++q) Ax[0][q] += bw[s] * Gx[0][q];
+        for (size_t q = 0; q < (size_t)ncx * (ncv + 1); ++q) Av[0][q] += bw[s] * Gv[0][q];
+    }
+
+    /* 2. the fine patches: R substeps of dt / R; f_out holds the fine state */
+    memcpy(f_out, f_in, sizeof(double) * N);
+    for (int m = 0; m < R; ++m) {
+        for (int p = 1; p <= np; ++p) {
+            int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
+            memset(Sx[p], 0, sizeof(double) * (size_t)(nx + 1) * nv);
+            memset(Sv[p], 0, sizeof(double) * (size_t)nx * (nv + 1));
+        }
+        for (int s = 0; s < 4; ++s) {
+            double b[4];
+            vpo_rk4_substage_weights((double)m / R, 1.0 / R, s, b);
+            for (long q = 0; q < Nc; ++q)
+                fs[q] = f_in[q] + dt * (b[0] * K[0][q] + b[1] * K[1][q] + b[2] * K[2][q] + b[3] * K[3][q]);
+            for (long q = Nc; q < N; ++q) fs[q] = f_out[q] + alpha[s] * hs * kf[q];
+            vpo_amr_constraints(h, fs, a, NULL);
+            for (int p = 1; p <= np; ++p) {
+                int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
+                fine_patch_fluxes(c, fs, a, p - 1, Gx[p], Gv[p]);
+                divergence(nx, nv, Gx[p], Gv[p], c->dxf, c->dvf, kf + c->off[p - 1]);
+                for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Sx[p][q] += bw[s] * Gx[p][q];
+                for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Sv[p][q] += bw[s] * Gv[p][q];
+            }
+        }
+        for (int p = 1; p <= np; ++p) {
+            int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
+            double* kp = kf + c->off[p - 1];
+            divergence(nx, nv, Sx[p], Sv[p], c->dxf, c->dvf, kp);
+            for (long q = 0; q < (long)nx * nv; ++q) f_out[c->off[p - 1] + q] += hs * kp[q];
+            for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[p][q] += Sx[p][q] / R;
+            for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[p][q] += Sv[p][q] / R;
+        }
+    }
+
+    /* 3. the coarse update with the time-averaged fine fluxes on the
+     * coarse-fine faces, then the average-down */
+    amr_update(c, f_in, Ax, Av, kf, f_out, dt, 0);
+
+    vpo_poisson_free(Pc);
+    for (int p = 0; p <= np; ++p) { free(Gx[p]); free(Gv[p]); free(Ax[p]); free(Av[p]); free(Sx[p]); free(Sv[p]); }
+    free(Gx); free(Gv); free(Ax); free(Av); free(Sx); free(Sv);
+    for (int s = 0; s < 4; ++s) free(K[s]);
+    free(fs); free(kf); free(a);
 }
