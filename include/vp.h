@@ -248,6 +248,33 @@ vp_status vp_rk4_step(const vp_plan* plan, void* f, double* a, double dt, void* 
                       hipStream_t stream);
 
 /*
+ * One subcycled step of a two-level plan: asynchronous time stepping, which
+ * section 5 names as future work (citing the high-order subcycling of
+ * McCorquodale and Colella); the reading taken here:
+ *   1. the coarse level takes one RK4 step of dt on its own, with the field
+ *      of its own velocity moment solved on the coarse configuration mesh
+ *      (covered coarse cells hold the mean of their fine cells);
+ *   2. the patches take R RK4 substeps of dt/R.  The coarse data of each
+ *      fine stage (the source of the fine ghost cells and of the uncovered
+ *      part of the composite moment) are the RK4 stage values taken on the
+ *      Taylor expansion, at the substep start, of the third-order continuous
+ *      extension of the coarse step; the field is the synchronous
+ *      constraint of those coarse data and the fine predictor;
+ *   3. the coarse cells next to coarse-fine faces take the fine fluxes
+ *      averaged over the R substeps, and covered coarse cells the mean of
+ *      their fine cells (Alg. msfduc).
+ *   f     hierarchy state (layout of vp_rk4_step), overwritten
+ *   a     in: any values (overwritten in the first stage); out: the
+ *         acceleration of the new state (the synchronous constraint)
+ *   dt    coarse time step (the patches take dt / R)
+ *   work  >= vp_workspace_bytes
+ * Errors: VP_EINVAL for a single-level plan, NULL pointers or a non-finite
+ * dt.  Enqueued on `stream`; host-side it only sequences launches.
+ */
+vp_status vp_amr_subcycle_step(const vp_plan* plan, void* f, double* a, double dt, void* work,
+                               hipStream_t stream);
+
+/*
  * As vp_rk4_step (single level), and also records the stage states
  * f(2), f(3), f(4) and the four stage accelerations in `stages`
  * (vp_stage_elems elements of the plan dtype; the accelerations are

@@ -497,6 +497,8 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     T.add(&M->d_rowptr_m, rowptr_m);
     T.add(&M->d_idx_m, idx_m);
     T.add(&M->d_w_m, w_m);
+    const std::vector<double> green_c = poisson_green_table(ncx);     // add() keeps a pointer until commit()
+    T.add(&M->d_green_c, green_c);
     VP_HIP(T.commit(&M->d_tables));
 
     // ---- workspace: acc, two predictors, accumulated face fluxes, reduction slots, n, E
@@ -512,6 +514,9 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->ws_n = o; o += align256((size_t)M->nfx * sizeof(double));
     M->ws_E = o; o += align256((size_t)M->nfx * sizeof(double));
     M->ws_fld = o; o += align256(((size_t)M->nfx + 2 * ((size_t)M->nfx / kFieldChunk + 1) + 64) * sizeof(double));
+    M->hist_stride = align256((size_t)ncx * ncv * sizeof(double)) / sizeof(double);
+    M->ws_hist = o; o += 5 * M->hist_stride * sizeof(double);
+    M->ws_nc = o; o += align256((size_t)ncx * sizeof(double));
     p->ws_total = o;
     p->state_elems = M->total;
     return VP_OK;
@@ -603,6 +608,104 @@ vp_status amr_end_sync(const vp_plan* p, void* f, double dt, void* work, hipStre
     S.dtv = dt / M.dvc;
     VP_HIP(timed(p, kTSync, stream, [&] { return launch_amr_sync(S, stream); }));
     return VP_OK;
+}
+
+// Substep weights: the coarse data of fine stage s of the substep
+// [theta0, theta0 + eta] (units of the coarse step) are f^n + dt sum_q w_q K_q.
+// They are the classical RK4 stage values taken on the Taylor expansion at
+// theta0 of the continuous extension P(theta) = f^n + dt sum_q b_q(theta) K_q
+// of the coarse step, b_1 = theta - 3/2 theta^2 + 2/3 theta^3,
+// b_2 = b_3 = theta^2 - 2/3 theta^3, b_4 = -1/2 theta^2 + 2/3 theta^3
+// (asynchronous stepping, future work of section 5, after McCorquodale and
+// Colella).  With P(theta0 + x) = d0 + d1 x + d2 x^2 + d3 x^3 the four stage
+// values are d0; d0 + eta/2 d1; d0 + eta/2 d1 + eta^2/2 d2;
+// d0 + eta d1 + eta^2 d2 + 3/2 eta^3 d3.
+static void substage_weights(double theta0, double eta, int s, double w[4])
+{
+    // b_q(theta) = sum_j p[q][j] theta^j
+    static const double p[4][4] = {{0.0, 1.0, -1.5, 2.0 / 3.0},
+                                   {0.0, 0.0, 1.0, -2.0 / 3.0},
+                                   {0.0, 0.0, 1.0, -2.0 / 3.0},
+                                   {0.0, 0.0, -0.5, 2.0 / 3.0}};
+    // stage s: coefficient of eta^k d_k
+    static const double g[4][4] = {{1.0, 0.0, 0.0, 0.0},
+                                   {1.0, 0.5, 0.0, 0.0},
+                                   {1.0, 0.5, 0.5, 0.0},
+                                   {1.0, 1.0, 1.0, 1.5}};
+    static const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+    for (int q = 0; q < 4; ++q) {
+        double sum = 0.0, e = 1.0;
+        for (int k = 0; k < 4; ++k) {
+            double dk = 0.0;             // Taylor coefficient k of b_q at theta0
+            for (int j = 3; j >= k; --j) dk = dk * theta0 + p[q][j] * binom[j][k];
+            sum += g[s][k] * e * dk;
+            e *= eta;
+        }
+        w[q] = sum;
+    }
+}
+
+vp_status amr_subcycle(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
+{
+    const AmrPlan& M = *p->amr;
+    const size_t nc = (size_t)M.ncx * M.ncv;
+    double* hist = reinterpret_cast<double*>(wsp(work, M.ws_hist));
+    double* H[5];
+    for (int q = 0; q < 5; ++q) H[q] = hist + q * M.hist_stride;
+    double* nmom = reinterpret_cast<double*>(wsp(work, M.ws_nc));
+    void* acc = wsp(work, p->ws_acc);
+    const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double cnext[4] = {0.5, 0.5, 1.0, 0.0};
+    const int kinds[4] = {kStage1, kStage23, kStage23, kStage4};
+    const int cap = 256 * 8;
+    auto range = [&](int kind, const AmrArgs& A, int t0, int t1) {
+        return launch_amr_stage(M.w, M.nt, kind, A, t0, t1, std::min(std::max(t1 - t0, 1), cap), stream);
+    };
+
+    // 1. the coarse level: one RK4 step of dt with the field of its own
+    // moment on the coarse configuration mesh; its stage states go to H[1..4]
+    VP_HIP(hipMemcpyAsync(H[0], f, nc * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    for (int s = 0; s < 4; ++s) {
+        const void* in = s == 0 ? f : static_cast<const void*>(H[s]);
+        VP_HIP(timed(p, kTMoment, stream, [&] {
+            return launch_moment_rows(VP_F64, in, M.ncx, M.ncv, M.dvc, nmom, stream);
+        }));
+        VP_HIP(timed(p, kTField, stream, [&] {
+            return launch_poisson1d(nullptr, 0, nmom, 1.0, M.ncx, M.dxc, p->pb.qm, M.d_green_c, p->gk, nullptr,
+                                    nullptr, nullptr, a, stream);
+        }));
+        AmrArgs A = stage_args(p, in, f, acc, H[s + 1], a, dt * b[s], dt * cnext[s], b[s], s == 0, work);
+        VP_HIP(timed(p, kTStage, stream, [&] {
+            hipError_t e = range(kinds[s], A, 0, M.ncoarse_tiles);
+            return e == hipSuccess ? range(kinds[s], A, M.face_tile_begin, M.ntiles) : e;
+        }));
+    }
+
+    // 2. the patches: R substeps of dt / R; the coarse part of each stage
+    // input holds that stage's coarse data
+    const double h = dt / M.R, eta = 1.0 / M.R;
+    for (int m = 0; m < M.R; ++m)
+        for (int s = 0; s < 4; ++s) {
+            void* in = s == 0 ? f : amr_stage_output(p, s - 1, f, work);
+            void* out = amr_stage_output(p, s, f, work);
+            double w[4];
+            substage_weights(m * eta, eta, s, w);
+            // in terms of the stored states: dt K_1 = 2 (H1 - H0), dt K_2 = 2 (H2 - H0),
+            // dt K_3 = H3 - H0, dt K_4 = 6 (H4 - H0) - 2 (H1 - H0) - 4 (H2 - H0) - 2 (H3 - H0)
+            const double c[4] = {2.0 * w[0] - 2.0 * w[3], 2.0 * w[1] - 4.0 * w[3], w[2] - 2.0 * w[3], 6.0 * w[3]};
+            VP_HIP(timed(p, kTOther, stream, [&] {
+                return launch_amr_substage(H[0], nc, M.hist_stride, c, static_cast<double*>(in), stream);
+            }));
+            if (vp_status st = constraint(p, static_cast<const double*>(in), a, work, stream)) return st;
+            AmrArgs A = stage_args(p, in, f, acc, out, a, h * b[s], h * cnext[s], b[s] / M.R, m == 0 && s == 0, work);
+            VP_HIP(timed(p, kTStage, stream, [&] { return range(kinds[s], A, M.ncoarse_tiles, M.face_tile_begin); }));
+        }
+
+    // 3. the coarse level's end state, the fine fluxes on coarse-fine faces
+    // (averaged over the substeps), the average-down, and the field
+    VP_HIP(hipMemcpyAsync(f, H[4], nc * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    if (vp_status st = amr_end_sync(p, f, dt, work, stream)) return st;
+    return constraint(p, static_cast<const double*>(f), a, work, stream);
 }
 
 }  // namespace vp

@@ -97,6 +97,8 @@ vp_status check_plan(const vp_plan* p)
 
 }  // namespace
 
+std::vector<double> poisson_green_table(int n) { return tridiag_green(n, kGreenTaps); }
+
 Rk4Setup1D rk4_setup_1d(const vp_plan* p, void* f, void* work, double dt, void* st_f)
 {
     Rk4Setup1D R{};
@@ -612,6 +614,15 @@ vp_status vp_rk4_step(const vp_plan* p, void* f, double* a, double dt, void* wor
     if (p->amr) return amr_rk4(p, f, a, dt, work, stream);
     if (p->p4) return p4_rk4(p, f, a, dt, work, stream);
     return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
+}
+
+vp_status vp_amr_subcycle_step(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!f || !a || !work) return fail(VP_EINVAL, "vp_amr_subcycle_step: NULL pointer");
+    if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_amr_subcycle_step: dt is not finite");
+    if (!p->amr) return fail(VP_EINVAL, "vp_amr_subcycle_step: needs a two-level plan");
+    return amr_subcycle(p, f, a, dt, work, stream);
 }
 
 vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, void* stages, void* work,

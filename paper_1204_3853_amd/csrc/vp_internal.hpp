@@ -259,6 +259,9 @@ struct AmrSyncArgs {
     double dtx, dtv;           // dt / dx_coarse, dt / dv_coarse
 };
 hipError_t launch_amr_sync(const AmrSyncArgs& a, hipStream_t stream);
+// subcycled steps: out = hist + sum_q c[q - 1] (hist[q stride] - hist), q = 1..4, over n elements
+hipError_t launch_amr_substage(const double* hist, size_t n, size_t stride, const double c[4], double* out,
+                               hipStream_t stream);
 
 }  // namespace vp
 
@@ -319,8 +322,12 @@ struct AmrPlan {
     int* d_idx_m = nullptr;
     double* d_w_m = nullptr;
     size_t ws_slots_m = 0;
-    // workspace offsets
+    // Poisson table of the coarse configuration mesh (subcycled steps)
+    double* d_green_c = nullptr;
+    // workspace offsets; ws_hist: the five coarse states of a subcycled
+    // step, hist_stride elements apart; ws_nc: the coarse moment
     size_t ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0, ws_fld = 0;
+    size_t ws_hist = 0, ws_nc = 0, hist_stride = 0;
 };
 }  // namespace vp
 
@@ -405,6 +412,10 @@ vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt
 void* amr_stage_output(const vp_plan* p, int s, void* f, void* work);
 vp_status amr_end_sync(const vp_plan* p, void* f, double dt, void* work, hipStream_t stream);
 vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx);
+// one subcycled step: the coarse level takes dt, the patches R substeps
+vp_status amr_subcycle(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
+// Green's-function table of the periodic fourth-order Poisson solve on n cells
+std::vector<double> poisson_green_table(int n);
 // 2D+2V host sequences (vp_4d.hip)
 vp_status p4_create(vp_plan* p, const vp_problem* pb);
 void p4_destroy(vp_plan* p);

@@ -497,6 +497,21 @@ hipError_t launch_amr_t(int kind, const AmrArgs& a, int t0, int t1, int grid, hi
 
 }  // namespace
 
+// coarse data of one fine stage of a subcycled step, from the coarse step's
+// states h_0 = f^n, h_1 .. h_3 (the stage predictors) and h_4 (the end of
+// the step), each `stride` elements apart: out = h_0 + sum_q c_q (h_q - h_0)
+__global__ __launch_bounds__(256) void k_amr_substage(const double* __restrict__ h, size_t n, size_t stride,
+                                                     double c1, double c2, double c3, double c4,
+                                                     double* __restrict__ out)
+{
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (size_t)gridDim.x * 256) {
+        const double b = h[q];
+        const double d1 = h[stride + q] - b, d2 = h[2 * stride + q] - b;
+        const double d3 = h[3 * stride + q] - b, d4 = h[4 * stride + q] - b;
+        out[q] = b + (c1 * d1 + c2 * d2 + c3 * d3 + c4 * d4);
+    }
+}
+
 hipError_t launch_amr_stage(int w, int nt, int kind, const AmrArgs& a, int t_begin, int t_end, int grid,
                             hipStream_t stream)
 {
@@ -536,6 +551,16 @@ hipError_t launch_amr_inject(const double* E, int ncx, int R, double qm, double*
 {
     const int n = ncx + ncx * R;
     hipLaunchKernelGGL(k_amr_inject, dim3((n + 255) / 256), dim3(256), 0, stream, E, ncx, R, qm, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_substage(const double* hist, size_t n, size_t stride, const double c[4], double* out,
+                               hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_amr_substage, dim3(grid), dim3(256), 0, stream, hist, n, stride, c[0], c[1], c[2], c[3],
+                       out);
     return hipGetLastError();
 }
 

@@ -82,6 +82,7 @@ SIGNATURES = {
     "vp_poisson_periodic": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "vp_inject_field": (ctypes.c_int, [_P, _P, _P, _P]),
     "vp_rk4_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P]),
+    "vp_amr_subcycle_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P]),
     "vp_rk4_step_record": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P]),
     "vp_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P, _P]),
     "vp_field_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
@@ -372,6 +373,16 @@ def rk4_step(plan, f, a, dt):
     plan._state(f, "f")
     plan._cfg(a, "a", plan.field_elems)
     _check(lib().vp_rk4_step(plan.h, _ptr(f), _ptr(a), ctypes.c_double(dt), _ptr(plan.work), _stream()))
+    return f, a
+
+
+def amr_subcycle_step(plan, f, a, dt):
+    """One subcycled step of a two-level plan in place (the coarse level
+    takes dt, the patches R substeps of dt / R); a out: the field of the new
+    state."""
+    plan._state(f, "f")
+    plan._cfg(a, "a", plan.field_elems)
+    _check(lib().vp_amr_subcycle_step(plan.h, _ptr(f), _ptr(a), ctypes.c_double(dt), _ptr(plan.work), _stream()))
     return f, a
 
 

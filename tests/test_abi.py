@@ -50,6 +50,10 @@ def test_null_plan_is_rejected_without_gpu(libvp):
     libvp.vp_last_error.restype = ctypes.c_char_p
     assert libvp.vp_rhs(None, None, None, None, None) == 1   # VP_EINVAL
     assert b"NULL" in libvp.vp_last_error()
+    libvp.vp_amr_subcycle_step.restype = ctypes.c_int
+    libvp.vp_amr_subcycle_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_void_p]
+    assert libvp.vp_amr_subcycle_step(None, None, None, 0.1, None, None) == 1
 
 
 def test_amr_run_parameters_rejected_without_gpu(libvp):
