@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--regrid-only", action="store_true", help="run only the regridding section (for profiling)")
     ap.add_argument("--no-amr-run", action="store_true")
     ap.add_argument("--no-species", action="store_true")
+    ap.add_argument("--no-subcycle", action="store_true")
+    ap.add_argument("--subcycle-only", action="store_true", help="run only the subcycled-stepping section")
     ap.add_argument("--species-only", action="store_true", help="run only the two-species section")
     ap.add_argument("--amr-run-only", action="store_true", help="run only the adaptive bump-on-tail section")
     ap.add_argument("--amr-run-t", type=float, default=22.5, help="end time of the adaptive bump-on-tail runs")
@@ -295,6 +297,66 @@ def amr_bench(steps=100, warmup=3):
                              "sub_patch_over_mask": round(red["sub_patch"] / red["mask"], 3)}}
 
 
+def subcycle_bench(steps=40, warmup=3, cfl=0.5):
+    """Subcycled against synchronous two-level stepping, each at its largest
+    CFL-0.5 step, on two ratio-4 hierarchies over a 512 x 512 coarse Landau
+    level (FP64): the 40 seeded patches inside |v| < 3, and one patch over
+    the high-velocity band v in [4, 7.5) (every coarse column but the last).
+    Synchronous: dt = cfl / max(nu_coarse, nu_fine).  Subcycled: the coarse
+    step dt_c = cfl min(1 / nu_coarse, R / nu_fine) with R fine substeps.
+    Reported: ms per step and simulated time per wall-clock second."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+    ncx = ncv = 512
+    R = 4
+    dxc, dvc = 4 * math.pi / ncx, 16.0 / ncv
+    layouts = {
+        "core_40_patches_v_lt_3": I.amr_boxes(0),
+        "band_v_4_to_7.5": [{"level": 1, "lo": [0, 12 * 32 * R], "hi": [(ncx - 1) * R - 1, int(15.5 * 32) * R - 1]}],
+    }
+    out = {}
+    for name, boxes in layouts.items():
+        f0, veq_c, veq_f = I.amr_landau(boxes)
+        plan = vp.Plan(vp.two_level_spec(ncx, ncv, 4 * math.pi, -8.0, 8.0, -1.0, R, veq_c, veq_f), boxes=boxes)
+        f = torch.tensor(f0, dtype=torch.float64, device="cuda")
+        a = vp.field_of(plan, f)
+        an = a.cpu().numpy()
+        dxf, dvf = dxc / R, dvc / R
+        nu_c = 8.0 / dxc + abs(an[:ncx]).max() / dvc
+        vmax_f = max(max(abs(-8.0 + b["lo"][1] * dvf), abs(-8.0 + (b["hi"][1] + 1) * dvf)) for b in boxes)
+        nu_f = vmax_f / dxf + abs(an[ncx:]).max() / dvf
+        dt_sync = cfl / max(nu_c, nu_f)
+        dt_sub = cfl * min(1.0 / nu_c, R / nu_f)
+
+        def timed(fn, dt):
+            g, ga = f.clone(), a.clone()
+            for _ in range(warmup):
+                fn(plan, g, ga, dt)
+            st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            st.record()
+            for _ in range(steps):
+                fn(plan, g, ga, dt)
+            sp.record()
+            torch.cuda.synchronize()
+            return st.elapsed_time(sp) / steps
+
+        ms_sync = timed(vp.rk4_step, dt_sync)
+        ms_sub = timed(vp.amr_subcycle_step, dt_sub)
+        sim_sync = dt_sync / (ms_sync * 1e-3)
+        sim_sub = dt_sub / (ms_sub * 1e-3)
+        out[name] = {"coarse_cells": ncx * ncv, "fine_cells": plan.state_elems - ncx * ncv,
+                     "dt_sync": round(dt_sync, 7), "dt_subcycled": round(dt_sub, 7),
+                     "ms_per_step_sync": round(ms_sync, 4), "ms_per_step_subcycled": round(ms_sub, 4),
+                     "sim_time_per_s_sync": round(sim_sync, 3), "sim_time_per_s_subcycled": round(sim_sub, 3),
+                     "subcycled_over_sync": round(sim_sub / sim_sync, 3)}
+        del plan
+    out["workload"] = ("Landau 1D+1V two-level, coarse 512x512, ratio 4, FP64: subcycled (coarse dt, 4 fine "
+                       "substeps) vs synchronous steps, each at its largest CFL-0.5 step")
+    return out
+
+
 def regrid_bench(reps=50):
     """Regridding (section 3): the tagging kernel on the 4096 x 4096
     two-stream level (8 B read + 1 B written per cell) and on level 0 of the
@@ -532,6 +594,9 @@ def main():
     if args.amr_run_only:
         print(json.dumps({"amr_run": amr_run_bench(args.amr_run_t)}), flush=True)
         return
+    if args.subcycle_only:
+        print(json.dumps({"subcycle": subcycle_bench()}), flush=True)
+        return
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
     n = args.n
     p = I.two_stream(n, n)
@@ -596,6 +661,7 @@ def main():
     regrid = None if args.no_regrid else regrid_bench()
     amr_run = None if args.no_amr_run else amr_run_bench(args.amr_run_t)
     species = None if args.no_species else species_bench(steps=args.steps, warmup=args.warmup)
+    subcycle = None if args.no_subcycle else subcycle_bench()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -627,6 +693,7 @@ def main():
         "regrid": regrid,
         "amr_run": amr_run,
         "species": species,
+        "subcycle": subcycle,
     }
     print(json.dumps(out), flush=True)
 

@@ -109,3 +109,20 @@ def test_errors(vp):
     a2 = torch.zeros(plan2.field_elems, dtype=torch.float64, device="cuda")
     with pytest.raises(vp.VPError, match="finite"):
         vp.amr_subcycle_step(plan2, f2, a2, float("nan"))
+
+
+def test_high_velocity_band_layout(vp, oracle):
+    """One patch of 2044 x 448 fine cells over v in [4, 7.5) (the layout the
+    subcycling benchmark also times): synchronous and subcycled steps."""
+    R = 4
+    boxes = [{"level": 1, "lo": [0, 12 * 32 * R], "hi": [511 * R - 1, 496 * R - 1]}]
+    c = Case(vp, oracle, boxes, 512, 512, R, eps=0.01, k=0.5, noise=0.0)
+    f = c.gpu(c.f0)
+    a = vp.field_of(c.plan, f)
+    vp.rk4_step(c.plan, f, a, c.dt)
+    torch.cuda.synchronize()
+    cmp(f, c.o.step(c.f0, c.dt), rel_tol(), "synchronous step, band layout")
+    f = c.gpu(c.f0)
+    vp.amr_subcycle_step(c.plan, f, a, 2 * c.dt)
+    torch.cuda.synchronize()
+    cmp(f, c.o.subcycle_step(c.f0, 2 * c.dt), rel_tol(), "subcycled step, band layout")
