@@ -304,7 +304,8 @@ def subcycle_bench(steps=40, warmup=3, cfl=0.5):
     the high-velocity band v in [4, 7.5) (every coarse column but the last).
     Synchronous: dt = cfl / max(nu_coarse, nu_fine).  Subcycled: the coarse
     step dt_c = cfl min(1 / nu_coarse, R / nu_fine) with R fine substeps.
-    Reported: ms per step and simulated time per wall-clock second."""
+    Reported: ms per step (the faster of eager launches and a replayed HIP
+    graph) and simulated time per wall-clock second."""
     import torch
 
     import vp_inputs as I
@@ -329,6 +330,7 @@ def subcycle_bench(steps=40, warmup=3, cfl=0.5):
         nu_f = vmax_f / dxf + abs(an[ncx:]).max() / dvf
         dt_sync = cfl / max(nu_c, nu_f)
         dt_sub = cfl * min(1.0 / nu_c, R / nu_f)
+        _, shape, _ = plan.autotune(f.clone(), a.clone(), dt_sync, reps=5)     # tile shape for both
 
         def timed(fn, dt):
             g, ga = f.clone(), a.clone()
@@ -342,13 +344,38 @@ def subcycle_bench(steps=40, warmup=3, cfl=0.5):
             torch.cuda.synchronize()
             return st.elapsed_time(sp) / steps
 
-        ms_sync = timed(vp.rk4_step, dt_sync)
-        ms_sub = timed(vp.amr_subcycle_step, dt_sub)
+        def timed_graph(fn, dt):
+            g, ga = f.clone(), a.clone()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                fn(plan, g, ga, dt)
+            torch.cuda.current_stream().wait_stream(s)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                fn(plan, g, ga, dt)
+            for _ in range(warmup):
+                graph.replay()
+            st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            st.record()
+            for _ in range(steps):
+                graph.replay()
+            sp.record()
+            torch.cuda.synchronize()
+            return st.elapsed_time(sp) / steps
+
+        ms_sync = min(timed(vp.rk4_step, dt_sync), timed_graph(vp.rk4_step, dt_sync))
+        ms_sub_eager = timed(vp.amr_subcycle_step, dt_sub)
+        ms_sub_graph = timed_graph(vp.amr_subcycle_step, dt_sub)
+        ms_sub = min(ms_sub_eager, ms_sub_graph)
         sim_sync = dt_sync / (ms_sync * 1e-3)
         sim_sub = dt_sub / (ms_sub * 1e-3)
         out[name] = {"coarse_cells": ncx * ncv, "fine_cells": plan.state_elems - ncx * ncv,
+                     "tuned_shape": {"threads": shape[0], "cells_per_thread": shape[1], "rows": shape[2]},
                      "dt_sync": round(dt_sync, 7), "dt_subcycled": round(dt_sub, 7),
                      "ms_per_step_sync": round(ms_sync, 4), "ms_per_step_subcycled": round(ms_sub, 4),
+                     "ms_per_step_subcycled_eager": round(ms_sub_eager, 4),
+                     "ms_per_step_subcycled_graph": round(ms_sub_graph, 4),
                      "sim_time_per_s_sync": round(sim_sync, 3), "sim_time_per_s_subcycled": round(sim_sub, 3),
                      "subcycled_over_sync": round(sim_sub / sim_sync, 3)}
         del plan

@@ -126,3 +126,28 @@ def test_high_velocity_band_layout(vp, oracle):
     vp.amr_subcycle_step(c.plan, f, a, 2 * c.dt)
     torch.cuda.synchronize()
     cmp(f, c.o.subcycle_step(c.f0, 2 * c.dt), rel_tol(), "subcycled step, band layout")
+
+
+def test_graph_replay_matches_eager(vp, oracle):
+    """The subcycled step captured in a HIP graph and replayed gives the
+    eager results, replay after replay (with eager work in between)."""
+    L = LAYOUTS["small"]
+    c = Case(vp, oracle, L["boxes"], L["ncx"], L["ncv"], L["R"])
+    f_e = c.gpu(c.f0)
+    a_e = vp.field_of(c.plan, f_e)
+    f_g, a_g = f_e.clone(), a_e.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        vp.amr_subcycle_step(c.plan, f_g, a_g, 4 * c.dt)
+    torch.cuda.current_stream().wait_stream(s)
+    vp.amr_subcycle_step(c.plan, f_e, a_e, 4 * c.dt)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        vp.amr_subcycle_step(c.plan, f_g, a_g, 4 * c.dt)
+    for r in range(3):
+        g.replay()
+        vp.amr_subcycle_step(c.plan, f_e, a_e, 4 * c.dt)
+        torch.cuda.synchronize()
+        assert torch.equal(f_g, f_e), f"replay {r}"
+        assert torch.equal(a_g, a_e), f"replay {r}"
