@@ -268,6 +268,9 @@ vp_status vp_rk4_step(const vp_plan* plan, void* f, double* a, double dt, void* 
  *         acceleration of the new state (the synchronous constraint)
  *   dt    coarse time step (the patches take dt / R)
  *   work  >= vp_workspace_bytes
+ * The plan's reduction algorithm (vp_reduction_set) applies to every fine
+ * stage's composite moment; the launch mode does not apply (the coarse and
+ * the fine tile ranges are each one persistent launch).
  * Errors: VP_EINVAL for a single-level plan, NULL pointers or a non-finite
  * dt.  Enqueued on `stream`; host-side it only sequences launches.
  */

@@ -151,3 +151,19 @@ def test_graph_replay_matches_eager(vp, oracle):
         torch.cuda.synchronize()
         assert torch.equal(f_g, f_e), f"replay {r}"
         assert torch.equal(a_g, a_e), f"replay {r}"
+
+
+def test_subcycle_with_mask_reduction(vp, oracle):
+    """The fine stages' composite moment by the Mask reduction gives the
+    same step (both reductions are exact sums of the same cells)."""
+    L = LAYOUTS["ratio2_odd"]
+    c = Case(vp, oracle, L["boxes"], L["ncx"], L["ncv"], L["R"])
+    c.plan.set_reduction(vp.REDUCE_MASK)
+    try:
+        f = c.gpu(c.f0)
+        a = torch.zeros(c.plan.field_elems, dtype=torch.float64, device="cuda")
+        vp.amr_subcycle_step(c.plan, f, a, 2 * c.dt)
+        torch.cuda.synchronize()
+        cmp(f, c.o.subcycle_step(c.f0, 2 * c.dt), rel_tol(), "subcycled step, Mask reduction")
+    finally:
+        c.plan.set_reduction(vp.REDUCE_SUBPATCH)
