@@ -49,7 +49,7 @@ typedef enum vp_status {
     VP_EINVAL = 1,     /* bad argument (null pointer, non-positive size, bad box) */
     VP_ESHAPE = 2,     /* sizes inconsistent with the plan                         */
     VP_EDTYPE = 3,     /* unsupported element type for this call                    */
-    VP_ENOTSUP = 4,    /* valid request outside what this build supports            */
+    VP_ENOTSUP = 4,    /* valid request outside what this library supports          */
     VP_EHIP = 5,       /* a HIP runtime call failed                                 */
     VP_ENOMEM = 6      /* plan tables could not be allocated                        */
 } vp_status;
