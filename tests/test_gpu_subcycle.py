@@ -6,7 +6,9 @@ extension of the coarse RK4 step, then refluxing and the average-down
 
 Layouts: the small ratio-4 hierarchy (three patches, one across the periodic
 x boundary), the ratio-2 hierarchy with an odd coarse velocity count, no
-patches at all, and the 512 x 512 ratio-4 hierarchy with 40 patches.
+patches at all, the 512 x 512 ratio-4 hierarchy with 40 patches and one with
+a single large patch over a high-velocity band; graph replay, the Mask
+reduction, and the Landau damping rate of a GPU run.
 """
 import math
 
@@ -167,3 +169,36 @@ def test_subcycle_with_mask_reduction(vp, oracle):
         cmp(f, c.o.subcycle_step(c.f0, 2 * c.dt), rel_tol(), "subcycled step, Mask reduction")
     finally:
         c.plan.set_reduction(vp.REDUCE_SUBPATCH)
+
+
+def test_subcycled_landau_damping_rate_on_gpu(vp):
+    """Physics of the GPU path alone: 64 x 128 coarse cells with a ratio-2
+    patch over v in [1, 3.625) (every coarse column but the last), subcycled
+    to t = 30: the field decays at the Landau rate (the root of the
+    dispersion relation for k = 0.5)."""
+    from test_oracle_pins import landau_fit, landau_root
+    w = landau_root()
+    ncx, ncv, R = 64, 128, 2
+    boxes = [{"level": 1, "lo": [0, 72 * R], "hi": [63 * R - 1, 93 * R - 1]}]
+    f0, veq_c, veq_f = I._amr_state(I.maxwellian, 0.0, 4 * math.pi, -8.0, 8.0, 0.01, 0.5, boxes, (ncx, ncv), R)
+    plan = vp.Plan(vp.two_level_spec(ncx, ncv, 4 * math.pi, -8.0, 8.0, -1.0, R, veq_c, veq_f), boxes=boxes)
+    a = torch.zeros(plan.field_elems, dtype=torch.float64, device="cuda")
+
+    class P:
+        dx = 4 * math.pi / (ncx * R)
+
+        @staticmethod
+        def initial_state():
+            return torch.tensor(f0, dtype=torch.float64, device="cuda")
+
+    def step(g, dt):
+        vp.amr_subcycle_step(plan, g, a, dt)
+        return g
+
+    def field(g):
+        return -vp.field_of(plan, g)[ncx:].cpu().numpy()          # E = a / (q/m), q/m = -1
+
+    dt = 0.5 / (8.0 / (4 * math.pi / ncx) + 0.01 / (16.0 / ncv))
+    gamma, omega = landau_fit(step, field, P, dt)
+    assert abs(gamma - w.imag) < 0.003, gamma
+    assert abs(omega - w.real) < 0.006, omega
