@@ -94,6 +94,8 @@ def _declare_extra(L):
         "vpo_amr_fill_ghosts": (None, [_V, _D, _I, _D]),
         "vpo_amr_rk4_step": (None, [_V, _D, _D, _F]),
         "vpo_amr_subcycle_step": (None, [_V, _D, _D, _F]),
+        "vpo4_tag": (None, [_V, _D, _F, ctypes.c_void_p, _D]),
+        "vpo4_tag_value": (_F, [_V, _D, _I, _I, _I, _I]),
         "vpo_rk4_dense_weights": (None, [_F, _D]),
         "vpo_rk4_substage_weights": (None, [_F, _F, _I, _D]),
         "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
@@ -551,6 +553,20 @@ class Oracle4D:
         if getattr(self, "h", None) and _lib is not None:
             _lib.vpo4_ctx_free(self.h)
             self.h = None
+
+    def tag(self, f, tol):
+        """(tags uint8, delta1 f + delta2 f) of every cell, the criterion of
+        section 3 summed over x, y, vx, vy."""
+        f = _f64(f)
+        tags = np.empty(f.size, dtype=np.uint8)
+        vals = np.empty(f.size)
+        lib().vpo4_tag(self.h, _p(f), tol, tags.ctypes.data_as(ctypes.c_void_p), _p(vals))
+        shape = (self.nx, self.ny, self.nvx, self.nvy)
+        return tags.reshape(shape), vals.reshape(shape)
+
+    def tag_value(self, f, i, j, k, l):
+        f = _f64(f)
+        return lib().vpo4_tag_value(self.h, _p(f), i, j, k, l)
 
     def moment(self, f):
         f = _f64(f)

@@ -83,6 +83,9 @@ void vpo4_constraints(void* h, double* f, double* a, double* phi_out, double* E_
 void vpo4_rhs(void* h, double* f, double* a, double* k);
 void vpo4_rk4_step(void* h, double* f_in, double* f_out, double dt);
 void vpo4_rk4_step_fixed_a(void* h, double* f_in, double* f_out, double* a, double dt);
+/* refinement criterion on a 2D+2V mesh (sums over x, y, vx, vy) */
+double vpo4_tag_value(void* h, double* f, int i, int j, int k, int l);
+void vpo4_tag(void* h, double* f, double tol, unsigned char* tags, double* values);
 void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt);
 /* subcycled two-level step: the coarse level takes dt with its own field,
  * the patches R substeps of dt/R (continuous extension of the coarse step

@@ -290,3 +290,42 @@ void vpo4_rk4_step_fixed_a(void* h, double* f_in, double* f_out, double* a, doub
 {
     rk4(h, f_in, f_out, dt, a);
 }
+
+/* Refinement criterion of section 3 (mesh refinement criteria) on a 2D+2V
+ * mesh: delta1 f + delta2 f with the sums over the four directions x, y,
+ * vx, vy (the printed criterion sums over the phase-space directions),
+ *   delta1 f = [ 1/2 sum_d h_d (f(+e_d) - f(-e_d))^2 ]^(1/2),
+ *   delta2 f = 1/2 sum_d h_d^2 |f(+e_d) - 2 f + f(-e_d)|,
+ * x and y periodic, velocity ghosts the equilibrium.  Terms are added in
+ * the order x, y, vx, vy. */
+double vpo4_tag_value(void* h, double* f, int i, int j, int k, int l)
+{
+    const vpo4* c = (const vpo4*)h;
+    const double hd[4] = {c->dx, c->dy, c->dvx, c->dvy};
+    const int e[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    const double u = at(c, f, i, j, k, l);
+    double s1 = 0.0, s2 = 0.0;
+    for (int d = 0; d < 4; ++d) {
+        const double p = at(c, f, i + e[d][0], j + e[d][1], k + e[d][2], l + e[d][3]);
+        const double m = at(c, f, i - e[d][0], j - e[d][1], k - e[d][2], l - e[d][3]);
+        const double g = p - m, s = (p - 2.0 * u) + m;
+        s1 = d == 0 ? hd[d] * (g * g) : s1 + hd[d] * (g * g);
+        s2 = d == 0 ? (hd[d] * hd[d]) * fabs(s) : s2 + (hd[d] * hd[d]) * fabs(s);
+    }
+    return sqrt(0.5 * s1) + 0.5 * s2;
+}
+
+void vpo4_tag(void* h, double* f, double tol, unsigned char* tags, double* values)
+{
+    const vpo4* c = (const vpo4*)h;
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < c->nx; ++i)
+        for (int j = 0; j < c->ny; ++j)
+            for (int k = 0; k < c->nvx; ++k)
+                for (int l = 0; l < c->nvy; ++l) {
+                    const size_t q = (((size_t)i * c->ny + j) * c->nvx + k) * c->nvy + l;
+                    const double v = vpo4_tag_value(h, f, i, j, k, l);
+                    tags[q] = v > tol ? 1 : 0;
+                    if (values) values[q] = v;
+                }
+}
