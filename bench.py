@@ -417,6 +417,18 @@ def regrid_bench(reps=50):
                        "achieved_GBs": round(9 * cells / (ms * 1e-3) / 1e9, 1)}
     del plan1, f1, tags1
 
+    # the criterion summed over x, y, vx, vy on the 64^4 2D+2V mesh
+    p4 = I.Problem2D(64, 64, 64, 64)
+    plan4 = vp.Plan(p4)
+    f4 = torch.tensor(p4.initial_state().ravel(), dtype=torch.float64, device="cuda")
+    tags4 = torch.empty(64 ** 4, dtype=torch.uint8, device="cuda")
+    ms = ev_time(lambda: vp._check(vp.lib().vp_tag_cells(plan4.h, vp._ptr(f4), vp.ctypes.c_double(1e-4),
+                                                         vp._ptr(tags4), None, vp._stream())), reps)
+    cells = 64 ** 4
+    out["tag_2d2v_64"] = {"us": round(ms * 1e3, 2), "algorithmic_bytes": 9 * cells,
+                          "achieved_GBs": round(9 * cells / (ms * 1e-3) / 1e9, 1)}
+    del plan4, f4, tags4
+
     boxes = I.amr_boxes(0)
     f, veq_c, veq_f = I.amr_landau(boxes)
     spec = vp.two_level_spec(512, 512, 4 * math.pi, -8.0, 8.0, -1.0, 4, veq_c, veq_f)

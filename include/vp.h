@@ -384,13 +384,16 @@ vp_status vp_timing_read(vp_plan* plan, double* ms, int64_t* counts, int32_t ncl
  *   delta1 f = [ 1/2 sum_d h_d (f(+e_d) - f(-e_d))^2 ]^(1/2),
  *   delta2 f = 1/2 sum_d h_d^2 |f(+e_d) - 2 f + f(-e_d)|,
  * summed over d = x, v (as printed), x periodic, velocity ghosts the
- * equilibrium.  The value is formed in a fixed order without fused
- * multiply-adds and with a correctly rounded square root, so that it is
- * reproducible bit for bit.
+ * equilibrium; on a 2D+2V plan over d = x, y, vx, vy (the sums run over
+ * the phase-space directions), x and y periodic, velocity ghosts the
+ * equilibrium product.  The value is formed in a fixed order (directions
+ * in the order listed) without fused multiply-adds and with a correctly
+ * rounded square root, so that it is reproducible bit for bit.
  *   f       the state (level 0 is read)
- *   tags    output, device uint8 [ncx][ncv]: 1 where tagged, else 0
- *   values  output or NULL: delta1 f + delta2 f per level-0 cell (double)
- * Enqueued on `stream`; VP_ENOTSUP for 2D+2V or FP32 plans.
+ *   tags    output, device uint8 [ncx][ncv] (2D+2V: [nx][ny][nvx][nvy]):
+ *           1 where tagged, else 0
+ *   values  output or NULL: delta1 f + delta2 f per cell (double)
+ * Enqueued on `stream`; VP_ENOTSUP for FP32 plans.
  */
 vp_status vp_tag_cells(const vp_plan* plan, const void* f, double tol, uint8_t* tags, double* values,
                        hipStream_t stream);

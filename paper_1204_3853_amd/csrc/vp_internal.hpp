@@ -259,6 +259,18 @@ struct AmrSyncArgs {
     double dtx, dtv;           // dt / dx_coarse, dt / dv_coarse
 };
 hipError_t launch_amr_sync(const AmrSyncArgs& a, hipStream_t stream);
+// refinement criterion on a 2D+2V mesh (vp_kernels_regrid.hip)
+struct Tag4DArgs {
+    const double* f;           // [x][y][vx][vy]
+    int nx, ny, nvx, nvy;
+    const double* gx;          // vx equilibrium factors with ghosts (nvx + 4)
+    const double* gy;          // vy equilibrium factors with ghosts (nvy + 4)
+    double h[4];               // dx, dy, dvx, dvy
+    double tol;
+    unsigned char* tags;
+    double* values;            // or null
+};
+hipError_t launch_tag4d(const Tag4DArgs& a, hipStream_t stream);
 // subcycled steps: out = hist + sum_q c[q - 1] (hist[q stride] - hist), q = 1..4, over n elements
 hipError_t launch_amr_substage(const double* hist, size_t n, size_t stride, const double c[4], double* out,
                                hipStream_t stream);

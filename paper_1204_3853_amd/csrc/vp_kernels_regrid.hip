@@ -153,6 +153,70 @@ __global__ __launch_bounds__(256) void k_tag(const double* __restrict__ f, int n
     if (values) values[e] = t;
 }
 
+// The criterion on a 2D+2V mesh [x][y][vx][vy]: the sums over the four
+// directions in the order x, y, vx, vy, each term formed as in tag_from
+// (no fused multiply-adds, correctly rounded square root).  Block row
+// blockIdx.y is a run of kTag4DRows configuration cells along y at one x;
+// its threads cover 256 consecutive cells of the velocity plane and march
+// along y, so every neighbour load (the same plane position in the x and y
+// neighbour planes, vx +- 1 rows, vy +- 1 lanes) is coalesced and the y
+// neighbours are reused from registers.  Index arithmetic is 32-bit (the plan limits
+// keep every element offset below 2^31).
+__device__ __forceinline__ double tag_term(double p, double m, double u, double h, double& s2)
+{
+#pragma clang fp contract(off)
+    const double g = p - m, sd = (p - 2.0 * u) + m;
+    s2 = (h * h) * __builtin_fabs(sd);
+    return h * (g * g);
+}
+
+constexpr int kTag4DRows = 8;     // configuration cells along y per thread
+
+__global__ __launch_bounds__(256) void k_tag4d(Tag4DArgs a)
+{
+#pragma clang fp contract(off)
+    const int plane = a.nvx * a.nvy;
+    const int q = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (q >= plane) return;
+    const int nyb = (a.ny + kTag4DRows - 1) / kTag4DRows;
+    const int by = (int)blockIdx.y;
+    const int i = by / nyb, j0 = (by - (by / nyb) * nyb) * kTag4DRows;
+    const int j1 = min(j0 + kTag4DRows, a.ny);
+    const int k = q / a.nvy, l = q - (q / a.nvy) * a.nvy;
+    const int ip = i + 1 == a.nx ? 0 : i + 1, im = i == 0 ? a.nx - 1 : i - 1;
+    const double* f = a.f;
+    const double gyl = a.gy[l + 2], gxk = a.gx[k + 2];
+    const double gvxp = a.gx[k + 3] * gyl, gvxm = a.gx[k + 1] * gyl;
+    const double gvyp = gxk * a.gy[l + 3], gvym = gxk * a.gy[l + 1];
+    // march along y, the y neighbours rolling through registers
+    double ym = f[(i * a.ny + (j0 == 0 ? a.ny - 1 : j0 - 1)) * plane + q];
+    double u = f[(i * a.ny + j0) * plane + q];
+    for (int j = j0; j < j1; ++j) {
+        const int jp = j + 1 == a.ny ? 0 : j + 1;
+        const int base = (i * a.ny + j) * plane;
+        const double yp = f[(i * a.ny + jp) * plane + q];
+        const double xp = f[(ip * a.ny + j) * plane + q], xm = f[(im * a.ny + j) * plane + q];
+        const double vxp = k + 1 < a.nvx ? f[base + q + a.nvy] : gvxp;
+        const double vxm = k > 0 ? f[base + q - a.nvy] : gvxm;
+        const double vyp = l + 1 < a.nvy ? f[base + q + 1] : gvyp;
+        const double vym = l > 0 ? f[base + q - 1] : gvym;
+        double t2, s1, s2;
+        s1 = tag_term(xp, xm, u, a.h[0], t2);
+        s2 = t2;
+        s1 = s1 + tag_term(yp, ym, u, a.h[1], t2);
+        s2 = s2 + t2;
+        s1 = s1 + tag_term(vxp, vxm, u, a.h[2], t2);
+        s2 = s2 + t2;
+        s1 = s1 + tag_term(vyp, vym, u, a.h[3], t2);
+        s2 = s2 + t2;
+        const double v = __builtin_sqrt(0.5 * s1) + 0.5 * s2;
+        a.tags[base + q] = v > a.tol ? 1 : 0;
+        if (a.values) a.values[base + q] = v;
+        ym = u;
+        u = yp;
+    }
+}
+
 // R fine cell averages of the middle of u[0..4] (eqs. aux1, aux2,
 // interp_r_avg; B^(0) = 2 D_i - D_{i+1}, the value the definition gives);
 // every candidate renormalised to the coarse average, then combined with
@@ -246,6 +310,18 @@ __global__ __launch_bounds__(256) void k_copy_old(const double* __restrict__ fol
 }
 
 }  // namespace
+
+hipError_t launch_tag4d(const Tag4DArgs& a, hipStream_t stream)
+{
+    const long long n = (long long)a.nx * a.ny * a.nvx * a.nvy;
+    if (n == 0) return hipSuccess;
+    if (n >= (1ll << 31) || a.nx * a.ny > 65535) return hipErrorInvalidValue;
+    const int plane = a.nvx * a.nvy;
+    const int nyb = (a.ny + kTag4DRows - 1) / kTag4DRows;
+    hipLaunchKernelGGL(k_tag4d, dim3((unsigned)((plane + 255) / 256), (unsigned)(a.nx * nyb)), dim3(256), 0, stream,
+                       a);
+    return hipGetLastError();
+}
 
 hipError_t launch_tag(const double* f, int nx, int nv, const double* vg, double dx, double dv, double tol,
                       unsigned char* tags, double* values, hipStream_t stream)

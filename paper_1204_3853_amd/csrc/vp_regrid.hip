@@ -136,6 +136,27 @@ vp_status vp_tag_cells(const vp_plan* p, const void* f, double tol, uint8_t* tag
     Level0 L;
     if (!p) return fail(VP_EINVAL, "vp_tag_cells: plan is NULL");
     if (!f || !tags) return fail(VP_EINVAL, "vp_tag_cells: NULL pointer");
+    if (p->p4) {
+        if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_tag_cells: FP64 plans only");
+        const Plan4D& Q = *p->p4;
+        Tag4DArgs a{};
+        a.f = static_cast<const double*>(f);
+        a.nx = Q.nx;
+        a.ny = Q.ny;
+        a.nvx = Q.nvx;
+        a.nvy = Q.nvy;
+        a.gx = Q.d_gx;
+        a.gy = Q.d_gy;
+        a.h[0] = Q.dx;
+        a.h[1] = Q.dy;
+        a.h[2] = Q.dvx;
+        a.h[3] = Q.dvy;
+        a.tol = tol;
+        a.tags = tags;
+        a.values = values;
+        VP_HIP(launch_tag4d(a, stream));
+        return VP_OK;
+    }
     if (!level0_of(p, L)) return fail(VP_ENOTSUP, "vp_tag_cells: 1D+1V plans only");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_tag_cells: FP64 plans only");
     VP_HIP(launch_tag(static_cast<const double*>(f), L.nx, L.nv, L.vg, L.dx, L.dv, tol, tags, values, stream));

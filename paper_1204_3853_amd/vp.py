@@ -420,12 +420,16 @@ def field_adjoint(plan, abar, fbar=None):
 
 
 def tag_cells(plan, f, tol, values=False):
-    """Refinement tags of level 0 (uint8 [ncx][ncv] on the device); with
-    values=True also delta1 f + delta2 f per level-0 cell."""
+    """Refinement tags of level 0 (uint8 [ncx][ncv] on the device; for a
+    2D+2V plan uint8 [nx][ny][nvx][nvy]); with values=True also
+    delta1 f + delta2 f per cell."""
     plan._state(f, "f")
-    ncx, ncv = plan.spec["cells"][0], plan.spec["cells"][1]
-    tags = torch.empty((ncx, ncv), dtype=torch.uint8, device=f.device)
-    vals = torch.empty((ncx, ncv), dtype=torch.float64, device=f.device) if values else None
+    if plan.spec["ndim"] == 2:
+        shape = tuple(plan.spec["cells"])               # every cell of the 2D+2V mesh
+    else:
+        shape = (plan.spec["cells"][0], plan.spec["cells"][1])
+    tags = torch.empty(shape, dtype=torch.uint8, device=f.device)
+    vals = torch.empty(shape, dtype=torch.float64, device=f.device) if values else None
     _check(lib().vp_tag_cells(plan.h, _ptr(f), ctypes.c_double(tol), _ptr(tags), _ptr(vals), _stream()))
     return (tags, vals) if values else tags
 

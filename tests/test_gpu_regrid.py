@@ -174,3 +174,38 @@ def test_regrid_end_to_end_full(vp, oracle):
     want = o.step(fnh, dt)
     got = fn.cpu().numpy()
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("shape", [(6, 5, 10, 12), (16, 12, 20, 24)])
+def test_tag_2d2v_bitwise(vp, oracle, shape):
+    """The criterion summed over x, y, vx, vy on a 2D+2V plan: every value
+    equal to the oracle's to the last bit, tags identical at three
+    tolerances (ragged sizes; velocity ghosts at both ends of both axes)."""
+    p = I.Problem2D(*shape, eps=0.2)
+    plan = vp.Plan(p)
+    f0 = p.initial_state() * (1.0 + 0.05 * np.random.default_rng(7).random(shape))
+    o = oracle.Oracle4D.from_problem(p)
+    _, want = o.tag(f0, 0.0)
+    tags, vals = vp.tag_cells(plan, gpu(f0.ravel()), 0.0, values=True)
+    got = vals.cpu().numpy()
+    assert got.shape == shape
+    assert np.array_equal(got, want), np.abs(got - want).max()
+    for tol in np.quantile(want, [0.1, 0.5, 0.9]):
+        t = vp.tag_cells(plan, gpu(f0.ravel()), float(tol)).cpu().numpy()
+        assert np.array_equal(t, o.tag(f0, float(tol))[0])
+
+
+def test_tag_2d2v_full_size(vp, oracle):
+    """64^4 (the 2D+2V workload): all tags against the oracle's, values at
+    sampled cells bit for bit."""
+    p = I.Problem2D(64, 64, 64, 64, eps=0.05)
+    plan = vp.Plan(p)
+    f0 = p.initial_state()
+    o = oracle.Oracle4D.from_problem(p)
+    want_tags, want = o.tag(f0, 1e-4)
+    tags, vals = vp.tag_cells(plan, gpu(f0.ravel()), 1e-4, values=True)
+    assert np.array_equal(tags.cpu().numpy(), want_tags)
+    v = vals.cpu().numpy()
+    rng = np.random.default_rng(3)
+    for idx in zip(*(rng.integers(0, 64, 200) for _ in range(4))):
+        assert v[idx] == o.tag_value(f0, *map(int, idx))
