@@ -217,6 +217,74 @@ __global__ __launch_bounds__(256) void k_tag4d(Tag4DArgs a)
     }
 }
 
+// The same with four consecutive vy cells per thread (nvy % 4 == 0): the
+// rows come in as 32-byte vector loads, the inner vy neighbours are the
+// thread's own values, and the four tags go out as one 32-bit store.  Per
+// cell the arithmetic is that of k_tag4d, term by term.
+typedef double tag_d4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_tag4d_v4(Tag4DArgs a)
+{
+#pragma clang fp contract(off)
+    const int plane = a.nvx * a.nvy, nq = a.nvy >> 2;
+    const int g = (int)blockIdx.x * 256 + (int)threadIdx.x;      // group of four vy cells
+    if (g >= plane >> 2) return;
+    const int nyb = (a.ny + kTag4DRows - 1) / kTag4DRows;
+    const int by = (int)blockIdx.y;
+    const int i = by / nyb, j0 = (by - (by / nyb) * nyb) * kTag4DRows;
+    const int j1 = min(j0 + kTag4DRows, a.ny);
+    const int k = g / nq, l0 = (g - (g / nq) * nq) * 4;
+    const int q = k * a.nvy + l0;
+    const int ip = i + 1 == a.nx ? 0 : i + 1, im = i == 0 ? a.nx - 1 : i - 1;
+    const double* f = a.f;
+    auto ld4 = [&](int off) { return *reinterpret_cast<const tag_d4*>(f + off); };
+    double gvxp[4], gvxm[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        gvxp[w] = a.gx[k + 3] * a.gy[l0 + w + 2];
+        gvxm[w] = a.gx[k + 1] * a.gy[l0 + w + 2];
+    }
+    const double gxk = a.gx[k + 2];
+    const double gvym = gxk * a.gy[l0 + 1], gvyp = gxk * a.gy[l0 + 6];
+    tag_d4 ym = ld4((i * a.ny + (j0 == 0 ? a.ny - 1 : j0 - 1)) * plane + q);
+    tag_d4 u = ld4((i * a.ny + j0) * plane + q);
+    for (int j = j0; j < j1; ++j) {
+        const int jp = j + 1 == a.ny ? 0 : j + 1;
+        const int base = (i * a.ny + j) * plane;
+        const tag_d4 yp = ld4((i * a.ny + jp) * plane + q);
+        const tag_d4 xp = ld4((ip * a.ny + j) * plane + q), xm = ld4((im * a.ny + j) * plane + q);
+        const tag_d4 vxp = k + 1 < a.nvx ? ld4(base + q + a.nvy) : tag_d4{gvxp[0], gvxp[1], gvxp[2], gvxp[3]};
+        const tag_d4 vxm = k > 0 ? ld4(base + q - a.nvy) : tag_d4{gvxm[0], gvxm[1], gvxm[2], gvxm[3]};
+        const double left = l0 > 0 ? f[base + q - 1] : gvym;
+        const double right = l0 + 4 < a.nvy ? f[base + q + 4] : gvyp;
+        const double uu[6] = {left, u.x, u.y, u.z, u.w, right};
+        const double xpv[4] = {xp.x, xp.y, xp.z, xp.w}, xmv[4] = {xm.x, xm.y, xm.z, xm.w};
+        const double ypv[4] = {yp.x, yp.y, yp.z, yp.w}, ymv[4] = {ym.x, ym.y, ym.z, ym.w};
+        const double vxpv[4] = {vxp.x, vxp.y, vxp.z, vxp.w}, vxmv[4] = {vxm.x, vxm.y, vxm.z, vxm.w};
+        unsigned packed = 0;
+        double vout[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const double c = uu[w + 1];
+            double t2, s1, s2;
+            s1 = tag_term(xpv[w], xmv[w], c, a.h[0], t2);
+            s2 = t2;
+            s1 = s1 + tag_term(ypv[w], ymv[w], c, a.h[1], t2);
+            s2 = s2 + t2;
+            s1 = s1 + tag_term(vxpv[w], vxmv[w], c, a.h[2], t2);
+            s2 = s2 + t2;
+            s1 = s1 + tag_term(uu[w + 2], uu[w], c, a.h[3], t2);
+            s2 = s2 + t2;
+            vout[w] = __builtin_sqrt(0.5 * s1) + 0.5 * s2;
+            packed |= (vout[w] > a.tol ? 1u : 0u) << (8 * w);
+        }
+        *reinterpret_cast<unsigned*>(a.tags + base + q) = packed;
+        if (a.values) *reinterpret_cast<tag_d4*>(a.values + base + q) = tag_d4{vout[0], vout[1], vout[2], vout[3]};
+        ym = u;
+        u = yp;
+    }
+}
+
 // R fine cell averages of the middle of u[0..4] (eqs. aux1, aux2,
 // interp_r_avg; B^(0) = 2 D_i - D_{i+1}, the value the definition gives);
 // every candidate renormalised to the coarse average, then combined with
@@ -318,8 +386,15 @@ hipError_t launch_tag4d(const Tag4DArgs& a, hipStream_t stream)
     if (n >= (1ll << 31) || a.nx * a.ny > 65535) return hipErrorInvalidValue;
     const int plane = a.nvx * a.nvy;
     const int nyb = (a.ny + kTag4DRows - 1) / kTag4DRows;
-    hipLaunchKernelGGL(k_tag4d, dim3((unsigned)((plane + 255) / 256), (unsigned)(a.nx * nyb)), dim3(256), 0, stream,
-                       a);
+    const bool v4 = a.nvy % 4 == 0 && (reinterpret_cast<uintptr_t>(a.f) & 31) == 0 &&
+                    (reinterpret_cast<uintptr_t>(a.tags) & 3) == 0 &&
+                    (reinterpret_cast<uintptr_t>(a.values) & 31) == 0;
+    if (v4)
+        hipLaunchKernelGGL(k_tag4d_v4, dim3((unsigned)((plane / 4 + 255) / 256), (unsigned)(a.nx * nyb)), dim3(256),
+                           0, stream, a);
+    else
+        hipLaunchKernelGGL(k_tag4d, dim3((unsigned)((plane + 255) / 256), (unsigned)(a.nx * nyb)), dim3(256), 0,
+                           stream, a);
     return hipGetLastError();
 }
 

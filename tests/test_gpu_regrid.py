@@ -176,11 +176,13 @@ def test_regrid_end_to_end_full(vp, oracle):
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
 
 
-@pytest.mark.parametrize("shape", [(6, 5, 10, 12), (16, 12, 20, 24)])
+@pytest.mark.parametrize("shape", [(6, 5, 10, 12), (16, 12, 20, 24), (5, 9, 7, 9)])
 def test_tag_2d2v_bitwise(vp, oracle, shape):
     """The criterion summed over x, y, vx, vy on a 2D+2V plan: every value
     equal to the oracle's to the last bit, tags identical at three
-    tolerances (ragged sizes; velocity ghosts at both ends of both axes)."""
+    tolerances (ragged sizes; velocity ghosts at both ends of both axes;
+    nvy = 9 takes the one-cell-per-thread kernel, the others the
+    four-cells-per-thread one)."""
     p = I.Problem2D(*shape, eps=0.2)
     plan = vp.Plan(p)
     f0 = p.initial_state() * (1.0 + 0.05 * np.random.default_rng(7).random(shape))
