@@ -441,11 +441,13 @@ vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const v
  * (section 4), in the library.  A run owns the plan of its current
  * hierarchy and the device buffers of its state, field and workspace.
  *
- * Time step: dt = min(cap, cfl * L), L the largest step with
- * dt (max|v| / dx + max|a| / dv) <= 1 on every level (level 0 over the
- * whole mesh; level 1 per patch, over the patch's velocity faces and
- * configuration columns); cap = dt_initial for the first step, else
- * dt_growth times the previous step.  Regridding after every
+ * Time step: dt = min(cap, cfl * L), L the linear stability limit of the
+ * fourth-order scheme under RK4, the largest step with
+ * dt (max|v| / dx + max|a| / dv) <= 2 sqrt(2) / max_t (8 sin t - sin 2t)/6
+ * (about 2.0612) on every level (level 0 over the whole mesh; level 1 per
+ * patch, over the patch's velocity faces and configuration columns);
+ * cap = dt_initial for the first step, else dt_growth times the previous
+ * step.  Regridding after every
  * regrid_interval steps: vp_tag_cells with tol, vp_cluster_tags with
  * efficiency, min_width and buffer, a new plan with the same problem and
  * the new boxes (default tile shape, launch mode and reduction),
@@ -457,7 +459,7 @@ typedef struct vp_amr_params {
     double efficiency;         /* clustering: tagged fraction of a box, (0, 1]         */
     int32_t min_width;         /* clustering: smallest split part, level-0 cells (>= 1) */
     int32_t buffer;            /* level-0 cells added around tagged regions (>= 0)     */
-    double cfl;                /* fraction of the stability limit (> 0; 0.5)           */
+    double cfl;                /* fraction of the linear stability limit (> 0; 0.5)    */
     double dt_growth;          /* largest ratio of consecutive steps (>= 1; 1.1)       */
     double dt_initial;         /* first time step (> 0)                                 */
 } vp_amr_params;

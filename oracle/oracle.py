@@ -8,6 +8,7 @@ does.  All arrays are float64, row-major [x][v].
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -285,11 +286,27 @@ def regrid_transfer(f_old, old_boxes, new_boxes, ncx, ncv, R, vghost_c):
     return np.concatenate(parts)
 
 
+def linear_stability_courant():
+    """Largest Courant number nu = dt (|v| / dx + |a| / dv) for which classic
+    RK4 (eq. rk4) on the centred fourth-order flux divergence of section 2 is
+    linearly stable.  The divergence of the face averages maps the Fourier
+    mode exp(i theta j) to i s(theta) / h, s(theta) = (8 sin theta -
+    sin 2 theta) / 6, whose maximum is at cos theta = 1 - sqrt(6)/2; summed
+    over the two phase directions the largest eigenvalue modulus is
+    nu max s.  RK4's amplification |P(i y)|^2 = 1 - y^6/72 + y^8/576 stays
+    <= 1 exactly for y <= 2 sqrt 2, so nu <= 2 sqrt 2 / max s (about 2.0612)."""
+    c = 1.0 - math.sqrt(6.0) / 2.0
+    s_max = math.sqrt(1.0 - c * c) * (4.0 - c) / 3.0
+    return 2.0 * math.sqrt(2.0) / s_max
+
+
 def amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, boxes):
-    """Largest dt with dt (max|v| / dx + max|a| / dv) <= 1 on every level of a
-    two-level hierarchy: level 0 over its whole mesh; level 1 per patch, with
-    the largest |v| on the patch's velocity faces and the largest |a| over the
-    fine configuration columns it covers.  a = [a_coarse (ncx)][a_fine (ncx R)]."""
+    """Largest dt for which the step is linearly stable on every level of a
+    two-level hierarchy (section 4's time step control takes a fraction of
+    it): dt (max|v| / dx + max|a| / dv) <= linear_stability_courant(), on
+    level 0 over its whole mesh; on level 1 per patch, with the largest |v| on
+    the patch's velocity faces and the largest |a| over the fine
+    configuration columns it covers.  a = [a_coarse (ncx)][a_fine (ncx R)]."""
     a = _f64(a)
     dxc, dvc = x_len / ncx, (v_hi - v_lo) / ncv
     dxf, dvf = dxc / R, dvc / R
@@ -299,7 +316,7 @@ def amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, boxes):
         (x0, v0), (x1, v1) = b["lo"], b["hi"]
         vmax = max(abs(v_lo + v0 * dvf), abs(v_lo + (v1 + 1) * dvf))
         rate = max(rate, vmax / dxf + np.abs(af[x0:x1 + 1]).max() / dvf)
-    return 1.0 / rate
+    return linear_stability_courant() / rate
 
 
 class Oracle1D:

@@ -184,19 +184,65 @@ def test_regrid_transfer_keeps_old_values_and_conserves(oracle):
             assert abs(blk.mean() - f0[cx, cv]) <= 1e-14
 
 
+def test_linear_stability_courant(oracle):
+    """The Courant limit of the time step control (section 4: a fraction of
+    the linear stability limit of the fourth-order scheme) is 2 sqrt 2 over
+    the largest modulus of the flux-divergence symbol.  Pinned three ways:
+    the oracle's x-advection operator has the eigenvalues i s(theta_m)/dx on
+    every Fourier mode; RK4's amplification on the imaginary axis crosses 1
+    at 2 sqrt 2; and oracle RK4 steps of a Fourier-rich state stay bounded
+    just below the limit and grow just above it."""
+    nu = oracle.linear_stability_courant()
+    assert nu == pytest.approx(2.0612, abs=5e-5)
+    # symbol of the oracle's operator: one velocity row with v = 1, zero ghosts, a = 0
+    nx, dx = 16, 0.25
+    L = np.empty((nx, nx))
+    for q in range(nx):
+        e = np.zeros((nx, 1))
+        e[q, 0] = 1.0
+        L[:, q] = oracle.rhs(e, np.zeros(nx), dx, 1.0, 0.5, np.zeros(4))[:, 0]
+    th = 2.0 * np.pi * np.arange(nx) / nx
+    s = (8.0 * np.sin(th) - np.sin(2.0 * th)) / 6.0
+    modes = np.exp(1j * np.outer(np.arange(nx), th))
+    np.testing.assert_allclose(L @ modes, modes * (-1j * s / dx)[None, :], atol=1e-12)
+    dense = np.linspace(0.0, np.pi, 200001)
+    s_max = ((8.0 * np.sin(dense) - np.sin(2.0 * dense)) / 6.0).max()
+    assert 2.0 * np.sqrt(2.0) / s_max == pytest.approx(nu, rel=1e-9)
+
+    def amp(y):
+        z = 1j * y
+        return abs(1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24)
+
+    y0 = 2.0 * np.sqrt(2.0)
+    assert amp(0.999 * y0) <= 1.0 < amp(1.001 * y0)
+    # oracle RK4 steps, a mesh with a mode at theta = 2 pi 2/7 (near the symbol's maximum)
+    nx = 7
+    f0 = np.random.default_rng(3).random((nx, 1))
+    o = oracle.Oracle1D(nx, 1, nx * dx, 0.5, 1.5, 0.0, np.zeros(4))
+    growth = {}
+    for frac in (0.98, 1.05):
+        f = f0.copy()
+        for _ in range(200):
+            f = o.step_fixed_a(f, np.zeros(nx), frac * nu * dx)
+        growth[frac] = np.abs(f - f0.mean()).max() / np.abs(f0 - f0.mean()).max()
+    assert growth[0.98] < 1.0 and growth[1.05] > 1e3, growth
+
+
 def test_stability_limit_closed_forms(oracle):
     ncx, ncv, R, x_len, v_lo, v_hi = 8, 16, 4, 2.0, -8.0, 10.0
     dxc, dvc = x_len / ncx, (v_hi - v_lo) / ncv
+    nu = oracle.linear_stability_courant()
     a = np.zeros(ncx + ncx * R)
-    assert oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, []) == pytest.approx(dxc / 10.0, rel=1e-15)
+    assert oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, []) == pytest.approx(nu * dxc / 10.0,
+                                                                                              rel=1e-15)
     a[:ncx] = 0.5
     a[ncx:] = np.linspace(-2.0, 1.0, ncx * R)
-    want0 = 1.0 / (10.0 / dxc + 0.5 / dvc)
+    want0 = nu / (10.0 / dxc + 0.5 / dvc)
     assert oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, []) == pytest.approx(want0, rel=1e-15)
     # a patch over fine v cells 8..15 (faces at v = -5.75 and -3.5) and fine x 0..3 (a in [-2, -1.71])
     box = {"level": 1, "lo": [0, 8], "hi": [3, 15]}
     dxf, dvf = dxc / R, dvc / R
-    want1 = 1.0 / (5.75 / dxf + 2.0 / dvf)
+    want1 = nu / (5.75 / dxf + 2.0 / dvf)
     got = oracle.amr_stability_limit(a, ncx, ncv, R, x_len, v_lo, v_hi, [box])
     assert got == pytest.approx(min(want0, want1), rel=1e-15)
     assert got == oracle.amr_stability_limit(-a, ncx, ncv, R, x_len, v_lo, v_hi, [box])
