@@ -248,6 +248,23 @@ vp_status vp_rk4_step(const vp_plan* plan, void* f, double* a, double dt, void* 
                       hipStream_t stream);
 
 /*
+ * vp_rk4_step without a `work` argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It runs the same kernels as
+ * vp_rk4_step with their workspace in a static device array of the library
+ * (32 MiB, held on each device the library runs on until the process
+ * ends), and calls no hipMalloc, hipFree or allocating routine.
+ *   f, a, dt  as for vp_rk4_step
+ * Single-level 1D+1V plans only (VP_ENOTSUP otherwise); VP_ESHAPE if the
+ * step needs more than 32 MiB of workspace (FP64: up to about 1.3M cells,
+ * e.g. 1024 x 1024).  Every call on one device shares that device's array
+ * and leaves its contents behind: calls that overlap in time on one device
+ * (several streams or threads) race and must be serialised by the caller.
+ */
+vp_status vp_rk4_step_noalloc(const vp_plan* plan, void* f, double* a, double dt,
+                              hipStream_t stream);
+
+/*
  * One subcycled step of a two-level plan: asynchronous time stepping, which
  * section 5 names as future work (citing the high-order subcycling of
  * McCorquodale and Colella); the reading taken here:

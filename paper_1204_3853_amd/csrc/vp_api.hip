@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -170,6 +171,36 @@ vp_status rk4_1d(const vp_plan* p, void* f, double* a, double dt, void* work, vo
                                     ncfg, nullptr, nullptr, a_next, stream);
         }));
     }
+    return VP_OK;
+}
+
+// The allocation-free RK4 step keeps its workspace in this file-scope
+// device array (each device holds its own copy until the process ends).
+// On the host the array's name is only a stand-in for the symbol, never a
+// device address: host code takes the address once per device with
+// hipGetSymbolAddress (scratch_address) and passes that pointer on.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current)
+vp_status scratch_address(void** out)
+{
+    int dev = -1;
+    VP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return fail(VP_ENOTSUP, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        VP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(VP_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
     return VP_OK;
 }
 
@@ -360,6 +391,7 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
     p->ws_fsb = off; off += sb;
     p->ws_part = off; off += align256((size_t)max_strips * p->nx * sizeof(double));
     p->ws_cfg = off; off += align256((size_t)8 * p->nx * sizeof(double));
+    p->ws_step = off;
     if (p->dtype == VP_F64) {   // adjoint recompute: copy of f_n and a_n, stage record
         p->ws_tmpf = off; off += sb;
         p->ws_tmpa = off; off += align256((size_t)p->nx * sizeof(double));
@@ -613,6 +645,21 @@ vp_status vp_rk4_step(const vp_plan* p, void* f, double* a, double dt, void* wor
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step: dt is not finite");
     if (p->amr) return amr_rk4(p, f, a, dt, work, stream);
     if (p->p4) return p4_rk4(p, f, a, dt, work, stream);
+    return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
+}
+
+vp_status vp_rk4_step_noalloc(const vp_plan* p, void* f, double* a, double dt, hipStream_t stream)
+{
+    if (vp_status s = check_plan(p)) return s;
+    if (!f || !a) return fail(VP_EINVAL, "vp_rk4_step_noalloc: NULL pointer");
+    if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_noalloc: dt is not finite");
+    if (p->amr || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_noalloc: single-level 1D+1V plans only");
+    if (p->ws_step > kScratchBytes)
+        return fail(VP_ESHAPE, "vp_rk4_step_noalloc: the step needs " + std::to_string(p->ws_step) +
+                                   " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
+                                   " bytes of the static scratch array");
+    void* work = nullptr;
+    if (vp_status s = scratch_address(&work)) return s;
     return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
 }
 

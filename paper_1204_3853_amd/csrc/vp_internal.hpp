@@ -384,6 +384,7 @@ struct vp_plan {
 
     // workspace layout (byte offsets)
     size_t ws_acc = 0, ws_fsa = 0, ws_fsb = 0, ws_part = 0, ws_cfg = 0, ws_total = 0;
+    size_t ws_step = 0;   // prefix of the workspace that a forward RK4 step uses (single-level 1D+1V)
     size_t ws_tmpf = 0, ws_stages = 0, ws_tmpa = 0;   // adjoint recompute (f_n copy, stage record)
     size_t state_elems = 0;
 

@@ -82,6 +82,7 @@ SIGNATURES = {
     "vp_poisson_periodic": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "vp_inject_field": (ctypes.c_int, [_P, _P, _P, _P]),
     "vp_rk4_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P]),
+    "vp_rk4_step_noalloc": (ctypes.c_int, [_P, _P, _P, _D, _P]),
     "vp_amr_subcycle_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P]),
     "vp_rk4_step_record": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P]),
     "vp_adjoint_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _D, _P, _P]),
@@ -373,6 +374,14 @@ def rk4_step(plan, f, a, dt):
     plan._state(f, "f")
     plan._cfg(a, "a", plan.field_elems)
     _check(lib().vp_rk4_step(plan.h, _ptr(f), _ptr(a), ctypes.c_double(dt), _ptr(plan.work), _stream()))
+    return f, a
+
+
+def rk4_step_noalloc(plan, f, a, dt):
+    """vp_rk4_step with the library's static scratch array as workspace."""
+    plan._state(f, "f")
+    plan._cfg(a, "a", plan.field_elems)
+    _check(lib().vp_rk4_step_noalloc(plan.h, _ptr(f), _ptr(a), ctypes.c_double(dt), _stream()))
     return f, a
 
 
