@@ -23,8 +23,11 @@
  *   - two dimensions: x first, then v (dimension by dimension);
  *   - the coarse field is the mean of the R fine field values;
  *   - fine ghosts outside the velocity domain hold the fine equilibrium.
- * The configuration requires every patch boundary to be a coarse-fine
- * interface (patches separated by at least one coarse cell).
+ * Patches are disjoint and may touch, also across the periodic x boundary:
+ * fine ghost cells held by a patch are copied from it, so the two patches
+ * on a fine-fine face compute its flux from the same values (the flux
+ * exchange of Alg. msrhsfa then changes nothing) and only coarse-fine faces
+ * take coarsened fluxes.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -135,7 +138,26 @@ static double interp_fine(const vpo_amr* c, const double* f, int I, int J)
     return acc;
 }
 
-/* patch p with two ghost layers: (nxp + 4) x (nvp + 4), ghosts from the coarse level */
+/* fine cell (I, J) (I periodic) held by a level-1 patch: 1 and its value in
+ * *val, else 0 (ghost cells for inter-patch communication, section 3) */
+static int same_level_at(const vpo_amr* c, const double* f, int I, int J, double* val)
+{
+    if (J < 0 || J >= c->nfv) return 0;
+    const int Iw = wrap(I, c->nfx);
+    for (int p = 0; p < c->np; ++p) {
+        const int x0 = c->box[4 * p], v0 = c->box[4 * p + 1];
+        if (Iw < x0 || Iw > c->box[4 * p + 2] || J < v0 || J > c->box[4 * p + 3]) continue;
+        *val = f[c->off[p] + (size_t)(Iw - x0) * NVP(c, p) + (J - v0)];
+        return 1;
+    }
+    return 0;
+}
+
+/* patch p with two ghost layers: (nxp + 4) x (nvp + 4).  A ghost cell that a
+ * level-1 patch holds (a touching patch, also across the periodic x
+ * boundary, or the patch itself when it spans the whole x range) takes that
+ * value (the exchange of ghost cells on a level, Alg. mspsc); the others
+ * are interpolated from the coarse level */
 void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out)
 {
     vpo_amr* c = (vpo_amr*)h;
@@ -146,7 +168,7 @@ void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out)
         for (int q = -2; q < nvp + 2; ++q) {
             double v;
             if (r >= 0 && r < nxp && q >= 0 && q < nvp) v = fp[(size_t)r * nvp + q];
-            else v = interp_fine(c, f, x0 + r, v0 + q);
+            else if (!same_level_at(c, f, x0 + r, v0 + q, &v)) v = interp_fine(c, f, x0 + r, v0 + q);
             out[(size_t)(r + 2) * W + (q + 2)] = v;
         }
 }
