@@ -100,13 +100,16 @@ typedef struct vp_problem {
  * A level-1 patch: inclusive cell range [lo, hi] per direction in the
  * level-1 global index space (section 3, box notation).  Level 0 always
  * covers the whole domain and is implicit.  Patches must be inside the
- * domain (no periodic wrap inside one patch) and aligned to the refinement
- * ratio (lo and hi + 1 multiples of it), and any two patches must be
- * separated by at least one level-0 cell, also across the periodic
- * boundary, so that every patch boundary is a coarse-fine interface
- * (VP_EINVAL for a bad box, VP_ENOTSUP for patches that touch).  Two
- * levels are supported for 1D+1V in FP64 with ratio 2 or 4 (equal in x
- * and v) and a finest configuration mesh of at most 8192 cells.
+ * domain (no periodic wrap inside one patch), aligned to the refinement
+ * ratio (lo and hi + 1 multiples of it) and disjoint (VP_EINVAL
+ * otherwise).  Patches may touch, also across the periodic x boundary:
+ * ghost cells that a neighbouring patch holds are copied from it (ghost
+ * cells for inter-patch communication, section 3; Alg. mspsc), the others
+ * interpolated from level 0, so a fine-fine face gets the same flux from
+ * both sides and only coarse-fine faces are corrected at the end of a
+ * step.  Two levels are supported for 1D+1V in FP64 with ratio 2 or 4
+ * (equal in x and v) and a finest configuration mesh of at most 8192
+ * cells.
  */
 typedef struct vp_box {
     int32_t level;
@@ -423,10 +426,10 @@ vp_status vp_tag_cells(const vp_plan* plan, const void* f, double tol, uint8_t* 
  * inflection of a signature's second difference, else in the middle of
  * its longer side, until every box holds at least `efficiency` tagged
  * cells per cell or cannot be split into parts of `min_width` cells; every
- * box then grows by `buffer` cells, and boxes closer than one level-0 cell
- * (also across the periodic x boundary) are merged into their bounding
- * box.  The last level-0 column is never refined, so that boxes reaching
- * the two ends of the periodic x range stay one cell apart.  The boxes are
+ * box then grows by `buffer` cells (clipped to the domain), and boxes that
+ * then overlap are merged into their bounding box.  Boxes may touch, also
+ * across the periodic x boundary (a tagged region across x = x_lo is
+ * covered by boxes at both ends of the x range).  The boxes are
  * returned in level-1 indices (level-0 box times `ratio`), sorted by
  * (x, v) origin, and satisfy vp_plan_create's rules.
  *   tags       host uint8 [ncx][ncv]

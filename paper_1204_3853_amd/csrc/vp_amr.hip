@@ -157,6 +157,7 @@ AmrArgs stage_args(const vp_plan* p, const void* fs, const void* fn, void* acc, 
     A.a_f = a + M.ncx;
     A.B = M.d_B;
     A.faces = M.d_faces;
+    A.nb = M.d_nb;
     A.cf_acc = work ? reinterpret_cast<double*>(wsp(work, M.ws_cf)) : nullptr;
     A.ff_acc = work ? reinterpret_cast<double*>(wsp(work, M.ws_ff)) : nullptr;
     A.c_flux = c_flux;
@@ -289,7 +290,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->vgf[0] = vf[0]; M->vgf[1] = vf[1]; M->vgf[2] = vf[M->nfv + 2]; M->vgf[3] = vf[M->nfv + 3];
     if (M->nfx > kMaxPoisson1D) return fail(VP_ENOTSUP, "finest configuration mesh larger than 8192 cells");
 
-    // ---- boxes: level 1, inside the domain, aligned to R, separated by one coarse cell
+    // ---- boxes: level 1, inside the domain, aligned to R, disjoint (touching allowed)
     std::vector<Box> bx;
     for (int q = 0; q < nbox; ++q) {
         const vp_box& b = boxes[q];
@@ -299,20 +300,9 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
             return fail(VP_EINVAL, "box " + std::to_string(q) + " is empty or outside the level-1 domain");
         if (B.xlo % R || B.vlo % R || (B.xhi + 1) % R || (B.vhi + 1) % R)
             return fail(VP_EINVAL, "box " + std::to_string(q) + " is not aligned to the refinement ratio");
-        for (size_t r = 0; r < bx.size(); ++r) {
-            const Box& o = bx[r];
-            Box grown{B.xlo - R, B.vlo - R, B.xhi + R, B.vhi + R};
-            if (!intersect(grown, o).empty())
-                return fail(VP_ENOTSUP, "boxes " + std::to_string(r) + " and " + std::to_string(q) +
-                                            " overlap or are closer than one coarse cell");
-            // periodic images in x
-            for (int sh : {-M->nfx, M->nfx}) {
-                Box g2{grown.xlo + sh, grown.vlo, grown.xhi + sh, grown.vhi};
-                if (!intersect(g2, o).empty())
-                    return fail(VP_ENOTSUP, "boxes " + std::to_string(r) + " and " + std::to_string(q) +
-                                                " are closer than one coarse cell across the periodic boundary");
-            }
-        }
+        for (size_t r = 0; r < bx.size(); ++r)
+            if (!intersect(B, bx[r]).empty())
+                return fail(VP_EINVAL, "boxes " + std::to_string(r) + " and " + std::to_string(q) + " overlap");
         bx.push_back(B);
     }
 
@@ -332,6 +322,25 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     }
     M->total = off;
     M->fflux = foff;
+
+    // ---- neighbour lists: the patches (the patch itself included when its x
+    // range wraps onto it) holding cells of the two-cell ghost frame of each
+    // patch, x periodic; those ghost cells are copied, not interpolated
+    std::vector<int> nb;
+    for (size_t q = 0; q < bx.size(); ++q) {
+        const Box g{bx[q].xlo - 2, bx[q].vlo - 2, bx[q].xhi + 2, bx[q].vhi + 2};
+        M->patches[q].nb0 = (int)nb.size();
+        for (size_t r = 0; r < bx.size(); ++r)
+            for (int sh : {-M->nfx, 0, M->nfx}) {
+                if (r == q && sh == 0) continue;
+                const Box o{bx[r].xlo + sh, bx[r].vlo, bx[r].xhi + sh, bx[r].vhi};
+                if (!intersect(g, o).empty()) {
+                    nb.push_back((int)r);
+                    break;
+                }
+            }
+        M->patches[q].nb1 = (int)nb.size();
+    }
 
     // ---- coverage of coarse cells, coarse-fine faces, corrections, restriction
     const int ncx = M->ncx, ncv = M->ncv;
@@ -481,6 +490,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     TableArena T;
     T.add(&M->d_patches, M->patches);
     T.add(&M->d_faces, M->faces);
+    T.add(&M->d_nb, nb);
     T.add(&M->d_B, B);
     T.add(&M->d_task_off, task_off);
     T.add(&M->d_task_len, task_len);

@@ -116,6 +116,7 @@ struct AmrPatch {              // one level-1 patch
     long long foff;            // offset of its boundary-flux block: [x lo: nv][x hi: nv][v lo: nx][v hi: nx]
     int gx0, gv0;              // level-1 global index of its cell (0, 0)
     int nx, nv;                // cells
+    int nb0, nb1;              // range of its neighbour list: patches holding some of its ghost cells
 };
 
 enum AmrTileKind : int { kTileCoarse = 0, kTileFine = 1, kTileFaces = 2 };
@@ -145,6 +146,7 @@ struct AmrArgs {
     const double* a_f;         // level-1 acceleration (nfx)
     const double* B;           // sub-cell interpolation weights b_j(s) at B[s * 5 + j + 2] (device)
     const AmrFace* faces;
+    const int* nb;             // neighbour lists (AmrPatch::nb0 .. nb1)
     double* cf_acc;            // accumulated coarse fluxes on the listed faces
     double* ff_acc;            // accumulated fine boundary fluxes
     double c_flux;             // b_s (0: no accumulation)
@@ -309,6 +311,7 @@ struct AmrPlan {
     // tile table, which a tile shape change rebuilds
     void* d_tables = nullptr;
     AmrPatch* d_patches = nullptr;
+    int* d_nb = nullptr;
     AmrTile* d_tiles = nullptr;
     AmrFace* d_faces = nullptr;
     double* d_B = nullptr;

@@ -161,6 +161,55 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
             }
             __syncthreads();
         }
+        // Halo cells that a level-1 patch holds (a touching patch, also
+        // across the periodic x boundary) take its value of the same stage
+        // input instead (the exchange of ghost cells on a level); the same
+        // regions as above, each cell written by the thread that wrote it.
+        if (P.nb1 > P.nb0) {
+            const double* fall = static_cast<const double*>(C.fs);
+            // the neighbours' records, staged in LDS (the first kNbLds of them)
+            constexpr int kNbLds = 8;
+            __shared__ AmrPatch nbs[kNbLds];
+            const int nnb = P.nb1 - P.nb0;
+            for (int e = t; e < min(nnb, kNbLds); e += NT) nbs[e] = A.patches[A.nb[P.nb0 + e]];
+            __syncthreads();
+            auto held = [&](int X, int V, T& out) -> bool {
+                if (V < 0 || V >= A.nfv) return false;
+                const int Xw = wrapi(X, A.nfx);
+                for (int e = 0; e < nnb; ++e) {
+                    const AmrPatch Q = e < kNbLds ? nbs[e] : A.patches[A.nb[P.nb0 + e]];
+                    const int dx = Xw - Q.gx0, dv = V - Q.gv0;
+                    if (dx >= 0 && dx < Q.nx && dv >= 0 && dv < Q.nv) {
+                        out = fall[Q.off + (size_t)dx * Q.nv + dv];
+                        return true;
+                    }
+                }
+                return false;
+            };
+            for (int q2 = 0; q2 < 2; ++q2) {
+                if (q2 == 0 ? !top : !bot) continue;
+                const int X0 = P.gx0 + (q2 == 0 ? -2 : nx);
+                const int ncols = TV + 4;
+                for (int k = t; k < 2 * ncols; k += NT) {
+                    const int q = k / ncols, c = k - q * ncols;
+                    const int j = j0 - 2 + c;
+                    T v;
+                    if (j >= -2 && j <= nv + 1 && held(X0 + q, P.gv0 + j, v)) hrow[2 * q2 + q][c] = v;
+                }
+            }
+            for (int q2 = 0; q2 < 2; ++q2) {
+                if (q2 == 0 ? !left : !right) continue;
+                for (int k = t; k < 2 * (i1 - i0 + 4); k += NT) {
+                    const int q = k & 1, rr = k >> 1;
+                    const int r = i0 - 2 + rr;
+                    if (r < 0 || r >= nx) continue;
+                    const int j = q2 == 0 ? q - 2 : nv + q;
+                    T v;
+                    if (held(P.gx0 + r, P.gv0 + j, v)) hcol[rr][2 * q2 + q] = v;
+                }
+            }
+            __syncthreads();
+        }
     }
     // value of a cell of the tile window that is not patch data
     auto halo_val = [&](int r, int j) -> T {

@@ -112,14 +112,9 @@ void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double ef
     br_cluster(tag, nv, hi, eff, minw, out);
 }
 
-bool too_close(const CBox& a, const CBox& b, int period)
+bool overlap(const CBox& a, const CBox& b)
 {
-    for (int sh : {0, -period, period}) {
-        const int xlo = std::max(a.xlo - 1, b.xlo + sh), xhi = std::min(a.xhi + 1, b.xhi + sh);
-        const int vlo = std::max(a.vlo - 1, b.vlo), vhi = std::min(a.vhi + 1, b.vhi);
-        if (xlo <= xhi && vlo <= vhi) return true;
-    }
-    return false;
+    return std::max(a.xlo, b.xlo) <= std::min(a.xhi, b.xhi) && std::max(a.vlo, b.vlo) <= std::min(a.vhi, b.vhi);
 }
 
 }  // namespace
@@ -167,26 +162,24 @@ vp_status vp_cluster_tags(const uint8_t* tags, int32_t ncx, int32_t ncv, int32_t
                           int32_t min_width, int32_t buffer, vp_box* boxes, int32_t max_boxes, int32_t* nbox)
 {
     if (!tags || !nbox || (max_boxes > 0 && !boxes)) return fail(VP_EINVAL, "vp_cluster_tags: NULL pointer");
-    if (ncx < 3 || ncv < 1 || ratio < 1 || min_width < 1 || buffer < 0 || !(efficiency > 0.0 && efficiency <= 1.0))
+    if (ncx < 1 || ncv < 1 || ratio < 1 || min_width < 1 || buffer < 0 || !(efficiency > 0.0 && efficiency <= 1.0))
         return fail(VP_EINVAL, "vp_cluster_tags: bad sizes or parameters");
-    // the last level-0 column is never refined: it keeps one coarse cell
-    // between boxes that reach the two ends of the periodic x range
     std::vector<unsigned char> t(tags, tags + (size_t)ncx * ncv);
-    for (int j = 0; j < ncv; ++j) t[(size_t)(ncx - 1) * ncv + j] = 0;
     std::vector<CBox> bx;
-    br_cluster(t, ncv, CBox{0, 0, ncx - 2, ncv - 1}, efficiency, min_width, bx);
-    // buffer cells around every box, inside the refinable range
+    br_cluster(t, ncv, CBox{0, 0, ncx - 1, ncv - 1}, efficiency, min_width, bx);
+    // buffer cells around every box, inside the domain (patches may touch,
+    // also across the periodic x boundary, but never wrap)
     for (CBox& b : bx) {
-        b.xlo = std::max(b.xlo - buffer, 0); b.xhi = std::min(b.xhi + buffer, ncx - 2);
+        b.xlo = std::max(b.xlo - buffer, 0); b.xhi = std::min(b.xhi + buffer, ncx - 1);
         b.vlo = std::max(b.vlo - buffer, 0); b.vhi = std::min(b.vhi + buffer, ncv - 1);
     }
-    // boxes closer than one level-0 cell (also across the periodic boundary)
-    // are replaced by their bounding box until none are
+    // boxes that overlap after the buffer are replaced by their bounding box
+    // until none do
     for (bool merged = true; merged;) {
         merged = false;
         for (size_t a = 0; a < bx.size() && !merged; ++a)
             for (size_t b = a + 1; b < bx.size() && !merged; ++b)
-                if (too_close(bx[a], bx[b], ncx)) {
+                if (overlap(bx[a], bx[b])) {
                     CBox u{std::min(bx[a].xlo, bx[b].xlo), std::min(bx[a].vlo, bx[b].vlo),
                            std::max(bx[a].xhi, bx[b].xhi), std::max(bx[a].vhi, bx[b].vhi)};
                     bx[a] = u;

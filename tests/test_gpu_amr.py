@@ -6,8 +6,10 @@ coarse-fine flux correction and average-down).
 Layouts: a small hierarchy (32 x 48 coarse, ratio 4, three patches, one
 touching the periodic x boundary), a ratio-2 hierarchy with an odd coarse
 velocity count (one cell per thread, ragged strips) and patches touching
-both ends of the velocity box, and the 512 x 512
-ratio-4 hierarchy with 40 seeded patches of sides 16..128 inside |v| < 3.
+both ends of the velocity box, patches touching each other (in x, in v and
+across the periodic x boundary: ghost cells copied from the neighbour), a
+patch over the whole x range, and the 512 x 512 ratio-4 hierarchy with 40
+seeded patches of sides 16..128 inside |v| < 3 (two pairs touch).
 """
 import math
 
@@ -26,9 +28,21 @@ RATIO2 = [{"level": 1, "lo": [6, 20], "hi": [17, 33]}, {"level": 1, "lo": [0, 50
           {"level": 1, "lo": [30, 36], "hi": [45, 43]}, {"level": 1, "lo": [20, 0], "hi": [27, 7]},
           {"level": 1, "lo": [36, 80], "hi": [41, 89]}]
 
+# touching patches: in x, in v (partly), across the periodic x boundary
+TOUCHING = [{"level": 1, "lo": [16, 40], "hi": [39, 63]}, {"level": 1, "lo": [40, 40], "hi": [55, 63]},
+            {"level": 1, "lo": [24, 64], "hi": [31, 79]}, {"level": 1, "lo": [40, 64], "hi": [47, 71]},
+            {"level": 1, "lo": [0, 96], "hi": [15, 111]}, {"level": 1, "lo": [112, 100], "hi": [127, 115]},
+            {"level": 1, "lo": [64, 140], "hi": [79, 151]}]
+# a patch over the whole x range (its x ghosts wrap onto itself), a patch
+# touching it in v, and a patch on the lower velocity boundary
+WHOLE_X = [{"level": 1, "lo": [0, 20], "hi": [47, 33]}, {"level": 1, "lo": [6, 34], "hi": [17, 43]},
+           {"level": 1, "lo": [20, 0], "hi": [27, 7]}]
+
 LAYOUTS = {
     "small": dict(boxes=SMALL, ncx=32, ncv=48, R=4),
     "ratio2_odd": dict(boxes=RATIO2, ncx=24, ncv=45, R=2),
+    "touching": dict(boxes=TOUCHING, ncx=32, ncv=48, R=4),
+    "whole_x_ratio2": dict(boxes=WHOLE_X, ncx=24, ncv=45, R=2),
 }
 
 

@@ -32,27 +32,20 @@ def vp():
 
 
 def check_clustering(tags, values, tol, boxes, R):
-    """Every oracle-tagged level-0 cell (except the last column, never refined,
-    and cells whose criterion is within 1e-9 of tol) lies in a box; boxes are
-    aligned, inside the refinable range and a level-0 cell apart."""
+    """Every oracle-tagged level-0 cell (except cells whose criterion is
+    within 1e-9 of tol) lies in a box; boxes are aligned, inside the domain
+    and disjoint (touching allowed)."""
     ncx, ncv = tags.shape
     cov = np.zeros(tags.shape, dtype=bool)
-    cb = []
     for b in boxes:
         (x0, v0), (x1, v1) = b["lo"], b["hi"]
         assert x0 % R == 0 and v0 % R == 0 and (x1 + 1) % R == 0 and (v1 + 1) % R == 0
         c = (x0 // R, v0 // R, (x1 + 1) // R - 1, (v1 + 1) // R - 1)
-        assert 0 <= c[0] <= c[2] <= ncx - 2 and 0 <= c[1] <= c[3] <= ncv - 1
+        assert 0 <= c[0] <= c[2] <= ncx - 1 and 0 <= c[1] <= c[3] <= ncv - 1
+        assert not cov[c[0]:c[2] + 1, c[1]:c[3] + 1].any()
         cov[c[0]:c[2] + 1, c[1]:c[3] + 1] = True
-        cb.append(c)
     sure = tags.astype(bool) & (np.abs(values - tol) > 1e-9 * tol)
-    sure[-1, :] = False
     assert not (sure & ~cov).any()
-    for p in range(len(cb)):
-        for q in range(p + 1, len(cb)):
-            A, B = cb[p], cb[q]
-            for sh in (0, -ncx, ncx):
-                assert max(A[0], B[0] + sh) - min(A[2], B[2] + sh) > 1 or max(A[1], B[1]) - min(A[3], B[3]) > 1
 
 
 def oracle_run(oracle, run, coarse, R, boxes, f0, veq_c, veq_f, tol, interval, blocks, cfl, growth, dt0):

@@ -194,13 +194,13 @@ class Problem2D:
 
 def amr_boxes(seed: int = 0, coarse=(512, 512), ratio: int = 4, npatch: int = 40,
               side_lo: int = 16, side_hi: int = 128, v_lo: float = -8.0, v_hi: float = 8.0,
-              v_band: float = 3.0, gap: int = 4):
+              v_band: float = 3.0, gap: int = 0):
     """Seeded layout of level-1 patches (inclusive lo/hi in the level-1 index
     space): sides drawn uniformly from {side_lo, side_lo+4, ..., side_hi},
     corners aligned to the refinement ratio, confined to the velocity band
-    |v| < v_band, not wrapping in x.  Patches grown by `gap` fine cells (one
-    coarse cell) must not intersect, so every patch boundary is a
-    coarse-fine interface; draws that violate this are rejected."""
+    |v| < v_band, not wrapping in x.  Patches grown by `gap` fine cells must
+    not intersect; draws that violate this are rejected.  gap = 0: disjoint,
+    touching allowed (seed 0: 40 patches, two touching pairs)."""
     rng = np.random.default_rng(seed)
     nxf, nvf = coarse[0] * ratio, coarse[1] * ratio
     dvf = (v_hi - v_lo) / nvf
@@ -268,12 +268,11 @@ def amr_bump_on_tail(boxes, coarse=(16, 32), ratio: int = 4, eps: float = 0.04, 
 
 def bump_on_tail_initial_boxes(coarse=(16, 32), ratio: int = 4):
     """The initial refinement of the bump-on-tail run, level-0 cells
-    [0, 15] x [8, 24] of a 16 x 32 mesh, scaled to `coarse`; the last
-    level-0 column is left out (a patch may not meet itself across the
-    periodic boundary)."""
+    [0, 15] x [8, 24] of a 16 x 32 mesh (the whole periodic x range),
+    scaled to `coarse`."""
     ncx, ncv = coarse
     sv = ncv // 32
-    return [{"level": 1, "lo": [0, 8 * sv * ratio], "hi": [(ncx - 1) * ratio - 1, (24 * sv + sv) * ratio - 1]}]
+    return [{"level": 1, "lo": [0, 8 * sv * ratio], "hi": [ncx * ratio - 1, (24 * sv + sv) * ratio - 1]}]
 
 
 def save_boxes(path, boxes):
