@@ -16,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["vp_oracle.c", "vp_oracle_adjoint.c", "vp_oracle_amr.c", "vp_oracle_4d.c", "vp_oracle_limited.c",
-           "vp_oracle_regrid.c"]
+           "vp_oracle_regrid.c", "vp_oracle_hier.c"]
 LIB = os.path.join(HERE, "libvp_oracle.so")
 
 
@@ -100,6 +100,16 @@ def _declare_extra(L):
         "vpo_rk4_dense_weights": (None, [_F, _D]),
         "vpo_rk4_substage_weights": (None, [_F, _F, _I, _D]),
         "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
+        "vpo_hier_new": (_V, [_I, _I, _I, _F, _F, _F, _F, ctypes.POINTER(ctypes.c_int), _I,
+                              ctypes.POINTER(ctypes.c_int), _D, ctypes.POINTER(ctypes.c_int)]),
+        "vpo_hier_free": (None, [_V]),
+        "vpo_hier_state_size": (ctypes.c_long, [_V]),
+        "vpo_hier_patch_offset": (ctypes.c_long, [_V, _I]),
+        "vpo_hier_fill_ghosts": (None, [_V, _D, _I, _D]),
+        "vpo_hier_reduce_mask": (None, [_V, _D, _D]),
+        "vpo_hier_constraints": (None, [_V, _D, _D, _D]),
+        "vpo_hier_rhs": (None, [_V, _D, _D, _D]),
+        "vpo_hier_rk4_step": (None, [_V, _D, _D, _F]),
         "vpo_amr_species_constraints": (None, [_I, ctypes.POINTER(_V), ctypes.POINTER(_D), _D, _F,
                                                ctypes.POINTER(_D)]),
         "vpo_amr_species_rk4_step": (None, [_I, ctypes.POINTER(_V), ctypes.POINTER(_D), ctypes.POINTER(_D), _D,
@@ -507,6 +517,90 @@ class OracleAMR:
         f = _f64(f)
         out = np.empty_like(f)
         lib().vpo_amr_subcycle_step(self.h, _p(f), _p(out), dt)
+        return out
+
+
+class OracleHier:
+    """L-level 1D+1V oracle (vp_oracle_hier.c): level 0 (ncx x ncv) and
+    patches on levels 1 .. L-1 (boxes: dicts with "level" and inclusive
+    lo/hi in that level's index space); ratios[l-1] = (r_x, r_v) of level
+    l-1 -> l; veqs[l]: level-l equilibrium with two ghosts per side."""
+
+    def __init__(self, L, ncx, ncv, x_len, v_lo, v_hi, qm, ratios, boxes, veqs):
+        self.L, self.ncx, self.ncv = L, ncx, ncv
+        self.ratios = [tuple(r) for r in ratios]
+        self.boxes = boxes
+        self.nx, self.nv = [ncx], [ncv]
+        for rx, rv in self.ratios:
+            self.nx.append(self.nx[-1] * rx)
+            self.nv.append(self.nv[-1] * rv)
+        rat = np.ascontiguousarray(np.array(self.ratios, dtype=np.int32).ravel() if ratios else np.zeros(2, np.int32))
+        arr = np.array([[b["level"], b["lo"][0], b["lo"][1], b["hi"][0], b["hi"][1]] for b in boxes],
+                       dtype=np.int32).ravel()
+        self._rat, self._boxes = rat, np.ascontiguousarray(arr if arr.size else np.zeros(5, np.int32))
+        self._veq = _f64(np.concatenate([np.asarray(v, dtype=np.float64) for v in veqs]))
+        err = ctypes.c_int(0)
+        self.h = lib().vpo_hier_new(L, ncx, ncv, x_len, v_lo, v_hi, qm,
+                                    self._rat.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(boxes),
+                                    self._boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(self._veq),
+                                    ctypes.byref(err))
+        if not self.h:
+            raise ValueError(f"bad hierarchy (code {err.value})")
+        self.size = lib().vpo_hier_state_size(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.vpo_hier_free(self.h)
+            self.h = None
+
+    @property
+    def nfx(self):
+        return self.nx[-1]
+
+    @property
+    def field_elems(self):
+        return sum(self.nx)
+
+    def offset(self, p):
+        """element offset of boxes[p] (p = -1: level 0)"""
+        return lib().vpo_hier_patch_offset(self.h, p)
+
+    def ghosted(self, f, p):
+        """patch p (-1: level 0) with two ghost layers"""
+        f = _f64(f)
+        if p < 0:
+            nx, nv = self.ncx, self.ncv
+        else:
+            b = self.boxes[p]
+            nx, nv = b["hi"][0] - b["lo"][0] + 1, b["hi"][1] - b["lo"][1] + 1
+        out = np.empty((nx + 4, nv + 4))
+        lib().vpo_hier_fill_ghosts(self.h, _p(f), p + 1, _p(out))
+        return out
+
+    def reduce_mask(self, f):
+        f = _f64(f)
+        n = np.empty(self.nfx)
+        lib().vpo_hier_reduce_mask(self.h, _p(f), _p(n))
+        return n
+
+    def constraints(self, f):
+        """(a on every level, concatenated from level 0; E on the finest mesh)"""
+        f = _f64(f)
+        a = np.empty(self.field_elems)
+        E = np.empty(self.nfx)
+        lib().vpo_hier_constraints(self.h, _p(f), _p(a), _p(E))
+        return a, E
+
+    def rhs(self, f, a):
+        f, a = _f64(f), _f64(a)
+        k = np.empty_like(f)
+        lib().vpo_hier_rhs(self.h, _p(f), _p(a), _p(k))
+        return k
+
+    def step(self, f, dt):
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().vpo_hier_rk4_step(self.h, _p(f), _p(out), dt)
         return out
 
 

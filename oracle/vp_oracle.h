@@ -56,6 +56,28 @@ void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out);
 void vpo_amr_reduce_mask(void* h, double* f, double* n);
 void vpo_amr_constraints(void* h, double* f, double* a, double* E_out);
 void vpo_amr_rhs(void* h, double* f, double* a, double* k);
+/* fluxes of section 2 on one patch from its data with two ghost layers g
+ * ((nx+4) x (nv+4)): Gx[(nx+1) x nv], Gv[nx x (nv+1)]; a_ext[i+1] = a at row
+ * i = -1 .. nx; and their divergence */
+void vpo_patch_fluxes(int nx, int nv, const double* g, double dv, double v0, const double* a_ext,
+                      double* Gx, double* Gv);
+void vpo_divergence(int nx, int nv, const double* Gx, const double* Gv, double dx, double dv, double* k);
+
+/* L-level hierarchy with per-level, per-direction ratios (vp_oracle_hier.c);
+ * ratios[2(l-1)], ratios[2(l-1)+1]: x and v ratio of level l-1 -> l;
+ * boxes: nbox x (level, lo_x, lo_v, hi_x, hi_v); veq_all: the equilibrium
+ * with ghosts of every level, concatenated (nv_l + 4 each); *err != 0 and
+ * NULL on a bad hierarchy */
+void* vpo_hier_new(int L, int ncx, int ncv, double x_len, double v_lo, double v_hi, double qm, const int* ratios,
+                   int nbox, const int* boxes, const double* veq_all, int* err);
+void vpo_hier_free(void* h);
+long vpo_hier_state_size(void* h);
+long vpo_hier_patch_offset(void* h, int p);
+void vpo_hier_fill_ghosts(void* h, const double* f, int p, double* out);
+void vpo_hier_reduce_mask(void* h, const double* f, double* n);
+void vpo_hier_constraints(void* h, const double* f, double* a, double* E_out);
+void vpo_hier_rhs(void* h, const double* f, const double* a, double* k);
+void vpo_hier_rk4_step(void* h, const double* f_in, double* f_out, double dt);
 
 /* regridding (section 3): refinement criterion and conservative limited interpolation */
 double vpo_tag_value(int nx, int nv, double dx, double dv, const double* vghost, const double* f, int i, int j);

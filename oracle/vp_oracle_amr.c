@@ -230,8 +230,8 @@ static double face4(double um1, double u0, double u1, double u2)
 /* Fluxes of section 2 on one patch from its ghosted data g ((nx+4) x (nv+4)):
  * Gx[(nx+1) x nv] for x faces -1/2 .. nx-1/2, Gv[nx x (nv+1)] for v faces
  * -1/2 .. nv-1/2.  a_ext[i + 1] = a at patch row i, i = -1 .. nx. */
-static void patch_fluxes(int nx, int nv, const double* g, double dv, double v0, const double* a_ext,
-                         double* Gx, double* Gv)
+void vpo_patch_fluxes(int nx, int nv, const double* g, double dv, double v0, const double* a_ext,
+                      double* Gx, double* Gv)
 {
     int W = nv + 4;
 #define G(i, j) g[(size_t)((i) + 2) * W + ((j) + 2)]
@@ -256,7 +256,7 @@ static void patch_fluxes(int nx, int nv, const double* g, double dv, double v0, 
 }
 
 /* flux divergence: k_ij = -(Gx_{i+1/2} - Gx_{i-1/2})/dx - (Gv_{j+1/2} - Gv_{j-1/2})/dv */
-static void divergence(int nx, int nv, const double* Gx, const double* Gv, double dx, double dv, double* k)
+void vpo_divergence(int nx, int nv, const double* Gx, const double* Gv, double dx, double dv, double* k)
 {
     for (int i = 0; i < nx; ++i)
         for (int j = 0; j < nv; ++j)
@@ -275,7 +275,7 @@ static void coarse_fluxes(const vpo_amr* c, const double* f, const double* a, do
         for (int j = -2; j < ncv + 2; ++j) g[(size_t)(i + 2) * W + j + 2] = coarse_at(c, f, i, j);
     double* ae = (double*)malloc(sizeof(double) * (ncx + 2));
     for (int i = -1; i <= ncx; ++i) ae[i + 1] = a[wrap(i, ncx)];
-    patch_fluxes(ncx, ncv, g, c->dvc, c->v_lo, ae, Gx, Gv);
+    vpo_patch_fluxes(ncx, ncv, g, c->dvc, c->v_lo, ae, Gx, Gv);
     free(ae);
     free(g);
 }
@@ -288,7 +288,7 @@ static void fine_patch_fluxes(const vpo_amr* c, double* f, const double* a, int 
     vpo_amr_fill_ghosts((void*)c, f, p, g);
     double* ae = (double*)malloc(sizeof(double) * (nxp + 2));
     for (int i = -1; i <= nxp; ++i) ae[i + 1] = a[c->ncx + wrap(x0 + i, c->nfx)];
-    patch_fluxes(nxp, nvp, g, c->dvf, c->v_lo + v0 * c->dvf, ae, Gx, Gv);
+    vpo_patch_fluxes(nxp, nvp, g, c->dvf, c->v_lo + v0 * c->dvf, ae, Gx, Gv);
     free(ae);
     free(g);
 }
@@ -315,7 +315,7 @@ void vpo_amr_rhs(void* h, double* f, double* a, double* k)
     for (int p = 0; p <= np; ++p) {
         int nx = p == 0 ? c->ncx : NXP(c, p - 1), nv = p == 0 ? c->ncv : NVP(c, p - 1);
         double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
-        divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
+        vpo_divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
         free(Gx[p]);
         free(Gv[p]);
     }
@@ -336,7 +336,7 @@ static void amr_update(const vpo_amr* c, const double* fn, double** Ax, double**
     /* ComputeUpdate: finest level first */
     for (int p = 1; p <= np && update_fine; ++p) {
         int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
-        divergence(nx, nv, Ax[p], Av[p], c->dxf, c->dvf, k + c->off[p - 1]);
+        vpo_divergence(nx, nv, Ax[p], Av[p], c->dxf, c->dvf, k + c->off[p - 1]);
         for (long q = 0; q < (long)nx * nv; ++q) f_out[c->off[p - 1] + q] = fn[c->off[p - 1] + q] + dt * k[c->off[p - 1] + q];
     }
     /* coarsen the fine accumulated fluxes onto the coarse-fine faces */
@@ -374,7 +374,7 @@ static void amr_update(const vpo_amr* c, const double* fn, double** Ax, double**
             if (left_cov != right_cov) { double v = left_cov ? *fN : *f0; *f0 = v; *fN = v; }
         }
     }
-    divergence(ncx, ncv, Ax[0], Av[0], c->dxc, c->dvc, k);
+    vpo_divergence(ncx, ncv, Ax[0], Av[0], c->dxc, c->dvc, k);
     for (long q = 0; q < (long)ncx * ncv; ++q) f_out[q] = fn[q] + dt * k[q];
     /* average fine data down onto covered coarse cells */
     for (int p = 0; p < np; ++p) {
@@ -421,7 +421,7 @@ void vpo_amr_rk4_step(void* h, double* f_in, double* f_out, double dt)
         for (int p = 0; p <= np; ++p) {
             int nx = p == 0 ? ncx : NXP(c, p - 1), nv = p == 0 ? ncv : NVP(c, p - 1);
             double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
-            divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
+            vpo_divergence(nx, nv, Gx[p], Gv[p], dx, dv, k + (p == 0 ? 0 : c->off[p - 1]));
             for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[p][q] += bw[s] * Gx[p][q];
             for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[p][q] += bw[s] * Gv[p][q];
         }
@@ -513,7 +513,7 @@ void vpo_amr_species_rk4_step(int ns, void* const* hs, double* const* f_in, doub
             for (int p = 0; p <= c->np; ++p) {
                 int nx = p == 0 ? c->ncx : NXP(c, p - 1), nv = p == 0 ? c->ncv : NVP(c, p - 1);
                 double dx = p == 0 ? c->dxc : c->dxf, dv = p == 0 ? c->dvc : c->dvf;
-                divergence(nx, nv, Gx[s][p], Gv[s][p], dx, dv, k[s] + (p == 0 ? 0 : c->off[p - 1]));
+                vpo_divergence(nx, nv, Gx[s][p], Gv[s][p], dx, dv, k[s] + (p == 0 ? 0 : c->off[p - 1]));
                 for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[s][p][q] += bw[st] * Gx[s][p][q];
                 for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[s][p][q] += bw[st] * Gv[s][p][q];
             }
@@ -633,7 +633,7 @@ void vpo_amr_subcycle_step(void* h, double* f_in, double* f_out, double dt)
         for (long q = 0; q < Nc; ++q) fs[q] = f_in[q] + (s > 0 ? alpha[s] * dt * K[s - 1][q] : 0.0);
         coarse_level_field(c, Pc, fs, a);
         coarse_fluxes(c, fs, a, Gx[0], Gv[0]);
-        divergence(ncx, ncv, Gx[0], Gv[0], c->dxc, c->dvc, K[s]);
+        vpo_divergence(ncx, ncv, Gx[0], Gv[0], c->dxc, c->dvc, K[s]);
         for (size_t q = 0; q < (size_t)(ncx + 1) * ncv; ++q) Ax[0][q] += bw[s] * Gx[0][q];
         for (size_t q = 0; q < (size_t)ncx * (ncv + 1); ++q) Av[0][q] += bw[s] * Gv[0][q];
     }
@@ -656,7 +656,7 @@ void vpo_amr_subcycle_step(void* h, double* f_in, double* f_out, double dt)
             for (int p = 1; p <= np; ++p) {
                 int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
                 fine_patch_fluxes(c, fs, a, p - 1, Gx[p], Gv[p]);
-                divergence(nx, nv, Gx[p], Gv[p], c->dxf, c->dvf, kf + c->off[p - 1]);
+                vpo_divergence(nx, nv, Gx[p], Gv[p], c->dxf, c->dvf, kf + c->off[p - 1]);
                 for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Sx[p][q] += bw[s] * Gx[p][q];
                 for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Sv[p][q] += bw[s] * Gv[p][q];
             }
@@ -664,7 +664,7 @@ void vpo_amr_subcycle_step(void* h, double* f_in, double* f_out, double dt)
         for (int p = 1; p <= np; ++p) {
             int nx = NXP(c, p - 1), nv = NVP(c, p - 1);
             double* kp = kf + c->off[p - 1];
-            divergence(nx, nv, Sx[p], Sv[p], c->dxf, c->dvf, kp);
+            vpo_divergence(nx, nv, Sx[p], Sv[p], c->dxf, c->dvf, kp);
             for (long q = 0; q < (long)nx * nv; ++q) f_out[c->off[p - 1] + q] += hs * kp[q];
             for (size_t q = 0; q < (size_t)(nx + 1) * nv; ++q) Ax[p][q] += Sx[p][q] / R;
             for (size_t q = 0; q < (size_t)nx * (nv + 1); ++q) Av[p][q] += Sv[p][q] / R;

@@ -253,6 +253,26 @@ def amr_landau(boxes, coarse=(512, 512), ratio: int = 4, eps: float = 0.01, k: f
     return _amr_state(maxwellian, 0.0, 4.0 * math.pi, -8.0, 8.0, eps, k, boxes, coarse, ratio)
 
 
+def hier_state(profile, x_lo, x_len, v_lo, v_hi, eps, k, coarse, ratios, boxes):
+    """Exact cell averages of (1 + eps cos(k x)) profile(v) on level 0 and on
+    every patch of a multi-level hierarchy (ratios[l-1] = (r_x, r_v) of
+    level l-1 -> l; boxes with "level" and inclusive lo/hi in that level's
+    indices), concatenated as [level 0][boxes in order]; returns
+    (state, [equilibrium with ghosts of each level])."""
+    nx, nv = [coarse[0]], [coarse[1]]
+    for rx, rv in ratios:
+        nx.append(nx[-1] * rx)
+        nv.append(nv[-1] * rv)
+    veqs = [cell_average_1d(profile, v_lo, v_hi, n, first=-2, count=n + 4) for n in nv]
+    xs = [1.0 + eps * cos_cell_average(x_lo, x_len, n, k) for n in nx]
+    parts = [(xs[0][:, None] * veqs[0][None, 2:nv[0] + 2]).ravel()]
+    for b in boxes:
+        lv = b["level"]
+        (x0, v0), (x1, v1) = b["lo"], b["hi"]
+        parts.append((xs[lv][x0:x1 + 1, None] * veqs[lv][None, 2 + v0:2 + v1 + 1]).ravel())
+    return np.concatenate(parts), veqs
+
+
 # bump-on-tail problem of the numerical results (section 4)
 BUMP_X_LO = -10.0 * math.pi / 3.0
 BUMP_X_LEN = 20.0 * math.pi / 3.0
