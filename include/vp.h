@@ -56,7 +56,7 @@ typedef enum vp_status {
 
 typedef enum vp_dtype { VP_F64 = 0, VP_F32 = 1 } vp_dtype;
 
-#define VP_MAX_LEVELS 2
+#define VP_MAX_LEVELS 4
 
 /*
  * Problem statement (section 2 of the paper; the box hierarchy of
@@ -65,9 +65,12 @@ typedef enum vp_dtype { VP_F64 = 0, VP_F32 = 1 } vp_dtype;
  *
  *   ndim      N = M, the number of configuration (= velocity) dimensions: 1 or 2
  *   dtype     element type of the phase-space state (vp_dtype)
- *   n_levels  1 (uniform mesh) or 2 (coarse level plus level-1 patches)
+ *   n_levels  1 (uniform mesh) .. VP_MAX_LEVELS (level 0 plus patches on
+ *             levels 1 .. n_levels-1)
  *   cells     level-0 cells per direction
- *   ratio     level-0 -> level-1 refinement ratio per direction (n_levels == 2)
+ *   ratio     ratio[l][d]: refinement ratio of level l -> level l+1 along
+ *             direction d (configuration directions first, then velocity),
+ *             l < n_levels - 1; section 4 runs [2,4], [4,2], [2,2]
  *   x_lo, x_len  periodic configuration box [x_lo, x_lo + x_len) per direction
  *   v_lo, v_hi   truncated velocity box per velocity direction
  *   qm        charge-to-mass ratio of the species (-1 for electrons)
@@ -87,7 +90,7 @@ typedef struct vp_problem {
     int32_t dtype;
     int32_t n_levels;
     int32_t cells[4];
-    int32_t ratio[4];
+    int32_t ratio[VP_MAX_LEVELS - 1][4];
     double x_lo[2];
     double x_len[2];
     double v_lo[2];

@@ -14,18 +14,6 @@
 
 namespace vp {
 
-namespace {
-
-struct Box {
-    int xlo, vlo, xhi, vhi;   // inclusive
-    bool empty() const { return xlo > xhi || vlo > vhi; }
-};
-
-Box intersect(const Box& a, const Box& b)
-{
-    return Box{std::max(a.xlo, b.xlo), std::max(a.vlo, b.vlo), std::min(a.xhi, b.xhi), std::min(a.vhi, b.vhi)};
-}
-
 // b_j(s) of the fifth-order conservative sub-cell interpolation (section 3),
 // with p_k(s) = ((s+1)^{k+1} - s^{k+1}) / R^k
 std::vector<double> interp_table(int R)
@@ -44,6 +32,18 @@ std::vector<double> interp_table(int R)
     return B;
 }
 
+namespace {
+
+struct Box {
+    int xlo, vlo, xhi, vhi;   // inclusive
+    bool empty() const { return xlo > xhi || vlo > vhi; }
+};
+
+Box intersect(const Box& a, const Box& b)
+{
+    return Box{std::max(a.xlo, b.xlo), std::max(a.vlo, b.vlo), std::min(a.xhi, b.xhi), std::min(a.vhi, b.vhi)};
+}
+
 template <typename T>
 hipError_t upload(T** dst, const std::vector<T>& v)
 {
@@ -58,39 +58,6 @@ hipError_t upload(T** dst, const std::vector<T>& v)
 char* wsp(void* work, size_t off) { return static_cast<char*>(work) + off; }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// host tables packed into one device allocation and one copy: add() records
-// each table, commit() allocates, copies and sets the device pointers
-struct TableArena {
-    struct Item {
-        void** dst;
-        const void* src;
-        size_t bytes, off;
-    };
-    std::vector<Item> items;
-    size_t total = 0;
-    template <typename T>
-    void add(T** dst, const std::vector<T>& v)
-    {
-        *dst = nullptr;
-        if (v.empty()) return;
-        items.push_back(Item{reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T), total});
-        total += align256(v.size() * sizeof(T));
-    }
-    hipError_t commit(void** base)
-    {
-        *base = nullptr;
-        if (total == 0) return hipSuccess;
-        std::vector<char> host(total, 0);
-        for (const Item& it : items) std::memcpy(host.data() + it.off, it.src, it.bytes);
-        hipError_t e = hipMalloc(base, total);
-        if (e != hipSuccess) return e;
-        e = hipMemcpy(*base, host.data(), total, hipMemcpyHostToDevice);
-        if (e != hipSuccess) return e;
-        for (const Item& it : items) *it.dst = static_cast<char*>(*base) + it.off;
-        return hipSuccess;
-    }
-};
 
 // tile table for the shape (nt, w, tx)
 void build_tiles(AmrPlan& A)
@@ -268,8 +235,8 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
 {
     if (pb->ndim != 1) return fail(VP_ENOTSUP, "two levels are supported for 1D+1V");
     if (pb->dtype != VP_F64) return fail(VP_ENOTSUP, "two levels are supported in FP64");
-    const int R = pb->ratio[0];
-    if (pb->ratio[1] != R || (R != 2 && R != 4)) return fail(VP_ENOTSUP, "refinement ratio must be 2 or 4, equal in x and v");
+    const int R = pb->ratio[0][0];
+    if (pb->ratio[0][1] != R || (R != 2 && R != 4)) return fail(VP_ENOTSUP, "refinement ratio must be 2 or 4, equal in x and v");
     if (!pb->veq[1][0]) return fail(VP_EINVAL, "veq[1][0] (level-1 equilibrium with ghosts) is required");
     AmrPlan* M = new AmrPlan();
     p->amr = M;

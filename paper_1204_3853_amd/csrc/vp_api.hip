@@ -204,9 +204,10 @@ vp_status scratch_address(void** out)
     return VP_OK;
 }
 
-// two-level plan: geometry, box calculus and tables (vp_amr.hip), then the
-// Poisson tables of the finest configuration mesh
-vp_status create_two_level(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out)
+// plan of two or more levels: geometry, box calculus and tables (two-level
+// engine in vp_amr.hip, multi-level engine in vp_hier.hip), then the Poisson
+// tables of the finest configuration mesh
+vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out)
 {
     vp_plan* p = new (std::nothrow) vp_plan();
     if (!p) return fail(VP_ENOMEM, "out of host memory");
@@ -217,24 +218,43 @@ vp_status create_two_level(const vp_problem* pb, const vp_box* boxes, int nbox, 
     p->esize = pb->dtype == VP_F64 ? 8 : 4;
     for (int l = 0; l < VP_MAX_LEVELS; ++l)
         for (int d = 0; d < 2; ++d) p->pb.veq[l][d] = nullptr;
-    vp_status st = amr_create(p, pb, boxes, nbox);
+    p->nlev = pb->n_levels;
+    // two levels with one ratio (2 or 4) in x and v take the two-level engine
+    // (ghost interpolation fused into the stage tiles, subcycling, species,
+    // adaptive runs); deeper or anisotropic hierarchies the multi-level one
+    const bool two = pb->n_levels == 2 && pb->ratio[0][0] == pb->ratio[0][1] &&
+                     (pb->ratio[0][0] == 2 || pb->ratio[0][0] == 4);
+    vp_status st = two ? amr_create(p, pb, boxes, nbox) : hier_create(p, pb, boxes, nbox);
     if (st == VP_OK) {
         // kept so that a plan of another hierarchy can be made from this one
-        p->veq[0][0].assign(pb->veq[0][0], pb->veq[0][0] + pb->cells[1] + 4);
-        p->veq[1][0].assign(pb->veq[1][0], pb->veq[1][0] + pb->cells[1] * pb->ratio[1] + 4);
+        int nv = pb->cells[1];
+        for (int l = 0; l < pb->n_levels; ++l) {
+            if (l > 0) nv *= pb->ratio[l - 1][1];
+            p->veq[l][0].assign(pb->veq[l][0], pb->veq[l][0] + nv + 4);
+        }
     }
     if (st != VP_OK) {
         amr_destroy(p);
+        hier_destroy(p);
         delete p;
         return st;
     }
-    const AmrPlan& M = *p->amr;
     // the configuration-space calls act on the finest configuration mesh
-    p->nx = M.nfx;
-    p->nv = M.nfv;
-    p->dx = M.dxf;
-    p->dv = M.dvf;
-    p->v_lo = M.v_lo;
+    if (p->amr) {
+        const AmrPlan& M = *p->amr;
+        p->nx = M.nfx;
+        p->nv = M.nfv;
+        p->dx = M.dxf;
+        p->dv = M.dvf;
+        p->v_lo = M.v_lo;
+    } else {
+        const HierPlan& H = *p->hier;
+        p->nx = H.lv[H.L - 1].nx;
+        p->nv = H.lv[H.L - 1].nv;
+        p->dx = H.dxf;
+        p->dv = H.lv[H.L - 1].dv;
+        p->v_lo = pb->v_lo[0];
+    }
     std::vector<double> g = tridiag_green(p->nx, kGreenTaps);
     p->gk = kGreenTaps;
     hipError_t e = hipMalloc(&p->d_green, g.size() * sizeof(double));
@@ -245,6 +265,7 @@ vp_status create_two_level(const vp_problem* pb, const vp_box* boxes, int nbox, 
         st = hip_fail(e, "vp_plan_create: Poisson tables");
         if (p->d_green) (void)hipFree(p->d_green);
         amr_destroy(p);
+        hier_destroy(p);
         delete p;
         return st;
     }
@@ -295,7 +316,7 @@ std::vector<StageShape> amr_shape_table()
 std::vector<StageShape> plan_shapes(const vp_plan* p)
 {
     if (p->p4) return shape_table_4d();
-    return p->amr ? amr_shape_table() : shape_table(p->dtype);
+    return (p->amr || p->hier) ? amr_shape_table() : shape_table(p->dtype);
 }
 
 }  // namespace
@@ -328,7 +349,7 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
     *out = nullptr;
     if (pb->ndim != 1 && pb->ndim != 2) return fail(VP_EINVAL, "ndim must be 1 or 2");
     if (pb->dtype != VP_F64 && pb->dtype != VP_F32) return fail(VP_EDTYPE, "dtype must be VP_F64 or VP_F32");
-    if (pb->n_levels < 1 || pb->n_levels > VP_MAX_LEVELS) return fail(VP_EINVAL, "n_levels must be 1 or 2");
+    if (pb->n_levels < 1 || pb->n_levels > VP_MAX_LEVELS) return fail(VP_EINVAL, "n_levels must be 1 .. 4");
     if (nbox < 0 || (nbox > 0 && !boxes)) return fail(VP_EINVAL, "bad box list");
     const int nd = 2 * pb->ndim;
     for (int d = 0; d < nd; ++d)
@@ -338,7 +359,7 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
         if (!(pb->v_hi[d] > pb->v_lo[d])) return fail(VP_EINVAL, "v_hi must exceed v_lo");
         if (!pb->veq[0][d]) return fail(VP_EINVAL, "veq[0][d] (equilibrium with ghosts) is required");
     }
-    if (pb->n_levels == 2) return create_two_level(pb, boxes, nbox, out);
+    if (pb->n_levels >= 2) return create_multi_level(pb, boxes, nbox, out);
     if (nbox != 0) return fail(VP_EINVAL, "a single-level plan takes no boxes");
     if (pb->ndim == 2) return create_4d(pb, out);
 
@@ -426,6 +447,9 @@ vp_status vp_tile_shape_set(vp_plan* p, int32_t index)
     if (p->amr) {
         if (vp_status s = amr_set_shape(p, tab[index].nt, tab[index].w, tab[index].tx)) return s;
     }
+    if (p->hier) {
+        if (vp_status s = hier_set_shape(p, tab[index].nt, tab[index].w, tab[index].tx)) return s;
+    }
     if (p->p4) {
         p->p4->tile_x = tab[index].w;
         p->p4->tile_y = tab[index].tx;
@@ -439,7 +463,7 @@ vp_status vp_face_scheme_set(vp_plan* p, int32_t scheme)
     if (vp_status s = check_plan(p)) return s;
     if (scheme != VP_FACE_CENTERED && scheme != VP_FACE_LIMITED)
         return fail(VP_EINVAL, "vp_face_scheme_set: unknown scheme");
-    if (scheme == VP_FACE_LIMITED && (p->amr || p->p4))
+    if (scheme == VP_FACE_LIMITED && (p->amr || p->hier || p->p4))
         return fail(VP_ENOTSUP, "vp_face_scheme_set: limited faces are built for single-level 1D+1V plans");
     p->face_scheme = scheme;
     return VP_OK;
@@ -451,6 +475,8 @@ vp_status vp_reduction_set(vp_plan* p, int32_t algorithm)
     if (algorithm != VP_REDUCE_SUBPATCH && algorithm != VP_REDUCE_MASK)
         return fail(VP_EINVAL, "vp_reduction_set: unknown algorithm");
     if (p->amr) p->amr->reduce_mode = algorithm;
+    if (p->hier && algorithm != VP_REDUCE_SUBPATCH)
+        return fail(VP_ENOTSUP, "vp_reduction_set: multi-level plans use the Sub-Patch reduction");
     return VP_OK;
 }
 
@@ -460,6 +486,8 @@ vp_status vp_launch_mode_set(vp_plan* p, int32_t mode)
     if (mode != VP_LAUNCH_PERSISTENT && mode != VP_LAUNCH_PER_PATCH)
         return fail(VP_EINVAL, "vp_launch_mode_set: unknown mode");
     if (p->amr) p->amr->mode = mode;
+    if (p->hier && mode != VP_LAUNCH_PERSISTENT)
+        return fail(VP_ENOTSUP, "vp_launch_mode_set: multi-level plans use the persistent launch");
     return VP_OK;
 }
 
@@ -551,6 +579,7 @@ vp_status vp_plan_destroy(vp_plan* p)
         if (e) (void)hipEventDestroy(e);
     if (p->d_green) (void)hipFree(p->d_green);
     amr_destroy(p);
+    hier_destroy(p);
     p4_destroy(p);
     delete p;
     return VP_OK;
@@ -563,6 +592,7 @@ int64_t vp_patch_offset(const vp_plan* p, int32_t patch)
     if (!p) return -1;
     if (patch == -1) return 0;
     if (p->amr && patch >= 0 && patch < (int32_t)p->amr->patches.size()) return p->amr->patches[patch].off;
+    if (p->hier && patch >= 0 && patch + 1 < (int32_t)p->hier->patches.size()) return p->hier->patches[patch + 1].off;
     return -1;
 }
 
@@ -571,13 +601,14 @@ size_t vp_field_elems(const vp_plan* p)
 {
     if (!p) return 0;
     if (p->p4) return 2 * (size_t)p->nx;
+    if (p->hier) return (size_t)p->hier->na;
     return p->amr ? (size_t)(p->amr->ncx + p->amr->nfx) : (size_t)p->nx;
 }
 size_t vp_workspace_bytes(const vp_plan* p) { return p ? p->ws_total : 0; }
 
 size_t vp_stage_elems(const vp_plan* p)
 {
-    if (!p || p->amr || p->p4) return 0;
+    if (!p || p->amr || p->hier || p->p4) return 0;
     const size_t a_bytes = 4 * (size_t)p->nx * sizeof(double);
     return 3 * p->state_elems + (a_bytes + p->esize - 1) / p->esize;
 }
@@ -588,6 +619,7 @@ vp_status vp_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipS
     if (!f || !a || !k) return fail(VP_EINVAL, "vp_rhs: NULL pointer");
     if (f == k) return fail(VP_EINVAL, "vp_rhs: k must not alias f");
     if (p->amr) return amr_rhs(p, f, a, k, stream);
+    if (p->hier) return hier_rhs(p, f, a, k, stream);
     if (p->p4) return p4_rhs(p, f, a, k, stream);
     const StageShape sh = pick_shape(p, {f, k});
     Stage1DArgs A = base_args(p, sh);
@@ -605,6 +637,10 @@ vp_status vp_reduce_moment(const vp_plan* p, const void* f, double* n, void* wor
     if (p->amr) {
         if (!work) return fail(VP_EINVAL, "vp_reduce_moment: a two-level plan needs the workspace");
         return amr_reduce(p, f, n, work, stream);
+    }
+    if (p->hier) {
+        if (!work) return fail(VP_EINVAL, "vp_reduce_moment: a multi-level plan needs the workspace");
+        return hier_reduce(p, f, n, work, stream);
     }
     if (p->p4) return p4_reduce(p, f, n, stream);
     VP_HIP(timed(p, kTMoment, stream, [&] { return launch_moment_rows(p->dtype, f, p->nx, p->nv, p->dv, n, stream); }));
@@ -630,6 +666,7 @@ vp_status vp_inject_field(const vp_plan* p, const double* E, double* a, hipStrea
     if (vp_status s = check_plan(p)) return s;
     if (!E || !a) return fail(VP_EINVAL, "vp_inject_field: NULL pointer");
     if (p->amr) return amr_inject(p, E, a, stream);
+    if (p->hier) return hier_inject(p, E, a, stream);
     if (p->p4) {
         VP_HIP(timed(p, kTOther, stream, [&] { return launch_scale(E, p->pb.qm, a, 2 * p->nx, stream); }));
         return VP_OK;
@@ -644,6 +681,7 @@ vp_status vp_rk4_step(const vp_plan* p, void* f, double* a, double dt, void* wor
     if (!f || !a || !work) return fail(VP_EINVAL, "vp_rk4_step: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step: dt is not finite");
     if (p->amr) return amr_rk4(p, f, a, dt, work, stream);
+    if (p->hier) return hier_rk4(p, f, a, dt, work, stream);
     if (p->p4) return p4_rk4(p, f, a, dt, work, stream);
     return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
 }
@@ -653,7 +691,7 @@ vp_status vp_rk4_step_noalloc(const vp_plan* p, void* f, double* a, double dt, h
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a) return fail(VP_EINVAL, "vp_rk4_step_noalloc: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_noalloc: dt is not finite");
-    if (p->amr || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_noalloc: single-level 1D+1V plans only");
+    if (p->amr || p->hier || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_noalloc: single-level 1D+1V plans only");
     if (p->ws_step > kScratchBytes)
         return fail(VP_ESHAPE, "vp_rk4_step_noalloc: the step needs " + std::to_string(p->ws_step) +
                                    " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
@@ -678,7 +716,7 @@ vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, vo
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a || !work || !stages) return fail(VP_EINVAL, "vp_rk4_step_record: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_record: dt is not finite");
-    if (p->amr || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level 1D+1V plans only");
+    if (p->amr || p->hier || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level 1D+1V plans only");
     if (p->face_scheme != VP_FACE_CENTERED)
         return fail(VP_ENOTSUP, "vp_rk4_step_record: the adjoint is built for the centred (unlimited) scheme");
     double* st_a = reinterpret_cast<double*>(static_cast<char*>(stages) + 3 * p->state_elems * p->esize);
@@ -691,7 +729,7 @@ vp_status vp_field_adjoint(const vp_plan* p, const double* abar, void* fbar, voi
     if (vp_status s = check_plan(p)) return s;
     if (!abar || !fbar || !work) return fail(VP_EINVAL, "vp_field_adjoint: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_field_adjoint: FP64 only");
-    if (p->amr || p->p4) return fail(VP_ENOTSUP, "vp_field_adjoint: single-level 1D+1V plans only");
+    if (p->amr || p->hier || p->p4) return fail(VP_ENOTSUP, "vp_field_adjoint: single-level 1D+1V plans only");
     double* cfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
     double* ab = cfg;
     double* z = cfg + p->nx;
@@ -711,7 +749,7 @@ vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, 
     if (vp_status s = check_plan(p)) return s;
     if (!f_n || !a_n || !lam_np1 || !lam_n || !work) return fail(VP_EINVAL, "vp_adjoint_step: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is FP64 only");
-    if (p->amr || p->p4 || p->nlev != 1 || p->ndim != 1)
+    if (p->amr || p->hier || p->p4 || p->nlev != 1 || p->ndim != 1)
         return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
     if (p->face_scheme != VP_FACE_CENTERED)
         return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is built for the centred (unlimited) scheme");

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -152,6 +153,97 @@ struct AmrArgs {
     double c_flux;             // b_s (0: no accumulation)
     int first;                 // first stage: store instead of add
 };
+
+// ----------------------------------------------------------------- multi-level hierarchies
+
+constexpr int kHierLevels = VP_MAX_LEVELS;
+
+struct HLevel {                // one level of a multi-level hierarchy
+    int nx, nv;                // index space
+    int rx, rv;                // ratio from the parent level (1 on level 0)
+    int rt;                    // x ratio from this level to the finest
+    int a_off;                 // offset of the level's acceleration in a
+    double dxi, dvi, dv24, dv;
+};
+
+struct HPatch {                // a patch of a multi-level hierarchy (level 0 is patch 0)
+    long long off;             // element offset of its cells in the state
+    long long frame;           // its ghost frame: rows -2, -1, nx, nx+1 (nv + 4 each, column c <-> j = c - 2),
+                               // then columns -2, -1, nv, nv+1 of each interior row
+    long long foff;            // boundary-flux block: [x lo: nv][x hi: nv][v lo: nx][v hi: nx]
+    int lev, gx0, gv0, nx, nv;
+    int pad;
+};
+
+// Source of a frame cell or of a face-stencil value: src >= 0 is a state
+// element; src < 0 the equilibrium ghost value eqv[-1 - src].
+struct HInterp {               // a ghost cell interpolated from the parent level
+    int src[25];               // parent cells (ci + a, cj + b) at src[(a + 2) * 5 + b + 2]
+    int lev, s, t;             // the fine cell's level and its sub-cell position in x and v
+};
+
+struct HFace {                 // a face of level l on a coarse-fine interface with level l + 1
+    int src[12];               // x face: cells (i-1 .. i+2) x (j-1 .. j+1) at src[(m + 1) * 4 + q],
+                               // v face: cells (i-1 .. i+1) x (j-1 .. j+2) at src[(m + 1) * 4 + q]
+    int dir, lev;              // 0: x face, 1: v face
+    int ai[3];                 // v face: absolute indices of a at i-1, i, i+1
+    int pad;
+    double vb;                 // x face: cell-centre velocity of row j
+};
+
+struct HierArgs {
+    HLevel lv[kHierLevels];
+    const HPatch* patches;
+    const AmrTile* tiles;
+    int tx;                    // rows per tile
+    double v_lo;
+    const double* fs;          // stage input (whole hierarchy)
+    const double* fn;
+    double* acc;
+    double* fout;
+    const double* a;           // acceleration of every level
+    const double* frame;       // ghost frames of fs
+    const double* eqv;         // equilibrium ghost values, 4 per level (j = -2, -1, nv, nv+1)
+    const HFace* faces;
+    double* cf_acc;            // accumulated coarse fluxes on the listed faces
+    double* ff_acc;            // accumulated patch boundary fluxes
+    double c_acc, c_next, c_flux;
+    int first;
+};
+
+struct HierSyncArgs {
+    double* f;
+    HLevel lv[kHierLevels];
+    double dt;
+    const HFace* faces;
+    const double* cf_acc;
+    const double* ff_acc;
+    const int* corr_ptr;       // per corrected cell: its faces corr_face[corr_ptr[k] .. corr_ptr[k+1])
+    const int* corr_face;      // face index, negative (-1 - index) when the face is the cell's lower face
+    const long long* corr_cell;
+    const long long* corr_fine;  // per face: first of its fine faces in ff_acc
+    const int* corr_nfine;       // per face: number of fine faces
+    int ncorr;
+};
+
+struct HierAvgArgs {           // covered cells of one level take the mean of the next finer level
+    double* f;
+    const long long* dst;
+    const long long* src;      // first fine cell
+    const int* stride;         // fine row length
+    int rx, rv, n;
+};
+
+hipError_t launch_hier_fill(const double* f, const int2* desc, const HInterp* rec, const double* wts,
+                            const int* wofs, const double* eqv, double* frame, int n, hipStream_t stream);
+hipError_t launch_hier_stage(int w, int nt, int kind, const HierArgs& a, int t_begin, int t_end, int grid,
+                             hipStream_t stream);
+hipError_t launch_hier_rowsum(const double* f, const double* frame, const long long* task_off, const int* task_len,
+                              int ntasks, double* slots, hipStream_t stream);
+hipError_t launch_hier_inject(const double* E, const HLevel* lv, int L, double qm, double* a, int na,
+                              hipStream_t stream);
+hipError_t launch_hier_reflux(const HierSyncArgs& s, hipStream_t stream);
+hipError_t launch_hier_average(const HierAvgArgs& s, hipStream_t stream);
 
 // Optional inputs and outputs of the 1D Poisson kernel for two-level plans:
 // the moment taken from a fixed-order weighted list over row-sum slots, and
@@ -344,6 +436,52 @@ struct AmrPlan {
     size_t ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0, ws_fld = 0;
     size_t ws_hist = 0, ws_nc = 0, hist_stride = 0;
 };
+
+// multi-level plan (vp_hier.hip): L levels, a ratio per level and direction
+struct HierPlan {
+    int L = 2;
+    int na = 0;                                      // elements of a: every level's configuration mesh
+    double dxf = 0;                                  // finest configuration cell
+    HLevel lv[kHierLevels] = {};
+    std::vector<HPatch> patches;                     // patch 0 is level 0
+    std::vector<double> eqv;                         // 4 per level
+    size_t total = 0, frame_elems = 0, fflux = 0;
+    int nframe = 0, nfaces = 0;
+    int nt = 64, w = 1, tx = 8;
+    int ntiles = 0, face_tile_begin = 0;
+    std::vector<AmrTile> tiles;
+    void* d_tables = nullptr;
+    AmrTile* d_tiles = nullptr;
+    HPatch* d_patches = nullptr;
+    int2* d_desc = nullptr;
+    HInterp* d_rec = nullptr;
+    double* d_wts = nullptr;
+    int* d_wofs = nullptr;                           // per level: offsets of its x and v weight tables in d_wts
+    double* d_eqv = nullptr;
+    HFace* d_faces = nullptr;
+    HLevel* d_lv = nullptr;
+    int ntasks = 0;
+    long long* d_task_off = nullptr;                 // >= 0: state offset; < 0: frame offset -1 - off
+    int* d_task_len = nullptr;
+    int* d_rowptr = nullptr;
+    int* d_idx = nullptr;
+    double* d_w = nullptr;
+    int ncorr = 0;
+    int* d_corr_ptr = nullptr;
+    int* d_corr_face = nullptr;
+    long long* d_corr_cell = nullptr;
+    long long* d_corr_fine = nullptr;
+    int* d_corr_nfine = nullptr;
+    struct Avg {
+        int rx = 1, rv = 1, n = 0;
+        long long* d_dst = nullptr;
+        long long* d_src = nullptr;
+        int* d_stride = nullptr;
+    };
+    Avg avg[kHierLevels];                            // avg[l]: level-l cells covered by level l + 1
+    double* d_rhs_frame = nullptr;                   // frames for vp_rhs, which takes no workspace
+    size_t ws_frame = 0, ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0, ws_fld = 0;
+};
 }  // namespace vp
 
 // ----------------------------------------------------------------- 2D+2V plan
@@ -394,6 +532,7 @@ struct vp_plan {
     mutable Timing timing;
     vp::AmrPlan* amr = nullptr;
     vp::Plan4D* p4 = nullptr;
+    vp::HierPlan* hier = nullptr;
 };
 
 namespace vp {
@@ -413,6 +552,52 @@ struct Rk4Setup1D {
 Rk4Setup1D rk4_setup_1d(const vp_plan* p, void* f, void* work, double dt, void* st_f);
 // the arguments of stage s (0..3) with the acceleration a
 Stage1DArgs rk4_stage_args_1d(const Rk4Setup1D& R, int s, const double* a);
+
+// host tables packed into one device allocation and one copy: add() records
+// each table, commit() allocates, copies and sets the device pointers
+struct TableArena {
+    struct Item {
+        void** dst;
+        const void* src;
+        size_t bytes, off;
+    };
+    std::vector<Item> items;
+    size_t total = 0;
+    template <typename T>
+    void add(T** dst, const std::vector<T>& v)
+    {
+        *dst = nullptr;
+        if (v.empty()) return;
+        items.push_back(Item{reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T), total});
+        total += (v.size() * sizeof(T) + 255) & ~size_t(255);
+    }
+    hipError_t commit(void** base)
+    {
+        *base = nullptr;
+        if (total == 0) return hipSuccess;
+        std::vector<char> host(total, 0);
+        for (const Item& it : items) std::memcpy(host.data() + it.off, it.src, it.bytes);
+        hipError_t e = hipMalloc(base, total);
+        if (e != hipSuccess) return e;
+        e = hipMemcpy(*base, host.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+        for (const Item& it : items) *it.dst = static_cast<char*>(*base) + it.off;
+        return hipSuccess;
+    }
+};
+
+// b_j(s) of the conservative fifth-order sub-cell interpolation for ratio R
+// (section 3), R x 5 values at [s * 5 + j + 2] (vp_amr.hip)
+std::vector<double> interp_table(int R);
+
+// multi-level host sequences (vp_hier.hip)
+vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);
+void hier_destroy(vp_plan* p);
+vp_status hier_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream);
+vp_status hier_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream);
+vp_status hier_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
+vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
+vp_status hier_set_shape(vp_plan* p, int nt, int w, int tx);
 
 // two-level host sequences (vp_amr.hip)
 vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);

@@ -31,7 +31,7 @@ struct Level0 {
 
 bool level0_of(const vp_plan* p, Level0& L)
 {
-    if (!p || p->p4 || p->ndim != 1) return false;
+    if (!p || p->p4 || p->hier || p->ndim != 1) return false;
     if (p->amr) {
         const AmrPlan& M = *p->amr;
         L = Level0{M.ncx, M.ncv, M.dxc, M.dvc, M.vgc};

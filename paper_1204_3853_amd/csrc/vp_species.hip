@@ -120,6 +120,7 @@ vp_status vp_species_group_create(const vp_plan* const* plans, const double* cha
         const vp_plan* p = plans[s];
         if (!p) return fail(VP_EINVAL, "vp_species_group_create: NULL plan");
         if (p->p4 || p->ndim != 1) return fail(VP_ENOTSUP, "vp_species_group_create: 1D+1V plans only");
+        if (p->hier) return fail(VP_ENOTSUP, "vp_species_group_create: single-level or two-level plans only");
         if (!std::isfinite(charge[s])) return fail(VP_EINVAL, "vp_species_group_create: charges must be finite");
         if (p->dtype != p0->dtype) return fail(VP_EINVAL, "vp_species_group_create: the plans differ in dtype");
         if (p->nx != p0->nx || p->pb.x_lo[0] != p0->pb.x_lo[0] || p->pb.x_len[0] != p0->pb.x_len[0])

@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvp.so")
 
 VP_F64, VP_F32 = 0, 1
-VP_MAX_LEVELS = 2
+VP_MAX_LEVELS = 4
 _STATUS = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ESHAPE", 3: "VP_EDTYPE", 4: "VP_ENOTSUP", 5: "VP_EHIP",
            6: "VP_ENOMEM"}
 
@@ -34,7 +34,7 @@ class vp_problem(ctypes.Structure):
         ("dtype", ctypes.c_int32),
         ("n_levels", ctypes.c_int32),
         ("cells", ctypes.c_int32 * 4),
-        ("ratio", ctypes.c_int32 * 4),
+        ("ratio", (ctypes.c_int32 * 4) * (VP_MAX_LEVELS - 1)),
         ("x_lo", ctypes.c_double * 2),
         ("x_len", ctypes.c_double * 2),
         ("v_lo", ctypes.c_double * 2),
@@ -174,8 +174,12 @@ def _make_problem(spec, dtype):
     pb.n_levels = spec.get("n_levels", 1)
     for d, c in enumerate(spec["cells"]):
         pb.cells[d] = c
-    for d, r in enumerate(spec.get("ratio", [1, 1, 1, 1])):
-        pb.ratio[d] = r
+    ratios = spec.get("ratios")
+    if ratios is None:                       # one ratio vector: level 0 -> level 1
+        ratios = [spec.get("ratio", [1, 1, 1, 1])]
+    for lvl, rv in enumerate(ratios):
+        for d, r in enumerate(rv):
+            pb.ratio[lvl][d] = r
     for d in range(spec["ndim"]):
         pb.x_lo[d] = spec["x_lo"][d]
         pb.x_len[d] = spec["x_len"][d]
@@ -308,6 +312,15 @@ def two_level_spec(ncx, ncv, x_len, v_lo, v_hi, qm, ratio, veq_c, veq_f, x_lo=0.
     """Problem spec of a two-level 1D+1V hierarchy (level 0: ncx x ncv)."""
     return {"ndim": 1, "n_levels": 2, "cells": [ncx, ncv], "ratio": [ratio, ratio], "x_lo": [x_lo],
             "x_len": [x_len], "v_lo": [v_lo], "v_hi": [v_hi], "qm": qm, "veq": [[veq_c], [veq_f]]}
+
+
+def hierarchy_spec(ncx, ncv, x_len, v_lo, v_hi, qm, ratios, veqs, x_lo=0.0):
+    """Problem of a 1D+1V hierarchy of len(ratios) + 1 levels: ratios[l] =
+    (r_x, r_v) of level l -> l+1; veqs[l]: level-l equilibrium with two ghost
+    cells per side."""
+    return {"ndim": 1, "n_levels": len(ratios) + 1, "cells": [ncx, ncv], "ratios": [list(r) for r in ratios],
+            "x_lo": [x_lo], "x_len": [x_len], "v_lo": [v_lo], "v_hi": [v_hi], "qm": qm,
+            "veq": [[list(v)] for v in veqs]}
 
 
 def _problem_dict(p):

@@ -26,7 +26,7 @@ def make_problem(V, ncx=32, ncv=48, R=4, dtype=0, ndim=1):
     pb.dtype = dtype
     pb.n_levels = 2
     pb.cells[0], pb.cells[1] = ncx, ncv
-    pb.ratio[0], pb.ratio[1] = R, R
+    pb.ratio[0][0], pb.ratio[0][1] = R, R
     pb.x_len[0] = 4 * math.pi
     pb.v_lo[0], pb.v_hi[0] = -8.0, 8.0
     pb.qm = -1.0
