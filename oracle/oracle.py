@@ -110,6 +110,8 @@ def _declare_extra(L):
         "vpo_hier_constraints": (None, [_V, _D, _D, _D]),
         "vpo_hier_rhs": (None, [_V, _D, _D, _D]),
         "vpo_hier_rk4_step": (None, [_V, _D, _D, _F]),
+        "vpo_hier_tag_values": (None, [_V, _D, _I, _D]),
+        "vpo_hier_prolong_box": (_I, [_V, _D, _I, _I, _I, _I, _I, _D]),
         "vpo_amr_species_constraints": (None, [_I, ctypes.POINTER(_V), ctypes.POINTER(_D), _D, _F,
                                                ctypes.POINTER(_D)]),
         "vpo_amr_species_rk4_step": (None, [_I, ctypes.POINTER(_V), ctypes.POINTER(_D), ctypes.POINTER(_D), _D,
@@ -528,6 +530,7 @@ class OracleHier:
 
     def __init__(self, L, ncx, ncv, x_len, v_lo, v_hi, qm, ratios, boxes, veqs):
         self.L, self.ncx, self.ncv = L, ncx, ncv
+        self.x_len_ = x_len
         self.ratios = [tuple(r) for r in ratios]
         self.boxes = boxes
         self.nx, self.nv = [ncx], [ncv]
@@ -602,6 +605,82 @@ class OracleHier:
         out = np.empty_like(f)
         lib().vpo_hier_rk4_step(self.h, _p(f), _p(out), dt)
         return out
+
+    def tag_values(self, f, level):
+        """delta1 f + delta2 f on the cells level `level` holds (NaN elsewhere)"""
+        f = _f64(f)
+        out = np.empty(self.nx[level] * self.nv[level])
+        lib().vpo_hier_tag_values(self.h, _p(f), level, _p(out))
+        return out.reshape(self.nx[level], self.nv[level])
+
+    def prolong_box(self, f, level, lo, hi):
+        """WENO5 prolongation of level-1 data into the level-`level` box [lo, hi]"""
+        f = _f64(f)
+        out = np.empty((hi[0] - lo[0] + 1, hi[1] - lo[1] + 1))
+        ok = lib().vpo_hier_prolong_box(self.h, _p(f), level, lo[0], lo[1], hi[0], hi[1], _p(out))
+        if not ok:
+            raise ValueError("a parent cell of the box is not held by the parent level")
+        return out
+
+    def patch_data(self, f, p):
+        b = self.boxes[p]
+        nx, nv = b["hi"][0] - b["lo"][0] + 1, b["hi"][1] - b["lo"][1] + 1
+        o = self.offset(p)
+        return np.asarray(f)[o:o + nx * nv].reshape(nx, nv)
+
+    def level_array(self, f, level):
+        """level `level` as a dense array, NaN where it has no patch"""
+        if level == 0:
+            return np.asarray(f)[: self.ncx * self.ncv].reshape(self.ncx, self.ncv).copy()
+        out = np.full((self.nx[level], self.nv[level]), np.nan)
+        for p, b in enumerate(self.boxes):
+            if b["level"] == level:
+                out[b["lo"][0]:b["hi"][0] + 1, b["lo"][1]:b["hi"][1] + 1] = self.patch_data(f, p)
+        return out
+
+
+def hier_regrid_transfer(old, f_old, new):
+    """State of hierarchy `new` from hierarchy `old` after a regrid (section 3):
+    level 0 copied; on each finer level, from the coarsest, every new cell an
+    old patch of the same level held keeps the old value, the others are the
+    conservative limited WENO5 prolongation of the new parent level."""
+    f_new = np.zeros(new.size)
+    f_new[: new.ncx * new.ncv] = np.asarray(f_old)[: old.ncx * old.ncv]
+    for lv in range(1, new.L):
+        old_lv = old.level_array(f_old, lv) if lv < old.L else None
+        for p, b in enumerate(new.boxes):
+            if b["level"] != lv:
+                continue
+            vals = new.prolong_box(f_new, lv, b["lo"], b["hi"])
+            if old_lv is not None:
+                o = old_lv[b["lo"][0]:b["hi"][0] + 1, b["lo"][1]:b["hi"][1] + 1]
+                vals = np.where(np.isnan(o), vals, o)
+            off = new.offset(p)
+            f_new[off:off + vals.size] = vals.ravel()
+    return f_new
+
+
+def hier_stability_limit(o, a, v_lo, v_hi):
+    """Largest linearly stable RK4 step of a multi-level hierarchy: dt times
+    max over every level's patches of (max |v| on the patch's velocity faces
+    / dx_l + max |a_l| over its configuration columns / dv_l) at the RK4 +
+    centred fourth-order limit."""
+    rate = 0.0
+    off = 0
+    a = np.asarray(a)
+    al = []
+    for lv in range(o.L):
+        al.append(a[off:off + o.nx[lv]])
+        off += o.nx[lv]
+    patches = [(0, 0, 0, o.ncx - 1, o.ncv - 1)] + [(b["level"], b["lo"][0], b["lo"][1], b["hi"][0], b["hi"][1])
+                                                    for b in o.boxes]
+    for lv, x0, v0, x1, v1 in patches:
+        dxl = o.x_len_ / o.nx[lv]
+        dvl = (v_hi - v_lo) / o.nv[lv]
+        vmax = max(abs(v_lo + v0 * dvl), abs(v_lo + (v1 + 1) * dvl))
+        amax = np.abs(al[lv][x0:x1 + 1]).max()
+        rate = max(rate, vmax / dxl + amax / dvl)
+    return linear_stability_courant() / rate
 
 
 def rk4_dense_weights(theta):

@@ -78,6 +78,8 @@ void vpo_hier_reduce_mask(void* h, const double* f, double* n);
 void vpo_hier_constraints(void* h, const double* f, double* a, double* E_out);
 void vpo_hier_rhs(void* h, const double* f, const double* a, double* k);
 void vpo_hier_rk4_step(void* h, const double* f_in, double* f_out, double dt);
+void vpo_hier_tag_values(void* h, const double* f, int l, double* values);
+int vpo_hier_prolong_box(void* h, const double* f, int l, int x0, int v0, int x1, int v1, double* out);
 
 /* regridding (section 3): refinement criterion and conservative limited interpolation */
 double vpo_tag_value(int nx, int nv, double dx, double dv, const double* vghost, const double* f, int i, int j);

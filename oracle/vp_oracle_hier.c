@@ -441,3 +441,66 @@ void vpo_hier_rk4_step(void* ptr, const double* f_in, double* f_out, double dt)
     free_fluxes(h, Ax, Av);
     free(fs); free(k); free(a);
 }
+
+/* ---- regridding of a multi-level hierarchy (section 3) ------------------ */
+
+/* The refinement criterion of section 3 on every cell that a level-l patch
+ * holds (delta1 f + delta2 f over x and v with the level's cell sizes;
+ * neighbours outside the patch are its ghost cells), in the operation order
+ * of vpo_tag_value; values[nx_l * nv_l] is NaN where level l has no patch. */
+void vpo_hier_tag_values(void* ptr, const double* f, int l, double* values)
+{
+    const vpo_hier* h = (const vpo_hier*)ptr;
+    const int nx = h->nx[l], nv = h->nv[l];
+    const double dx = h->dx[l], dv = h->dv[l];
+    for (long e = 0; e < (long)nx * nv; ++e) values[e] = NAN;
+    for (int p = 0; p < h->np; ++p) {
+        const hpatch* q = &h->P[p];
+        if (q->lev != l) continue;
+        for (int i = q->xlo; i <= q->xhi; ++i)
+            for (int j = q->vlo; j <= q->vhi; ++j) {
+                int ok = 1;
+                const double c = cell_value(h, f, l, i, j, &ok);
+                const double xm = cell_value(h, f, l, i - 1, j, &ok), xp = cell_value(h, f, l, i + 1, j, &ok);
+                const double vm = cell_value(h, f, l, i, j - 1, &ok), vp = cell_value(h, f, l, i, j + 1, &ok);
+                const double gx = xp - xm, gv = vp - vm;
+                const double d1 = sqrt(0.5 * (dx * (gx * gx) + dv * (gv * gv)));
+                const double sx = (xp - 2.0 * c) + xm, sv = (vp - 2.0 * c) + vm;
+                const double d2 = 0.5 * ((dx * dx) * fabs(sx) + (dv * dv) * fabs(sv));
+                values[(long)i * nv + j] = d1 + d2;
+            }
+    }
+}
+
+/* Conservative limited WENO5 prolongation (section 3, eqs. aux1, aux2,
+ * interp_r_avg) of level l-1 into the level-l box [x0, x1] x [v0, v1]
+ * (aligned to the level pair's ratios): x first with r_x (parent rows
+ * cj-2 .. cj+2), then v with r_v; parent cells are read where level l-1
+ * holds them, the level's equilibrium outside the velocity box.  out is
+ * [x1 - x0 + 1][v1 - v0 + 1]; returns 0 when a parent cell is not held. */
+int vpo_hier_prolong_box(void* ptr, const double* f, int l, int x0, int v0, int x1, int v1, double* out)
+{
+    const vpo_hier* h = (const vpo_hier*)ptr;
+    const int rx = h->rx[l], rv = h->rv[l];
+    const int cx0 = x0 / rx, cx1 = x1 / rx, cv0 = v0 / rv, cv1 = v1 / rv;
+    const int nfx = x1 - x0 + 1, nfv = v1 - v0 + 1, nvt = cv1 - cv0 + 5;
+    double* T = (double*)malloc(sizeof(double) * (size_t)nfx * nvt);
+    int ok = 1;
+    for (int cx = cx0; cx <= cx1; ++cx)
+        for (int q = 0; q < nvt; ++q) {
+            double u[5], o[64];
+            for (int e = 0; e < 5; ++e)
+                if (!level_value(h, f, l - 1, cx - 2 + e, cv0 - 2 + q, &u[e])) ok = 0;
+            vpo_prolong1d(u, rx, o);
+            for (int s = 0; s < rx; ++s) T[(size_t)((cx - cx0) * rx + s) * nvt + q] = o[s];
+        }
+    for (int x = 0; x < nfx; ++x)
+        for (int cv = cv0; cv <= cv1; ++cv) {
+            double u[5], o[64];
+            for (int e = 0; e < 5; ++e) u[e] = T[(size_t)x * nvt + (cv - cv0) + e];
+            vpo_prolong1d(u, rv, o);
+            for (int s = 0; s < rv; ++s) out[(size_t)x * nfv + (cv - cv0) * rv + s] = o[s];
+        }
+    free(T);
+    return ok;
+}

@@ -284,3 +284,93 @@ def test_bad_hierarchies_are_rejected(oracle):
     with pytest.raises(ValueError, match="code 4"):        # level 2 too close to the edge of level 1
         oracle.OracleHier(3, 32, 24, X_LEN, V_LO, V_HI, -1.0, ratios,
                           [box(1, 8, 24, 31, 71), box(2, 32, 48, 63, 79)], veqs)
+
+
+# ---- regridding pieces of a multi-level hierarchy -------------------------
+
+def test_tag_values_equal_the_single_level_criterion(oracle):
+    """Level 0, and a level 1 that the patches tile completely, give the
+    single-level criterion of the same array bit for bit."""
+    ratios = [(2, 4)]
+    ncx, ncv = 8, 6
+    boxes = tile_level(16, 24, [6], [8], 1)
+    o, f, veqs = landau_hier(oracle, ncx, ncv, ratios, boxes, noise=0.05, seed=4)
+    for lv in range(2):
+        arr = o.level_array(f, lv)
+        vg = veqs[lv]
+        want = oracle.tag_values(arr, X_LEN / o.nx[lv], 16.0 / o.nv[lv], np.array([vg[0], vg[1], vg[-2], vg[-1]]))
+        got = o.tag_values(f, lv)
+        assert np.array_equal(got, want), lv
+
+
+def test_tag_values_only_where_the_level_has_patches(oracle):
+    o, f, _ = landau_hier(oracle, 32, 24, [(2, 4), (4, 2)], HIER3, seed=2)
+    t1 = o.tag_values(f, 1)
+    held = ~np.isnan(o.level_array(f, 1))
+    assert np.array_equal(~np.isnan(t1), held)
+    assert (t1[held] > 0).all()
+
+
+@pytest.mark.parametrize("R", [2, 4])
+def test_prolong_box_equals_the_two_level_prolongation(oracle, R):
+    ncx, ncv = 16, 12
+    boxes = [box(1, 4 * R, 2 * R, 9 * R - 1, 8 * R - 1)]
+    o, f, veqs = landau_hier(oracle, ncx, ncv, [(R, R)], boxes, noise=0.1, seed=8)
+    fc = f[: ncx * ncv].reshape(ncx, ncv)
+    vg = veqs[0]
+    b = boxes[0]
+    want = oracle.prolong_box(fc, np.array([vg[0], vg[1], vg[-2], vg[-1]]), R,
+                              (b["lo"][0], b["lo"][1], b["hi"][0], b["hi"][1]))
+    got = o.prolong_box(f, 1, boxes[0]["lo"], boxes[0]["hi"])
+    assert np.array_equal(got, want)
+
+
+def test_prolong_box_anisotropic_conserves_and_reads_parent_patches(oracle):
+    """Level 2 ([4,2] from level 1) prolonged from two touching level-1
+    patches: every parent cell's mean is kept exactly (conservation), and a
+    smooth parent is reproduced to the scheme's order."""
+    o, f, _ = landau_hier(oracle, 32, 24, [(2, 4), (4, 2)], HIER3, seed=12)
+    lo, hi = [56, 64], [143, 119]                       # across level-1 patches 0 and 1
+    fine = o.prolong_box(f, 2, lo, hi)
+    parent = o.level_array(f, 1)[lo[0] // 4:(hi[0] + 1) // 4, lo[1] // 2:(hi[1] + 1) // 2]
+    means = fine.reshape(parent.shape[0], 4, parent.shape[1], 2).mean(axis=(1, 3))
+    np.testing.assert_allclose(means, parent, rtol=1e-14, atol=0)
+    with pytest.raises(ValueError):
+        o.prolong_box(f, 2, [0, 0], [31, 31])            # level 1 does not hold those parents
+
+
+def test_regrid_transfer_keeps_old_cells_and_conserves(oracle):
+    ratios = [(2, 4), (4, 2)]
+    o, f, veqs = landau_hier(oracle, 32, 24, ratios, HIER3, seed=3)
+    new_boxes = [box(1, 8, 24, 43, 71), box(1, 0, 32, 7, 55), box(1, 56, 32, 63, 63),
+                 box(2, 60, 60, 131, 119), box(2, 240, 88, 255, 95)]
+    n = oracle.OracleHier(3, 32, 24, X_LEN, V_LO, V_HI, -1.0, ratios, new_boxes, veqs)
+    g = oracle.hier_regrid_transfer(o, f, n)
+    np.testing.assert_array_equal(g[: 32 * 24], f[: 32 * 24])
+    for lv in (1, 2):
+        old, new = o.level_array(f, lv), n.level_array(g, lv)
+        kept = ~np.isnan(old) & ~np.isnan(new)
+        assert np.array_equal(new[kept], old[kept])
+    # new level-1 cells that no old patch held keep the parent's mean
+    new1, old1 = n.level_array(g, 1), o.level_array(f, 1)
+    fresh = ~np.isnan(new1) & np.isnan(old1)
+    assert fresh.any()
+    m = new1.reshape(32, 2, 24, 4).mean(axis=(1, 3))
+    c = f[: 32 * 24].reshape(32, 24)
+    whole = fresh.reshape(32, 2, 24, 4).all(axis=(1, 3))
+    np.testing.assert_allclose(m[whole], c[whole], rtol=1e-14)
+
+
+def test_stability_limit_closed_form(oracle):
+    ratios = [(2, 4), (4, 2)]
+    o, f, _ = landau_hier(oracle, 32, 24, ratios, HIER3, seed=3)
+    a = np.zeros(o.field_elems)
+    lim = oracle.hier_stability_limit(o, a, V_LO, V_HI)
+    # a = 0: the fastest patch is level 2, |v| up to |v_lo + 88 dv_2| or so; the rate is max |v| / dx over patches
+    rates = [8.0 / (X_LEN / 32)]
+    for b in HIER3:
+        lv = b["level"]
+        dv = 16.0 / o.nv[lv]
+        vmax = max(abs(V_LO + b["lo"][1] * dv), abs(V_LO + (b["hi"][1] + 1) * dv))
+        rates.append(vmax / (X_LEN / o.nx[lv]))
+    assert abs(lim - oracle.linear_stability_courant() / max(rates)) <= 1e-15 * lim
