@@ -444,6 +444,37 @@ vp_status vp_cluster_tags(const uint8_t* tags, int32_t ncx, int32_t ncv, int32_t
                           int32_t min_width, int32_t buffer, vp_box* boxes, int32_t max_boxes, int32_t* nbox);
 
 /*
+ * Regridding of a multi-level plan (section 3, mesh refinement criteria;
+ * the hierarchy is rebuilt from the coarsest level up, so a new level is
+ * clustered from the tags of the new level below it).
+ *
+ * vp_tag_level: the criterion delta1 f + delta2 f > tol (as vp_tag_cells,
+ *   with the level's cell sizes) on every cell that level `level` holds,
+ *   neighbours outside a patch taken from its ghost cells.  tags: device
+ *   uint8 [nx_l][nv_l] (0 where the level has no patch); values: device
+ *   double [nx_l][nv_l] or NULL (NaN where the level has no patch).  work:
+ *   the plan's workspace (its ghost-frame buffer is used).  VP_ENOTSUP for
+ *   plans that are not multi-level.
+ * vp_cluster_level (host): level-(level+1) boxes (level+1 index space,
+ *   aligned to the ratios ratio_x, ratio_v of level -> level+1) covering
+ *   the tagged level-`level` cells (tags: host uint8 [nx_l][nv_l]) that
+ *   nesting allows: a cell is allowed when the plan's level `level` holds it
+ *   and every cell within three cells of it (x periodic; outside the
+ *   velocity box counts as held), so that the new level can be created
+ *   over this plan's levels 0 .. level.  Berger-Rigoutsos as in
+ *   vp_cluster_tags (efficiency, min_width and buffer in level-`level`
+ *   cells); boxes that then hold disallowed cells are halved along their
+ *   longer side until they do not (parts without tags dropped); boxes
+ *   larger than max_x x max_v cells of the new level (0: no limit) are split
+ *   into near-equal parts.  The boxes may touch.
+ */
+vp_status vp_tag_level(const vp_plan* plan, const void* f, int32_t level, double tol, uint8_t* tags, double* values,
+                       void* work, hipStream_t stream);
+vp_status vp_cluster_level(const vp_plan* plan, int32_t level, const uint8_t* tags, int32_t ratio_x, int32_t ratio_v,
+                           double efficiency, int32_t min_width, int32_t buffer, int32_t max_x, int32_t max_v,
+                           vp_box* boxes, int32_t max_boxes, int32_t* nbox);
+
+/*
  * vp_regrid_transfer: fills the state of new_plan from the state of
  * old_plan after a regrid (section 3): level 0 is copied; every new
  * level-1 cell covered by an old level-1 patch takes the old fine value,
@@ -453,7 +484,12 @@ vp_status vp_cluster_tags(const uint8_t* tags, int32_t ncx, int32_t ncv, int32_t
  * the candidate gives), applied in x and then in v.  Both plans are 1D+1V
  * FP64 with the same level 0 (cells, spacing, equilibrium) and the same
  * ratio; either may have one level.  f_old and f_new must not overlap.
- * Enqueued on `stream`.
+ * Enqueued on `stream`.  Multi-level plans (both): level 0 copied, then
+ * every finer level of new_plan from the coarsest: the cells an old patch
+ * of the same level holds keep the old value, the others are that
+ * interpolation of the new parent level with the level pair's ratios in x
+ * and in v (anisotropic); VP_EINVAL if a new patch is not nested in its new
+ * parent level; synchronises the stream (its tables are freed on return).
  */
 vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const vp_plan* new_plan, void* f_new,
                              hipStream_t stream);
@@ -485,6 +521,8 @@ typedef struct vp_amr_params {
     double cfl;                /* fraction of the linear stability limit (> 0; 0.5)    */
     double dt_growth;          /* largest ratio of consecutive steps (>= 1; 1.1)       */
     double dt_initial;         /* first time step (> 0)                                 */
+    int32_t max_size[VP_MAX_LEVELS][2];  /* largest patch on level l in its own cells
+                                  (x, v); 0: no limit (multi-level runs only)            */
 } vp_amr_params;
 
 typedef struct vp_amr_info {
@@ -500,11 +538,18 @@ typedef struct vp_amr_info {
 
 typedef struct vp_amr_run vp_amr_run;
 
-/* Creates a run from a two-level 1D+1V FP64 problem, its initial boxes and
- * the initial state f0 (device, the layout of vp_plan_create(problem,
- * boxes), copied).  Allocates device memory; enqueues the copy and the
- * field solve on `stream`.  VP_EINVAL for bad parameters or a problem
- * without two levels; plan creation errors as vp_plan_create. */
+/* Creates a run from a 1D+1V FP64 problem of two or more levels, its
+ * initial boxes and the initial state f0 (device, the layout of
+ * vp_plan_create(problem, boxes), copied).  Allocates device memory;
+ * enqueues the copy and the field solve on `stream`.  A multi-level
+ * problem (more than two levels, or different ratios in x and v) regrids
+ * from the coarsest level up: level l of the new hierarchy is tagged
+ * (vp_tag_level; level 0 on the old state, finer levels on the new levels
+ * below them with their transferred state), clustered into level-(l+1)
+ * boxes nested in it (vp_cluster_level with min_width, buffer, efficiency
+ * and max_size[l+1]), and the new state transferred from the old one
+ * (vp_regrid_transfer).  VP_EINVAL for bad parameters or a problem with
+ * one level; plan creation errors as vp_plan_create. */
 vp_status vp_amr_run_create(const vp_problem* problem, const vp_box* boxes, int32_t nbox, const void* f0,
                             const vp_amr_params* params, vp_amr_run** out, hipStream_t stream);
 /* Advances `steps` time steps on `stream`.  Synchronises the stream every

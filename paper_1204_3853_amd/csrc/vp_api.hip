@@ -207,7 +207,7 @@ vp_status scratch_address(void** out)
 // plan of two or more levels: geometry, box calculus and tables (two-level
 // engine in vp_amr.hip, multi-level engine in vp_hier.hip), then the Poisson
 // tables of the finest configuration mesh
-vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out)
+vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out, bool force_hier)
 {
     vp_plan* p = new (std::nothrow) vp_plan();
     if (!p) return fail(VP_ENOMEM, "out of host memory");
@@ -222,7 +222,7 @@ vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox
     // two levels with one ratio (2 or 4) in x and v take the two-level engine
     // (ghost interpolation fused into the stage tiles, subcycling, species,
     // adaptive runs); deeper or anisotropic hierarchies the multi-level one
-    const bool two = pb->n_levels == 2 && pb->ratio[0][0] == pb->ratio[0][1] &&
+    const bool two = !force_hier && pb->n_levels == 2 && pb->ratio[0][0] == pb->ratio[0][1] &&
                      (pb->ratio[0][0] == 2 || pb->ratio[0][0] == 4);
     vp_status st = two ? amr_create(p, pb, boxes, nbox) : hier_create(p, pb, boxes, nbox);
     if (st == VP_OK) {
@@ -335,6 +335,15 @@ vp_status hip_fail(hipError_t e, const char* what)
     return VP_EHIP;
 }
 
+vp_status hier_plan_create(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out)
+{
+    if (!pb || !out) return fail(VP_EINVAL, "hier_plan_create: NULL pointer");
+    *out = nullptr;
+    if (pb->n_levels < 2 || pb->n_levels > VP_MAX_LEVELS) return fail(VP_EINVAL, "n_levels must be 2 .. 4");
+    if (!pb->veq[0][0]) return fail(VP_EINVAL, "veq[0][0] (equilibrium with ghosts) is required");
+    return create_multi_level(pb, boxes, nbox, out, true);
+}
+
 }  // namespace vp
 
 using namespace vp;
@@ -359,7 +368,7 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
         if (!(pb->v_hi[d] > pb->v_lo[d])) return fail(VP_EINVAL, "v_hi must exceed v_lo");
         if (!pb->veq[0][d]) return fail(VP_EINVAL, "veq[0][d] (equilibrium with ghosts) is required");
     }
-    if (pb->n_levels >= 2) return create_multi_level(pb, boxes, nbox, out);
+    if (pb->n_levels >= 2) return create_multi_level(pb, boxes, nbox, out, false);
     if (nbox != 0) return fail(VP_EINVAL, "a single-level plan takes no boxes");
     if (pb->ndim == 2) return create_4d(pb, out);
 

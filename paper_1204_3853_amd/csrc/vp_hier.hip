@@ -113,6 +113,12 @@ HierArgs base_args(const vp_plan* p, const double* fs, const double* a, void* wo
 
 vp_status fill_frames(const vp_plan* p, const double* f, void* work, hipStream_t stream)
 {
+    return hier_fill_frames(p, f, work, stream);
+}
+}  // namespace
+
+vp_status hier_fill_frames(const vp_plan* p, const double* f, void* work, hipStream_t stream)
+{
     const HierPlan& H = *p->hier;
     double* frame = reinterpret_cast<double*>(wsp(work, H.ws_frame));
     VP_HIP(timed(p, kTOther, stream, [&] {
@@ -120,6 +126,8 @@ vp_status fill_frames(const vp_plan* p, const double* f, void* work, hipStream_t
     }));
     return VP_OK;
 }
+
+namespace {
 
 // the velocity moment on the finest configuration mesh (Sub-Patch
 // reduction); the frames of f must be filled
@@ -528,6 +536,15 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     fill_tiles(H);
     VP_HIP(upload_tiles(H));
     std::vector<HLevel> lvv(H.lv, H.lv + L);
+    for (int l = 0; l < L; ++l) {
+        H.level_begin[l] = (int)H.level_list.size();
+        for (size_t q = 0; q < H.patches.size(); ++q)
+            if (H.patches[q].lev == l) {
+                H.level_list.push_back((int)q);
+                H.level_max_cells[l] = std::max(H.level_max_cells[l], H.patches[q].nx * H.patches[q].nv);
+            }
+    }
+    H.level_begin[L] = (int)H.level_list.size();
     TableArena T;
     T.add(&H.d_patches, H.patches);
     T.add(&H.d_desc, desc);
@@ -547,6 +564,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     T.add(&H.d_corr_cell, corr_cell);
     T.add(&H.d_corr_fine, corr_fine);
     T.add(&H.d_corr_nfine, corr_nfine);
+    T.add(&H.d_level_list, H.level_list);
     for (int l = 0; l + 1 < L; ++l) {
         H.avg[l].rx = B.lv[l + 1].rx;
         H.avg[l].rv = B.lv[l + 1].rv;

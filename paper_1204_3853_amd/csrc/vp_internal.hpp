@@ -234,6 +234,25 @@ struct HierAvgArgs {           // covered cells of one level take the mean of th
     int rx, rv, n;
 };
 
+// regridding of a multi-level hierarchy (vp_kernels_regrid.hip)
+struct HProlongPatch {         // a new patch filled by prolongation of its new parent level
+    long long off;             // the new patch's state offset
+    int nv;                    // its velocity width
+    int pcx, pcv;              // parent cells it covers
+    int win;                   // offset of its (pcx + 4) x (pcv + 4) window sources in the source table
+};
+struct HCopyBlock {            // an intersection of a new patch with an old patch of the same level
+    long long dst, src;        // its first cell in the new and in the old state
+    int dst_stride, src_stride, nx, nv;
+};
+hipError_t launch_hier_tag(const double* f, const double* frame, const HPatch* d_patches, const int* d_list, int n,
+                           int max_cells, int nv_l, double dx, double dv, double tol, uint8_t* tags, double* values,
+                           hipStream_t stream);
+hipError_t launch_hier_prolong(double* f, const int* d_win, const HProlongPatch* pp, int n, int max_parent_cells,
+                               int rx, int rv, const double* eqv, hipStream_t stream);
+hipError_t launch_hier_copy(double* fnew, const double* fold, const HCopyBlock* d_blocks, int n, int max_cells,
+                            hipStream_t stream);
+
 hipError_t launch_hier_fill(const double* f, const int2* desc, const HInterp* rec, const double* wts,
                             const int* wofs, const double* eqv, double* frame, int n, hipStream_t stream);
 hipError_t launch_hier_stage(int w, int nt, int kind, const HierArgs& a, int t_begin, int t_end, int grid,
@@ -480,6 +499,10 @@ struct HierPlan {
     };
     Avg avg[kHierLevels];                            // avg[l]: level-l cells covered by level l + 1
     double* d_rhs_frame = nullptr;                   // frames for vp_rhs, which takes no workspace
+    std::vector<int> level_list;                     // patch indices grouped by level
+    int level_begin[kHierLevels + 1] = {};           // level l: level_list[level_begin[l] .. level_begin[l+1])
+    int level_max_cells[kHierLevels] = {};           // largest patch of each level, in cells
+    int* d_level_list = nullptr;
     size_t ws_frame = 0, ws_cf = 0, ws_ff = 0, ws_slots = 0, ws_n = 0, ws_E = 0, ws_fld = 0;
 };
 }  // namespace vp
@@ -590,6 +613,14 @@ struct TableArena {
 // (section 3), R x 5 values at [s * 5 + j + 2] (vp_amr.hip)
 std::vector<double> interp_table(int R);
 
+// clustering (vp_regrid.hip): an inclusive box of cells of the level that is
+// clustered, and Berger-Rigoutsos on a dense [x][v] tag field
+struct CBox {
+    int xlo, vlo, xhi, vhi;
+    long long area() const { return (long long)(xhi - xlo + 1) * (vhi - vlo + 1); }
+};
+void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double eff, int minw, std::vector<CBox>& out);
+
 // multi-level host sequences (vp_hier.hip)
 vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);
 void hier_destroy(vp_plan* p);
@@ -598,6 +629,22 @@ vp_status hier_reduce(const vp_plan* p, const void* f, double* n, void* work, hi
 vp_status hier_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
 vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
 vp_status hier_set_shape(vp_plan* p, int nt, int w, int tx);
+// ghost frames of state f into the workspace frame buffer
+vp_status hier_fill_frames(const vp_plan* p, const double* f, void* work, hipStream_t stream);
+// multi-level regridding (vp_hier_regrid.hip): the criterion on level l
+// (dense [nx_l][nv_l] tags and optionally values, NaN where level l has no
+// patch); the state of a new plan from an old one (level 0 copied, every
+// finer level from the coarsest: old cells of the same level kept, the others
+// prolonged from the new parent level); clustering of level-l tags into
+// level-(l+1) boxes nested in plan p's level l
+vp_status hier_tag_level(const vp_plan* p, const double* f, int l, double tol, uint8_t* d_tags, double* d_values,
+                         void* work, hipStream_t stream);
+vp_status hier_transfer(const vp_plan* old_plan, const double* f_old, const vp_plan* new_plan, double* f_new,
+                        hipStream_t stream);
+vp_status hier_cluster(const vp_plan* p, int l, const uint8_t* tags, int rx, int rv, double efficiency, int min_width,
+                       int buffer, int max_x, int max_v, std::vector<vp_box>& out);
+// a plan on the multi-level engine whatever its levels and ratios (vp_api.hip)
+vp_status hier_plan_create(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out);
 
 // two-level host sequences (vp_amr.hip)
 vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);

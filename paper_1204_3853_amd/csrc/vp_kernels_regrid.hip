@@ -377,6 +377,88 @@ __global__ __launch_bounds__(256) void k_copy_old(const double* __restrict__ fol
     }
 }
 
+// ---- multi-level hierarchies
+
+// the criterion on every cell of the listed patches of one level, its
+// neighbours outside the patch read from the patch's ghost frame; tags and
+// values land in the level's dense [nx_l][nv_l] arrays
+__global__ __launch_bounds__(256) void k_hier_tag(const double* __restrict__ f, const double* __restrict__ frame,
+                                                 const HPatch* __restrict__ patches, const int* __restrict__ list,
+                                                 int nv_l, double dx, double dv, double tol,
+                                                 uint8_t* __restrict__ tags, double* __restrict__ values)
+{
+    const HPatch P = patches[list[blockIdx.y]];
+    const int q = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (q >= P.nx * P.nv) return;
+    const int r = q / P.nv, c = q - (q / P.nv) * P.nv;
+    const double* fp = f + P.off;
+    const double* fr = frame + P.frame;
+    const double* fc = fr + (size_t)4 * (P.nv + 4);
+    const double cc = fp[q];
+    const double xm = r > 0 ? fp[q - P.nv] : fr[(size_t)1 * (P.nv + 4) + c + 2];
+    const double xp = r + 1 < P.nx ? fp[q + P.nv] : fr[(size_t)2 * (P.nv + 4) + c + 2];
+    const double vm = c > 0 ? fp[q - 1] : fc[(size_t)r * 4 + 1];
+    const double vp = c + 1 < P.nv ? fp[q + 1] : fc[(size_t)r * 4 + 2];
+    const double t = tag_from(cc, xm, xp, vm, vp, dx, dv);
+    const size_t o = (size_t)(P.gx0 + r) * nv_l + (P.gv0 + c);
+    tags[o] = t > tol ? 1 : 0;
+    if (values) values[o] = t;
+}
+
+// conservative limited WENO5 prolongation of the new parent level into the
+// listed new patches of one level (x with RX, then v with RV): a thread per
+// parent cell of a patch reads its 5 x 5 parent window from a source table
+// (state element, or equilibrium value eqv[-1 - src]) and writes RX x RV
+// fine cells
+
+template <int RX, int RV>
+__global__ __launch_bounds__(128) void k_hier_prolong(double* __restrict__ f, const int* __restrict__ win,
+                                                     const HProlongPatch* __restrict__ pp,
+                                                     const double* __restrict__ eqv)
+{
+    const HProlongPatch P = pp[blockIdx.y];
+    const int q = (int)(blockIdx.x * 128 + threadIdx.x);
+    if (q >= P.pcx * P.pcv) return;
+    const int cxl = q / P.pcv, cvl = q - (q / P.pcv) * P.pcv;
+    const int W = P.pcv + 4;
+    const int* w0 = win + P.win + (size_t)cxl * W + cvl;   // window cell (cxl - 2 + 2, cvl - 2 + 2)
+    auto val = [&](int a, int b) {
+        const int s = w0[(size_t)a * W + b];
+        return s >= 0 ? f[s] : eqv[-1 - s];
+    };
+    double T[RX][5];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+        double u[5], o[RX];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) u[k] = val(k, e);
+        prolong1d<RX>(u, o);
+#pragma unroll
+        for (int s = 0; s < RX; ++s) T[s][e] = o[s];
+    }
+#pragma unroll
+    for (int s = 0; s < RX; ++s) {
+        double o[RV];
+        prolong1d<RV>(T[s], o);
+        double* dst = f + P.off + (size_t)(cxl * RX + s) * P.nv + (size_t)cvl * RV;
+#pragma unroll
+        for (int t = 0; t < RV; ++t) dst[t] = o[t];
+    }
+}
+
+// old values into new patches: one block column per (new patch, old patch)
+// intersection, copying its rows
+
+__global__ __launch_bounds__(256) void k_hier_copy(double* __restrict__ fnew, const double* __restrict__ fold,
+                                                  const HCopyBlock* __restrict__ blocks)
+{
+    const HCopyBlock B = blocks[blockIdx.y];
+    const int q = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (q >= B.nx * B.nv) return;
+    const int r = q / B.nv, c = q - (q / B.nv) * B.nv;
+    fnew[B.dst + (size_t)r * B.dst_stride + c] = fold[B.src + (size_t)r * B.src_stride + c];
+}
+
 }  // namespace
 
 hipError_t launch_tag4d(const Tag4DArgs& a, hipStream_t stream)
@@ -437,6 +519,42 @@ hipError_t launch_copy_old(const double* fold, const AmrPatch* d_old, int nold, 
     if (nnew == 0 || nold == 0) return hipSuccess;
     const dim3 grid((unsigned)((max_fine_cells + 255) / 256), (unsigned)nnew);
     hipLaunchKernelGGL(k_copy_old, grid, dim3(256), 0, stream, fold, d_old, nold, d_new, fnew);
+    return hipGetLastError();
+}
+
+hipError_t launch_hier_tag(const double* f, const double* frame, const HPatch* d_patches, const int* d_list, int n,
+                           int max_cells, int nv_l, double dx, double dv, double tol, uint8_t* tags, double* values,
+                           hipStream_t stream)
+{
+    if (n <= 0 || max_cells <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_cells + 255) / 256), (unsigned)n);
+    hipLaunchKernelGGL(k_hier_tag, grid, dim3(256), 0, stream, f, frame, d_patches, d_list, nv_l, dx, dv, tol, tags,
+                       values);
+    return hipGetLastError();
+}
+
+hipError_t launch_hier_prolong(double* f, const int* d_win, const HProlongPatch* pp, int n, int max_parent_cells,
+                               int rx, int rv, const double* eqv, hipStream_t stream)
+{
+    if (n <= 0 || max_parent_cells <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_parent_cells + 127) / 128), (unsigned)n), blk(128);
+#define VP_HP(RX, RV)                                                                                   \
+    if (rx == RX && rv == RV) {                                                                          \
+        hipLaunchKernelGGL((k_hier_prolong<RX, RV>), grid, blk, 0, stream, f, d_win, pp, eqv);           \
+        return hipGetLastError();                                                                        \
+    }
+    VP_HP(1, 2) VP_HP(1, 4) VP_HP(1, 8) VP_HP(2, 1) VP_HP(2, 2) VP_HP(2, 4) VP_HP(2, 8) VP_HP(4, 1) VP_HP(4, 2)
+    VP_HP(4, 4) VP_HP(4, 8) VP_HP(8, 1) VP_HP(8, 2) VP_HP(8, 4) VP_HP(8, 8)
+#undef VP_HP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_hier_copy(double* fnew, const double* fold, const HCopyBlock* d_blocks, int n, int max_cells,
+                            hipStream_t stream)
+{
+    if (n <= 0 || max_cells <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_cells + 255) / 256), (unsigned)n);
+    hipLaunchKernelGGL(k_hier_copy, grid, dim3(256), 0, stream, fnew, fold, d_blocks);
     return hipGetLastError();
 }
 

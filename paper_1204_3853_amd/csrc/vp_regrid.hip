@@ -41,10 +41,7 @@ bool level0_of(const vp_plan* p, Level0& L)
     return true;
 }
 
-struct CBox {
-    int xlo, vlo, xhi, vhi;        // inclusive, level-0 cells
-    long long area() const { return (long long)(xhi - xlo + 1) * (vhi - vlo + 1); }
-};
+}  // namespace
 
 // Berger-Rigoutsos: split the bounding box of the tags inside B at a hole
 // of a signature, else at the strongest inflection of a signature's
@@ -111,6 +108,8 @@ void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double ef
     br_cluster(tag, nv, lo, eff, minw, out);
     br_cluster(tag, nv, hi, eff, minw, out);
 }
+
+namespace {
 
 bool overlap(const CBox& a, const CBox& b)
 {
@@ -211,6 +210,8 @@ vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const v
 {
     Level0 A, B;
     if (!old_plan || !new_plan || !f_old || !f_new) return fail(VP_EINVAL, "vp_regrid_transfer: NULL pointer");
+    if (old_plan->hier || new_plan->hier)
+        return hier_transfer(old_plan, static_cast<const double*>(f_old), new_plan, static_cast<double*>(f_new), stream);
     if (!level0_of(old_plan, A) || !level0_of(new_plan, B))
         return fail(VP_ENOTSUP, "vp_regrid_transfer: 1D+1V plans only");
     if (old_plan->dtype != VP_F64 || new_plan->dtype != VP_F64)
@@ -235,6 +236,33 @@ vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const v
         VP_HIP(launch_copy_old(fo, O.d_patches, (int)O.patches.size(), N.d_patches, (int)N.patches.size(), max_f, fn,
                                stream));
     }
+    return VP_OK;
+}
+
+vp_status vp_tag_level(const vp_plan* p, const void* f, int32_t level, double tol, uint8_t* tags, double* values,
+                       void* work, hipStream_t stream)
+{
+    if (!p || !f || !tags || !work) return fail(VP_EINVAL, "vp_tag_level: NULL pointer");
+    if (!p->hier) return fail(VP_ENOTSUP, "vp_tag_level: multi-level plans only (vp_tag_cells for the others)");
+    return hier_tag_level(p, static_cast<const double*>(f), level, tol, tags, values, work, stream);
+}
+
+vp_status vp_cluster_level(const vp_plan* p, int32_t level, const uint8_t* tags, int32_t ratio_x, int32_t ratio_v,
+                           double efficiency, int32_t min_width, int32_t buffer, int32_t max_x, int32_t max_v,
+                           vp_box* boxes, int32_t max_boxes, int32_t* nbox)
+{
+    if (!p || !tags || !nbox || (max_boxes > 0 && !boxes)) return fail(VP_EINVAL, "vp_cluster_level: NULL pointer");
+    if (!p->hier) return fail(VP_ENOTSUP, "vp_cluster_level: multi-level plans only (vp_cluster_tags for the others)");
+    if (min_width < 1 || buffer < 0 || max_x < 0 || max_v < 0 || !(efficiency > 0.0 && efficiency <= 1.0))
+        return fail(VP_EINVAL, "vp_cluster_level: bad parameters");
+    std::vector<vp_box> out;
+    if (vp_status st = hier_cluster(p, level, tags, ratio_x, ratio_v, efficiency, min_width, buffer, max_x, max_v, out))
+        return st;
+    *nbox = (int32_t)out.size();
+    if (*nbox > max_boxes)
+        return fail(VP_EINVAL, "vp_cluster_level: " + std::to_string(out.size()) + " boxes, room for " +
+                                   std::to_string(max_boxes));
+    std::copy(out.begin(), out.end(), boxes);
     return VP_OK;
 }
 

@@ -154,14 +154,28 @@ vp_status stability_limit(vp_amr_run* r, hipStream_t s, double* lim)
 {
     for (int q = 0; q < r->ns; ++q) {
         RunSpecies& S = r->sp[q];
-        const AmrPlan& M = *S.plan->amr;
-        S.a_host.resize((size_t)M.ncx + (size_t)M.nfx);
+        S.a_host.resize(vp_field_elems(S.plan));
         VP_HIP(hipMemcpyAsync(S.a_host.data(), S.a, S.a_host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     VP_HIP(hipStreamSynchronize(s));
     double rate = 0.0;
     for (int q = 0; q < r->ns; ++q) {
         const RunSpecies& S = r->sp[q];
+        if (S.plan->hier) {
+            // every patch of every level (level 0 is patch 0) over its own
+            // velocity faces and configuration columns
+            const HierPlan& H = *S.plan->hier;
+            const double v_lo = S.plan->pb.v_lo[0];
+            for (const HPatch& P : H.patches) {
+                const HLevel& v = H.lv[P.lev];
+                const double* al = S.a_host.data() + v.a_off;
+                const double v0 = v_lo + P.gv0 * v.dv, v1 = v_lo + (P.gv0 + P.nv) * v.dv;
+                double ap = 0.0;
+                for (int i = P.gx0; i < P.gx0 + P.nx; ++i) ap = std::max(ap, std::fabs(al[i]));
+                rate = std::max(rate, std::max(std::fabs(v0), std::fabs(v1)) * v.dxi + ap * v.dvi);
+            }
+            continue;
+        }
         const AmrPlan& M = *S.plan->amr;
         const double* ac = S.a_host.data();
         const double* af = ac + M.ncx;
@@ -180,9 +194,78 @@ vp_status stability_limit(vp_amr_run* r, hipStream_t s, double* lim)
     return VP_OK;
 }
 
+// regrid of a multi-level hierarchy, from the coarsest level up: level l of
+// the new hierarchy is tagged (level 0: the old state; finer: a plan of the
+// new levels 0 .. l with its transferred state), its tags clustered into
+// level-(l+1) boxes nested in it; the final plan's state transferred from the
+// old hierarchy
+vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s)
+{
+    const vp_plan* old = S.plan;
+    const int L = old->hier->L;
+    vp_problem pb = old->pb;
+    for (int l = 0; l < L; ++l) pb.veq[l][0] = old->veq[l][0].data();
+    std::vector<vp_box> nb;
+    vp_plan* P = nullptr;          // the new levels 0 .. l
+    void* F = nullptr;             // its state
+    size_t fcap = 0;
+    vp_status st = VP_OK;
+    for (int l = 0; l + 1 < L && st == VP_OK; ++l) {
+        const vp_plan* tp = l == 0 ? old : P;
+        const void* tf = l == 0 ? S.f : F;
+        const HLevel& v = tp->hier->lv[l];
+        st = ensure_buf(&S.work, &S.work_bytes, vp_workspace_bytes(tp));
+        if (st == VP_OK) st = hier_tag_level(tp, static_cast<const double*>(tf), l, r->prm.tol, S.d_tags, nullptr,
+                                             S.work, s);
+        if (st != VP_OK) break;
+        S.tags.resize((size_t)v.nx * v.nv);
+        hipError_t e = hipMemcpyAsync(S.tags.data(), S.d_tags, S.tags.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { st = hip_fail(e, "vp_amr_run_advance: tags"); break; }
+        std::vector<vp_box> add;
+        const int mx = r->prm.max_size[l + 1][0], mv = r->prm.max_size[l + 1][1];
+        st = hier_cluster(tp, l, S.tags.data(), pb.ratio[l][0], pb.ratio[l][1], r->prm.efficiency, r->prm.min_width,
+                          r->prm.buffer, mx, mv, add);
+        if (st != VP_OK || add.empty()) break;
+        nb.insert(nb.end(), add.begin(), add.end());
+        if (l + 2 < L) {                      // the new levels 0 .. l+1, to tag level l+1 next
+            vp_problem pbi = pb;
+            pbi.n_levels = l + 2;
+            vp_plan* Pn = nullptr;
+            st = hier_plan_create(&pbi, nb.data(), (int)nb.size(), &Pn);
+            if (st == VP_OK) st = ensure_buf(&F, &fcap, std::max<size_t>(vp_state_elems(Pn), 1) * sizeof(double));
+            if (st == VP_OK) st = hier_transfer(old, static_cast<const double*>(S.f), Pn, static_cast<double*>(F), s);
+            if (P) vp_plan_destroy(P);
+            P = Pn;
+        }
+    }
+    if (P) vp_plan_destroy(P);
+    free_dev(F);
+    if (st != VP_OK) return st;
+    vp_plan* np = nullptr;
+    st = hier_plan_create(&pb, nb.data(), (int)nb.size(), &np);
+    if (st != VP_OK) return st;
+    size_t spare_bytes = S.spare_cap * sizeof(double);
+    st = ensure_buf(&S.f_spare, &spare_bytes, std::max<size_t>(vp_state_elems(np), 1) * sizeof(double));
+    S.spare_cap = spare_bytes / sizeof(double);
+    if (st == VP_OK) st = ensure_buf(&S.work, &S.work_bytes, vp_workspace_bytes(np));
+    if (st == VP_OK) st = hier_transfer(old, static_cast<const double*>(S.f), np, static_cast<double*>(S.f_spare), s);
+    if (st != VP_OK) {
+        vp_plan_destroy(np);
+        return st;
+    }
+    vp_plan_destroy(S.plan);
+    std::swap(S.f, S.f_spare);
+    std::swap(S.f_cap, S.spare_cap);
+    S.plan = np;
+    S.boxes = nb;
+    return VP_OK;
+}
+
 // regrid of one species' hierarchy from its own tags
 vp_status regrid_species(vp_amr_run* r, RunSpecies& S, hipStream_t s)
 {
+    if (S.plan->hier) return regrid_hier(r, S, s);
     const AmrPlan& M = *S.plan->amr;
     const int ncx = M.ncx, ncv = M.ncv, R = M.R;
     vp_status st = vp_tag_cells(S.plan, S.f, r->prm.tol, S.d_tags, nullptr, s);
@@ -244,6 +327,8 @@ vp_status check_params(const vp_amr_params& q)
     if (!(q.tol >= 0.0) || !std::isfinite(q.tol) || q.regrid_interval < 1 || !(q.efficiency > 0.0 && q.efficiency <= 1.0) ||
         q.min_width < 1 || q.buffer < 0 || !(q.cfl > 0.0) || !(q.dt_growth >= 1.0) || !(q.dt_initial > 0.0))
         return fail(VP_EINVAL, "vp_amr_run_create: bad parameters");
+    for (int l = 0; l < VP_MAX_LEVELS; ++l)
+        if (q.max_size[l][0] < 0 || q.max_size[l][1] < 0) return fail(VP_EINVAL, "vp_amr_run_create: bad patch size limit");
     return VP_OK;
 }
 
@@ -253,7 +338,14 @@ vp_status add_species(vp_amr_run* r, int q, const vp_problem* pb, const vp_box* 
 {
     RunSpecies& S = r->sp[q];
     if (vp_status st = vp_plan_create(pb, boxes, nbox, &S.plan)) return st;
-    const AmrPlan& M = *S.plan->amr;
+    if (!S.plan->amr && !S.plan->hier) return fail(VP_EINVAL, "vp_amr_run_create: the problem must have two or more levels");
+    size_t tag_cells = 0;
+    if (S.plan->amr) {
+        tag_cells = (size_t)S.plan->amr->ncx * S.plan->amr->ncv;
+    } else {
+        for (int l = 0; l < S.plan->hier->L; ++l)
+            tag_cells = std::max(tag_cells, (size_t)S.plan->hier->lv[l].nx * S.plan->hier->lv[l].nv);
+    }
     const size_t ne = std::max<size_t>(vp_state_elems(S.plan), 1);
     size_t fb = 0, ab = 0, tb = 0;
     if (vp_status st = ensure_buf(&S.f, &fb, ne * sizeof(double))) return st;
@@ -262,7 +354,7 @@ vp_status add_species(vp_amr_run* r, int q, const vp_problem* pb, const vp_box* 
     if (vp_status st = ensure_buf(&a, &ab, vp_field_elems(S.plan) * sizeof(double))) return st;
     S.a = static_cast<double*>(a);
     void* tg = nullptr;
-    if (vp_status st = ensure_buf(&tg, &tb, (size_t)M.ncx * M.ncv)) return st;
+    if (vp_status st = ensure_buf(&tg, &tb, tag_cells)) return st;
     S.d_tags = static_cast<uint8_t*>(tg);
     if (vp_status st = ensure_buf(&S.work, &S.work_bytes, vp_workspace_bytes(S.plan))) return st;
     VP_HIP(hipMemcpyAsync(S.f, f0, vp_state_elems(S.plan) * sizeof(double), hipMemcpyDeviceToDevice, stream));
@@ -283,14 +375,14 @@ vp_status vp_amr_run_create(const vp_problem* problem, const vp_box* boxes, int3
     if (!problem || !params || !out || !f0) return fail(VP_EINVAL, "vp_amr_run_create: NULL pointer");
     *out = nullptr;
     if (vp_status st = check_params(*params)) return st;
-    if (problem->n_levels != 2) return fail(VP_EINVAL, "vp_amr_run_create: the problem must have two levels");
+    if (problem->n_levels < 2) return fail(VP_EINVAL, "vp_amr_run_create: the problem must have two or more levels");
     vp_amr_run* r = new (std::nothrow) vp_amr_run();
     if (!r) return fail(VP_ENOMEM, "out of host memory");
     r->prm = *params;
     r->ns = 1;
     vp_status st = add_species(r, 0, problem, boxes, nbox, f0, stream);
     if (st == VP_OK) {
-        const size_t nf = (size_t)r->sp[0].plan->amr->nfx;
+        const size_t nf = vp_config_elems(r->sp[0].plan);
         size_t c1 = 0, c2 = 0, c3 = 0;
         st = ensure_buf(reinterpret_cast<void**>(&r->n), &c1, nf * sizeof(double));
         if (st == VP_OK) st = ensure_buf(reinterpret_cast<void**>(&r->phi), &c2, nf * sizeof(double));

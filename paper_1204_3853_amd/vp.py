@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -51,7 +52,8 @@ class vp_box(ctypes.Structure):
 class vp_amr_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("regrid_interval", ctypes.c_int32), ("efficiency", ctypes.c_double),
                 ("min_width", ctypes.c_int32), ("buffer", ctypes.c_int32), ("cfl", ctypes.c_double),
-                ("dt_growth", ctypes.c_double), ("dt_initial", ctypes.c_double)]
+                ("dt_growth", ctypes.c_double), ("dt_initial", ctypes.c_double),
+                ("max_size", (ctypes.c_int32 * 2) * VP_MAX_LEVELS)]
 
 
 class vp_amr_info(ctypes.Structure):
@@ -104,6 +106,11 @@ SIGNATURES = {
                                        _D, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp_box), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32)]),
     "vp_regrid_transfer": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "vp_tag_level": (ctypes.c_int, [_P, _P, ctypes.c_int32, _D, _P, _P, _P, _P]),
+    "vp_cluster_level": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32,
+                                        ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.POINTER(vp_box), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "vp_amr_run_create": (ctypes.c_int, [ctypes.POINTER(vp_problem), ctypes.POINTER(vp_box), ctypes.c_int32, _P,
                                          ctypes.POINTER(vp_amr_params), ctypes.POINTER(_P), _P]),
     "vp_amr_run_advance": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
@@ -267,6 +274,15 @@ class Plan:
 
     def set_tile_shape(self, index):
         _check(lib().vp_tile_shape_set(self.h, index))
+
+    def level_shape(self, level):
+        """(nx, nv) of a level's index space"""
+        nx, nv = self.spec["cells"][0], self.spec["cells"][1]
+        ratios = self.spec.get("ratios") or [self.spec.get("ratio", [1, 1])]
+        for l in range(level):
+            nx *= ratios[l][0]
+            nv *= ratios[l][1]
+        return nx, nv
 
     def patch_offset(self, p):
         return lib().vp_patch_offset(self.h, p)
@@ -480,6 +496,29 @@ def regrid_transfer(old_plan, f_old, new_plan, f_new=None):
     return f_new
 
 
+def tag_level(plan, f, level, tol, values=False):
+    """Criterion on level `level` of a multi-level plan: (tags, values or None)
+    as [nx_l, nv_l] device tensors (values NaN where the level has no patch)."""
+    plan._state(f, "f")
+    nx, nv = plan.level_shape(level)
+    tags = torch.empty((nx, nv), dtype=torch.uint8, device=f.device)
+    vals = torch.empty((nx, nv), dtype=torch.float64, device=f.device) if values else None
+    _check(lib().vp_tag_level(plan.h, _ptr(f), int(level), ctypes.c_double(tol), _ptr(tags), _ptr(vals),
+                              _ptr(plan.work), _stream()))
+    return tags, vals
+
+
+def cluster_level(plan, level, tags, ratio, efficiency=0.7, min_width=2, buffer=1, max_size=(0, 0), max_boxes=4096):
+    """Level-(level+1) boxes nested in the plan's level `level` from host tags."""
+    t = np.ascontiguousarray(tags.cpu().numpy() if hasattr(tags, "cpu") else tags, dtype=np.uint8)
+    arr = (vp_box * max_boxes)()
+    n = ctypes.c_int32()
+    _check(lib().vp_cluster_level(plan.h, int(level), t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                  int(ratio[0]), int(ratio[1]), ctypes.c_double(efficiency), int(min_width),
+                                  int(buffer), int(max_size[0]), int(max_size[1]), arr, max_boxes, ctypes.byref(n)))
+    return _boxes_out(arr, n.value)
+
+
 def regrid(plan, f, tol, efficiency=0.7, min_width=2, buffer=1):
     """Regrid a two-level plan: tag level 0, cluster on the host, create the
     plan of the new hierarchy and transfer the state.  Returns
@@ -494,13 +533,14 @@ def regrid(plan, f, tol, efficiency=0.7, min_width=2, buffer=1):
 
 
 class AmrRun:
-    """Adaptive two-level run (vp_amr_run): RK4 steps with a time step
-    limited by the stability condition, regridding every regrid_interval
-    steps.  spec: a two-level spec dict (two_level_spec); boxes: the
-    initial level-1 boxes; f0: the initial state in that plan's layout."""
+    """Adaptive run (vp_amr_run): RK4 steps with a time step limited by the
+    stability condition, regridding every regrid_interval steps.  spec: a
+    spec dict of two or more levels (two_level_spec, hierarchy_spec); boxes:
+    the initial boxes; f0: the initial state in that plan's layout;
+    max_size: largest patch per level (multi-level runs)."""
 
     def __init__(self, spec, boxes, f0, tol, regrid_interval, efficiency=0.7, min_width=2, buffer=1, cfl=0.5,
-                 dt_growth=1.1, dt_initial=0.01, charges=None, background=None):
+                 dt_growth=1.1, dt_initial=0.01, charges=None, background=None, max_size=None):
         """One species: spec (a two-level spec dict), boxes, f0.  Several
         species: lists spec[s], boxes[s], f0[s] and their charges; the field
         of rho = background + sum_s charge_s n_s."""
@@ -508,6 +548,8 @@ class AmrRun:
             raise RuntimeError("the Vlasov-Poisson library needs a HIP GPU (torch.cuda is unavailable)")
         prm = vp_amr_params(float(tol), int(regrid_interval), float(efficiency), int(min_width), int(buffer),
                             float(cfl), float(dt_growth), float(dt_initial))
+        for lvl, (mx, mv) in enumerate(max_size or []):       # largest patch per level, in its own cells
+            prm.max_size[lvl][0], prm.max_size[lvl][1] = int(mx), int(mv)
         several = charges is not None
         specs, blist, flist = (spec, boxes, f0) if several else ([spec], [boxes], [f0])
         for f in flist:

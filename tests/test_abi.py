@@ -72,10 +72,14 @@ def test_amr_run_parameters_rejected_without_gpu(libvp):
         prm = vp.vp_amr_params(**dict(good, **bad))
         assert L.vp_amr_run_create(ctypes.byref(pb), None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
         assert b"bad parameters" in L.vp_last_error()
+    prm = vp.vp_amr_params(**good)
+    prm.max_size[1][0] = -1
+    assert L.vp_amr_run_create(ctypes.byref(pb), None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
+    assert b"patch size" in L.vp_last_error()
     pb.n_levels = 1
     prm = vp.vp_amr_params(**good)
     assert L.vp_amr_run_create(ctypes.byref(pb), None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
-    assert b"two levels" in L.vp_last_error()
+    assert b"two or more levels" in L.vp_last_error()
     assert L.vp_amr_run_create(None, None, 0, dummy, ctypes.byref(prm), ctypes.byref(out), None) == 1
     assert L.vp_amr_run_destroy(None) == 0
 

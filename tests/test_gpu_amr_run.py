@@ -130,7 +130,7 @@ def test_run_errors(vp):
         vp.AmrRun(spec, boxes, fg, 0.01, 0)
     with pytest.raises(vp.VPError, match="bad parameters"):
         vp.AmrRun(spec, boxes, fg, 0.01, 2, dt_growth=0.9)
-    with pytest.raises(vp.VPError, match="two levels"):
+    with pytest.raises(vp.VPError, match="two or more levels"):
         single = dict(spec, n_levels=1, veq=[[veq_c]])
         vp.AmrRun(single, [], fg, 0.01, 2)
     run = vp.AmrRun(spec, boxes, fg, 0.01, 2)
