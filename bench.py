@@ -457,70 +457,97 @@ def regrid_bench(reps=50):
     return out
 
 
+def linear_stability_courant():
+    """RK4 on the centred fourth-order flux divergence: the largest Courant
+    sum dt (|v|/dx + |a|/dv) of linear stability, 2 sqrt 2 over the peak of
+    the divergence symbol (8 sin t - sin 2t)/6 (at cos t = 1 - sqrt(6)/2)."""
+    c = 1.0 - math.sqrt(6.0) / 2.0
+    return 2.0 * math.sqrt(2.0) / (math.sqrt(1.0 - c * c) * (4.0 - c) / 3.0)
+
+
+# section 4, Table amr_param: largest patch per level (level 0 is one patch
+# here whatever its limit), smallest patch, regrid interval, tag buffer
+AMR_CASES = (
+    ("amr1", dict(largest=[(32, 32), (64, 64), (64, 64), (64, 64)], smallest=4, interval=2, buffer=1)),
+    ("amr2", dict(largest=[(16, 32), (32, 128), (128, 256), (128, 256)], smallest=8, interval=4, buffer=4)),
+    ("amr3", dict(largest=[(16, 32), (32, 128), (128, 256), (128, 256)], smallest=8, interval=8, buffer=8)),
+)
+
+
 def amr_run_bench(t_end=22.5):
-    """Adaptive bump-on-tail runs (section 4) on the two-level engine: level 0
-    64 x 128, ratio 2, so the finest mesh is the 128 x 256 the paper's AMR
-    runs resolve; tol = 0.01, dt = min(1.1 x previous, 0.5 x stability
-    limit), first dt 0.01.  Three regrid settings after the paper's AMR1-3
-    (regrid interval 2 / 4 / 8 steps, tag buffer 1 / 4 / 8 level-0 cells,
-    smallest split part 2 / 4 / 4 level-0 cells), each run to t_end; then
-    a uniform 128 x 256 run to t_end with the same time step rule.  Reports
-    wall time, regrid time, and the mean number of cells against the
-    uniform mesh."""
+    """Adaptive bump-on-tail runs of section 4 as specified: level 0 16 x 32,
+    refinement ratios [2,4], [4,2], [2,2] (up to four levels: the finest mesh
+    is 256 x 512), initial refinement [(0,8),(15,24)], tol 0.01, dt =
+    min(1.1 x previous, 0.5 x linear stability limit), first dt 0.01, the
+    three parameter sets AMR1-3 of Table amr_param (the smallest patch size
+    is taken as the smallest split part of the clustering, in cells of the
+    level that is clustered: half the new level's size at ratio 2); each
+    run to t_end; then the uniform 256 x 512 run to t_end with the same time
+    step rule.  Reports wall time, regrid time, the deepest level reached,
+    and the mean number of cells against the uniform mesh."""
     import torch
 
     import vp_inputs as I
     from paper_1204_3853_amd import vp
-    coarse, R, tol = (64, 128), 2, 0.01
+    coarse, ratios, tol = (16, 32), [(2, 4), (4, 2), (2, 2)], 0.01
     ncx, ncv = coarse
-    boxes0 = I.bump_on_tail_initial_boxes(coarse, R)
-    f0, veq_c, veq_f = I.amr_bump_on_tail(boxes0, coarse, R)
-    spec = vp.two_level_spec(ncx, ncv, I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI, -1.0, R, veq_c, veq_f,
-                             x_lo=I.BUMP_X_LO)
+    boxes0 = [{"level": 1, "lo": [0, 32], "hi": [31, 99]}]
+    f0, veqs = I.hier_state(I.bump_on_tail_profile, I.BUMP_X_LO, I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI, 0.04, 0.3,
+                            coarse, ratios, boxes0)
+    spec = vp.hierarchy_spec(ncx, ncv, I.BUMP_X_LEN, I.BUMP_V_LO, I.BUMP_V_HI, -1.0, ratios, veqs, x_lo=I.BUMP_X_LO)
     fg = torch.tensor(f0, device="cuda")
-    uniform_cells = ncx * R * ncv * R
-    out = {"workload": f"bump-on-tail, level 0 {ncx} x {ncv}, ratio {R}, tol {tol}, to t = {t_end}"}
-    for name, interval, buf, minw in (("amr1", 2, 1, 2), ("amr2", 4, 4, 4), ("amr3", 8, 8, 4)):
-        run = vp.AmrRun(spec, boxes0, fg, tol, interval, efficiency=0.7, min_width=minw, buffer=buf, cfl=0.5,
-                        dt_growth=1.1, dt_initial=0.01)
+    nxf, nvf = ncx, ncv
+    for rx, rv in ratios:
+        nxf, nvf = nxf * rx, nvf * rv
+    uniform_cells = nxf * nvf
+    out = {"workload": f"bump-on-tail (section 4), level 0 {ncx} x {ncv}, ratios {ratios}, up to "
+                       f"{len(ratios) + 1} levels (finest {nxf} x {nvf}), tol {tol}, to t = {t_end}"}
+    for name, c in AMR_CASES:
+        minw = max(1, c["smallest"] // 2)
+        run = vp.AmrRun(spec, boxes0, fg, tol, c["interval"], efficiency=0.7, min_width=minw, buffer=c["buffer"],
+                        cfl=0.5, dt_growth=1.1, dt_initial=0.01, max_size=c["largest"])
         torch.cuda.synchronize()
-        cell_steps, t0 = 0, time.perf_counter()
+        cell_steps, t0, deepest = 0, time.perf_counter(), 1
         info = run.info()
         while info["t"] < t_end:
             cells = info["state_elems"]
-            run.advance(interval)
+            run.advance(c["interval"])
             info = run.info()
-            cell_steps += cells * interval
+            cell_steps += cells * c["interval"]
+            deepest = max([deepest] + [b["level"] for b in run.boxes()])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out[name] = {"regrid_interval": interval, "tag_buffer": buf, "steps": info["steps"],
-                     "t_end": round(info["t"], 3), "wall_s": round(wall, 3),
-                     "ms_per_step": round(wall / info["steps"] * 1e3, 3), "regrids": info["regrids"],
-                     "regrid_s": round(info["regrid_seconds"], 3), "final_patches": info["npatch"],
+        out[name] = {"regrid_interval": c["interval"], "tag_buffer": c["buffer"], "largest_patch": c["largest"],
+                     "smallest_patch": c["smallest"], "steps": info["steps"], "t_end": round(info["t"], 3),
+                     "wall_s": round(wall, 3), "ms_per_step": round(wall / info["steps"] * 1e3, 3),
+                     "regrids": info["regrids"], "regrid_s": round(info["regrid_seconds"], 3),
+                     "final_patches": info["npatch"], "deepest_level": deepest,
                      "mean_cells": round(cell_steps / info["steps"]), "uniform_cells": uniform_cells,
                      "mean_reduction": round(1.0 - cell_steps / info["steps"] / uniform_cells, 3)}
         print(f"amr_run {name}: {out[name]}", file=sys.stderr, flush=True)
         del run
-    # uniform 128 x 256 reference with the same time step rule
-    nx, nv = ncx * R, ncv * R
-    prob = I.Problem1D(nx=nx, nv=nv, x_lo=I.BUMP_X_LO, x_len=I.BUMP_X_LEN, v_lo=I.BUMP_V_LO, v_hi=I.BUMP_V_HI,
+    # uniform 256 x 512 reference with the same time step rule
+    prob = I.Problem1D(nx=nxf, nv=nvf, x_lo=I.BUMP_X_LO, x_len=I.BUMP_X_LEN, v_lo=I.BUMP_V_LO, v_hi=I.BUMP_V_HI,
                        profile="bump_on_tail", eps=0.04, k=0.3)
     plan = vp.Plan(prob)
     f = torch.tensor(prob.initial_state().ravel(), device="cuda")
     a = vp.field_of(plan, f)
     vmax = max(abs(I.BUMP_V_LO), abs(I.BUMP_V_HI))
+    courant = linear_stability_courant()
     torch.cuda.synchronize()
     t, dt, steps, t0 = 0.0, None, 0, time.perf_counter()
     while t < t_end:
-        lim = 1.0 / (vmax / prob.dx + float(a.abs().max()) / prob.dv)
+        lim = courant / (vmax / prob.dx + float(a.abs().max()) / prob.dv)
         dt = min(0.01 if dt is None else 1.1 * dt, 0.5 * lim)
         vp.rk4_step(plan, f, a, dt)
         t += dt
         steps += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out["uniform"] = {"cells": nx * nv, "steps": steps, "t_end": round(t, 3), "wall_s": round(wall, 3),
+    out["uniform"] = {"cells": nxf * nvf, "steps": steps, "t_end": round(t, 3), "wall_s": round(wall, 3),
                       "ms_per_step": round(wall / steps * 1e3, 3)}
+    for name, _ in AMR_CASES:
+        out[name]["speedup_vs_uniform"] = round(wall / out[name]["wall_s"], 3)
     return out
 
 
