@@ -16,7 +16,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["vp_oracle.c", "vp_oracle_adjoint.c", "vp_oracle_amr.c", "vp_oracle_4d.c", "vp_oracle_limited.c",
-           "vp_oracle_regrid.c", "vp_oracle_hier.c"]
+           "vp_oracle_regrid.c", "vp_oracle_hier.c",
+           "vp_oracle_amr4d.c"]
 LIB = os.path.join(HERE, "libvp_oracle.so")
 
 
@@ -100,6 +101,16 @@ def _declare_extra(L):
         "vpo_rk4_dense_weights": (None, [_F, _D]),
         "vpo_rk4_substage_weights": (None, [_F, _F, _I, _D]),
         "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
+        "vpo_a4_new": (_V, [ctypes.POINTER(ctypes.c_int), _F, _F, _F, _F, _F, _I, _I, ctypes.POINTER(ctypes.c_int),
+                            _D, _D, _D, _D]),
+        "vpo_a4_free": (None, [_V]),
+        "vpo_a4_state_size": (ctypes.c_long, [_V]),
+        "vpo_a4_patch_offset": (ctypes.c_long, [_V, _I]),
+        "vpo_a4_fill_ghosts": (None, [_V, _D, _I, _D]),
+        "vpo_a4_reduce_mask": (None, [_V, _D, _D]),
+        "vpo_a4_constraints": (None, [_V, _D, _D, _D]),
+        "vpo_a4_rhs": (None, [_V, _D, _D, _D]),
+        "vpo_a4_rk4_step": (None, [_V, _D, _D, _F]),
         "vpo_hier_new": (_V, [_I, _I, _I, _F, _F, _F, _F, ctypes.POINTER(ctypes.c_int), _I,
                               ctypes.POINTER(ctypes.c_int), _D, ctypes.POINTER(ctypes.c_int)]),
         "vpo_hier_free": (None, [_V]),
@@ -636,6 +647,78 @@ class OracleHier:
         for p, b in enumerate(self.boxes):
             if b["level"] == level:
                 out[b["lo"][0]:b["hi"][0] + 1, b["lo"][1]:b["hi"][1] + 1] = self.patch_data(f, p)
+        return out
+
+
+class OracleAMR4D:
+    """Two-level 2D+2V oracle (vp_oracle_amr4d.c): level 0 of ncells =
+    (nx, ny, nvx, nvy) cells and level-1 patches (boxes with 4-entry lo/hi
+    in level-1 indices), one ratio R in every direction; g*: the 1D
+    equilibria with two ghosts per side along vx and vy of both levels."""
+
+    def __init__(self, ncells, x_len, y_len, v_lo, v_hi, qm, R, boxes, gxc, gyc, gxf, gyf):
+        self.n = tuple(ncells)
+        self.R = R
+        self.nf = tuple(c * R for c in ncells)
+        self.boxes = boxes
+        arr = np.array([list(b["lo"]) + list(b["hi"]) for b in boxes], dtype=np.int32).ravel()
+        self._boxes = np.ascontiguousarray(arr if arr.size else np.zeros(8, np.int32))
+        self._n = np.ascontiguousarray(np.array(ncells, dtype=np.int32))
+        self._g = [_f64(g) for g in (gxc, gyc, gxf, gyf)]
+        self.h = lib().vpo_a4_new(self._n.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), x_len, y_len, v_lo, v_hi,
+                                  qm, R, len(boxes), self._boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  *[_p(g) for g in self._g])
+        self.size = lib().vpo_a4_state_size(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.vpo_a4_free(self.h)
+            self.h = None
+
+    def offset(self, p):
+        return lib().vpo_a4_patch_offset(self.h, p)
+
+    def shape(self, p):
+        if p < 0:
+            return self.n
+        b = self.boxes[p]
+        return tuple(b["hi"][d] - b["lo"][d] + 1 for d in range(4))
+
+    def patch(self, f, p):
+        s = self.shape(p)
+        o = self.offset(p)
+        return np.asarray(f)[o:o + int(np.prod(s))].reshape(s)
+
+    def ghosted(self, f, p):
+        f = _f64(f)
+        s = tuple(c + 4 for c in self.shape(p))
+        out = np.empty(s)
+        lib().vpo_a4_fill_ghosts(self.h, _p(f), p, _p(out))
+        return out
+
+    def reduce_mask(self, f):
+        f = _f64(f)
+        out = np.empty(self.nf[0] * self.nf[1])
+        lib().vpo_a4_reduce_mask(self.h, _p(f), _p(out))
+        return out
+
+    def constraints(self, f):
+        f = _f64(f)
+        a = np.empty(2 * (self.n[0] * self.n[1] + self.nf[0] * self.nf[1]))
+        E = np.empty(2 * self.nf[0] * self.nf[1])
+        lib().vpo_a4_constraints(self.h, _p(f), _p(a), _p(E))
+        return a, E
+
+    def rhs(self, f, a):
+        f, a = _f64(f), _f64(a)
+        k = np.empty_like(f)
+        lib().vpo_a4_rhs(self.h, _p(f), _p(a), _p(k))
+        return k
+
+    def step(self, f, dt):
+        f = _f64(f)
+        out = np.empty_like(f)
+        lib().vpo_a4_rk4_step(self.h, _p(f), _p(out), dt)
         return out
 
 

@@ -81,6 +81,20 @@ void vpo_hier_rk4_step(void* h, const double* f_in, double* f_out, double dt);
 void vpo_hier_tag_values(void* h, const double* f, int l, double* values);
 int vpo_hier_prolong_box(void* h, const double* f, int l, int x0, int v0, int x1, int v1, double* out);
 
+/* two-level 2D+2V hierarchy (vp_oracle_amr4d.c): ncells[4] level-0 cells
+ * (x, y, vx, vy), one ratio R in every direction, boxes: np x 8 (lo[4],
+ * hi[4] in level-1 indices); a = [a_c (2 ncx ncy)][a_f (2 nfx nfy)] */
+void* vpo_a4_new(const int* ncells, double x_len, double y_len, double v_lo, double v_hi, double qm, int R, int np,
+                 const int* boxes, const double* gxc, const double* gyc, const double* gxf, const double* gyf);
+void vpo_a4_free(void* h);
+long vpo_a4_state_size(void* h);
+long vpo_a4_patch_offset(void* h, int p);
+void vpo_a4_fill_ghosts(void* h, const double* f, int p, double* out);
+void vpo_a4_reduce_mask(void* h, const double* f, double* n);
+void vpo_a4_constraints(void* h, const double* f, double* a, double* E_out);
+void vpo_a4_rhs(void* h, const double* f, const double* a, double* k);
+void vpo_a4_rk4_step(void* h, const double* f_in, double* f_out, double dt);
+
 /* regridding (section 3): refinement criterion and conservative limited interpolation */
 double vpo_tag_value(int nx, int nv, double dx, double dv, const double* vghost, const double* f, int i, int j);
 void vpo_tag(int nx, int nv, double dx, double dv, const double* vghost, const double* f, double tol,

@@ -189,6 +189,25 @@ class Problem2D:
         return np.ascontiguousarray(xy[:, :, None, None] * gx[None, None, :, None] * gy[None, None, None, :])
 
 
+def amr4d_state(ncells, R, boxes, eps=0.05, k=0.5, x_len=4.0 * math.pi, y_len=4.0 * math.pi, v_lo=-6.0,
+                v_hi=6.0):
+    """Two-level 2D+2V state: exact cell averages of (1 + eps (cos kx +
+    cos ky)) M(vx) M(vy) on level 0 (ncells = (nx, ny, nvx, nvy)) and on
+    every level-1 patch (ratio R in every direction; boxes with 4-entry
+    lo/hi), concatenated [level 0][patches in order]; returns (state, gxc,
+    gyc, gxf, gyf), the 1D equilibria with two ghosts per side."""
+    c = Problem2D(*ncells, x_len=x_len, y_len=y_len, v_lo=v_lo, v_hi=v_hi, eps=eps, k=k)
+    fpb = Problem2D(*[n * R for n in ncells], x_len=x_len, y_len=y_len, v_lo=v_lo, v_hi=v_hi, eps=eps, k=k)
+    parts = [c.initial_state().ravel()]
+    ff = None
+    for b in boxes:
+        if ff is None:
+            ff = fpb.initial_state()
+        sl = tuple(slice(b["lo"][d], b["hi"][d] + 1) for d in range(4))
+        parts.append(np.ascontiguousarray(ff[sl]).ravel())
+    return np.concatenate(parts), c.veq_x, c.veq_y, fpb.veq_x, fpb.veq_y
+
+
 # ---------------------------------------------------------------- AMR layout
 
 
