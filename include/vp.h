@@ -82,8 +82,15 @@ typedef enum vp_dtype { VP_F64 = 0, VP_F32 = 1 } vp_dtype;
  *             equilibrium supplied on both ends); in 2D+2V the equilibrium
  *             is the product veq[l][0][j] * veq[l][1][k].  Copied at plan
  *             creation.
- * 2D+2V plans are single-level FP64 with nx, ny <= 64, nvx <= 1024 and
- * nvy <= 64 (VP_ENOTSUP otherwise).
+ * Single-level 2D+2V plans are FP64 with nx, ny <= 64, nvx <= 1024 and
+ * nvy <= 64 (VP_ENOTSUP otherwise).  Two-level 2D+2V plans (the hierarchy
+ * of section 3 in the 2D+2V phase space) are FP64 with one ratio, 2 or 4,
+ * in all four directions, the same velocity interval along vx and vy, and
+ * a fine configuration mesh of at most 64 x 64 cells; their charge density
+ * is the Mask reduction (Alg. mreduce) onto the fine configuration mesh,
+ * where the Poisson equation is solved, and a holds [level-0 x][level-0
+ * y][level-1 x][level-1 y] components, level 0 taking the mean of its
+ * R x R fine values.
  */
 typedef struct vp_problem {
     int32_t ndim;
@@ -100,19 +107,21 @@ typedef struct vp_problem {
 } vp_problem;
 
 /*
- * A level-1 patch: inclusive cell range [lo, hi] per direction in the
- * level-1 global index space (section 3, box notation).  Level 0 always
- * covers the whole domain and is implicit.  Patches must be inside the
- * domain (no periodic wrap inside one patch), aligned to the refinement
- * ratio (lo and hi + 1 multiples of it) and disjoint (VP_EINVAL
- * otherwise).  Patches may touch, also across the periodic x boundary:
+ * A patch on level `level` >= 1: inclusive cell range [lo, hi] per
+ * direction in that level's global index space (section 3, box notation).
+ * Level 0 always covers the whole domain and is implicit.  Patches must be
+ * inside the domain (no periodic wrap inside one patch), aligned to the
+ * refinement ratio of their parent level (lo and hi + 1 multiples of it)
+ * and disjoint on their level (VP_EINVAL otherwise); a patch on level
+ * l >= 2 must be nested in level l-1 with room for its ghost
+ * interpolation.  Patches may touch, also across the periodic x boundary:
  * ghost cells that a neighbouring patch holds are copied from it (ghost
  * cells for inter-patch communication, section 3; Alg. mspsc), the others
- * interpolated from level 0, so a fine-fine face gets the same flux from
- * both sides and only coarse-fine faces are corrected at the end of a
- * step.  Two levels are supported for 1D+1V in FP64 with ratio 2 or 4
- * (equal in x and v) and a finest configuration mesh of at most 8192
- * cells.
+ * interpolated from the parent level, so a fine-fine face gets the same
+ * flux from both sides and only coarse-fine faces are corrected at the end
+ * of a step.  1D+1V: FP64, up to VP_MAX_LEVELS levels with a ratio per
+ * level and direction, a finest configuration mesh of at most 8192 cells.
+ * 2D+2V: FP64, two levels (lo and hi hold x, y, vx, vy).
  */
 typedef struct vp_box {
     int32_t level;

@@ -11,8 +11,6 @@
 
 namespace vp {
 
-namespace {
-
 // Real orthonormal Fourier basis of the periodic n-cell mesh, Q[i * n + m]:
 // m = 0 the constant, m = 2k - 1 / 2k the cosine / sine of frequency k,
 // and for even n the last column the alternating vector.  Every symmetric
@@ -45,6 +43,8 @@ std::vector<double> fourier_symbol(int n, double h)
     }
     return lam;
 }
+
+namespace {
 
 hipError_t upload(double** dst, const std::vector<double>& v)
 {

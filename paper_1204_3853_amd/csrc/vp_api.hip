@@ -273,6 +273,32 @@ vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox
     return VP_OK;
 }
 
+// two-level 2D+2V plan (vp_amr4d.hip): the configuration-space calls act
+// on the fine configuration mesh
+vp_status create_amr4d(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out)
+{
+    if (pb->n_levels != 2) return fail(VP_ENOTSUP, "2D+2V hierarchies have two levels");
+    vp_plan* p = new (std::nothrow) vp_plan();
+    if (!p) return fail(VP_ENOMEM, "out of host memory");
+    p->pb = *pb;
+    p->ndim = 2;
+    p->dtype = pb->dtype;
+    p->nlev = 2;
+    p->esize = 8;
+    for (int l = 0; l < VP_MAX_LEVELS; ++l)
+        for (int d = 0; d < 2; ++d) p->pb.veq[l][d] = nullptr;
+    vp_status st = a4_create(p, pb, boxes, nbox);
+    if (st != VP_OK) {
+        a4_destroy(p);
+        delete p;
+        return st;
+    }
+    p->nx = p->a4->nf[0] * p->a4->nf[1];
+    p->shape = StageShape{256, 1, 1};
+    *out = p;
+    return VP_OK;
+}
+
 // single-level 2D+2V plan (vp_4d.hip)
 vp_status create_4d(const vp_problem* pb, vp_plan** out)
 {
@@ -316,6 +342,7 @@ std::vector<StageShape> amr_shape_table()
 std::vector<StageShape> plan_shapes(const vp_plan* p)
 {
     if (p->p4) return shape_table_4d();
+    if (p->a4) return {StageShape{256, 1, 1}};
     return (p->amr || p->hier) ? amr_shape_table() : shape_table(p->dtype);
 }
 
@@ -368,6 +395,7 @@ vp_status vp_plan_create(const vp_problem* pb, const vp_box* boxes, int32_t nbox
         if (!(pb->v_hi[d] > pb->v_lo[d])) return fail(VP_EINVAL, "v_hi must exceed v_lo");
         if (!pb->veq[0][d]) return fail(VP_EINVAL, "veq[0][d] (equilibrium with ghosts) is required");
     }
+    if (pb->n_levels >= 2 && pb->ndim == 2) return create_amr4d(pb, boxes, nbox, out);
     if (pb->n_levels >= 2) return create_multi_level(pb, boxes, nbox, out, false);
     if (nbox != 0) return fail(VP_EINVAL, "a single-level plan takes no boxes");
     if (pb->ndim == 2) return create_4d(pb, out);
@@ -472,7 +500,7 @@ vp_status vp_face_scheme_set(vp_plan* p, int32_t scheme)
     if (vp_status s = check_plan(p)) return s;
     if (scheme != VP_FACE_CENTERED && scheme != VP_FACE_LIMITED)
         return fail(VP_EINVAL, "vp_face_scheme_set: unknown scheme");
-    if (scheme == VP_FACE_LIMITED && (p->amr || p->hier || p->p4))
+    if (scheme == VP_FACE_LIMITED && (p->amr || p->hier || p->p4 || p->a4))
         return fail(VP_ENOTSUP, "vp_face_scheme_set: limited faces are built for single-level 1D+1V plans");
     p->face_scheme = scheme;
     return VP_OK;
@@ -486,6 +514,8 @@ vp_status vp_reduction_set(vp_plan* p, int32_t algorithm)
     if (p->amr) p->amr->reduce_mode = algorithm;
     if (p->hier && algorithm != VP_REDUCE_SUBPATCH)
         return fail(VP_ENOTSUP, "vp_reduction_set: multi-level plans use the Sub-Patch reduction");
+    if (p->a4 && algorithm != VP_REDUCE_MASK)
+        return fail(VP_ENOTSUP, "vp_reduction_set: two-level 2D+2V plans use the Mask reduction");
     return VP_OK;
 }
 
@@ -495,8 +525,8 @@ vp_status vp_launch_mode_set(vp_plan* p, int32_t mode)
     if (mode != VP_LAUNCH_PERSISTENT && mode != VP_LAUNCH_PER_PATCH)
         return fail(VP_EINVAL, "vp_launch_mode_set: unknown mode");
     if (p->amr) p->amr->mode = mode;
-    if (p->hier && mode != VP_LAUNCH_PERSISTENT)
-        return fail(VP_ENOTSUP, "vp_launch_mode_set: multi-level plans use the persistent launch");
+    if ((p->hier || p->a4) && mode != VP_LAUNCH_PERSISTENT)
+        return fail(VP_ENOTSUP, "vp_launch_mode_set: multi-level and 2D+2V plans use the persistent launch");
     return VP_OK;
 }
 
@@ -590,6 +620,7 @@ vp_status vp_plan_destroy(vp_plan* p)
     amr_destroy(p);
     hier_destroy(p);
     p4_destroy(p);
+    a4_destroy(p);
     delete p;
     return VP_OK;
 }
@@ -602,6 +633,7 @@ int64_t vp_patch_offset(const vp_plan* p, int32_t patch)
     if (patch == -1) return 0;
     if (p->amr && patch >= 0 && patch < (int32_t)p->amr->patches.size()) return p->amr->patches[patch].off;
     if (p->hier && patch >= 0 && patch + 1 < (int32_t)p->hier->patches.size()) return p->hier->patches[patch + 1].off;
+    if (p->a4 && patch >= 0 && patch + 1 < (int32_t)p->a4->patches.size()) return p->a4->patches[patch + 1].off;
     return -1;
 }
 
@@ -610,6 +642,7 @@ size_t vp_field_elems(const vp_plan* p)
 {
     if (!p) return 0;
     if (p->p4) return 2 * (size_t)p->nx;
+    if (p->a4) return 2 * (size_t)(p->a4->nc[0] * p->a4->nc[1] + p->nx);
     if (p->hier) return (size_t)p->hier->na;
     return p->amr ? (size_t)(p->amr->ncx + p->amr->nfx) : (size_t)p->nx;
 }
@@ -617,7 +650,7 @@ size_t vp_workspace_bytes(const vp_plan* p) { return p ? p->ws_total : 0; }
 
 size_t vp_stage_elems(const vp_plan* p)
 {
-    if (!p || p->amr || p->hier || p->p4) return 0;
+    if (!p || p->amr || p->hier || p->p4 || p->a4) return 0;
     const size_t a_bytes = 4 * (size_t)p->nx * sizeof(double);
     return 3 * p->state_elems + (a_bytes + p->esize - 1) / p->esize;
 }
@@ -630,6 +663,7 @@ vp_status vp_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipS
     if (p->amr) return amr_rhs(p, f, a, k, stream);
     if (p->hier) return hier_rhs(p, f, a, k, stream);
     if (p->p4) return p4_rhs(p, f, a, k, stream);
+    if (p->a4) return a4_rhs(p, f, a, k, stream);
     const StageShape sh = pick_shape(p, {f, k});
     Stage1DArgs A = base_args(p, sh);
     A.fs = f;
@@ -652,6 +686,10 @@ vp_status vp_reduce_moment(const vp_plan* p, const void* f, double* n, void* wor
         return hier_reduce(p, f, n, work, stream);
     }
     if (p->p4) return p4_reduce(p, f, n, stream);
+    if (p->a4) {
+        if (!work) return fail(VP_EINVAL, "vp_reduce_moment: a two-level plan needs the workspace");
+        return a4_reduce(p, f, n, work, stream);
+    }
     VP_HIP(timed(p, kTMoment, stream, [&] { return launch_moment_rows(p->dtype, f, p->nx, p->nv, p->dv, n, stream); }));
     return VP_OK;
 }
@@ -663,6 +701,7 @@ vp_status vp_poisson_periodic(const vp_plan* p, const double* n, double* phi, do
     if (vp_status s = check_plan(p)) return s;
     if (!n) return fail(VP_EINVAL, "vp_poisson_periodic: NULL n");
     if (p->p4) return p4_poisson(p, n, phi, E, stream);
+    if (p->a4) return a4_poisson(p, n, phi, E, stream);
     VP_HIP(timed(p, kTField, stream, [&] {
         return launch_poisson1d(nullptr, 0, n, p->dv, p->nx, p->dx, p->pb.qm, p->d_green, p->gk, nullptr, phi, E,
                                 nullptr, stream);
@@ -676,6 +715,7 @@ vp_status vp_inject_field(const vp_plan* p, const double* E, double* a, hipStrea
     if (!E || !a) return fail(VP_EINVAL, "vp_inject_field: NULL pointer");
     if (p->amr) return amr_inject(p, E, a, stream);
     if (p->hier) return hier_inject(p, E, a, stream);
+    if (p->a4) return a4_inject(p, E, a, stream);
     if (p->p4) {
         VP_HIP(timed(p, kTOther, stream, [&] { return launch_scale(E, p->pb.qm, a, 2 * p->nx, stream); }));
         return VP_OK;
@@ -692,6 +732,7 @@ vp_status vp_rk4_step(const vp_plan* p, void* f, double* a, double dt, void* wor
     if (p->amr) return amr_rk4(p, f, a, dt, work, stream);
     if (p->hier) return hier_rk4(p, f, a, dt, work, stream);
     if (p->p4) return p4_rk4(p, f, a, dt, work, stream);
+    if (p->a4) return a4_rk4(p, f, a, dt, work, stream);
     return rk4_1d(p, f, a, dt, work, nullptr, nullptr, stream);
 }
 
@@ -700,7 +741,7 @@ vp_status vp_rk4_step_noalloc(const vp_plan* p, void* f, double* a, double dt, h
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a) return fail(VP_EINVAL, "vp_rk4_step_noalloc: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_noalloc: dt is not finite");
-    if (p->amr || p->hier || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_noalloc: single-level 1D+1V plans only");
+    if (p->amr || p->hier || p->p4 || p->a4) return fail(VP_ENOTSUP, "vp_rk4_step_noalloc: single-level 1D+1V plans only");
     if (p->ws_step > kScratchBytes)
         return fail(VP_ESHAPE, "vp_rk4_step_noalloc: the step needs " + std::to_string(p->ws_step) +
                                    " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
@@ -725,7 +766,7 @@ vp_status vp_rk4_step_record(const vp_plan* p, void* f, double* a, double dt, vo
     if (vp_status s = check_plan(p)) return s;
     if (!f || !a || !work || !stages) return fail(VP_EINVAL, "vp_rk4_step_record: NULL pointer");
     if (!std::isfinite(dt)) return fail(VP_EINVAL, "vp_rk4_step_record: dt is not finite");
-    if (p->amr || p->hier || p->p4) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level 1D+1V plans only");
+    if (p->amr || p->hier || p->p4 || p->a4) return fail(VP_ENOTSUP, "vp_rk4_step_record: single-level 1D+1V plans only");
     if (p->face_scheme != VP_FACE_CENTERED)
         return fail(VP_ENOTSUP, "vp_rk4_step_record: the adjoint is built for the centred (unlimited) scheme");
     double* st_a = reinterpret_cast<double*>(static_cast<char*>(stages) + 3 * p->state_elems * p->esize);
@@ -738,7 +779,7 @@ vp_status vp_field_adjoint(const vp_plan* p, const double* abar, void* fbar, voi
     if (vp_status s = check_plan(p)) return s;
     if (!abar || !fbar || !work) return fail(VP_EINVAL, "vp_field_adjoint: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_field_adjoint: FP64 only");
-    if (p->amr || p->hier || p->p4) return fail(VP_ENOTSUP, "vp_field_adjoint: single-level 1D+1V plans only");
+    if (p->amr || p->hier || p->p4 || p->a4) return fail(VP_ENOTSUP, "vp_field_adjoint: single-level 1D+1V plans only");
     double* cfg = reinterpret_cast<double*>(wsp(work, p->ws_cfg));
     double* ab = cfg;
     double* z = cfg + p->nx;
@@ -758,7 +799,7 @@ vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, 
     if (vp_status s = check_plan(p)) return s;
     if (!f_n || !a_n || !lam_np1 || !lam_n || !work) return fail(VP_EINVAL, "vp_adjoint_step: NULL pointer");
     if (p->dtype != VP_F64) return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is FP64 only");
-    if (p->amr || p->hier || p->p4 || p->nlev != 1 || p->ndim != 1)
+    if (p->amr || p->hier || p->p4 || p->a4 || p->nlev != 1 || p->ndim != 1)
         return fail(VP_ENOTSUP, "vp_adjoint_step: single-level 1D+1V only");
     if (p->face_scheme != VP_FACE_CENTERED)
         return fail(VP_ENOTSUP, "vp_adjoint_step: the adjoint is built for the centred (unlimited) scheme");

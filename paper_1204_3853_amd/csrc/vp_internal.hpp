@@ -154,6 +154,59 @@ struct AmrArgs {
     int first;                 // first stage: store instead of add
 };
 
+// ----------------------------------------------------------------- two-level 2D+2V
+
+struct A4Patch {               // level 0 (patch 0) or a level-1 patch of a two-level 2D+2V plan
+    long long off;             // state offset, [x][y][vx][vy]
+    long long pad;             // offset of its padded copy (two ghost layers per direction)
+    long long foff;            // boundary flux blocks: x lo/hi [ny][nvx][nvy], y lo/hi [nx][nvx][nvy],
+                               // vx lo/hi [nx][ny][nvy], vy lo/hi [nx][ny][nvx]
+    int lo[4], sz[4];          // first cell (level index space) and cells per direction
+    int lev, nb0, nb1, pad_;   // level; neighbour list range (patches holding some of its ghost cells)
+};
+
+struct A4Level {
+    int n[4];                  // index space
+    double h[4], hi[4];        // cell sizes and their inverses
+    double v_lo;
+    int a_off;                 // offset of the level's a: [x component][y component], each n0 n1
+};
+
+struct A4Args {
+    A4Level lv[2];
+    const A4Patch* patches;
+    const int* nb;
+    const int* tiles;          // per tile: patch index and first cell (2 ints)
+    int ntiles;
+    const double* pad;         // padded copies of the stage input
+    const double* fn;
+    double* acc;
+    double* fout;
+    const double* a;
+    double* ff_acc;            // accumulated patch boundary fluxes
+    double c_acc, c_next, c_flux;
+    int first;
+};
+
+struct A4Face {                // a level-0 face on a coarse-fine interface
+    int cell[4];               // the low cell (the face is its upper face along dir)
+    int dir;
+    int pad_;
+};
+
+hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
+                         const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
+                         const double* gyc, const double* gxf, const double* gyf, double* pad, hipStream_t stream);
+hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream);
+hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, double* cf_acc, hipStream_t stream);
+hipError_t launch_a4_masked(const double* f0, const unsigned char* mask, const int* n, double* M, hipStream_t stream);
+hipError_t launch_a4_inject(double* a, int ncx, int ncy, int R, hipStream_t stream);
+hipError_t launch_a4_reflux(double* f, const long long* cell, const int* ptr, const int* code, const int* fine,
+                            int nfine, const double* ff, const double* cf, const A4Face* faces, const double* hdt, double dt,
+                            int ncorr, hipStream_t stream);
+hipError_t launch_a4_average(double* f, const long long* dst, const long long* src, const int* strides, int R, int n,
+                             hipStream_t stream);
+
 // ----------------------------------------------------------------- multi-level hierarchies
 
 constexpr int kHierLevels = VP_MAX_LEVELS;
@@ -456,6 +509,41 @@ struct AmrPlan {
     size_t ws_hist = 0, ws_nc = 0, hist_stride = 0;
 };
 
+// two-level 2D+2V plan (vp_amr4d.hip)
+struct Amr4DPlan {
+    int R = 2;
+    int nc[4] = {}, nf[4] = {};
+    A4Level lv[2] = {};
+    std::vector<A4Patch> patches;                    // patch 0 is level 0
+    size_t total = 0, pad_total = 0, fflux = 0;
+    int ntiles = 0, nfaces = 0, ncorr = 0, ntasks = 0, navg = 0, ncfg = 0;
+    void* d_tables = nullptr;
+    A4Patch* d_patches = nullptr;
+    int* d_list = nullptr;
+    int* d_nb = nullptr;
+    int* d_tiles = nullptr;
+    double* d_B = nullptr;
+    double *d_gxc = nullptr, *d_gyc = nullptr, *d_gxf = nullptr, *d_gyf = nullptr;
+    A4Face* d_faces = nullptr;
+    unsigned char* d_mask = nullptr;
+    long long* d_task_off = nullptr;
+    int* d_task_len = nullptr;
+    int* d_rowptr = nullptr;
+    int* d_idx = nullptr;
+    double* d_w = nullptr;
+    long long* d_corr_cell = nullptr;
+    int* d_corr_ptr = nullptr;
+    int* d_corr_code = nullptr;
+    int* d_fine = nullptr;                           // per face: its R^3 fine faces in the boundary-flux buffer
+    long long* d_avg_dst = nullptr;
+    long long* d_avg_src = nullptr;
+    int* d_avg_strides = nullptr;
+    double *d_Qx = nullptr, *d_Qy = nullptr, *d_inv = nullptr;   // fine configuration mesh Fourier tables
+    double* d_rhs_pad = nullptr;                     // padded copies for vp_rhs, which takes no workspace
+    double* d_g = nullptr;                           // Fourier coefficients of vp_poisson_periodic calls
+    size_t ws_pad = 0, ws_ff = 0, ws_cf = 0, ws_slots = 0, ws_n = 0, ws_g = 0;
+};
+
 // multi-level plan (vp_hier.hip): L levels, a ratio per level and direction
 struct HierPlan {
     int L = 2;
@@ -556,6 +644,7 @@ struct vp_plan {
     vp::AmrPlan* amr = nullptr;
     vp::Plan4D* p4 = nullptr;
     vp::HierPlan* hier = nullptr;
+    vp::Amr4DPlan* a4 = nullptr;
 };
 
 namespace vp {
@@ -608,6 +697,19 @@ struct TableArena {
         return hipSuccess;
     }
 };
+
+// two-level 2D+2V host sequences (vp_amr4d.hip)
+vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);
+void a4_destroy(vp_plan* p);
+vp_status a4_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream);
+vp_status a4_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream);
+vp_status a4_poisson(const vp_plan* p, const double* n, double* phi, double* E, hipStream_t stream);
+vp_status a4_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
+vp_status a4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
+// real orthonormal Fourier basis and the symbol of the 1D fourth-order
+// Poisson operator on an n-cell periodic mesh (vp_4d.hip)
+std::vector<double> fourier_basis(int n);
+std::vector<double> fourier_symbol(int n, double h);
 
 // b_j(s) of the conservative fifth-order sub-cell interpolation for ratio R
 // (section 3), R x 5 values at [s * 5 + j + 2] (vp_amr.hip)

@@ -1,0 +1,407 @@
+// HIP kernels of the two-level 2D+2V path (the AMR of section 3 carried to
+// the 2D+2V phase space).  Every patch, level 0 included, is copied each
+// stage into a padded array with two ghost layers per direction; only the
+// ghost cells the flux stencils read are filled (a cell outside the patch
+// along one direction, or along one configuration and one velocity
+// direction): on level 0 the periodic wrap and the equilibrium product; on
+// level 1 the value of the level-1 patch that holds the cell, the fine
+// equilibrium product outside the velocity box, else the conservative
+// fifth-order sub-cell interpolation of level 0 as a tensor product over
+// x, y, vx, vy.  The stage kernel then evaluates the fluxes of section 2
+// direction by direction (the single-level 2D+2V formulas) from the padded
+// arrays, one thread per cell.
+#include <hip/hip_runtime.h>
+
+#include "vp_internal.hpp"
+#include "vp_stage_tile.hpp"
+
+namespace vp {
+
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ int wrap4(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+
+struct A4View {
+    const double* p;
+    long long s0, s1, s2;      // strides of the padded array (the last is 1)
+    __device__ __forceinline__ double operator()(int i, int j, int k, int l) const
+    {
+        return p[(i + 2) * s0 + (j + 2) * s1 + (k + 2) * s2 + (l + 2)];
+    }
+};
+
+__device__ __forceinline__ A4View view_of(const double* pad, const A4Patch& P)
+{
+    A4View v;
+    v.p = pad + P.pad;
+    v.s2 = P.sz[3] + 4;
+    v.s1 = (long long)(P.sz[2] + 4) * v.s2;
+    v.s0 = (long long)(P.sz[1] + 4) * v.s1;
+    return v;
+}
+
+__device__ __forceinline__ double a_at(const double* a, const A4Level& L, int comp, int I, int J)
+{
+    return a[L.a_off + comp * L.n[0] * L.n[1] + wrap4(I, L.n[0]) * L.n[1] + wrap4(J, L.n[1])];
+}
+
+// flux through the upper face along `dir` of cell (i, j, k, l) of a patch
+// (local indices; the face's other cells come from the padded copy)
+__device__ double face_flux(const A4View& U, const A4Patch& P, const A4Level& L, const double* a, int dir, int i,
+                            int j, int k, int l)
+{
+    if (dir == 0) {
+        const double fc = face4<double>(U(i - 1, j, k, l), U(i, j, k, l), U(i + 1, j, k, l), U(i + 2, j, k, l));
+        const double fu = face4<double>(U(i - 1, j, k + 1, l), U(i, j, k + 1, l), U(i + 1, j, k + 1, l),
+                                        U(i + 2, j, k + 1, l));
+        const double fd = face4<double>(U(i - 1, j, k - 1, l), U(i, j, k - 1, l), U(i + 1, j, k - 1, l),
+                                        U(i + 2, j, k - 1, l));
+        const double vb = L.v_lo + ((double)(P.lo[2] + k) + 0.5) * L.h[2];
+        return vb * fc + L.h[2] / 24.0 * (fu - fd);
+    }
+    if (dir == 1) {
+        const double fc = face4<double>(U(i, j - 1, k, l), U(i, j, k, l), U(i, j + 1, k, l), U(i, j + 2, k, l));
+        const double fu = face4<double>(U(i, j - 1, k, l + 1), U(i, j, k, l + 1), U(i, j + 1, k, l + 1),
+                                        U(i, j + 2, k, l + 1));
+        const double fd = face4<double>(U(i, j - 1, k, l - 1), U(i, j, k, l - 1), U(i, j + 1, k, l - 1),
+                                        U(i, j + 2, k, l - 1));
+        const double vb = L.v_lo + ((double)(P.lo[3] + l) + 0.5) * L.h[3];
+        return vb * fc + L.h[3] / 24.0 * (fu - fd);
+    }
+    const int I = P.lo[0] + i, J = P.lo[1] + j;
+    const int c = dir - 2;
+    const double ac = a_at(a, L, c, I, J);
+    const double dax = a_at(a, L, c, I + 1, J) - a_at(a, L, c, I - 1, J);
+    const double day = a_at(a, L, c, I, J + 1) - a_at(a, L, c, I, J - 1);
+    auto fv = [&](int ii, int jj) {
+        return dir == 2 ? face4<double>(U(ii, jj, k - 1, l), U(ii, jj, k, l), U(ii, jj, k + 1, l), U(ii, jj, k + 2, l))
+                        : face4<double>(U(ii, jj, k, l - 1), U(ii, jj, k, l), U(ii, jj, k, l + 1), U(ii, jj, k, l + 2));
+    };
+    return ac * fv(i, j) + (dax * (fv(i + 1, j) - fv(i - 1, j)) + day * (fv(i, j + 1) - fv(i, j - 1))) / 48.0;
+}
+
+struct A4PadArgs {
+    const double* f;
+    const A4Patch* patches;
+    const int* list;
+    int npatch;
+    const int* nb;
+    A4Level lv[2];
+    const double* B;           // b_j(s) at B[s * 5 + j + 2]
+    int R;
+    const double *gxc, *gyc, *gxf, *gyf;
+    double* pad;
+};
+
+// level-0 value with x, y periodic and the coarse equilibrium product outside the velocity box
+__device__ __forceinline__ double coarse_at(const A4PadArgs& A, int i, int j, int k, int l)
+{
+    const A4Level& L = A.lv[0];
+    if (k < 0 || k >= L.n[2] || l < 0 || l >= L.n[3]) return A.gxc[k + 2] * A.gyc[l + 2];
+    return A.f[(((long long)wrap4(i, L.n[0]) * L.n[1] + wrap4(j, L.n[1])) * L.n[2] + k) * L.n[3] + l];
+}
+
+__global__ __launch_bounds__(256) void k_a4_pad(A4PadArgs A, long long total)
+{
+    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (g >= total) return;
+    // the patch whose padded range holds g (patches are listed in padded order)
+    int lo = 0, hi = A.npatch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.patches[A.list[mid]].pad <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const A4Patch P = A.patches[A.list[lo]];
+    long long r = g - P.pad;
+    const int g3 = P.sz[3] + 4, g2 = P.sz[2] + 4, g1 = P.sz[1] + 4;
+    const int l = (int)(r % g3) - 2; r /= g3;
+    const int k = (int)(r % g2) - 2; r /= g2;
+    const int j = (int)(r % g1) - 2; r /= g1;
+    const int i = (int)r - 2;
+    const bool ox = i < 0 || i >= P.sz[0], oy = j < 0 || j >= P.sz[1];
+    const bool ok = k < 0 || k >= P.sz[2], ol = l < 0 || l >= P.sz[3];
+    const int nout = (int)ox + (int)oy + (int)ok + (int)ol;
+    double v;
+    if (nout == 0) {
+        v = A.f[P.off + (((long long)i * P.sz[1] + j) * P.sz[2] + k) * P.sz[3] + l];
+    } else {
+        // only the ghost cells the flux stencils read: outside along one
+        // direction, or along one configuration and one velocity direction
+        if (nout > 2 || (ox && oy) || (ok && ol)) return;
+        const A4Level& L = A.lv[P.lev];
+        const int I = P.lo[0] + i, J = P.lo[1] + j, K = P.lo[2] + k, Lv = P.lo[3] + l;
+        if (P.lev == 0) {
+            v = coarse_at(A, I, J, K, Lv);
+        } else if (K < 0 || K >= L.n[2] || Lv < 0 || Lv >= L.n[3]) {
+            v = A.gxf[K + 2] * A.gyf[Lv + 2];
+        } else {
+            bool held = false;
+            const int Iw = wrap4(I, L.n[0]), Jw = wrap4(J, L.n[1]);
+            for (int e = P.nb0; e < P.nb1 && !held; ++e) {
+                const A4Patch Q = A.patches[A.nb[e]];
+                const int di = Iw - Q.lo[0], dj = Jw - Q.lo[1], dk = K - Q.lo[2], dl = Lv - Q.lo[3];
+                if (di >= 0 && di < Q.sz[0] && dj >= 0 && dj < Q.sz[1] && dk >= 0 && dk < Q.sz[2] && dl >= 0 &&
+                    dl < Q.sz[3]) {
+                    v = A.f[Q.off + (((long long)di * Q.sz[1] + dj) * Q.sz[2] + dk) * Q.sz[3] + dl];
+                    held = true;
+                }
+            }
+            if (!held) {
+                const int R = A.R;
+                const int ci = (I >= 0 ? I : I - R + 1) / R, cj = (J >= 0 ? J : J - R + 1) / R;
+                const int ck = K / R, cl = Lv / R;
+                const double* bi = A.B + (I - ci * R) * 5;
+                const double* bj = A.B + (J - cj * R) * 5;
+                const double* bk = A.B + (K - ck * R) * 5;
+                const double* bl = A.B + (Lv - cl * R) * 5;
+                double acc = 0.0;
+                for (int d = 0; d < 5; ++d) {
+                    double av = 0.0;
+                    for (int e = 0; e < 5; ++e) {
+                        double ay = 0.0;
+                        for (int b = 0; b < 5; ++b) {
+                            double ax = 0.0;
+#pragma unroll
+                            for (int aa = 0; aa < 5; ++aa)
+                                ax += bi[aa] * coarse_at(A, ci + aa - 2, cj + b - 2, ck + e - 2, cl + d - 2);
+                            ay += bj[b] * ax;
+                        }
+                        av += bk[e] * ay;
+                    }
+                    acc += bl[d] * av;
+                }
+                v = acc;
+            }
+        }
+    }
+    A.pad[g] = v;
+}
+
+__device__ __forceinline__ void flux_store(double* p, double v, const A4Args& A)
+{
+    if (A.first) *p = A.c_flux * v;
+    else *p += A.c_flux * v;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_a4_stage(A4Args A)
+{
+    const int t = blockIdx.x;
+    const A4Patch P = A.patches[A.tiles[2 * t]];
+    const long long c = (long long)A.tiles[2 * t + 1] + threadIdx.x;
+    const long long ncell = (long long)P.sz[0] * P.sz[1] * P.sz[2] * P.sz[3];
+    if (c >= ncell) return;
+    long long r = c;
+    const int l = (int)(r % P.sz[3]); r /= P.sz[3];
+    const int k = (int)(r % P.sz[2]); r /= P.sz[2];
+    const int j = (int)(r % P.sz[1]); r /= P.sz[1];
+    const int i = (int)r;
+    const A4Level& L = A.lv[P.lev];
+    const A4View U = view_of(A.pad, P);
+    const double gx1 = face_flux(U, P, L, A.a, 0, i, j, k, l), gx0 = face_flux(U, P, L, A.a, 0, i - 1, j, k, l);
+    const double gy1 = face_flux(U, P, L, A.a, 1, i, j, k, l), gy0 = face_flux(U, P, L, A.a, 1, i, j - 1, k, l);
+    const double gk1 = face_flux(U, P, L, A.a, 2, i, j, k, l), gk0 = face_flux(U, P, L, A.a, 2, i, j, k - 1, l);
+    const double gl1 = face_flux(U, P, L, A.a, 3, i, j, k, l), gl0 = face_flux(U, P, L, A.a, 3, i, j, k, l - 1);
+    const double kk = -(gx1 - gx0) * L.hi[0] - (gy1 - gy0) * L.hi[1] - (gk1 - gk0) * L.hi[2] - (gl1 - gl0) * L.hi[3];
+    if (KIND != kRhs && A.ff_acc && A.c_flux != 0.0 && P.lev == 1) {
+        const int n0 = P.sz[0], n1 = P.sz[1], n2 = P.sz[2], n3 = P.sz[3];
+        const long long S0 = (long long)n1 * n2 * n3, S1 = (long long)n0 * n2 * n3, S2 = (long long)n0 * n1 * n3;
+        double* ff = A.ff_acc + P.foff;
+        if (i == 0) flux_store(ff + ((long long)j * n2 + k) * n3 + l, gx0, A);
+        if (i == n0 - 1) flux_store(ff + S0 + ((long long)j * n2 + k) * n3 + l, gx1, A);
+        ff += 2 * S0;
+        if (j == 0) flux_store(ff + ((long long)i * n2 + k) * n3 + l, gy0, A);
+        if (j == n1 - 1) flux_store(ff + S1 + ((long long)i * n2 + k) * n3 + l, gy1, A);
+        ff += 2 * S1;
+        if (k == 0) flux_store(ff + ((long long)i * n1 + j) * n3 + l, gk0, A);
+        if (k == n2 - 1) flux_store(ff + S2 + ((long long)i * n1 + j) * n3 + l, gk1, A);
+        ff += 2 * S2;
+        if (l == 0) flux_store(ff + ((long long)i * n1 + j) * n2 + k, gl0, A);
+        if (l == n3 - 1) flux_store(ff + (long long)n0 * n1 * n2 + ((long long)i * n1 + j) * n2 + k, gl1, A);
+    }
+    const long long o = P.off + c;
+    if (KIND == kRhs) {
+        A.fout[o] = kk;
+    } else if (KIND == kStage1) {
+        const double f0 = U(i, j, k, l);
+        A.acc[o] = f0 + A.c_acc * kk;
+        A.fout[o] = f0 + A.c_next * kk;
+    } else if (KIND == kStage23) {
+        A.acc[o] = A.acc[o] + A.c_acc * kk;
+        A.fout[o] = A.fn[o] + A.c_next * kk;
+    } else {
+        A.fout[o] = A.acc[o] + A.c_acc * kk;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_a4_faces(A4Args A, const A4Face* __restrict__ faces, int nfaces,
+                                                 double* __restrict__ cf)
+{
+    const int q = (int)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nfaces) return;
+    const A4Face F = faces[q];
+    const A4Patch P = A.patches[0];
+    const double G = face_flux(view_of(A.pad, P), P, A.lv[0], A.a, F.dir, F.cell[0], F.cell[1], F.cell[2], F.cell[3]);
+    if (A.first) cf[q] = A.c_flux * G;
+    else cf[q] += A.c_flux * G;
+}
+
+// M[((i ncy + j) * 25 + (a+2) * 5 + (b+2)] = sum over the velocity plane of
+// level-0 column (i + a, j + b), masked by the coverage of column (i, j);
+// one wave per sum
+__global__ __launch_bounds__(256) void k_a4_masked(const double* __restrict__ f0,
+                                                  const unsigned char* __restrict__ mask, int ncx, int ncy,
+                                                  int plane, double* __restrict__ M)
+{
+    const int task = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (task >= 25 * ncx * ncy) return;
+    const int cell = task / 25, s = task - cell * 25;
+    const int i = cell / ncy, j = cell - (cell / ncy) * ncy;
+    const int a = s / 5 - 2, b = s % 5 - 2;
+    const double* src = f0 + ((long long)wrap4(i + a, ncx) * ncy + wrap4(j + b, ncy)) * plane;
+    const unsigned char* m = mask + (long long)cell * plane;
+    double acc = 0.0;
+    for (int q = lane; q < plane; q += 64) acc += m[q] ? 0.0 : src[q];
+    acc = wave_sum(acc);
+    if (lane == 0) M[task] = acc;
+}
+
+// the coarse acceleration: the mean of the R x R fine values of each component
+__global__ __launch_bounds__(256) void k_a4_inject(double* __restrict__ a, int ncx, int ncy, int R)
+{
+    const int q = (int)blockIdx.x * 256 + threadIdx.x;
+    const int nc = ncx * ncy;
+    if (q >= 2 * nc) return;
+    const int comp = q / nc, cell = q - comp * nc;
+    const int i = cell / ncy, j = cell - (cell / ncy) * ncy;
+    const int nfy = ncy * R;
+    const double* af = a + 2 * nc + (long long)comp * nc * R * R;
+    double s = 0.0;
+    for (int u = 0; u < R; ++u)
+        for (int w = 0; w < R; ++w) s += af[(long long)(i * R + u) * nfy + (j * R + w)];
+    a[q] = s / (R * R);
+}
+
+__global__ __launch_bounds__(256) void k_a4_reflux(double* __restrict__ f, const long long* __restrict__ cell,
+                                                  const int* __restrict__ ptr, const int* __restrict__ code,
+                                                  const int* __restrict__ fine, int nfine,
+                                                  const double* __restrict__ ff, const double* __restrict__ cf,
+                                                  const A4Face* __restrict__ faces, double h0, double h1, double h2,
+                                                  double h3, int ncorr)
+{
+    const int q = (int)blockIdx.x * 256 + threadIdx.x;
+    if (q >= ncorr) return;
+    double val = f[cell[q]];
+    for (int e = ptr[q]; e < ptr[q + 1]; ++e) {
+        const int cd = code[e];
+        const bool lower = cd < 0;                   // the face is the cell's lower face
+        const int fi = lower ? -cd - 1 : cd;
+        double s = 0.0;
+        for (int u = 0; u < nfine; ++u) s += ff[fine[(long long)fi * nfine + u]];
+        const double diff = s / nfine - cf[fi];
+        const int d = faces[fi].dir;
+        const double h = d == 0 ? h0 : (d == 1 ? h1 : (d == 2 ? h2 : h3));
+        val += lower ? h * diff : -h * diff;
+    }
+    f[cell[q]] = val;
+}
+
+__global__ __launch_bounds__(256) void k_a4_average(double* __restrict__ f, const long long* __restrict__ dst,
+                                                   const long long* __restrict__ src, const int* __restrict__ strides,
+                                                   int R, int n)
+{
+    const int q = (int)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const long long s0 = strides[3 * q], s1 = strides[3 * q + 1], s2 = strides[3 * q + 2];
+    const double* b = f + src[q];
+    double s = 0.0;
+    for (int u0 = 0; u0 < R; ++u0)
+        for (int u1 = 0; u1 < R; ++u1)
+            for (int u2 = 0; u2 < R; ++u2)
+                for (int u3 = 0; u3 < R; ++u3) s += b[u0 * s0 + u1 * s1 + u2 * s2 + u3];
+    f[dst[q]] = s / ((double)R * R * R * R);
+}
+
+}  // namespace
+
+hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
+                         const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
+                         const double* gyc, const double* gxf, const double* gyf, double* pad, hipStream_t stream)
+{
+    if (total <= 0) return hipSuccess;
+    A4PadArgs A{};
+    A.f = f;
+    A.patches = patches;
+    A.list = list;
+    A.npatch = npatch;
+    A.nb = nb;
+    A.lv[0] = lv_host[0];
+    A.lv[1] = lv_host[1];
+    A.B = B;
+    A.R = R;
+    A.gxc = gxc;
+    A.gyc = gyc;
+    A.gxf = gxf;
+    A.gyf = gyf;
+    A.pad = pad;
+    hipLaunchKernelGGL(k_a4_pad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, A, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    const dim3 g(a.ntiles), b(256);
+    switch (kind) {
+    case kRhs: hipLaunchKernelGGL(k_a4_stage<kRhs>, g, b, 0, stream, a); break;
+    case kStage1: hipLaunchKernelGGL(k_a4_stage<kStage1>, g, b, 0, stream, a); break;
+    case kStage23: hipLaunchKernelGGL(k_a4_stage<kStage23>, g, b, 0, stream, a); break;
+    default: hipLaunchKernelGGL(k_a4_stage<kStage4>, g, b, 0, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, double* cf_acc, hipStream_t stream)
+{
+    if (nfaces <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_a4_faces, dim3((nfaces + 255) / 256), dim3(256), 0, stream, a, faces, nfaces, cf_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_a4_masked(const double* f0, const unsigned char* mask, const int* n, double* M, hipStream_t stream)
+{
+    const int tasks = 25 * n[0] * n[1];
+    hipLaunchKernelGGL(k_a4_masked, dim3((tasks + 3) / 4), dim3(256), 0, stream, f0, mask, n[0], n[1], n[2] * n[3], M);
+    return hipGetLastError();
+}
+
+hipError_t launch_a4_inject(double* a, int ncx, int ncy, int R, hipStream_t stream)
+{
+    const int n = 2 * ncx * ncy;
+    hipLaunchKernelGGL(k_a4_inject, dim3((n + 255) / 256), dim3(256), 0, stream, a, ncx, ncy, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_a4_reflux(double* f, const long long* cell, const int* ptr, const int* code, const int* fine,
+                            int nfine, const double* ff, const double* cf, const A4Face* faces, const double* hdt,
+                            double dt, int ncorr, hipStream_t stream)
+{
+    if (ncorr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_a4_reflux, dim3((ncorr + 255) / 256), dim3(256), 0, stream, f, cell, ptr, code, fine, nfine,
+                       ff, cf, faces, dt * hdt[0], dt * hdt[1], dt * hdt[2], dt * hdt[3], ncorr);
+    return hipGetLastError();
+}
+
+hipError_t launch_a4_average(double* f, const long long* dst, const long long* src, const int* strides, int R, int n,
+                             hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_a4_average, dim3((n + 255) / 256), dim3(256), 0, stream, f, dst, src, strides, R, n);
+    return hipGetLastError();
+}
+
+}  // namespace vp

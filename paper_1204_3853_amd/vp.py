@@ -339,6 +339,17 @@ def hierarchy_spec(ncx, ncv, x_len, v_lo, v_hi, qm, ratios, veqs, x_lo=0.0):
             "veq": [[list(v)] for v in veqs]}
 
 
+def amr4d_spec(ncells, x_len, y_len, v_lo, v_hi, qm, ratio, veqs):
+    """Problem of a two-level 2D+2V hierarchy: level 0 of ncells = (nx, ny,
+    nvx, nvy) cells, one ratio in every direction, the same velocity
+    interval along vx and vy; veqs = (gx, gy) of level 0 and of level 1, each
+    with two ghost cells per side."""
+    gxc, gyc, gxf, gyf = veqs
+    return {"ndim": 2, "n_levels": 2, "cells": list(ncells), "ratio": [ratio] * 4, "x_lo": [0.0, 0.0],
+            "x_len": [x_len, y_len], "v_lo": [v_lo, v_lo], "v_hi": [v_hi, v_hi], "qm": qm,
+            "veq": [[list(gxc), list(gyc)], [list(gxf), list(gyf)]]}
+
+
 def _problem_dict(p):
     """Problem spec from a vp_inputs.Problem1D / Problem2D."""
     if hasattr(p, "nvx"):

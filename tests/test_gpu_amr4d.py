@@ -1,0 +1,210 @@
+"""GPU parity of the two-level 2D+2V path (the AMR of section 3 carried to
+the 2D+2V phase space) with the oracle (oracle/vp_oracle_amr4d.c): the
+right-hand side with ghost cells from neighbouring patches, the periodic
+wrap, the fine equilibrium and the tensor sub-cell interpolation of level
+0; the Mask reduction onto the fine configuration mesh; the field on both
+levels; RK4 steps with the reflux of every coarse-fine face and the average
+down; plan errors.
+
+Tolerances (FP64): 1e-12 of max|.| for the right-hand side, the moment and
+the field, 1e-12 of max|f| per step (rounding order differs: the RK4
+stages are combined as a running sum on the device, the oracle divides the
+accumulated fluxes).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import vp_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+X_LEN = Y_LEN = 4 * math.pi
+V_LO, V_HI = -6.0, 6.0
+
+
+def box(lo, hi):
+    return {"level": 1, "lo": list(lo), "hi": list(hi)}
+
+
+@pytest.fixture(scope="module")
+def vp():
+    from paper_1204_3853_amd import vp as V
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    V.lib()
+    return V
+
+
+def setup(vp, oracle, n, R, boxes, seed=0, v=(V_LO, V_HI), noise=0.02):
+    print(f"case n={n} R={R} boxes={len(boxes)} seed={seed}", flush=True)
+    f, gxc, gyc, gxf, gyf = I.amr4d_state(n, R, boxes, eps=0.05, v_lo=v[0], v_hi=v[1])
+    f = f * (1 + noise * np.random.default_rng(seed).random(f.size))
+    gs = (gxc, gyc, gxf, gyf)
+    o = oracle.OracleAMR4D(n, X_LEN, Y_LEN, v[0], v[1], -1.0, R, boxes, *gs)
+    spec = vp.amr4d_spec(n, X_LEN, Y_LEN, v[0], v[1], -1.0, R, gs)
+    plan = vp.Plan(spec, boxes=boxes)
+    assert plan.state_elems == o.size
+    return o, plan, f
+
+
+def close(got, want, tol):
+    got = got.cpu().numpy() if hasattr(got, "cpu") else np.asarray(got)
+    scale = np.abs(want).max()
+    err = np.abs(got - want).max()
+    assert err <= tol * scale, f"max error {err:.3e} vs scale {scale:.3e}"
+
+
+# patch layouts on level 0 of (4, 4, 6, 6), R = 2: one patch; two touching
+# along y; a patch against the periodic x boundary touching one across it
+SMALL = {
+    "one": [box((2, 2, 4, 4), (5, 5, 9, 7))],
+    "touch_y": [box((2, 2, 4, 4), (5, 3, 9, 7)), box((2, 4, 4, 4), (5, 5, 9, 7))],
+    "periodic": [box((0, 2, 4, 2), (1, 5, 7, 7)), box((6, 2, 4, 4), (7, 7, 9, 9)), box((2, 0, 2, 4), (5, 1, 5, 9))],
+}
+
+
+@pytest.mark.parametrize("layout", sorted(SMALL))
+def test_rhs(vp, oracle, layout):
+    n, R = (4, 4, 6, 6), 2
+    o, plan, f = setup(vp, oracle, n, R, SMALL[layout], seed=1)
+    a = np.random.default_rng(2).normal(0.0, 0.1, plan.field_elems)
+    want = o.rhs(f, a)
+    k = vp.rhs(plan, torch.tensor(f, device="cuda"), torch.tensor(a, device="cuda"))
+    close(k, want, 1e-12)
+
+
+@pytest.mark.parametrize("layout", sorted(SMALL))
+def test_moment_and_field(vp, oracle, layout):
+    n, R = (4, 4, 6, 6), 2
+    o, plan, f = setup(vp, oracle, n, R, SMALL[layout], seed=3)
+    ft = torch.tensor(f, device="cuda")
+    nm = vp.reduce_moment(plan, ft)
+    close(nm, o.reduce_mask(f), 1e-13)
+    a_want, E_want = o.constraints(f)
+    _, E = vp.poisson_periodic(plan, nm)
+    close(E, E_want, 1e-12)
+    a = vp.inject_field(plan, E)
+    close(a, a_want, 1e-12)
+    close(vp.field_of(plan, ft), a_want, 1e-12)
+
+
+@pytest.mark.parametrize("layout", sorted(SMALL))
+def test_steps(vp, oracle, layout):
+    n, R = (4, 4, 6, 6), 2
+    o, plan, f = setup(vp, oracle, n, R, SMALL[layout], seed=4)
+    ft = torch.tensor(f, device="cuda")
+    a = vp.field_of(plan, ft)
+    dt = 0.03
+    for s in range(3):
+        f = o.step(f, dt)
+        vp.rk4_step(plan, ft, a, dt)
+        torch.cuda.synchronize()
+        close(ft, f, 1e-12)
+    a_want, _ = o.constraints(f)
+    close(a, a_want, 1e-12)
+
+
+def test_ratio_four(vp, oracle):
+    n, R = (4, 4, 8, 8), 4
+    boxes = [box((4, 4, 8, 12), (11, 7, 23, 19)), box((4, 8, 8, 12), (11, 11, 15, 19))]
+    o, plan, f = setup(vp, oracle, n, R, boxes, seed=5)
+    ft = torch.tensor(f, device="cuda")
+    a = vp.field_of(plan, ft)
+    close(a, o.constraints(f)[0], 1e-12)
+    dt = 0.02
+    for _ in range(2):
+        f = o.step(f, dt)
+        vp.rk4_step(plan, ft, a, dt)
+    torch.cuda.synchronize()
+    close(ft, f, 1e-12)
+
+
+def test_seeded_layout_32(vp, oracle):
+    """Level 0 of 32^4 cells, R = 2 (the fine configuration mesh is 64 x
+    64), six seeded patches in the central half of the velocity box: one
+    step equals the oracle's."""
+    n, R = (32, 32, 32, 32), 2
+    boxes = I.amr4d_boxes(0, n, R)
+    o, plan, f = setup(vp, oracle, n, R, boxes, seed=6)
+    ft = torch.tensor(f, device="cuda")
+    a = vp.field_of(plan, ft)
+    close(a, o.constraints(f)[0], 1e-12)
+    dt = 0.02
+    want = o.step(f, dt)
+    vp.rk4_step(plan, ft, a, dt)
+    torch.cuda.synchronize()
+    close(ft, want, 1e-12)
+
+
+def composite_mass(o, f, vspan):
+    n, R = o.n, o.R
+    vol_c = X_LEN / n[0] * Y_LEN / n[1] * vspan / n[2] * vspan / n[3]
+    cov = np.zeros(n, bool)
+    m = 0.0
+    for p, b in enumerate(o.boxes):
+        cov[tuple(slice(b["lo"][d] // R, (b["hi"][d] + 1) // R) for d in range(4))] = True
+        m += o.patch(f, p).sum() * vol_c / R ** 4
+    return m + o.patch(f, -1)[~cov].sum() * vol_c
+
+
+def test_composite_mass_conserved(vp, oracle):
+    """Velocity box [-14, 14]^2 on 12 cells: over two steps no mass reaches
+    the velocity boundary, so the composite mass stays to rounding; later
+    the tails the field builds reach it (the oracle loses 4e-13 of the mass
+    in five steps), and the GPU's mass follows the oracle's."""
+    n, R = (4, 4, 12, 12), 2
+    boxes = [box((2, 2, 8, 8), (5, 3, 15, 13)), box((2, 4, 8, 8), (5, 5, 15, 13))]
+    o, plan, f = setup(vp, oracle, n, R, boxes, seed=8, v=(-14.0, 14.0))
+    ft = torch.tensor(f, device="cuda")
+    a = vp.field_of(plan, ft)
+    m0 = composite_mass(o, f, 28.0)
+    for _ in range(2):
+        vp.rk4_step(plan, ft, a, 0.02)
+    g = ft.cpu().numpy()
+    assert abs(composite_mass(o, g, 28.0) - m0) <= 1e-13 * m0
+    assert np.abs(g - f).max() > 1e-4
+    want = f
+    for _ in range(5):
+        want = o.step(want, 0.02)
+    for _ in range(3):
+        vp.rk4_step(plan, ft, a, 0.02)
+    g = ft.cpu().numpy()
+    assert abs(composite_mass(o, g, 28.0) - composite_mass(o, want, 28.0)) <= 1e-14 * m0
+
+
+def test_plan_errors(vp):
+    n, R = (4, 4, 6, 6), 2
+    _, gxc, gyc, gxf, gyf = I.amr4d_state(n, R, [])
+    spec = vp.amr4d_spec(n, X_LEN, Y_LEN, V_LO, V_HI, -1.0, R, (gxc, gyc, gxf, gyf))
+    good = box((2, 2, 4, 4), (5, 5, 9, 7))
+    vp.Plan(spec, boxes=[good])
+    with pytest.raises(vp.VPError, match="aligned"):
+        vp.Plan(spec, boxes=[box((1, 2, 4, 4), (4, 5, 9, 7))])
+    with pytest.raises(vp.VPError, match="overlap"):
+        vp.Plan(spec, boxes=[good, box((4, 4, 6, 6), (7, 7, 9, 9))])
+    with pytest.raises(vp.VPError, match="outside"):
+        vp.Plan(spec, boxes=[box((6, 2, 4, 4), (9, 5, 9, 7))])
+    with pytest.raises(vp.VPError, match="level 1"):
+        vp.Plan(spec, boxes=[dict(good, level=2)])
+    with pytest.raises(vp.VPError, match="FP64"):
+        vp.Plan(spec, dtype=torch.float32, boxes=[good])
+    bad = dict(spec, ratio=[2, 2, 4, 4])
+    with pytest.raises(vp.VPError, match="ratio"):
+        vp.Plan(bad, boxes=[good])
+    bad = dict(spec, v_hi=[V_HI, V_HI + 1.0])
+    with pytest.raises(vp.VPError, match="velocity interval"):
+        vp.Plan(bad, boxes=[good])
+    _, gxc, gyc, gxf, gyf = I.amr4d_state((40, 4, 6, 6), R, [])
+    big = vp.amr4d_spec((40, 4, 6, 6), X_LEN, Y_LEN, V_LO, V_HI, -1.0, R, (gxc, gyc, gxf, gyf))
+    with pytest.raises(vp.VPError, match="64 x 64"):
+        vp.Plan(big)
+    p = vp.Plan(spec, boxes=[good])
+    with pytest.raises(vp.VPError):
+        p.set_face_scheme(vp.FACE_LIMITED)
+    with pytest.raises(vp.VPError):
+        p.set_reduction(vp.REDUCE_SUBPATCH)
+    p.set_reduction(vp.REDUCE_MASK)

@@ -208,6 +208,44 @@ def amr4d_state(ncells, R, boxes, eps=0.05, k=0.5, x_len=4.0 * math.pi, y_len=4.
     return np.concatenate(parts), c.veq_x, c.veq_y, fpb.veq_x, fpb.veq_y
 
 
+def amr4d_boxes(seed: int = 0, ncells=(32, 32, 32, 32), ratio: int = 2, npatch: int = 6, sides=(4, 8, 12),
+                v_band=(0.25, 0.75), touch: bool = True):
+    """Seeded level-1 patches of a two-level 2D+2V hierarchy (4-entry lo/hi in
+    level-1 indices): sides drawn from `sides` coarse cells per direction,
+    corners on coarse cells (so aligned to the ratio), x and y anywhere (no
+    wrap inside a patch), velocity corners inside the central fraction
+    v_band of each velocity range; disjoint, touching allowed.  With touch,
+    the second patch is placed against the first along x when it fits."""
+    rng = np.random.default_rng(seed)
+    boxes = []
+    tries = 0
+    while len(boxes) < npatch and tries < 10000:
+        tries += 1
+        lo, hi = [], []
+        for d in range(4):
+            w = int(rng.choice(sides))
+            if d < 2:
+                if w > ncells[d]:
+                    w = ncells[d]
+                c0 = int(rng.integers(0, ncells[d] - w + 1))
+            else:
+                a = int(math.ceil(v_band[0] * ncells[d]))
+                bnd = int(math.floor(v_band[1] * ncells[d]))
+                w = min(w, bnd - a)
+                c0 = int(rng.integers(a, bnd - w + 1))
+            if touch and len(boxes) == 1 and d == 0:
+                prev = boxes[0]
+                c1 = (prev["hi"][0] + 1) // ratio
+                if c1 + w <= ncells[0]:
+                    c0 = c1
+            lo.append(c0 * ratio)
+            hi.append((c0 + w) * ratio - 1)
+        clash = any(all(max(lo[d], b["lo"][d]) <= min(hi[d], b["hi"][d]) for d in range(4)) for b in boxes)
+        if not clash:
+            boxes.append({"level": 1, "lo": lo, "hi": hi})
+    return boxes
+
+
 # ---------------------------------------------------------------- AMR layout
 
 
