@@ -176,16 +176,16 @@ void vpo_poisson_free(vpo_poisson* P)
     free(P);
 }
 
-/* phi solves A phi = 12 dx^2 (rho - mean rho) with sum(phi) = 0. */
-void vpo_poisson_solve(const vpo_poisson* P, double dx, const double* rho, double* phi)
+/* One solve of the bordered system with the stored factors: right-hand
+ * side b (N values) and constraint value c; returns phi and lam. */
+static void bordered_solve(const vpo_poisson* P, const double* b, double c, double* phi, double* lam)
 {
     int N = P->N;
-    if (N < 2) { if (N == 1) phi[0] = 0.0; return; }
     int nb = P->nb;
     double* y = (double*)malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
-    for (int i = 0; i < nb; ++i) y[i] = 12.0 * dx * dx * rho[i];
+    for (int i = 0; i < nb; ++i) y[i] = b[i];
     if (nb > 0) band_solve(P, y);
-    double q[3] = {12.0 * dx * dx * rho[N - 2], 12.0 * dx * dx * rho[N - 1], 0.0};
+    double q[3] = {b[N - 2], b[N - 1], c};
     for (int r = 0; r < 3; ++r) {
         double s = 0.0;
         for (int i = 0; i < nb; ++i) {
@@ -204,14 +204,47 @@ void vpo_poisson_solve(const vpo_poisson* P, double dx, const double* rho, doubl
         for (int i = k + 1; i < 3; ++i) q[i] -= P->S[i][k] * q[k];
     for (int k = 2; k >= 0; --k) {
         double s = q[k];
-        for (int c = k + 1; c < 3; ++c) s -= P->S[k][c] * q[c];
+        for (int cc = k + 1; cc < 3; ++cc) s -= P->S[k][cc] * q[cc];
         q[k] = s / P->S[k][k];
     }
     for (int i = 0; i < nb; ++i)
         phi[i] = y[i] - (P->Z[i * 3 + 0] * q[0] + P->Z[i * 3 + 1] * q[1] + P->Z[i * 3 + 2] * q[2]);
     phi[N - 2] = q[0];
     phi[N - 1] = q[1];
+    *lam = q[2];
     free(y);
+}
+
+/* phi solves A phi = 12 dx^2 (rho - mean rho) with sum(phi) = 0.
+ * The system is the exact definition of phi; its condition number grows
+ * like N^2, so the rounding of one LU solve grows with the mesh.  Two
+ * steps of iterative refinement (residual of the bordered system in
+ * extended precision, correction from the same factors) bring phi to
+ * rounding of the exact solution. */
+void vpo_poisson_solve(const vpo_poisson* P, double dx, const double* rho, double* phi)
+{
+    int N = P->N;
+    if (N < 2) { if (N == 1) phi[0] = 0.0; return; }
+    double* b = (double*)malloc(sizeof(double) * (size_t)N);
+    double* r = (double*)malloc(sizeof(double) * (size_t)N);
+    double* dphi = (double*)malloc(sizeof(double) * (size_t)N);
+    for (int i = 0; i < N; ++i) b[i] = 12.0 * dx * dx * rho[i];
+    double lam = 0.0, dlam = 0.0;
+    bordered_solve(P, b, 0.0, phi, &lam);
+    static const long double c[5] = {1.0L, -16.0L, 30.0L, -16.0L, 1.0L};   /* offsets -2..2 */
+    for (int it = 0; it < 2; ++it) {
+        long double sphi = 0.0L;
+        for (int i = 0; i < N; ++i) {
+            long double ap = 0.0L;
+            for (int o = -2; o <= 2; ++o) ap += c[o + 2] * (long double)phi[wrap(i + o, N)];
+            r[i] = (double)((long double)b[i] - ap - (long double)lam);
+            sphi += (long double)phi[i];
+        }
+        bordered_solve(P, r, (double)(-sphi), dphi, &dlam);
+        for (int i = 0; i < N; ++i) phi[i] += dphi[i];
+        lam += dlam;
+    }
+    free(b); free(r); free(dphi);
 }
 
 /* E_i = -[8 (phi_{i+1} - phi_{i-1}) - (phi_{i+2} - phi_{i-2})] / (12 dx) */

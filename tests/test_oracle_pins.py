@@ -42,6 +42,28 @@ def test_poisson_dft_symbol(oracle, nx):
             np.testing.assert_allclose(phi, 12.0 * dx * dx * rho / lam, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("nx", [1024, 8192])
+def test_poisson_large_mesh_near_rounding(oracle, nx):
+    """On large meshes the solve stays at rounding of the exact periodic
+    solution: a random rho is expanded in the Fourier basis, where the
+    operator is diagonal with lambda = 4 sin^2(theta/2) (14 - 2 cos theta)
+    (the factored form of the symbol above, free of cancellation at small
+    theta), and phi compared to 1e-12 of max|phi|.  An LU solve without
+    refinement misses this by orders of magnitude (its rounding grows
+    with the N^2 condition number)."""
+    rng = np.random.default_rng(nx)
+    rho = rng.normal(size=nx) + 0.7
+    dx = 4.0 * math.pi / nx
+    th = 2.0 * math.pi * np.arange(nx) / nx
+    lam = 4.0 * np.sin(th / 2) ** 2 * (14.0 - 2.0 * np.cos(th))
+    rh = np.fft.fft(rho)
+    ph = np.zeros_like(rh)
+    ph[1:] = 12.0 * dx * dx * rh[1:] / lam[1:]
+    want = np.real(np.fft.ifft(ph))
+    phi = oracle.poisson_solve(rho, dx)
+    assert np.abs(phi - want).max() <= 1e-12 * np.abs(want).max()
+
+
 def test_poisson_zero_mean_and_constant(oracle):
     rng = np.random.default_rng(5)
     rho = rng.normal(size=50)
