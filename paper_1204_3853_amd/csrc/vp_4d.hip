@@ -31,7 +31,9 @@ std::vector<double> fourier_basis(int n)
     return Q;
 }
 
-// eigenvalue of (30 - 16 (S + S^-1) + (S^2 + S^-2)) / (12 h^2) on basis column m
+// eigenvalue of (30 - 16 (S + S^-1) + (S^2 + S^-2)) / (12 h^2) on basis column m,
+// 30 - 32 cos t + 2 cos 2t in its factored form 4 sin^2(t/2) (14 - 2 cos t),
+// which keeps full relative accuracy at small t
 std::vector<double> fourier_symbol(int n, double h)
 {
     const double pi = 3.14159265358979323846;
@@ -39,7 +41,8 @@ std::vector<double> fourier_symbol(int n, double h)
     for (int m = 0; m < n; ++m) {
         const int k = (m + 1) / 2;
         const double th = 2.0 * pi * k / n;
-        lam[m] = (30.0 - 32.0 * std::cos(th) + 2.0 * std::cos(2.0 * th)) / (12.0 * h * h);
+        const double s = std::sin(0.5 * th);
+        lam[m] = 4.0 * s * s * (14.0 - 2.0 * std::cos(th)) / (12.0 * h * h);
     }
     return lam;
 }

@@ -490,7 +490,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->ws_slots_m = o; o += align256((size_t)(5 * ncx + (M->ntasks - M->fine_task0)) * sizeof(double));
     M->ws_n = o; o += align256((size_t)M->nfx * sizeof(double));
     M->ws_E = o; o += align256((size_t)M->nfx * sizeof(double));
-    M->ws_fld = o; o += align256(((size_t)M->nfx + 2 * ((size_t)M->nfx / kFieldChunk + 1) + 64) * sizeof(double));
+    M->ws_fld = o; o += align256(((size_t)M->nfx + 4 * ((size_t)M->nfx / kFieldChunk + 1) + 64) * sizeof(double));
     M->hist_stride = align256((size_t)ncx * ncv * sizeof(double)) / sizeof(double);
     M->ws_hist = o; o += 5 * M->hist_stride * sizeof(double);
     M->ws_nc = o; o += align256((size_t)ncx * sizeof(double));

@@ -588,7 +588,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     H.ws_slots = o; o += a256(std::max<size_t>(H.ntasks, 1) * sizeof(double));
     H.ws_n = o; o += a256((size_t)nfx * sizeof(double));
     H.ws_E = o; o += a256((size_t)nfx * sizeof(double));
-    H.ws_fld = o; o += a256(((size_t)nfx + 2 * ((size_t)nfx / kFieldChunk + 1) + 64) * sizeof(double));
+    H.ws_fld = o; o += a256(((size_t)nfx + 4 * ((size_t)nfx / kFieldChunk + 1) + 64) * sizeof(double));
     p->ws_total = o;
     p->state_elems = H.total;
     return VP_OK;

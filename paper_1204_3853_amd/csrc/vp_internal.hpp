@@ -373,7 +373,7 @@ struct FieldOutputs {
     int inject_R;
 };
 // moment from strip partials, Poisson, field and a = (q/m) E over many blocks
-// (nx >= kFieldSplitMin); work holds nx + 2 ceil(nx / kFieldChunk) doubles
+// (nx >= kFieldSplitMin); work holds nx + 4 ceil(nx / kFieldChunk) doubles
 hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv, double dx, double qm,
                               const double* green, double* work, double* a, hipStream_t stream);
 // the same from the charge density of several species (rho = background +

@@ -107,17 +107,79 @@ __device__ double block_exclusive_scan(double v, double* red)
 
 // ---------------------------------------------------------------- split field solve
 //
+// Double-double arithmetic (an unevaluated sum hi + lo, the error-free
+// transformations of Knuth's two-sum and of an fma product) for the sums
+// that reach across the whole mesh: the prefix of y up to a chunk is a
+// difference of two sums of size |mean y| times the chunk offset, so in
+// plain FP64 its rounding grows with the mesh size.
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD dd_two_sum(double a, double b)
+{
+    const double s = a + b;
+    const double bb = s - a;
+    return DD{s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b)
+{
+    const DD s = dd_two_sum(a.hi, b.hi);
+    const double lo = s.lo + (a.lo + b.lo);
+    const double hi = s.hi + lo;
+    return DD{hi, lo - (hi - s.hi)};
+}
+
+__device__ __forceinline__ DD dd_neg(DD a) { return DD{-a.hi, -a.lo}; }
+
+// a times a double
+__device__ __forceinline__ DD dd_mul(DD a, double b)
+{
+    const double p = a.hi * b;
+    const double e = fma(a.hi, b, -p) + a.lo * b;
+    const double hi = p + e;
+    return DD{hi, e - (hi - p)};
+}
+
+// a divided by a double
+__device__ __forceinline__ DD dd_div(DD a, double b)
+{
+    const double q = a.hi / b;
+    const double r = (fma(-q, b, a.hi) + a.lo) / b;
+    const double hi = q + r;
+    return DD{hi, r - (hi - q)};
+}
+
+// the product of two doubles, exactly
+__device__ __forceinline__ DD dd_prod(double a, double b)
+{
+    const double p = a * b;
+    return DD{p, fma(a, b, -p)};
+}
+
+__device__ __forceinline__ DD dd_wave_sum(DD v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const DD u{__shfl_xor(v.hi, o, 64), __shfl_xor(v.lo, o, 64)};
+        v = dd_add(v, u);
+    }
+    return v;
+}
+//
 // The same solve as k_poisson1d, spread over chunks of kFieldChunk
 // configuration cells so that many CUs share it (for meshes of at least
 // kFieldSplitMin cells):
 //   k_field_chunks: per chunk, the moment from the stage kernel's strip
 //     partials (with a 16-cell periodic halo), r = 12 dx^2 (1 - n), the
 //     tridiagonal-factor inverse y = g * r over the chunk, and the chunk's
-//     sums of y and of y_m (N - m);
+//     sums of y and of y_m (N - m) in double-double;
 //   k_field_finish: per chunk, the global mean of y and of D from the
-//     chunk sums, the chunk's prefix offset, an in-chunk scan for
-//     d = D - mean(D) (D_i = sum_{m <= i} (y_m - mean y)), and the field
-//     E_i = -(7 (d_i + d_{i-1}) - d_{i+1} - d_{i-2}) / (12 dx), a = (q/m) E.
+//     chunk sums, the chunk's prefix offset (all in double-double), an
+//     in-chunk scan for d = D - mean(D) (D_i = sum_{m <= i} (y_m - mean y)),
+//     and the field E_i = -(7 (d_i + d_{i-1}) - d_{i+1} - d_{i-2}) / (12 dx),
+//     a = (q/m) E.
 // All sums run in a fixed order.
 
 __global__ __launch_bounds__(kFieldChunk) void k_field_chunks(SpeciesMoments m, int nx, double dx,
@@ -127,7 +189,7 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_chunks(SpeciesMoments m, 
     constexpr int K = kGreenTaps;
     __shared__ double r[kFieldChunk + 2 * K];
     __shared__ double gs[K + 1];
-    __shared__ double red[2 * (kFieldChunk / 64)];
+    __shared__ double red[4 * (kFieldChunk / 64)];
     const int t = threadIdx.x;
     const int c0 = blockIdx.x * kFieldChunk;
     if (t <= K) gs[t] = green[t];
@@ -172,22 +234,33 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_chunks(SpeciesMoments m, 
     double yi = gs[0] * r[t + K];
 #pragma unroll
     for (int o = 1; o <= K; ++o) yi += gs[o] * (r[t + K + o] + r[t + K - o]);
-    double sy = 0.0, sw = 0.0;
+    DD sy{0.0, 0.0}, sw{0.0, 0.0};
     if (i < nx) {
         y[i] = yi;
-        sy = yi;
-        sw = yi * (double)(nx - i);
+        sy.hi = yi;
+        sw = dd_prod(yi, (double)(nx - i));
     }
-    sy = wave_sum(sy);
-    sw = wave_sum(sw);
+    sy = dd_wave_sum(sy);
+    sw = dd_wave_sum(sw);
     const int lane = t & 63, wave = t >> 6;
-    if (lane == 0) { red[wave] = sy; red[kFieldChunk / 64 + wave] = sw; }
+    constexpr int NW = kFieldChunk / 64;
+    if (lane == 0) {
+        red[wave] = sy.hi;
+        red[NW + wave] = sy.lo;
+        red[2 * NW + wave] = sw.hi;
+        red[3 * NW + wave] = sw.lo;
+    }
     __syncthreads();
     if (t == 0) {
-        double a = 0.0, b = 0.0;
-        for (int w = 0; w < kFieldChunk / 64; ++w) { a += red[w]; b += red[kFieldChunk / 64 + w]; }
-        csum[2 * blockIdx.x] = a;
-        csum[2 * blockIdx.x + 1] = b;
+        DD a{0.0, 0.0}, b{0.0, 0.0};
+        for (int w = 0; w < NW; ++w) {
+            a = dd_add(a, DD{red[w], red[NW + w]});
+            b = dd_add(b, DD{red[2 * NW + w], red[3 * NW + w]});
+        }
+        csum[4 * blockIdx.x] = a.hi;
+        csum[4 * blockIdx.x + 1] = a.lo;
+        csum[4 * blockIdx.x + 2] = b.hi;
+        csum[4 * blockIdx.x + 3] = b.lo;
     }
 }
 
@@ -197,7 +270,7 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
 {
     __shared__ double d[kFieldChunk + 4];     // d_i for i = c0 - 2 .. c0 + kFieldChunk + 1
     __shared__ double red[kFieldChunk / 64];
-    __shared__ double cs[2 * (kMaxPoisson1D / kFieldChunk)];
+    __shared__ double cs[4 * (kMaxPoisson1D / kFieldChunk)];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int c = blockIdx.x, c0 = c * kFieldChunk;
@@ -205,20 +278,24 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
     const double yt = y[wrapi(c0 + t, nx)];
     const double ye0 = y[wrapi(c0 + kFieldChunk, nx)], ye1 = y[wrapi(c0 + kFieldChunk + 1, nx)];
     const double ym1 = y[wrapi(c0 - 1, nx)];
-    if (t < 2 * nchunk) cs[t] = csum[t];
+    if (t < 4 * nchunk) cs[t] = csum[t];
     __syncthreads();
-    // global sums and the prefix of y - mean(y) up to the chunk start, in chunk order
-    double sy = 0.0, sw = 0.0, pre = 0.0;
+    // global sums and the prefix of y - mean(y) up to the chunk start, in
+    // chunk order, in double-double
+    DD sy{0.0, 0.0}, sw{0.0, 0.0}, pre{0.0, 0.0};
     for (int q = 0; q < nchunk; ++q) {
         if (q == c) pre = sy;
-        sy += cs[2 * q];
-        sw += cs[2 * q + 1];
+        sy = dd_add(sy, DD{cs[4 * q], cs[4 * q + 1]});
+        sw = dd_add(sw, DD{cs[4 * q + 2], cs[4 * q + 3]});
     }
-    const double ybar = sy / nx;
-    const double mean_D = (sw - ybar * 0.5 * (double)nx * (double)(nx + 1)) / nx;
-    const double off = pre - ybar * (double)c0 - mean_D;            // d_{c0 - 1}
+    const DD ybar_dd = dd_div(sy, (double)nx);
+    // sum_i i for i = 1 .. nx is an integer below 2^53
+    const DD mean_D = dd_div(dd_add(sw, dd_neg(dd_mul(ybar_dd, 0.5 * (double)nx * (double)(nx + 1)))), (double)nx);
+    const DD off_dd = dd_add(dd_add(pre, dd_neg(dd_mul(ybar_dd, (double)c0))), dd_neg(mean_D));   // d_{c0 - 1}
+    const double ybar = ybar_dd.hi, ybar_lo = ybar_dd.lo;
+    const double off = off_dd.hi + off_dd.lo;
     // inclusive scan of y - mean(y) over rows c0 .. c0 + kFieldChunk + 1 (periodic)
-    const double yv = yt - ybar;
+    const double yv = (yt - ybar) - ybar_lo;
     double x = yv;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -234,14 +311,14 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
         // rows past the chunk: d continues with y of rows c0 + 256, c0 + 257
         double tail = 0.0;
         for (int w = 0; w < kFieldChunk / 64; ++w) tail += red[w];
-        double e = off + tail + (ye0 - ybar);
-        if (t == 1) e += ye1 - ybar;
+        double e = off + tail + ((ye0 - ybar) - ybar_lo);
+        if (t == 1) e += (ye1 - ybar) - ybar_lo;
         d[kFieldChunk + 2 + t] = e;
     }
     if (t == 0) {
         // rows before the chunk: d_{c0 - 1} = off, d_{c0 - 2} = off - (y_{c0 - 1} - mean y)
         d[1] = off;
-        d[0] = off - (ym1 - ybar);
+        d[0] = off - ((ym1 - ybar) - ybar_lo);
     }
     __syncthreads();
     const int i = c0 + t;

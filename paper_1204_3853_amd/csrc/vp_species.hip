@@ -140,7 +140,7 @@ vp_status vp_species_group_create(const vp_plan* const* plans, const double* cha
     g->ws_n = o; o += (size_t)nspecies * row;
     g->ws_neff = o; o += row;
     g->ws_E = o; o += row;
-    g->ws_cfg = o; o += align256s(((size_t)g->nx + 2 * ((size_t)g->nx / kFieldChunk + 1) + 64) * sizeof(double));
+    g->ws_cfg = o; o += align256s(((size_t)g->nx + 4 * ((size_t)g->nx / kFieldChunk + 1) + 64) * sizeof(double));
     g->ws_total = o;
     *out = g;
     return VP_OK;

@@ -48,9 +48,7 @@ def run_case(vp, oracle, probs, charges, background, steps, dt, dtype=torch.floa
     sp = [species_of(p) for p in probs]
     start = [f.double().cpu().numpy().reshape(p.nx, p.nv) for f, p in zip(fs, probs)]
     want_a, _ = oracle.species_field(start, sp, charges, background, probs[0].dx)
-    # the split field solve (nx >= 1024) carries a prefix sum over nx cells
-    nx = probs[0].nx
-    tol_a = 1e-11 if nx < 1024 else max(1e-10, 5e-14 * nx)
+    tol_a = 1e-12
     for ag, aw in zip(a, want_a):
         assert np.abs(ag.cpu().numpy() - aw).max() <= tol_a * max(np.abs(aw).max(), 1e-300)
     want = start
@@ -63,7 +61,7 @@ def run_case(vp, oracle, probs, charges, background, steps, dt, dtype=torch.floa
         assert np.abs(got - w).max() <= tol * np.abs(w).max()
     # the accelerations after the step are the field of the new states
     want_a, _ = oracle.species_field(want, sp, charges, background, probs[0].dx)
-    tol_a = max(1e-9, 5e-13 * nx) if dtype == torch.float64 else 1e-4
+    tol_a = 1e-11 * steps if dtype == torch.float64 else 1e-4
     for ag, aw in zip(a, want_a):
         assert np.abs(ag.cpu().numpy() - aw).max() <= tol_a * np.abs(aw).max()
 
