@@ -82,11 +82,11 @@ typedef enum vp_dtype { VP_F64 = 0, VP_F32 = 1 } vp_dtype;
  *             equilibrium supplied on both ends); in 2D+2V the equilibrium
  *             is the product veq[l][0][j] * veq[l][1][k].  Copied at plan
  *             creation.
- * Single-level 2D+2V plans are FP64 with nx, ny <= 64, nvx <= 1024 and
- * nvy <= 64 (VP_ENOTSUP otherwise).  Two-level 2D+2V plans (the hierarchy
+ * Single-level 2D+2V plans are FP64 with nx, ny <= 256, nvx <= 1024 and
+ * fewer than 2^31 phase-space cells (VP_ENOTSUP otherwise).  Two-level 2D+2V plans (the hierarchy
  * of section 3 in the 2D+2V phase space) are FP64 with one ratio, 2 or 4,
  * in all four directions, the same velocity interval along vx and vy, and
- * a fine configuration mesh of at most 64 x 64 cells; their charge density
+ * a fine configuration mesh of at most 256 x 256 cells; their charge density
  * is the Mask reduction (Alg. mreduce) onto the fine configuration mesh,
  * where the Poisson equation is solved, and a holds [level-0 x][level-0
  * y][level-1 x][level-1 y] components, level 0 taking the mean of its

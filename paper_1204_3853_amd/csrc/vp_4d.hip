@@ -47,6 +47,16 @@ std::vector<double> fourier_symbol(int n, double h)
     return lam;
 }
 
+// Q followed by its transpose (the Poisson solve of larger meshes reads both)
+std::vector<double> fourier_basis_and_transpose(int n)
+{
+    std::vector<double> Q = fourier_basis(n);
+    Q.resize((size_t)2 * n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Q[(size_t)n * n + (size_t)j * n + i] = Q[(size_t)i * n + j];
+    return Q;
+}
+
 namespace {
 
 hipError_t upload(double** dst, const std::vector<double>& v)
@@ -99,9 +109,10 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     M->nvx = pb->cells[2];
     M->nvy = pb->cells[3];
     if (M->nx > kMaxPoisson2D || M->ny > kMaxPoisson2D)
-        return fail(VP_ENOTSUP, "2D+2V configuration mesh is limited to 64 x 64 cells");
-    if (M->nvy > kMaxVy4D) return fail(VP_ENOTSUP, "2D+2V is limited to 64 cells along vy");
+        return fail(VP_ENOTSUP, "2D+2V configuration mesh is limited to 256 x 256 cells");
     if (M->nvx > kMaxVx4D) return fail(VP_ENOTSUP, "2D+2V is limited to 1024 cells along vx");
+    if ((double)M->nx * M->ny * M->nvx * M->nvy >= 2147483648.0)
+        return fail(VP_ENOTSUP, "2D+2V is limited to 2^31 phase-space cells");
     M->dx = pb->x_len[0] / M->nx;
     M->dy = pb->x_len[1] / M->ny;
     M->dvx = (pb->v_hi[0] - pb->v_lo[0]) / M->nvx;
@@ -109,7 +120,7 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     M->v_lo = pb->v_lo[0];
     std::vector<double> gx(pb->veq[0][0], pb->veq[0][0] + M->nvx + 4);
     std::vector<double> gy(pb->veq[0][1], pb->veq[0][1] + M->nvy + 4);
-    const std::vector<double> Qx = fourier_basis(M->nx), Qy = fourier_basis(M->ny);
+    const std::vector<double> Qx = fourier_basis(M->nx), Qy = fourier_basis_and_transpose(M->ny);
     const std::vector<double> lx = fourier_symbol(M->nx, M->dx), ly = fourier_symbol(M->ny, M->dy);
     std::vector<double> inv((size_t)M->nx * M->ny);
     for (int l = 0; l < M->ny; ++l)
@@ -122,7 +133,7 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     VP_HIP(upload(&M->d_Qx, Qx));
     VP_HIP(upload(&M->d_Qy, Qy));
     VP_HIP(upload(&M->d_invlamT, inv));
-    VP_HIP(upload(&M->d_g, std::vector<double>((size_t)M->nx * M->ny, 0.0)));
+    VP_HIP(upload(&M->d_g, std::vector<double>((size_t)2 * M->nx * M->ny, 0.0)));
 
     p->state_elems = (size_t)M->nx * M->ny * M->nvx * M->nvy;
     const size_t sb = align256(p->state_elems * sizeof(double));
@@ -130,7 +141,8 @@ vp_status p4_create(vp_plan* p, const vp_problem* pb)
     p->ws_acc = o; o += sb;
     p->ws_fsa = o; o += sb;
     p->ws_fsb = o; o += sb;
-    M->ws_n = o; o += align256((size_t)M->nx * M->ny * sizeof(double));
+    const size_t nseg = M->nvy > kMaxVy4D ? (size_t)(M->nvy + kSegVy4D - 1) / kSegVy4D : 1;
+    M->ws_n = o; o += align256(nseg * M->nx * M->ny * sizeof(double));      // per vy segment
     M->ws_E = o; o += align256((size_t)2 * M->nx * M->ny * sizeof(double));   // Fourier coefficients in rk4
     p->ws_total = o;
     return VP_OK;

@@ -102,7 +102,7 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
         M.nf[d] = pb->cells[d] * R;
     }
     if (M.nf[0] > kMaxPoisson2D || M.nf[1] > kMaxPoisson2D)
-        return fail(VP_ENOTSUP, "two-level 2D+2V: the fine configuration mesh is limited to 64 x 64 cells");
+        return fail(VP_ENOTSUP, "two-level 2D+2V: the fine configuration mesh is limited to 256 x 256 cells");
     const double len[4] = {pb->x_len[0], pb->x_len[1], pb->v_hi[0] - pb->v_lo[0], pb->v_hi[1] - pb->v_lo[1]};
     for (int l = 0; l < 2; ++l) {
         A4Level& L = M.lv[l];
@@ -336,7 +336,7 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     M.navg = (int)avg_dst.size();
 
     // ---- Fourier tables of the fine configuration mesh
-    const std::vector<double> Qx = fourier_basis(nfx), Qy = fourier_basis(nfy);
+    const std::vector<double> Qx = fourier_basis(nfx), Qy = fourier_basis_and_transpose(nfy);
     const std::vector<double> lx = fourier_symbol(nfx, M.lv[1].h[0]), ly = fourier_symbol(nfy, M.lv[1].h[1]);
     std::vector<double> inv((size_t)nfx * nfy);
     for (int l = 0; l < nfy; ++l)
@@ -374,7 +374,7 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     T.add(&M.d_inv, inv);
     VP_HIP(T.commit(&M.d_tables));
     VP_HIP(hipMalloc(&M.d_rhs_pad, std::max<size_t>(M.pad_total, 1) * sizeof(double)));
-    VP_HIP(hipMalloc(&M.d_g, std::max<size_t>((size_t)nfx * nfy, 1) * sizeof(double)));
+    VP_HIP(hipMalloc(&M.d_g, (size_t)2 * nfx * nfy * sizeof(double)));
 
     // ---- workspace: acc, two predictors, padded copies, boundary and coarse-fine fluxes, slots, n, g
     const size_t sb = al256(M.total * sizeof(double));
@@ -387,7 +387,7 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     M.ws_cf = o; o += al256(std::max<size_t>(faces.size(), 1) * sizeof(double));
     M.ws_slots = o; o += al256((size_t)(m0 + M.ntasks) * sizeof(double));
     M.ws_n = o; o += al256((size_t)nfx * nfy * sizeof(double));
-    M.ws_g = o; o += al256((size_t)nfx * nfy * sizeof(double));
+    M.ws_g = o; o += al256((size_t)2 * nfx * nfy * sizeof(double));
     p->ws_total = o;
     p->state_elems = M.total;
     return VP_OK;

@@ -91,8 +91,10 @@ struct Adjoint1DArgs {
 
 // ----------------------------------------------------------------- 2D+2V
 
-constexpr int kMaxPoisson2D = 64;     // configuration cells per direction of the 2D+2V path
-constexpr int kMaxVy4D = 64;          // velocity cells along vy (one lane each)
+constexpr int kMaxPoisson2D = 256;    // configuration cells per direction of the 2D+2V path
+constexpr int kPoisson2DSmall = 64;   // up to this many per direction: the two-kernel Poisson solve
+constexpr int kMaxVy4D = 64;          // velocity cells along vy with one lane each; more: segments
+constexpr int kSegVy4D = 60;          // vy cells per segment (64 lanes with two ghost lanes per side)
 constexpr int kMaxVx4D = 1024;        // velocity cells along vx (equilibrium factors staged in LDS)
 
 // Arguments of the 2D+2V stage kernel (FP64).
@@ -390,7 +392,8 @@ hipError_t poisson1d_prepare();
 // tx x ty configuration cells per block (4x4, 2x4, 4x2, 2x2), one wave per cell
 hipError_t launch_stage4d(int tx, int ty, int kind, const Stage4DArgs& a, hipStream_t stream);
 hipError_t launch_moment4d(const double* f, int ncfg, size_t plane, double scale, double* n, hipStream_t stream);
-// g: nx * ny doubles of device scratch (the scaled Fourier coefficients)
+// g: 2 nx ny doubles of device scratch (the scaled Fourier coefficients, then
+// the potential); Qy: the basis, followed by its transpose; nx, ny <= 256
 hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
                             const double* Qy, const double* invlamT, double* g, double* phi, double* E, double* a,
                             hipStream_t stream);
@@ -709,6 +712,7 @@ vp_status a4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
 // real orthonormal Fourier basis and the symbol of the 1D fourth-order
 // Poisson operator on an n-cell periodic mesh (vp_4d.hip)
 std::vector<double> fourier_basis(int n);
+std::vector<double> fourier_basis_and_transpose(int n);
 std::vector<double> fourier_symbol(int n, double h);
 
 // b_j(s) of the conservative fifth-order sub-cell interpolation for ratio R

@@ -3,8 +3,11 @@
 //
 // Stage kernel: one wavefront per configuration cell (x, y) advances that
 // cell's whole velocity plane.  Lane l owns the velocity column vy = l and
-// the wave marches along vx; at each vx position it reads the rows of the
-// nine planes of the stencil (the cell itself and its x +-1, +-2 and
+// the wave marches along vx.  With more than 64 cells along vy the plane is
+// cut into segments of 60 columns, one block row per segment: lane l owns
+// vy = 60 s - 2 + l, lanes 2 .. 61 produce the segment, and the two outer
+// lanes on each side hold its neighbours or the equilibrium ghosts.  At
+// each vx position the wave reads the rows of the nine planes of the stencil (the cell itself and its x +-1, +-2 and
 // y +-1, +-2 neighbours), 64 contiguous doubles per row, from rows the
 // block stages in LDS for its whole tile of cells.  Face averages along x
 // and y are formed from those rows, faces along vx from a rolling window of
@@ -92,7 +95,7 @@ struct Tile4D {
     }
 };
 
-template <int KIND, int TX, int TY>
+template <int KIND, int TX, int TY, bool SV>
 __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
 {
     using TL = Tile4D<TX, TY>;
@@ -117,11 +120,15 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
     const bool cell_in = x < nx && y < ny;
     const size_t P = (size_t)nvx * nvy;
     auto cfg = [&](int xx, int yy) { return wrapi(xx, nx) * ny + wrapi(yy, ny); };
-
-    const bool act = lane < nvy;
-    const int vyl = act ? lane : nvy - 1;
+    // the lane's vy cell; act: the lane produces an output; vin: the lane
+    // holds a mesh cell rather than a velocity ghost (segments only)
+    const int seg = SV ? (int)blockIdx.y : 0;
+    const int vyr = SV ? seg * kSegVy4D - 2 + lane : lane;
+    const bool act = SV ? (lane >= 2 && lane < kSegVy4D + 2 && vyr < nvy) : lane < nvy;
+    const bool vin = !SV || (vyr >= 0 && vyr < nvy);
+    const int vyl = min(max(vyr, 0), nvy - 1);
     // rows this wave loads each position: planes wave, wave + NW, ...
-    // (element offsets below 2^31: nx, ny <= 64, nvx <= 1024, nvy <= 64)
+    // (element offsets below 2^31: the plan limits the state to 2^31 elements)
     unsigned lpo[LPW];
 #pragma unroll
     for (int k = 0; k < LPW; ++k) {
@@ -130,7 +137,9 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
         lpo[k] = (unsigned)((size_t)cfg(x0 + i, y0 + j) * P + vyl);
     }
     for (int q = (int)threadIdx.x; q < nvx + 4; q += 64 * NW) gxs[q] = A.gx[q];
-    for (int q = (int)threadIdx.x; q < nvy + 4; q += 64 * NW) gys[q] = A.gy[q];
+    if (!SV)
+        for (int q = (int)threadIdx.x; q < nvy + 4; q += 64 * NW) gys[q] = A.gy[q];
+    const double gyl = SV ? A.gy[min(max(vyr + 2, 0), nvy + 3)] : 0.0;   // the lane's vy equilibrium factor
     // rows this wave reads: c, x-1, x+1, y-1, y+1, x-2, x+2, y-2, y+2
     const int rp[9] = {TL::pid(tx, ty),     TL::pid(tx - 1, ty), TL::pid(tx + 1, ty),
                        TL::pid(tx, ty - 1), TL::pid(tx, ty + 1), TL::pid(tx - 2, ty),
@@ -148,12 +157,14 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
                  cay_y = uniform_f64((ay[cfg(x, y + 1)] - ay[cfg(x, y - 1)]) * (1.0 / 48.0));
     // vy equilibrium factor of vy cell j (-2 <= j < nvy + 2), staged in LDS
     auto gy_at = [&](int j) { return gys[min(max(j + 2, 0), nvy + 3)]; };
-    const double vby = A.vy_lo + ((double)lane + 0.5) * A.dvy;
+    const double vby = A.vy_lo + ((double)vyr + 0.5) * A.dvy;
     const double dxi = A.dxi, dyi = A.dyi, dvxi = A.dvxi, dvyi = A.dvyi, dvx24 = A.dvx24, dvy24 = A.dvy24;
 
     // sv = the value of lane + d of a per-lane quantity whose ghost value at
     // lane + d is gq * gy[lane + d]; lanes past the velocity range take the ghost
+    // (segments: every lane holds its cell or ghost value, nothing to replace)
     auto nb = [&](double sv, int d, double gq) {
+        if (SV) return sv;
         const int src = lane + d;
         return (src >= 0 && src < nvy) ? sv : gq * gy_at(src);
     };
@@ -182,8 +193,8 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
     double vw[4] = {0, 0, 0, 0}, uw[3] = {0, 0, 0}, cw[3] = {0, 0, 0}, dxw[4] = {0, 0, 0, 0}, dyw[3] = {0, 0, 0};
     auto shift_in = [&](int slot, int p) {
         double (*rs)[64] = rows[slot];
-        const bool in = p >= 0 && p < nvx;
-        const double g = gxs[min(max(p + 2, 0), nvx + 3)] * gy_at(lane);
+        const bool in = p >= 0 && p < nvx && vin;
+        const double g = gxs[min(max(p + 2, 0), nvx + 3)] * (SV ? gyl : gy_at(lane));
         double v[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) v[q] = in ? rs[rp[q]][lane] : g;
@@ -238,14 +249,17 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
             const double r1 = dpp_f64<kLaneNext>(u0), r2 = dpp_f64<kLaneNext>(r1), rm = dpp_f64<kLanePrev>(u0);
             const double um = nb(rm, -1, gu), u1 = nb(r1, 1, gu), u2 = nb(r2, 2, gu);
             const double gvy_hi = f4(um, u0, u1, u2);
-            const double gvy_b = f4(gu * gy_at(lane - 2), um, u0, u1);
             const double gvy_s = dpp_f64<kLanePrev>(gvy_hi);
-            const double gvy_lo = lane == 0 ? gvy_b : gvy_s;
+            double gvy_lo = gvy_s;
+            if (!SV) {
+                const double gvy_b = f4(gu * gy_at(lane - 2), um, u0, u1);
+                gvy_lo = lane == 0 ? gvy_b : gvy_s;
+            }
 
             const double k = -kx - ky - (gvx_hi - gvx_lo) * dvxi - (gvy_hi - gvy_lo) * dvyi;
             gvx_lo = gvx_hi;
 
-            const size_t o = po_c + (size_t)t * nvy + lane;
+            const size_t o = po_c + (size_t)t * nvy + vyl;
             const bool st = act && cell_in;
             const double f0 = cw[0];                 // the stage state at the output position
             double out;
@@ -284,8 +298,18 @@ __global__ __launch_bounds__(64 * TX * TY) void k_stage4d(Stage4DArgs A)
     }
     if (KIND != kRhs && A.n && cell_in) {
         const double sm = wave_sum(msum);
-        if (lane == 0) A.n[cfg(x, y)] = sm * A.mscale;
+        if (lane == 0) A.n[(size_t)seg * nx * ny + cfg(x, y)] = sm * A.mscale;   // a segment's share
     }
+}
+
+// n[e] = sum over the segments of their shares of the moment
+__global__ __launch_bounds__(256) void k_sum_segments(double* __restrict__ n, int nseg, int ncfg)
+{
+    const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (e >= ncfg) return;
+    double s = n[e];
+    for (int q = 1; q < nseg; ++q) s += n[(size_t)q * ncfg + e];
+    n[e] = s;
 }
 
 // n = dvx dvy sum over the velocity plane, one wave per configuration cell
@@ -309,11 +333,11 @@ __global__ __launch_bounds__(256) void k_moment4d(const double* __restrict__ f, 
 // diagonalises every symmetric circulant matrix:
 //   g = (Qx^T rho Qy) / lambda (zero mode dropped),  phi = Qx g Qy^T,
 // then E = -D phi per direction and a = (q/m) E.  Two launches of one
-// block per row (nx, ny <= 64): the forward transform of one Fourier row,
+// block per row (nx, ny <= 64; larger meshes below): the forward transform of one Fourier row,
 // then the inverse transform of five x rows and the field of the middle
 // one.  Rows computed by several blocks are computed identically.
 
-constexpr int kP2 = kMaxPoisson2D;          // 64: rows and columns per matrix at most
+constexpr int kP2 = kPoisson2DSmall;        // 64: rows and columns per matrix at most
 constexpr int kP2Q = 256 / kP2;             // 4 groups of 64 threads split each sum
 
 // block k: g[k][l] = invlam(k, l) sum_j (sum_i Qx[i][k] rho'[i][j]) Qy[j][l],
@@ -447,16 +471,92 @@ __global__ __launch_bounds__(256) void k_poisson2d_inv(const double* __restrict_
     }
 }
 
+// ---------------------------------------------------------------- 2D Poisson, larger meshes
+//
+// The same solve for meshes of more than 64 cells in x or y (up to 256):
+// one block per Fourier row computes g[k][:] = -(Qx^T n Qy)[k][:] / lambda
+// (the mean of n lies in the zero mode, which is dropped), one block per x
+// row the potential phi[i][:] = (Qx g Qy^T)[i][:], then one thread per cell
+// the field.  QyT holds Qy transposed so that every inner loop reads
+// consecutive doubles across the threads.
+__global__ __launch_bounds__(256) void k_poisson2d_fwd_l(const double* __restrict__ n, int nx, int ny,
+                                                        const double* __restrict__ Qx, const double* __restrict__ Qy,
+                                                        const double* __restrict__ invlamT, double* __restrict__ g)
+{
+    __shared__ double w[kMaxPoisson2D];
+    const int k = blockIdx.x, t = threadIdx.x;
+    if (t < ny) {
+        double acc = 0.0;
+        for (int i = 0; i < nx; ++i) acc += Qx[i * nx + k] * n[i * ny + t];
+        w[t] = acc;
+    }
+    __syncthreads();
+    if (t < ny) {
+        double acc = 0.0;
+        for (int j = 0; j < ny; ++j) acc += w[j] * Qy[j * ny + t];
+        g[k * ny + t] = -acc * invlamT[t * nx + k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_poisson2d_inv_l(const double* __restrict__ g, int nx, int ny,
+                                                        const double* __restrict__ Qx, const double* __restrict__ QyT,
+                                                        double* __restrict__ phi)
+{
+    __shared__ double h[kMaxPoisson2D];
+    const int i = blockIdx.x, t = threadIdx.x;
+    if (t < ny) {
+        double acc = 0.0;
+        for (int k = 0; k < nx; ++k) acc += Qx[i * nx + k] * g[k * ny + t];
+        h[t] = acc;
+    }
+    __syncthreads();
+    if (t < ny) {
+        double acc = 0.0;
+        for (int l = 0; l < ny; ++l) acc += h[l] * QyT[l * ny + t];
+        phi[i * ny + t] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_field2d_l(const double* __restrict__ ph, int nx, int ny, double dx,
+                                                  double dy, double qm, double* __restrict__ phi_out,
+                                                  double* __restrict__ E_out, double* __restrict__ a_out)
+{
+    const int e = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    const int N = nx * ny;
+    if (e >= N) return;
+    const int i = e / ny, j = e - (e / ny) * ny;
+    auto at = [&](int ii, int jj) { return ph[wrapi(ii, nx) * ny + wrapi(jj, ny)]; };
+    const double ex = -(8.0 * (at(i + 1, j) - at(i - 1, j)) - (at(i + 2, j) - at(i - 2, j))) / (12.0 * dx);
+    const double ey = -(8.0 * (at(i, j + 1) - at(i, j - 1)) - (at(i, j + 2) - at(i, j - 2))) / (12.0 * dy);
+    if (phi_out) phi_out[e] = ph[e];
+    if (E_out) { E_out[e] = ex; E_out[N + e] = ey; }
+    if (a_out) { a_out[e] = qm * ex; a_out[N + e] = qm * ey; }
+}
+
+template <int KIND, bool SV>
+hipError_t launch_stage4d_t(int tx, int ty, const Stage4DArgs& a, hipStream_t stream)
+{
+    const int nseg = SV ? (a.nvy + kSegVy4D - 1) / kSegVy4D : 1;
+    const dim3 g((unsigned)(((a.nx + tx - 1) / tx) * ((a.ny + ty - 1) / ty)), (unsigned)nseg);
+    if (tx == 4 && ty == 4) hipLaunchKernelGGL((k_stage4d<KIND, 4, 4, SV>), g, dim3(1024), 0, stream, a);
+    else if (tx == 2 && ty == 4) hipLaunchKernelGGL((k_stage4d<KIND, 2, 4, SV>), g, dim3(512), 0, stream, a);
+    else if (tx == 4 && ty == 2) hipLaunchKernelGGL((k_stage4d<KIND, 4, 2, SV>), g, dim3(512), 0, stream, a);
+    else if (tx == 2 && ty == 2) hipLaunchKernelGGL((k_stage4d<KIND, 2, 2, SV>), g, dim3(256), 0, stream, a);
+    else return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && SV && KIND != kRhs && a.n) {
+        const int ncfg = a.nx * a.ny;
+        hipLaunchKernelGGL(k_sum_segments, dim3((ncfg + 255) / 256), dim3(256), 0, stream, a.n, nseg, ncfg);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
 template <int KIND>
 hipError_t launch_stage4d_k(int tx, int ty, const Stage4DArgs& a, hipStream_t stream)
 {
-    const dim3 g((unsigned)(((a.nx + tx - 1) / tx) * ((a.ny + ty - 1) / ty)));
-    if (tx == 4 && ty == 4) hipLaunchKernelGGL((k_stage4d<KIND, 4, 4>), g, dim3(1024), 0, stream, a);
-    else if (tx == 2 && ty == 4) hipLaunchKernelGGL((k_stage4d<KIND, 2, 4>), g, dim3(512), 0, stream, a);
-    else if (tx == 4 && ty == 2) hipLaunchKernelGGL((k_stage4d<KIND, 4, 2>), g, dim3(512), 0, stream, a);
-    else if (tx == 2 && ty == 2) hipLaunchKernelGGL((k_stage4d<KIND, 2, 2>), g, dim3(256), 0, stream, a);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    return a.nvy > kMaxVy4D ? launch_stage4d_t<KIND, true>(tx, ty, a, stream)
+                            : launch_stage4d_t<KIND, false>(tx, ty, a, stream);
 }
 
 }  // namespace
@@ -483,9 +583,18 @@ hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double d
                             const double* Qy, const double* invlamT, double* g, double* phi, double* E, double* a,
                             hipStream_t stream)
 {
-    if (nx > kMaxPoisson2D || ny > kMaxPoisson2D || !g) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_poisson2d_fwd, dim3(nx), dim3(256), 0, stream, n, nx, ny, Qx, Qy, invlamT, g);
-    hipLaunchKernelGGL(k_poisson2d_inv, dim3(nx), dim3(256), 0, stream, g, nx, ny, dx, dy, qm, Qx, Qy, phi, E, a);
+    if (nx > kMaxPoisson2D || ny > kMaxPoisson2D || nx < 1 || ny < 1 || !g) return hipErrorInvalidValue;
+    if (nx <= kPoisson2DSmall && ny <= kPoisson2DSmall) {
+        hipLaunchKernelGGL(k_poisson2d_fwd, dim3(nx), dim3(256), 0, stream, n, nx, ny, Qx, Qy, invlamT, g);
+        hipLaunchKernelGGL(k_poisson2d_inv, dim3(nx), dim3(256), 0, stream, g, nx, ny, dx, dy, qm, Qx, Qy, phi, E, a);
+        return hipGetLastError();
+    }
+    // g holds the coefficients, then the potential; Qy is followed by its transpose
+    const int N = nx * ny;
+    double* ph = g + N;
+    hipLaunchKernelGGL(k_poisson2d_fwd_l, dim3(nx), dim3(256), 0, stream, n, nx, ny, Qx, Qy, invlamT, g);
+    hipLaunchKernelGGL(k_poisson2d_inv_l, dim3(nx), dim3(256), 0, stream, g, nx, ny, Qx, Qy + (size_t)ny * ny, ph);
+    hipLaunchKernelGGL(k_field2d_l, dim3((N + 255) / 256), dim3(256), 0, stream, ph, nx, ny, dx, dy, qm, phi, E, a);
     return hipGetLastError();
 }
 

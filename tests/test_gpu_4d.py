@@ -15,7 +15,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 SIZES = [(4, 4, 8, 8), (5, 6, 12, 10), (8, 8, 16, 16), (3, 7, 9, 64), (6, 5, 20, 63), (1, 2, 5, 1), (2, 3, 1, 33),
-         (16, 12, 24, 40)]
+         (16, 12, 24, 40),
+         # more than 64 cells along vy: segments of 60 (two and three, ragged last)
+         (3, 4, 10, 100), (2, 3, 6, 150), (4, 2, 5, 65),
+         # configuration meshes past 64 cells: the larger-mesh Poisson path
+         (72, 66, 4, 6), (5, 130, 3, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -104,8 +108,9 @@ def test_rk4_steps(vp, oracle, shape):
         cmp(f, want.ravel(), 1e-12 * (s + 1), f"step {s + 1}")
 
 
-def test_load_batches_agree(vp, oracle):
-    p = problem(8, 6, 20, 64)
+@pytest.mark.parametrize("nvy", [64, 100])
+def test_load_batches_agree(vp, oracle, nvy):
+    p = problem(8, 6, 20, nvy)
     plan = vp.Plan(p)
     f0 = random_state(p, 4)
     outs = []
@@ -141,3 +146,19 @@ def test_adjoint_not_supported(vp):
     a = vp.field_of(plan, f)
     with pytest.raises(vp.VPError, match="ENOTSUP"):
         vp.adjoint_step(plan, f, a, f.clone(), 0.01)
+
+
+def test_128_128_32_32(vp, oracle):
+    """A 128 x 128 configuration mesh (the larger-mesh Poisson path) with
+    32 x 32 velocity cells: field and one RK4 step against the oracle."""
+    p = I.Problem2D(128, 128, 32, 32)
+    o = oracle.Oracle4D.from_problem(p)
+    plan = vp.Plan(p)
+    f0 = random_state(p, 9)
+    f = gpu(f0)
+    a = vp.field_of(plan, f)
+    a_o, _, _ = o.constraints(f0)
+    cmp(a, a_o, 1e-10, "a")
+    dt = 4e-3
+    vp.rk4_step(plan, f, a, dt)
+    cmp(f, o.step(f0, dt).ravel(), 1e-12, "step")

@@ -198,9 +198,9 @@ def test_plan_errors(vp):
     bad = dict(spec, v_hi=[V_HI, V_HI + 1.0])
     with pytest.raises(vp.VPError, match="velocity interval"):
         vp.Plan(bad, boxes=[good])
-    _, gxc, gyc, gxf, gyf = I.amr4d_state((40, 4, 6, 6), R, [])
-    big = vp.amr4d_spec((40, 4, 6, 6), X_LEN, Y_LEN, V_LO, V_HI, -1.0, R, (gxc, gyc, gxf, gyf))
-    with pytest.raises(vp.VPError, match="64 x 64"):
+    _, gxc, gyc, gxf, gyf = I.amr4d_state((130, 4, 6, 6), R, [])
+    big = vp.amr4d_spec((130, 4, 6, 6), X_LEN, Y_LEN, V_LO, V_HI, -1.0, R, (gxc, gyc, gxf, gyf))
+    with pytest.raises(vp.VPError, match="256 x 256"):
         vp.Plan(big)
     p = vp.Plan(spec, boxes=[good])
     with pytest.raises(vp.VPError):

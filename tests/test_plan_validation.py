@@ -118,7 +118,8 @@ def make_problem_4d(V, nx=8, ny=8, nvx=16, nvy=16, dtype=0):
     return pb, keep
 
 
-@pytest.mark.parametrize("kw,code", [(dict(nvy=65), 4), (dict(nx=65), 4), (dict(ny=80), 4), (dict(dtype=1), 4)])
+@pytest.mark.parametrize("kw,code", [(dict(nx=257), 4), (dict(ny=300), 4), (dict(nvx=1025), 4), (dict(dtype=1), 4),
+                                     (dict(nx=256, ny=256, nvx=1024, nvy=32), 4)])
 def test_4d_limits(V, kw, code):
     pb, keep = make_problem_4d(V, **kw)
     assert create(V, pb, [])[0] == code
