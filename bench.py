@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three device-to-device copies of MIB MiB (reference for HBM traffic counters)")
     ap.add_argument("--4d-only", dest="fourd_only", action="store_true", help="run only the 2D+2V section")
+    ap.add_argument("--limited-only", action="store_true", help="run only the limited-face section")
     return ap.parse_args()
 
 
@@ -645,6 +646,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.limited_only:
+        print(json.dumps({"limited": limited_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
     if args.fourd_only:
         print(json.dumps({"2d2v": fourd_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
         return

@@ -156,25 +156,53 @@ __device__ __forceinline__ double centre_unfused(double lo, double x, double h)
     return lo + p;
 }
 
+// 1 / d for d > 0: the hardware estimate refined by Newton-Raphson steps
+// r <- r + r (1 - d r), each of which squares the relative error
+__device__ __forceinline__ double recip_nr(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ __forceinline__ float recip_nr(float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+
 // Limited face average between u0 and u1 (section 2, eq. limitedFace): the
 // left- and right-biased third-order candidates (eqs. thirdLeft,
 // thirdRight) weighted by provisional WENO weights from the Jiang-Shu
 // smoothness of their stencils (ideal weights 1/2, epsilon 1e-6, power 2),
 // the larger weight given to the upwind candidate (upl: flow towards +).
+// With s = (beta + eps)^2 the provisional left weight is s_r / (s_l + s_r),
+// the larger weight max(s_l, s_r) / (s_l + s_r), and the face
+// w_l f_l + w_r f_r = f_r + w_l (f_l - f_r).
 template <typename T>
 __device__ __forceinline__ T face_lim(T um1, T u0, T u1, T u2, bool upl)
 {
-    const T fl = (T(5) * u0 + T(2) * u1 - um1) * T(1.0 / 6.0);
     const T fr = (T(2) * u0 + T(5) * u1 - u2) * T(1.0 / 6.0);
+    const T dlr = (T(3) * (u0 - u1) + (u2 - um1)) * T(1.0 / 6.0);     // f_l - f_r
     const T d1 = um1 - T(2) * u0 + u1, e1 = um1 - u1;
     const T d2 = u0 - T(2) * u1 + u2, e2 = T(3) * u0 - T(4) * u1 + u2;
     const T bl = T(13.0 / 12.0) * d1 * d1 + T(0.25) * e1 * e1 + T(1e-6);
     const T br = T(13.0 / 12.0) * d2 * d2 + T(0.25) * e2 * e2 + T(1e-6);
     const T sl = bl * bl, sr = br * br;
-    const T wl = sr / (sl + sr);                 // provisional left weight, (1/sl) / (1/sl + 1/sr)
-    const T wmax = wl > T(0.5) ? wl : T(1) - wl;
-    const T wmin = T(1) - wmax;
-    return upl ? wmax * fl + wmin * fr : wmin * fl + wmax * fr;
+    const T wmax = (sl > sr ? sl : sr) * recip_nr(sl + sr);
+    return fr + (upl ? wmax : T(1) - wmax) * dlr;
+}
+
+// x moved by the wave-wide DPP shift CTRL (wave_shl:1 = 0x130: lane l reads
+// lane l + 1; wave_shr:1 = 0x138: lane l reads lane l - 1); the lane with no
+// source receives an unspecified value, which the callers replace
+constexpr int kWaveShl1 = 0x130;
+constexpr int kWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double x) { return dpp_f64<CTRL>(x); }
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
 }
 
 // Stage kernel.  A block owns a strip of TV = NT*W velocity cells and a
@@ -309,10 +337,23 @@ __device__ __forceinline__ void stage_tile_uniform(const Stage1DArgs& A, int til
             const T* u0 = DN ? r2 : r1;
             const T* u1 = DN ? r1 : r2;
             const T* u2 = DN ? r0 : r3;
+            if (LIM) {
+                // limited faces are costly: each thread evaluates those of its
+                // own W columns and takes the two next to them from the
+                // neighbouring lanes; lanes at the ends of the wave evaluate
+                // theirs (one face per thread: column jt - 1 in lane 0, jt + W
+                // in lane 63)
 #pragma unroll
-            for (int q = 0; q < W + 2; ++q) {
-                if (LIM) Fx[q] = face_lim<T>(um1[q + 1], u0[q + 1], u1[q + 1], u2[q + 1], upx[q]);
-                else Fx[q] = face4<T>(um1[q + 1], u0[q + 1], u1[q + 1], u2[q + 1]);
+                for (int q = 1; q <= W; ++q) Fx[q] = face_lim<T>(um1[q + 1], u0[q + 1], u1[q + 1], u2[q + 1], upx[q]);
+                const bool rt = lane == 63;
+                const T fe = face_lim<T>(rt ? um1[W + 2] : um1[1], rt ? u0[W + 2] : u0[1], rt ? u1[W + 2] : u1[1],
+                                         rt ? u2[W + 2] : u2[1], rt ? upx[W + 1] : upx[0]);
+                const T fprev = wave_shift<kWaveShr1>(Fx[W]), fnext = wave_shift<kWaveShl1>(Fx[1]);
+                Fx[0] = lane == 0 ? fe : fprev;
+                Fx[W + 1] = rt ? fe : fnext;
+            } else {
+#pragma unroll
+                for (int q = 0; q < W + 2; ++q) Fx[q] = face4<T>(um1[q + 1], u0[q + 1], u1[q + 1], u2[q + 1]);
             }
         };
         // v faces jt-1/2 .. jt+W-1/2 of window row u (row r)
