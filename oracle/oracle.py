@@ -101,6 +101,7 @@ def _declare_extra(L):
         "vpo_rk4_dense_weights": (None, [_F, _D]),
         "vpo_rk4_substage_weights": (None, [_F, _F, _I, _D]),
         "vpo_amr_rhs": (None, [_V, _D, _D, _D]),
+        "vpo_amr_set_limited": (None, [_V, _I]),
         "vpo_a4_new": (_V, [ctypes.POINTER(ctypes.c_int), _F, _F, _F, _F, _F, _I, _I, ctypes.POINTER(ctypes.c_int),
                             _D, _D, _D, _D]),
         "vpo_a4_free": (None, [_V]),
@@ -485,6 +486,11 @@ class OracleAMR:
 
     def offset(self, p):
         return lib().vpo_amr_patch_offset(self.h, p)
+
+    def set_limited(self, on=True):
+        """Limited face averages (section 2, eq. limitedFace) on both levels."""
+        lib().vpo_amr_set_limited(self.h, int(bool(on)))
+        return self
 
     def reduce_mask(self, f):
         f = _f64(f)

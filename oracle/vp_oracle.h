@@ -56,6 +56,9 @@ void vpo_amr_fill_ghosts(void* h, double* f, int p, double* out);
 void vpo_amr_reduce_mask(void* h, double* f, double* n);
 void vpo_amr_constraints(void* h, double* f, double* a, double* E_out);
 void vpo_amr_rhs(void* h, double* f, double* a, double* k);
+void vpo_amr_set_limited(void* h, int on);
+void vpo_patch_fluxes_limited(int nx, int nv, const double* g, double dv, double v_lo, int col0,
+                              const double* a_ext, double* Gx, double* Gv);
 /* fluxes of section 2 on one patch from its data with two ghost layers g
  * ((nx+4) x (nv+4)): Gx[(nx+1) x nv], Gv[nx x (nv+1)]; a_ext[i+1] = a at row
  * i = -1 .. nx; and their divergence */

@@ -66,6 +66,7 @@ typedef struct {
     double B[16][5];      /* R <= 16 */
     vpo_poisson* P;
     long total;
+    int limited;          /* face averages: 0 centred, 1 limited (section 2, eq. limitedFace) */
 } vpo_amr;
 
 void* vpo_amr_new(int ncx, int ncv, double x_len, double v_lo, double v_hi, double qm, int R, int np,
@@ -255,6 +256,44 @@ void vpo_patch_fluxes(int nx, int nv, const double* g, double dv, double v0, con
 #undef G
 }
 
+/* The same fluxes with the limited face averages of section 2 (eq.
+ * limitedFace) in place of every centred one, the neighbouring ones of the
+ * product-rule corrections included: an x face is upwinded by the sign of
+ * the centre velocity of its column, v_lo + (col0 + j + 1/2) dv with col0
+ * the level's global index of local column 0, a v face by the sign of a in
+ * its row. */
+void vpo_patch_fluxes_limited(int nx, int nv, const double* g, double dv, double v_lo, int col0,
+                              const double* a_ext, double* Gx, double* Gv)
+{
+    int W = nv + 4;
+#define G(i, j) g[(size_t)((i) + 2) * W + ((j) + 2)]
+#define VC(j) (v_lo + ((double)(col0 + (j)) + 0.5) * dv)
+    for (int i = -1; i < nx; ++i)           /* face i + 1/2 */
+        for (int j = 0; j < nv; ++j) {
+            double fc = vpo_face_limited(G(i - 1, j), G(i, j), G(i + 1, j), G(i + 2, j), VC(j) > 0.0);
+            double fu = vpo_face_limited(G(i - 1, j + 1), G(i, j + 1), G(i + 1, j + 1), G(i + 2, j + 1),
+                                         VC(j + 1) > 0.0);
+            double fd = vpo_face_limited(G(i - 1, j - 1), G(i, j - 1), G(i + 1, j - 1), G(i + 2, j - 1),
+                                         VC(j - 1) > 0.0);
+            Gx[(size_t)(i + 1) * nv + j] = VC(j) * fc + dv / 24.0 * (fu - fd);
+        }
+    for (int i = 0; i < nx; ++i) {
+        double ai = a_ext[i + 1], da = a_ext[i + 2] - a_ext[i];
+        for (int j = -1; j < nv; ++j) {      /* face j + 1/2 */
+            double fc = vpo_face_limited(G(i, j - 1), G(i, j), G(i, j + 1), G(i, j + 2), a_ext[i + 1] > 0.0);
+            double fp = vpo_face_limited(G(i + 1, j - 1), G(i + 1, j), G(i + 1, j + 1), G(i + 1, j + 2),
+                                         a_ext[i + 2] > 0.0);
+            double fm = vpo_face_limited(G(i - 1, j - 1), G(i - 1, j), G(i - 1, j + 1), G(i - 1, j + 2),
+                                         a_ext[i] > 0.0);
+            Gv[(size_t)i * (nv + 1) + (j + 1)] = ai * fc + da / 48.0 * (fp - fm);
+        }
+    }
+#undef VC
+#undef G
+}
+
+void vpo_amr_set_limited(void* h, int on) { ((vpo_amr*)h)->limited = on != 0; }
+
 /* flux divergence: k_ij = -(Gx_{i+1/2} - Gx_{i-1/2})/dx - (Gv_{j+1/2} - Gv_{j-1/2})/dv */
 void vpo_divergence(int nx, int nv, const double* Gx, const double* Gv, double dx, double dv, double* k)
 {
@@ -275,7 +314,8 @@ static void coarse_fluxes(const vpo_amr* c, const double* f, const double* a, do
         for (int j = -2; j < ncv + 2; ++j) g[(size_t)(i + 2) * W + j + 2] = coarse_at(c, f, i, j);
     double* ae = (double*)malloc(sizeof(double) * (ncx + 2));
     for (int i = -1; i <= ncx; ++i) ae[i + 1] = a[wrap(i, ncx)];
-    vpo_patch_fluxes(ncx, ncv, g, c->dvc, c->v_lo, ae, Gx, Gv);
+    if (c->limited) vpo_patch_fluxes_limited(ncx, ncv, g, c->dvc, c->v_lo, 0, ae, Gx, Gv);
+    else vpo_patch_fluxes(ncx, ncv, g, c->dvc, c->v_lo, ae, Gx, Gv);
     free(ae);
     free(g);
 }
@@ -288,7 +328,8 @@ static void fine_patch_fluxes(const vpo_amr* c, double* f, const double* a, int 
     vpo_amr_fill_ghosts((void*)c, f, p, g);
     double* ae = (double*)malloc(sizeof(double) * (nxp + 2));
     for (int i = -1; i <= nxp; ++i) ae[i + 1] = a[c->ncx + wrap(x0 + i, c->nfx)];
-    vpo_patch_fluxes(nxp, nvp, g, c->dvf, c->v_lo + v0 * c->dvf, ae, Gx, Gv);
+    if (c->limited) vpo_patch_fluxes_limited(nxp, nvp, g, c->dvf, c->v_lo, v0, ae, Gx, Gv);
+    else vpo_patch_fluxes(nxp, nvp, g, c->dvf, c->v_lo + v0 * c->dvf, ae, Gx, Gv);
     free(ae);
     free(g);
 }
