@@ -193,7 +193,9 @@ vp_status vp_reduce_moment(const vp_plan* plan, const void* f, double* n, void* 
  *                     the upwind candidate (x faces: sign of the column's
  *                     velocity; v faces: sign of the row's acceleration)
  * The limited scheme is nonlinear: vp_rk4_step_record / vp_adjoint_step
- * return VP_ENOTSUP for it.  VP_ENOTSUP for two-level and 2D+2V plans.
+ * return VP_ENOTSUP for it.  Two-level plans take it on both levels (the
+ * coarse fluxes on coarse-fine faces included; synchronous and subcycled
+ * steps); VP_ENOTSUP for plans of more than two levels and 2D+2V plans.
  * Not safe to call while calls on the plan are being enqueued.
  */
 #define VP_FACE_CENTERED 0

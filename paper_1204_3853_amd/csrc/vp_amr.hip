@@ -110,6 +110,7 @@ AmrArgs stage_args(const vp_plan* p, const void* fs, const void* fn, void* acc, 
     A.patches = M.d_patches;
     A.tiles = M.d_tiles;
     A.ntiles = M.ntiles;
+    A.lim = p->face_scheme == VP_FACE_LIMITED;
     A.nfx = M.nfx;
     A.nfv = M.nfv;
     A.R = M.R;

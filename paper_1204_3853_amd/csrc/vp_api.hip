@@ -500,8 +500,8 @@ vp_status vp_face_scheme_set(vp_plan* p, int32_t scheme)
     if (vp_status s = check_plan(p)) return s;
     if (scheme != VP_FACE_CENTERED && scheme != VP_FACE_LIMITED)
         return fail(VP_EINVAL, "vp_face_scheme_set: unknown scheme");
-    if (scheme == VP_FACE_LIMITED && (p->amr || p->hier || p->p4 || p->a4))
-        return fail(VP_ENOTSUP, "vp_face_scheme_set: limited faces are built for single-level 1D+1V plans");
+    if (scheme == VP_FACE_LIMITED && (p->hier || p->p4 || p->a4))
+        return fail(VP_ENOTSUP, "vp_face_scheme_set: limited faces are built for 1D+1V plans of one or two levels");
     p->face_scheme = scheme;
     return VP_OK;
 }

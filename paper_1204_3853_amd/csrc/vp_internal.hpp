@@ -154,6 +154,7 @@ struct AmrArgs {
     double* ff_acc;            // accumulated fine boundary fluxes
     double c_flux;             // b_s (0: no accumulation)
     int first;                 // first stage: store instead of add
+    int lim;                   // limited face averages on both levels
 };
 
 // ----------------------------------------------------------------- two-level 2D+2V

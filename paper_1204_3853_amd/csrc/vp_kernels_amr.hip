@@ -47,7 +47,7 @@ __device__ __forceinline__ void flux_acc(double* p, double v, const AmrArgs& A)
 // Stage tile on a level-1 patch (FP64): same march and arithmetic as the
 // single-level tile; the halo cells are interpolated from the coarse level
 // (x then v, the sub-cell weights b_j(s) of section 3).
-template <int W, int NT, int KIND>
+template <int W, int NT, int KIND, bool LIM>
 __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile& tl)
 {
     using T = double;
@@ -242,12 +242,20 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
         }
         if (has_halo) dst[hcol_idx] = (rowdata && halo_data) ? h : halo_val(r, hj);
     };
+    // limited faces (section 2, eq. limitedFace): an x face upwinded by the
+    // sign of its column's centre velocity (global column, rounded after the
+    // product and after the sum), a v face by the sign of a in its row
+    bool upx[W + 2];
+#pragma unroll
+    for (int q = 0; q < W + 2; ++q)
+        upx[q] = LIM && centre_unfused(A.v_lo, (double)(P.gv0 + jt - 1 + q) + 0.5, A.dvf) > 0.0;
     auto fx_cols = [&](int r, T* Fx) {
         const int sm1 = slot_of(r - 1), s0 = slot_of(r), s1 = slot_of(r + 1), s2 = slot_of(r + 2);
 #pragma unroll
         for (int q = 0; q < W + 2; ++q) {
             const int c = c0 - 1 + q;
-            Fx[q] = face4<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c]);
+            if (LIM) Fx[q] = face_lim<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c], upx[q]);
+            else Fx[q] = face4<T>(ring[sm1][c], ring[s0][c], ring[s1][c], ring[s2][c]);
         }
     };
     auto fv_faces = [&](int r, T* Fv) {
@@ -255,8 +263,12 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
         T u[W + 4];
 #pragma unroll
         for (int q = 0; q < W + 4; ++q) u[q] = ring[sl][c0 - 2 + q];
+        const bool upv = LIM && aseg[r - i0 + 1] > 0.0;
 #pragma unroll
-        for (int m = 0; m <= W; ++m) Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
+        for (int m = 0; m <= W; ++m) {
+            if (LIM) Fv[m] = face_lim<T>(u[m], u[m + 1], u[m + 2], u[m + 3], upv);
+            else Fv[m] = face4<T>(u[m], u[m + 1], u[m + 2], u[m + 3]);
+        }
     };
 
     T vb[W];
@@ -381,7 +393,7 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
 }
 
 // coarse fluxes on a chunk of coarse-fine faces, accumulated with weight b_s
-template <int NT>
+template <int NT, bool LIM>
 __device__ __forceinline__ void face_chunk(const AmrArgs& A, const AmrTile& tl)
 {
     const Stage1DArgs& C = A.coarse;
@@ -397,7 +409,11 @@ __device__ __forceinline__ void face_chunk(const AmrArgs& A, const AmrTile& tl)
 #pragma unroll
             for (int m = -1; m <= 1; ++m) {
                 const int c = F.j + m;
-                fx[m + 1] = face4<double>(at(F.i - 1, c), at(F.i, c), at(F.i + 1, c), at(F.i + 2, c));
+                if (LIM)
+                    fx[m + 1] = face_lim<double>(at(F.i - 1, c), at(F.i, c), at(F.i + 1, c), at(F.i + 2, c),
+                                                 centre_unfused(C.v_lo, (double)c + 0.5, C.dv) > 0.0);
+                else
+                    fx[m + 1] = face4<double>(at(F.i - 1, c), at(F.i, c), at(F.i + 1, c), at(F.i + 2, c));
             }
             const double vb = C.v_lo + ((double)F.j + 0.5) * C.dv;
             G = vb * fx[1] + C.dv24 * (fx[2] - fx[0]);
@@ -406,7 +422,11 @@ __device__ __forceinline__ void face_chunk(const AmrArgs& A, const AmrTile& tl)
 #pragma unroll
             for (int m = -1; m <= 1; ++m) {
                 const int r = F.i + m;
-                fv[m + 1] = face4<double>(at(r, F.j - 1), at(r, F.j), at(r, F.j + 1), at(r, F.j + 2));
+                if (LIM)
+                    fv[m + 1] = face_lim<double>(at(r, F.j - 1), at(r, F.j), at(r, F.j + 1), at(r, F.j + 2),
+                                                 C.a[wrapi(r, C.nx)] > 0.0);
+                else
+                    fv[m + 1] = face4<double>(at(r, F.j - 1), at(r, F.j), at(r, F.j + 1), at(r, F.j + 2));
             }
             const double ai = C.a[wrapi(F.i, C.nx)];
             const double da48 = (C.a[wrapi(F.i + 1, C.nx)] - C.a[wrapi(F.i - 1, C.nx)]) * (1.0 / 48.0);
@@ -416,17 +436,17 @@ __device__ __forceinline__ void face_chunk(const AmrArgs& A, const AmrTile& tl)
     }
 }
 
-template <int W, int NT, int KIND>
+template <int W, int NT, int KIND, bool LIM>
 __global__ __launch_bounds__(NT) void k_amr_stage(AmrArgs A, int t_begin, int t_end)
 {
     for (int t = t_begin + (int)blockIdx.x; t < t_end; t += (int)gridDim.x) {
         const AmrTile tl = A.tiles[t];
         if (tl.kind == kTileCoarse) {
-            stage_tile_uniform<double, W, NT, KIND>(A.coarse, tl.a);
+            stage_tile_uniform<double, W, NT, KIND, LIM>(A.coarse, tl.a);
         } else if (tl.kind == kTileFine) {
-            stage_tile_fine<W, NT, KIND>(A, tl);
+            stage_tile_fine<W, NT, KIND, LIM>(A, tl);
         } else if (KIND != kRhs && A.cf_acc != nullptr && A.c_flux != 0.0) {
-            face_chunk<NT>(A, tl);
+            face_chunk<NT, LIM>(A, tl);
         }
         __syncthreads();
     }
@@ -531,17 +551,24 @@ __global__ __launch_bounds__(256) void k_amr_sync(AmrSyncArgs S)
     }
 }
 
-template <int W, int NT>
-hipError_t launch_amr_t(int kind, const AmrArgs& a, int t0, int t1, int grid, hipStream_t stream)
+template <int W, int NT, bool LIM>
+hipError_t launch_amr_l(int kind, const AmrArgs& a, int t0, int t1, int grid, hipStream_t stream)
 {
     const dim3 g(grid), b(NT);
     switch (kind) {
-    case kRhs: hipLaunchKernelGGL((k_amr_stage<W, NT, kRhs>), g, b, 0, stream, a, t0, t1); break;
-    case kStage1: hipLaunchKernelGGL((k_amr_stage<W, NT, kStage1>), g, b, 0, stream, a, t0, t1); break;
-    case kStage23: hipLaunchKernelGGL((k_amr_stage<W, NT, kStage23>), g, b, 0, stream, a, t0, t1); break;
-    default: hipLaunchKernelGGL((k_amr_stage<W, NT, kStage4>), g, b, 0, stream, a, t0, t1); break;
+    case kRhs: hipLaunchKernelGGL((k_amr_stage<W, NT, kRhs, LIM>), g, b, 0, stream, a, t0, t1); break;
+    case kStage1: hipLaunchKernelGGL((k_amr_stage<W, NT, kStage1, LIM>), g, b, 0, stream, a, t0, t1); break;
+    case kStage23: hipLaunchKernelGGL((k_amr_stage<W, NT, kStage23, LIM>), g, b, 0, stream, a, t0, t1); break;
+    default: hipLaunchKernelGGL((k_amr_stage<W, NT, kStage4, LIM>), g, b, 0, stream, a, t0, t1); break;
     }
     return hipGetLastError();
+}
+
+template <int W, int NT>
+hipError_t launch_amr_t(int kind, const AmrArgs& a, int t0, int t1, int grid, hipStream_t stream)
+{
+    return a.lim ? launch_amr_l<W, NT, true>(kind, a, t0, t1, grid, stream)
+                 : launch_amr_l<W, NT, false>(kind, a, t0, t1, grid, stream);
 }
 
 }  // namespace
