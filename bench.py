@@ -276,6 +276,11 @@ def amr_bench(steps=100, warmup=3):
         red[name] = round(t[0] / t[1] * 1e3, 2)
     plan.set_reduction(vp.REDUCE_SUBPATCH)
 
+    # limited face averages on both levels (section 2, eq. limitedFace)
+    plan.set_face_scheme(vp.FACE_LIMITED)
+    ms_limited = timed_steps(steps)
+    plan.set_face_scheme(vp.FACE_CENTERED)
+
     cells = plan.state_elems
     stage_ms, stage_n = tm["stage"]
     stage_us = stage_ms / stage_n * 1e3
@@ -288,6 +293,7 @@ def amr_bench(steps=100, warmup=3):
             "ms_per_step_persistent": round(ms_persistent, 4),
             "ms_per_step_graph": round(ms_graph, 4),
             "ms_per_step_per_patch": round(ms_per_patch, 4),
+            "ms_per_step_limited_faces": round(ms_limited, 4),
             "speedup_persistent_vs_per_patch": round(ms_per_patch / ms_persistent, 3),
             "speedup_graph_vs_per_patch": round(ms_per_patch / ms_graph, 3),
             "cell_updates_per_s_graph": cells / (ms_graph * 1e-3),
