@@ -62,6 +62,7 @@ def parse():
                     help="first run three device-to-device copies of MIB MiB (reference for HBM traffic counters)")
     ap.add_argument("--4d-only", dest="fourd_only", action="store_true", help="run only the 2D+2V section")
     ap.add_argument("--limited-only", action="store_true", help="run only the limited-face section")
+    ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint section")
     return ap.parse_args()
 
 
@@ -128,6 +129,10 @@ def adjoint_ratio(steps=400, every=20):
     pt = torch.tensor(pvec, dtype=torch.float64, device="cuda", requires_grad=True)
     ct = torch.tensor(c, dtype=torch.float64, device="cuda")
     gt = torch.tensor(g, dtype=torch.float64, device="cuda")
+    # the forward tile shape for this mesh (on copies of the initial state)
+    with torch.no_grad():
+        f_tune = ((1.0 + ct + pt)[:, None] * gt[None, :]).contiguous()
+        _, shape, _ = plan.autotune(f_tune, vp.field_of(plan, f_tune), dt, reps=5)
 
     def run():
         pt.grad = None
@@ -147,6 +152,7 @@ def adjoint_ratio(steps=400, every=20):
     fw, bw = min(run() for _ in range(3))
     return {"workload": "Landau 1D+1V 512x512 FP64, 400 RK4 steps, checkpoint every 20, "
                         "gradient of 1/2 sum E^2 w.r.t. the 512-value initial profile",
+            "forward_tile_shape": {"threads": shape[0], "cells_per_thread": shape[1], "rows": shape[2]},
             "forward_ms": round(fw * 1e3, 2), "backward_ms": round(bw * 1e3, 2), "ratio": round(bw / fw, 3)}
 
 
@@ -652,6 +658,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_ratio()}), flush=True)
+        return
     if args.limited_only:
         print(json.dumps({"limited": limited_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
         return

@@ -833,8 +833,11 @@ vp_status vp_adjoint_step(const vp_plan* p, const void* f_n, const double* a_n, 
     Adjoint1DArgs A{};
     A.nx = nx;
     A.nv = nv;
-    A.tx = 16;
     A.nstrip = (nv + 128 * w - 1) / (128 * w);
+    // rows per tile: 16, halved (down to 4) while the grid has fewer than
+    // 512 tiles, so that small meshes still give every CU work
+    A.tx = 16;
+    while (A.tx > 4 && (size_t)A.nstrip * ((nx + A.tx - 1) / A.tx) < 512) A.tx /= 2;
     A.dxi = 1.0 / p->dx;
     A.dvi = 1.0 / p->dv;
     A.dv24 = p->dv / 24.0;
