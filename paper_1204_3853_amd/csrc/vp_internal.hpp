@@ -329,6 +329,10 @@ struct PoissonExtra {
     const int* idx;
     const double* w;
     int inject_R;              // > 0: a = [(q/m) mean of R fine E per coarse cell][(q/m) E]
+    const double* part;        // non-null: n_i = dv sum over the strips of part[s nx + i]
+    int nstrip;
+    double dv;
+    double* n_out;             // non-null (with part): receives that n
 };
 
 // Launchers (defined in vp_kernels_1d.hip).

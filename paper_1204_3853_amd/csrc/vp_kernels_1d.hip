@@ -342,24 +342,6 @@ __global__ __launch_bounds__(kFieldChunk) void k_field_finish(const double* __re
     }
 }
 
-// n_i = dv * sum over strips of the stage kernel's per-strip partial sums,
-// one row per thread with all strip loads in flight, fixed summation order.
-__global__ __launch_bounds__(256) void k_moment_finalize(const double* __restrict__ part, int nstrip, int nx,
-                                                        double dv, double* __restrict__ n)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= nx) return;
-    double acc = 0.0;
-    for (int q0 = 0; q0 < nstrip; q0 += 16) {
-        double v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = (q0 + u < nstrip) ? part[(size_t)(q0 + u) * nx + i] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc += v[u];
-    }
-    n[i] = dv * acc;
-}
-
 // adjoint = 0: r = 12 dx^2 (1 - n) from the moment n_in; outputs phi, E, a.
 // adjoint = 1: n_in holds abar; r = 12 dx^2 D (q/m) abar (D the field
 // stencil without its sign); phi_out receives phi_scale * S r / (12 dx^2)-
@@ -408,6 +390,17 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
                     for (int k = k0; k < k1; ++k) sacc += X.w[k] * X.slots[X.idx[k]];
                 }
                 nv[m] = sacc;
+            }
+        } else if (X.part) {
+            // the moment from the stage kernel's strip partials, in strip order
+#pragma unroll
+            for (int m = 0; m < RM; ++m) {
+                const int i = t + m * kPoissonThreads;
+                double sacc = 0.0;
+                if (i < nx)
+                    for (int q = 0; q < X.nstrip; ++q) sacc += X.part[(size_t)q * nx + i];
+                nv[m] = X.dv * sacc;
+                if (X.n_out && i < nx) X.n_out[i] = nv[m];
             }
         } else {
 #pragma unroll
@@ -650,16 +643,17 @@ hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, 
                             double dx, double qm, const double* green, int gk, double* n_out,
                             double* phi, double* E, double* a, hipStream_t stream)
 {
-    // with partial sums: finalise the moment into n_out first (n_out is required)
+    // with partial sums the kernel forms the moment itself (n_out unused)
+    (void)n_out;
+    PoissonExtra X{};
     if (part) {
-        if (!n_out) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_moment_finalize, dim3((nx + 255) / 256), dim3(256), 0, stream, part, nstrip, nx,
-                           dv, n_out);
-        n_in = n_out;
+        X.part = part;
+        X.nstrip = nstrip;
+        X.dv = dv;
     }
     const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
-                       phi, E, a, 0, 1.0, PoissonExtra{});
+                       phi, E, a, 0, 1.0, X);
     return hipGetLastError();
 }
 
@@ -714,12 +708,17 @@ hipError_t launch_field_split_species(const SpeciesMoments& m, int nx, double dx
 hipError_t launch_poisson1d_adjoint(const double* part, int nstrip, int nx, double dx, double dv, double qm,
                                     const double* green, int gk, double* abar_out, double* z, hipStream_t stream)
 {
-    if (part)
-        hipLaunchKernelGGL(k_moment_finalize, dim3((nx + 255) / 256), dim3(256), 0, stream, part, nstrip, nx, 1.0,
-                           abar_out);
+    // with partial sums the kernel sums them (and keeps abar in abar_out)
+    PoissonExtra X{};
+    if (part) {
+        X.part = part;
+        X.nstrip = nstrip;
+        X.dv = 1.0;
+        X.n_out = abar_out;
+    }
     const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, abar_out, nx, dx, qm, green,
-                       gk, z, nullptr, nullptr, 1, -dv, PoissonExtra{});
+                       gk, z, nullptr, nullptr, 1, -dv, X);
     return hipGetLastError();
 }
 
