@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--4d-only", dest="fourd_only", action="store_true", help="run only the 2D+2V section")
     ap.add_argument("--limited-only", action="store_true", help="run only the limited-face section")
     ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint section")
+    ap.add_argument("--amr4d-only", action="store_true", help="run only the two-level 2D+2V section")
+    ap.add_argument("--no-amr4d", action="store_true")
     return ap.parse_args()
 
 
@@ -640,6 +642,71 @@ def fourd_bench(steps=50, warmup=3):
             "field_solve_us": round(tm["field"][0] / tm["field"][1] * 1e3, 2)}
 
 
+def amr4d_bench(steps=20, warmup=3):
+    """Two-level 2D+2V (the AMR of section 3 in the 2D+2V phase space):
+    level 0 of 32^4 cells on x, y in [0, 4pi), v in [-6, 6]^2, ratio 2 in
+    every direction (the fine mesh is 64^4), six seeded level-1 patches in
+    the central half of the velocity box (the layout of the parity tests),
+    Landau-type state, FP64: synchronous RK4 steps, against the uniform 64^4
+    step of the same fine mesh."""
+    import torch
+
+    import vp_inputs as I
+    from paper_1204_3853_amd import vp
+    n, R = (32, 32, 32, 32), 2
+    boxes = I.amr4d_boxes(0, n, R)
+    f0, gxc, gyc, gxf, gyf = I.amr4d_state(n, R, boxes, eps=0.05)
+    spec = vp.amr4d_spec(n, 4 * math.pi, 4 * math.pi, -6.0, 6.0, -1.0, R, (gxc, gyc, gxf, gyf))
+    plan = vp.Plan(spec, boxes=boxes)
+    f = torch.tensor(f0, dtype=torch.float64, device="cuda")
+    a = vp.field_of(plan, f)
+    dt = 0.01
+    for _ in range(warmup):
+        vp.rk4_step(plan, f, a, dt)
+    st, sp = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    st.record()
+    for _ in range(steps):
+        vp.rk4_step(plan, f, a, dt)
+    sp.record()
+    torch.cuda.synchronize()
+    ms = st.elapsed_time(sp) / steps
+    plan.timing_enable(True)
+    for _ in range(steps):
+        vp.rk4_step(plan, f, a, dt)
+    torch.cuda.synchronize()
+    tm = plan.timing_read()
+    plan.timing_enable(False)
+    cells = plan.state_elems
+    coarse = n[0] * n[1] * n[2] * n[3]
+    stage_us = tm["stage"][0] / tm["stage"][1] * 1e3
+    # stage launches (face chunks included): 16 state words per cell and step over 4 launches
+    bytes_launch = 16 * 8 * cells / 4
+    per_launch = {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in tm.items() if v[1]}
+    # the uniform fine mesh
+    pu = I.Problem2D(64, 64, 64, 64, eps=0.05)
+    plan_u = vp.Plan(pu)
+    fu = torch.tensor(pu.initial_state().ravel(), dtype=torch.float64, device="cuda")
+    au = vp.field_of(plan_u, fu)
+    for _ in range(warmup):
+        vp.rk4_step(plan_u, fu, au, dt)
+    torch.cuda.synchronize()
+    st.record()
+    for _ in range(steps):
+        vp.rk4_step(plan_u, fu, au, dt)
+    sp.record()
+    torch.cuda.synchronize()
+    ms_u = st.elapsed_time(sp) / steps
+    return {"workload": "2D+2V two-level: level 0 32^4, ratio 2 (fine mesh 64^4), 6 seeded patches, FP64, dt=%g" % dt,
+            "cells": cells, "coarse_cells": coarse, "fine_cells": cells - coarse,
+            "uniform_fine_cells": 64 ** 4, "cell_fraction_of_uniform": round(cells / 64 ** 4, 4),
+            "ms_per_step": round(ms, 4), "cell_updates_per_s": cells / (ms * 1e-3),
+            "uniform_64_4_ms_per_step": round(ms_u, 4), "time_fraction_of_uniform": round(ms / ms_u, 3),
+            "stage_kernel": {"avg_launch_us": round(stage_us, 2), "algorithmic_bytes_per_launch": bytes_launch,
+                             "achieved_GBs": round(bytes_launch / (stage_us * 1e-6) / 1e9, 1)},
+            "us_per_launch_by_class": per_launch}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -658,6 +725,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.amr4d_only:
+        print(json.dumps({"amr4d": amr4d_bench(steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_ratio()}), flush=True)
         return
@@ -742,6 +812,7 @@ def main():
     adj = None if args.no_adjoint else adjoint_ratio()
     amr = None if args.no_amr else amr_bench()
     fourd = None if args.no_4d else fourd_bench()
+    amr4d = None if args.no_amr4d else amr4d_bench()
     limited = None if args.no_limited else limited_bench(n)
     regrid = None if args.no_regrid else regrid_bench()
     amr_run = None if args.no_amr_run else amr_run_bench(args.amr_run_t)
@@ -774,6 +845,7 @@ def main():
         "adjoint": adj,
         "amr": amr,
         "2d2v": fourd,
+        "amr4d": amr4d,
         "limited": limited,
         "regrid": regrid,
         "amr_run": amr_run,

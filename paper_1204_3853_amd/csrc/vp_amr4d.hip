@@ -39,12 +39,13 @@ A4Args base_args(const vp_plan* p, const double* pad, const double* a)
     return A;
 }
 
-vp_status pad_launch(const vp_plan* p, const double* f, double* pad, hipStream_t stream)
+vp_status pad_launch(const vp_plan* p, const double* f, double* pad, double* scratch, hipStream_t stream)
 {
     const Amr4DPlan& M = *p->a4;
     VP_HIP(timed(p, kTOther, stream, [&] {
         return launch_a4_pad(f, M.d_patches, M.d_list, (int)M.patches.size(), (long long)M.pad_total, M.d_nb, M.lv,
-                             M.d_B, M.R, M.d_gxc, M.d_gyc, M.d_gxf, M.d_gyf, pad, stream);
+                             M.d_B, M.R, M.d_gxc, M.d_gyc, M.d_gxf, M.d_gyf, M.d_interp, M.pass_total, scratch, pad,
+                             stream);
     }));
     return VP_OK;
 }
@@ -54,7 +55,8 @@ vp_status moment(const vp_plan* p, const double* f, double* n, void* work, hipSt
     const Amr4DPlan& M = *p->a4;
     double* slots = reinterpret_cast<double*>(wp(work, M.ws_slots));
     VP_HIP(timed(p, kTMoment, stream, [&] {
-        hipError_t e = launch_a4_masked(f, M.d_mask, M.nc, slots, stream);
+        double* psum = reinterpret_cast<double*>(wp(work, M.ws_psum));
+        hipError_t e = launch_a4_masked(f, M.d_rect_ptr, M.d_rects, M.nc, psum, slots, stream);
         if (e == hipSuccess)
             e = launch_amr_rowsum(f, M.d_task_off, M.d_task_len, M.ntasks, slots + 25 * M.nc[0] * M.nc[1], stream);
         if (e == hipSuccess) e = launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.ncfg, n, stream);
@@ -204,8 +206,20 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
             for (int j = P[q].lo[1] / R; j < (P[q].lo[1] + P[q].sz[1]) / R; ++j)
                 for (int k = P[q].lo[2] / R; k < (P[q].lo[2] + P[q].sz[2]) / R; ++k)
                     for (int l = P[q].lo[3] / R; l < (P[q].lo[3] + P[q].sz[3]) / R; ++l) own[cidx(i, j, k, l)] = (int)q;
-    std::vector<unsigned char> mask((size_t)ncells0);
-    for (long long c = 0; c < ncells0; ++c) mask[c] = own[c] >= 0;
+    // per level-0 configuration column, the velocity rectangles level 1 covers in it
+    std::vector<int> rect_ptr{0};
+    std::vector<int4> rects;
+    for (int i = 0; i < n[0]; ++i)
+        for (int j = 0; j < n[1]; ++j) {
+            for (size_t q = 1; q < P.size(); ++q) {
+                const A4Patch& G = P[q];
+                if (i < G.lo[0] / R || i >= (G.lo[0] + G.sz[0]) / R || j < G.lo[1] / R || j >= (G.lo[1] + G.sz[1]) / R)
+                    continue;
+                rects.push_back(make_int4(G.lo[2] / R, (G.lo[2] + G.sz[2]) / R - 1, G.lo[3] / R,
+                                          (G.lo[3] + G.sz[3]) / R - 1));
+            }
+            rect_ptr.push_back((int)rects.size());
+        }
 
     // ---- coarse-fine faces of level 0: every side of every patch, where the
     // level-0 cell outside is not covered (velocity sides inside the box only)
@@ -345,7 +359,34 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     const std::vector<double> gxf(pb->veq[1][0], pb->veq[1][0] + M.nf[2] + 4),
         gyf(pb->veq[1][1], pb->veq[1][1] + M.nf[3] + 4);
 
+    // ---- separable interpolation passes over every level-1 patch's padded box
+    std::vector<A4Interp> ip;
+    auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    for (size_t q = 1; q < P.size(); ++q) {
+        A4Interp Q{};
+        for (int d = 0; d < 4; ++d) {
+            Q.plo[d] = P[q].lo[d] - 2;
+            Q.pn[d] = P[q].sz[d] + 4;
+            Q.clo[d] = fdiv(Q.plo[d], R) - 2;
+            Q.cn[d] = fdiv(Q.plo[d] + Q.pn[d] - 1, R) + 2 - Q.clo[d] + 1;
+        }
+        ip.push_back(Q);
+    }
+    long long acc_o = 0;
+    for (int dir = 0; dir < 3; ++dir) {
+        M.pass_total[dir] = 0;
+        for (A4Interp& Q : ip) {
+            long long n = 1;
+            for (int d = 0; d < 4; ++d) n *= d <= dir ? Q.pn[d] : Q.cn[d];
+            Q.o[dir] = acc_o;
+            acc_o += n;
+            M.pass_total[dir] += n;
+        }
+    }
+    const size_t scratch_elems = (size_t)std::max<long long>(acc_o, 1);
+
     TableArena T;
+    T.add(&M.d_interp, ip);
     T.add(&M.d_patches, P);
     T.add(&M.d_list, list);
     T.add(&M.d_nb, nb);
@@ -356,7 +397,8 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     T.add(&M.d_gxf, gxf);
     T.add(&M.d_gyf, gyf);
     T.add(&M.d_faces, faces);
-    T.add(&M.d_mask, mask);
+    T.add(&M.d_rect_ptr, rect_ptr);
+    T.add(&M.d_rects, rects);
     T.add(&M.d_task_off, task_off);
     T.add(&M.d_task_len, task_len);
     T.add(&M.d_rowptr, rowptr);
@@ -374,6 +416,7 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     T.add(&M.d_inv, inv);
     VP_HIP(T.commit(&M.d_tables));
     VP_HIP(hipMalloc(&M.d_rhs_pad, std::max<size_t>(M.pad_total, 1) * sizeof(double)));
+    VP_HIP(hipMalloc(&M.d_rhs_scratch, scratch_elems * sizeof(double)));
     VP_HIP(hipMalloc(&M.d_g, (size_t)2 * nfx * nfy * sizeof(double)));
 
     // ---- workspace: acc, two predictors, padded copies, boundary and coarse-fine fluxes, slots, n, g
@@ -383,10 +426,12 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     p->ws_fsa = o; o += sb;
     p->ws_fsb = o; o += sb;
     M.ws_pad = o; o += al256(std::max<size_t>(M.pad_total, 1) * sizeof(double));
+    M.ws_interp = o; o += al256(scratch_elems * sizeof(double));
     M.ws_ff = o; o += al256(std::max<size_t>(M.fflux, 1) * sizeof(double));
     M.ws_cf = o; o += al256(std::max<size_t>(faces.size(), 1) * sizeof(double));
     M.ws_slots = o; o += al256((size_t)(m0 + M.ntasks) * sizeof(double));
     M.ws_n = o; o += al256((size_t)nfx * nfy * sizeof(double));
+    M.ws_psum = o; o += al256((size_t)ncx * ncy * sizeof(double));
     M.ws_g = o; o += al256((size_t)2 * nfx * nfy * sizeof(double));
     p->ws_total = o;
     p->state_elems = M.total;
@@ -399,6 +444,7 @@ void a4_destroy(vp_plan* p)
     if (!M) return;
     if (M->d_tables) (void)hipFree(M->d_tables);
     if (M->d_rhs_pad) (void)hipFree(M->d_rhs_pad);
+    if (M->d_rhs_scratch) (void)hipFree(M->d_rhs_scratch);
     if (M->d_g) (void)hipFree(M->d_g);
     delete M;
     p->a4 = nullptr;
@@ -408,7 +454,7 @@ vp_status a4_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipS
 {
     const Amr4DPlan& M = *p->a4;
     const double* fd = static_cast<const double*>(f);
-    if (vp_status st = pad_launch(p, fd, M.d_rhs_pad, stream)) return st;
+    if (vp_status st = pad_launch(p, fd, M.d_rhs_pad, M.d_rhs_scratch, stream)) return st;
     A4Args A = base_args(p, M.d_rhs_pad, a);
     A.fout = static_cast<double*>(k);
     VP_HIP(timed(p, kTStage, stream, [&] { return launch_a4_stage(kRhs, A, stream); }));
@@ -452,10 +498,11 @@ vp_status a4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
     double* pad = reinterpret_cast<double*>(wp(work, M.ws_pad));
     double* ff = reinterpret_cast<double*>(wp(work, M.ws_ff));
     double* cf = reinterpret_cast<double*>(wp(work, M.ws_cf));
+    double* scr = reinterpret_cast<double*>(wp(work, M.ws_interp));
     double* out[4] = {sa, sb, sa, fd};
     const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     const double cnext[3] = {0.5 * dt, 0.5 * dt, dt};
-    if (vp_status st = pad_launch(p, fd, pad, stream)) return st;
+    if (vp_status st = pad_launch(p, fd, pad, scr, stream)) return st;
     for (int s = 0; s < 4; ++s) {
         const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
         A4Args A = base_args(p, pad, a);
@@ -473,7 +520,7 @@ vp_status a4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
             return e;
         }));
         if (s < 3) {
-            if (vp_status st = pad_launch(p, out[s], pad, stream)) return st;
+            if (vp_status st = pad_launch(p, out[s], pad, scr, stream)) return st;
             if (vp_status st = constraint(p, out[s], a, work, stream)) return st;
         }
     }

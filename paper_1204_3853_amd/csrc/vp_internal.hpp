@@ -191,6 +191,12 @@ struct A4Args {
     int first;
 };
 
+struct A4Interp {              // separable sub-cell interpolation over one level-1 patch's padded box
+    long long o[3];            // scratch offsets of its x, then y, then vx pass results
+    int plo[4], pn[4];         // padded box: first fine cell and cells per direction
+    int clo[4], cn[4];         // level-0 cells the passes read (stencils included)
+};
+
 struct A4Face {                // a level-0 face on a coarse-fine interface
     int cell[4];               // the low cell (the face is its upper face along dir)
     int dir;
@@ -199,10 +205,13 @@ struct A4Face {                // a level-0 face on a coarse-fine interface
 
 hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
                          const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
-                         const double* gyc, const double* gxf, const double* gyf, double* pad, hipStream_t stream);
+                         const double* gyc, const double* gxf, const double* gyf, const A4Interp* ip,
+                         const long long* pass_total, double* scratch, double* pad, hipStream_t stream);
 hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream);
 hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, double* cf_acc, hipStream_t stream);
-hipError_t launch_a4_masked(const double* f0, const unsigned char* mask, const int* n, double* M, hipStream_t stream);
+// masked plane sums of level 0 for the Mask reduction; S: ncx ncy doubles of scratch
+hipError_t launch_a4_masked(const double* f0, const int* rp, const int4* rects, const int* n, double* S, double* M,
+                            hipStream_t stream);
 hipError_t launch_a4_inject(double* a, int ncx, int ncy, int R, hipStream_t stream);
 hipError_t launch_a4_reflux(double* f, const long long* cell, const int* ptr, const int* code, const int* fine,
                             int nfine, const double* ff, const double* cf, const A4Face* faces, const double* hdt, double dt,
@@ -533,7 +542,11 @@ struct Amr4DPlan {
     double* d_B = nullptr;
     double *d_gxc = nullptr, *d_gyc = nullptr, *d_gxf = nullptr, *d_gyf = nullptr;
     A4Face* d_faces = nullptr;
-    unsigned char* d_mask = nullptr;
+    A4Interp* d_interp = nullptr;                    // per level-1 patch, the separable interpolation passes
+    long long pass_total[3] = {0, 0, 0};
+    double* d_rhs_scratch = nullptr;                 // pass results of vp_rhs calls
+    int* d_rect_ptr = nullptr;                       // per level-0 column: its covered velocity rectangles
+    int4* d_rects = nullptr;
     long long* d_task_off = nullptr;
     int* d_task_len = nullptr;
     int* d_rowptr = nullptr;
@@ -549,7 +562,7 @@ struct Amr4DPlan {
     double *d_Qx = nullptr, *d_Qy = nullptr, *d_inv = nullptr;   // fine configuration mesh Fourier tables
     double* d_rhs_pad = nullptr;                     // padded copies for vp_rhs, which takes no workspace
     double* d_g = nullptr;                           // Fourier coefficients of vp_poisson_periodic calls
-    size_t ws_pad = 0, ws_ff = 0, ws_cf = 0, ws_slots = 0, ws_n = 0, ws_g = 0;
+    size_t ws_pad = 0, ws_ff = 0, ws_cf = 0, ws_slots = 0, ws_n = 0, ws_g = 0, ws_interp = 0, ws_psum = 0;
 };
 
 // multi-level plan (vp_hier.hip): L levels, a ratio per level and direction

@@ -92,6 +92,9 @@ struct A4PadArgs {
     const double* B;           // b_j(s) at B[s * 5 + j + 2]
     int R;
     const double *gxc, *gyc, *gxf, *gyf;
+    const A4Interp* ip;        // per level-1 patch (list index - 1)
+    int nip;
+    double* scratch;           // pass results
     double* pad;
 };
 
@@ -101,6 +104,72 @@ __device__ __forceinline__ double coarse_at(const A4PadArgs& A, int i, int j, in
     const A4Level& L = A.lv[0];
     if (k < 0 || k >= L.n[2] || l < 0 || l >= L.n[3]) return A.gxc[k + 2] * A.gyc[l + 2];
     return A.f[(((long long)wrap4(i, L.n[0]) * L.n[1] + wrap4(j, L.n[1])) * L.n[2] + k) * L.n[3] + l];
+}
+
+// One pass of the separable sub-cell interpolation of level 0 over every
+// level-1 patch's padded box (the tensor product of section 3's
+// one-dimensional weights, x innermost as in the definition, then y, vx
+// and vy): DIR 0 reads level 0 and interpolates along x, DIR 1 along y,
+// DIR 2 along vx; the vy pass is the last step of k_a4_pad.
+template <int DIR>
+__global__ __launch_bounds__(256) void k_a4_interp(A4PadArgs A, long long total)
+{
+    const long long first = A.ip[0].o[DIR];              // the pass's results start here
+    const long long g = first + (long long)blockIdx.x * 256 + threadIdx.x;
+    if (g >= first + total) return;
+    int lo = 0, hi = A.nip - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.ip[mid].o[DIR] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const A4Interp Q = A.ip[lo];
+    // output extents: fine along x .. DIR, coarse after
+    int ext[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) ext[d] = d <= DIR ? Q.pn[d] : Q.cn[d];
+    long long r = g - Q.o[DIR];
+    int idx[4];
+    idx[3] = (int)(r % ext[3]); r /= ext[3];
+    idx[2] = (int)(r % ext[2]); r /= ext[2];
+    idx[1] = (int)(r % ext[1]); r /= ext[1];
+    idx[0] = (int)r;
+    const int R = A.R;
+    const int F = Q.plo[DIR] + idx[DIR];
+    const int c = (F >= 0 ? F : F - R + 1) / R;
+    const double* b = A.B + (F - c * R) * 5;
+    double acc = 0.0;
+    if (DIR == 0) {
+        // velocity cells of the padded box beyond the velocity ghosts (only
+        // read for fine cells outside the velocity box, which take the fine
+        // equilibrium instead) use the nearest ghost factor
+        const A4Level& L = A.lv[0];
+        const int k = Q.clo[2] + idx[2], l = Q.clo[3] + idx[3];
+        const bool vin = k >= 0 && k < L.n[2] && l >= 0 && l < L.n[3];
+        const double geq = A.gxc[min(max(k + 2, 0), L.n[2] + 3)] * A.gyc[min(max(l + 2, 0), L.n[3] + 3)];
+        const int j = wrap4(Q.clo[1] + idx[1], L.n[1]);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            const double cv = vin ? A.f[(((long long)wrap4(c + t - 2, L.n[0]) * L.n[1] + j) * L.n[2] + (vin ? k : 0)) *
+                                            L.n[3] + (vin ? l : 0)]
+                                  : geq;
+            acc += b[t] * cv;
+        }
+    } else {
+        // the previous pass: extent coarse along DIR
+        int pe[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) pe[d] = d < DIR ? Q.pn[d] : Q.cn[d];
+        const double* in = A.scratch + Q.o[DIR - 1];
+        const long long s3 = 1, s2 = pe[3], s1 = (long long)pe[2] * pe[3], s0 = (long long)pe[1] * pe[2] * pe[3];
+        const long long sd = DIR == 1 ? s1 : s2;
+        long long base = idx[0] * s0 + idx[3] * s3;
+        base += DIR == 1 ? idx[2] * s2 : idx[1] * s1;
+        base += (long long)(c - 2 - Q.clo[DIR]) * sd;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) acc += b[t] * in[base + t * sd];
+    }
+    A.scratch[g] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_a4_pad(A4PadArgs A, long long total)
@@ -150,29 +219,18 @@ __global__ __launch_bounds__(256) void k_a4_pad(A4PadArgs A, long long total)
                 }
             }
             if (!held) {
+                // the last (vy) pass of the separable interpolation over the
+                // results of the x, y and vx passes
+                const A4Interp Q = A.ip[A.list[lo] - 1];
                 const int R = A.R;
-                const int ci = (I >= 0 ? I : I - R + 1) / R, cj = (J >= 0 ? J : J - R + 1) / R;
-                const int ck = K / R, cl = Lv / R;
-                const double* bi = A.B + (I - ci * R) * 5;
-                const double* bj = A.B + (J - cj * R) * 5;
-                const double* bk = A.B + (K - ck * R) * 5;
+                const int cl = Lv / R;
                 const double* bl = A.B + (Lv - cl * R) * 5;
+                const int X = i + 2, Y = j + 2, Kk = k + 2;
+                const double* t3 = A.scratch + Q.o[2] +
+                                   (((long long)X * Q.pn[1] + Y) * Q.pn[2] + Kk) * Q.cn[3] + (cl - 2 - Q.clo[3]);
                 double acc = 0.0;
-                for (int d = 0; d < 5; ++d) {
-                    double av = 0.0;
-                    for (int e = 0; e < 5; ++e) {
-                        double ay = 0.0;
-                        for (int b = 0; b < 5; ++b) {
-                            double ax = 0.0;
 #pragma unroll
-                            for (int aa = 0; aa < 5; ++aa)
-                                ax += bi[aa] * coarse_at(A, ci + aa - 2, cj + b - 2, ck + e - 2, cl + d - 2);
-                            ay += bj[b] * ax;
-                        }
-                        av += bk[e] * ay;
-                    }
-                    acc += bl[d] * av;
-                }
+                for (int d = 0; d < 5; ++d) acc += bl[d] * t3[d];
                 v = acc;
             }
         }
@@ -249,12 +307,28 @@ __global__ __launch_bounds__(256) void k_a4_faces(A4Args A, const A4Face* __rest
     else cf[q] += A.c_flux * G;
 }
 
+// S[c] = sum over the velocity plane of level-0 configuration column c, one wave per column
+__global__ __launch_bounds__(256) void k_a4_planesum(const double* __restrict__ f0, int ncol, int plane,
+                                                    double* __restrict__ S)
+{
+    const int c = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= ncol) return;
+    const double* src = f0 + (long long)c * plane;
+    double acc = 0.0;
+    for (int q = lane; q < plane; q += 64) acc += src[q];
+    acc = wave_sum(acc);
+    if (lane == 0) S[c] = acc;
+}
+
 // M[((i ncy + j) * 25 + (a+2) * 5 + (b+2)] = sum over the velocity plane of
-// level-0 column (i + a, j + b), masked by the coverage of column (i, j);
-// one wave per sum
-__global__ __launch_bounds__(256) void k_a4_masked(const double* __restrict__ f0,
-                                                  const unsigned char* __restrict__ mask, int ncx, int ncy,
-                                                  int plane, double* __restrict__ M)
+// level-0 column (i + a, j + b) masked by the coverage of column (i, j):
+// the plane sum less the cells of the velocity rectangles level 1 covers in
+// column (i, j) (rects[rp[c] .. rp[c+1]), k0 k1 l0 l1 inclusive); one wave
+// per sum
+__global__ __launch_bounds__(256) void k_a4_masked(const double* __restrict__ f0, const double* __restrict__ S,
+                                                  const int* __restrict__ rp, const int4* __restrict__ rects,
+                                                  int ncx, int ncy, int nvy, int plane, double* __restrict__ M)
 {
     const int task = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -262,12 +336,16 @@ __global__ __launch_bounds__(256) void k_a4_masked(const double* __restrict__ f0
     const int cell = task / 25, s = task - cell * 25;
     const int i = cell / ncy, j = cell - (cell / ncy) * ncy;
     const int a = s / 5 - 2, b = s % 5 - 2;
-    const double* src = f0 + ((long long)wrap4(i + a, ncx) * ncy + wrap4(j + b, ncy)) * plane;
-    const unsigned char* m = mask + (long long)cell * plane;
-    double acc = 0.0;
-    for (int q = lane; q < plane; q += 64) acc += m[q] ? 0.0 : src[q];
-    acc = wave_sum(acc);
-    if (lane == 0) M[task] = acc;
+    const int col = wrap4(i + a, ncx) * ncy + wrap4(j + b, ncy);
+    const double* src = f0 + (long long)col * plane;
+    double cov = 0.0;
+    for (int e = rp[cell]; e < rp[cell + 1]; ++e) {
+        const int4 r = rects[e];
+        const int w = r.w - r.z + 1, cnt = (r.y - r.x + 1) * w;
+        for (int q = lane; q < cnt; q += 64) cov += src[(r.x + q / w) * nvy + r.z + q % w];
+    }
+    cov = wave_sum(cov);
+    if (lane == 0) M[task] = S[col] - cov;
 }
 
 // the coarse acceleration: the mean of the R x R fine values of each component
@@ -330,7 +408,8 @@ __global__ __launch_bounds__(256) void k_a4_average(double* __restrict__ f, cons
 
 hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
                          const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
-                         const double* gyc, const double* gxf, const double* gyf, double* pad, hipStream_t stream)
+                         const double* gyc, const double* gxf, const double* gyf, const A4Interp* ip,
+                         const long long* pass_total, double* scratch, double* pad, hipStream_t stream)
 {
     if (total <= 0) return hipSuccess;
     A4PadArgs A{};
@@ -347,7 +426,18 @@ hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* lis
     A.gyc = gyc;
     A.gxf = gxf;
     A.gyf = gyf;
+    A.ip = ip;
+    A.nip = npatch - 1;
+    A.scratch = scratch;
     A.pad = pad;
+    if (A.nip > 0) {
+        hipLaunchKernelGGL(k_a4_interp<0>, dim3((unsigned)((pass_total[0] + 255) / 256)), dim3(256), 0, stream, A,
+                           pass_total[0]);
+        hipLaunchKernelGGL(k_a4_interp<1>, dim3((unsigned)((pass_total[1] + 255) / 256)), dim3(256), 0, stream, A,
+                           pass_total[1]);
+        hipLaunchKernelGGL(k_a4_interp<2>, dim3((unsigned)((pass_total[2] + 255) / 256)), dim3(256), 0, stream, A,
+                           pass_total[2]);
+    }
     hipLaunchKernelGGL(k_a4_pad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, A, total);
     return hipGetLastError();
 }
@@ -372,10 +462,13 @@ hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, dou
     return hipGetLastError();
 }
 
-hipError_t launch_a4_masked(const double* f0, const unsigned char* mask, const int* n, double* M, hipStream_t stream)
+hipError_t launch_a4_masked(const double* f0, const int* rp, const int4* rects, const int* n, double* S, double* M,
+                            hipStream_t stream)
 {
-    const int tasks = 25 * n[0] * n[1];
-    hipLaunchKernelGGL(k_a4_masked, dim3((tasks + 3) / 4), dim3(256), 0, stream, f0, mask, n[0], n[1], n[2] * n[3], M);
+    const int ncol = n[0] * n[1], tasks = 25 * ncol;
+    hipLaunchKernelGGL(k_a4_planesum, dim3((ncol + 3) / 4), dim3(256), 0, stream, f0, ncol, n[2] * n[3], S);
+    hipLaunchKernelGGL(k_a4_masked, dim3((tasks + 3) / 4), dim3(256), 0, stream, f0, S, rp, rects, n[0], n[1], n[3],
+                       n[2] * n[3], M);
     return hipGetLastError();
 }
 
