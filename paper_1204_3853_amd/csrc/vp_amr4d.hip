@@ -148,6 +148,10 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     }
     size_t off = 0, pad = 0, foff = 0;
     for (A4Patch& q : P) {
+        for (int d = 0; d < 4; ++d) {
+            q.isz[d] = 1.0 / q.sz[d];
+            q.ipz[d] = 1.0 / (q.sz[d] + 4);
+        }
         const long long n0 = q.sz[0], n1 = q.sz[1], n2 = q.sz[2], n3 = q.sz[3];
         q.off = (long long)off;
         q.pad = (long long)pad;
@@ -369,6 +373,8 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
             Q.pn[d] = P[q].sz[d] + 4;
             Q.clo[d] = fdiv(Q.plo[d], R) - 2;
             Q.cn[d] = fdiv(Q.plo[d] + Q.pn[d] - 1, R) + 2 - Q.clo[d] + 1;
+            Q.ipn[d] = 1.0 / Q.pn[d];
+            Q.icn[d] = 1.0 / Q.cn[d];
         }
         ip.push_back(Q);
     }

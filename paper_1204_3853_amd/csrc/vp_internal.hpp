@@ -166,6 +166,7 @@ struct A4Patch {               // level 0 (patch 0) or a level-1 patch of a two-
                                // vx lo/hi [nx][ny][nvy], vy lo/hi [nx][ny][nvx]
     int lo[4], sz[4];          // first cell (level index space) and cells per direction
     int lev, nb0, nb1, pad_;   // level; neighbour list range (patches holding some of its ghost cells)
+    double isz[4], ipz[4];     // 1 / sz and 1 / (sz + 4), for index decoding
 };
 
 struct A4Level {
@@ -195,6 +196,7 @@ struct A4Interp {              // separable sub-cell interpolation over one leve
     long long o[3];            // scratch offsets of its x, then y, then vx pass results
     int plo[4], pn[4];         // padded box: first fine cell and cells per direction
     int clo[4], cn[4];         // level-0 cells the passes read (stencils included)
+    double ipn[4], icn[4];     // 1 / pn and 1 / cn, for index decoding
 };
 
 struct A4Face {                // a level-0 face on a coarse-fine interface

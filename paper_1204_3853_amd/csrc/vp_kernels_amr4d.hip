@@ -42,14 +42,46 @@ __device__ __forceinline__ A4View view_of(const double* pad, const A4Patch& P)
     return v;
 }
 
-__device__ __forceinline__ double a_at(const double* a, const A4Level& L, int comp, int I, int J)
+// r % d with r = r / d for 0 <= r < 2^31, from a double reciprocal of d
+// (the quotient estimate is off by at most one, which the remainder fixes)
+__device__ __forceinline__ int divmod_rcp(int& r, int d, double inv)
 {
-    return a[L.a_off + comp * L.n[0] * L.n[1] + wrap4(I, L.n[0]) * L.n[1] + wrap4(J, L.n[1])];
+    int q = (int)((double)r * inv);
+    int m = r - q * d;
+    if (m < 0) { --q; m += d; }
+    else if (m >= d) { ++q; m -= d; }
+    r = q;
+    return m;
+}
+
+// i in [-n, 2n) wrapped into [0, n)
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// the accelerations a velocity-face flux of configuration cell (I, J) needs:
+// a at the cell and the differences of its x and y neighbours, per component
+struct A4Acc {
+    double c[2], dx[2], dy[2];
+};
+
+__device__ __forceinline__ A4Acc acc_at(const double* a, const A4Level& L, int I, int J)
+{
+    const int n0 = L.n[0], n1 = L.n[1];
+    const int i = wrap1(I, n0), j = wrap1(J, n1);
+    const int ip = wrap1(i + 1, n0), im = wrap1(i - 1, n0), jp = wrap1(j + 1, n1), jm = wrap1(j - 1, n1);
+    A4Acc r;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double* ac = a + L.a_off + c * n0 * n1;
+        r.c[c] = ac[i * n1 + j];
+        r.dx[c] = ac[ip * n1 + j] - ac[im * n1 + j];
+        r.dy[c] = ac[i * n1 + jp] - ac[i * n1 + jm];
+    }
+    return r;
 }
 
 // flux through the upper face along `dir` of cell (i, j, k, l) of a patch
 // (local indices; the face's other cells come from the padded copy)
-__device__ double face_flux(const A4View& U, const A4Patch& P, const A4Level& L, const double* a, int dir, int i,
+__device__ double face_flux(const A4View& U, const A4Patch& P, const A4Level& L, const A4Acc& ac4, int dir, int i,
                             int j, int k, int l)
 {
     if (dir == 0) {
@@ -70,11 +102,8 @@ __device__ double face_flux(const A4View& U, const A4Patch& P, const A4Level& L,
         const double vb = L.v_lo + ((double)(P.lo[3] + l) + 0.5) * L.h[3];
         return vb * fc + L.h[3] / 24.0 * (fu - fd);
     }
-    const int I = P.lo[0] + i, J = P.lo[1] + j;
     const int c = dir - 2;
-    const double ac = a_at(a, L, c, I, J);
-    const double dax = a_at(a, L, c, I + 1, J) - a_at(a, L, c, I - 1, J);
-    const double day = a_at(a, L, c, I, J + 1) - a_at(a, L, c, I, J - 1);
+    const double ac = ac4.c[c], dax = ac4.dx[c], day = ac4.dy[c];
     auto fv = [&](int ii, int jj) {
         return dir == 2 ? face4<double>(U(ii, jj, k - 1, l), U(ii, jj, k, l), U(ii, jj, k + 1, l), U(ii, jj, k + 2, l))
                         : face4<double>(U(ii, jj, k, l - 1), U(ii, jj, k, l), U(ii, jj, k, l + 1), U(ii, jj, k, l + 2));
@@ -126,14 +155,18 @@ __global__ __launch_bounds__(256) void k_a4_interp(A4PadArgs A, long long total)
     const A4Interp Q = A.ip[lo];
     // output extents: fine along x .. DIR, coarse after
     int ext[4];
+    double iext[4];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) ext[d] = d <= DIR ? Q.pn[d] : Q.cn[d];
-    long long r = g - Q.o[DIR];
+    for (int d = 0; d < 4; ++d) {
+        ext[d] = d <= DIR ? Q.pn[d] : Q.cn[d];
+        iext[d] = d <= DIR ? Q.ipn[d] : Q.icn[d];
+    }
+    int r = (int)(g - Q.o[DIR]);
     int idx[4];
-    idx[3] = (int)(r % ext[3]); r /= ext[3];
-    idx[2] = (int)(r % ext[2]); r /= ext[2];
-    idx[1] = (int)(r % ext[1]); r /= ext[1];
-    idx[0] = (int)r;
+    idx[3] = divmod_rcp(r, ext[3], iext[3]);
+    idx[2] = divmod_rcp(r, ext[2], iext[2]);
+    idx[1] = divmod_rcp(r, ext[1], iext[1]);
+    idx[0] = r;
     const int R = A.R;
     const int F = Q.plo[DIR] + idx[DIR];
     const int c = (F >= 0 ? F : F - R + 1) / R;
@@ -184,12 +217,11 @@ __global__ __launch_bounds__(256) void k_a4_pad(A4PadArgs A, long long total)
         else hi = mid - 1;
     }
     const A4Patch P = A.patches[A.list[lo]];
-    long long r = g - P.pad;
-    const int g3 = P.sz[3] + 4, g2 = P.sz[2] + 4, g1 = P.sz[1] + 4;
-    const int l = (int)(r % g3) - 2; r /= g3;
-    const int k = (int)(r % g2) - 2; r /= g2;
-    const int j = (int)(r % g1) - 2; r /= g1;
-    const int i = (int)r - 2;
+    int r = (int)(g - P.pad);
+    const int l = divmod_rcp(r, P.sz[3] + 4, P.ipz[3]) - 2;
+    const int k = divmod_rcp(r, P.sz[2] + 4, P.ipz[2]) - 2;
+    const int j = divmod_rcp(r, P.sz[1] + 4, P.ipz[1]) - 2;
+    const int i = r - 2;
     const bool ox = i < 0 || i >= P.sz[0], oy = j < 0 || j >= P.sz[1];
     const bool ok = k < 0 || k >= P.sz[2], ol = l < 0 || l >= P.sz[3];
     const int nout = (int)ox + (int)oy + (int)ok + (int)ol;
@@ -252,17 +284,18 @@ __global__ __launch_bounds__(256) void k_a4_stage(A4Args A)
     const long long c = (long long)A.tiles[2 * t + 1] + threadIdx.x;
     const long long ncell = (long long)P.sz[0] * P.sz[1] * P.sz[2] * P.sz[3];
     if (c >= ncell) return;
-    long long r = c;
-    const int l = (int)(r % P.sz[3]); r /= P.sz[3];
-    const int k = (int)(r % P.sz[2]); r /= P.sz[2];
-    const int j = (int)(r % P.sz[1]); r /= P.sz[1];
-    const int i = (int)r;
+    int r = (int)c;
+    const int l = divmod_rcp(r, P.sz[3], P.isz[3]);
+    const int k = divmod_rcp(r, P.sz[2], P.isz[2]);
+    const int j = divmod_rcp(r, P.sz[1], P.isz[1]);
+    const int i = r;
     const A4Level& L = A.lv[P.lev];
     const A4View U = view_of(A.pad, P);
-    const double gx1 = face_flux(U, P, L, A.a, 0, i, j, k, l), gx0 = face_flux(U, P, L, A.a, 0, i - 1, j, k, l);
-    const double gy1 = face_flux(U, P, L, A.a, 1, i, j, k, l), gy0 = face_flux(U, P, L, A.a, 1, i, j - 1, k, l);
-    const double gk1 = face_flux(U, P, L, A.a, 2, i, j, k, l), gk0 = face_flux(U, P, L, A.a, 2, i, j, k - 1, l);
-    const double gl1 = face_flux(U, P, L, A.a, 3, i, j, k, l), gl0 = face_flux(U, P, L, A.a, 3, i, j, k, l - 1);
+    const A4Acc ac4 = acc_at(A.a, L, P.lo[0] + i, P.lo[1] + j);
+    const double gx1 = face_flux(U, P, L, ac4, 0, i, j, k, l), gx0 = face_flux(U, P, L, ac4, 0, i - 1, j, k, l);
+    const double gy1 = face_flux(U, P, L, ac4, 1, i, j, k, l), gy0 = face_flux(U, P, L, ac4, 1, i, j - 1, k, l);
+    const double gk1 = face_flux(U, P, L, ac4, 2, i, j, k, l), gk0 = face_flux(U, P, L, ac4, 2, i, j, k - 1, l);
+    const double gl1 = face_flux(U, P, L, ac4, 3, i, j, k, l), gl0 = face_flux(U, P, L, ac4, 3, i, j, k, l - 1);
     const double kk = -(gx1 - gx0) * L.hi[0] - (gy1 - gy0) * L.hi[1] - (gk1 - gk0) * L.hi[2] - (gl1 - gl0) * L.hi[3];
     if (KIND != kRhs && A.ff_acc && A.c_flux != 0.0 && P.lev == 1) {
         const int n0 = P.sz[0], n1 = P.sz[1], n2 = P.sz[2], n3 = P.sz[3];
@@ -302,7 +335,8 @@ __global__ __launch_bounds__(256) void k_a4_faces(A4Args A, const A4Face* __rest
     if (q >= nfaces) return;
     const A4Face F = faces[q];
     const A4Patch P = A.patches[0];
-    const double G = face_flux(view_of(A.pad, P), P, A.lv[0], A.a, F.dir, F.cell[0], F.cell[1], F.cell[2], F.cell[3]);
+    const A4Acc ac4 = acc_at(A.a, A.lv[0], F.cell[0], F.cell[1]);
+    const double G = face_flux(view_of(A.pad, P), P, A.lv[0], ac4, F.dir, F.cell[0], F.cell[1], F.cell[2], F.cell[3]);
     if (A.first) cf[q] = A.c_flux * G;
     else cf[q] += A.c_flux * G;
 }
