@@ -282,7 +282,13 @@ def amr_bench(steps=100, warmup=3):
         t = plan.timing_read()["moment"]
         plan.timing_enable(False)
         red[name] = round(t[0] / t[1] * 1e3, 2)
-    plan.set_reduction(vp.REDUCE_SUBPATCH)
+    # the step with each reduction: the default takes the predictors' moments
+    # from the stage kernels' row sums
+    ms_by_reduction = {}
+    for name, alg in (("sub_patch", vp.REDUCE_SUBPATCH), ("mask", vp.REDUCE_MASK), ("fused", vp.REDUCE_FUSED)):
+        plan.set_reduction(alg)
+        ms_by_reduction[name] = round(timed_steps(steps), 4)
+    plan.set_reduction(vp.REDUCE_FUSED)
 
     # limited face averages on both levels (section 2, eq. limitedFace)
     plan.set_face_scheme(vp.FACE_LIMITED)
@@ -309,7 +315,8 @@ def amr_bench(steps=100, warmup=3):
                              "achieved_GBs": round(bytes_launch / (stage_us * 1e-6) / 1e9, 1)},
             "us_per_launch_by_class": per_launch,
             "reduction_us": {"sub_patch": red["sub_patch"], "mask": red["mask"],
-                             "sub_patch_over_mask": round(red["sub_patch"] / red["mask"], 3)}}
+                             "sub_patch_over_mask": round(red["sub_patch"] / red["mask"], 3)},
+            "ms_per_step_by_reduction": ms_by_reduction}
 
 
 def subcycle_bench(steps=40, warmup=3, cfl=0.5):

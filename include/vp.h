@@ -204,19 +204,32 @@ vp_status vp_face_scheme_set(vp_plan* plan, int32_t scheme);
 
 /*
  * Reduction algorithm of a two-level plan (section 3):
- *   VP_REDUCE_SUBPATCH  Sub-Patch reduction (Alg. spreduce, default): the
- *                       uncovered coarse region is split into rectangles
- *                       (Alg. subdiv), each grown by two columns in x,
- *                       summed over its velocity range and refined in x
+ *   VP_REDUCE_SUBPATCH  Sub-Patch reduction (Alg. spreduce): the uncovered
+ *                       coarse region is split into rectangles (Alg.
+ *                       subdiv), each grown by two columns in x, summed
+ *                       over its velocity range and refined in x
  *   VP_REDUCE_MASK      Mask reduction (Alg. mreduce): every coarse row is
  *                       refined in x, masked by the coverage of the target
  *                       column and summed over velocity
- * Both give the same n up to rounding; they differ in cost.  No effect on
+ *   VP_REDUCE_FUSED     the Mask reduction with its row sums formed by the
+ *                       stage kernels (default): inside vp_rk4_step the
+ *                       stages that produce a predictor also write the
+ *                       velocity sums of its coarse and fine rows per tile
+ *                       strip, and one kernel forms n from them (the masked
+ *                       sum of a coarse row is its total less the cells
+ *                       level 1 covers in the target column).  The field
+ *                       after the end-of-step synchronisation (which changes
+ *                       coarse cells next to coarse-fine faces), subcycled
+ *                       steps and vp_reduce_moment compute n as
+ *                       VP_REDUCE_SUBPATCH does (the cheaper of the two
+ *                       without the stage kernels' sums).
+ * All give the same n up to rounding; they differ in cost.  No effect on
  * single-level plans.  Not safe to call while calls on the plan are being
  * enqueued.
  */
 #define VP_REDUCE_SUBPATCH 0
 #define VP_REDUCE_MASK 1
+#define VP_REDUCE_FUSED 2
 vp_status vp_reduction_set(vp_plan* plan, int32_t algorithm);
 
 /*

@@ -83,6 +83,34 @@ void build_tiles(AmrPlan& A)
     A.ntiles = (int)A.tiles.size();
 }
 
+// the fine strip partials of each coarse column's R fine cells, for the
+// Mask reduction from the stage kernel's row sums: fine cell by fine cell,
+// patch by patch (patch order), strip by strip (the tiles' strips)
+hipError_t upload_fused_lists(AmrPlan& A)
+{
+    const int tv = A.nt * A.w;
+    std::vector<int> ptr{0};
+    std::vector<int2> ent;
+    for (int i = 0; i < A.ncx; ++i) {
+        for (int s = 0; s < A.R; ++s) {
+            const int I = i * A.R + s;
+            for (const AmrPatch& P : A.patches) {
+                if (I < P.gx0 || I >= P.gx0 + P.nx) continue;
+                const int ns = (P.nv + tv - 1) / tv;
+                for (int b = 0; b < ns; ++b)
+                    ent.push_back(make_int2((int)(P.fpart + (long long)b * P.nx + (I - P.gx0)), s));
+            }
+        }
+        ptr.push_back((int)ent.size());
+    }
+    if (A.d_fz) (void)hipFree(A.d_fz);
+    A.d_fz = nullptr;
+    TableArena T;
+    T.add(&A.d_fz_ptr, ptr);
+    T.add(&A.d_fz_entry, ent);
+    return T.commit(&A.d_fz);
+}
+
 AmrArgs stage_args(const vp_plan* p, const void* fs, const void* fn, void* acc, void* fout, const double* a,
                    double c_acc, double c_next, double c_flux, int first, void* work)
 {
@@ -173,14 +201,43 @@ hipError_t reduce_launch(const AmrPlan& M, const double* f, double* n, void* wor
     return launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.nfx, n, stream);
 }
 
+// the Mask reduction of the stage state f from the strip partials the
+// stage kernel wrote for it
+hipError_t reduce_fused_launch(const AmrPlan& M, const double* f, double* n, void* work, hipStream_t stream)
+{
+    AmrMaskFusedArgs R{};
+    R.f = f;
+    R.part_c = reinterpret_cast<const double*>(wsp(work, M.ws_pc));
+    R.part_f = reinterpret_cast<const double*>(wsp(work, M.ws_pf));
+    R.patches = M.d_patches;
+    R.cov_ptr = M.d_covc_ptr;
+    R.cov_j = M.d_covc_j;
+    R.fz_ptr = M.d_fz_ptr;
+    R.fz_entry = M.d_fz_entry;
+    R.B = M.d_B;
+    R.ncx = M.ncx;
+    R.ncv = M.ncv;
+    R.nstrip = M.nstrip_c;
+    R.R = M.R;
+    R.tv = M.nt * M.w;
+    R.dvc = M.dvc;
+    R.dvf = M.dvf;
+    R.n = n;
+    return launch_amr_mask_fused(R, stream);
+}
+
 // reduction -> Poisson on the finest configuration mesh -> injection (the
-// Poisson block also injects the field onto both levels)
-vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, hipStream_t stream)
+// Poisson block also injects the field onto both levels); partials: the
+// stage kernel that wrote f also wrote its strip partials
+vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, hipStream_t stream,
+                     bool partials = false)
 {
     const AmrPlan& M = *p->amr;
     double* n = reinterpret_cast<double*>(wsp(work, M.ws_n));
     double* E = reinterpret_cast<double*>(wsp(work, M.ws_E));
-    VP_HIP(timed(p, kTMoment, stream, [&] { return reduce_launch(M, f, n, work, stream); }));
+    VP_HIP(timed(p, kTMoment, stream, [&] {
+        return partials ? reduce_fused_launch(M, f, n, work, stream) : reduce_launch(M, f, n, work, stream);
+    }));
     if (M.nfx >= kFieldSplitMin) {
         // the split solve over many blocks; its last kernel also injects
         SpeciesMoments m{};
@@ -229,6 +286,7 @@ vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx)
     M.tx = tx;
     build_tiles(M);
     VP_HIP(upload(&M.d_tiles, M.tiles));
+    VP_HIP(upload_fused_lists(M));
     return VP_OK;
 }
 
@@ -275,7 +333,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     }
 
     // ---- patches and state layout
-    size_t off = (size_t)M->ncx * M->ncv, foff = 0;
+    size_t off = (size_t)M->ncx * M->ncv, foff = 0, fpart = 0;
     for (const Box& B : bx) {
         AmrPatch P{};
         P.off = (long long)off;
@@ -284,8 +342,10 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
         P.gv0 = B.vlo;
         P.nx = B.xhi - B.xlo + 1;
         P.nv = B.vhi - B.vlo + 1;
+        P.fpart = (long long)fpart;
         off += (size_t)P.nx * P.nv;
         foff += 2 * (size_t)(P.nx + P.nv);
+        fpart += (size_t)((P.nv + kMinStripCells - 1) / kMinStripCells) * P.nx;
         M->patches.push_back(P);
     }
     M->total = off;
@@ -448,6 +508,15 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
         rowptr_m.push_back((int)idx_m.size());
     }
 
+    // ---- the Mask reduction from strip partials: each coarse column's
+    // covered cells
+    std::vector<int> covc_ptr{0}, covc_j;
+    for (int i = 0; i < ncx; ++i) {
+        for (int j = 0; j < ncv; ++j)
+            if (mask[(size_t)i * ncv + j]) covc_j.push_back(j);
+        covc_ptr.push_back((int)covc_j.size());
+    }
+
     // ---- device tables
     M->w = (M->ncv % 2 == 0 && std::all_of(M->patches.begin(), M->patches.end(),
                                            [](const AmrPatch& P) { return P.nv % 2 == 0; })) ? 2 : 1;
@@ -455,6 +524,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->tx = 8;
     build_tiles(*M);
     VP_HIP(upload(&M->d_tiles, M->tiles));
+    VP_HIP(upload_fused_lists(*M));
     TableArena T;
     T.add(&M->d_patches, M->patches);
     T.add(&M->d_faces, M->faces);
@@ -475,6 +545,8 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     T.add(&M->d_rowptr_m, rowptr_m);
     T.add(&M->d_idx_m, idx_m);
     T.add(&M->d_w_m, w_m);
+    T.add(&M->d_covc_ptr, covc_ptr);
+    T.add(&M->d_covc_j, covc_j);
     const std::vector<double> green_c = poisson_green_table(ncx);     // add() keeps a pointer until commit()
     T.add(&M->d_green_c, green_c);
     VP_HIP(T.commit(&M->d_tables));
@@ -489,6 +561,8 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->ws_ff = o; o += align256(std::max<size_t>(M->fflux, 1) * sizeof(double));
     M->ws_slots = o; o += align256(std::max(M->ntasks, 1) * sizeof(double));
     M->ws_slots_m = o; o += align256((size_t)(5 * ncx + (M->ntasks - M->fine_task0)) * sizeof(double));
+    M->ws_pc = o; o += align256((size_t)((ncv + kMinStripCells - 1) / kMinStripCells) * ncx * sizeof(double));
+    M->ws_pf = o; o += align256(std::max<size_t>(fpart, 1) * sizeof(double));
     M->ws_n = o; o += align256((size_t)M->nfx * sizeof(double));
     M->ws_E = o; o += align256((size_t)M->nfx * sizeof(double));
     M->ws_fld = o; o += align256(((size_t)M->nfx + 4 * ((size_t)M->nfx / kFieldChunk + 1) + 64) * sizeof(double));
@@ -506,6 +580,7 @@ void amr_destroy(vp_plan* p)
     if (!M) return;
     if (M->d_tables) (void)hipFree(M->d_tables);
     if (M->d_tiles) (void)hipFree(M->d_tiles);
+    if (M->d_fz) (void)hipFree(M->d_fz);
     delete M;
     p->amr = nullptr;
 }
@@ -517,12 +592,17 @@ vp_status amr_rhs(const vp_plan* p, const void* f, const double* a, void* k, hip
     return VP_OK;
 }
 
-vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream)
+vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream, bool partials)
 {
     const AmrPlan& M = *p->amr;
-    VP_HIP(timed(p, kTMoment, stream, [&] { return reduce_launch(M, static_cast<const double*>(f), n, work, stream); }));
+    const double* fd = static_cast<const double*>(f);
+    VP_HIP(timed(p, kTMoment, stream, [&] {
+        return partials ? reduce_fused_launch(M, fd, n, work, stream) : reduce_launch(M, fd, n, work, stream);
+    }));
     return VP_OK;
 }
+
+bool amr_stage_partials(const vp_plan* p, int s) { return s < 3 && p->amr->reduce_mode == VP_REDUCE_FUSED; }
 
 vp_status amr_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream)
 {
@@ -537,7 +617,8 @@ void* amr_stage_output(const vp_plan* p, int s, void* f, void* work)
     return out[s];
 }
 
-vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt, void* work, hipStream_t stream)
+vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt, void* work, hipStream_t stream,
+                    bool partials)
 {
     void* acc = wsp(work, p->ws_acc);
     const void* in[4] = {f, amr_stage_output(p, 0, f, work), amr_stage_output(p, 1, f, work),
@@ -547,6 +628,11 @@ vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt
     const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
     AmrArgs A = stage_args(p, in[s], f, acc, amr_stage_output(p, s, f, work), a, dt * b[s], s < 3 ? cnext[s] : 0.0,
                            b[s], s == 0, work);
+    if (partials) {
+        const AmrPlan& M = *p->amr;
+        A.coarse.part = reinterpret_cast<double*>(wsp(work, M.ws_pc));
+        A.fpart = reinterpret_cast<double*>(wsp(work, M.ws_pf));
+    }
     VP_HIP(timed(p, kTStage, stream, [&] { return launch_stage_all(p, kind, A, stream); }));
     return VP_OK;
 }
@@ -554,10 +640,11 @@ vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt
 vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
 {
     for (int s = 0; s < 4; ++s) {
-        if (vp_status st = amr_stage(p, s, f, a, dt, work, stream)) return st;
+        const bool partials = amr_stage_partials(p, s);
+        if (vp_status st = amr_stage(p, s, f, a, dt, work, stream, partials)) return st;
         if (s < 3)
             if (vp_status st = constraint(p, static_cast<const double*>(amr_stage_output(p, s, f, work)), a, work,
-                                          stream))
+                                          stream, partials))
                 return st;
     }
     if (vp_status st = amr_end_sync(p, f, dt, work, stream)) return st;

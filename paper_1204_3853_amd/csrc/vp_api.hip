@@ -509,13 +509,13 @@ vp_status vp_face_scheme_set(vp_plan* p, int32_t scheme)
 vp_status vp_reduction_set(vp_plan* p, int32_t algorithm)
 {
     if (vp_status s = check_plan(p)) return s;
-    if (algorithm != VP_REDUCE_SUBPATCH && algorithm != VP_REDUCE_MASK)
+    if (algorithm != VP_REDUCE_SUBPATCH && algorithm != VP_REDUCE_MASK && algorithm != VP_REDUCE_FUSED)
         return fail(VP_EINVAL, "vp_reduction_set: unknown algorithm");
-    if (p->amr) p->amr->reduce_mode = algorithm;
     if (p->hier && algorithm != VP_REDUCE_SUBPATCH)
         return fail(VP_ENOTSUP, "vp_reduction_set: multi-level plans use the Sub-Patch reduction");
     if (p->a4 && algorithm != VP_REDUCE_MASK)
         return fail(VP_ENOTSUP, "vp_reduction_set: two-level 2D+2V plans use the Mask reduction");
+    if (p->amr) p->amr->reduce_mode = algorithm;
     return VP_OK;
 }
 

@@ -38,6 +38,7 @@ struct StageShape {
 };
 
 constexpr int kMaxTx = 128;          // bound on rows per segment (LDS moment buffer)
+constexpr int kMinStripCells = 64;   // the narrowest velocity strip of a two-level tile (64 threads x 1 cell)
 constexpr int kPoissonThreads = 256;
 constexpr int kMaxPoisson1D = 8192;  // configuration cells handled by the one-block solver
 constexpr int kGreenTaps = 16;       // taps of the truncated Green's function: r^17 ~ 3.6e-20
@@ -120,6 +121,8 @@ struct AmrPatch {              // one level-1 patch
     int gx0, gv0;              // level-1 global index of its cell (0, 0)
     int nx, nv;                // cells
     int nb0, nb1;              // range of its neighbour list: patches holding some of its ghost cells
+    long long fpart;           // its row sums per velocity strip in the fine partial buffer, [strip][row]
+                               // (room for strips of 64 cells, the narrowest tile)
 };
 
 enum AmrTileKind : int { kTileCoarse = 0, kTileFine = 1, kTileFaces = 2 };
@@ -155,6 +158,8 @@ struct AmrArgs {
     double c_flux;             // b_s (0: no accumulation)
     int first;                 // first stage: store instead of add
     int lim;                   // limited face averages on both levels
+    double* fpart;             // fine row sums of the new stage state per velocity strip (or null);
+                               // the coarse ones go to coarse.part
 };
 
 // ----------------------------------------------------------------- two-level 2D+2V
@@ -424,6 +429,22 @@ hipError_t launch_amr_reduce_finalize(const double* slots, const int* rowptr, co
 // Mask reduction: S[i * 5 + a + 2] = sum over uncovered (i, j) of f_coarse(i + a, j)
 hipError_t launch_amr_mask_rows(const double* f, const unsigned char* covered, int ncx, int ncv, double* S,
                                 hipStream_t stream);
+// Mask reduction from the stage kernel's strip partials (see k_amr_mask_fused)
+struct AmrMaskFusedArgs {
+    const double* f;           // the stage state (coarse level at offset 0)
+    const double* part_c;      // coarse row sums, [strip][ncx]
+    const double* part_f;      // fine row sums, per patch at AmrPatch::fpart, [strip][row]
+    const AmrPatch* patches;
+    const int* cov_ptr;        // per coarse column, its covered cells (ncx + 1 entries)
+    const int* cov_j;          // their velocity indices
+    const int* fz_ptr;         // per coarse column, its fine strip partials (ncx + 1 entries)
+    const int2* fz_entry;      // (index in part_f, fine cell of the column 0 .. R-1), in a fixed order
+    const double* B;           // b_j(s) at B[s * 5 + j + 2]
+    int ncx, ncv, nstrip, R, tv;
+    double dvc, dvf;
+    double* n;                 // out: n on the fine configuration mesh
+};
+hipError_t launch_amr_mask_fused(const AmrMaskFusedArgs& a, hipStream_t stream);
 hipError_t launch_amr_inject(const double* E, int ncx, int R, double qm, double* a, hipStream_t stream);
 // end of step: coarse cells next to coarse-fine faces take the fine
 // accumulated fluxes; covered coarse cells take the mean of their fine cells
@@ -513,13 +534,24 @@ struct AmrPlan {
     int* d_cov_nv = nullptr;
     int nsub = 0;                                    // sub-patches of the coarse level (Alg. subdiv)
     // Mask reduction (Alg. mreduce): coverage mask, fixed-order lists over [S (5 ncx) | fine row sums]
-    int reduce_mode = 0;                             // VP_REDUCE_SUBPATCH or VP_REDUCE_MASK
+    int reduce_mode = VP_REDUCE_FUSED;               // VP_REDUCE_SUBPATCH, VP_REDUCE_MASK or VP_REDUCE_FUSED
     int fine_task0 = 0;                              // first fine-row task in the task list
     unsigned char* d_mask = nullptr;
     int* d_rowptr_m = nullptr;
     int* d_idx_m = nullptr;
     double* d_w_m = nullptr;
     size_t ws_slots_m = 0;
+    // the Mask reduction from the stage kernel's row sums: per coarse column
+    // its covered cells (covc_ptr, ncx + 1 entries; covc_j their velocity
+    // indices) and the fine strip partials of its fine cells (fz, rebuilt
+    // with the tile table: the strips are the tiles'); the coarse and fine
+    // strip partials in the workspace (ws_pc, ws_pf)
+    int* d_covc_ptr = nullptr;
+    int* d_covc_j = nullptr;
+    void* d_fz = nullptr;
+    int* d_fz_ptr = nullptr;
+    int2* d_fz_entry = nullptr;
+    size_t ws_pc = 0, ws_pf = 0;
     // Poisson table of the coarse configuration mesh (subcycled steps)
     double* d_green_c = nullptr;
     // workspace offsets; ws_hist: the five coarse states of a subcycled
@@ -776,13 +808,21 @@ vp_status hier_plan_create(const vp_problem* pb, const vp_box* boxes, int nbox, 
 vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);
 void amr_destroy(vp_plan* p);
 vp_status amr_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream);
-vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream);
+// partials: the stage kernel that wrote f also wrote its strip partials
+// (amr_stage with partials), so the fused Mask reduction forms n from them
+vp_status amr_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream,
+                     bool partials = false);
 vp_status amr_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
 vp_status amr_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
 // the pieces of amr_rk4: stage s (0..3) reading the acceleration a, its
 // output state (the stage-4 output is f itself), and the end-of-step
 // coarse-fine synchronisation (flux correction and average-down of f)
-vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt, void* work, hipStream_t stream);
+// partials: also write the strip partials of the new stage state's rows
+// (the coarse ones at ws_pc, the fine ones at ws_pf)
+vp_status amr_stage(const vp_plan* p, int s, void* f, const double* a, double dt, void* work, hipStream_t stream,
+                    bool partials = false);
+// whether stage s of a step takes the fused Mask reduction
+bool amr_stage_partials(const vp_plan* p, int s);
 void* amr_stage_output(const vp_plan* p, int s, void* f, void* work);
 vp_status amr_end_sync(const vp_plan* p, void* f, double dt, void* work, hipStream_t stream);
 vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx);

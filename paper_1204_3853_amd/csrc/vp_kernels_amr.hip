@@ -72,10 +72,14 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
     const bool do_flux = (KIND != kRhs) && ff != nullptr && A.c_flux != 0.0;
 
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
     const int jt = j0 + t * W;
     const bool own_in = jt < nv;
     const int jld = own_in ? jt : 0;
     const int c0 = LPAD + t * W;
+    // velocity sums of the tile's new rows, per wave (Alg. mreduce's fine row sums)
+    __shared__ double momf[NT / 64][kMaxTx];
+    const bool do_mom = KIND != kRhs && A.fpart != nullptr;
     const bool has_halo = t < 4;
     const int hj = t < 2 ? j0 - 2 + t : j0 + TV + (t - 2);
     const int hcol_idx = t < 2 ? LPAD - 2 + t : LPAD + TV + (t - 2);
@@ -389,6 +393,30 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
                 }
             }
         }
+        if (do_mom) {
+            double sm4[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                sm4[q] = 0.0;
+                if (own_in) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) sm4[q] += o2[q][w];
+                }
+            }
+            const double tot = wave_sum4(sm4, lane);      // row q = lane / 16 of the batch
+            const int g = lane >> 4;
+            if ((lane & 15) == 0 && ib + g < i1) momf[wave][ib + g - i0] = tot;
+        }
+    }
+    if (do_mom) {
+        __syncthreads();
+        double* dst = A.fpart + P.fpart + (size_t)tl.b * nx;
+        for (int q = t; q < i1 - i0; q += NT) {
+            double sm = 0.0;
+#pragma unroll
+            for (int wv = 0; wv < NT / 64; ++wv) sm += momf[wv][q];
+            dst[i0 + q] = sm;
+        }
     }
 }
 
@@ -507,6 +535,70 @@ __global__ __launch_bounds__(256) void k_amr_reduce_finalize(const double* __res
     if (l == 0 && I < nfx) n[I] = s;
 }
 
+// Mask reduction (Alg. mreduce) from the stage kernel's row sums.  For the
+// target coarse column i and x-stencil offset a, the masked sum over row
+// i + a is that row's total (its strip partials) less its cells in the
+// velocity intervals level 1 covers in column i (read back from the state:
+// a few cells per column); the R fine cells of column i take the
+// x-refinement of the five masked sums, times dv_c, plus dv_f times the row
+// sums of the patches over them (their strip partials, listed per column).
+// One wave per coarse column.  The loads form three rounds (list bounds and
+// the coarse partials; list entries; the values they name), each issued
+// for all three sums at once, one element per lane; each lane keeps its
+// terms per target and each target's total is a wave sum (a fixed butterfly
+// order, so the result does not depend on timing).
+__global__ __launch_bounds__(256) void k_amr_mask_fused(AmrMaskFusedArgs M)
+{
+    const int wv = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int i = min(wv, M.ncx - 1);      // waves past the end recompute the last column, store nothing
+    const int lane = threadIdx.x & 63;
+    int row[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) row[a] = wrapi(i + a - 2, M.ncx);
+    const int nc = 5 * M.nstrip;
+    const int k0 = M.cov_ptr[i], k1 = M.cov_ptr[i + 1];
+    const int e0 = M.fz_ptr[i], e1 = M.fz_ptr[i + 1];
+    double T[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // row totals (this lane's strips)
+    double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // covered cells of column i (this lane's)
+    double F[4] = {0.0, 0.0, 0.0, 0.0};        // fine row sums (R is 2 or 4)
+    for (int l0 = 0; l0 < max(nc, max(k1 - k0, e1 - e0)); l0 += 64) {
+        const int l = l0 + lane;
+        // coarse partial l: strip l % nstrip of row l / nstrip
+        const int ac = l < nc ? l / M.nstrip : 5;
+        const double vc = l < nc ? M.part_c[(size_t)(l - ac * M.nstrip) * M.ncx + row[min(ac, 4)]] : 0.0;
+        const int j = k0 + l < k1 ? M.cov_j[k0 + l] : -1;
+        const int2 en = e0 + l < e1 ? M.fz_entry[e0 + l] : make_int2(0, -1);
+        double cf[5];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) cf[a] = j >= 0 ? M.f[(size_t)row[a] * M.ncv + j] : 0.0;
+        const double vf = en.y >= 0 ? M.part_f[en.x] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            T[a] += ac == a ? vc : 0.0;
+            c[a] += cf[a];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) F[s] += en.y == s ? vf : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        T[a] = wave_sum(T[a]);
+        c[a] = wave_sum(c[a]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (s < M.R) F[s] = wave_sum(F[s]);
+    if (lane >= M.R || wv >= M.ncx) return;
+    double n = 0.0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) n += M.B[lane * 5 + a] * M.dvc * (T[a] - c[a]);
+    double fl = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (s == lane) fl = F[s];
+    M.n[i * M.R + lane] = n + M.dvf * fl;
+}
+
 // a_c = (q/m) mean of the R fine E values over each coarse cell, a_f = (q/m) E
 __global__ __launch_bounds__(256) void k_amr_inject(const double* __restrict__ E, int ncx, int R, double qm,
                                                    double* __restrict__ a)
@@ -620,6 +712,12 @@ hipError_t launch_amr_mask_rows(const double* f, const unsigned char* covered, i
                                 hipStream_t stream)
 {
     hipLaunchKernelGGL(k_amr_mask_rows, dim3((5 * ncx + 3) / 4), dim3(256), 0, stream, f, covered, ncx, ncv, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_mask_fused(const AmrMaskFusedArgs& a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_amr_mask_fused, dim3((a.ncx + 3) / 4), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

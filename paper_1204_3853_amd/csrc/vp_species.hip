@@ -207,11 +207,12 @@ vp_status vp_species_rk4_step(const vp_species_group* g, void* const* f, double*
         for (int s = 0; s < g->ns; ++s) {
             const vp_plan* p = g->plans[s];
             if (p->amr) {
-                if (vp_status e = amr_stage(p, st, f[s], a[s], dt, work[s], stream)) return e;
+                const bool partials = amr_stage_partials(p, st);
+                if (vp_status e = amr_stage(p, st, f[s], a[s], dt, work[s], stream, partials)) return e;
                 if (st == 3)
                     if (vp_status e = amr_end_sync(p, f[s], dt, work[s], stream)) return e;
                 const void* out = amr_stage_output(p, st, f[s], work[s]);
-                if (vp_status e = amr_reduce(p, out, moment_buf(g, gwork, s), work[s], stream)) return e;
+                if (vp_status e = amr_reduce(p, out, moment_buf(g, gwork, s), work[s], stream, partials)) return e;
                 continue;
             }
             const Stage1DArgs A = rk4_stage_args_1d(R[s], st, a[s]);

@@ -140,7 +140,7 @@ SIGNATURES = {
 
 TIMING_CLASSES = ["stage", "field", "moment", "sync", "adjoint", "other"]
 LAUNCH_PERSISTENT, LAUNCH_PER_PATCH = 0, 1
-REDUCE_SUBPATCH, REDUCE_MASK = 0, 1
+REDUCE_SUBPATCH, REDUCE_MASK, REDUCE_FUSED = 0, 1, 2
 FACE_CENTERED, FACE_LIMITED = 0, 1
 
 
@@ -297,7 +297,8 @@ class Plan:
         _check(lib().vp_face_scheme_set(self.h, int(scheme)))
 
     def set_reduction(self, algorithm):
-        """REDUCE_SUBPATCH (Alg. spreduce) or REDUCE_MASK (Alg. mreduce), two-level plans."""
+        """REDUCE_SUBPATCH (Alg. spreduce), REDUCE_MASK (Alg. mreduce) or REDUCE_FUSED
+        (the Mask reduction from the stage kernels' row sums, the default), two-level plans."""
         _check(lib().vp_reduction_set(self.h, int(algorithm)))
 
     def autotune(self, f, a, dt, reps=3):

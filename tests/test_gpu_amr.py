@@ -37,12 +37,16 @@ TOUCHING = [{"level": 1, "lo": [16, 40], "hi": [39, 63]}, {"level": 1, "lo": [40
 # touching it in v, and a patch on the lower velocity boundary
 WHOLE_X = [{"level": 1, "lo": [0, 20], "hi": [47, 33]}, {"level": 1, "lo": [6, 34], "hi": [17, 43]},
            {"level": 1, "lo": [20, 0], "hi": [27, 7]}]
+# a patch over the whole velocity range (coarse columns covered from end to
+# end), one against the periodic x boundary beside it
+WHOLE_V = [{"level": 1, "lo": [10, 0], "hi": [17, 89]}, {"level": 1, "lo": [40, 30], "hi": [47, 51]}]
 
 LAYOUTS = {
     "small": dict(boxes=SMALL, ncx=32, ncv=48, R=4),
     "ratio2_odd": dict(boxes=RATIO2, ncx=24, ncv=45, R=2),
     "touching": dict(boxes=TOUCHING, ncx=32, ncv=48, R=4),
     "whole_x_ratio2": dict(boxes=WHOLE_X, ncx=24, ncv=45, R=2),
+    "whole_v_ratio2": dict(boxes=WHOLE_V, ncx=24, ncv=45, R=2),
 }
 
 
@@ -112,15 +116,42 @@ def test_mask_reduction(vp, case):
     """Alg. mreduce on the GPU: the same n as the oracle's Mask reduction and
     as the GPU Sub-Patch reduction, to rounding."""
     f = case.gpu(case.f0)
-    n_sp = vp.reduce_moment(case.plan, f).cpu().numpy()
-    case.plan.set_reduction(vp.REDUCE_MASK)
+    case.plan.set_reduction(vp.REDUCE_SUBPATCH)
     try:
+        n_sp = vp.reduce_moment(case.plan, f).cpu().numpy()
+        case.plan.set_reduction(vp.REDUCE_MASK)
         n_m = vp.reduce_moment(case.plan, f)
     finally:
-        case.plan.set_reduction(vp.REDUCE_SUBPATCH)
+        case.plan.set_reduction(vp.REDUCE_FUSED)
     want = case.o.reduce_mask(case.f0)
     cmp(n_m, want, 1e-13, "mask n")
     cmp(n_m, n_sp, 1e-13, "mask vs sub-patch")
+
+
+def test_step_by_each_reduction(vp, case):
+    """Two steps with each reduction: the fused one (the stage kernels write
+    their rows' velocity sums per strip, one kernel subtracts the covered
+    coarse cells and refines in x), Sub-Patch and Mask all equal the oracle's
+    steps, and each other to rounding; the field after the steps too."""
+    want = case.f0
+    for _ in range(2):
+        want = case.o.step(want, case.dt)
+    a_want, _ = case.o.constraints(want)
+    got = {}
+    try:
+        for alg in (vp.REDUCE_FUSED, vp.REDUCE_SUBPATCH, vp.REDUCE_MASK):
+            case.plan.set_reduction(alg)
+            f = case.gpu(case.f0)
+            a = vp.field_of(case.plan, f)
+            for _ in range(2):
+                vp.rk4_step(case.plan, f, a, case.dt)
+            cmp(f, want, rel_tol(), f"step, reduction {alg}")
+            cmp(a, a_want, 1e-11, f"a, reduction {alg}")
+            got[alg] = f.cpu().numpy()
+    finally:
+        case.plan.set_reduction(vp.REDUCE_FUSED)
+    cmp(got[vp.REDUCE_FUSED], got[vp.REDUCE_MASK], 1e-14, "fused vs mask")
+    cmp(got[vp.REDUCE_FUSED], got[vp.REDUCE_SUBPATCH], 1e-14, "fused vs sub-patch")
 
 
 def test_constraints(vp, case):
@@ -193,15 +224,16 @@ def test_full_config_one_step(vp, full):
     cmp(f, full.o.step(full.f0, full.dt), rel_tol(), "step")
 
 
-def test_full_config_step_with_mask_reduction(vp, full):
-    full.plan.set_reduction(vp.REDUCE_MASK)
+@pytest.mark.parametrize("alg", ["mask", "sub_patch"])
+def test_full_config_step_with_other_reductions(vp, full, alg):
+    full.plan.set_reduction(vp.REDUCE_MASK if alg == "mask" else vp.REDUCE_SUBPATCH)
     try:
         f = full.gpu(full.f0)
         a = vp.field_of(full.plan, f)
         vp.rk4_step(full.plan, f, a, full.dt)
     finally:
-        full.plan.set_reduction(vp.REDUCE_SUBPATCH)
-    cmp(f, full.o.step(full.f0, full.dt), rel_tol(), "step (mask reduction)")
+        full.plan.set_reduction(vp.REDUCE_FUSED)
+    cmp(f, full.o.step(full.f0, full.dt), rel_tol(), f"step ({alg} reduction)")
 
 
 def test_full_config_persistent_equals_per_patch(vp, full):

@@ -168,7 +168,7 @@ def test_subcycle_with_mask_reduction(vp, oracle):
         torch.cuda.synchronize()
         cmp(f, c.o.subcycle_step(c.f0, 2 * c.dt), rel_tol(), "subcycled step, Mask reduction")
     finally:
-        c.plan.set_reduction(vp.REDUCE_SUBPATCH)
+        c.plan.set_reduction(vp.REDUCE_FUSED)
 
 
 def test_subcycled_landau_damping_rate_on_gpu(vp):
