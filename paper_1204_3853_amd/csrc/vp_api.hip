@@ -207,7 +207,8 @@ vp_status scratch_address(void** out)
 // plan of two or more levels: geometry, box calculus and tables (two-level
 // engine in vp_amr.hip, multi-level engine in vp_hier.hip), then the Poisson
 // tables of the finest configuration mesh
-vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out, bool force_hier)
+vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out, bool force_hier,
+                             bool tag_only = false)
 {
     vp_plan* p = new (std::nothrow) vp_plan();
     if (!p) return fail(VP_ENOMEM, "out of host memory");
@@ -224,7 +225,7 @@ vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox
     // adaptive runs); deeper or anisotropic hierarchies the multi-level one
     const bool two = !force_hier && pb->n_levels == 2 && pb->ratio[0][0] == pb->ratio[0][1] &&
                      (pb->ratio[0][0] == 2 || pb->ratio[0][0] == 4);
-    vp_status st = two ? amr_create(p, pb, boxes, nbox) : hier_create(p, pb, boxes, nbox);
+    vp_status st = two ? amr_create(p, pb, boxes, nbox) : hier_create(p, pb, boxes, nbox, tag_only);
     if (st == VP_OK) {
         // kept so that a plan of another hierarchy can be made from this one
         int nv = pb->cells[1];
@@ -254,6 +255,10 @@ vp_status create_multi_level(const vp_problem* pb, const vp_box* boxes, int nbox
         p->dx = H.dxf;
         p->dv = H.lv[H.L - 1].dv;
         p->v_lo = pb->v_lo[0];
+        if (H.tag_only) {
+            *out = p;
+            return VP_OK;
+        }
     }
     std::vector<double> g = tridiag_green(p->nx, kGreenTaps);
     p->gk = kGreenTaps;
@@ -362,13 +367,13 @@ vp_status hip_fail(hipError_t e, const char* what)
     return VP_EHIP;
 }
 
-vp_status hier_plan_create(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out)
+vp_status hier_plan_create(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out, bool tag_only)
 {
     if (!pb || !out) return fail(VP_EINVAL, "hier_plan_create: NULL pointer");
     *out = nullptr;
     if (pb->n_levels < 2 || pb->n_levels > VP_MAX_LEVELS) return fail(VP_EINVAL, "n_levels must be 2 .. 4");
     if (!pb->veq[0][0]) return fail(VP_EINVAL, "veq[0][0] (equilibrium with ghosts) is required");
-    return create_multi_level(pb, boxes, nbox, out, true);
+    return create_multi_level(pb, boxes, nbox, out, true, tag_only);
 }
 
 }  // namespace vp

@@ -203,7 +203,7 @@ vp_status hier_set_shape(vp_plan* p, int nt, int w, int tx)
     return VP_OK;
 }
 
-vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox)
+vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox, bool tag_only)
 {
     if (pb->ndim != 1) return fail(VP_ENOTSUP, "multi-level hierarchies are supported for 1D+1V");
     if (pb->dtype != VP_F64) return fail(VP_ENOTSUP, "multi-level hierarchies are supported in FP64");
@@ -214,6 +214,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     p->hier = Hp;
     HierPlan& H = *Hp;
     H.L = L;
+    H.tag_only = tag_only;
     const double x_len = pb->x_len[0], vspan = pb->v_hi[0] - pb->v_lo[0];
     for (int l = 0; l < L; ++l) {
         HLevel& v = B.lv[l];
@@ -385,7 +386,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
         if (q < 0) { nested = false; return 0; }
         return B.offset(q, l, i, j);
     };
-    for (size_t gi = 1; gi < B.P.size(); ++gi) {
+    for (size_t gi = 1; gi < (tag_only ? 1 : B.P.size()); ++gi) {
         const HPatch& G = B.P[gi];
         const int l = G.lev - 1;
         const int rx = B.lv[l + 1].rx, rv = B.lv[l + 1].rv;
@@ -466,8 +467,8 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     // rows summed over its velocity range, refined in x to the finest mesh
     std::vector<long long> task_off;
     std::vector<int> task_len;
-    std::vector<std::vector<std::pair<int, double>>> contrib(nfx);
-    for (size_t pi = 0; pi < B.P.size(); ++pi) {
+    std::vector<std::vector<std::pair<int, double>>> contrib(tag_only ? 0 : nfx);
+    for (size_t pi = 0; pi < (tag_only ? 0 : B.P.size()); ++pi) {
         const HPatch& q = B.P[pi];
         const int l = q.lev;
         const HBox box{q.gx0, q.gv0, q.gx0 + q.nx - 1, q.gv0 + q.nv - 1};
@@ -519,7 +520,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     H.ntasks = (int)task_off.size();
     std::vector<int> rowptr{0}, idx;
     std::vector<double> w;
-    for (int I = 0; I < nfx; ++I) {
+    for (int I = 0; I < (tag_only ? 0 : nfx); ++I) {
         for (const auto& c : contrib[I]) {
             idx.push_back(c.first);
             w.push_back(c.second);
@@ -533,8 +534,10 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     H.w = std::all_of(H.patches.begin(), H.patches.end(), [](const HPatch& q) { return q.nv % 2 == 0; }) ? 2 : 1;
     H.nt = 64;
     H.tx = 8;
-    fill_tiles(H);
-    VP_HIP(upload_tiles(H));
+    if (!tag_only) {
+        fill_tiles(H);
+        VP_HIP(upload_tiles(H));
+    }
     std::vector<HLevel> lvv(H.lv, H.lv + L);
     for (int l = 0; l < L; ++l) {
         H.level_begin[l] = (int)H.level_list.size();
@@ -574,7 +577,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
         T.add(&H.avg[l].d_stride, avg_stride[l]);
     }
     VP_HIP(T.commit(&H.d_tables));
-    VP_HIP(hipMalloc(&H.d_rhs_frame, std::max<size_t>(H.frame_elems, 1) * sizeof(double)));
+    if (!tag_only) VP_HIP(hipMalloc(&H.d_rhs_frame, std::max<size_t>(H.frame_elems, 1) * sizeof(double)));
 
     // ---- workspace: acc, two predictors, frames, accumulated fluxes, row sums, n, E, field scratch
     const size_t sb = a256(H.total * sizeof(double));

@@ -31,17 +31,10 @@ std::vector<int> owner_map(const HierPlan& H, int l)
     return own;
 }
 
-template <class T>
-struct DevBuf {
-    T* p = nullptr;
-    ~DevBuf() { if (p) (void)hipFree(p); }
-    hipError_t up(const std::vector<T>& v)
-    {
-        if (v.empty()) return hipSuccess;
-        hipError_t e = hipMalloc(&p, v.size() * sizeof(T));
-        if (e != hipSuccess) return e;
-        return hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-    }
+// device memory freed at the end of a scope
+struct DevMem {
+    void* p = nullptr;
+    ~DevMem() { if (p) (void)hipFree(p); }
 };
 
 }  // namespace
@@ -133,23 +126,27 @@ vp_status hier_transfer(const vp_plan* old_plan, const double* f_old, const vp_p
             }
         }
     }
-    std::vector<DevBuf<int>> dwin(N.L);
-    std::vector<DevBuf<HProlongPatch>> dpp(N.L);
-    std::vector<DevBuf<HCopyBlock>> dcp(N.L);
+    // every level's records in one allocation and one copy
+    std::vector<int*> dwin(N.L, nullptr);
+    std::vector<HProlongPatch*> dpp(N.L, nullptr);
+    std::vector<HCopyBlock*> dcp(N.L, nullptr);
+    TableArena T;
     for (int l = 1; l < N.L; ++l) {
-        VP_HIP(dwin[l].up(win[l]));
-        VP_HIP(dpp[l].up(pp[l]));
-        VP_HIP(dcp[l].up(cp[l]));
+        T.add(&dwin[l], win[l]);
+        T.add(&dpp[l], pp[l]);
+        T.add(&dcp[l], cp[l]);
     }
+    DevMem recs;
+    VP_HIP(T.commit(&recs.p));
     // level 0 copied, then every level from the coarsest: prolongation from
     // the new parent level, then the old cells of the level
     VP_HIP(hipMemcpyAsync(f_new, f_old, sizeof(double) * (size_t)N.lv[0].nx * N.lv[0].nv, hipMemcpyDeviceToDevice,
                           stream));
     hipError_t e = hipSuccess;
     for (int l = 1; l < N.L && e == hipSuccess; ++l) {
-        e = launch_hier_prolong(f_new, dwin[l].p, dpp[l].p, (int)pp[l].size(), maxpc[l], N.lv[l].rx, N.lv[l].rv,
+        e = launch_hier_prolong(f_new, dwin[l], dpp[l], (int)pp[l].size(), maxpc[l], N.lv[l].rx, N.lv[l].rv,
                                 N.d_eqv, stream);
-        if (e == hipSuccess) e = launch_hier_copy(f_new, f_old, dcp[l].p, (int)cp[l].size(), maxc[l], stream);
+        if (e == hipSuccess) e = launch_hier_copy(f_new, f_old, dcp[l], (int)cp[l].size(), maxc[l], stream);
     }
     const hipError_t es = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "hier_transfer: launch");
@@ -170,23 +167,32 @@ vp_status hier_cluster(const vp_plan* p, int l, const uint8_t* tags, int rx, int
     // counts as held), so the new level is nested with room for its ghost
     // interpolation (the nesting rule of the multi-level plan)
     const std::vector<int> own = owner_map(H, l);
-    std::vector<unsigned char> held((size_t)nx * nv), allowed((size_t)nx * nv);
-    for (size_t c = 0; c < held.size(); ++c) held[c] = own[c] >= 0;
-    for (int i = 0; i < nx; ++i)
+    // the 7 x 7 erosion of the held cells, one direction at a time: held
+    // over the velocity window [j - 3, j + 3] clipped to the box (a prefix
+    // count per row), then over the periodic window of rows [i - 3, i + 3]
+    std::vector<unsigned char> held_v((size_t)nx * nv), allowed((size_t)nx * nv);
+    std::vector<int> pre(nv + 1);
+    for (int i = 0; i < nx; ++i) {
+        const int* o = own.data() + (size_t)i * nv;
+        pre[0] = 0;
+        for (int j = 0; j < nv; ++j) pre[j + 1] = pre[j] + (o[j] >= 0);
         for (int j = 0; j < nv; ++j) {
-            bool ok = true;
-            for (int a = -3; a <= 3 && ok; ++a)
-                for (int b = -3; b <= 3 && ok; ++b) {
-                    const int jj = j + b;
-                    if (jj < 0 || jj >= nv) continue;
-                    ok = held[(size_t)rwrap(i + a, nx) * nv + jj] != 0;
-                }
-            allowed[(size_t)i * nv + j] = ok;
+            const int j0 = std::max(j - 3, 0), j1 = std::min(j + 3, nv - 1);
+            held_v[(size_t)i * nv + j] = pre[j1 + 1] - pre[j0] == j1 - j0 + 1;
         }
+    }
+    for (int i = 0; i < nx; ++i) {
+        const unsigned char* r[7];
+        for (int a = -3; a <= 3; ++a) r[a + 3] = held_v.data() + (size_t)rwrap(i + a, nx) * nv;
+        unsigned char* dst = allowed.data() + (size_t)i * nv;
+        for (int j = 0; j < nv; ++j)
+            dst[j] = r[0][j] & r[1][j] & r[2][j] & r[3][j] & r[4][j] & r[5][j] & r[6][j];
+    }
     std::vector<unsigned char> t((size_t)nx * nv);
     for (size_t c = 0; c < t.size(); ++c) t[c] = tags[c] && allowed[c];
+    const TagSums st(t, nx, nv);
     std::vector<CBox> bx;
-    br_cluster(t, nv, CBox{0, 0, nx - 1, nv - 1}, efficiency, min_width, bx);
+    br_cluster(st, CBox{0, 0, nx - 1, nv - 1}, efficiency, min_width, bx);
     for (CBox& b : bx) {
         b.xlo = std::max(b.xlo - buffer, 0); b.xhi = std::min(b.xhi + buffer, nx - 1);
         b.vlo = std::max(b.vlo - buffer, 0); b.vhi = std::min(b.vhi + buffer, nv - 1);
@@ -207,18 +213,13 @@ vp_status hier_cluster(const vp_plan* p, int l, const uint8_t* tags, int rx, int
     }
     // a box holding disallowed cells is halved along its longer side until
     // every part is allowed; parts without tags are dropped
-    auto count = [&](const std::vector<unsigned char>& m, const CBox& b) {
-        long long n = 0;
-        for (int i = b.xlo; i <= b.xhi; ++i)
-            for (int j = b.vlo; j <= b.vhi; ++j) n += m[(size_t)i * nv + j];
-        return n;
-    };
+    const TagSums sa(allowed, nx, nv);
     std::vector<CBox> todo(bx.begin(), bx.end()), fit;
     while (!todo.empty()) {
         const CBox b = todo.back();
         todo.pop_back();
-        if (count(t, b) == 0) continue;
-        if (count(allowed, b) == b.area()) {
+        if (st.count(b.xlo, b.vlo, b.xhi, b.vhi) == 0) continue;
+        if (sa.count(b.xlo, b.vlo, b.xhi, b.vhi) == b.area()) {
             fit.push_back(b);
             continue;
         }

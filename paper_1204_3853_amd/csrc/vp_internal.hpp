@@ -602,6 +602,7 @@ struct Amr4DPlan {
 // multi-level plan (vp_hier.hip): L levels, a ratio per level and direction
 struct HierPlan {
     int L = 2;
+    bool tag_only = false;                           // patches, frames and level lists only (see hier_create)
     int na = 0;                                      // elements of a: every level's configuration mesh
     double dxf = 0;                                  // finest configuration cell
     HLevel lv[kHierLevels] = {};
@@ -777,10 +778,25 @@ struct CBox {
     int xlo, vlo, xhi, vhi;
     long long area() const { return (long long)(xhi - xlo + 1) * (vhi - vlo + 1); }
 };
+// summed-area table of a 0/1 mask of nx x nv cells ([x][v]): the cells set
+// in a box in four lookups
+struct TagSums {
+    int nx = 0, nv = 0;
+    std::vector<int> s;                              // s[(i + 1)(nv + 1) + j + 1] = cells set in [0, i] x [0, j]
+    TagSums(const std::vector<unsigned char>& m, int nx_, int nv_);
+    long long count(int xlo, int vlo, int xhi, int vhi) const   // inclusive bounds
+    {
+        const size_t w = (size_t)nv + 1;
+        return (long long)s[(xhi + 1) * w + vhi + 1] - s[xlo * w + vhi + 1] - s[(xhi + 1) * w + vlo] + s[xlo * w + vlo];
+    }
+};
 void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double eff, int minw, std::vector<CBox>& out);
+void br_cluster(const TagSums& T, CBox B, double eff, int minw, std::vector<CBox>& out);
 
 // multi-level host sequences (vp_hier.hip)
-vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);
+// tag_only: build only what tagging a level and transferring a state into
+// the plan need (patches, ghost frames, level lists); such a plan cannot step
+vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox, bool tag_only = false);
 void hier_destroy(vp_plan* p);
 vp_status hier_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream);
 vp_status hier_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream);
@@ -802,7 +818,7 @@ vp_status hier_transfer(const vp_plan* old_plan, const double* f_old, const vp_p
 vp_status hier_cluster(const vp_plan* p, int l, const uint8_t* tags, int rx, int rv, double efficiency, int min_width,
                        int buffer, int max_x, int max_v, std::vector<vp_box>& out);
 // a plan on the multi-level engine whatever its levels and ratios (vp_api.hip)
-vp_status hier_plan_create(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out);
+vp_status hier_plan_create(const vp_problem* pb, const vp_box* boxes, int nbox, vp_plan** out, bool tag_only = false);
 
 // two-level host sequences (vp_amr.hip)
 vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int nbox);

@@ -43,35 +43,49 @@ bool level0_of(const vp_plan* p, Level0& L)
 
 }  // namespace
 
+TagSums::TagSums(const std::vector<unsigned char>& m, int nx_, int nv_) : nx(nx_), nv(nv_)
+{
+    s.assign((size_t)(nx + 1) * (nv + 1), 0);
+    for (int i = 0; i < nx; ++i) {
+        int row = 0;
+        for (int j = 0; j < nv; ++j) {
+            row += m[(size_t)i * nv + j] != 0;
+            s[(size_t)(i + 1) * (nv + 1) + j + 1] = s[(size_t)i * (nv + 1) + j + 1] + row;
+        }
+    }
+}
+
+namespace {
+
 // Berger-Rigoutsos: split the bounding box of the tags inside B at a hole
 // of a signature, else at the strongest inflection of a signature's
 // second difference, else in the middle of the longer side, until each
 // box holds at least `eff` tagged cells per cell or cannot be split into
-// two parts of at least `minw` cells.
-void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double eff, int minw,
-                std::vector<CBox>& out)
+// two parts of at least `minw` cells.  The signatures (tagged cells per
+// row and per column of B) come from the summed-area table, so a box costs
+// the length of its sides, not its area.
+void br_split(const TagSums& T, CBox B, double eff, int minw, std::vector<CBox>& out)
 {
-    // shrink to the tags' bounding box
-    int xlo = B.xhi + 1, xhi = B.xlo - 1, vlo = B.vhi + 1, vhi = B.vlo - 1;
+    const int bwx = B.xhi - B.xlo + 1, bwv = B.vhi - B.vlo + 1;
+    std::vector<long long> fx(bwx), fv(bwv);
     long long nt = 0;
-    for (int i = B.xlo; i <= B.xhi; ++i)
-        for (int j = B.vlo; j <= B.vhi; ++j)
-            if (tag[(size_t)i * nv + j]) {
-                ++nt;
-                xlo = std::min(xlo, i); xhi = std::max(xhi, i);
-                vlo = std::min(vlo, j); vhi = std::max(vhi, j);
-            }
+    for (int i = 0; i < bwx; ++i) nt += fx[i] = T.count(B.xlo + i, B.vlo, B.xlo + i, B.vhi);
     if (nt == 0) return;
-    B = CBox{xlo, vlo, xhi, vhi};
+    for (int j = 0; j < bwv; ++j) fv[j] = T.count(B.xlo, B.vlo + j, B.xhi, B.vlo + j);
+    // shrink to the tags' bounding box (every tag of B lies in it, so the
+    // signatures over B restricted to it are its own)
+    int x0 = 0, x1 = bwx - 1, v0 = 0, v1 = bwv - 1;
+    while (fx[x0] == 0) ++x0;
+    while (fx[x1] == 0) --x1;
+    while (fv[v0] == 0) ++v0;
+    while (fv[v1] == 0) --v1;
+    const std::vector<long long> sx(fx.begin() + x0, fx.begin() + x1 + 1), sv(fv.begin() + v0, fv.begin() + v1 + 1);
+    B = CBox{B.xlo + x0, B.vlo + v0, B.xlo + x1, B.vlo + v1};
     const int wx = B.xhi - B.xlo + 1, wv = B.vhi - B.vlo + 1;
     if ((double)nt >= eff * (double)B.area() || (wx < 2 * minw && wv < 2 * minw)) {
         out.push_back(B);
         return;
     }
-    std::vector<long long> sx(wx, 0), sv(wv, 0);
-    for (int i = B.xlo; i <= B.xhi; ++i)
-        for (int j = B.vlo; j <= B.vhi; ++j)
-            if (tag[(size_t)i * nv + j]) { ++sx[i - B.xlo]; ++sv[j - B.vlo]; }
     // candidate cut: the first cell of the upper part, at offset c of a side
     // of width w (minw <= c <= w - minw); best = (class, score, distance to the middle)
     int best_dir = -1, best_cut = 0;
@@ -85,15 +99,15 @@ void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double ef
         }
     };
     for (int dir = 0; dir < 2; ++dir) {
-        const std::vector<long long>& s = dir == 0 ? sx : sv;
-        const int w = (int)s.size();
+        const std::vector<long long>& sg = dir == 0 ? sx : sv;
+        const int w = (int)sg.size();
         if (w < 2 * minw) continue;
         for (int c = minw; c <= w - minw; ++c)
-            if (s[c - 1] == 0 || s[c] == 0) consider(dir, c, 0, 0, w);
+            if (sg[c - 1] == 0 || sg[c] == 0) consider(dir, c, 0, 0, w);
         for (int c = std::max(minw, 2); c <= std::min(w - minw, w - 2); ++c) {
             // inflection between cells c-1 and c: second differences change sign
-            const long long l0 = s[c - 2] - 2 * s[c - 1] + s[c];
-            const long long l1 = s[c - 1] - 2 * s[c] + s[c + 1];
+            const long long l0 = sg[c - 2] - 2 * sg[c - 1] + sg[c];
+            const long long l1 = sg[c - 1] - 2 * sg[c] + sg[c + 1];
             if ((l0 < 0 && l1 > 0) || (l0 > 0 && l1 < 0)) consider(dir, c, 1, std::llabs(l1 - l0), w);
         }
         consider(dir, w / 2, 2, w, w);
@@ -105,8 +119,17 @@ void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double ef
     CBox lo = B, hi = B;
     if (best_dir == 0) { lo.xhi = B.xlo + best_cut - 1; hi.xlo = B.xlo + best_cut; }
     else { lo.vhi = B.vlo + best_cut - 1; hi.vlo = B.vlo + best_cut; }
-    br_cluster(tag, nv, lo, eff, minw, out);
-    br_cluster(tag, nv, hi, eff, minw, out);
+    br_split(T, lo, eff, minw, out);
+    br_split(T, hi, eff, minw, out);
+}
+
+}  // namespace
+
+void br_cluster(const TagSums& T, CBox B, double eff, int minw, std::vector<CBox>& out) { br_split(T, B, eff, minw, out); }
+
+void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double eff, int minw, std::vector<CBox>& out)
+{
+    br_split(TagSums(tag, (int)(tag.size() / (size_t)nv), nv), B, eff, minw, out);
 }
 
 namespace {

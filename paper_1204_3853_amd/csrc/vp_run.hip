@@ -232,7 +232,7 @@ vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s)
             vp_problem pbi = pb;
             pbi.n_levels = l + 2;
             vp_plan* Pn = nullptr;
-            st = hier_plan_create(&pbi, nb.data(), (int)nb.size(), &Pn);
+            st = hier_plan_create(&pbi, nb.data(), (int)nb.size(), &Pn, true);
             if (st == VP_OK) st = ensure_buf(&F, &fcap, std::max<size_t>(vp_state_elems(Pn), 1) * sizeof(double));
             if (st == VP_OK) st = hier_transfer(old, static_cast<const double*>(S.f), Pn, static_cast<double*>(F), s);
             if (P) vp_plan_destroy(P);
