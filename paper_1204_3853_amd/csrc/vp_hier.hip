@@ -167,12 +167,18 @@ vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, h
             double* scratch = reinterpret_cast<double*>(wsp(work, H.ws_fld));
             return launch_field_split_species(m, nfx, H.dxf, p->d_green, scratch, out, stream);
         }
-        return launch_poisson1d(nullptr, 0, n, 1.0, nfx, H.dxf, 1.0, p->d_green, p->gk, nullptr, nullptr, E, nullptr,
-                                stream);
+        // the injection onto every level in the same launch
+        int off[kHierLevels], rt[kHierLevels];
+        for (int l = 0; l < H.L; ++l) {
+            off[l] = H.lv[l].a_off;
+            rt[l] = H.lv[l].rt;
+        }
+        return launch_poisson1d_levels(n, nfx, H.dxf, p->pb.qm, p->d_green, p->gk, E, a, H.L, off, rt, stream);
     }));
-    VP_HIP(timed(p, kTOther, stream, [&] {
-        return launch_hier_inject(E, H.lv, H.L, p->pb.qm, a, H.na, stream);
-    }));
+    if (nfx >= kFieldSplitMin)
+        VP_HIP(timed(p, kTOther, stream, [&] {
+            return launch_hier_inject(E, H.lv, H.L, p->pb.qm, a, H.na, stream);
+        }));
     return VP_OK;
 }
 

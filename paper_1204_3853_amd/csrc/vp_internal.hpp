@@ -349,6 +349,9 @@ struct PoissonExtra {
     int nstrip;
     double dv;
     double* n_out;             // non-null (with part): receives that n
+    int inject_L;              // > 0: a of every level of a hierarchy, level l at inject_off[l]:
+    int inject_off[kHierLevels];  // (q/m) times the mean of the inject_rt[l] fine E values of each cell
+    int inject_rt[kHierLevels];
 };
 
 // Launchers (defined in vp_kernels_1d.hip).
@@ -403,6 +406,11 @@ hipError_t launch_field_split(const double* part, int nstrip, int nx, double dv,
 // sum_s w_s sum_strips part_s), writing every array of `out`
 hipError_t launch_field_split_species(const SpeciesMoments& m, int nx, double dx, const double* green, double* work,
                                       const FieldOutputs& out, hipStream_t stream);
+// Poisson, field and the injection onto every level of a hierarchy (L <= 4
+// levels; level l's cell holds rt[l] finest cells, its a starts at off[l])
+// in one launch, for meshes below kFieldSplitMin cells
+hipError_t launch_poisson1d_levels(const double* n_in, int nx, double dx, double qm, const double* green, int gk,
+                                   double* E, double* a, int L, const int* off, const int* rt, hipStream_t stream);
 // Poisson, field and two-level injection in one launch; the moment is n_in,
 // or is finalised from the weighted list of x when x.slots is set
 hipError_t launch_poisson1d_inject(const double* n_in, const PoissonExtra& x, int nx, double dx, double qm,

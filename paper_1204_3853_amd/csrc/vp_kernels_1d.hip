@@ -503,9 +503,25 @@ __global__ __launch_bounds__(kPoissonThreads) void k_poisson1d(
         if (X.inject_R > 0) {
             ybuf[pad(i)] = E;
             a_out[nx / X.inject_R + i] = qm * E;
+        } else if (X.inject_L > 0) {
+            ybuf[pad(i)] = E;
         } else if (a_out) {
             a_out[i] = qm * E;
         }
+    }
+    if (X.inject_L > 0) {
+        // every level of a hierarchy: (q/m) times the mean of the rt fine
+        // values over each of its cells (rt = 1 on the finest level)
+        __syncthreads();
+        for (int l = 0; l < X.inject_L; ++l) {
+            const int rt = X.inject_rt[l];
+            for (int k = t; k < nx / rt; k += kPoissonThreads) {
+                double se = 0.0;
+                for (int q = 0; q < rt; ++q) se += ybuf[pad(k * rt + q)];
+                a_out[X.inject_off[l] + k] = qm * (se / rt);
+            }
+        }
+        return;      // phi is not requested with injection
     }
     if (X.inject_R > 0) {
         // two levels: the coarse acceleration is (q/m) times the mean of the R fine values
@@ -654,6 +670,23 @@ hipError_t launch_poisson1d(const double* part, int nstrip, const double* n_in, 
     const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
     hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
                        phi, E, a, 0, 1.0, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_poisson1d_levels(const double* n_in, int nx, double dx, double qm, const double* green, int gk,
+                                   double* E, double* a, int L, const int* off, const int* rt, hipStream_t stream)
+{
+    if (!n_in || !a || L < 1 || L > kHierLevels) return hipErrorInvalidValue;
+    PoissonExtra X{};
+    X.inject_L = L;
+    for (int l = 0; l < L; ++l) {
+        if (rt[l] < 1 || nx % rt[l]) return hipErrorInvalidValue;
+        X.inject_off[l] = off[l];
+        X.inject_rt[l] = rt[l];
+    }
+    const size_t lds = poisson1d_lds_doubles(nx) * sizeof(double);
+    hipLaunchKernelGGL(k_poisson1d, dim3(1), dim3(kPoissonThreads), lds, stream, n_in, nx, dx, qm, green, gk,
+                       nullptr, E, a, 0, 1.0, X);
     return hipGetLastError();
 }
 
