@@ -187,10 +187,14 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     std::vector<int> list(P.size());
     for (size_t q = 0; q < P.size(); ++q) list[q] = (int)q;
 
-    // ---- stage tiles: 256 cells of one patch each
+    for (const A4Patch& q : P)     // kernels index a patch's cells, and its padded copy, in 32 bits
+        if ((long long)(q.sz[0] + 4) * (q.sz[1] + 4) * (q.sz[2] + 4) * (q.sz[3] + 4) >= (1LL << 31))
+            return fail(VP_ENOTSUP, "two-level 2D+2V: a patch (or level 0) of 2^31 cells or more");
+    // ---- stage tiles: 256 threads of one patch each (a thread per run of
+    // kA4VxRun cells along vx)
     std::vector<int> tiles;
     for (size_t q = 0; q < P.size(); ++q) {
-        const long long n = (long long)P[q].sz[0] * P[q].sz[1] * P[q].sz[2] * P[q].sz[3];
+        const long long n = (long long)P[q].sz[0] * P[q].sz[1] * ((P[q].sz[2] + kA4VxRun - 1) / kA4VxRun) * P[q].sz[3];
         for (long long c = 0; c < n; c += 256) {
             tiles.push_back((int)q);
             tiles.push_back((int)c);

@@ -181,11 +181,14 @@ struct A4Level {
     int a_off;                 // offset of the level's a: [x component][y component], each n0 n1
 };
 
+constexpr int kA4VxRun = 2;  // cells along vx per thread of the two-level 2D+2V stage kernel
+
 struct A4Args {
     A4Level lv[2];
     const A4Patch* patches;
     const int* nb;
-    const int* tiles;          // per tile: patch index and first cell (2 ints)
+    const int* tiles;          // per tile: patch index and first thread (2 ints); a patch's threads
+                               // are its (x, y, run of kA4VxRun vx cells, vy), vy fastest
     int ntiles;
     const double* pad;         // padded copies of the stage input
     const double* fn;

@@ -276,55 +276,156 @@ __device__ __forceinline__ void flux_store(double* p, double v, const A4Args& A)
     else *p += A.c_flux * v;
 }
 
+// One thread per kA4VxRun cells along vx of one (x, y, vy) of a patch
+// (lanes along vy, so loads are coalesced): the x and vx face averages of
+// the run come from windows of the padded copy held in registers, every
+// face flux of the run evaluated once (the x faces on vx rows k0 - 1 ..
+// k0 + run, the vx faces k0 - 1/2 .. k0 + run - 1/2); the y and vy faces,
+// whose corrections take vy +- 1 and vy +- 2, per cell.  The same formulas
+// and operand order as face_flux.  Rows past a ragged last run read the
+// last row of the padded copy and are dropped.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_a4_stage(A4Args A)
 {
+    constexpr int K = kA4VxRun;
     const int t = blockIdx.x;
     const A4Patch P = A.patches[A.tiles[2 * t]];
-    const long long c = (long long)A.tiles[2 * t + 1] + threadIdx.x;
-    const long long ncell = (long long)P.sz[0] * P.sz[1] * P.sz[2] * P.sz[3];
-    if (c >= ncell) return;
-    int r = (int)c;
-    const int l = divmod_rcp(r, P.sz[3], P.isz[3]);
-    const int k = divmod_rcp(r, P.sz[2], P.isz[2]);
-    const int j = divmod_rcp(r, P.sz[1], P.isz[1]);
+    const int n0 = P.sz[0], n1 = P.sz[1], n2 = P.sz[2], n3 = P.sz[3];
+    const int ng = (n2 + K - 1) / K;
+    const int c = A.tiles[2 * t + 1] + (int)threadIdx.x;       // below 2^31: the host checks the patch sizes
+    if (c >= n0 * n1 * ng * n3) return;
+    int r = c;
+    const int l = divmod_rcp(r, n3, P.isz[3]);
+    const int kg = divmod_rcp(r, ng, 1.0 / ng);
+    const int j = divmod_rcp(r, n1, P.isz[1]);
     const int i = r;
+    const int k0 = kg * K;
     const A4Level& L = A.lv[P.lev];
     const A4View U = view_of(A.pad, P);
     const A4Acc ac4 = acc_at(A.a, L, P.lo[0] + i, P.lo[1] + j);
-    const double gx1 = face_flux(U, P, L, ac4, 0, i, j, k, l), gx0 = face_flux(U, P, L, ac4, 0, i - 1, j, k, l);
-    const double gy1 = face_flux(U, P, L, ac4, 1, i, j, k, l), gy0 = face_flux(U, P, L, ac4, 1, i, j - 1, k, l);
-    const double gk1 = face_flux(U, P, L, ac4, 2, i, j, k, l), gk0 = face_flux(U, P, L, ac4, 2, i, j, k - 1, l);
-    const double gl1 = face_flux(U, P, L, ac4, 3, i, j, k, l), gl0 = face_flux(U, P, L, ac4, 3, i, j, k, l - 1);
-    const double kk = -(gx1 - gx0) * L.hi[0] - (gy1 - gy0) * L.hi[1] - (gk1 - gk0) * L.hi[2] - (gl1 - gl0) * L.hi[3];
-    if (KIND != kRhs && A.ff_acc && A.c_flux != 0.0 && P.lev == 1) {
-        const int n0 = P.sz[0], n1 = P.sz[1], n2 = P.sz[2], n3 = P.sz[3];
-        const long long S0 = (long long)n1 * n2 * n3, S1 = (long long)n0 * n2 * n3, S2 = (long long)n0 * n1 * n3;
-        double* ff = A.ff_acc + P.foff;
-        if (i == 0) flux_store(ff + ((long long)j * n2 + k) * n3 + l, gx0, A);
-        if (i == n0 - 1) flux_store(ff + S0 + ((long long)j * n2 + k) * n3 + l, gx1, A);
-        ff += 2 * S0;
-        if (j == 0) flux_store(ff + ((long long)i * n2 + k) * n3 + l, gy0, A);
-        if (j == n1 - 1) flux_store(ff + S1 + ((long long)i * n2 + k) * n3 + l, gy1, A);
-        ff += 2 * S1;
-        if (k == 0) flux_store(ff + ((long long)i * n1 + j) * n3 + l, gk0, A);
-        if (k == n2 - 1) flux_store(ff + S2 + ((long long)i * n1 + j) * n3 + l, gk1, A);
-        ff += 2 * S2;
-        if (l == 0) flux_store(ff + ((long long)i * n1 + j) * n2 + k, gl0, A);
-        if (l == n3 - 1) flux_store(ff + (long long)n0 * n1 * n2 + ((long long)i * n1 + j) * n2 + k, gl1, A);
+    const bool acc_ff = KIND != kRhs && A.ff_acc && A.c_flux != 0.0 && P.lev == 1;
+    const long long S0 = (long long)n1 * n2 * n3, S1 = (long long)n0 * n2 * n3, S2 = (long long)n0 * n1 * n3;
+    double* ff = acc_ff ? A.ff_acc + P.foff : nullptr;
+    auto row = [&](int k) { return min(k, n2 + 1); };
+    double kk[K], f0[K];
+
+    // x faces (transverse correction along vx)
+    {
+        double fp[K + 2], fm[K + 2];
+#pragma unroll
+        for (int q = 0; q < K + 2; ++q) {
+            const int k = row(k0 - 1 + q);
+            const double u0 = U(i - 2, j, k, l), u1 = U(i - 1, j, k, l), u2 = U(i, j, k, l), u3 = U(i + 1, j, k, l),
+                         u4 = U(i + 2, j, k, l);
+            fp[q] = face4<double>(u1, u2, u3, u4);
+            fm[q] = face4<double>(u0, u1, u2, u3);
+            if (q >= 1 && q <= K) f0[q - 1] = u2;
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int k = k0 + q;
+            const double vb = L.v_lo + ((double)(P.lo[2] + k) + 0.5) * L.h[2];
+            const double gx1 = vb * fp[q + 1] + L.h[2] / 24.0 * (fp[q + 2] - fp[q]);
+            const double gx0 = vb * fm[q + 1] + L.h[2] / 24.0 * (fm[q + 2] - fm[q]);
+            kk[q] = -(gx1 - gx0) * L.hi[0];
+            if (acc_ff && k < n2) {
+                if (i == 0) flux_store(ff + ((long long)j * n2 + k) * n3 + l, gx0, A);
+                if (i == n0 - 1) flux_store(ff + S0 + ((long long)j * n2 + k) * n3 + l, gx1, A);
+            }
+        }
     }
-    const long long o = P.off + c;
-    if (KIND == kRhs) {
-        A.fout[o] = kk;
-    } else if (KIND == kStage1) {
-        const double f0 = U(i, j, k, l);
-        A.acc[o] = f0 + A.c_acc * kk;
-        A.fout[o] = f0 + A.c_next * kk;
-    } else if (KIND == kStage23) {
-        A.acc[o] = A.acc[o] + A.c_acc * kk;
-        A.fout[o] = A.fn[o] + A.c_next * kk;
-    } else {
-        A.fout[o] = A.acc[o] + A.c_acc * kk;
+    // y faces (transverse correction along vy)
+    {
+        const double vbl = L.v_lo + ((double)(P.lo[3] + l) + 0.5) * L.h[3];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int k = row(k0 + q);
+            double fp[3], fm[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double u0 = U(i, j - 2, k, l + b - 1), u1 = U(i, j - 1, k, l + b - 1), u2 = U(i, j, k, l + b - 1),
+                             u3 = U(i, j + 1, k, l + b - 1), u4 = U(i, j + 2, k, l + b - 1);
+                fp[b] = face4<double>(u1, u2, u3, u4);
+                fm[b] = face4<double>(u0, u1, u2, u3);
+            }
+            const double gy1 = vbl * fp[1] + L.h[3] / 24.0 * (fp[2] - fp[0]);
+            const double gy0 = vbl * fm[1] + L.h[3] / 24.0 * (fm[2] - fm[0]);
+            kk[q] = kk[q] - (gy1 - gy0) * L.hi[1];
+            if (acc_ff && k0 + q < n2) {
+                double* fy = ff + 2 * S0;
+                if (j == 0) flux_store(fy + ((long long)i * n2 + k) * n3 + l, gy0, A);
+                if (j == n1 - 1) flux_store(fy + S1 + ((long long)i * n2 + k) * n3 + l, gy1, A);
+            }
+        }
+    }
+    // the five configuration positions of the velocity faces' corrections
+    const int pi[5] = {i, i + 1, i - 1, i, i}, pj[5] = {j, j, j, j + 1, j - 1};
+    const double acx = ac4.c[0], daxx = ac4.dx[0], dayx = ac4.dy[0];
+    const double acy = ac4.c[1], daxy = ac4.dx[1], dayy = ac4.dy[1];
+    // vx faces k0 - 1/2 .. k0 + K - 1/2
+    {
+        double G[K + 1];
+        double w[5][K + 4];            // vx rows k0 - 2 .. k0 + K + 1
+#pragma unroll
+        for (int p = 0; p < 5; ++p)
+#pragma unroll
+            for (int q = 0; q < K + 4; ++q) w[p][q] = U(pi[p], pj[p], row(k0 - 2 + q), l);
+#pragma unroll
+        for (int m = 0; m < K + 1; ++m) {
+            double fv[5];
+#pragma unroll
+            for (int p = 0; p < 5; ++p) fv[p] = face4<double>(w[p][m], w[p][m + 1], w[p][m + 2], w[p][m + 3]);
+            G[m] = acx * fv[0] + (daxx * (fv[1] - fv[2]) + dayx * (fv[3] - fv[4])) / 48.0;
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int k = k0 + q;
+            kk[q] = kk[q] - (G[q + 1] - G[q]) * L.hi[2];
+            if (acc_ff && k < n2) {
+                double* fk = ff + 2 * S0 + 2 * S1;
+                if (k == 0) flux_store(fk + ((long long)i * n1 + j) * n3 + l, G[q], A);
+                if (k == n2 - 1) flux_store(fk + S2 + ((long long)i * n1 + j) * n3 + l, G[q + 1], A);
+            }
+        }
+    }
+    // vy faces l - 1/2 and l + 1/2, per cell
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const int k = row(k0 + q);
+        double fvp[5], fvm[5];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            const double u0 = U(pi[p], pj[p], k, l - 2), u1 = U(pi[p], pj[p], k, l - 1), u2 = U(pi[p], pj[p], k, l),
+                         u3 = U(pi[p], pj[p], k, l + 1), u4 = U(pi[p], pj[p], k, l + 2);
+            fvp[p] = face4<double>(u1, u2, u3, u4);
+            fvm[p] = face4<double>(u0, u1, u2, u3);
+        }
+        const double gl1 = acy * fvp[0] + (daxy * (fvp[1] - fvp[2]) + dayy * (fvp[3] - fvp[4])) / 48.0;
+        const double gl0 = acy * fvm[0] + (daxy * (fvm[1] - fvm[2]) + dayy * (fvm[3] - fvm[4])) / 48.0;
+        kk[q] = kk[q] - (gl1 - gl0) * L.hi[3];
+        if (acc_ff && k0 + q < n2) {
+            double* fl = ff + 2 * S0 + 2 * S1 + 2 * S2;
+            if (l == 0) flux_store(fl + ((long long)i * n1 + j) * n2 + k, gl0, A);
+            if (l == n3 - 1) flux_store(fl + (long long)n0 * n1 * n2 + ((long long)i * n1 + j) * n2 + k, gl1, A);
+        }
+    }
+    // the stage combine of the run's cells
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const int k = k0 + q;
+        if (k >= n2) break;
+        const long long o = P.off + (((long long)i * n1 + j) * n2 + k) * n3 + l;
+        if (KIND == kRhs) {
+            A.fout[o] = kk[q];
+        } else if (KIND == kStage1) {
+            A.acc[o] = f0[q] + A.c_acc * kk[q];
+            A.fout[o] = f0[q] + A.c_next * kk[q];
+        } else if (KIND == kStage23) {
+            A.acc[o] = A.acc[o] + A.c_acc * kk[q];
+            A.fout[o] = A.fn[o] + A.c_next * kk[q];
+        } else {
+            A.fout[o] = A.acc[o] + A.c_acc * kk[q];
+        }
     }
 }
 
