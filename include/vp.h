@@ -576,10 +576,15 @@ typedef struct vp_amr_run vp_amr_run;
  * one level; plan creation errors as vp_plan_create. */
 vp_status vp_amr_run_create(const vp_problem* problem, const vp_box* boxes, int32_t nbox, const void* f0,
                             const vp_amr_params* params, vp_amr_run** out, hipStream_t stream);
-/* Advances `steps` time steps on `stream`.  Synchronises the stream every
- * step (the time step needs max|a| on the host) and at every regrid, which
- * allocates the new state and frees the old one.  After an error the run
- * should only be destroyed. */
+/* Advances `steps` time steps on `stream`.  A run of one species on a
+ * multi-level plan keeps its time step and time in device memory: each
+ * step's time step is computed on the device from the field (the same
+ * rule and arithmetic as on the host) and the step's kernels read it
+ * there, so the stream is synchronised only at a regrid and at the end of
+ * the call.  Two-level plans and several species synchronise every step
+ * (the time step needs max|a| on the host).  A regrid allocates the new
+ * state and frees the old one.  After an error the run should only be
+ * destroyed. */
 vp_status vp_amr_run_advance(vp_amr_run* run, int32_t steps, hipStream_t stream);
 vp_status vp_amr_run_info(const vp_amr_run* run, vp_amr_info* info);
 /* The plan of the current hierarchy (owned by the run; replaced at a regrid). */

@@ -650,7 +650,8 @@ vp_status hier_inject(const vp_plan* p, const double* E, double* a, hipStream_t 
     return VP_OK;
 }
 
-vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream)
+vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream,
+                   const double* dt_dev)
 {
     const HierPlan& H = *p->hier;
     double* fd = static_cast<double*>(f);
@@ -660,7 +661,9 @@ vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, 
     const double* in[4] = {fd, sa, sb, sa};
     double* out[4] = {sa, sb, sa, fd};
     const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    const double cnext[3] = {0.5 * dt, 0.5 * dt, dt};
+    // with the time step in device memory the kernels multiply it in (dt b_s, dt/2, dt: the same products)
+    const double sc = dt_dev ? 1.0 : dt;
+    const double cnext[3] = {0.5 * sc, 0.5 * sc, sc};
     if (vp_status st = fill_frames(p, fd, work, stream)) return st;
     for (int s = 0; s < 4; ++s) {
         const int kind = s == 0 ? kStage1 : (s == 3 ? kStage4 : kStage23);
@@ -668,8 +671,9 @@ vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, 
         A.fn = fd;
         A.acc = acc;
         A.fout = out[s];
-        A.c_acc = dt * b[s];
+        A.c_acc = dt_dev ? b[s] : dt * b[s];
         A.c_next = s < 3 ? cnext[s] : 0.0;
+        A.dt = dt_dev;
         A.c_flux = b[s];
         A.first = s == 0;
         if (vp_status st = launch_stage(p, kind, A, stream)) return st;
@@ -684,6 +688,7 @@ vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, 
     S.f = fd;
     for (int l = 0; l < H.L; ++l) S.lv[l] = H.lv[l];
     S.dt = dt;
+    S.dt_dev = dt_dev;
     S.faces = H.d_faces;
     S.cf_acc = reinterpret_cast<const double*>(wsp(work, H.ws_cf));
     S.ff_acc = reinterpret_cast<const double*>(wsp(work, H.ws_ff));

@@ -284,12 +284,15 @@ struct HierArgs {
     double* ff_acc;            // accumulated patch boundary fluxes
     double c_acc, c_next, c_flux;
     int first;
+    const double* dt;          // null: c_acc and c_next are the stage coefficients; else they are
+                               // multiplied by the time step held in device memory at dt
 };
 
 struct HierSyncArgs {
     double* f;
     HLevel lv[kHierLevels];
     double dt;
+    const double* dt_dev;      // non-null: the time step is read there instead
     const HFace* faces;
     const double* cf_acc;
     const double* ff_acc;
@@ -812,7 +815,18 @@ void hier_destroy(vp_plan* p);
 vp_status hier_rhs(const vp_plan* p, const void* f, const double* a, void* k, hipStream_t stream);
 vp_status hier_reduce(const vp_plan* p, const void* f, double* n, void* work, hipStream_t stream);
 vp_status hier_inject(const vp_plan* p, const double* E, double* a, hipStream_t stream);
-vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream);
+// dt_dev: non-null, the time step is the value held there in device memory
+// (written by an earlier launch on the stream; dt is then unused)
+vp_status hier_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hipStream_t stream,
+                   const double* dt_dev = nullptr);
+// the time step control of the adaptive run on the device (section 4): the
+// largest linearly stable step of a multi-level state's field a, every
+// patch of every level over its own velocity faces and configuration
+// columns; state[0] = dt = min(first ? dt_initial : growth state[0],
+// cfl courant / rate), state[1] += dt
+hipError_t launch_hier_dt(const double* a, const HPatch* patches, int npatch, const HLevel* lv, int L, double v_lo,
+                          double courant, double cfl, double growth, double dt_initial, int first, double* state,
+                          hipStream_t stream);
 vp_status hier_set_shape(vp_plan* p, int nt, int w, int tx);
 // ghost frames of state f into the workspace frame buffer
 vp_status hier_fill_frames(const vp_plan* p, const double* f, void* work, hipStream_t stream);

@@ -176,7 +176,8 @@ __device__ __forceinline__ void stage_tile_frame(const HierArgs& A, const AmrTil
 #pragma unroll
     for (int w = 0; w < W; ++w) vb[w] = A.v_lo + ((double)(P.gv0 + jt + w) + 0.5) * Lv.dv;
     const T dxi = Lv.dxi, dvi = Lv.dvi, dv24 = Lv.dv24;
-    const T cacc = A.c_acc, cnext = A.c_next;
+    const double dts = A.dt ? *A.dt : 0.0;
+    const T cacc = A.dt ? dts * A.c_acc : A.c_acc, cnext = A.dt ? dts * A.c_next : A.c_next;
     const double* __restrict__ al = A.a + Lv.a_off;
 
     __syncthreads();                          // frame cells in LDS
@@ -390,10 +391,51 @@ __global__ __launch_bounds__(256) void k_hier_reflux(HierSyncArgs S)
         double s = 0.0;
         for (int q = 0; q < nf; ++q) s += fine[q];
         const double diff = s / nf - S.cf_acc[fi];
-        const double h = S.dt * (F.dir == 0 ? S.lv[F.lev].dxi : S.lv[F.lev].dvi);
+        const double h = (S.dt_dev ? *S.dt_dev : S.dt) * (F.dir == 0 ? S.lv[F.lev].dxi : S.lv[F.lev].dvi);
         val += lower ? h * diff : -h * diff;
     }
     S.f[S.corr_cell[k]] = val;
+}
+
+// the adaptive run's time step on the device: the stability rate of every
+// patch of every level, max(|v| at its velocity faces) / dx + |a| / dv over
+// its configuration columns (a maximum, so its order does not matter; the
+// products and sums rounded one by one, as the host rule computes them),
+// then dt and t; one block
+struct HierDtArgs {
+    const double* a;
+    const HPatch* patches;
+    int npatch;
+    HLevel lv[kHierLevels];
+    double v_lo, courant, cfl, growth, dt_initial;
+    int first;
+    double* state;             // [dt, t]
+};
+
+__global__ __launch_bounds__(256) void k_hier_dt(HierDtArgs D)
+{
+    __shared__ double red[4];
+    double rate = 0.0;
+    for (int p = 0; p < D.npatch; ++p) {
+        const HPatch P = D.patches[p];
+        const HLevel& v = D.lv[P.lev];
+        const double v0 = __dadd_rn(D.v_lo, __dmul_rn((double)P.gv0, v.dv));
+        const double v1 = __dadd_rn(D.v_lo, __dmul_rn((double)(P.gv0 + P.nv), v.dv));
+        const double vt = __dmul_rn(fmax(fabs(v0), fabs(v1)), v.dxi);
+        const double* al = D.a + v.a_off + P.gx0;
+        for (int i = threadIdx.x; i < P.nx; i += 256) rate = fmax(rate, __dadd_rn(vt, __dmul_rn(fabs(al[i]), v.dvi)));
+    }
+    for (int m = 32; m >= 1; m >>= 1) rate = fmax(rate, __shfl_xor(rate, m, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rate;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        rate = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        const double lim = D.courant / rate;
+        const double cap = D.first ? D.dt_initial : __dmul_rn(D.growth, D.state[0]);
+        const double dt = fmin(cap, __dmul_rn(D.cfl, lim));
+        D.state[0] = dt;
+        D.state[1] = __dadd_rn(D.state[1], dt);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_hier_average(HierAvgArgs S)
@@ -464,6 +506,26 @@ hipError_t launch_hier_inject(const double* E, const HLevel* lv, int L, double q
         Z.rt[l] = lv[l].rt;
     }
     hipLaunchKernelGGL(k_hier_inject, dim3((na + 255) / 256), dim3(256), 0, stream, E, Z, qm, a, na);
+    return hipGetLastError();
+}
+
+hipError_t launch_hier_dt(const double* a, const HPatch* patches, int npatch, const HLevel* lv, int L, double v_lo,
+                          double courant, double cfl, double growth, double dt_initial, int first, double* state,
+                          hipStream_t stream)
+{
+    HierDtArgs D{};
+    D.a = a;
+    D.patches = patches;
+    D.npatch = npatch;
+    for (int l = 0; l < L; ++l) D.lv[l] = lv[l];
+    D.v_lo = v_lo;
+    D.courant = courant;
+    D.cfl = cfl;
+    D.growth = growth;
+    D.dt_initial = dt_initial;
+    D.first = first;
+    D.state = state;
+    hipLaunchKernelGGL(k_hier_dt, dim3(1), dim3(256), 0, stream, D);
     return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ struct vp_amr_run {
     double* phi = nullptr;
     double* E = nullptr;
     double t = 0.0, dt = 0.0;
+    double* d_clock = nullptr;         // [dt, t] on the device (one species on a multi-level hierarchy)
     long long steps = 0;
     int regrids = 0;
     double regrid_seconds = 0.0;
@@ -84,6 +85,7 @@ void run_free(vp_amr_run* r)
         S.plan = nullptr;
     }
     free_dev(r->gwork);
+    free_dev(r->d_clock);
     free_dev(r->n);
     free_dev(r->phi);
     free_dev(r->E);
@@ -362,6 +364,37 @@ vp_status add_species(vp_amr_run* r, int q, const vp_problem* pb, const vp_box* 
     return VP_OK;
 }
 
+// One species on a multi-level hierarchy: the time step is computed on the
+// device from the field the previous step (or the regrid) left, and the
+// step's kernels read it there, so the steps between two regrids are
+// enqueued without waiting for the GPU; dt and t come back to the host at
+// the end of the call (or when a regrid synchronises anyway).
+vp_status advance_device_clock(vp_amr_run* r, int32_t steps, hipStream_t stream)
+{
+    RunSpecies& S = r->sp[0];
+    if (!r->d_clock) {
+        VP_HIP(hipMalloc(&r->d_clock, 2 * sizeof(double)));
+        const double c[2] = {r->dt, r->t};
+        VP_HIP(hipMemcpy(r->d_clock, c, sizeof(c), hipMemcpyHostToDevice));
+    }
+    const double courant = linear_stability_courant();
+    for (int32_t k = 0; k < steps; ++k) {
+        const HierPlan& H = *S.plan->hier;
+        VP_HIP(launch_hier_dt(S.a, H.d_patches, (int)H.patches.size(), H.lv, H.L, S.plan->pb.v_lo[0], courant,
+                              r->prm.cfl, r->prm.dt_growth, r->prm.dt_initial, r->steps == 0, r->d_clock, stream));
+        if (vp_status st = hier_rk4(S.plan, S.f, S.a, 0.0, S.work, stream, r->d_clock)) return st;
+        ++r->steps;
+        if (r->steps % r->prm.regrid_interval == 0)
+            if (vp_status st = regrid(r, stream)) return st;
+    }
+    double c[2];
+    VP_HIP(hipMemcpyAsync(c, r->d_clock, sizeof(c), hipMemcpyDeviceToHost, stream));
+    VP_HIP(hipStreamSynchronize(stream));
+    r->dt = c[0];
+    r->t = c[1];
+    return VP_OK;
+}
+
 }  // namespace
 }  // namespace vp
 
@@ -441,6 +474,7 @@ vp_status vp_amr_run_advance(vp_amr_run* r, int32_t steps, hipStream_t stream)
 {
     if (!r) return fail(VP_EINVAL, "vp_amr_run_advance: run is NULL");
     if (steps < 0) return fail(VP_EINVAL, "vp_amr_run_advance: negative step count");
+    if (!r->group_field && r->sp[0].plan->hier) return advance_device_clock(r, steps, stream);
     for (int32_t k = 0; k < steps; ++k) {
         double lim = 0.0;
         vp_status st = stability_limit(r, stream, &lim);
