@@ -12,7 +12,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <map>
 #include <string>
 #include <vector>
 
@@ -283,12 +282,11 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
         if (X.xlo % v.rx || (X.xhi + 1) % v.rx || X.vlo % v.rv || (X.vhi + 1) % v.rv)
             return fail(VP_EINVAL, "box " + std::to_string(k) + " is not aligned to its level's refinement ratio");
         const int pid = (int)B.P.size();
+        for (size_t r = 1; r < bx.size(); ++r)
+            if (B.P[r].lev == l && !hsect(bx[r], X).empty())
+                return fail(VP_EINVAL, "boxes " + std::to_string(r - 1) + " and " + std::to_string(k) + " overlap");
         for (int i = X.xlo; i <= X.xhi; ++i)
-            for (int j = X.vlo; j <= X.vhi; ++j) {
-                int& o = B.owner[l][(size_t)i * v.nv + j];
-                if (o >= 0) return fail(VP_EINVAL, "boxes " + std::to_string(o - 1) + " and " + std::to_string(k) + " overlap");
-                o = pid;
-            }
+            std::fill_n(B.owner[l].begin() + (size_t)i * v.nv + X.vlo, X.vhi - X.vlo + 1, pid);
         HPatch q{};
         q.lev = l;
         q.gx0 = X.xlo;
@@ -319,6 +317,13 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     for (size_t pi = 0; pi < B.P.size(); ++pi) {
         const HPatch& q = B.P[pi];
         const int l = q.lev;
+        // the parent cells a frame reads, each one's 25 sources found once:
+        // the record that first used it, per parent cell of the frame's
+        // bounding box (x unwrapped)
+        const int rxl = l > 0 ? B.lv[l].rx : 1, rvl = l > 0 ? B.lv[l].rv : 1;
+        const int pc0 = (q.gx0 - 2 - (rxl - 1)) / rxl - 1, pv0 = std::max(q.gv0 - 2, 0) / rvl;
+        const int pcn = (q.gx0 + q.nx + 2) / rxl - pc0 + 2, pvn = (q.gv0 + q.nv + 2) / rvl - pv0 + 2;
+        std::vector<int> first_rec(l > 0 ? (size_t)pcn * pvn : 0, -1);
         auto add = [&](int r, int c) -> bool {
             const int X = q.gx0 + r, V = q.gv0 + c;
             const int s = B.source(l, X, V);
@@ -333,12 +338,21 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
             const int ci = Xw / v.rx, cj = V / v.rv;
             R.s = Xw - ci * v.rx;
             R.t = V - cj * v.rv;
-            for (int a = -2; a <= 2; ++a)
-                for (int b = -2; b <= 2; ++b) {
-                    const int src = B.source(l - 1, ci + a, cj + b);
-                    if (src == INT32_MIN) return false;
-                    R.src[(a + 2) * 5 + b + 2] = src;
-                }
+            const int cu = (X >= 0 ? X : X - v.rx + 1) / v.rx;          // parent cell, x unwrapped
+            int* cached = nullptr;
+            if (l > 0 && cu >= pc0 && cu < pc0 + pcn && cj >= pv0 && cj < pv0 + pvn)
+                cached = &first_rec[(size_t)(cu - pc0) * pvn + (cj - pv0)];
+            if (cached && *cached >= 0) {
+                std::memcpy(R.src, rec[*cached].src, sizeof(R.src));
+            } else {
+                for (int a = -2; a <= 2; ++a)
+                    for (int b = -2; b <= 2; ++b) {
+                        const int src = B.source(l - 1, ci + a, cj + b);
+                        if (src == INT32_MIN) return false;
+                        R.src[(a + 2) * 5 + b + 2] = src;
+                    }
+                if (cached) *cached = (int)rec.size();
+            }
             desc.push_back(int2{-2, (int)rec.size()});
             rec.push_back(R);
             return true;
@@ -370,7 +384,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     std::vector<HFace> faces;
     std::vector<long long> corr_fine;
     std::vector<int> corr_nfine;
-    std::map<long long, std::vector<int>> corr;       // corrected cell -> encoded faces
+    std::vector<std::pair<long long, int>> corr;     // (corrected cell, encoded face), in the order found
     std::vector<std::vector<long long>> avg_dst(L), avg_src(L);
     std::vector<std::vector<int>> avg_stride(L);
     bool nested = true;
@@ -406,7 +420,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
                 F.lev = l;
                 F.vb = pb->v_lo[0] + (cj + 0.5) * B.lv[l].dv;
                 stencil(l, cx0 - 1, cj, 0, F);
-                corr[cell_off(l, cx0 - 1, cj)].push_back((int)faces.size());            // its upper face
+                corr.emplace_back(cell_off(l, cx0 - 1, cj), (int)faces.size());         // its upper face
                 corr_fine.push_back(G.foff + (cj * rv - G.gv0));
                 corr_nfine.push_back(rv);
                 faces.push_back(F);
@@ -418,7 +432,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
                 F.lev = l;
                 F.vb = pb->v_lo[0] + (cj + 0.5) * B.lv[l].dv;
                 stencil(l, cx1, cj, 0, F);
-                corr[cell_off(l, cx1 + 1, cj)].push_back(-1 - (int)faces.size());       // its lower face
+                corr.emplace_back(cell_off(l, cx1 + 1, cj), -1 - (int)faces.size());    // its lower face
                 corr_fine.push_back(G.foff + G.nv + (cj * rv - G.gv0));
                 corr_nfine.push_back(rv);
                 faces.push_back(F);
@@ -434,7 +448,7 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
                 F.lev = l;
                 F.ai[0] = aim; F.ai[1] = ai0; F.ai[2] = aip;
                 stencil(l, ci, cv0 - 1, 1, F);
-                corr[cell_off(l, ci, cv0 - 1)].push_back((int)faces.size());
+                corr.emplace_back(cell_off(l, ci, cv0 - 1), (int)faces.size());
                 corr_fine.push_back(G.foff + 2 * G.nv + (ci * rx - G.gx0));
                 corr_nfine.push_back(rx);
                 faces.push_back(F);
@@ -445,13 +459,16 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
                 F.lev = l;
                 F.ai[0] = aim; F.ai[1] = ai0; F.ai[2] = aip;
                 stencil(l, ci, cv1, 1, F);
-                corr[cell_off(l, ci, cv1 + 1)].push_back(-1 - (int)faces.size());
+                corr.emplace_back(cell_off(l, ci, cv1 + 1), -1 - (int)faces.size());
                 corr_fine.push_back(G.foff + 2 * G.nv + G.nx + (ci * rx - G.gx0));
                 corr_nfine.push_back(rx);
                 faces.push_back(F);
             }
+            const int* own_row = B.owner[l].data() + (size_t)hwrap(ci, ncx) * B.lv[l].nv;
             for (int cj = cv0; cj <= cv1; ++cj) {
-                avg_dst[l].push_back(cell_off(l, ci, cj));
+                const int q = own_row[cj];
+                if (q < 0) { nested = false; continue; }
+                avg_dst[l].push_back(B.P[q].off + (long long)(hwrap(ci, ncx) - B.P[q].gx0) * B.P[q].nv + (cj - B.P[q].gv0));
                 avg_src[l].push_back(G.off + (long long)(ci * rx - G.gx0) * G.nv + (cj * rv - G.gv0));
                 avg_stride[l].push_back(G.nv);
             }
@@ -459,13 +476,17 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     }
     if (!nested) return fail(VP_EINVAL, "a coarse-fine face or a covered cell lies outside the parent level");
     H.nfaces = (int)faces.size();
+    // grouped by cell in increasing order, each cell's faces in the order found
+    std::stable_sort(corr.begin(), corr.end(),
+                     [](const std::pair<long long, int>& a, const std::pair<long long, int>& b) { return a.first < b.first; });
     std::vector<int> corr_ptr{0}, corr_face;
     std::vector<long long> corr_cell;
-    for (const auto& kv : corr) {
-        corr_cell.push_back(kv.first);
-        for (int e : kv.second) corr_face.push_back(e);
-        corr_ptr.push_back((int)corr_face.size());
+    for (size_t e = 0; e < corr.size(); ++e) {
+        if (e > 0 && corr[e].first != corr[e - 1].first) corr_ptr.push_back((int)corr_face.size());
+        if (e == 0 || corr[e].first != corr[e - 1].first) corr_cell.push_back(corr[e].first);
+        corr_face.push_back(corr[e].second);
     }
+    if (!corr.empty()) corr_ptr.push_back((int)corr_face.size());
     H.ncorr = (int)corr_cell.size();
 
     // ---- Sub-Patch reduction: each patch minus the next finer level (Alg. subdiv),
@@ -473,7 +494,11 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
     // rows summed over its velocity range, refined in x to the finest mesh
     std::vector<long long> task_off;
     std::vector<int> task_len;
-    std::vector<std::vector<std::pair<int, double>>> contrib(tag_only ? 0 : nfx);
+    struct Contrib {
+        int I, slot;
+        double w;
+    };
+    std::vector<Contrib> contrib;                    // (fine cell, slot, weight), in the order found
     for (size_t pi = 0; pi < (tag_only ? 0 : B.P.size()); ++pi) {
         const HPatch& q = B.P[pi];
         const int l = q.lev;
@@ -519,19 +544,22 @@ vp_status hier_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int
             for (int i = s.xlo; i <= s.xhi; ++i)
                 for (int sx = 0; sx < rt; ++sx)
                     for (int a = -2; a <= 2; ++a)
-                        contrib[(size_t)i * rt + sx].push_back(
-                            {base + (i + a - (s.xlo - 2)), Br[sx * 5 + a + 2] * B.lv[l].dv});
+                        contrib.push_back(Contrib{i * rt + sx, base + (i + a - (s.xlo - 2)), Br[sx * 5 + a + 2] * B.lv[l].dv});
         }
     }
     H.ntasks = (int)task_off.size();
-    std::vector<int> rowptr{0}, idx;
-    std::vector<double> w;
-    for (int I = 0; I < (tag_only ? 0 : nfx); ++I) {
-        for (const auto& c : contrib[I]) {
-            idx.push_back(c.first);
-            w.push_back(c.second);
+    // per fine cell, its terms in the order found (a counting sort)
+    std::vector<int> rowptr(tag_only ? 1 : (size_t)nfx + 1, 0), idx(contrib.size());
+    std::vector<double> w(contrib.size());
+    if (!tag_only) {
+        for (const Contrib& c : contrib) ++rowptr[c.I + 1];
+        for (int I = 0; I < nfx; ++I) rowptr[I + 1] += rowptr[I];
+        std::vector<int> fill(rowptr.begin(), rowptr.end() - 1);
+        for (const Contrib& c : contrib) {
+            const int e = fill[c.I]++;
+            idx[e] = c.slot;
+            w[e] = c.w;
         }
-        rowptr.push_back((int)idx.size());
     }
 
     // ---- device tables
