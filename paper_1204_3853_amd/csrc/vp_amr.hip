@@ -94,8 +94,8 @@ hipError_t upload_fused_lists(AmrPlan& A)
     for (int i = 0; i < A.ncx; ++i) {
         for (int s = 0; s < A.R; ++s) {
             const int I = i * A.R + s;
-            for (const AmrPatch& P : A.patches) {
-                if (I < P.gx0 || I >= P.gx0 + P.nx) continue;
+            for (int e = A.fcol_ptr[I]; e < A.fcol_ptr[I + 1]; ++e) {
+                const AmrPatch& P = A.patches[A.fcol_patch[e]];
                 const int ns = (P.nv + tv - 1) / tv;
                 for (int b = 0; b < ns; ++b)
                     ent.push_back(make_int2((int)(P.fpart + (long long)b * P.nx + (I - P.gx0)), s));
@@ -372,61 +372,106 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
 
     // ---- coverage of coarse cells, coarse-fine faces, corrections, restriction
     const int ncx = M->ncx, ncv = M->ncv;
-    std::vector<int> owner((size_t)ncx * ncv, -1);
+    // per coarse column the velocity runs the patches cover, in increasing
+    // velocity (patches are disjoint): the owner of a coarse cell
+    struct Run {
+        int i, j0, j1, q;
+    };
+    std::vector<Run> runs;
     for (size_t q = 0; q < bx.size(); ++q)
-        for (int i = bx[q].xlo / R; i <= bx[q].xhi / R; ++i)
-            for (int j = bx[q].vlo / R; j <= bx[q].vhi / R; ++j) owner[(size_t)i * ncv + j] = (int)q;
-    auto own = [&](int i, int j) { return owner[(size_t)(((i % ncx) + ncx) % ncx) * ncv + j]; };
-    std::vector<std::vector<int>> corr((size_t)ncx * ncv);   // per coarse cell: encoded faces
-    for (int i = 0; i < ncx; ++i)
-        for (int j = 0; j < ncv; ++j) {
-            // x face between (i, j) and (i + 1, j)
-            const int a = own(i, j), b = own(i + 1, j);
-            if ((a < 0) != (b < 0)) {
-                AmrFace F{i, j, 0, 0};
-                const int q = a >= 0 ? a : b;
-                const AmrPatch& P = M->patches[q];
-                // covered on the high side: the patch's lower x face; else its upper x face
-                F.fine = (int)(P.foff + (a < 0 ? 0 : P.nv) + (j * R - P.gv0));
-                const int fi = (int)M->faces.size();
-                M->faces.push_back(F);
-                if (a < 0) corr[(size_t)i * ncv + j].push_back(fi);                               // face above cell (i, j)
-                else corr[(size_t)(((i + 1) % ncx)) * ncv + j].push_back(-fi - 1);              // face below cell (i+1, j)
-            }
-            if (j + 1 < ncv) {
-                const int c = own(i, j + 1);
-                if ((a < 0) != (c < 0)) {
-                    AmrFace F{i, j, 1, 0};
-                    const int q = a >= 0 ? a : c;
-                    const AmrPatch& P = M->patches[q];
-                    F.fine = (int)(P.foff + 2 * P.nv + (a < 0 ? 0 : P.nx) + (i * R - P.gx0));
-                    const int fi = (int)M->faces.size();
-                    M->faces.push_back(F);
-                    if (a < 0) corr[(size_t)i * ncv + j].push_back(fi);
-                    else corr[(size_t)i * ncv + j + 1].push_back(-fi - 1);
-                }
-            }
+        for (int i = bx[q].xlo / R; i <= bx[q].xhi / R; ++i) runs.push_back(Run{i, bx[q].vlo / R, bx[q].vhi / R, (int)q});
+    std::sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.i != b.i ? a.i < b.i : a.j0 < b.j0; });
+    std::vector<int> run_ptr((size_t)ncx + 1, 0);
+    for (const Run& u : runs) ++run_ptr[u.i + 1];
+    for (int i = 0; i < ncx; ++i) run_ptr[i + 1] += run_ptr[i];
+    auto own = [&](int i, int j) {
+        const int iw = ((i % ncx) + ncx) % ncx;
+        for (int e = run_ptr[iw]; e < run_ptr[iw + 1]; ++e)
+            if (j >= runs[e].j0 && j <= runs[e].j1) return runs[e].q;
+        return -1;
+    };
+    // a coarse face with one covered side lies on a patch's boundary: the
+    // candidates from every patch's four sides, each named by its low cell,
+    // in the order of a row-major scan of the low cells (x face before v face)
+    struct FaceAt {
+        int i, j, dir;
+    };
+    std::vector<FaceAt> cand;
+    for (const Box& X : bx) {
+        const int cx0 = X.xlo / R, cx1 = X.xhi / R, cv0 = X.vlo / R, cv1 = X.vhi / R;
+        for (int j = cv0; j <= cv1; ++j) {
+            if (own(cx0 - 1, j) < 0) cand.push_back(FaceAt{((cx0 - 1) % ncx + ncx) % ncx, j, 0});
+            if (own(cx1 + 1, j) < 0) cand.push_back(FaceAt{cx1, j, 0});
         }
-    std::vector<int> corr_ptr{0}, corr_face, corr_cell;
-    for (size_t c = 0; c < corr.size(); ++c) {
-        if (corr[c].empty()) continue;
-        corr_cell.push_back((int)c);
-        for (int e : corr[c]) corr_face.push_back(e);
-        corr_ptr.push_back((int)corr_face.size());
+        for (int i = cx0; i <= cx1; ++i) {
+            if (cv0 > 0 && own(i, cv0 - 1) < 0) cand.push_back(FaceAt{i, cv0 - 1, 1});
+            if (cv1 + 1 < ncv && own(i, cv1 + 1) < 0) cand.push_back(FaceAt{i, cv1, 1});
+        }
     }
+    std::sort(cand.begin(), cand.end(), [](const FaceAt& a, const FaceAt& b) {
+        return a.i != b.i ? a.i < b.i : (a.j != b.j ? a.j < b.j : a.dir < b.dir);
+    });
+    std::vector<std::pair<int, int>> corr;           // (corrected cell, encoded face), in face order
+    for (const FaceAt& c : cand) {
+        const int i = c.i, j = c.j;
+        const int a = own(i, j);
+        if (c.dir == 0) {            // x face between (i, j) and (i + 1, j)
+            const int b = own(i + 1, j);
+            AmrFace F{i, j, 0, 0};
+            const AmrPatch& P = M->patches[a >= 0 ? a : b];
+            // covered on the high side: the patch's lower x face; else its upper x face
+            F.fine = (int)(P.foff + (a < 0 ? 0 : P.nv) + (j * R - P.gv0));
+            const int fi = (int)M->faces.size();
+            M->faces.push_back(F);
+            if (a < 0) corr.emplace_back(i * ncv + j, fi);                                    // face above cell (i, j)
+            else corr.emplace_back(((i + 1) % ncx) * ncv + j, -fi - 1);                     // face below cell (i+1, j)
+        } else {                     // v face between (i, j) and (i, j + 1)
+            const int b = own(i, j + 1);
+            AmrFace F{i, j, 1, 0};
+            const AmrPatch& P = M->patches[a >= 0 ? a : b];
+            F.fine = (int)(P.foff + 2 * P.nv + (a < 0 ? 0 : P.nx) + (i * R - P.gx0));
+            const int fi = (int)M->faces.size();
+            M->faces.push_back(F);
+            if (a < 0) corr.emplace_back(i * ncv + j, fi);
+            else corr.emplace_back(i * ncv + j + 1, -fi - 1);
+        }
+    }
+    // per corrected cell (increasing), its faces in face order
+    std::stable_sort(corr.begin(), corr.end(),
+                     [](const std::pair<int, int>& x, const std::pair<int, int>& y) { return x.first < y.first; });
+    std::vector<int> corr_ptr{0}, corr_face, corr_cell;
+    for (size_t e = 0; e < corr.size(); ++e) {
+        if (e == 0 || corr[e].first != corr[e - 1].first) {
+            if (e > 0) corr_ptr.push_back((int)corr_face.size());
+            corr_cell.push_back(corr[e].first);
+        }
+        corr_face.push_back(corr[e].second);
+    }
+    if (!corr.empty()) corr_ptr.push_back((int)corr_face.size());
     M->ncorr = (int)corr_cell.size();
+    // covered coarse cells in row-major order
     std::vector<int> cov_cell, cov_nv;
     std::vector<long long> cov_fine;
-    for (int i = 0; i < ncx; ++i)
-        for (int j = 0; j < ncv; ++j) {
-            const int q = owner[(size_t)i * ncv + j];
-            if (q < 0) continue;
-            const AmrPatch& P = M->patches[q];
-            cov_cell.push_back(i * ncv + j);
-            cov_fine.push_back(P.off + (long long)(i * R - P.gx0) * P.nv + (j * R - P.gv0));
+    for (const Run& u : runs) {
+        const AmrPatch& P = M->patches[u.q];
+        for (int j = u.j0; j <= u.j1; ++j) {
+            cov_cell.push_back(u.i * ncv + j);
+            cov_fine.push_back(P.off + (long long)(u.i * R - P.gx0) * P.nv + (j * R - P.gv0));
             cov_nv.push_back(P.nv);
         }
+    }
     M->ncov = (int)cov_cell.size();
+    // the patches over each fine configuration column, in patch order
+    M->fcol_ptr.assign((size_t)M->nfx + 1, 0);
+    for (const AmrPatch& P : M->patches)
+        for (int I = P.gx0; I < P.gx0 + P.nx; ++I) ++M->fcol_ptr[I + 1];
+    for (int I = 0; I < M->nfx; ++I) M->fcol_ptr[I + 1] += M->fcol_ptr[I];
+    M->fcol_patch.assign(M->fcol_ptr.back(), 0);
+    {
+        std::vector<int> at(M->fcol_ptr.begin(), M->fcol_ptr.end() - 1);
+        for (size_t q = 0; q < M->patches.size(); ++q)
+            for (int I = M->patches[q].gx0; I < M->patches[q].gx0 + M->patches[q].nx; ++I) M->fcol_patch[at[I]++] = (int)q;
+    }
 
     // ---- Sub-Patch reduction: Alg. subdiv on the coarse level, then the
     // row-sum tasks (each sub-patch grown by two columns in x) and the
@@ -468,29 +513,39 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->ntasks = (int)task_off.size();
     M->fine_task0 = fine_base.empty() ? M->ntasks : fine_base[0];
     const std::vector<double> B = interp_table(R);
+    // the sub-patches over each coarse column, in sub-patch order
+    std::vector<int> scol_ptr((size_t)ncx + 1, 0), scol;
+    for (const Box& b : S)
+        for (int i = b.xlo; i <= b.xhi; ++i) ++scol_ptr[i + 1];
+    for (int i = 0; i < ncx; ++i) scol_ptr[i + 1] += scol_ptr[i];
+    scol.resize(scol_ptr.back());
+    {
+        std::vector<int> at(scol_ptr.begin(), scol_ptr.end() - 1);
+        for (size_t q = 0; q < S.size(); ++q)
+            for (int i = S[q].xlo; i <= S[q].xhi; ++i) scol[at[i]++] = (int)q;
+    }
     std::vector<int> rowptr{0}, idx;
     std::vector<double> w;
     for (int I = 0; I < M->nfx; ++I) {
         const int i = I / R, s = I % R;
-        for (size_t q = 0; q < S.size(); ++q) {
-            if (i < S[q].xlo || i > S[q].xhi) continue;
+        for (int e = scol_ptr[i]; e < scol_ptr[i + 1]; ++e) {
+            const int q = scol[e];
             for (int a = -2; a <= 2; ++a) {
                 idx.push_back(sub_base[q] + (i + a - (S[q].xlo - 2)));
                 w.push_back(B[s * 5 + a + 2] * M->dvc);
             }
         }
-        for (size_t q = 0; q < M->patches.size(); ++q) {
-            const AmrPatch& P = M->patches[q];
-            if (I < P.gx0 || I >= P.gx0 + P.nx) continue;
-            idx.push_back(fine_base[q] + (I - P.gx0));
+        for (int e = M->fcol_ptr[I]; e < M->fcol_ptr[I + 1]; ++e) {
+            const int q = M->fcol_patch[e];
+            idx.push_back(fine_base[q] + (I - M->patches[q].gx0));
             w.push_back(M->dvf);
         }
         rowptr.push_back((int)idx.size());
     }
 
     // ---- Mask reduction lists: the masked, x-refined coarse sums S[i][a] and the fine row sums
-    std::vector<unsigned char> mask((size_t)ncx * ncv);
-    for (size_t c = 0; c < mask.size(); ++c) mask[c] = owner[c] >= 0 ? 1 : 0;
+    std::vector<unsigned char> mask((size_t)ncx * ncv, 0);
+    for (const Run& u : runs) std::fill_n(mask.begin() + (size_t)u.i * ncv + u.j0, u.j1 - u.j0 + 1, 1);
     std::vector<int> rowptr_m{0}, idx_m;
     std::vector<double> w_m;
     for (int I = 0; I < M->nfx; ++I) {
@@ -499,10 +554,9 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
             idx_m.push_back(i * 5 + a + 2);
             w_m.push_back(B[s * 5 + a + 2] * M->dvc);
         }
-        for (size_t q = 0; q < M->patches.size(); ++q) {
-            const AmrPatch& P = M->patches[q];
-            if (I < P.gx0 || I >= P.gx0 + P.nx) continue;
-            idx_m.push_back(5 * ncx + (fine_base[q] - M->fine_task0) + (I - P.gx0));
+        for (int e = M->fcol_ptr[I]; e < M->fcol_ptr[I + 1]; ++e) {
+            const int q = M->fcol_patch[e];
+            idx_m.push_back(5 * ncx + (fine_base[q] - M->fine_task0) + (I - M->patches[q].gx0));
             w_m.push_back(M->dvf);
         }
         rowptr_m.push_back((int)idx_m.size());
@@ -510,12 +564,12 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
 
     // ---- the Mask reduction from strip partials: each coarse column's
     // covered cells
-    std::vector<int> covc_ptr{0}, covc_j;
-    for (int i = 0; i < ncx; ++i) {
-        for (int j = 0; j < ncv; ++j)
-            if (mask[(size_t)i * ncv + j]) covc_j.push_back(j);
-        covc_ptr.push_back((int)covc_j.size());
+    std::vector<int> covc_ptr((size_t)ncx + 1, 0), covc_j;
+    for (const Run& u : runs) {
+        for (int j = u.j0; j <= u.j1; ++j) covc_j.push_back(j);
+        covc_ptr[u.i + 1] = (int)covc_j.size();
     }
+    for (int i = 0; i < ncx; ++i) covc_ptr[i + 1] = std::max(covc_ptr[i + 1], covc_ptr[i]);
 
     // ---- device tables
     M->w = (M->ncv % 2 == 0 && std::all_of(M->patches.begin(), M->patches.end(),

@@ -190,7 +190,7 @@ vp_status hier_cluster(const vp_plan* p, int l, const uint8_t* tags, int rx, int
     }
     std::vector<unsigned char> t((size_t)nx * nv);
     for (size_t c = 0; c < t.size(); ++c) t[c] = tags[c] && allowed[c];
-    const TagSums st(t, nx, nv);
+    const TagSums st(t, nx, nv, true);
     std::vector<CBox> bx;
     br_cluster(st, CBox{0, 0, nx - 1, nv - 1}, efficiency, min_width, bx);
     for (CBox& b : bx) {

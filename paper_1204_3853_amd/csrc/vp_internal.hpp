@@ -524,6 +524,7 @@ struct AmrPlan {
     int ncoarse_tiles = 0, ntiles = 0, nstrip_c = 1;
     std::vector<AmrTile> tiles;
     std::vector<int> patch_tile_begin;               // per patch, plus the face chunks at the end
+    std::vector<int> fcol_ptr, fcol_patch;           // the patches over each fine configuration column (CSR)
     int face_tile_begin = 0;
     // device tables: one allocation (d_tables) holds every table but the
     // tile table, which a tile shape change rebuilds
@@ -793,13 +794,20 @@ struct CBox {
     long long area() const { return (long long)(xhi - xlo + 1) * (vhi - vlo + 1); }
 };
 // summed-area table of a 0/1 mask of nx x nv cells ([x][v]): the cells set
-// in a box in four lookups
+// in a box in four lookups.  With `bounded`, the table covers only the
+// bounding box of the set cells (none lie outside it), and a box is
+// clipped to it first
 struct TagSums {
-    int nx = 0, nv = 0;
-    std::vector<int> s;                              // s[(i + 1)(nv + 1) + j + 1] = cells set in [0, i] x [0, j]
-    TagSums(const std::vector<unsigned char>& m, int nx_, int nv_);
+    int x0 = 0, v0 = 0, nx = 0, nv = 0;              // the table's window: [x0, x0 + nx) x [v0, v0 + nv)
+    std::vector<int> s;                              // s[(i + 1)(nv + 1) + j + 1] = cells set in the window's [0, i] x [0, j]
+    TagSums(const std::vector<unsigned char>& m, int mx, int mv, bool bounded = false);
     long long count(int xlo, int vlo, int xhi, int vhi) const   // inclusive bounds
     {
+        xlo = std::max(xlo - x0, 0);
+        vlo = std::max(vlo - v0, 0);
+        xhi = std::min(xhi - x0, nx - 1);
+        vhi = std::min(vhi - v0, nv - 1);
+        if (xlo > xhi || vlo > vhi) return 0;
         const size_t w = (size_t)nv + 1;
         return (long long)s[(xhi + 1) * w + vhi + 1] - s[xlo * w + vhi + 1] - s[(xhi + 1) * w + vlo] + s[xlo * w + vlo];
     }

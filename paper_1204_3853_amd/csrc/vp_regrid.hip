@@ -43,13 +43,34 @@ bool level0_of(const vp_plan* p, Level0& L)
 
 }  // namespace
 
-TagSums::TagSums(const std::vector<unsigned char>& m, int nx_, int nv_) : nx(nx_), nv(nv_)
+TagSums::TagSums(const std::vector<unsigned char>& m, int mx, int mv, bool bounded) : nx(mx), nv(mv)
 {
+    if (bounded) {
+        // the rows holding set cells, and the velocity range of those cells
+        int xa = mx, xb = -1, va = mv, vb = -1;
+        for (int i = 0; i < mx; ++i) {
+            const unsigned char* r = m.data() + (size_t)i * mv;
+            const unsigned char* f = std::find_if(r, r + mv, [](unsigned char c) { return c != 0; });
+            if (f == r + mv) continue;
+            const unsigned char* l = r + mv - 1;
+            while (*l == 0) --l;
+            xa = std::min(xa, i);
+            xb = i;
+            va = std::min(va, (int)(f - r));
+            vb = std::max(vb, (int)(l - r));
+        }
+        if (xb < 0) { xa = xb = 0; va = vb = 0; }
+        x0 = xa;
+        v0 = va;
+        nx = xb - xa + 1;
+        nv = vb - va + 1;
+    }
     s.assign((size_t)(nx + 1) * (nv + 1), 0);
     for (int i = 0; i < nx; ++i) {
+        const unsigned char* r = m.data() + (size_t)(x0 + i) * mv + v0;
         int row = 0;
         for (int j = 0; j < nv; ++j) {
-            row += m[(size_t)i * nv + j] != 0;
+            row += r[j] != 0;
             s[(size_t)(i + 1) * (nv + 1) + j + 1] = s[(size_t)i * (nv + 1) + j + 1] + row;
         }
     }
@@ -129,7 +150,7 @@ void br_cluster(const TagSums& T, CBox B, double eff, int minw, std::vector<CBox
 
 void br_cluster(const std::vector<unsigned char>& tag, int nv, CBox B, double eff, int minw, std::vector<CBox>& out)
 {
-    br_split(TagSums(tag, (int)(tag.size() / (size_t)nv), nv), B, eff, minw, out);
+    br_split(TagSums(tag, (int)(tag.size() / (size_t)nv), nv, true), B, eff, minw, out);
 }
 
 namespace {
