@@ -44,8 +44,8 @@ vp_status pad_launch(const vp_plan* p, const double* f, double* pad, double* scr
     const Amr4DPlan& M = *p->a4;
     VP_HIP(timed(p, kTOther, stream, [&] {
         return launch_a4_pad(f, M.d_patches, M.d_list, (int)M.patches.size(), (long long)M.pad_total, M.d_nb, M.lv,
-                             M.d_B, M.R, M.d_gxc, M.d_gyc, M.d_gxf, M.d_gyf, M.d_interp, M.pass_total, scratch, pad,
-                             stream);
+                             M.d_B, M.R, M.d_gxc, M.d_gyc, M.d_gxf, M.d_gyf, M.d_interp, M.pass_total, M.ptiles, scratch,
+                             pad, stream);
     }));
     return VP_OK;
 }
@@ -394,8 +394,25 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
         }
     }
     const size_t scratch_elems = (size_t)std::max<long long>(acc_o, 1);
+    // block tables of the padded copies (every patch) and of the passes
+    std::vector<int2> ptile, itile[3];
+    for (size_t q = 0; q < P.size(); ++q) {
+        const A4Patch& Pq = P[list[q]];
+        const long long n = (long long)(Pq.sz[0] + 4) * (Pq.sz[1] + 4) * (Pq.sz[2] + 4) * (Pq.sz[3] + 4);
+        for (long long c = 0; c < n; c += 256) ptile.push_back(make_int2((int)q, (int)c));
+    }
+    for (int dir = 0; dir < 3; ++dir)
+        for (size_t e = 0; e < ip.size(); ++e) {
+            long long n = 1;
+            for (int d = 0; d < 4; ++d) n *= d <= dir ? ip[e].pn[d] : ip[e].cn[d];
+            for (long long c = 0; c < n; c += 256) itile[dir].push_back(make_int2((int)e, (int)c));
+        }
+    int2* d_pt = nullptr;
+    int2* d_it[3] = {nullptr, nullptr, nullptr};
 
     TableArena T;
+    T.add(&d_pt, ptile);
+    for (int dir = 0; dir < 3; ++dir) T.add(&d_it[dir], itile[dir]);
     T.add(&M.d_interp, ip);
     T.add(&M.d_patches, P);
     T.add(&M.d_list, list);
@@ -425,6 +442,12 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     T.add(&M.d_Qy, Qy);
     T.add(&M.d_inv, inv);
     VP_HIP(T.commit(&M.d_tables));
+    M.ptiles.pad = d_pt;
+    M.ptiles.npad = (int)ptile.size();
+    for (int dir = 0; dir < 3; ++dir) {
+        M.ptiles.pass[dir] = d_it[dir];
+        M.ptiles.npass[dir] = (int)itile[dir].size();
+    }
     VP_HIP(hipMalloc(&M.d_rhs_pad, std::max<size_t>(M.pad_total, 1) * sizeof(double)));
     VP_HIP(hipMalloc(&M.d_rhs_scratch, scratch_elems * sizeof(double)));
     VP_HIP(hipMalloc(&M.d_g, (size_t)2 * nfx * nfy * sizeof(double)));

@@ -207,6 +207,13 @@ struct A4Interp {              // separable sub-cell interpolation over one leve
     double ipn[4], icn[4];     // 1 / pn and 1 / cn, for index decoding
 };
 
+struct A4PadTiles {            // blocks of 256 elements of one patch: (patch, its first element)
+    const int2* pad;           // padded copies, every patch in list order
+    int npad;
+    const int2* pass[3];       // interpolation passes: (level-1 patch's A4Interp index, first result)
+    int npass[3];
+};
+
 struct A4Face {                // a level-0 face on a coarse-fine interface
     int cell[4];               // the low cell (the face is its upper face along dir)
     int dir;
@@ -216,7 +223,7 @@ struct A4Face {                // a level-0 face on a coarse-fine interface
 hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
                          const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
                          const double* gyc, const double* gxf, const double* gyf, const A4Interp* ip,
-                         const long long* pass_total, double* scratch, double* pad, hipStream_t stream);
+                         const long long* pass_total, const A4PadTiles& tl, double* scratch, double* pad, hipStream_t stream);
 hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream);
 hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, double* cf_acc, hipStream_t stream);
 // masked plane sums of level 0 for the Mask reduction; S: ncx ncy doubles of scratch
@@ -593,6 +600,7 @@ struct Amr4DPlan {
     A4Face* d_faces = nullptr;
     A4Interp* d_interp = nullptr;                    // per level-1 patch, the separable interpolation passes
     long long pass_total[3] = {0, 0, 0};
+    A4PadTiles ptiles{};                             // block tables of the padded copies and the passes
     double* d_rhs_scratch = nullptr;                 // pass results of vp_rhs calls
     int* d_rect_ptr = nullptr;                       // per level-0 column: its covered velocity rectangles
     int4* d_rects = nullptr;

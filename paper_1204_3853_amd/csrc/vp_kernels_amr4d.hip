@@ -125,6 +125,7 @@ struct A4PadArgs {
     int nip;
     double* scratch;           // pass results
     double* pad;
+    A4PadTiles tl;
 };
 
 // level-0 value with x, y periodic and the coarse equilibrium product outside the velocity box
@@ -141,18 +142,11 @@ __device__ __forceinline__ double coarse_at(const A4PadArgs& A, int i, int j, in
 // and vy): DIR 0 reads level 0 and interpolates along x, DIR 1 along y,
 // DIR 2 along vx; the vy pass is the last step of k_a4_pad.
 template <int DIR>
-__global__ __launch_bounds__(256) void k_a4_interp(A4PadArgs A, long long total)
+__global__ __launch_bounds__(256) void k_a4_interp(A4PadArgs A)
 {
-    const long long first = A.ip[0].o[DIR];              // the pass's results start here
-    const long long g = first + (long long)blockIdx.x * 256 + threadIdx.x;
-    if (g >= first + total) return;
-    int lo = 0, hi = A.nip - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (A.ip[mid].o[DIR] <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    const A4Interp Q = A.ip[lo];
+    // the block's patch and first result from the block table
+    const int2 tb = A.tl.pass[DIR][blockIdx.x];
+    const A4Interp Q = A.ip[tb.x];
     // output extents: fine along x .. DIR, coarse after
     int ext[4];
     double iext[4];
@@ -161,7 +155,9 @@ __global__ __launch_bounds__(256) void k_a4_interp(A4PadArgs A, long long total)
         ext[d] = d <= DIR ? Q.pn[d] : Q.cn[d];
         iext[d] = d <= DIR ? Q.ipn[d] : Q.icn[d];
     }
-    int r = (int)(g - Q.o[DIR]);
+    int r = tb.y + (int)threadIdx.x;
+    if (r >= ext[0] * ext[1] * ext[2] * ext[3]) return;
+    const long long g = Q.o[DIR] + r;
     int idx[4];
     idx[3] = divmod_rcp(r, ext[3], iext[3]);
     idx[2] = divmod_rcp(r, ext[2], iext[2]);
@@ -205,19 +201,14 @@ __global__ __launch_bounds__(256) void k_a4_interp(A4PadArgs A, long long total)
     A.scratch[g] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_a4_pad(A4PadArgs A, long long total)
+__global__ __launch_bounds__(256) void k_a4_pad(A4PadArgs A)
 {
-    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (g >= total) return;
-    // the patch whose padded range holds g (patches are listed in padded order)
-    int lo = 0, hi = A.npatch - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (A.patches[A.list[mid]].pad <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    const A4Patch P = A.patches[A.list[lo]];
-    int r = (int)(g - P.pad);
+    // the block's patch and first padded element from the block table
+    const int2 tb = A.tl.pad[blockIdx.x];
+    const A4Patch P = A.patches[A.list[tb.x]];
+    int r = tb.y + (int)threadIdx.x;
+    if (r >= (P.sz[0] + 4) * (P.sz[1] + 4) * (P.sz[2] + 4) * (P.sz[3] + 4)) return;
+    const long long g = P.pad + r;
     const int l = divmod_rcp(r, P.sz[3] + 4, P.ipz[3]) - 2;
     const int k = divmod_rcp(r, P.sz[2] + 4, P.ipz[2]) - 2;
     const int j = divmod_rcp(r, P.sz[1] + 4, P.ipz[1]) - 2;
@@ -253,7 +244,7 @@ __global__ __launch_bounds__(256) void k_a4_pad(A4PadArgs A, long long total)
             if (!held) {
                 // the last (vy) pass of the separable interpolation over the
                 // results of the x, y and vx passes
-                const A4Interp Q = A.ip[A.list[lo] - 1];
+                const A4Interp Q = A.ip[A.list[tb.x] - 1];
                 const int R = A.R;
                 const int cl = Lv / R;
                 const double* bl = A.B + (Lv - cl * R) * 5;
@@ -544,7 +535,8 @@ __global__ __launch_bounds__(256) void k_a4_average(double* __restrict__ f, cons
 hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
                          const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
                          const double* gyc, const double* gxf, const double* gyf, const A4Interp* ip,
-                         const long long* pass_total, double* scratch, double* pad, hipStream_t stream)
+                         const long long* pass_total, const A4PadTiles& tl, double* scratch, double* pad,
+                         hipStream_t stream)
 {
     if (total <= 0) return hipSuccess;
     A4PadArgs A{};
@@ -565,15 +557,14 @@ hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* lis
     A.nip = npatch - 1;
     A.scratch = scratch;
     A.pad = pad;
+    A.tl = tl;
+    (void)pass_total;
     if (A.nip > 0) {
-        hipLaunchKernelGGL(k_a4_interp<0>, dim3((unsigned)((pass_total[0] + 255) / 256)), dim3(256), 0, stream, A,
-                           pass_total[0]);
-        hipLaunchKernelGGL(k_a4_interp<1>, dim3((unsigned)((pass_total[1] + 255) / 256)), dim3(256), 0, stream, A,
-                           pass_total[1]);
-        hipLaunchKernelGGL(k_a4_interp<2>, dim3((unsigned)((pass_total[2] + 255) / 256)), dim3(256), 0, stream, A,
-                           pass_total[2]);
+        if (tl.npass[0] > 0) hipLaunchKernelGGL(k_a4_interp<0>, dim3(tl.npass[0]), dim3(256), 0, stream, A);
+        if (tl.npass[1] > 0) hipLaunchKernelGGL(k_a4_interp<1>, dim3(tl.npass[1]), dim3(256), 0, stream, A);
+        if (tl.npass[2] > 0) hipLaunchKernelGGL(k_a4_interp<2>, dim3(tl.npass[2]), dim3(256), 0, stream, A);
     }
-    hipLaunchKernelGGL(k_a4_pad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, A, total);
+    if (tl.npad > 0) hipLaunchKernelGGL(k_a4_pad, dim3(tl.npad), dim3(256), 0, stream, A);
     return hipGetLastError();
 }
 
