@@ -55,10 +55,8 @@ vp_status moment(const vp_plan* p, const double* f, double* n, void* work, hipSt
     const Amr4DPlan& M = *p->a4;
     double* slots = reinterpret_cast<double*>(wp(work, M.ws_slots));
     VP_HIP(timed(p, kTMoment, stream, [&] {
-        double* psum = reinterpret_cast<double*>(wp(work, M.ws_psum));
-        hipError_t e = launch_a4_masked(f, M.d_rect_ptr, M.d_rects, M.nc, psum, slots, stream);
-        if (e == hipSuccess)
-            e = launch_amr_rowsum(f, M.d_task_off, M.d_task_len, M.ntasks, slots + 25 * M.nc[0] * M.nc[1], stream);
+        hipError_t e = launch_a4_moment_sums(f, M.d_rect_ptr, M.d_rects, M.nc, M.d_task_off, M.d_task_len, M.ntasks,
+                                             slots, stream);
         if (e == hipSuccess) e = launch_amr_reduce_finalize(slots, M.d_rowptr, M.d_idx, M.d_w, M.ncfg, n, stream);
         return e;
     }));
@@ -464,7 +462,6 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
     M.ws_cf = o; o += al256(std::max<size_t>(faces.size(), 1) * sizeof(double));
     M.ws_slots = o; o += al256((size_t)(m0 + M.ntasks) * sizeof(double));
     M.ws_n = o; o += al256((size_t)nfx * nfy * sizeof(double));
-    M.ws_psum = o; o += al256((size_t)ncx * ncy * sizeof(double));
     M.ws_g = o; o += al256((size_t)2 * nfx * nfy * sizeof(double));
     p->ws_total = o;
     p->state_elems = M.total;

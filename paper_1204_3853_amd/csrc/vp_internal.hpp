@@ -226,9 +226,11 @@ hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* lis
                          const long long* pass_total, const A4PadTiles& tl, double* scratch, double* pad, hipStream_t stream);
 hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream);
 hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, double* cf_acc, hipStream_t stream);
-// masked plane sums of level 0 for the Mask reduction; S: ncx ncy doubles of scratch
-hipError_t launch_a4_masked(const double* f0, const int* rp, const int4* rects, const int* n, double* S, double* M,
-                            hipStream_t stream);
+// the Mask reduction's sums: masked plane sums of level 0 (M[t * 25 + s]) and
+// level-1 row segments (M[25 ncx ncy + k]), one launch
+hipError_t launch_a4_moment_sums(const double* f, const int* rp, const int4* rects, const int* n,
+                                const long long* task_off, const int* task_len, int ntasks, double* M,
+                                hipStream_t stream);
 hipError_t launch_a4_inject(double* a, int ncx, int ncy, int R, hipStream_t stream);
 hipError_t launch_a4_reflux(double* f, const long long* cell, const int* ptr, const int* code, const int* fine,
                             int nfine, const double* ff, const double* cf, const A4Face* faces, const double* hdt, double dt,
@@ -619,7 +621,7 @@ struct Amr4DPlan {
     double *d_Qx = nullptr, *d_Qy = nullptr, *d_inv = nullptr;   // fine configuration mesh Fourier tables
     double* d_rhs_pad = nullptr;                     // padded copies for vp_rhs, which takes no workspace
     double* d_g = nullptr;                           // Fourier coefficients of vp_poisson_periodic calls
-    size_t ws_pad = 0, ws_ff = 0, ws_cf = 0, ws_slots = 0, ws_n = 0, ws_g = 0, ws_interp = 0, ws_psum = 0;
+    size_t ws_pad = 0, ws_ff = 0, ws_cf = 0, ws_slots = 0, ws_n = 0, ws_g = 0, ws_interp = 0;
 };
 
 // multi-level plan (vp_hier.hip): L levels, a ratio per level and direction

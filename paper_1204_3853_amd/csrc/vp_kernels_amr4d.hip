@@ -433,45 +433,61 @@ __global__ __launch_bounds__(256) void k_a4_faces(A4Args A, const A4Face* __rest
     else cf[q] += A.c_flux * G;
 }
 
-// S[c] = sum over the velocity plane of level-0 configuration column c, one wave per column
-__global__ __launch_bounds__(256) void k_a4_planesum(const double* __restrict__ f0, int ncol, int plane,
-                                                    double* __restrict__ S)
+// The sums the Mask reduction combines, in one launch.  Blocks below ncx ncy:
+// one per level-0 configuration column c, whose velocity plane sum S the
+// block forms once; every masked sum that reads column c (target column
+// c - (a, b) for stencil offsets a, b in [-2, 2], masked by the velocity
+// rectangles level 1 covers in the target column, rects[rp[t] .. rp[t+1]),
+// k0 k1 l0 l1 inclusive) is S less the covered cells, which one wave reads
+// back (the block has just read the plane, so from the caches), and goes to
+// M[t * 25 + (a+2) * 5 + (b+2)].  Blocks from ncx ncy on: one wave per
+// level-1 row segment, M[25 ncx ncy + k] = the sum of len[k] consecutive
+// values at off[k].
+__global__ __launch_bounds__(256) void k_a4_moment_sums(const double* __restrict__ f, const int* __restrict__ rp,
+                                                       const int4* __restrict__ rects, int ncx, int ncy, int nvy,
+                                                       int plane, const long long* __restrict__ off,
+                                                       const int* __restrict__ len, int ntasks,
+                                                       double* __restrict__ M)
 {
-    const int c = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (c >= ncol) return;
-    const double* src = f0 + (long long)c * plane;
-    double acc = 0.0;
-    for (int q = lane; q < plane; q += 64) acc += src[q];
-    acc = wave_sum(acc);
-    if (lane == 0) S[c] = acc;
-}
-
-// M[((i ncy + j) * 25 + (a+2) * 5 + (b+2)] = sum over the velocity plane of
-// level-0 column (i + a, j + b) masked by the coverage of column (i, j):
-// the plane sum less the cells of the velocity rectangles level 1 covers in
-// column (i, j) (rects[rp[c] .. rp[c+1]), k0 k1 l0 l1 inclusive); one wave
-// per sum
-__global__ __launch_bounds__(256) void k_a4_masked(const double* __restrict__ f0, const double* __restrict__ S,
-                                                  const int* __restrict__ rp, const int4* __restrict__ rects,
-                                                  int ncx, int ncy, int nvy, int plane, double* __restrict__ M)
-{
-    const int task = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (task >= 25 * ncx * ncy) return;
-    const int cell = task / 25, s = task - cell * 25;
-    const int i = cell / ncy, j = cell - (cell / ncy) * ncy;
-    const int a = s / 5 - 2, b = s % 5 - 2;
-    const int col = wrap4(i + a, ncx) * ncy + wrap4(j + b, ncy);
-    const double* src = f0 + (long long)col * plane;
-    double cov = 0.0;
-    for (int e = rp[cell]; e < rp[cell + 1]; ++e) {
-        const int4 r = rects[e];
-        const int w = r.w - r.z + 1, cnt = (r.y - r.x + 1) * w;
-        for (int q = lane; q < cnt; q += 64) cov += src[(r.x + q / w) * nvy + r.z + q % w];
+    __shared__ double red[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int ncol = ncx * ncy;
+    if ((int)blockIdx.x >= ncol) {
+        const int task = ((int)blockIdx.x - ncol) * 4 + wv;
+        if (task >= ntasks) return;                      // uniform per wave
+        const double* p = f + off[task];
+        const int n = len[task];
+        double s = 0.0;
+        for (int j = lane; j < n; j += 64) s += p[j];
+        s = wave_sum(s);
+        if (lane == 0) M[25 * ncol + task] = s;
+        return;
     }
-    cov = wave_sum(cov);
-    if (lane == 0) M[task] = S[col] - cov;
+    const int c = (int)blockIdx.x;
+    const int ci = c / ncy, cj = c - ci * ncy;
+    const double* src = f + (long long)c * plane;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int q = t; q < plane; q += 256) acc += src[q];
+    acc = wave_sum(acc);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    const double S = ((red[0] + red[1]) + red[2]) + red[3];
+    for (int s = wv; s < 25; s += 4) {
+        const int a = s / 5 - 2, b = s - (s / 5) * 5 - 2;
+        const int tgt = wrap4(ci - a, ncx) * ncy + wrap4(cj - b, ncy);
+        const int e0 = rp[tgt], e1 = rp[tgt + 1];
+        double cov = 0.0;
+        if (e0 < e1) {                                   // uniform per wave
+            for (int e = e0; e < e1; ++e) {
+                const int4 r = rects[e];
+                const int w = r.w - r.z + 1, cnt = (r.y - r.x + 1) * w;
+                for (int q = lane; q < cnt; q += 64) cov += src[(r.x + q / w) * nvy + r.z + q % w];
+            }
+            cov = wave_sum(cov);
+        }
+        if (lane == 0) M[tgt * 25 + s] = S - cov;
+    }
 }
 
 // the coarse acceleration: the mean of the R x R fine values of each component
@@ -588,13 +604,14 @@ hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, dou
     return hipGetLastError();
 }
 
-hipError_t launch_a4_masked(const double* f0, const int* rp, const int4* rects, const int* n, double* S, double* M,
-                            hipStream_t stream)
+hipError_t launch_a4_moment_sums(const double* f, const int* rp, const int4* rects, const int* n,
+                                const long long* task_off, const int* task_len, int ntasks, double* M,
+                                hipStream_t stream)
 {
-    const int ncol = n[0] * n[1], tasks = 25 * ncol;
-    hipLaunchKernelGGL(k_a4_planesum, dim3((ncol + 3) / 4), dim3(256), 0, stream, f0, ncol, n[2] * n[3], S);
-    hipLaunchKernelGGL(k_a4_masked, dim3((tasks + 3) / 4), dim3(256), 0, stream, f0, S, rp, rects, n[0], n[1], n[3],
-                       n[2] * n[3], M);
+    const int ncol = n[0] * n[1];
+    const int blocks = ncol + (ntasks + 3) / 4;
+    hipLaunchKernelGGL(k_a4_moment_sums, dim3(blocks), dim3(256), 0, stream, f, rp, rects, n[0], n[1], n[3],
+                       n[2] * n[3], task_off, task_len, ntasks, M);
     return hipGetLastError();
 }
 
