@@ -72,6 +72,10 @@ vp_status constraint(const vp_plan* p, const double* f, double* a, void* work, h
     if (vp_status st = moment(p, f, n, work, stream)) return st;
     const int nc = M.nc[0] * M.nc[1];
     VP_HIP(timed(p, kTField, stream, [&] {
+        // small fine meshes: the inverse transform also forms the coarse a
+        if (M.nf[0] <= kPoisson2DSmall && M.nf[1] <= kPoisson2DSmall)
+            return launch_poisson2d_coarse(n, M.nf[0], M.nf[1], M.lv[1].h[0], M.lv[1].h[1], p->pb.qm, M.d_Qx, M.d_Qy,
+                                           M.d_inv, g, nullptr, nullptr, a + 2 * nc, M.R, a, stream);
         hipError_t e = launch_poisson2d(n, M.nf[0], M.nf[1], M.lv[1].h[0], M.lv[1].h[1], p->pb.qm, M.d_Qx, M.d_Qy,
                                         M.d_inv, g, nullptr, nullptr, a + 2 * nc, stream);
         if (e == hipSuccess) e = launch_a4_inject(a, M.nc[0], M.nc[1], M.R, stream);

@@ -441,6 +441,12 @@ hipError_t launch_moment4d(const double* f, int ncfg, size_t plane, double scale
 hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double dy, double qm, const double* Qx,
                             const double* Qy, const double* invlamT, double* g, double* phi, double* E, double* a,
                             hipStream_t stream);
+// the same, and with a_coarse (R = 2 or 4, nx and ny <= 64, multiples of R) also
+// the mean of the R x R fine accelerations over each cell of the coarse mesh
+// of nx/R x ny/R cells, components one after the other
+hipError_t launch_poisson2d_coarse(const double* n, int nx, int ny, double dx, double dy, double qm,
+                                   const double* Qx, const double* Qy, const double* invlamT, double* g, double* phi,
+                                   double* E, double* a, int R, double* a_coarse, hipStream_t stream);
 
 // two-level launchers (vp_kernels_amr.hip)
 hipError_t launch_amr_stage(int w, int nt, int kind, const AmrArgs& a, int t_begin, int t_end, int grid,

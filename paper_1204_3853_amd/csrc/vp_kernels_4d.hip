@@ -402,26 +402,33 @@ __global__ __launch_bounds__(256) void k_poisson2d_fwd(const double* __restrict_
     }
 }
 
-// block i: phi at rows i-2 .. i+2 (periodic), phi[i'][j] = sum_l h[i'][l] Qy[j][l]
-// with h[i'][l] = sum_k Qx[i'][k] g[k][l]; then E and a at row i
+// block b: phi at rows R b - 2 .. R b + R + 1 (periodic), phi[i'][j] =
+// sum_l h[i'][l] Qy[j][l] with h[i'][l] = sum_k Qx[i'][k] g[k][l]; then E
+// and a at rows R b .. R b + R - 1.  R > 1 (the fine configuration mesh of a
+// two-level hierarchy of ratio R): also the coarse a of coarse row b, the
+// mean of the R x R fine values over each coarse cell.
+template <int R>
 __global__ __launch_bounds__(256) void k_poisson2d_inv(const double* __restrict__ g, int nx, int ny, double dx,
                                                       double dy, double qm, const double* __restrict__ Qx,
                                                       const double* __restrict__ Qy, double* __restrict__ phi_out,
-                                                      double* __restrict__ E_out, double* __restrict__ a_out)
+                                                      double* __restrict__ E_out, double* __restrict__ a_out,
+                                                      double* __restrict__ a_coarse)
 {
     constexpr int SEG = kP2 / kP2Q;
-    __shared__ double part[kP2Q][5][kP2];
-    __shared__ double h[5][kP2];
-    __shared__ double ph[5][kP2];
-    __shared__ double qx[5][kP2];
+    constexpr int NR = R + 4;                    // potential rows of the block
+    __shared__ double part[kP2Q][NR][kP2];
+    __shared__ double h[NR][kP2];
+    __shared__ double ph[NR][kP2];
+    __shared__ double qx[NR][kP2];
+    __shared__ double af[2][R][kP2];
     const int t = threadIdx.x, lane = t & 63, q = t >> 6;
-    const int i = blockIdx.x;
+    const int i0 = (int)blockIdx.x * R;
     const int N = nx * ny;
-    // Qx rows i-2 .. i+2 into LDS; g column l = lane for k in [SEG q, SEG q + SEG);
+    // Qx rows i0-2 .. i0+R+1 into LDS; g column l = lane for k in [SEG q, SEG q + SEG);
     // Qy[j = lane][l] for l in [SEG q, SEG q + SEG)
-    for (int e = t; e < 5 * kP2; e += 256) {
+    for (int e = t; e < NR * kP2; e += 256) {
         const int r = e / kP2, kk = e - r * kP2;
-        qx[r][kk] = kk < nx ? Qx[wrapi(i - 2 + r, nx) * nx + kk] : 0.0;
+        qx[r][kk] = kk < nx ? Qx[wrapi(i0 - 2 + r, nx) * nx + kk] : 0.0;
     }
     double vg[SEG], vy[SEG];
 #pragma unroll
@@ -433,41 +440,56 @@ __global__ __launch_bounds__(256) void k_poisson2d_inv(const double* __restrict_
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 5; ++r) {
+    for (int r = 0; r < NR; ++r) {
         double acc = 0.0;
 #pragma unroll
         for (int u = 0; u < SEG; ++u) acc += qx[r][q * SEG + u] * vg[u];
         part[q][r][lane] = acc;
     }
     __syncthreads();
-    for (int e = t; e < 5 * kP2; e += 256) {
+    for (int e = t; e < NR * kP2; e += 256) {
         const int r = e / kP2, l = e - r * kP2;
         h[r][l] = ((part[0][r][l] + part[1][r][l]) + part[2][r][l]) + part[3][r][l];
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 5; ++r) {
+    for (int r = 0; r < NR; ++r) {
         double acc = 0.0;
 #pragma unroll
         for (int u = 0; u < SEG; ++u) acc += h[r][q * SEG + u] * vy[u];
         part[q][r][lane] = acc;
     }
     __syncthreads();
-    for (int e = t; e < 5 * kP2; e += 256) {
+    for (int e = t; e < NR * kP2; e += 256) {
         const int r = e / kP2, jj = e - r * kP2;
         ph[r][jj] = ((part[0][r][jj] + part[1][r][jj]) + part[2][r][jj]) + part[3][r][jj];
     }
     __syncthreads();
-    if (t < ny) {
-        const int jj = t;
+    for (int e = t; e < R * ny; e += 256) {
+        const int rr = e / ny, jj = e - rr * ny;
+        const int c = rr + 2;                    // the row's potential row
         const int jp1 = wrapi(jj + 1, ny), jm1 = wrapi(jj - 1, ny), jp2 = wrapi(jj + 2, ny), jm2 = wrapi(jj - 2, ny);
         const double cx = 1.0 / (12.0 * dx), cy = 1.0 / (12.0 * dy);
-        const double ex = -(8.0 * (ph[3][jj] - ph[1][jj]) - (ph[4][jj] - ph[0][jj])) * cx;
-        const double ey = -(8.0 * (ph[2][jp1] - ph[2][jm1]) - (ph[2][jp2] - ph[2][jm2])) * cy;
-        const int e = i * ny + jj;
-        if (phi_out) phi_out[e] = ph[2][jj];
-        if (E_out) { E_out[e] = ex; E_out[N + e] = ey; }
-        if (a_out) { a_out[e] = qm * ex; a_out[N + e] = qm * ey; }
+        const double ex = -(8.0 * (ph[c + 1][jj] - ph[c - 1][jj]) - (ph[c + 2][jj] - ph[c - 2][jj])) * cx;
+        const double ey = -(8.0 * (ph[c][jp1] - ph[c][jm1]) - (ph[c][jp2] - ph[c][jm2])) * cy;
+        const int o = (i0 + rr) * ny + jj;
+        if (phi_out) phi_out[o] = ph[c][jj];
+        if (E_out) { E_out[o] = ex; E_out[N + o] = ey; }
+        if (a_out) { a_out[o] = qm * ex; a_out[N + o] = qm * ey; }
+        if (R > 1) { af[0][rr][jj] = qm * ex; af[1][rr][jj] = qm * ey; }
+    }
+    if (R > 1) {
+        __syncthreads();
+        const int ncy = ny / R, nc = (nx / R) * ncy;
+        for (int e = t; e < 2 * ncy; e += 256) {
+            const int comp = e / ncy, jc = e - comp * ncy;
+            double s = 0.0;
+#pragma unroll
+            for (int u = 0; u < R; ++u)
+#pragma unroll
+                for (int w = 0; w < R; ++w) s += af[comp][u][jc * R + w];
+            a_coarse[comp * nc + (int)blockIdx.x * ncy + jc] = s / (R * R);
+        }
     }
 }
 
@@ -583,10 +605,27 @@ hipError_t launch_poisson2d(const double* n, int nx, int ny, double dx, double d
                             const double* Qy, const double* invlamT, double* g, double* phi, double* E, double* a,
                             hipStream_t stream)
 {
+    return launch_poisson2d_coarse(n, nx, ny, dx, dy, qm, Qx, Qy, invlamT, g, phi, E, a, 1, nullptr, stream);
+}
+
+hipError_t launch_poisson2d_coarse(const double* n, int nx, int ny, double dx, double dy, double qm,
+                                   const double* Qx, const double* Qy, const double* invlamT, double* g, double* phi,
+                                   double* E, double* a, int R, double* a_coarse, hipStream_t stream)
+{
     if (nx > kMaxPoisson2D || ny > kMaxPoisson2D || nx < 1 || ny < 1 || !g) return hipErrorInvalidValue;
+    if (a_coarse && ((R != 2 && R != 4) || nx % R || ny % R || nx > kPoisson2DSmall || ny > kPoisson2DSmall))
+        return hipErrorInvalidValue;
     if (nx <= kPoisson2DSmall && ny <= kPoisson2DSmall) {
         hipLaunchKernelGGL(k_poisson2d_fwd, dim3(nx), dim3(256), 0, stream, n, nx, ny, Qx, Qy, invlamT, g);
-        hipLaunchKernelGGL(k_poisson2d_inv, dim3(nx), dim3(256), 0, stream, g, nx, ny, dx, dy, qm, Qx, Qy, phi, E, a);
+        if (!a_coarse)
+            hipLaunchKernelGGL(k_poisson2d_inv<1>, dim3(nx), dim3(256), 0, stream, g, nx, ny, dx, dy, qm, Qx, Qy, phi,
+                               E, a, nullptr);
+        else if (R == 2)
+            hipLaunchKernelGGL(k_poisson2d_inv<2>, dim3(nx / 2), dim3(256), 0, stream, g, nx, ny, dx, dy, qm, Qx, Qy,
+                               phi, E, a, a_coarse);
+        else
+            hipLaunchKernelGGL(k_poisson2d_inv<4>, dim3(nx / 4), dim3(256), 0, stream, g, nx, ny, dx, dy, qm, Qx, Qy,
+                               phi, E, a, a_coarse);
         return hipGetLastError();
     }
     // g holds the coefficients, then the potential; Qy is followed by its transpose
