@@ -548,11 +548,10 @@ vp_status a4_rk4(const vp_plan* p, void* f, double* a, double dt, void* work, hi
         A.c_next = s < 3 ? cnext[s] : 0.0;
         A.c_flux = b[s];
         A.first = s == 0;
-        VP_HIP(timed(p, kTStage, stream, [&] {
-            hipError_t e = launch_a4_stage(kind, A, stream);
-            if (e == hipSuccess) e = launch_a4_faces(A, M.d_faces, M.nfaces, cf, stream);
-            return e;
-        }));
+        A.faces = M.d_faces;
+        A.nfaces = M.nfaces;
+        A.cf = cf;
+        VP_HIP(timed(p, kTStage, stream, [&] { return launch_a4_stage(kind, A, stream); }));
         if (s < 3) {
             if (vp_status st = pad_launch(p, out[s], pad, scr, stream)) return st;
             if (vp_status st = constraint(p, out[s], a, work, stream)) return st;

@@ -183,6 +183,12 @@ struct A4Level {
 
 constexpr int kA4VxRun = 2;  // cells along vx per thread of the two-level 2D+2V stage kernel
 
+struct A4Face {                // a level-0 face on a coarse-fine interface
+    int cell[4];               // the low cell (the face is its upper face along dir)
+    int dir;
+    int pad_;
+};
+
 struct A4Args {
     A4Level lv[2];
     const A4Patch* patches;
@@ -196,6 +202,9 @@ struct A4Args {
     double* fout;
     const double* a;
     double* ff_acc;            // accumulated patch boundary fluxes
+    const A4Face* faces;       // level-0 faces on coarse-fine interfaces: their fluxes go to cf
+    int nfaces;                // (RK4 stages only; blocks after the tiles)
+    double* cf;
     double c_acc, c_next, c_flux;
     int first;
 };
@@ -214,18 +223,12 @@ struct A4PadTiles {            // blocks of 256 elements of one patch: (patch, i
     int npass[3];
 };
 
-struct A4Face {                // a level-0 face on a coarse-fine interface
-    int cell[4];               // the low cell (the face is its upper face along dir)
-    int dir;
-    int pad_;
-};
 
 hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
                          const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
                          const double* gyc, const double* gxf, const double* gyf, const A4Interp* ip,
                          const long long* pass_total, const A4PadTiles& tl, double* scratch, double* pad, hipStream_t stream);
 hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream);
-hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, double* cf_acc, hipStream_t stream);
 // the Mask reduction's sums: masked plane sums of level 0 (M[t * 25 + s]) and
 // level-1 row segments (M[25 ncx ncy + k]), one launch
 hipError_t launch_a4_moment_sums(const double* f, const int* rp, const int4* rects, const int* n,

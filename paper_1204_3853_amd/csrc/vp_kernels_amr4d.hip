@@ -275,11 +275,28 @@ __device__ __forceinline__ void flux_store(double* p, double v, const A4Args& A)
 // whose corrections take vy +- 1 and vy +- 2, per cell.  The same formulas
 // and operand order as face_flux.  Rows past a ragged last run read the
 // last row of the padded copy and are dropped.
+// level-0 flux through coarse-fine face q, accumulated with the stage's
+// weight for the reflux at the end of the step
+__device__ __forceinline__ void a4_face(const A4Args& A, int q)
+{
+    if (q >= A.nfaces) return;
+    const A4Face F = A.faces[q];
+    const A4Patch P = A.patches[0];
+    const A4Acc ac4 = acc_at(A.a, A.lv[0], F.cell[0], F.cell[1]);
+    const double G = face_flux(view_of(A.pad, P), P, A.lv[0], ac4, F.dir, F.cell[0], F.cell[1], F.cell[2], F.cell[3]);
+    if (A.first) A.cf[q] = A.c_flux * G;
+    else A.cf[q] += A.c_flux * G;
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256) void k_a4_stage(A4Args A)
 {
     constexpr int K = kA4VxRun;
     const int t = blockIdx.x;
+    if (KIND != kRhs && t >= A.ntiles) {          // the blocks after the tiles: coarse-fine faces
+        a4_face(A, (t - A.ntiles) * 256 + (int)threadIdx.x);
+        return;
+    }
     const A4Patch P = A.patches[A.tiles[2 * t]];
     const int n0 = P.sz[0], n1 = P.sz[1], n2 = P.sz[2], n3 = P.sz[3];
     const int ng = (n2 + K - 1) / K;
@@ -418,19 +435,6 @@ __global__ __launch_bounds__(256) void k_a4_stage(A4Args A)
             A.fout[o] = A.acc[o] + A.c_acc * kk[q];
         }
     }
-}
-
-__global__ __launch_bounds__(256) void k_a4_faces(A4Args A, const A4Face* __restrict__ faces, int nfaces,
-                                                 double* __restrict__ cf)
-{
-    const int q = (int)blockIdx.x * 256 + threadIdx.x;
-    if (q >= nfaces) return;
-    const A4Face F = faces[q];
-    const A4Patch P = A.patches[0];
-    const A4Acc ac4 = acc_at(A.a, A.lv[0], F.cell[0], F.cell[1]);
-    const double G = face_flux(view_of(A.pad, P), P, A.lv[0], ac4, F.dir, F.cell[0], F.cell[1], F.cell[2], F.cell[3]);
-    if (A.first) cf[q] = A.c_flux * G;
-    else cf[q] += A.c_flux * G;
 }
 
 // The sums the Mask reduction combines, in one launch.  Blocks below ncx ncy:
@@ -586,21 +590,15 @@ hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* lis
 
 hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream)
 {
-    if (a.ntiles <= 0) return hipSuccess;
-    const dim3 g(a.ntiles), b(256);
+    const int fblocks = kind != kRhs && a.cf ? (a.nfaces + 255) / 256 : 0;
+    if (a.ntiles + fblocks <= 0) return hipSuccess;
+    const dim3 g(a.ntiles + fblocks), b(256);
     switch (kind) {
     case kRhs: hipLaunchKernelGGL(k_a4_stage<kRhs>, g, b, 0, stream, a); break;
     case kStage1: hipLaunchKernelGGL(k_a4_stage<kStage1>, g, b, 0, stream, a); break;
     case kStage23: hipLaunchKernelGGL(k_a4_stage<kStage23>, g, b, 0, stream, a); break;
     default: hipLaunchKernelGGL(k_a4_stage<kStage4>, g, b, 0, stream, a); break;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_a4_faces(const A4Args& a, const A4Face* faces, int nfaces, double* cf_acc, hipStream_t stream)
-{
-    if (nfaces <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_a4_faces, dim3((nfaces + 255) / 256), dim3(256), 0, stream, a, faces, nfaces, cf_acc);
     return hipGetLastError();
 }
 
