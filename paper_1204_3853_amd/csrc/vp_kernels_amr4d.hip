@@ -81,7 +81,7 @@ __device__ __forceinline__ A4Acc acc_at(const double* a, const A4Level& L, int I
 
 // flux through the upper face along `dir` of cell (i, j, k, l) of a patch
 // (local indices; the face's other cells come from the padded copy)
-__device__ double face_flux(const A4View& U, const A4Patch& P, const A4Level& L, const A4Acc& ac4, int dir, int i,
+__device__ __forceinline__ double face_flux(const A4View& U, const A4Patch& P, const A4Level& L, const A4Acc& ac4, int dir, int i,
                             int j, int k, int l)
 {
     if (dir == 0) {
@@ -102,8 +102,8 @@ __device__ double face_flux(const A4View& U, const A4Patch& P, const A4Level& L,
         const double vb = L.v_lo + ((double)(P.lo[3] + l) + 0.5) * L.h[3];
         return vb * fc + L.h[3] / 24.0 * (fu - fd);
     }
-    const int c = dir - 2;
-    const double ac = ac4.c[c], dax = ac4.dx[c], day = ac4.dy[c];
+    const bool c0 = dir == 2;                  // the component along the face's velocity direction
+    const double ac = c0 ? ac4.c[0] : ac4.c[1], dax = c0 ? ac4.dx[0] : ac4.dx[1], day = c0 ? ac4.dy[0] : ac4.dy[1];
     auto fv = [&](int ii, int jj) {
         return dir == 2 ? face4<double>(U(ii, jj, k - 1, l), U(ii, jj, k, l), U(ii, jj, k + 1, l), U(ii, jj, k + 2, l))
                         : face4<double>(U(ii, jj, k, l - 1), U(ii, jj, k, l), U(ii, jj, k, l + 1), U(ii, jj, k, l + 2));
@@ -267,14 +267,6 @@ __device__ __forceinline__ void flux_store(double* p, double v, const A4Args& A)
     else *p += A.c_flux * v;
 }
 
-// One thread per kA4VxRun cells along vx of one (x, y, vy) of a patch
-// (lanes along vy, so loads are coalesced): the x and vx face averages of
-// the run come from windows of the padded copy held in registers, every
-// face flux of the run evaluated once (the x faces on vx rows k0 - 1 ..
-// k0 + run, the vx faces k0 - 1/2 .. k0 + run - 1/2); the y and vy faces,
-// whose corrections take vy +- 1 and vy +- 2, per cell.  The same formulas
-// and operand order as face_flux.  Rows past a ragged last run read the
-// last row of the padded copy and are dropped.
 // level-0 flux through coarse-fine face q, accumulated with the stage's
 // weight for the reflux at the end of the step
 __device__ __forceinline__ void a4_face(const A4Args& A, int q)
@@ -288,6 +280,14 @@ __device__ __forceinline__ void a4_face(const A4Args& A, int q)
     else A.cf[q] += A.c_flux * G;
 }
 
+// One thread per kA4VxRun cells along vx of one (x, y, vy) of a patch
+// (lanes along vy, so loads are coalesced): the x and vx face averages of
+// the run come from windows of the padded copy held in registers, every
+// face flux of the run evaluated once (the x faces on vx rows k0 - 1 ..
+// k0 + run, the vx faces k0 - 1/2 .. k0 + run - 1/2); the y and vy faces,
+// whose corrections take vy +- 1 and vy +- 2, per cell.  The same formulas
+// and operand order as face_flux.  Rows past a ragged last run read the
+// last row of the padded copy and are dropped.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_a4_stage(A4Args A)
 {
