@@ -140,6 +140,29 @@ def test_seeded_layout_32(vp, oracle):
     close(ft, want, 1e-12)
 
 
+# fine configuration meshes above 64 cells per direction: the field solve
+# takes the larger-mesh kernels and the coarse acceleration its own launch
+LARGE = {
+    "ratio2_72x68": ((36, 34, 6, 6), 2, [box((4, 4, 4, 4), (11, 9, 7, 7)), box((64, 10, 4, 2), (71, 15, 7, 7))]),
+    "ratio4_80x72": ((20, 18, 4, 4), 4, [box((8, 8, 4, 4), (15, 15, 11, 11))]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(LARGE))
+def test_fine_mesh_above_64(vp, oracle, case):
+    n, R, boxes = LARGE[case]
+    o, plan, f = setup(vp, oracle, n, R, boxes, seed=7)
+    ft = torch.tensor(f, device="cuda")
+    a = vp.field_of(plan, ft)
+    close(a, o.constraints(f)[0], 1e-12)
+    dt = 0.02
+    want = o.step(f, dt)
+    vp.rk4_step(plan, ft, a, dt)
+    torch.cuda.synchronize()
+    close(ft, want, 1e-12)
+    close(a, o.constraints(want)[0], 1e-12)
+
+
 def composite_mass(o, f, vspan):
     n, R = o.n, o.R
     vol_c = X_LEN / n[0] * Y_LEN / n[1] * vspan / n[2] * vspan / n[3]
