@@ -196,12 +196,27 @@ vp_status stability_limit(vp_amr_run* r, hipStream_t s, double* lim)
     return VP_OK;
 }
 
+// the boxes of a and b are the same sequence (level and the x, v corners;
+// the adaptive run is 1D+1V)
+bool same_boxes(const vp_box* a, size_t na, const vp_box* b, size_t nb)
+{
+    if (na != nb) return false;
+    for (size_t q = 0; q < na; ++q)
+        if (a[q].level != b[q].level || a[q].lo[0] != b[q].lo[0] || a[q].lo[1] != b[q].lo[1] ||
+            a[q].hi[0] != b[q].hi[0] || a[q].hi[1] != b[q].hi[1])
+            return false;
+    return true;
+}
+
 // regrid of a multi-level hierarchy, from the coarsest level up: level l of
 // the new hierarchy is tagged (level 0: the old state; finer: a plan of the
 // new levels 0 .. l with its transferred state), its tags clustered into
 // level-(l+1) boxes nested in it; the final plan's state transferred from the
-// old hierarchy
-vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s)
+// old hierarchy.  While the new levels 0 .. l are the old ones, box for box,
+// the transfer would copy them unchanged, so level l is tagged on the old
+// plan and state; a new hierarchy equal to the old one keeps the old plan
+// and state (*changed = false).
+vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s, bool* changed)
 {
     const vp_plan* old = S.plan;
     const int L = old->hier->L;
@@ -211,10 +226,11 @@ vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s)
     vp_plan* P = nullptr;          // the new levels 0 .. l
     void* F = nullptr;             // its state
     size_t fcap = 0;
+    bool same = true;              // the new levels 0 .. l are the old ones
     vp_status st = VP_OK;
     for (int l = 0; l + 1 < L && st == VP_OK; ++l) {
-        const vp_plan* tp = l == 0 ? old : P;
-        const void* tf = l == 0 ? S.f : F;
+        const vp_plan* tp = same ? old : P;
+        const void* tf = same ? S.f : F;
         const HLevel& v = tp->hier->lv[l];
         st = ensure_buf(&S.work, &S.work_bytes, vp_workspace_bytes(tp));
         if (st == VP_OK) st = hier_tag_level(tp, static_cast<const double*>(tf), l, r->prm.tol, S.d_tags, nullptr,
@@ -230,7 +246,13 @@ vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s)
                           r->prm.buffer, mx, mv, add);
         if (st != VP_OK || add.empty()) break;
         nb.insert(nb.end(), add.begin(), add.end());
-        if (l + 2 < L) {                      // the new levels 0 .. l+1, to tag level l+1 next
+        if (same) {
+            std::vector<vp_box> ol;               // the old level-(l+1) boxes
+            for (const vp_box& b : S.boxes)
+                if (b.level == l + 1) ol.push_back(b);
+            same = same_boxes(add.data(), add.size(), ol.data(), ol.size());
+        }
+        if (l + 2 < L && !same) {             // the new levels 0 .. l+1, to tag level l+1 next
             vp_problem pbi = pb;
             pbi.n_levels = l + 2;
             vp_plan* Pn = nullptr;
@@ -244,6 +266,8 @@ vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s)
     if (P) vp_plan_destroy(P);
     free_dev(F);
     if (st != VP_OK) return st;
+    *changed = !same_boxes(nb.data(), nb.size(), S.boxes.data(), S.boxes.size());
+    if (!*changed) return VP_OK;
     vp_plan* np = nullptr;
     st = hier_plan_create(&pb, nb.data(), (int)nb.size(), &np);
     if (st != VP_OK) return st;
@@ -264,10 +288,11 @@ vp_status regrid_hier(vp_amr_run* r, RunSpecies& S, hipStream_t s)
     return VP_OK;
 }
 
-// regrid of one species' hierarchy from its own tags
-vp_status regrid_species(vp_amr_run* r, RunSpecies& S, hipStream_t s)
+// regrid of one species' hierarchy from its own tags; *changed = false when
+// the new boxes are the old ones (the plan and state are kept)
+vp_status regrid_species(vp_amr_run* r, RunSpecies& S, hipStream_t s, bool* changed)
 {
-    if (S.plan->hier) return regrid_hier(r, S, s);
+    if (S.plan->hier) return regrid_hier(r, S, s, changed);
     const AmrPlan& M = *S.plan->amr;
     const int ncx = M.ncx, ncv = M.ncv, R = M.R;
     vp_status st = vp_tag_cells(S.plan, S.f, r->prm.tol, S.d_tags, nullptr, s);
@@ -282,6 +307,8 @@ vp_status regrid_species(vp_amr_run* r, RunSpecies& S, hipStream_t s)
                          (int32_t)bx.size(), &nb);
     if (st != VP_OK) return st;
     bx.resize((size_t)nb);
+    *changed = !same_boxes(bx.data(), bx.size(), S.boxes.data(), S.boxes.size());
+    if (!*changed) return VP_OK;
     vp_problem pb = S.plan->pb;
     pb.veq[0][0] = S.plan->veq[0][0].data();
     pb.veq[1][0] = S.plan->veq[1][0].data();
@@ -314,9 +341,14 @@ vp_status regrid_species(vp_amr_run* r, RunSpecies& S, hipStream_t s)
 vp_status regrid(vp_amr_run* r, hipStream_t s)
 {
     const auto t0 = std::chrono::steady_clock::now();
-    for (int q = 0; q < r->ns; ++q)
-        if (vp_status st = regrid_species(r, r->sp[q], s)) return st;
-    if (vp_status st = rebuild_group(r)) return st;
+    bool any = false;
+    for (int q = 0; q < r->ns; ++q) {
+        bool changed = true;
+        if (vp_status st = regrid_species(r, r->sp[q], s, &changed)) return st;
+        any = any || changed;
+    }
+    if (any)
+        if (vp_status st = rebuild_group(r)) return st;
     if (vp_status st = run_field(r, s)) return st;
     VP_HIP(hipStreamSynchronize(s));
     ++r->regrids;
