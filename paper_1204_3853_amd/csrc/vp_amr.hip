@@ -83,6 +83,21 @@ void build_tiles(AmrPlan& A)
     A.ntiles = (int)A.tiles.size();
 }
 
+// the tile table on the device: the table, then the same tiles in the order
+// the one-launch stage takes them.  One block per tile: the longer fine tiles
+// (their halo is interpolated from the coarse level first) are dispatched
+// first, and the short coarse and face tiles fill the CUs as blocks finish.
+hipError_t upload_tiles(AmrPlan& A)
+{
+    std::vector<AmrTile> v(A.tiles);
+    v.insert(v.end(), A.tiles.begin() + A.ncoarse_tiles, A.tiles.begin() + A.face_tile_begin);
+    v.insert(v.end(), A.tiles.begin(), A.tiles.begin() + A.ncoarse_tiles);
+    v.insert(v.end(), A.tiles.begin() + A.face_tile_begin, A.tiles.end());
+    hipError_t e = upload(&A.d_tiles, v);
+    A.d_tiles_run = A.d_tiles ? A.d_tiles + A.ntiles : nullptr;
+    return e;
+}
+
 // the fine strip partials of each coarse column's R fine cells, for the
 // Mask reduction from the stage kernel's row sums: fine cell by fine cell,
 // patch by patch (patch order), strip by strip (the tiles' strips)
@@ -166,8 +181,9 @@ hipError_t launch_stage_all(const vp_plan* p, int kind, const AmrArgs& A, hipStr
     const AmrPlan& M = *p->amr;
     const int cap = 256 * 8;
     if (M.mode == 0) {
-        const int grid = std::min(M.ntiles, cap);
-        return launch_amr_stage(M.w, M.nt, kind, A, 0, M.ntiles, grid, stream);
+        AmrArgs B = A;
+        B.tiles = M.d_tiles_run;
+        return launch_amr_stage(M.w, M.nt, kind, B, 0, M.ntiles, std::min(M.ntiles, 1 << 16), stream);
     }
     // baseline: the coarse level, each patch and the face chunks as separate launches
     hipError_t e = launch_amr_stage(M.w, M.nt, kind, A, 0, M.ncoarse_tiles, std::min(M.ncoarse_tiles, cap), stream);
@@ -285,7 +301,7 @@ vp_status amr_set_shape(vp_plan* p, int nt, int w, int tx)
     M.w = w;
     M.tx = tx;
     build_tiles(M);
-    VP_HIP(upload(&M.d_tiles, M.tiles));
+    VP_HIP(upload_tiles(M));
     VP_HIP(upload_fused_lists(M));
     return VP_OK;
 }
@@ -577,7 +593,7 @@ vp_status amr_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int 
     M->nt = 64;
     M->tx = 8;
     build_tiles(*M);
-    VP_HIP(upload(&M->d_tiles, M->tiles));
+    VP_HIP(upload_tiles(*M));
     VP_HIP(upload_fused_lists(*M));
     TableArena T;
     T.add(&M->d_patches, M->patches);

@@ -550,6 +550,8 @@ struct AmrPlan {
     AmrPatch* d_patches = nullptr;
     int* d_nb = nullptr;
     AmrTile* d_tiles = nullptr;
+    AmrTile* d_tiles_run = nullptr;                  // the same tiles in the order of the one-launch stage
+                                                     // (fine, coarse, faces; in d_tiles' allocation)
     AmrFace* d_faces = nullptr;
     double* d_B = nullptr;
     int ntasks = 0;
