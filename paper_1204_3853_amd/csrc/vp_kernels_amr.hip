@@ -138,13 +138,42 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
             if (q2 == 0 ? !top : !bot) continue;
             const int X0 = P.gx0 + (q2 == 0 ? -2 : nx);
             const int wi0 = (X0 >> lr) - 2, wj0 = cjlo - 2, ww = cjhi - cjlo + 5;
-            fill(wi0, wj0, 5 + ((X0 + 1) >> lr) - (X0 >> lr), ww);
+            const int wh = 5 + ((X0 + 1) >> lr) - (X0 >> lr);
+            fill(wi0, wj0, wh, ww);
+            __syncthreads();
+            // the same sums as interp_win, split: the x sums of every window
+            // column for the two rows first (after the window in the ring's
+            // storage: (wh + 2) ww <= 8 ww fits), then the v sums per cell
+            double* gxr = win + wh * ww;
+            for (int k = t; k < 2 * ww; k += NT) {
+                const int q = k / ww, cc = k - q * ww;
+                const int X = X0 + q, ci = X >> lr, sx = X & (R - 1);
+                const double* w0 = win + (ci - 2 - wi0) * ww + cc;
+                double gx = 0.0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) gx += bs[sx * 5 + a] * w0[a * ww];
+                gxr[k] = gx;
+            }
             __syncthreads();
             const int ncols = TV + 4;
             for (int k = t; k < 2 * ncols; k += NT) {
                 const int q = k / ncols, c = k - q * ncols;
                 const int j = j0 - 2 + c;
-                hrow[2 * q2 + q][c] = (j >= -2 && j <= nv + 1) ? interp_win(X0 + q, P.gv0 + j, wi0, wj0, ww) : T(0);
+                const int V = P.gv0 + j;
+                T val = T(0);
+                if (j >= -2 && j <= nv + 1) {
+                    if (V < 0 || V >= A.nfv) {
+                        val = pick_ghost(V, A.nfv, fg0, fg1, fg2, fg3);
+                    } else {
+                        const int cj = V >> lr, sv = V & (R - 1);
+                        const double* g0 = gxr + q * ww + (cj - 2 - wj0);
+                        double acc = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 5; ++b) acc += bs[sv * 5 + b] * g0[b];
+                        val = acc;
+                    }
+                }
+                hrow[2 * q2 + q][c] = val;
             }
             __syncthreads();
         }
