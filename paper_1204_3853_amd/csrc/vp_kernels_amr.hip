@@ -86,6 +86,20 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
     const bool halo_data = has_halo && hj >= 0 && hj < nv;
     const int hld = halo_data ? hj : jld;
 
+    auto load_row = [&](int r, T* v, T& h) {
+        const int rc = min(max(r, 0), nx - 1);
+        const T* row = fs + (size_t)rc * nv;
+        VecIO<T, W>::ld(row + jld, v);
+        h = row[hld];
+    };
+    // the first rows of the march and the tile's accelerations, loaded
+    // before the halo work so that their latency overlaps it
+    T v0[4][W], h0[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) load_row(i0 - 2 + q, v0[q], h0[q]);
+    for (int q = t; q < i1 - i0 + 2; q += NT) aseg[q] = A.a_f[wrapi(P.gx0 + i0 - 1 + q, A.nfx)];
+    for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
+
     // Coarse-fine halo of the tile, interpolated once into LDS before the
     // march: patch rows -2, -1 (first segment) and nx, nx+1 (last segment)
     // over the tile's columns, and columns -2, -1, nv, nv+1 of its rows.
@@ -253,12 +267,6 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
     };
 
     auto slot_of = [&](int r) { return (r - i0 + 2) & (NSLOT - 1); };
-    auto load_row = [&](int r, T* v, T& h) {
-        const int rc = min(max(r, 0), nx - 1);
-        const T* row = fs + (size_t)rc * nv;
-        VecIO<T, W>::ld(row + jld, v);
-        h = row[hld];
-    };
     auto store_row = [&](int r, const T* v, T h) {
         T* dst = &ring[slot_of(r)][0];
         if (r > i1 + 1) {               // past the tile window (last batch): never read
@@ -310,15 +318,8 @@ __device__ __forceinline__ void stage_tile_fine(const AmrArgs& A, const AmrTile&
     const T dxi = A.dxfi, dvi = A.dvfi, dv24 = A.dvf24;
     const T cacc = A.coarse.c_acc, cnext = A.coarse.c_next;
 
-    {
-        T v[4][W], h[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) load_row(i0 - 2 + q, v[q], h[q]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) store_row(i0 - 2 + q, v[q], h[q]);
-    }
-    for (int q = t; q < i1 - i0 + 2; q += NT) aseg[q] = A.a_f[wrapi(P.gx0 + i0 - 1 + q, A.nfx)];
-    for (int q = i1 - i0 + 2 + t; q < kMaxTx + RB + 2; q += NT) aseg[q] = 0.0;
+    for (int q = 0; q < 4; ++q) store_row(i0 - 2 + q, v0[q], h0[q]);
     __syncthreads();
 
     T gx_old[W];
