@@ -44,8 +44,7 @@ vp_status pad_launch(const vp_plan* p, const double* f, double* pad, double* scr
     const Amr4DPlan& M = *p->a4;
     VP_HIP(timed(p, kTOther, stream, [&] {
         return launch_a4_pad(f, M.d_patches, M.d_list, (int)M.patches.size(), (long long)M.pad_total, M.d_nb, M.lv,
-                             M.d_B, M.R, M.d_gxc, M.d_gyc, M.d_gxf, M.d_gyf, M.d_interp, M.pass_total, M.ptiles, scratch,
-                             pad, stream);
+                             M.d_B, M.R, M.d_gxc, M.d_gyc, M.d_gxf, M.d_gyf, M.d_interp, M.ptiles, scratch, pad, stream);
     }));
     return VP_OK;
 }
@@ -385,16 +384,13 @@ vp_status a4_create(vp_plan* p, const vp_problem* pb, const vp_box* boxes, int n
         ip.push_back(Q);
     }
     long long acc_o = 0;
-    for (int dir = 0; dir < 3; ++dir) {
-        M.pass_total[dir] = 0;
+    for (int dir = 0; dir < 3; ++dir)
         for (A4Interp& Q : ip) {
             long long n = 1;
             for (int d = 0; d < 4; ++d) n *= d <= dir ? Q.pn[d] : Q.cn[d];
             Q.o[dir] = acc_o;
             acc_o += n;
-            M.pass_total[dir] += n;
         }
-    }
     const size_t scratch_elems = (size_t)std::max<long long>(acc_o, 1);
     // block tables of the padded copies (every patch) and of the passes
     std::vector<int2> ptile, itile[3];

@@ -227,7 +227,7 @@ struct A4PadTiles {            // blocks of 256 elements of one patch: (patch, i
 hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
                          const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
                          const double* gyc, const double* gxf, const double* gyf, const A4Interp* ip,
-                         const long long* pass_total, const A4PadTiles& tl, double* scratch, double* pad, hipStream_t stream);
+                         const A4PadTiles& tl, double* scratch, double* pad, hipStream_t stream);
 hipError_t launch_a4_stage(int kind, const A4Args& a, hipStream_t stream);
 // the Mask reduction's sums: masked plane sums of level 0 (M[t * 25 + s]) and
 // level-1 row segments (M[25 ncx ncy + k]), one launch
@@ -612,7 +612,6 @@ struct Amr4DPlan {
     double *d_gxc = nullptr, *d_gyc = nullptr, *d_gxf = nullptr, *d_gyf = nullptr;
     A4Face* d_faces = nullptr;
     A4Interp* d_interp = nullptr;                    // per level-1 patch, the separable interpolation passes
-    long long pass_total[3] = {0, 0, 0};
     A4PadTiles ptiles{};                             // block tables of the padded copies and the passes
     double* d_rhs_scratch = nullptr;                 // pass results of vp_rhs calls
     int* d_rect_ptr = nullptr;                       // per level-0 column: its covered velocity rectangles

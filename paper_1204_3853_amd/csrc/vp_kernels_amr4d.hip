@@ -555,8 +555,7 @@ __global__ __launch_bounds__(256) void k_a4_average(double* __restrict__ f, cons
 hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* list, int npatch, long long total,
                          const int* nb, const A4Level* lv_host, const double* B, int R, const double* gxc,
                          const double* gyc, const double* gxf, const double* gyf, const A4Interp* ip,
-                         const long long* pass_total, const A4PadTiles& tl, double* scratch, double* pad,
-                         hipStream_t stream)
+                         const A4PadTiles& tl, double* scratch, double* pad, hipStream_t stream)
 {
     if (total <= 0) return hipSuccess;
     A4PadArgs A{};
@@ -578,7 +577,6 @@ hipError_t launch_a4_pad(const double* f, const A4Patch* patches, const int* lis
     A.scratch = scratch;
     A.pad = pad;
     A.tl = tl;
-    (void)pass_total;
     if (A.nip > 0) {
         if (tl.npass[0] > 0) hipLaunchKernelGGL(k_a4_interp<0>, dim3(tl.npass[0]), dim3(256), 0, stream, A);
         if (tl.npass[1] > 0) hipLaunchKernelGGL(k_a4_interp<1>, dim3(tl.npass[1]), dim3(256), 0, stream, A);
