@@ -534,7 +534,9 @@ vp_status vp_regrid_transfer(const vp_plan* old_plan, const void* f_old, const v
  * regrid_interval steps: vp_tag_cells with tol, vp_cluster_tags with
  * efficiency, min_width and buffer, a new plan with the same problem and
  * the new boxes (default tile shape, launch mode and reduction),
- * vp_regrid_transfer, then the field of the new state.
+ * vp_regrid_transfer, then the field of the new state.  A regrid that
+ * finds exactly the current boxes keeps the current plan and state (the
+ * transfer would copy every cell unchanged).
  */
 typedef struct vp_amr_params {
     double tol;                /* refinement threshold of delta1 f + delta2 f (>= 0)   */
@@ -569,7 +571,8 @@ typedef struct vp_amr_run vp_amr_run;
  * problem (more than two levels, or different ratios in x and v) regrids
  * from the coarsest level up: level l of the new hierarchy is tagged
  * (vp_tag_level; level 0 on the old state, finer levels on the new levels
- * below them with their transferred state), clustered into level-(l+1)
+ * below them with their transferred state, or on the old plan and state
+ * while those levels are the old ones box for box), clustered into level-(l+1)
  * boxes nested in it (vp_cluster_level with min_width, buffer, efficiency
  * and max_size[l+1]), and the new state transferred from the old one
  * (vp_regrid_transfer).  VP_EINVAL for bad parameters or a problem with
@@ -582,12 +585,13 @@ vp_status vp_amr_run_create(const vp_problem* problem, const vp_box* boxes, int3
  * rule and arithmetic as on the host) and the step's kernels read it
  * there, so the stream is synchronised only at a regrid and at the end of
  * the call.  Two-level plans and several species synchronise every step
- * (the time step needs max|a| on the host).  A regrid allocates the new
- * state and frees the old one.  After an error the run should only be
+ * (the time step needs max|a| on the host).  A regrid that changes the
+ * boxes allocates the new plan and state and frees the old ones.  After an error the run should only be
  * destroyed. */
 vp_status vp_amr_run_advance(vp_amr_run* run, int32_t steps, hipStream_t stream);
 vp_status vp_amr_run_info(const vp_amr_run* run, vp_amr_info* info);
-/* The plan of the current hierarchy (owned by the run; replaced at a regrid). */
+/* The plan of the current hierarchy (owned by the run; replaced at a regrid
+ * that changes the boxes). */
 const vp_plan* vp_amr_run_plan(const vp_amr_run* run);
 /* The current boxes (level-1 index space); *nbox receives the count,
  * VP_EINVAL when it exceeds max_boxes. */
